@@ -1,0 +1,20 @@
+"""CPU FP64 oracle for the statically condensed GL-DGSEM implicit solve.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call, link
+or execute anything in this package; only the tests, the smoke check and the
+CPU-baseline leg of the benchmark use it.  It shares no code with the HIP
+library (its index conventions are re-derived here with plain loops) and it
+never consumes a value produced by the GPU path.
+
+What it computes (each function cites the passage it follows):
+  * the global backward-Euler Jacobian A assembled from the per-element blocks
+    and the uncondensed solution of A dQ = B (eq. NewtonLinSys1) by LAPACK
+    dense LU or SuperLU;
+  * the Schur-complement quantities of eq. SC_step1 / SC_step2 written out as
+    their definitions, per element, with numpy.
+"""
+from .linalg import (  # noqa: F401
+    NodeSets, node_sets, dof_maps, assemble_global, solve_dense, solve_sparse,
+    element_inverse, element_schur, condensed_matrix_dense, condensed_rhs,
+    back_substitute, full_residual, gmres_mgs, condensed_solve_dense,
+)

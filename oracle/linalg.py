@@ -1,0 +1,237 @@
+"""Plain FP64 linear algebra of the statically condensed GL-DGSEM (test oracle).
+
+Subscripts are row-column: A_bi = A[b, i] (boundary rows, interior columns),
+A_ib = A[i, b].  With this convention the paper's block system
+(eq. StaticDGSEM_QbQiSystem) is
+    [ A_bb  A_bi ] [Q_b]   [B_b]
+    [ A_ib  A_ii ] [Q_i] = [B_i]
+and static condensation (eq. BlockSystem, SC_step1, SC_step2) reads
+    (A_bb - A_bi A_ii^-1 A_ib) Q_b = B_b - A_bi A_ii^-1 B_i
+    Q_i = A_ii^-1 (B_i - A_ib Q_b).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+NVAR = 5
+
+
+@dataclass
+class NodeSets:
+    interior: list      # local node ids with i, j, k in 1..N-1, increasing
+    boundary: list      # remaining local node ids, increasing
+
+
+def node_sets(order: int) -> NodeSets:
+    """Interior / element-boundary nodes of a GL hex element (paper, Section 3.1).
+
+    On Gauss-Lobatto nodes a basis function is nonzero on a face only if its
+    node lies on that face, so the element-boundary DOFs are exactly the nodes
+    with some index equal to 0 or N.
+    """
+    p = order + 1
+    interior, boundary = [], []
+    for k in range(p):
+        for j in range(p):
+            for i in range(p):
+                n = i + p * j + p * p * k
+                if 1 <= i <= order - 1 and 1 <= j <= order - 1 and 1 <= k <= order - 1:
+                    interior.append(n)
+                else:
+                    boundary.append(n)
+    return NodeSets(interior, boundary)
+
+
+def dof_maps(order: np.ndarray):
+    """Natural-order DOF indices of every element's interior and of every global boundary node.
+
+    Returns (interior_dofs: list of arrays [5 nI(e)], bnode_dofs: array [n_bnodes, 5]).
+    Global boundary node ids run element by element over each element's boundary
+    nodes in increasing local node id.
+    """
+    interior_dofs, bnode = [], []
+    off = 0
+    for n_e in order:
+        ns = node_sets(int(n_e))
+        interior_dofs.append(np.array([off + NVAR * n + v for n in ns.interior for v in range(NVAR)],
+                                      dtype=np.int64))
+        for n in ns.boundary:
+            bnode.append([off + NVAR * n + v for v in range(NVAR)])
+        off += NVAR * (int(n_e) + 1) ** 3
+    return interior_dofs, np.array(bnode, dtype=np.int64).reshape(-1, NVAR)
+
+
+def _c_dofs(e: int, c_ptr, c_node, bnode_dofs) -> np.ndarray:
+    nodes = c_node[c_ptr[e]:c_ptr[e + 1]]
+    return bnode_dofs[nodes].reshape(-1)
+
+
+def _b_index(bnode_dofs: np.ndarray, e: int, c_ptr, c_node) -> np.ndarray:
+    """Positions in the boundary vector (node-major, 5 per node) of C_e's DOFs."""
+    nodes = np.asarray(c_node[c_ptr[e]:c_ptr[e + 1]], dtype=np.int64)
+    return (nodes[:, None] * NVAR + np.arange(NVAR)[None, :]).reshape(-1)
+
+
+def assemble_global(order, c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi) -> sp.csr_matrix:
+    """Scatter the per-element blocks and A_bb back into the global Jacobian A
+    (natural DOF order).  Every entry of A lives in exactly one block."""
+    interior_dofs, bnode_dofs = dof_maps(order)
+    n_dof = int(sum(NVAR * (int(n) + 1) ** 3 for n in order))
+    rows, cols, vals = [], [], []
+
+    def put(r, c, m):
+        rr, cc = np.meshgrid(r, c, indexing="ij")
+        rows.append(rr.reshape(-1))
+        cols.append(cc.reshape(-1))
+        vals.append(np.asarray(m).reshape(-1))
+
+    for e in range(len(order)):
+        ii = interior_dofs[e]
+        cc = _c_dofs(e, c_ptr, c_node, bnode_dofs)
+        put(ii, ii, aii[e])
+        put(ii, cc, aib[e])
+        put(cc, ii, abi[e])
+    n_b = len(bb_rowptr) - 1
+    for g in range(n_b):
+        for t in range(bb_rowptr[g], bb_rowptr[g + 1]):
+            put(bnode_dofs[g], bnode_dofs[bb_col[t]], bb_val[t])
+    a = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n_dof, n_dof)).tocsr()
+    a.eliminate_zeros()
+    return a
+
+
+def solve_dense(a, b: np.ndarray) -> np.ndarray:
+    """Brute force: LAPACK LU with partial pivoting of the full matrix (eq. NewtonLinSys1)."""
+    dense = a.toarray() if sp.issparse(a) else np.asarray(a)
+    lu, piv = sla.lu_factor(dense)
+    return sla.lu_solve((lu, piv), b)
+
+
+def solve_sparse(a, b: np.ndarray) -> np.ndarray:
+    """Uncondensed direct solve of A dQ = B with SuperLU (eq. NewtonLinSys1)."""
+    return spla.splu(sp.csc_matrix(a)).solve(b)
+
+
+def element_inverse(aii_e: np.ndarray) -> np.ndarray:
+    """A_ii(e)^-1 (the paper inverts each interior block with LAPACK LU; Section 3.2)."""
+    return np.linalg.inv(aii_e)
+
+
+def element_schur(aii_e, aib_e, abi_e) -> np.ndarray:
+    """Element contribution A_bi(e) A_ii(e)^-1 A_ib(e) to the Schur complement (eq. SC_step1)."""
+    return abi_e @ np.linalg.solve(aii_e, aib_e)
+
+
+def _bb_dense(bb_rowptr, bb_col, bb_val, n_b: int) -> np.ndarray:
+    s = np.zeros((NVAR * n_b, NVAR * n_b))
+    for g in range(n_b):
+        for t in range(bb_rowptr[g], bb_rowptr[g + 1]):
+            h = bb_col[t]
+            s[NVAR * g:NVAR * g + NVAR, NVAR * h:NVAR * h + NVAR] += bb_val[t]
+    return s
+
+
+def condensed_matrix_dense(c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi) -> np.ndarray:
+    """S = A_bb - sum_e P_e A_bi(e) A_ii(e)^-1 A_ib(e) P_e^T as a dense matrix (eq. SC_step1)."""
+    n_b = len(bb_rowptr) - 1
+    s = _bb_dense(bb_rowptr, bb_col, bb_val, n_b)
+    for e in range(len(c_ptr) - 1):
+        idx = _b_index(None, e, c_ptr, c_node)
+        s[np.ix_(idx, idx)] -= element_schur(aii[e], aib[e], abi[e])
+    return s
+
+
+def condensed_rhs(order, c_ptr, c_node, aii, abi, b: np.ndarray) -> np.ndarray:
+    """b_S = B_b - sum_e P_e A_bi(e) A_ii(e)^-1 B_i(e) (eq. SC_step1, right-hand side)."""
+    interior_dofs, bnode_dofs = dof_maps(order)
+    bs = b[bnode_dofs].reshape(-1).copy()
+    for e in range(len(order)):
+        idx = _b_index(None, e, c_ptr, c_node)
+        bs[idx] -= abi[e] @ np.linalg.solve(aii[e], b[interior_dofs[e]])
+    return bs
+
+
+def back_substitute(order, c_ptr, c_node, aii, aib, b: np.ndarray, qb: np.ndarray) -> np.ndarray:
+    """Q_i(e) = A_ii(e)^-1 (B_i(e) - A_ib(e) Q_b[C_e]) (eq. SC_step2); returns dQ in natural order."""
+    interior_dofs, bnode_dofs = dof_maps(order)
+    dq = np.zeros_like(b)
+    dq[bnode_dofs.reshape(-1)] = qb
+    for e in range(len(order)):
+        idx = _b_index(None, e, c_ptr, c_node)
+        dq[interior_dofs[e]] = np.linalg.solve(aii[e], b[interior_dofs[e]] - aib[e] @ qb[idx])
+    return dq
+
+
+def condensed_solve_dense(order, c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi, b):
+    """Both condensation steps with a dense LU of S (the paper's direct route, Section 2.2)."""
+    s = condensed_matrix_dense(c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi)
+    bs = condensed_rhs(order, c_ptr, c_node, aii, abi, b)
+    qb = sla.lu_solve(sla.lu_factor(s), bs)
+    return back_substitute(order, c_ptr, c_node, aii, aib, b, qb)
+
+
+def full_residual(a, x: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """r = B - A dQ on the full (uncondensed) system."""
+    return b - a @ x
+
+
+def gmres_mgs(matvec, b: np.ndarray, tol: float, restart: int = 30, max_iter: int = 2000,
+              precond_diag: np.ndarray | None = None, x0: np.ndarray | None = None):
+    """Restarted GMRES(m), modified Gram-Schmidt, Givens rotations, optional right
+    point-Jacobi preconditioner; stops when ||b - A x|| <= tol ||b||.
+
+    The paper's Krylov runs use GMRES with a point-Jacobi preconditioner (Section 4).
+    Returns (x, iterations, final relative residual).
+    """
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else x0.astype(np.float64).copy()
+    dinv = np.ones(n) if precond_diag is None else 1.0 / precond_diag
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return np.zeros(n), 0, 0.0
+    it = 0
+    r = b - matvec(x)
+    beta = np.linalg.norm(r)
+    while it < max_iter:
+        if beta <= tol * bnorm:
+            break
+        v = np.zeros((restart + 1, n))
+        h = np.zeros((restart + 1, restart))
+        cs, sn = np.zeros(restart), np.zeros(restart)
+        g = np.zeros(restart + 1)
+        g[0] = beta
+        v[0] = r / beta
+        j_used = 0
+        for j in range(restart):
+            w = matvec(dinv * v[j])
+            for i in range(j + 1):
+                h[i, j] = np.dot(v[i], w)
+                w = w - h[i, j] * v[i]
+            h[j + 1, j] = np.linalg.norm(w)
+            if h[j + 1, j] != 0.0:
+                v[j + 1] = w / h[j + 1, j]
+            for i in range(j):
+                t = cs[i] * h[i, j] + sn[i] * h[i + 1, j]
+                h[i + 1, j] = -sn[i] * h[i, j] + cs[i] * h[i + 1, j]
+                h[i, j] = t
+            den = np.hypot(h[j, j], h[j + 1, j])
+            cs[j], sn[j] = h[j, j] / den, h[j + 1, j] / den
+            h[j, j] = den
+            h[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            j_used = j + 1
+            if abs(g[j + 1]) <= tol * bnorm or it >= max_iter:
+                break
+        y = sla.solve_triangular(h[:j_used, :j_used], g[:j_used])
+        x = x + dinv * (v[:j_used].T @ y)
+        r = b - matvec(x)
+        beta = np.linalg.norm(r)
+    return x, it, beta / bnorm
