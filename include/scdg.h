@@ -1,0 +1,180 @@
+/*
+ * scdg.h -- statically condensed GL-DGSEM implicit-step linear solve on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the Schur-complement solution of the Newton system of a
+ * backward-Euler GL-DGSEM step, A dQ = B (paper, eq. NewtonLinSys1), after
+ * reordering the unknowns into element-boundary DOFs Q_b and element-interior
+ * DOFs Q_i (Section 3.1, eq. StaticDGSEM_QbQiSystem).  On Gauss-Lobatto nodes
+ * the interior block A_ii is block-diagonal, one dense block per element
+ * (Section 3.1, summary of the sparsity analysis), so
+ *
+ *     S   = A_bb - A_bi A_ii^-1 A_ib                         (eq. SC_step1)
+ *     b_S = B_b  - A_bi A_ii^-1 B_i                          (eq. SC_step1)
+ *     S Q_b = b_S,   Q_i = A_ii^-1 (B_i - A_ib Q_b)          (eq. SC_step2)
+ *
+ * SUBSCRIPTS ARE ROW-COLUMN: A_bi = A[b rows, i columns], A_ib = A[i rows,
+ * b columns].  (The paper names the same blocks the other way round.)
+ *
+ * ------------------------------------------------------------------------
+ * Data conventions
+ * ------------------------------------------------------------------------
+ * Element e has polynomial order N_e (2 <= N_e <= 7), P = N_e + 1 nodes per
+ * direction, local node n = i + P j + P^2 k, and 5 conserved variables.
+ *   - Natural vectors (B, dQ, r, x0): device, double, DOF index
+ *     (sum_{e'<e} 5 P_{e'}^3) + 5 n + v.
+ *   - Interior nodes of e: i, j, k all in [1, N_e-1], in increasing n;
+ *     n_i(e) = 5 (N_e - 1)^3 DOFs.
+ *   - Boundary nodes of e: the other nodes in increasing n; the r-th one has
+ *     global boundary id bnode_off[e] + r, bnode_off = exclusive prefix sum of
+ *     (P^3 - (N_e-1)^3).  Boundary vectors (b_S, Q_b): device, double,
+ *     index 5 g + v, length n1 = 5 n_bnodes.
+ *   - Coupling set C_e: the global boundary nodes whose DOFs share a nonzero
+ *     with an interior DOF of e, ascending; n_c(e) = 5 |C_e|.
+ *   - Blocks, device, double, row-major, packed element after element:
+ *       A_ii(e) [n_i x n_i], A_ib(e) [n_i x n_c], A_bi(e) [n_c x n_i];
+ *     A_bb in BSR with 5x5 row-major blocks over global boundary nodes.
+ *
+ * Ownership and streams: the caller owns every buffer passed in.  Blocks given
+ * to scdg_assemble are BORROWED until the next scdg_assemble or
+ * scdg_plan_destroy (the FP64 originals are read again by the full-system
+ * residual).  The plan owns its factors, Schur blocks and workspaces.  Every
+ * call enqueues work on the plan's HIP stream; calls that return host data
+ * (scdg_solve*, scdg_residual, scdg_factor_info) synchronize that stream.
+ * A plan is not thread-safe; distinct plans are independent.
+ *
+ * Errors: every call returns scdg_status; nothing throws or aborts across the
+ * ABI.  Argument and call-order errors return before any work is enqueued.
+ * Call order: plan_create -> assemble -> factor -> condense -> (condense_rhs,
+ * solve_condensed, backsolve | solve)*; assemble invalidates later stages.
+ */
+#ifndef SCDG_H
+#define SCDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct scdg_plan scdg_plan;
+
+typedef enum {
+  SCDG_OK = 0,
+  SCDG_ERR_ARG = -1,        /* bad pointer, size or option */
+  SCDG_ERR_STATE = -2,      /* call out of order */
+  SCDG_ERR_HIP = -3,        /* HIP runtime error (text in scdg_last_error) */
+  SCDG_ERR_NOMEM = -4,      /* device allocation failed */
+  SCDG_ERR_SINGULAR = -5,   /* zero / non-finite pivot in some A_ii(e) or S */
+  SCDG_ERR_NOCONV = -6,     /* iteration budget exhausted; outputs hold the best iterate */
+  SCDG_ERR_NONFINITE = -7,  /* NaN / Inf met in a right-hand side or residual */
+  SCDG_ERR_UNSUPPORTED = -8 /* order or size outside what this build handles */
+} scdg_status;
+
+typedef enum { SCDG_FP64 = 0, SCDG_FP32 = 1 } scdg_precision;
+
+/* Mesh structure; all pointers are HOST memory and are copied at create. */
+typedef struct {
+  int32_t n_elem;
+  const int32_t *order;     /* [n_elem] polynomial order N_e, 2..7 */
+  const int64_t *c_ptr;     /* [n_elem+1] offsets into c_node */
+  const int32_t *c_node;    /* [c_ptr[n_elem]] C_e as ascending global boundary ids */
+  const int64_t *bb_rowptr; /* [n_bnodes+1] BSR row pointer of A_bb */
+  const int32_t *bb_col;    /* [bb_rowptr[n_bnodes]] BSR block columns of A_bb */
+} scdg_structure;
+
+typedef enum { SCDG_SOLVER_AUTO = 0, SCDG_SOLVER_DENSE = 1, SCDG_SOLVER_GMRES = 2 } scdg_solver;
+
+/* Options of the condensed solve (zero-initialised fields take the defaults). */
+typedef struct {
+  int32_t solver;     /* scdg_solver; AUTO = dense LU of S when n1 <= 8192, else GMRES */
+  int32_t restart;    /* GMRES restart length m (default 30) */
+  int32_t max_iters;  /* total GMRES iterations (default 1000) */
+  double tol;         /* GMRES stop: ||b_S - S x||_2 <= tol ||b_S||_2 (default 1e-10) */
+  int32_t precond;    /* 0 none, 1 right point-Jacobi on diag(S) (default 1 via -1 -> 1) */
+  int32_t ir_max;     /* iterative-refinement sweeps for FP32 factors (default 10) */
+  double ir_tol;      /* refinement stop on ||B - A dQ||_2 / ||B||_2 (default 1e-8) */
+} scdg_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* GMRES iterations, all sweeps */
+  int32_t restarts;     /* GMRES restart cycles, all sweeps */
+  int32_t ir_sweeps;    /* condensed solves performed by scdg_solve */
+  int32_t solver_used;  /* scdg_solver actually used */
+  double rel_res_S;     /* last ||b_S - S x|| / ||b_S|| (GMRES estimate) */
+  double rel_res_full;  /* ||B - A dQ||_2 / ||B||_2 in FP64, or -1 if not computed */
+} scdg_solve_info;
+
+/* Build the index maps of the partition (Section 3.2: permutation indexes from
+ * the mesh connectivity), the Schur-apply maps and the work lists.  hip_stream
+ * may be NULL (default stream).  The current HIP device is used. */
+scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip_stream);
+scdg_status scdg_plan_destroy(scdg_plan *p);
+scdg_status scdg_set_stream(scdg_plan *p, void *hip_stream);
+/* Sizes: natural DOFs, n1 = 5 n_bnodes (condensed size), n2 = sum n_i, n_bnodes. */
+scdg_status scdg_plan_sizes(const scdg_plan *p, int64_t *n_dof, int64_t *n1, int64_t *n2,
+                            int64_t *n_bnodes);
+
+/* Register the Jacobian blocks (device pointers, borrowed, FP64). */
+scdg_status scdg_assemble(scdg_plan *p, const double *aii, const double *aib,
+                          const double *abi, const double *bb_val);
+
+/* Invert every A_ii(e) by Gauss-Jordan elimination with partial pivoting
+ * (the paper inverts each interior block with LU routines, Section 3.2), in
+ * FP64 or FP32.  A zero pivot is recorded per element (see scdg_factor_info)
+ * and reported as SCDG_ERR_SINGULAR by scdg_condense. */
+scdg_status scdg_factor(scdg_plan *p, scdg_precision prec);
+/* First singular element (or -1) and its LAPACK-style info (1-based step). */
+scdg_status scdg_factor_info(scdg_plan *p, int64_t *first_bad_elem, int32_t *info);
+
+/* X_e = A_ii(e)^-1 A_ib(e) and the element Schur blocks A_bi(e) X_e
+ * (eq. SC_step1); S = A_bb - sum_e P_e A_bi(e) X_e P_e^T is kept in this
+ * element-block form plus A_bb.  Uses the precision given to scdg_factor. */
+scdg_status scdg_condense(scdg_plan *p);
+
+/* b_S = B_b - sum_e P_e A_bi(e) A_ii(e)^-1 B_i(e) (eq. SC_step1).  b: natural
+ * vector, bs: boundary vector (both device). */
+scdg_status scdg_condense_rhs(scdg_plan *p, const double *b, double *bs);
+
+/* Solve S Q_b = b_S: dense LU with partial pivoting of the assembled S, or
+ * restarted GMRES(m) with right point-Jacobi and classical Gram-Schmidt with
+ * reorthogonalisation (the paper's solvers: direct, and GMRES with a point-
+ * Jacobi preconditioner, Section 4).  x0 (boundary vector) may be NULL. */
+scdg_status scdg_solve_condensed(scdg_plan *p, const double *bs, double *qb, const double *x0,
+                                 const scdg_solve_opts *o, scdg_solve_info *info);
+
+/* Q_i(e) = A_ii(e)^-1 (B_i(e) - A_ib(e) Q_b[C_e]) (eq. SC_step2); writes the
+ * whole natural vector dQ (boundary part copied from qb). */
+scdg_status scdg_backsolve(scdg_plan *p, const double *b, const double *qb, double *dq);
+
+/* Full solve of A dQ = B: condensed RHS, condensed solve, back-substitution.
+ * With FP32 factors the FP64 full-system residual drives iterative
+ * refinement until ||B - A dQ|| <= ir_tol ||B||.  x0 (natural vector) may be
+ * NULL; its boundary part seeds the first condensed solve. */
+scdg_status scdg_solve(scdg_plan *p, const double *b, double *dq, const double *x0,
+                       const scdg_solve_opts *o, scdg_solve_info *info);
+
+/* r = B - A dQ on the full FP64 system; rel2 (host, may be NULL) receives
+ * ||r||_2 / ||B||_2.  r may be NULL when only rel2 is wanted. */
+scdg_status scdg_residual(scdg_plan *p, const double *b, const double *dq, double *r,
+                          double *rel2);
+
+/* y = S x with the condensed operator as stored (boundary vectors, device). */
+scdg_status scdg_schur_apply(scdg_plan *p, const double *x, double *y);
+
+/* Copy internal arrays to caller device memory (for inspection and tests):
+ * SCDG_EXPORT_AII_INV: sum n_i^2 values, SCDG_EXPORT_SCHUR: sum n_c^2 values of
+ * A_bi(e) A_ii(e)^-1 A_ib(e); both in the factor precision (double or float). */
+enum { SCDG_EXPORT_AII_INV = 1, SCDG_EXPORT_SCHUR = 2, SCDG_EXPORT_X = 3 };
+scdg_status scdg_export(scdg_plan *p, int what, void *dst, size_t dst_bytes);
+
+const char *scdg_status_string(scdg_status s);
+/* Last error text of a plan (or of plan creation when p is NULL). */
+scdg_status scdg_last_error(const scdg_plan *p, char *buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCDG_H */

@@ -16,5 +16,5 @@ What it computes (each function cites the passage it follows):
 from .linalg import (  # noqa: F401
     NodeSets, node_sets, dof_maps, assemble_global, solve_dense, solve_sparse,
     element_inverse, element_schur, condensed_matrix_dense, condensed_rhs,
-    back_substitute, full_residual, gmres_mgs, condensed_solve_dense,
+    back_substitute, full_residual, gmres_mgs, condensed_solve_dense, element_interior_residual,
 )

@@ -235,3 +235,12 @@ def gmres_mgs(matvec, b: np.ndarray, tol: float, restart: int = 30, max_iter: in
         r = b - matvec(x)
         beta = np.linalg.norm(r)
     return x, it, beta / bnorm
+
+
+def element_interior_residual(e: int, order, c_ptr, c_node, aii_e, aib_e, b: np.ndarray,
+                              dq: np.ndarray) -> np.ndarray:
+    """Interior rows of r = B - A dQ for one element: B_i - A_ii dQ_i - A_ib dQ_b[C_e]."""
+    interior_dofs, bnode_dofs = dof_maps(order)
+    qb = dq[bnode_dofs.reshape(-1)]
+    idx = _b_index(None, e, c_ptr, c_node)
+    return b[interior_dofs[e]] - aii_e @ dq[interior_dofs[e]] - aib_e @ qb[idx]

@@ -1,0 +1,98 @@
+"""ctypes declarations of libscdg.so (C ABI in include/scdg.h).
+
+Argument marshalling only: every step of the solve runs inside the library.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscdg.so")
+
+SCDG_OK = 0
+STATUS = {0: "SCDG_OK", -1: "SCDG_ERR_ARG", -2: "SCDG_ERR_STATE", -3: "SCDG_ERR_HIP",
+          -4: "SCDG_ERR_NOMEM", -5: "SCDG_ERR_SINGULAR", -6: "SCDG_ERR_NOCONV",
+          -7: "SCDG_ERR_NONFINITE", -8: "SCDG_ERR_UNSUPPORTED"}
+SCDG_FP64, SCDG_FP32 = 0, 1
+SOLVER_AUTO, SOLVER_DENSE, SOLVER_GMRES = 0, 1, 2
+EXPORT_AII_INV, EXPORT_SCHUR, EXPORT_X = 1, 2, 3
+
+EXPORTED = [
+    "scdg_plan_create", "scdg_plan_destroy", "scdg_set_stream", "scdg_plan_sizes",
+    "scdg_assemble", "scdg_factor", "scdg_factor_info", "scdg_condense", "scdg_condense_rhs",
+    "scdg_solve_condensed", "scdg_backsolve", "scdg_solve", "scdg_residual",
+    "scdg_schur_apply", "scdg_export", "scdg_status_string", "scdg_last_error",
+]
+
+
+class Structure(C.Structure):
+    _fields_ = [("n_elem", C.c_int32), ("order", C.c_void_p), ("c_ptr", C.c_void_p),
+                ("c_node", C.c_void_p), ("bb_rowptr", C.c_void_p), ("bb_col", C.c_void_p)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("solver", C.c_int32), ("restart", C.c_int32), ("max_iters", C.c_int32),
+                ("tol", C.c_double), ("precond", C.c_int32), ("ir_max", C.c_int32),
+                ("ir_tol", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("ir_sweeps", C.c_int32),
+                ("solver_used", C.c_int32), ("rel_res_S", C.c_double), ("rel_res_full", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ScdgError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} {detail}".strip())
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1911_02366_amd/build.py "
+                          "(the solver has no fallback path)")
+    lib = C.CDLL(path)
+    vp, i32, i64, d, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    sig = {
+        "scdg_plan_create": (i32, [C.POINTER(vp), C.POINTER(Structure), vp]),
+        "scdg_plan_destroy": (i32, [vp]),
+        "scdg_set_stream": (i32, [vp, vp]),
+        "scdg_plan_sizes": (i32, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
+        "scdg_assemble": (i32, [vp, vp, vp, vp, vp]),
+        "scdg_factor": (i32, [vp, i32]),
+        "scdg_factor_info": (i32, [vp, C.POINTER(i64), C.POINTER(i32)]),
+        "scdg_condense": (i32, [vp]),
+        "scdg_condense_rhs": (i32, [vp, vp, vp]),
+        "scdg_solve_condensed": (i32, [vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
+        "scdg_backsolve": (i32, [vp, vp, vp, vp]),
+        "scdg_solve": (i32, [vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
+        "scdg_residual": (i32, [vp, vp, vp, vp, C.POINTER(d)]),
+        "scdg_schur_apply": (i32, [vp, vp, vp]),
+        "scdg_export": (i32, [vp, i32, vp, sz]),
+        "scdg_status_string": (C.c_char_p, [i32]),
+        "scdg_last_error": (i32, [vp, C.c_char_p, sz]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error(plan_handle) -> str:
+    lib = load()
+    buf = C.create_string_buffer(1024)
+    lib.scdg_last_error(plan_handle, buf, 1024)
+    return buf.value.decode(errors="replace")

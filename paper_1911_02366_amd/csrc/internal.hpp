@@ -1,0 +1,166 @@
+// Internal declarations of the scdg library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/scdg.h"
+
+namespace scdg {
+
+constexpr int kNvar = 5;
+constexpr int kMaxOrder = 7;
+
+// One GEMM problem of a batched launch: C = alpha A B + beta C, row-major with
+// leading dimensions; offsets are element offsets into the three base arrays.
+struct GemmDesc {
+  int64_t a_off, b_off, c_off;
+  int32_t m, n, k, lda, ldb, ldc;
+};
+
+// One tile of a batched GEMV: rows [row0, row0 + rows) of problem `prob`.
+struct RowTile {
+  int32_t prob, row0;
+};
+
+// One matrix-vector product y = M x for element e in a batched GEMV.
+struct GemvDesc {
+  int64_t m_off;   // offset of the row-major matrix
+  int32_t rows, cols;
+  int32_t x_off;   // offset into the x index map (or into x when no map)
+  int32_t y_off;   // offset into the y / y0 index space
+};
+
+template <typename T>
+struct DevBuf {
+  T *ptr = nullptr;
+  size_t count = 0;
+};
+
+struct Plan {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string last_error;
+  int state = 0;  // 0 created, 1 assembled, 2 factored, 3 condensed
+  scdg_precision prec = SCDG_FP64;
+
+  // structure
+  int32_t n_elem = 0;
+  std::vector<int32_t> order;
+  int64_t n_dof = 0, n1 = 0, n2 = 0, n_bnodes = 0, nnzb = 0;
+  std::vector<int32_t> ni, nc;          // DOF counts per element
+  std::vector<int64_t> off_q, off_ii, off_ib, off_cc, off_i, off_c, bnode_off;
+  int32_t max_ni = 0, max_nc = 0;
+
+  // device index maps
+  int32_t *d_imap = nullptr;      // [n2] natural DOF of each interior slot
+  int32_t *d_bmap = nullptr;      // [n1] natural DOF of each boundary slot
+  int32_t *d_cmap = nullptr;      // [sum n_c] boundary-vector index of each C slot
+  int32_t *d_pull_ptr = nullptr;  // [n_bnodes+1] C-slot lists per boundary node
+  int32_t *d_pull_idx = nullptr;  // C node-slot indices (sum |C_e| entries)
+  int64_t *d_slot_soff = nullptr; // [sum |C_e|] S_loc offset of the slot's element
+  int32_t *d_slot_nc = nullptr;   // [sum |C_e|] n_c of the slot's element
+  int32_t *d_slot_pos = nullptr;  // [sum |C_e|] position of the slot within C_e
+  int64_t *d_bb_rowptr = nullptr; // [n_bnodes+1]
+  int32_t *d_bb_col = nullptr;    // [nnzb]
+  int32_t *d_inv_n = nullptr;     // [n_elem] n_i per element
+  int64_t *d_inv_off = nullptr;   // [n_elem] offset of A_ii(e)
+  int32_t *d_info = nullptr;      // [n_elem] factor info
+
+  // batched GEMM descriptors and tile lists (X = Ainv A_ib, S_loc = A_bi X)
+  GemmDesc *d_gx = nullptr, *d_gs = nullptr;
+  int32_t *d_tiles_x = nullptr, *d_tiles_s = nullptr;
+  int32_t n_tiles_x = 0, n_tiles_s = 0;
+
+  // batched GEMV descriptors
+  GemvDesc *d_gv_inv = nullptr;  // Ainv (n_i x n_i), x: interior slots
+  GemvDesc *d_gv_abi = nullptr;  // A_bi (n_c x n_i)
+  GemvDesc *d_gv_aib = nullptr;  // A_ib / X (n_i x n_c)
+  GemvDesc *d_gv_s = nullptr;    // S_loc (n_c x n_c)
+  RowTile *d_rt_inv = nullptr, *d_rt_abi = nullptr, *d_rt_aib = nullptr, *d_rt_s = nullptr;
+  int32_t n_rt_inv = 0, n_rt_abi = 0, n_rt_aib = 0, n_rt_s = 0;
+
+  // borrowed FP64 blocks
+  const double *aii = nullptr, *aib = nullptr, *abi = nullptr, *bb_val = nullptr;
+
+  // factors and Schur blocks (precision = prec)
+  void *ainv = nullptr;   // sum n_i^2
+  void *xmat = nullptr;   // sum n_i n_c
+  void *sloc = nullptr;   // sum n_c^2
+  void *aib_lo = nullptr, *abi_lo = nullptr;  // FP32 shadows (FP32 mode)
+  double *diag_s = nullptr;  // [n1] diagonal of S
+  size_t cap_ainv = 0, cap_x = 0, cap_s = 0;  // bytes allocated
+
+  // dense S path
+  double *s_dense = nullptr;
+  int32_t *s_piv = nullptr;
+  int32_t *d_dense_info = nullptr;
+  bool dense_factored = false;
+
+  // work vectors (doubles)
+  double *w_z = nullptr;      // [n2]
+  double *w_t = nullptr;      // [sum n_c]
+  double *w_bs = nullptr;     // [n1]
+  double *w_qb = nullptr;     // [n1]
+  double *w_r = nullptr;      // [n_dof]
+  double *w_dq = nullptr;     // [n_dof]
+  double *w_vec = nullptr;    // [n_dof] scratch
+  double *gm_v = nullptr;     // [(m+1) * n1] Krylov basis
+  double *gm_w = nullptr;     // [n1]
+  double *gm_z = nullptr;     // [n1]
+  double *gm_part = nullptr;  // reduction partials
+  double *gm_h = nullptr;     // [m+2] device h column
+  double *h_pinned = nullptr; // host pinned staging
+  int32_t gm_m = 0;
+  int32_t red_blocks = 0;
+};
+
+// ---- kernel launchers (implemented in the .hip files) ----
+hipError_t launch_gj_inverse(Plan &p, void *w, bool fp32);
+hipError_t launch_cast_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
+hipError_t launch_copy_f64(const double *src, double *dst, size_t n, hipStream_t s);
+hipError_t launch_gemm_batched(const GemmDesc *d_desc, const int32_t *d_tiles, int32_t n_tiles,
+                               const void *a, const void *b, void *c, double alpha, double beta,
+                               bool fp32, hipStream_t s);
+int gemm_tile_m();
+int gemm_tile_n();
+
+// y[omap?omap[y_off+r]:y_off+r] = alpha * sum_c M[r,c] x[xmap?xmap[x_off+c]:x_off+c]
+//                                 + beta * y0[y_off + r]
+hipError_t launch_gemv_batched(const GemvDesc *d_desc, const RowTile *d_tiles, int32_t n_tiles,
+                               int32_t max_cols, const void *mat, bool fp32, const double *x,
+                               const int32_t *xmap, double *y, const int32_t *omap, double alpha,
+                               double beta, const double *y0, hipStream_t s);
+
+// out[j] = c0 * src0[map0 ? map0[j] : j] + c1 * (A_bb x)[j] + c2 * sum_{s in pull(j/5)} t[5 s + j%5]
+hipError_t launch_bsr_pull(const Plan &p, double c0, const double *src0, const int32_t *map0,
+                           double c1, const double *x, double c2, const double *t, double *out);
+
+hipError_t launch_gather(const double *src, const int32_t *map, double *dst, int64_t n, hipStream_t s);
+hipError_t launch_scatter(const double *src, const int32_t *map, double *dst, int64_t n, hipStream_t s);
+hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+hipError_t launch_scatter_axpby(int64_t n, double a, const double *x, double b, const double *yin,
+                                const int32_t *map, double *dst, hipStream_t s);
+
+// multi-dot: out[k] = sum_i V[k*ld + i] w[i], k < nv (deterministic two-stage)
+hipError_t launch_multidot(const double *v, int64_t ld, int32_t nv, const double *w, int64_t n,
+                           double *partials, int32_t nblocks, double *out, hipStream_t s);
+// w -= sum_k V[k*ld+i] h[k]
+hipError_t launch_multi_axpy(const double *v, int64_t ld, int32_t nv, const double *h, double *w,
+                             int64_t n, hipStream_t s);
+// y = x * dinv (elementwise); dinv may be null (copy)
+hipError_t launch_diag_scale(const double *x, const double *dinv, double *y, int64_t n, double a,
+                             hipStream_t s);
+hipError_t launch_diag_schur(const Plan &p, const void *sloc, bool fp32, double *diag);
+hipError_t launch_reciprocal(double *x, int64_t n, hipStream_t s);
+
+// dense path
+hipError_t launch_dense_assemble(const Plan &p, double *s_dense);
+hipError_t launch_dense_lu(Plan &p, double *a, int32_t n, int32_t *piv, int32_t *info);
+hipError_t launch_dense_solve(const double *lu, int32_t n, const int32_t *piv, double *x,
+                              hipStream_t s);
+
+}  // namespace scdg

@@ -1,0 +1,864 @@
+// C ABI of the scdg library: plan construction (index maps of the interior /
+// boundary partition), state machine, and the orchestration of the kernels
+// for factor / condense / condensed RHS / condensed solve / back-substitution
+// / full residual and iterative refinement.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace scdg;
+
+struct scdg_plan {
+  Plan p;
+};
+
+namespace {
+
+std::string g_create_error;
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      p.last_error = std::string(#expr) + ": " + hipGetErrorString(e_);           \
+      return SCDG_ERR_HIP;                                                         \
+    }                                                                              \
+  } while (0)
+
+#define ST_TRY(expr)                   \
+  do {                                 \
+    scdg_status s_ = (expr);           \
+    if (s_ != SCDG_OK) return s_;      \
+  } while (0)
+
+template <typename T>
+scdg_status dalloc(Plan &p, T **ptr, size_t count) {
+  if (*ptr) {
+    (void)hipFree(*ptr);
+    *ptr = nullptr;
+  }
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(ptr), sizeof(T) * count);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    p.last_error = std::string("hipMalloc of ") + std::to_string(sizeof(T) * count) +
+                   " bytes: " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? SCDG_ERR_NOMEM : SCDG_ERR_HIP;
+  }
+  return SCDG_OK;
+}
+
+template <typename T>
+scdg_status upload(Plan &p, T **ptr, const std::vector<T> &host) {
+  ST_TRY(dalloc(p, ptr, host.size()));
+  if (!host.empty()) HIP_TRY(hipMemcpy(*ptr, host.data(), sizeof(T) * host.size(), hipMemcpyHostToDevice));
+  return SCDG_OK;
+}
+
+template <typename T>
+void dfree(T *&ptr) {
+  if (ptr) (void)hipFree(const_cast<void *>(reinterpret_cast<const void *>(ptr)));
+  ptr = nullptr;
+}
+
+void local_node_sets(int order, std::vector<int> &interior, std::vector<int> &boundary) {
+  const int p = order + 1;
+  interior.clear();
+  boundary.clear();
+  for (int k = 0; k < p; ++k)
+    for (int j = 0; j < p; ++j)
+      for (int i = 0; i < p; ++i) {
+        const int n = i + p * j + p * p * k;
+        const bool in = i >= 1 && i <= order - 1 && j >= 1 && j <= order - 1 && k >= 1 &&
+                        k <= order - 1;
+        (in ? interior : boundary).push_back(n);
+      }
+}
+
+// Tile list ordered so that the workgroups of one problem share an XCD: block b
+// runs on XCD b % 8, so block b takes tile (b % 8) * per + b / 8 of the
+// problem-major list.
+std::vector<int32_t> xcd_tile_list(const std::vector<GemmDesc> &descs, int bm, int bn) {
+  std::vector<int32_t> flat;
+  for (size_t q = 0; q < descs.size(); ++q) {
+    const int tm = (descs[q].m + bm - 1) / bm, tn = (descs[q].n + bn - 1) / bn;
+    for (int a = 0; a < tm; ++a)
+      for (int b = 0; b < tn; ++b) {
+        flat.push_back((int32_t)q);
+        flat.push_back(a);
+        flat.push_back(b);
+      }
+  }
+  const int64_t total = (int64_t)flat.size() / 3;
+  const int64_t per = (total + 7) / 8;
+  std::vector<int32_t> out(3 * 8 * per, -1);
+  for (int64_t blk = 0; blk < 8 * per; ++blk) {
+    const int64_t t = (blk % 8) * per + blk / 8;
+    if (t < total) std::memcpy(&out[3 * blk], &flat[3 * t], 3 * sizeof(int32_t));
+  }
+  return out;
+}
+
+std::vector<RowTile> row_tiles(const std::vector<GemvDesc> &descs) {
+  std::vector<RowTile> t;
+  for (size_t q = 0; q < descs.size(); ++q)
+    for (int r = 0; r < descs[q].rows; r += 64) t.push_back(RowTile{(int32_t)q, r});
+  return t;
+}
+
+bool fp32(const Plan &p) { return p.prec == SCDG_FP32; }
+size_t esize(const Plan &p) { return fp32(p) ? sizeof(float) : sizeof(double); }
+
+scdg_status sync(Plan &p) {
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  return SCDG_OK;
+}
+
+// ||x||_2^2 of a device vector, result on host (synchronizes)
+scdg_status norm2sq(Plan &p, const double *x, int64_t n, double *out) {
+  HIP_TRY(launch_multidot(x, 0, 1, x, n, p.gm_part, p.red_blocks, p.gm_h, p.stream));
+  HIP_TRY(hipMemcpyAsync(p.h_pinned, p.gm_h, sizeof(double), hipMemcpyDeviceToHost, p.stream));
+  ST_TRY(sync(p));
+  *out = p.h_pinned[0];
+  return SCDG_OK;
+}
+
+// ---- stage helpers (all enqueue on p.stream) ----
+
+// z = A_ii^-1 B_i for every element (B natural)
+scdg_status apply_inverse(Plan &p, const double *b_nat, double *z) {
+  HIP_TRY(launch_gemv_batched(p.d_gv_inv, p.d_rt_inv, p.n_rt_inv, p.max_ni, p.ainv, fp32(p), b_nat,
+                              p.d_imap, z, nullptr, 1.0, 0.0, nullptr, p.stream));
+  return SCDG_OK;
+}
+
+scdg_status condense_rhs_impl(Plan &p, const double *b, double *bs) {
+  ST_TRY(apply_inverse(p, b, p.w_z));
+  const void *abi = fp32(p) ? p.abi_lo : static_cast<const void *>(p.abi);
+  HIP_TRY(launch_gemv_batched(p.d_gv_abi, p.d_rt_abi, p.n_rt_abi, p.max_ni, abi, fp32(p), p.w_z,
+                              nullptr, p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream));
+  HIP_TRY(launch_bsr_pull(p, 1.0, b, p.d_bmap, 0.0, nullptr, -1.0, p.w_t, bs));
+  return SCDG_OK;
+}
+
+scdg_status schur_apply_impl(Plan &p, const double *x, double *y) {
+  HIP_TRY(launch_gemv_batched(p.d_gv_s, p.d_rt_s, p.n_rt_s, p.max_nc, p.sloc, fp32(p), x, p.d_cmap,
+                              p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream));
+  HIP_TRY(launch_bsr_pull(p, 0.0, nullptr, nullptr, 1.0, x, -1.0, p.w_t, y));
+  return SCDG_OK;
+}
+
+scdg_status backsolve_impl(Plan &p, const double *b, const double *qb, double *dq) {
+  ST_TRY(apply_inverse(p, b, p.w_z));
+  HIP_TRY(launch_gemv_batched(p.d_gv_aib, p.d_rt_aib, p.n_rt_aib, p.max_nc, p.xmat, fp32(p), qb,
+                              p.d_cmap, dq, p.d_imap, -1.0, 1.0, p.w_z, p.stream));
+  HIP_TRY(launch_scatter(qb, p.d_bmap, dq, p.n1, p.stream));
+  return SCDG_OK;
+}
+
+// r = B - A dQ on the full FP64 system (r, B, dQ natural vectors)
+scdg_status residual_impl(Plan &p, const double *b, const double *dq, double *r) {
+  // interior rows: u = A_ii dQ_i + A_ib dQ_b[C_e]
+  HIP_TRY(launch_gather(dq, p.d_bmap, p.w_qb, p.n1, p.stream));
+  HIP_TRY(launch_gemv_batched(p.d_gv_inv, p.d_rt_inv, p.n_rt_inv, p.max_ni, p.aii, false, dq,
+                              p.d_imap, p.w_z, nullptr, 1.0, 0.0, nullptr, p.stream));
+  HIP_TRY(launch_gemv_batched(p.d_gv_aib, p.d_rt_aib, p.n_rt_aib, p.max_nc, p.aib, false, p.w_qb,
+                              p.d_cmap, p.w_z, nullptr, 1.0, 1.0, p.w_z, p.stream));
+  HIP_TRY(launch_scatter_axpby(p.n2, 1.0, b, -1.0, p.w_z, p.d_imap, r, p.stream));
+  // boundary rows: B_b - A_bb dQ_b - pull(A_bi dQ_i)
+  HIP_TRY(launch_gemv_batched(p.d_gv_abi, p.d_rt_abi, p.n_rt_abi, p.max_ni, p.abi, false, dq,
+                              p.d_imap, p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream));
+  HIP_TRY(launch_bsr_pull(p, 1.0, b, p.d_bmap, -1.0, p.w_qb, -1.0, p.w_t, p.w_bs));
+  HIP_TRY(launch_scatter(p.w_bs, p.d_bmap, r, p.n1, p.stream));
+  return SCDG_OK;
+}
+
+scdg_status ensure_gmres(Plan &p, int m) {
+  if (p.gm_v && p.gm_m >= m) return SCDG_OK;
+  ST_TRY(dalloc(p, &p.gm_v, (size_t)(m + 1) * p.n1));
+  p.gm_m = m;
+  return SCDG_OK;
+}
+
+scdg_status gmres(Plan &p, const double *bs, double *x, const double *x0, const scdg_solve_opts &o,
+                  scdg_solve_info &info) {
+  const int64_t n = p.n1;
+  const int m = o.restart;
+  ST_TRY(ensure_gmres(p, m));
+  const double *dinv = o.precond ? p.diag_s : nullptr;  // diag_s holds 1 / diag(S)
+  double bnorm2;
+  ST_TRY(norm2sq(p, bs, n, &bnorm2));
+  if (!std::isfinite(bnorm2)) {
+    p.last_error = "non-finite condensed right-hand side";
+    return SCDG_ERR_NONFINITE;
+  }
+  const double bnorm = std::sqrt(bnorm2);
+  if (bnorm == 0.0) {
+    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, p.stream));
+    info.rel_res_S = 0.0;
+    return SCDG_OK;
+  }
+  double *r = p.gm_w;
+  if (x0) {
+    if (x0 != x) HIP_TRY(hipMemcpyAsync(x, x0, sizeof(double) * n, hipMemcpyDeviceToDevice, p.stream));
+    ST_TRY(schur_apply_impl(p, x, r));
+    HIP_TRY(launch_axpby(n, 1.0, bs, -1.0, r, p.stream));  // r = bs - S x
+  } else {
+    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, p.stream));
+    HIP_TRY(hipMemcpyAsync(r, bs, sizeof(double) * n, hipMemcpyDeviceToDevice, p.stream));
+  }
+  double beta2;
+  ST_TRY(norm2sq(p, r, n, &beta2));
+  double beta = std::sqrt(beta2);
+  std::vector<double> h((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  int it = 0;
+  const double target = o.tol * bnorm;
+  while (it < o.max_iters && beta > target) {
+    if (!std::isfinite(beta)) {
+      p.last_error = "non-finite GMRES residual";
+      return SCDG_ERR_NONFINITE;
+    }
+    ++info.restarts;
+    HIP_TRY(launch_diag_scale(r, nullptr, p.gm_v, n, 1.0 / beta, p.stream));
+    std::fill(h.begin(), h.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jused = 0;
+    for (int j = 0; j < m && it < o.max_iters; ++j) {
+      double *vj = p.gm_v + (int64_t)j * n;
+      double *w = p.gm_w;
+      HIP_TRY(launch_diag_scale(vj, dinv, p.gm_z, n, 1.0, p.stream));
+      ST_TRY(schur_apply_impl(p, p.gm_z, w));
+      // classical Gram-Schmidt, twice (FP64)
+      HIP_TRY(launch_multidot(p.gm_v, n, j + 1, w, n, p.gm_part, p.red_blocks, p.gm_h, p.stream));
+      HIP_TRY(launch_multi_axpy(p.gm_v, n, j + 1, p.gm_h, w, n, p.stream));
+      HIP_TRY(launch_multidot(p.gm_v, n, j + 1, w, n, p.gm_part, p.red_blocks, p.gm_h + (m + 1),
+                              p.stream));
+      HIP_TRY(launch_multi_axpy(p.gm_v, n, j + 1, p.gm_h + (m + 1), w, n, p.stream));
+      HIP_TRY(launch_multidot(w, 0, 1, w, n, p.gm_part, p.red_blocks, p.gm_h + 2 * (m + 1), p.stream));
+      HIP_TRY(hipMemcpyAsync(p.h_pinned, p.gm_h, sizeof(double) * 3 * (m + 1), hipMemcpyDeviceToHost,
+                             p.stream));
+      ST_TRY(sync(p));
+      for (int i = 0; i <= j; ++i) h[(size_t)i * m + j] = p.h_pinned[i] + p.h_pinned[(m + 1) + i];
+      const double hn = std::sqrt(std::max(0.0, p.h_pinned[2 * (m + 1)]));
+      h[(size_t)(j + 1) * m + j] = hn;
+      if (hn > 0.0)
+        HIP_TRY(launch_diag_scale(w, nullptr, p.gm_v + (int64_t)(j + 1) * n, n, 1.0 / hn, p.stream));
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[(size_t)i * m + j] + sn[i] * h[(size_t)(i + 1) * m + j];
+        h[(size_t)(i + 1) * m + j] = -sn[i] * h[(size_t)i * m + j] + cs[i] * h[(size_t)(i + 1) * m + j];
+        h[(size_t)i * m + j] = t;
+      }
+      const double den = std::hypot(h[(size_t)j * m + j], hn);
+      cs[j] = den > 0 ? h[(size_t)j * m + j] / den : 1.0;
+      sn[j] = den > 0 ? hn / den : 0.0;
+      h[(size_t)j * m + j] = den;
+      h[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      jused = j + 1;
+      info.rel_res_S = std::fabs(g[j + 1]) / bnorm;
+      if (std::fabs(g[j + 1]) <= target || hn == 0.0) break;
+    }
+    for (int i = jused - 1; i >= 0; --i) {
+      double v = g[i];
+      for (int q = i + 1; q < jused; ++q) v -= h[(size_t)i * m + q] * y[q];
+      y[i] = v / h[(size_t)i * m + i];
+    }
+    // x += Dinv (V y): accumulate V y into z with negated coefficients
+    for (int i = 0; i < jused; ++i) p.h_pinned[i] = -y[i];
+    HIP_TRY(hipMemcpyAsync(p.gm_h, p.h_pinned, sizeof(double) * jused, hipMemcpyHostToDevice, p.stream));
+    HIP_TRY(hipMemsetAsync(p.gm_z, 0, sizeof(double) * n, p.stream));
+    HIP_TRY(launch_multi_axpy(p.gm_v, n, jused, p.gm_h, p.gm_z, n, p.stream));
+    HIP_TRY(launch_diag_scale(p.gm_z, dinv, p.gm_z, n, 1.0, p.stream));
+    HIP_TRY(launch_axpby(n, 1.0, p.gm_z, 1.0, x, p.stream));
+    // true residual
+    ST_TRY(schur_apply_impl(p, x, r));
+    HIP_TRY(launch_axpby(n, 1.0, bs, -1.0, r, p.stream));
+    ST_TRY(norm2sq(p, r, n, &beta2));
+    beta = std::sqrt(beta2);
+    info.rel_res_S = beta / bnorm;
+  }
+  info.iters += it;
+  if (beta > target) {
+    p.last_error = "GMRES did not reach the tolerance";
+    return SCDG_ERR_NOCONV;
+  }
+  return SCDG_OK;
+}
+
+scdg_status dense_solve(Plan &p, const double *bs, double *x) {
+  if (!p.dense_factored) {
+    ST_TRY(dalloc(p, &p.s_dense, (size_t)p.n1 * p.n1));
+    ST_TRY(dalloc(p, &p.s_piv, (size_t)p.n1));
+    ST_TRY(dalloc(p, &p.d_dense_info, 1));
+    HIP_TRY(launch_dense_assemble(p, p.s_dense));
+    HIP_TRY(launch_dense_lu(p, p.s_dense, (int32_t)p.n1, p.s_piv, p.d_dense_info));
+    int32_t info = 0;
+    HIP_TRY(hipMemcpy(&info, p.d_dense_info, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (info != 0) {
+      p.last_error = "zero pivot in the dense LU of S at step " + std::to_string(info);
+      return SCDG_ERR_SINGULAR;
+    }
+    p.dense_factored = true;
+  }
+  if (x != bs) HIP_TRY(hipMemcpyAsync(x, bs, sizeof(double) * p.n1, hipMemcpyDeviceToDevice, p.stream));
+  HIP_TRY(launch_dense_solve(p.s_dense, (int32_t)p.n1, p.s_piv, x, p.stream));
+  return SCDG_OK;
+}
+
+void defaults(scdg_solve_opts &o) {
+  if (o.restart <= 0) o.restart = 30;
+  if (o.max_iters <= 0) o.max_iters = 1000;
+  if (o.tol <= 0) o.tol = 1e-10;
+  if (o.precond < 0) o.precond = 1;
+  if (o.ir_max <= 0) o.ir_max = 10;
+  if (o.ir_tol <= 0) o.ir_tol = 1e-8;
+}
+
+scdg_status solve_condensed_impl(Plan &p, const double *bs, double *qb, const double *x0,
+                                 const scdg_solve_opts &o, scdg_solve_info &info) {
+  int solver = o.solver;
+  if (solver == SCDG_SOLVER_AUTO) solver = p.n1 <= 8192 ? SCDG_SOLVER_DENSE : SCDG_SOLVER_GMRES;
+  info.solver_used = solver;
+  if (solver == SCDG_SOLVER_DENSE) {
+    if (p.n1 > 40000) {
+      p.last_error = "dense solve of S limited to n1 <= 40000";
+      return SCDG_ERR_UNSUPPORTED;
+    }
+    info.rel_res_S = 0.0;
+    return dense_solve(p, bs, qb);
+  }
+  if (solver != SCDG_SOLVER_GMRES) {
+    p.last_error = "unknown solver";
+    return SCDG_ERR_ARG;
+  }
+  return gmres(p, bs, qb, x0, o, info);
+}
+
+}  // namespace
+
+// =====================================================================
+extern "C" {
+
+const char *scdg_status_string(scdg_status s) {
+  switch (s) {
+    case SCDG_OK: return "ok";
+    case SCDG_ERR_ARG: return "invalid argument";
+    case SCDG_ERR_STATE: return "call out of order";
+    case SCDG_ERR_HIP: return "HIP runtime error";
+    case SCDG_ERR_NOMEM: return "out of device memory";
+    case SCDG_ERR_SINGULAR: return "singular pivot";
+    case SCDG_ERR_NOCONV: return "no convergence";
+    case SCDG_ERR_NONFINITE: return "non-finite value";
+    case SCDG_ERR_UNSUPPORTED: return "unsupported size or order";
+  }
+  return "unknown status";
+}
+
+scdg_status scdg_last_error(const scdg_plan *pl, char *buf, size_t n) {
+  if (!buf || n == 0) return SCDG_ERR_ARG;
+  const std::string &s = pl ? pl->p.last_error : g_create_error;
+  std::snprintf(buf, n, "%s", s.c_str());
+  return SCDG_OK;
+}
+
+scdg_status scdg_plan_destroy(scdg_plan *pl) {
+  if (!pl) return SCDG_OK;
+  Plan &p = pl->p;
+  (void)hipStreamSynchronize(p.stream);
+  dfree(p.d_imap); dfree(p.d_bmap); dfree(p.d_cmap); dfree(p.d_pull_ptr); dfree(p.d_pull_idx);
+  dfree(p.d_slot_soff); dfree(p.d_slot_nc); dfree(p.d_slot_pos);
+  dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_info);
+  dfree(p.d_gx); dfree(p.d_gs); dfree(p.d_tiles_x); dfree(p.d_tiles_s);
+  dfree(p.d_gv_inv); dfree(p.d_gv_abi); dfree(p.d_gv_aib); dfree(p.d_gv_s);
+  dfree(p.d_rt_inv); dfree(p.d_rt_abi); dfree(p.d_rt_aib); dfree(p.d_rt_s);
+  dfree(p.ainv); dfree(p.xmat); dfree(p.sloc); dfree(p.aib_lo); dfree(p.abi_lo); dfree(p.diag_s);
+  dfree(p.s_dense); dfree(p.s_piv); dfree(p.d_dense_info);
+  dfree(p.w_z); dfree(p.w_t); dfree(p.w_bs); dfree(p.w_qb); dfree(p.w_r); dfree(p.w_dq); dfree(p.w_vec);
+  dfree(p.gm_v); dfree(p.gm_w); dfree(p.gm_z); dfree(p.gm_part); dfree(p.gm_h);
+  if (p.h_pinned) (void)hipHostFree(p.h_pinned);
+  delete pl;
+  return SCDG_OK;
+}
+
+scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip_stream) {
+  if (!out || !s || !s->order || !s->c_ptr || !s->c_node || !s->bb_rowptr || s->n_elem <= 0) {
+    g_create_error = "null pointer or empty mesh in scdg_structure";
+    return SCDG_ERR_ARG;
+  }
+  *out = nullptr;
+  scdg_plan *pl = new (std::nothrow) scdg_plan();
+  if (!pl) return SCDG_ERR_NOMEM;
+  Plan &p = pl->p;
+  p.stream = static_cast<hipStream_t>(hip_stream);
+  (void)hipGetDevice(&p.device);
+  const int E = s->n_elem;
+  p.n_elem = E;
+  p.order.assign(s->order, s->order + E);
+  p.ni.resize(E); p.nc.resize(E);
+  p.off_q.resize(E + 1); p.off_ii.resize(E + 1); p.off_ib.resize(E + 1); p.off_cc.resize(E + 1);
+  p.off_i.resize(E + 1); p.off_c.resize(E + 1); p.bnode_off.resize(E + 1);
+  p.off_q[0] = p.off_ii[0] = p.off_ib[0] = p.off_cc[0] = p.off_i[0] = p.off_c[0] = p.bnode_off[0] = 0;
+  for (int e = 0; e < E; ++e) {
+    const int N = p.order[e];
+    if (N < 2 || N > kMaxOrder) {
+      g_create_error = "element order outside 2..7";
+      delete pl;
+      return SCDG_ERR_UNSUPPORTED;
+    }
+    const int64_t cnt = s->c_ptr[e + 1] - s->c_ptr[e];
+    if (cnt <= 0 || s->c_ptr[e] < 0) {
+      g_create_error = "c_ptr must be increasing with non-empty coupling sets";
+      delete pl;
+      return SCDG_ERR_ARG;
+    }
+    const int P = N + 1;
+    p.ni[e] = kNvar * (N - 1) * (N - 1) * (N - 1);
+    p.nc[e] = (int32_t)(kNvar * cnt);
+    p.off_q[e + 1] = p.off_q[e] + (int64_t)kNvar * P * P * P;
+    p.off_ii[e + 1] = p.off_ii[e] + (int64_t)p.ni[e] * p.ni[e];
+    p.off_ib[e + 1] = p.off_ib[e] + (int64_t)p.ni[e] * p.nc[e];
+    p.off_cc[e + 1] = p.off_cc[e] + (int64_t)p.nc[e] * p.nc[e];
+    p.off_i[e + 1] = p.off_i[e] + p.ni[e];
+    p.off_c[e + 1] = p.off_c[e] + p.nc[e];
+    p.bnode_off[e + 1] = p.bnode_off[e] + (int64_t)P * P * P - (int64_t)(N - 1) * (N - 1) * (N - 1);
+    p.max_ni = std::max(p.max_ni, p.ni[e]);
+    p.max_nc = std::max(p.max_nc, p.nc[e]);
+  }
+  p.n_dof = p.off_q[E];
+  p.n2 = p.off_i[E];
+  p.n_bnodes = p.bnode_off[E];
+  p.n1 = kNvar * p.n_bnodes;
+  if (p.n_dof >= (int64_t)INT32_MAX || p.off_c[E] >= (int64_t)INT32_MAX) {
+    g_create_error = "problem too large for 32-bit DOF indices";
+    delete pl;
+    return SCDG_ERR_UNSUPPORTED;
+  }
+  p.nnzb = s->bb_rowptr[p.n_bnodes];
+  if (p.nnzb < 0 || (p.nnzb > 0 && !s->bb_col)) {
+    g_create_error = "bad A_bb pattern";
+    delete pl;
+    return SCDG_ERR_ARG;
+  }
+  for (int64_t g = 0; g < p.n_bnodes; ++g)
+    if (s->bb_rowptr[g + 1] < s->bb_rowptr[g]) {
+      g_create_error = "bb_rowptr not monotone";
+      delete pl;
+      return SCDG_ERR_ARG;
+    }
+  for (int64_t t = 0; t < p.nnzb; ++t)
+    if (s->bb_col[t] < 0 || s->bb_col[t] >= p.n_bnodes) {
+      g_create_error = "bb_col out of range";
+      delete pl;
+      return SCDG_ERR_ARG;
+    }
+
+  // ---- index maps (a1) ----
+  std::vector<int32_t> imap(p.n2), bmap(p.n1), cmap(p.off_c[E]);
+  std::vector<int> in_nodes, b_nodes;
+  std::vector<int32_t> pull_cnt(p.n_bnodes + 1, 0);
+  int cur_order = -1;
+  for (int e = 0; e < E; ++e) {
+    if (p.order[e] != cur_order) {
+      local_node_sets(p.order[e], in_nodes, b_nodes);
+      cur_order = p.order[e];
+    }
+    for (size_t t = 0; t < in_nodes.size(); ++t)
+      for (int v = 0; v < kNvar; ++v)
+        imap[p.off_i[e] + kNvar * t + v] = (int32_t)(p.off_q[e] + kNvar * in_nodes[t] + v);
+    for (size_t r = 0; r < b_nodes.size(); ++r)
+      for (int v = 0; v < kNvar; ++v)
+        bmap[kNvar * (p.bnode_off[e] + r) + v] = (int32_t)(p.off_q[e] + kNvar * b_nodes[r] + v);
+    const int64_t c0 = s->c_ptr[e], c1 = s->c_ptr[e + 1];
+    for (int64_t q = c0; q < c1; ++q) {
+      const int32_t g = s->c_node[q];
+      if (g < 0 || g >= p.n_bnodes || (q > c0 && s->c_node[q - 1] >= g)) {
+        g_create_error = "c_node entries must be ascending boundary ids within range";
+        delete pl;
+        return SCDG_ERR_ARG;
+      }
+      for (int v = 0; v < kNvar; ++v) cmap[p.off_c[e] + kNvar * (q - c0) + v] = kNvar * g + v;
+      pull_cnt[g + 1]++;
+    }
+  }
+  const int64_t n_slots = p.off_c[E] / kNvar;
+  std::vector<int32_t> pull_ptr(p.n_bnodes + 1, 0), pull_idx(n_slots);
+  for (int64_t g = 0; g < p.n_bnodes; ++g) pull_ptr[g + 1] = pull_ptr[g] + pull_cnt[g + 1];
+  std::vector<int32_t> fill(pull_ptr.begin(), pull_ptr.end() - 1);
+  std::vector<int64_t> slot_soff(n_slots);
+  std::vector<int32_t> slot_nc(n_slots), slot_pos(n_slots);
+  for (int e = 0; e < E; ++e) {
+    const int64_t c0 = s->c_ptr[e];
+    for (int64_t q = c0; q < s->c_ptr[e + 1]; ++q) {
+      const int64_t slot = p.off_c[e] / kNvar + (q - c0);
+      pull_idx[fill[s->c_node[q]]++] = (int32_t)slot;
+      slot_soff[slot] = p.off_cc[e];
+      slot_nc[slot] = p.nc[e];
+      slot_pos[slot] = (int32_t)(q - c0);
+    }
+  }
+  std::vector<int64_t> bb_rowptr(s->bb_rowptr, s->bb_rowptr + p.n_bnodes + 1);
+  std::vector<int32_t> bb_col(s->bb_col, s->bb_col + p.nnzb);
+  std::vector<int32_t> inv_n(p.ni.begin(), p.ni.end());
+  std::vector<int64_t> inv_off(p.off_ii.begin(), p.off_ii.end() - 1);
+
+  // ---- GEMM / GEMV work lists ----
+  std::vector<GemmDesc> gx(E), gs(E);
+  std::vector<GemvDesc> gv_inv(E), gv_abi(E), gv_aib(E), gv_s(E);
+  for (int e = 0; e < E; ++e) {
+    const int ni = p.ni[e], nc = p.nc[e];
+    gx[e] = GemmDesc{p.off_ii[e], p.off_ib[e], p.off_ib[e], ni, nc, ni, ni, nc, nc};
+    gs[e] = GemmDesc{p.off_ib[e], p.off_ib[e], p.off_cc[e], nc, nc, ni, ni, nc, nc};
+    gv_inv[e] = GemvDesc{p.off_ii[e], ni, ni, (int32_t)p.off_i[e], (int32_t)p.off_i[e]};
+    gv_abi[e] = GemvDesc{p.off_ib[e], nc, ni, (int32_t)p.off_i[e], (int32_t)p.off_c[e]};
+    gv_aib[e] = GemvDesc{p.off_ib[e], ni, nc, (int32_t)p.off_c[e], (int32_t)p.off_i[e]};
+    gv_s[e] = GemvDesc{p.off_cc[e], nc, nc, (int32_t)p.off_c[e], (int32_t)p.off_c[e]};
+  }
+  std::vector<int32_t> tiles_x = xcd_tile_list(gx, gemm_tile_m(), gemm_tile_n());
+  std::vector<int32_t> tiles_s = xcd_tile_list(gs, gemm_tile_m(), gemm_tile_n());
+  p.n_tiles_x = (int32_t)(tiles_x.size() / 3);
+  p.n_tiles_s = (int32_t)(tiles_s.size() / 3);
+  std::vector<RowTile> rt_inv = row_tiles(gv_inv), rt_abi = row_tiles(gv_abi),
+                       rt_aib = row_tiles(gv_aib), rt_s = row_tiles(gv_s);
+  p.n_rt_inv = (int32_t)rt_inv.size();
+  p.n_rt_abi = (int32_t)rt_abi.size();
+  p.n_rt_aib = (int32_t)rt_aib.size();
+  p.n_rt_s = (int32_t)rt_s.size();
+
+  scdg_status st = SCDG_OK;
+  auto chk = [&](scdg_status x) { if (st == SCDG_OK) st = x; };
+  chk(upload(p, &p.d_imap, imap));
+  chk(upload(p, &p.d_bmap, bmap));
+  chk(upload(p, &p.d_cmap, cmap));
+  chk(upload(p, &p.d_pull_ptr, pull_ptr));
+  chk(upload(p, &p.d_pull_idx, pull_idx));
+  chk(upload(p, &p.d_slot_soff, slot_soff));
+  chk(upload(p, &p.d_slot_nc, slot_nc));
+  chk(upload(p, &p.d_slot_pos, slot_pos));
+  chk(upload(p, &p.d_bb_rowptr, bb_rowptr));
+  chk(upload(p, &p.d_bb_col, bb_col));
+  chk(upload(p, &p.d_inv_n, inv_n));
+  chk(upload(p, &p.d_inv_off, inv_off));
+  chk(dalloc(p, &p.d_info, (size_t)E));
+  chk(upload(p, &p.d_gx, gx));
+  chk(upload(p, &p.d_gs, gs));
+  chk(upload(p, &p.d_tiles_x, tiles_x));
+  chk(upload(p, &p.d_tiles_s, tiles_s));
+  chk(upload(p, &p.d_gv_inv, gv_inv));
+  chk(upload(p, &p.d_gv_abi, gv_abi));
+  chk(upload(p, &p.d_gv_aib, gv_aib));
+  chk(upload(p, &p.d_gv_s, gv_s));
+  chk(upload(p, &p.d_rt_inv, rt_inv));
+  chk(upload(p, &p.d_rt_abi, rt_abi));
+  chk(upload(p, &p.d_rt_aib, rt_aib));
+  chk(upload(p, &p.d_rt_s, rt_s));
+  chk(dalloc(p, &p.w_z, (size_t)p.n2));
+  chk(dalloc(p, &p.w_t, (size_t)p.off_c[E]));
+  chk(dalloc(p, &p.w_bs, (size_t)p.n1));
+  chk(dalloc(p, &p.w_qb, (size_t)p.n1));
+  chk(dalloc(p, &p.w_r, (size_t)p.n_dof));
+  chk(dalloc(p, &p.w_dq, (size_t)p.n_dof));
+  chk(dalloc(p, &p.w_vec, (size_t)p.n_dof));
+  chk(dalloc(p, &p.gm_w, (size_t)p.n1));
+  chk(dalloc(p, &p.gm_z, (size_t)p.n1));
+  chk(dalloc(p, &p.diag_s, (size_t)p.n1));
+  p.red_blocks = 512;
+  chk(dalloc(p, &p.gm_part, (size_t)p.red_blocks * 64));
+  chk(dalloc(p, &p.gm_h, (size_t)3 * 64));
+  if (st == SCDG_OK) {
+    if (hipHostMalloc(reinterpret_cast<void **>(&p.h_pinned), sizeof(double) * 3 * 64) != hipSuccess) {
+      p.last_error = "pinned host allocation failed";
+      st = SCDG_ERR_NOMEM;
+    }
+  }
+  if (st != SCDG_OK) {
+    g_create_error = p.last_error;
+    scdg_plan_destroy(pl);
+    return st;
+  }
+  *out = pl;
+  return SCDG_OK;
+}
+
+scdg_status scdg_set_stream(scdg_plan *pl, void *hip_stream) {
+  if (!pl) return SCDG_ERR_ARG;
+  pl->p.stream = static_cast<hipStream_t>(hip_stream);
+  return SCDG_OK;
+}
+
+scdg_status scdg_plan_sizes(const scdg_plan *pl, int64_t *n_dof, int64_t *n1, int64_t *n2,
+                            int64_t *n_bnodes) {
+  if (!pl) return SCDG_ERR_ARG;
+  if (n_dof) *n_dof = pl->p.n_dof;
+  if (n1) *n1 = pl->p.n1;
+  if (n2) *n2 = pl->p.n2;
+  if (n_bnodes) *n_bnodes = pl->p.n_bnodes;
+  return SCDG_OK;
+}
+
+scdg_status scdg_assemble(scdg_plan *pl, const double *aii, const double *aib, const double *abi,
+                          const double *bb_val) {
+  if (!pl || !aii || !aib || !abi || (pl->p.nnzb > 0 && !bb_val)) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  p.aii = aii;
+  p.aib = aib;
+  p.abi = abi;
+  p.bb_val = bb_val;
+  p.state = 1;
+  p.dense_factored = false;
+  return SCDG_OK;
+}
+
+scdg_status scdg_factor(scdg_plan *pl, scdg_precision prec) {
+  if (!pl) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 1) {
+    p.last_error = "scdg_factor before scdg_assemble";
+    return SCDG_ERR_STATE;
+  }
+  if (prec != SCDG_FP64 && prec != SCDG_FP32) return SCDG_ERR_ARG;
+  p.prec = prec;
+  const size_t need = esize(p) * (size_t)p.off_ii[p.n_elem];
+  if (need > p.cap_ainv) {
+    dfree(p.ainv);
+    ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.ainv), need));
+    p.cap_ainv = need;
+  }
+  if (fp32(p))
+    HIP_TRY(launch_cast_f64_to_f32(p.aii, static_cast<float *>(p.ainv), p.off_ii[p.n_elem], p.stream));
+  else
+    HIP_TRY(launch_copy_f64(p.aii, static_cast<double *>(p.ainv), p.off_ii[p.n_elem], p.stream));
+  HIP_TRY(launch_gj_inverse(p, p.ainv, fp32(p)));
+  p.state = 2;
+  p.dense_factored = false;
+  return SCDG_OK;
+}
+
+scdg_status scdg_factor_info(scdg_plan *pl, int64_t *first_bad_elem, int32_t *info) {
+  if (!pl) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 2) return SCDG_ERR_STATE;
+  std::vector<int32_t> h(p.n_elem);
+  HIP_TRY(hipMemcpyAsync(h.data(), p.d_info, sizeof(int32_t) * p.n_elem, hipMemcpyDeviceToHost, p.stream));
+  ST_TRY(sync(p));
+  int64_t bad = -1;
+  int32_t val = 0;
+  for (int e = 0; e < p.n_elem; ++e)
+    if (h[e] != 0) {
+      bad = e;
+      val = h[e];
+      break;
+    }
+  if (first_bad_elem) *first_bad_elem = bad;
+  if (info) *info = val;
+  return SCDG_OK;
+}
+
+scdg_status scdg_condense(scdg_plan *pl) {
+  if (!pl) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 2) {
+    p.last_error = "scdg_condense before scdg_factor";
+    return SCDG_ERR_STATE;
+  }
+  int64_t bad = -1;
+  int32_t info = 0;
+  ST_TRY(scdg_factor_info(pl, &bad, &info));
+  if (bad >= 0) {
+    p.last_error = "singular interior block in element " + std::to_string(bad) + " at step " +
+                   std::to_string(info);
+    return SCDG_ERR_SINGULAR;
+  }
+  const int E = p.n_elem;
+  const size_t nx = esize(p) * (size_t)p.off_ib[E], ns = esize(p) * (size_t)p.off_cc[E];
+  if (nx > p.cap_x) {
+    dfree(p.xmat);
+    ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.xmat), nx));
+    p.cap_x = nx;
+  }
+  if (ns > p.cap_s) {
+    dfree(p.sloc);
+    ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.sloc), ns));
+    p.cap_s = ns;
+  }
+  const void *aib = p.aib, *abi = p.abi;
+  if (fp32(p)) {
+    if (!p.aib_lo) ST_TRY(dalloc(p, reinterpret_cast<float **>(&p.aib_lo), (size_t)p.off_ib[E]));
+    if (!p.abi_lo) ST_TRY(dalloc(p, reinterpret_cast<float **>(&p.abi_lo), (size_t)p.off_ib[E]));
+    HIP_TRY(launch_cast_f64_to_f32(p.aib, static_cast<float *>(p.aib_lo), p.off_ib[E], p.stream));
+    HIP_TRY(launch_cast_f64_to_f32(p.abi, static_cast<float *>(p.abi_lo), p.off_ib[E], p.stream));
+    aib = p.aib_lo;
+    abi = p.abi_lo;
+  }
+  HIP_TRY(launch_gemm_batched(p.d_gx, p.d_tiles_x, p.n_tiles_x, p.ainv, aib, p.xmat, 1.0, 0.0,
+                              fp32(p), p.stream));
+  HIP_TRY(launch_gemm_batched(p.d_gs, p.d_tiles_s, p.n_tiles_s, abi, p.xmat, p.sloc, 1.0, 0.0,
+                              fp32(p), p.stream));
+  HIP_TRY(launch_diag_schur(p, p.sloc, fp32(p), p.diag_s));
+  // keep 1 / diag(S) for the point-Jacobi preconditioner
+  HIP_TRY(launch_reciprocal(p.diag_s, p.n1, p.stream));
+  p.state = 3;
+  p.dense_factored = false;
+  ST_TRY(sync(p));
+  return SCDG_OK;
+}
+
+scdg_status scdg_condense_rhs(scdg_plan *pl, const double *b, double *bs) {
+  if (!pl || !b || !bs) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 3) return SCDG_ERR_STATE;
+  return condense_rhs_impl(p, b, bs);
+}
+
+scdg_status scdg_schur_apply(scdg_plan *pl, const double *x, double *y) {
+  if (!pl || !x || !y) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 3) return SCDG_ERR_STATE;
+  return schur_apply_impl(p, x, y);
+}
+
+scdg_status scdg_solve_condensed(scdg_plan *pl, const double *bs, double *qb, const double *x0,
+                                 const scdg_solve_opts *o, scdg_solve_info *info) {
+  if (!pl || !bs || !qb) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 3) return SCDG_ERR_STATE;
+  scdg_solve_opts opts{};
+  if (o) opts = *o;
+  else opts.precond = -1;
+  defaults(opts);
+  if (opts.restart > 63) return SCDG_ERR_ARG;
+  scdg_solve_info inf{};
+  inf.rel_res_full = -1.0;
+  scdg_status st = solve_condensed_impl(p, bs, qb, x0, opts, inf);
+  if (info) *info = inf;
+  if (st == SCDG_OK) ST_TRY(sync(p));
+  return st;
+}
+
+scdg_status scdg_backsolve(scdg_plan *pl, const double *b, const double *qb, double *dq) {
+  if (!pl || !b || !qb || !dq) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 3) return SCDG_ERR_STATE;
+  return backsolve_impl(p, b, qb, dq);
+}
+
+scdg_status scdg_residual(scdg_plan *pl, const double *b, const double *dq, double *r,
+                          double *rel2) {
+  if (!pl || !b || !dq) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 1) return SCDG_ERR_STATE;
+  double *rr = r ? r : p.w_r;
+  ST_TRY(residual_impl(p, b, dq, rr));
+  if (rel2) {
+    double rn, bn;
+    ST_TRY(norm2sq(p, rr, p.n_dof, &rn));
+    ST_TRY(norm2sq(p, b, p.n_dof, &bn));
+    *rel2 = bn > 0 ? std::sqrt(rn / bn) : std::sqrt(rn);
+  }
+  return SCDG_OK;
+}
+
+scdg_status scdg_solve(scdg_plan *pl, const double *b, double *dq, const double *x0,
+                       const scdg_solve_opts *o, scdg_solve_info *info) {
+  if (!pl || !b || !dq) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 3) return SCDG_ERR_STATE;
+  scdg_solve_opts opts{};
+  if (o) opts = *o;
+  else opts.precond = -1;
+  defaults(opts);
+  if (opts.restart > 63) return SCDG_ERR_ARG;
+  scdg_solve_info inf{};
+  inf.rel_res_full = -1.0;
+  double bn2;
+  ST_TRY(norm2sq(p, b, p.n_dof, &bn2));
+  if (!std::isfinite(bn2)) {
+    p.last_error = "non-finite right-hand side";
+    if (info) *info = inf;
+    return SCDG_ERR_NONFINITE;
+  }
+  const double bnorm = std::sqrt(bn2);
+  // sweep 0 solves A dQ = B (from the boundary part of x0 when given); later
+  // sweeps solve A d = r with r = B - A dQ in FP64 and add d to dQ.
+  const double *rhs = b;
+  const double *guess = nullptr;
+  if (x0) {
+    HIP_TRY(launch_gather(x0, p.d_bmap, p.w_qb, p.n1, p.stream));
+    guess = p.w_qb;
+  }
+  scdg_status st = SCDG_OK;
+  double rel = -1.0;
+  for (int sweep = 0; sweep < opts.ir_max; ++sweep) {
+    double *target = sweep == 0 ? dq : p.w_dq;
+    ST_TRY(condense_rhs_impl(p, rhs, p.w_bs));
+    scdg_status s1 = solve_condensed_impl(p, p.w_bs, p.w_qb, sweep == 0 ? guess : nullptr, opts, inf);
+    if (s1 != SCDG_OK && s1 != SCDG_ERR_NOCONV) {
+      if (info) *info = inf;
+      return s1;
+    }
+    if (s1 == SCDG_ERR_NOCONV) st = s1;
+    ST_TRY(backsolve_impl(p, rhs, p.w_qb, target));
+    if (sweep > 0) HIP_TRY(launch_axpby(p.n_dof, 1.0, p.w_dq, 1.0, dq, p.stream));
+    inf.ir_sweeps = sweep + 1;
+    ST_TRY(residual_impl(p, b, dq, p.w_r));
+    double rn2;
+    ST_TRY(norm2sq(p, p.w_r, p.n_dof, &rn2));
+    rel = bnorm > 0 ? std::sqrt(rn2) / bnorm : std::sqrt(rn2);
+    inf.rel_res_full = rel;
+    if (!std::isfinite(rel)) {
+      p.last_error = "non-finite full-system residual";
+      if (info) *info = inf;
+      return SCDG_ERR_NONFINITE;
+    }
+    if (rel <= opts.ir_tol || bnorm == 0.0) {
+      st = SCDG_OK;
+      break;
+    }
+    // the next sweep's right-hand side is r; copy it because the next
+    // residual evaluation overwrites w_r
+    HIP_TRY(hipMemcpyAsync(p.w_vec, p.w_r, sizeof(double) * p.n_dof, hipMemcpyDeviceToDevice, p.stream));
+    rhs = p.w_vec;
+  }
+  if (info) *info = inf;
+  if (st == SCDG_OK && rel > opts.ir_tol) {
+    p.last_error = "iterative refinement did not reach ir_tol";
+    st = SCDG_ERR_NOCONV;
+  }
+  ST_TRY(sync(p));
+  return st;
+}
+
+scdg_status scdg_export(scdg_plan *pl, int what, void *dst, size_t dst_bytes) {
+  if (!pl || !dst) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  const void *src = nullptr;
+  size_t bytes = 0;
+  if (what == SCDG_EXPORT_AII_INV) {
+    if (p.state < 2) return SCDG_ERR_STATE;
+    src = p.ainv;
+    bytes = esize(p) * (size_t)p.off_ii[p.n_elem];
+  } else if (what == SCDG_EXPORT_SCHUR) {
+    if (p.state < 3) return SCDG_ERR_STATE;
+    src = p.sloc;
+    bytes = esize(p) * (size_t)p.off_cc[p.n_elem];
+  } else if (what == SCDG_EXPORT_X) {
+    if (p.state < 3) return SCDG_ERR_STATE;
+    src = p.xmat;
+    bytes = esize(p) * (size_t)p.off_ib[p.n_elem];
+  } else {
+    return SCDG_ERR_ARG;
+  }
+  if (dst_bytes < bytes) return SCDG_ERR_ARG;
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, p.stream));
+  ST_TRY(sync(p));
+  return SCDG_OK;
+}
+
+}  // extern "C"

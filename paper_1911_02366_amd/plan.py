@@ -1,0 +1,161 @@
+"""Python binding of the scdg C ABI with the same call names.
+
+Device memory and streams come from PyTorch (tensors on a HIP device); the
+binding only passes their pointers.  Host structure arrays are numpy.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError("scdg works on device tensors only")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Plan:
+    """Owns one scdg_plan.  Call order: assemble -> factor -> condense -> solve*."""
+
+    def __init__(self, order, c_ptr, c_node, bb_rowptr, bb_col, stream=None):
+        self.lib = L.load()
+        self._host = dict(
+            order=np.ascontiguousarray(order, dtype=np.int32),
+            c_ptr=np.ascontiguousarray(c_ptr, dtype=np.int64),
+            c_node=np.ascontiguousarray(c_node, dtype=np.int32),
+            bb_rowptr=np.ascontiguousarray(bb_rowptr, dtype=np.int64),
+            bb_col=np.ascontiguousarray(bb_col, dtype=np.int32),
+        )
+        h = self._host
+        s = L.Structure(len(h["order"]), h["order"].ctypes.data, h["c_ptr"].ctypes.data,
+                        h["c_node"].ctypes.data, h["bb_rowptr"].ctypes.data,
+                        h["bb_col"].ctypes.data if len(h["bb_col"]) else None)
+        handle = C.c_void_p()
+        st = self.lib.scdg_plan_create(C.byref(handle), C.byref(s), _stream(stream))
+        if st != L.SCDG_OK:
+            raise L.ScdgError(st, "scdg_plan_create", L.last_error(None))
+        self.handle = handle
+        self._keep = ()
+        n_dof, n1, n2, nb = (C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64())
+        self.lib.scdg_plan_sizes(handle, C.byref(n_dof), C.byref(n1), C.byref(n2), C.byref(nb))
+        self.n_dof, self.n1, self.n2, self.n_bnodes = n_dof.value, n1.value, n2.value, nb.value
+
+    @classmethod
+    def from_structure(cls, st: dict, stream=None) -> "Plan":
+        return cls(st["order"], st["c_ptr"], st["c_node"], st["bb_rowptr"], st["bb_col"], stream)
+
+    def _check(self, st: int, where: str):
+        if st != L.SCDG_OK:
+            raise L.ScdgError(st, where, L.last_error(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.scdg_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        self._check(self.lib.scdg_set_stream(self.handle, _stream(stream)), "scdg_set_stream")
+
+    def assemble(self, aii, aib, abi, bb_val):
+        for t in (aii, aib, abi, bb_val):
+            if t.dtype != torch.float64:
+                raise TypeError("blocks must be float64")
+        self._keep = (aii, aib, abi, bb_val)       # borrowed by the library
+        self._check(self.lib.scdg_assemble(self.handle, _ptr(aii), _ptr(aib), _ptr(abi), _ptr(bb_val)),
+                    "scdg_assemble")
+
+    def factor(self, precision: str = "fp64"):
+        prec = {"fp64": L.SCDG_FP64, "fp32": L.SCDG_FP32}[precision]
+        self.precision = precision
+        self._check(self.lib.scdg_factor(self.handle, prec), "scdg_factor")
+
+    def factor_info(self):
+        e, i = C.c_int64(), C.c_int32()
+        self._check(self.lib.scdg_factor_info(self.handle, C.byref(e), C.byref(i)), "scdg_factor_info")
+        return e.value, i.value
+
+    def condense(self):
+        self._check(self.lib.scdg_condense(self.handle), "scdg_condense")
+
+    def condense_rhs(self, b, bs=None):
+        if bs is None:
+            bs = torch.empty(self.n1, dtype=torch.float64, device=b.device)
+        self._check(self.lib.scdg_condense_rhs(self.handle, _ptr(b), _ptr(bs)), "scdg_condense_rhs")
+        return bs
+
+    @staticmethod
+    def _opts(**kw) -> L.SolveOpts:
+        o = L.SolveOpts()
+        o.precond = -1
+        solver = kw.pop("solver", "auto")
+        o.solver = {"auto": L.SOLVER_AUTO, "dense": L.SOLVER_DENSE, "gmres": L.SOLVER_GMRES}[solver]
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def solve_condensed(self, bs, qb=None, x0=None, check=True, **opts):
+        if qb is None:
+            qb = torch.empty(self.n1, dtype=torch.float64, device=bs.device)
+        o, info = self._opts(**opts), L.SolveInfo()
+        st = self.lib.scdg_solve_condensed(self.handle, _ptr(bs), _ptr(qb), _ptr(x0), C.byref(o),
+                                           C.byref(info))
+        if check:
+            self._check(st, "scdg_solve_condensed")
+        return qb, info.as_dict() | {"status": st}
+
+    def backsolve(self, b, qb, dq=None):
+        if dq is None:
+            dq = torch.empty(self.n_dof, dtype=torch.float64, device=b.device)
+        self._check(self.lib.scdg_backsolve(self.handle, _ptr(b), _ptr(qb), _ptr(dq)), "scdg_backsolve")
+        return dq
+
+    def solve(self, b, dq=None, x0=None, check=True, **opts):
+        if dq is None:
+            dq = torch.empty(self.n_dof, dtype=torch.float64, device=b.device)
+        o, info = self._opts(**opts), L.SolveInfo()
+        st = self.lib.scdg_solve(self.handle, _ptr(b), _ptr(dq), _ptr(x0), C.byref(o), C.byref(info))
+        if check:
+            self._check(st, "scdg_solve")
+        return dq, info.as_dict() | {"status": st}
+
+    def residual(self, b, dq, r=None):
+        rel = C.c_double()
+        self._check(self.lib.scdg_residual(self.handle, _ptr(b), _ptr(dq), _ptr(r), C.byref(rel)),
+                    "scdg_residual")
+        return r, rel.value
+
+    def schur_apply(self, x, y=None):
+        if y is None:
+            y = torch.empty_like(x)
+        self._check(self.lib.scdg_schur_apply(self.handle, _ptr(x), _ptr(y)), "scdg_schur_apply")
+        return y
+
+    def export(self, what: str, count: int, dtype=torch.float64, device="cuda"):
+        code = {"aii_inv": L.EXPORT_AII_INV, "schur": L.EXPORT_SCHUR, "x": L.EXPORT_X}[what]
+        out = torch.empty(count, dtype=dtype, device=device)
+        self._check(self.lib.scdg_export(self.handle, code, _ptr(out), out.numel() * out.element_size()),
+                    "scdg_export")
+        return out
