@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the statically condensed GL-DGSEM implicit-step solve on one GPU.
+
+One step = the whole hot path over one synthetic Newton system A dQ = B that is
+already resident in device memory: batched inversion of the interior blocks,
+X_e = A_ii^-1 A_ib and the element Schur blocks, condensed right-hand side,
+GMRES(30) with point-Jacobi on the condensed system, back-substitution, and the
+FP64 full-system residual that certifies ||B - A dQ|| / ||B|| <= 1e-8.
+
+Workload (default): 8^3 periodic hex elements of order 5 (552 960 DOFs), a
+Taylor-Green-like state at Ma 0.1, Re 1600, dt 5e-3, BR1 + local Lax-Friedrichs,
+generated on the device by the seeded generator in workload/.
+
+Prints ONE JSON line.  Per-kernel device times come from HIP events recorded
+by the library on its stream during the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
+
+
+def algorithmic_work(case, plan_prec: str) -> dict:
+    """Algorithmic flops / bytes per launch of each kernel (unpadded element blocks)."""
+    e, ni, nc = case.n_elem, case.n_i, case.n_c
+    esz = 8 if plan_prec == "fp64" else 4
+    nnzb = int(case.bb_rowptr[-1])
+    n1, n2, ndof = case.n1, case.n2, case.n_dof
+    bb_bytes = nnzb * 25 * 8 + nnzb * 4 + (case.n_bnodes + 1) * 8
+    return {
+        "inverse": {"flops": e * 2 * ni ** 3, "bytes": e * ni * ni * esz * 2},
+        "gemm_x": {"flops": e * 2 * ni * ni * nc, "bytes": e * (ni * ni + 2 * ni * nc) * esz},
+        "gemm_s": {"flops": e * 2 * nc * nc * ni, "bytes": e * (2 * ni * nc + nc * nc) * esz},
+        "schur_apply": {"flops": e * 2 * nc * nc + nnzb * 50,
+                        "bytes": e * nc * nc * esz + bb_bytes + 2 * n1 * 8},
+        "rhs": {"flops": e * (2 * ni * ni + 2 * nc * ni),
+                "bytes": e * (ni * ni + nc * ni) * esz + (ndof + n1) * 8},
+        "backsolve": {"flops": e * (2 * ni * ni + 2 * ni * nc),
+                      "bytes": e * (ni * ni + ni * nc) * esz + (2 * ndof + n1) * 8},
+        "residual": {"flops": 2 * e * (ni * ni + 2 * ni * nc) + nnzb * 50,
+                     "bytes": e * (ni * ni + 2 * ni * nc) * 8 + bb_bytes + 3 * ndof * 8},
+    }
+
+
+def roofline_entry(name, work, phase, prec):
+    if phase["count"] == 0 or phase["ms"] <= 0:
+        return None
+    per_launch_s = phase["ms"] / phase["count"] / 1e3
+    if name in ("gemm_x", "gemm_s", "inverse"):
+        peak = PEAK["fp64_mfma_tflops"] if prec == "fp64" else PEAK["fp32_mfma_tflops"]
+        achieved = work["flops"] / per_launch_s / 1e12
+        return {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "avg_launch_ms": round(per_launch_s * 1e3, 4), "launches": phase["count"],
+                "algorithmic_flops_per_launch": work["flops"]}
+    achieved = work["bytes"] / per_launch_s / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK["hbm_gbs"],
+            "unit": "GB/s", "frac": round(achieved / PEAK["hbm_gbs"], 4), "traffic": None,
+            "avg_launch_ms": round(per_launch_s * 1e3, 4), "launches": phase["count"],
+            "algorithmic_bytes_per_launch": work["bytes"]}
+
+
+def cpu_baseline(max_seconds: float) -> dict:
+    """The FP64 oracle (uncondensed brute force: assemble A, LAPACK dense LU) on a
+    bounded sample: the 2^3-element instance of the same order-5 workload."""
+    import numpy as np
+    import oracle
+    from workload.cases import build_case
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    case = build_case(2, 5, 1600.0, 5e-3, seed=0)
+    t = lambda x: x.cpu().numpy()
+    args = (case.order, case.c_ptr, case.c_node, case.bb_rowptr, case.bb_col, t(case.bb_val),
+            t(case.aii), t(case.aib), t(case.abi))
+    b = t(case.rhs)
+    solves, t0 = 0, time.perf_counter()
+    while True:
+        a = oracle.assemble_global(*args)
+        x = oracle.solve_dense(a, b)
+        solves += 1
+        el = time.perf_counter() - t0
+        if el >= max_seconds or solves >= 20:
+            break
+    rel = float(np.linalg.norm(b - a @ x) / np.linalg.norm(b))
+    return {"value": round(case.n_dof * solves / el, 2), "unit": "DOF/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"oracle assemble + LAPACK dense LU solve of the 2^3-element order-5 instance "
+                      f"of the same workload ({case.n_dof} DOFs), {solves} solves in {el:.1f} s, "
+                      f"residual {rel:.1e}"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="tgv_n5_k8")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    from paper_1911_02366_amd import Plan
+    from workload.cases import WORKLOADS, named_case
+
+    dev = "cuda"
+    case = named_case(args.workload, device=dev)
+    torch.cuda.synchronize()
+    b = case.rhs
+    plan = Plan.from_structure(case.structure())
+    plan.assemble(case.aii, case.aib, case.abi, case.bb_val)
+    dq = torch.empty(case.n_dof, dtype=torch.float64, device=dev)
+    opts = dict(solver="gmres", restart=30, tol=args.tol if args.precision == "fp64" else 1e-6,
+                ir_tol=1e-8, ir_max=10)
+
+    def step():
+        plan.factor(args.precision)
+        plan.condense()
+        _, info = plan.solve(b, dq, **opts)
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.enable_timing(True)
+    plan.phase_times()
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = plan.phase_times()
+    plan.enable_timing(False)
+
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    value = case.n_dof / (ms_per_step / 1e3)
+    work = algorithmic_work(case, args.precision)
+    kernels = {k: v for k, v in phases.items() if k in work}
+    dominant = max(kernels, key=lambda k: kernels[k]["ms"])
+    entries = {k: roofline_entry(k, work[k], kernels[k], args.precision) for k in kernels}
+    worst = max(i["rel_res_full"] for i in infos)
+    cfg = WORKLOADS[args.workload]
+    out = {
+        "metric": "condensed implicit-step DOF/s at 1e-8 residual",
+        "value": round(value, 1),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "elements": case.n_elem, "order": cfg["order"],
+                   "dofs": case.n_dof, "n1_condensed": case.n1, "n2_interior": case.n2,
+                   "reynolds": cfg["reynolds"], "mach": 0.1, "dt": cfg["dt"],
+                   "solver": "gmres(30)+point-jacobi", "gmres_tol": opts["tol"],
+                   "precision": args.precision},
+        "roofline": entries[dominant],
+        "roofline_all": entries,
+        "phase_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in phases.items()},
+        "rel_res_full_max": worst,
+        "gmres_iters_per_step": sum(i["iters"] for i in infos) / len(infos),
+        "ir_sweeps_per_step": sum(i["ir_sweeps"] for i in infos) / len(infos),
+    }
+    if worst > 1e-8:
+        out["warning"] = "full-system residual above 1e-8"
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    plan.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -169,6 +169,25 @@ scdg_status scdg_schur_apply(scdg_plan *p, const double *x, double *y);
 enum { SCDG_EXPORT_AII_INV = 1, SCDG_EXPORT_SCHUR = 2, SCDG_EXPORT_X = 3 };
 scdg_status scdg_export(scdg_plan *p, int what, void *dst, size_t dst_bytes);
 
+/* Device-time accounting per phase, measured with HIP events recorded on the
+ * plan's stream around each launch (asynchronous; off by default). */
+typedef enum {
+  SCDG_PHASE_INVERSE = 0,     /* batched Gauss-Jordan inverse of A_ii */
+  SCDG_PHASE_GEMM_X = 1,      /* X_e = A_ii^-1 A_ib */
+  SCDG_PHASE_GEMM_S = 2,      /* element Schur blocks A_bi X_e */
+  SCDG_PHASE_RHS = 3,         /* condensed right-hand side */
+  SCDG_PHASE_SCHUR_APPLY = 4, /* one product with S (element blocks + A_bb) */
+  SCDG_PHASE_CONDENSED = 5,   /* a whole condensed solve (GMRES or dense LU + solve) */
+  SCDG_PHASE_BACKSOLVE = 6,   /* back-substitution */
+  SCDG_PHASE_RESIDUAL = 7,    /* full-system FP64 residual */
+  SCDG_PHASE_COUNT = 8
+} scdg_phase;
+scdg_status scdg_enable_timing(scdg_plan *p, int on);
+/* Sum of event-measured milliseconds and launch counts per phase since the
+ * previous call (then reset).  Synchronizes the stream.  ms and count are host
+ * arrays of n entries (n <= SCDG_PHASE_COUNT). */
+scdg_status scdg_phase_times(scdg_plan *p, double *ms, int32_t *count, int32_t n);
+
 const char *scdg_status_string(scdg_status s);
 /* Last error text of a plan (or of plan creation when p is NULL). */
 scdg_status scdg_last_error(const scdg_plan *p, char *buf, size_t n);

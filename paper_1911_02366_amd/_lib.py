@@ -24,7 +24,10 @@ EXPORTED = [
     "scdg_assemble", "scdg_factor", "scdg_factor_info", "scdg_condense", "scdg_condense_rhs",
     "scdg_solve_condensed", "scdg_backsolve", "scdg_solve", "scdg_residual",
     "scdg_schur_apply", "scdg_export", "scdg_status_string", "scdg_last_error",
+    "scdg_enable_timing", "scdg_phase_times",
 ]
+PHASES = ["inverse", "gemm_x", "gemm_s", "rhs", "schur_apply", "condensed_solve", "backsolve",
+          "residual"]
 
 
 class Structure(C.Structure):
@@ -82,6 +85,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_export": (i32, [vp, i32, vp, sz]),
         "scdg_status_string": (C.c_char_p, [i32]),
         "scdg_last_error": (i32, [vp, C.c_char_p, sz]),
+        "scdg_enable_timing": (i32, [vp, i32]),
+        "scdg_phase_times": (i32, [vp, C.POINTER(d), C.POINTER(i32), i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

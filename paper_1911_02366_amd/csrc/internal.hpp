@@ -116,6 +116,11 @@ struct Plan {
   double *h_pinned = nullptr; // host pinned staging
   int32_t gm_m = 0;
   int32_t red_blocks = 0;
+
+  // phase timing (events recorded asynchronously, summed on query)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
 };
 
 // ---- kernel launchers (implemented in the .hip files) ----

@@ -111,6 +111,33 @@ std::vector<RowTile> row_tiles(const std::vector<GemvDesc> &descs) {
   return t;
 }
 
+// Event pair around a stretch of stream work when timing is on.
+struct PhaseTimer {
+  Plan &p;
+  int phase;
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  PhaseTimer(Plan &pl, int ph) : p(pl), phase(ph) {
+    if (!p.timing) return;
+    if (p.ev_pool.empty()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+      }
+      p.ev_pool.emplace_back(a, b);
+    }
+    ev = p.ev_pool.back();
+    p.ev_pool.pop_back();
+    (void)hipEventRecord(ev.first, p.stream);
+  }
+  ~PhaseTimer() {
+    if (!ev.first) return;
+    (void)hipEventRecord(ev.second, p.stream);
+    p.ev_used.emplace_back(phase, ev);
+  }
+};
+
 bool fp32(const Plan &p) { return p.prec == SCDG_FP32; }
 size_t esize(const Plan &p) { return fp32(p) ? sizeof(float) : sizeof(double); }
 
@@ -138,6 +165,7 @@ scdg_status apply_inverse(Plan &p, const double *b_nat, double *z) {
 }
 
 scdg_status condense_rhs_impl(Plan &p, const double *b, double *bs) {
+  PhaseTimer tm(p, SCDG_PHASE_RHS);
   ST_TRY(apply_inverse(p, b, p.w_z));
   const void *abi = fp32(p) ? p.abi_lo : static_cast<const void *>(p.abi);
   HIP_TRY(launch_gemv_batched(p.d_gv_abi, p.d_rt_abi, p.n_rt_abi, p.max_ni, abi, fp32(p), p.w_z,
@@ -147,6 +175,7 @@ scdg_status condense_rhs_impl(Plan &p, const double *b, double *bs) {
 }
 
 scdg_status schur_apply_impl(Plan &p, const double *x, double *y) {
+  PhaseTimer tm(p, SCDG_PHASE_SCHUR_APPLY);
   HIP_TRY(launch_gemv_batched(p.d_gv_s, p.d_rt_s, p.n_rt_s, p.max_nc, p.sloc, fp32(p), x, p.d_cmap,
                               p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream));
   HIP_TRY(launch_bsr_pull(p, 0.0, nullptr, nullptr, 1.0, x, -1.0, p.w_t, y));
@@ -154,6 +183,7 @@ scdg_status schur_apply_impl(Plan &p, const double *x, double *y) {
 }
 
 scdg_status backsolve_impl(Plan &p, const double *b, const double *qb, double *dq) {
+  PhaseTimer tm(p, SCDG_PHASE_BACKSOLVE);
   ST_TRY(apply_inverse(p, b, p.w_z));
   HIP_TRY(launch_gemv_batched(p.d_gv_aib, p.d_rt_aib, p.n_rt_aib, p.max_nc, p.xmat, fp32(p), qb,
                               p.d_cmap, dq, p.d_imap, -1.0, 1.0, p.w_z, p.stream));
@@ -163,6 +193,7 @@ scdg_status backsolve_impl(Plan &p, const double *b, const double *qb, double *d
 
 // r = B - A dQ on the full FP64 system (r, B, dQ natural vectors)
 scdg_status residual_impl(Plan &p, const double *b, const double *dq, double *r) {
+  PhaseTimer tm(p, SCDG_PHASE_RESIDUAL);
   // interior rows: u = A_ii dQ_i + A_ib dQ_b[C_e]
   HIP_TRY(launch_gather(dq, p.d_bmap, p.w_qb, p.n1, p.stream));
   HIP_TRY(launch_gemv_batched(p.d_gv_inv, p.d_rt_inv, p.n_rt_inv, p.max_ni, p.aii, false, dq,
@@ -324,6 +355,7 @@ void defaults(scdg_solve_opts &o) {
 
 scdg_status solve_condensed_impl(Plan &p, const double *bs, double *qb, const double *x0,
                                  const scdg_solve_opts &o, scdg_solve_info &info) {
+  PhaseTimer tm(p, SCDG_PHASE_CONDENSED);
   int solver = o.solver;
   if (solver == SCDG_SOLVER_AUTO) solver = p.n1 <= 8192 ? SCDG_SOLVER_DENSE : SCDG_SOLVER_GMRES;
   info.solver_used = solver;
@@ -384,6 +416,11 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.w_z); dfree(p.w_t); dfree(p.w_bs); dfree(p.w_qb); dfree(p.w_r); dfree(p.w_dq); dfree(p.w_vec);
   dfree(p.gm_v); dfree(p.gm_w); dfree(p.gm_z); dfree(p.gm_part); dfree(p.gm_h);
   if (p.h_pinned) (void)hipHostFree(p.h_pinned);
+  for (auto &u : p.ev_used) p.ev_pool.push_back(u.second);
+  for (auto &e : p.ev_pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   delete pl;
   return SCDG_OK;
 }
@@ -635,7 +672,10 @@ scdg_status scdg_factor(scdg_plan *pl, scdg_precision prec) {
     HIP_TRY(launch_cast_f64_to_f32(p.aii, static_cast<float *>(p.ainv), p.off_ii[p.n_elem], p.stream));
   else
     HIP_TRY(launch_copy_f64(p.aii, static_cast<double *>(p.ainv), p.off_ii[p.n_elem], p.stream));
-  HIP_TRY(launch_gj_inverse(p, p.ainv, fp32(p)));
+  {
+    PhaseTimer tm(p, SCDG_PHASE_INVERSE);
+    HIP_TRY(launch_gj_inverse(p, p.ainv, fp32(p)));
+  }
   p.state = 2;
   p.dense_factored = false;
   return SCDG_OK;
@@ -697,10 +737,16 @@ scdg_status scdg_condense(scdg_plan *pl) {
     aib = p.aib_lo;
     abi = p.abi_lo;
   }
-  HIP_TRY(launch_gemm_batched(p.d_gx, p.d_tiles_x, p.n_tiles_x, p.ainv, aib, p.xmat, 1.0, 0.0,
-                              fp32(p), p.stream));
-  HIP_TRY(launch_gemm_batched(p.d_gs, p.d_tiles_s, p.n_tiles_s, abi, p.xmat, p.sloc, 1.0, 0.0,
-                              fp32(p), p.stream));
+  {
+    PhaseTimer tm(p, SCDG_PHASE_GEMM_X);
+    HIP_TRY(launch_gemm_batched(p.d_gx, p.d_tiles_x, p.n_tiles_x, p.ainv, aib, p.xmat, 1.0, 0.0,
+                                fp32(p), p.stream));
+  }
+  {
+    PhaseTimer tm(p, SCDG_PHASE_GEMM_S);
+    HIP_TRY(launch_gemm_batched(p.d_gs, p.d_tiles_s, p.n_tiles_s, abi, p.xmat, p.sloc, 1.0, 0.0,
+                                fp32(p), p.stream));
+  }
   HIP_TRY(launch_diag_schur(p, p.sloc, fp32(p), p.diag_s));
   // keep 1 / diag(S) for the point-Jacobi preconditioner
   HIP_TRY(launch_reciprocal(p.diag_s, p.n1, p.stream));
@@ -833,6 +879,32 @@ scdg_status scdg_solve(scdg_plan *pl, const double *b, double *dq, const double 
   }
   ST_TRY(sync(p));
   return st;
+}
+
+scdg_status scdg_enable_timing(scdg_plan *pl, int on) {
+  if (!pl) return SCDG_ERR_ARG;
+  pl->p.timing = on != 0;
+  return SCDG_OK;
+}
+
+scdg_status scdg_phase_times(scdg_plan *pl, double *ms, int32_t *count, int32_t n) {
+  if (!pl || !ms || !count || n < 0 || n > SCDG_PHASE_COUNT) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  ST_TRY(sync(p));
+  for (int i = 0; i < n; ++i) {
+    ms[i] = 0.0;
+    count[i] = 0;
+  }
+  for (auto &u : p.ev_used) {
+    float t = 0.f;
+    if (u.first < n && hipEventElapsedTime(&t, u.second.first, u.second.second) == hipSuccess) {
+      ms[u.first] += t;
+      count[u.first] += 1;
+    }
+    p.ev_pool.push_back(u.second);
+  }
+  p.ev_used.clear();
+  return SCDG_OK;
 }
 
 scdg_status scdg_export(scdg_plan *pl, int what, void *dst, size_t dst_bytes) {

@@ -153,6 +153,16 @@ class Plan:
         self._check(self.lib.scdg_schur_apply(self.handle, _ptr(x), _ptr(y)), "scdg_schur_apply")
         return y
 
+    def enable_timing(self, on: bool = True):
+        self._check(self.lib.scdg_enable_timing(self.handle, int(on)), "scdg_enable_timing")
+
+    def phase_times(self) -> dict:
+        n = len(L.PHASES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int32 * n)()
+        self._check(self.lib.scdg_phase_times(self.handle, ms, cnt, n), "scdg_phase_times")
+        return {name: {"ms": ms[i], "count": cnt[i]} for i, name in enumerate(L.PHASES)}
+
     def export(self, what: str, count: int, dtype=torch.float64, device="cuda"):
         code = {"aii_inv": L.EXPORT_AII_INV, "schur": L.EXPORT_SCHUR, "x": L.EXPORT_X}[what]
         out = torch.empty(count, dtype=dtype, device=device)
