@@ -108,6 +108,8 @@ def main() -> int:
     ap.add_argument("--workload", default="tgv_n5_k8")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--precond", type=int, default=1, choices=[0, 1, 2],
+                    help="GMRES right preconditioner: 0 none, 1 point Jacobi, 2 5x5 node-block Jacobi")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -132,7 +134,7 @@ def main() -> int:
     plan.assemble(case.aii, case.aib, case.abi, case.bb_val)
     dq = torch.empty(case.n_dof, dtype=torch.float64, device=dev)
     opts = dict(solver="gmres", restart=30, tol=args.tol if args.precision == "fp64" else 1e-6,
-                ir_tol=1e-8, ir_max=10)
+                ir_tol=1e-8, ir_max=10, precond=args.precond)
 
     def step():
         plan.factor(args.precision)
@@ -140,6 +142,8 @@ def main() -> int:
         _, info = plan.solve(b, dq, **opts)
         return info
 
+    plan.factor(args.precision)
+    tuning = plan.autotune()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -179,12 +183,16 @@ def main() -> int:
         "config": {"workload": args.workload, "elements": case.n_elem, "order": cfg["order"],
                    "dofs": case.n_dof, "n1_condensed": case.n1, "n2_interior": case.n2,
                    "reynolds": cfg["reynolds"], "mach": 0.1, "dt": cfg["dt"],
-                   "solver": "gmres(30)+point-jacobi", "gmres_tol": opts["tol"],
+                   "solver": "gmres(30)+" + ["none", "point-jacobi", "block-jacobi-5x5"][args.precond],
+                   "gmres_tol": opts["tol"],
                    "precision": args.precision},
         "roofline": entries[dominant],
         "roofline_all": entries,
         "phase_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in phases.items()},
         "rel_res_full_max": worst,
+        "gemm_tiles": {"x": tuning["x"], "s": tuning["s"],
+                       "autotune_ms_s": {k: round(v, 3) for k, v in tuning["ms_s"].items()},
+                       "autotune_ms_x": {k: round(v, 3) for k, v in tuning["ms_x"].items()}},
         "gmres_iters_per_step": sum(i["iters"] for i in infos) / len(infos),
         "ir_sweeps_per_step": sum(i["ir_sweeps"] for i in infos) / len(infos),
     }

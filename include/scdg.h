@@ -92,7 +92,8 @@ typedef struct {
   int32_t restart;    /* GMRES restart length m (default 30) */
   int32_t max_iters;  /* total GMRES iterations (default 1000) */
   double tol;         /* GMRES stop: ||b_S - S x||_2 <= tol ||b_S||_2 (default 1e-10) */
-  int32_t precond;    /* 0 none, 1 right point-Jacobi on diag(S) (default 1 via -1 -> 1) */
+  int32_t precond;    /* right preconditioner: 0 none, 1 point Jacobi on diag(S), 2 Jacobi on
+                         the 5x5 diagonal node blocks of S (default: 1; -1 selects it) */
   int32_t ir_max;     /* iterative-refinement sweeps for FP32 factors (default 10) */
   double ir_tol;      /* refinement stop on ||B - A dQ||_2 / ||B||_2 (default 1e-8) */
 } scdg_solve_opts;
@@ -128,9 +129,13 @@ scdg_status scdg_factor(scdg_plan *p, scdg_precision prec);
 /* First singular element (or -1) and its LAPACK-style info (1-based step). */
 scdg_status scdg_factor_info(scdg_plan *p, int64_t *first_bad_elem, int32_t *info);
 
-/* X_e = A_ii(e)^-1 A_ib(e) and the element Schur blocks A_bi(e) X_e
- * (eq. SC_step1); S = A_bb - sum_e P_e A_bi(e) X_e P_e^T is kept in this
- * element-block form plus A_bb.  Uses the precision given to scdg_factor. */
+/* X_e = A_ii(e)^-1 A_ib(e) and the element blocks of the condensed matrix
+ * (eq. SC_step1).  S = A_bb - sum_e P_e A_bi(e) X_e P_e^T is stored as
+ *     S = R + sum_e P_e T_e P_e^T,   T_e = F_e - A_bi(e) X_e,
+ * where the A_bb block (g, h) is folded into F_e of the element e that owns
+ * node g if both g and h lie in C_e, else of the lowest-numbered element whose
+ * C_e holds both; blocks with no such element form the remainder R (BSR).
+ * Uses the precision given to scdg_factor. */
 scdg_status scdg_condense(scdg_plan *p);
 
 /* b_S = B_b - sum_e P_e A_bi(e) A_ii(e)^-1 B_i(e) (eq. SC_step1).  b: natural
@@ -164,8 +169,9 @@ scdg_status scdg_residual(scdg_plan *p, const double *b, const double *dq, doubl
 scdg_status scdg_schur_apply(scdg_plan *p, const double *x, double *y);
 
 /* Copy internal arrays to caller device memory (for inspection and tests):
- * SCDG_EXPORT_AII_INV: sum n_i^2 values, SCDG_EXPORT_SCHUR: sum n_c^2 values of
- * A_bi(e) A_ii(e)^-1 A_ib(e); both in the factor precision (double or float). */
+ * SCDG_EXPORT_AII_INV: sum n_i^2 values of A_ii(e)^-1; SCDG_EXPORT_SCHUR:
+ * sum n_c^2 values of T_e; SCDG_EXPORT_X: sum n_i n_c values of X_e; all in the
+ * factor precision (double or float). */
 enum { SCDG_EXPORT_AII_INV = 1, SCDG_EXPORT_SCHUR = 2, SCDG_EXPORT_X = 3 };
 scdg_status scdg_export(scdg_plan *p, int what, void *dst, size_t dst_bytes);
 
@@ -187,6 +193,16 @@ scdg_status scdg_enable_timing(scdg_plan *p, int on);
  * previous call (then reset).  Synchronizes the stream.  ms and count are host
  * arrays of n entries (n <= SCDG_PHASE_COUNT). */
 scdg_status scdg_phase_times(scdg_plan *p, double *ms, int32_t *count, int32_t n);
+
+/* Tile autotuner for the two batched GEMMs of scdg_condense (X_e and the
+ * element Schur blocks): every tile configuration is timed on the plan's own
+ * problems (HIP events, best of two runs) and the fastest is kept.  Needs
+ * scdg_factor; leaves the plan factored but not condensed.  ms_x / ms_s (host,
+ * n entries, may be NULL) receive the time per configuration (-1 if skipped). */
+scdg_status scdg_autotune(scdg_plan *p, double *ms_x, double *ms_s, int32_t n);
+/* Select / query the tile configuration of the two GEMMs (0 .. 6). */
+scdg_status scdg_set_gemm_config(scdg_plan *p, int32_t cfg_x, int32_t cfg_s);
+scdg_status scdg_get_gemm_config(const scdg_plan *p, int32_t *cfg_x, int32_t *cfg_s);
 
 const char *scdg_status_string(scdg_status s);
 /* Last error text of a plan (or of plan creation when p is NULL). */

@@ -24,8 +24,10 @@ EXPORTED = [
     "scdg_assemble", "scdg_factor", "scdg_factor_info", "scdg_condense", "scdg_condense_rhs",
     "scdg_solve_condensed", "scdg_backsolve", "scdg_solve", "scdg_residual",
     "scdg_schur_apply", "scdg_export", "scdg_status_string", "scdg_last_error",
-    "scdg_enable_timing", "scdg_phase_times",
+    "scdg_enable_timing", "scdg_phase_times", "scdg_autotune", "scdg_set_gemm_config",
+    "scdg_get_gemm_config",
 ]
+GEMM_CONFIGS = ["64x64", "64x128", "128x128", "128x128w8", "128x64", "240x80", "80x80"]
 PHASES = ["inverse", "gemm_x", "gemm_s", "rhs", "schur_apply", "condensed_solve", "backsolve",
           "residual"]
 
@@ -87,6 +89,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_last_error": (i32, [vp, C.c_char_p, sz]),
         "scdg_enable_timing": (i32, [vp, i32]),
         "scdg_phase_times": (i32, [vp, C.POINTER(d), C.POINTER(i32), i32]),
+        "scdg_autotune": (i32, [vp, C.POINTER(d), C.POINTER(d), i32]),
+        "scdg_set_gemm_config": (i32, [vp, i32, i32]),
+        "scdg_get_gemm_config": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -34,6 +34,9 @@ struct GemvDesc {
   int32_t y_off;   // offset into the y / y0 index space
 };
 
+// GEMM tile configurations (rows x columns of C per workgroup)
+enum { kGemm64x64 = 0, kGemm64x128 = 1, kGemm128x128 = 2, kGemmConfigs = 7 };
+
 template <typename T>
 struct DevBuf {
   T *ptr = nullptr;
@@ -66,6 +69,14 @@ struct Plan {
   int32_t *d_slot_pos = nullptr;  // [sum |C_e|] position of the slot within C_e
   int64_t *d_bb_rowptr = nullptr; // [n_bnodes+1]
   int32_t *d_bb_col = nullptr;    // [nnzb]
+  // A_bb blocks folded into the element Schur blocks T_e, and the remainder
+  int64_t n_fold = 0, n_rem = 0;
+  int64_t *d_fold_dst = nullptr;  // [n_fold] offset of the block's (0,0) entry in T
+  int32_t *d_fold_nc = nullptr;   // [n_fold] row stride (n_c of the element)
+  int32_t *d_fold_src = nullptr;  // [n_fold] block index into bb_val
+  int64_t *d_rem_rowptr = nullptr;  // [n_bnodes+1]
+  int32_t *d_rem_col = nullptr;     // [n_rem]
+  int32_t *d_rem_src = nullptr;     // [n_rem] block index into bb_val
   int32_t *d_inv_n = nullptr;     // [n_elem] n_i per element
   int64_t *d_inv_off = nullptr;   // [n_elem] offset of A_ii(e)
   int32_t *d_info = nullptr;      // [n_elem] factor info
@@ -74,6 +85,8 @@ struct Plan {
   GemmDesc *d_gx = nullptr, *d_gs = nullptr;
   int32_t *d_tiles_x = nullptr, *d_tiles_s = nullptr;
   int32_t n_tiles_x = 0, n_tiles_s = 0;
+  int gemm_cfg_x = kGemm64x128, gemm_cfg_s = kGemm128x128;
+  std::vector<GemmDesc> gx_host, gs_host;   // kept to rebuild tile lists
 
   // batched GEMV descriptors
   GemvDesc *d_gv_inv = nullptr;  // Ainv (n_i x n_i), x: interior slots
@@ -88,10 +101,12 @@ struct Plan {
 
   // factors and Schur blocks (precision = prec)
   void *ainv = nullptr;   // sum n_i^2
+  void *ainv_work = nullptr;  // sum n_i^2 (Gauss-Jordan work space)
   void *xmat = nullptr;   // sum n_i n_c
   void *sloc = nullptr;   // sum n_c^2
   void *aib_lo = nullptr, *abi_lo = nullptr;  // FP32 shadows (FP32 mode)
-  double *diag_s = nullptr;  // [n1] diagonal of S
+  double *diag_s = nullptr;  // [n1] 1 / diag(S) (point Jacobi)
+  double *pc_blk = nullptr;  // [n_bnodes * 25] inverse 5x5 diagonal blocks of S
   size_t cap_ainv = 0, cap_x = 0, cap_s = 0;  // bytes allocated
 
   // dense S path
@@ -124,14 +139,14 @@ struct Plan {
 };
 
 // ---- kernel launchers (implemented in the .hip files) ----
-hipError_t launch_gj_inverse(Plan &p, void *w, bool fp32);
+hipError_t launch_gj_inverse(Plan &p, void *work, void *out, bool fp32);
+bool gj_supported(int max_n, bool fp32);
 hipError_t launch_cast_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, size_t n, hipStream_t s);
-hipError_t launch_gemm_batched(const GemmDesc *d_desc, const int32_t *d_tiles, int32_t n_tiles,
-                               const void *a, const void *b, void *c, double alpha, double beta,
-                               bool fp32, hipStream_t s);
-int gemm_tile_m();
-int gemm_tile_n();
+void gemm_tile_shape(int cfg, int *bm, int *bn);
+hipError_t launch_gemm_batched(int cfg, const GemmDesc *d_desc, const int32_t *d_tiles,
+                               int32_t n_tiles, const void *a, const void *b, void *c, double alpha,
+                               double beta, bool fp32, hipStream_t s);
 
 // y[omap?omap[y_off+r]:y_off+r] = alpha * sum_c M[r,c] x[xmap?xmap[x_off+c]:x_off+c]
 //                                 + beta * y0[y_off + r]
@@ -140,9 +155,17 @@ hipError_t launch_gemv_batched(const GemvDesc *d_desc, const RowTile *d_tiles, i
                                const int32_t *xmap, double *y, const int32_t *omap, double alpha,
                                double beta, const double *y0, hipStream_t s);
 
-// out[j] = c0 * src0[map0 ? map0[j] : j] + c1 * (A_bb x)[j] + c2 * sum_{s in pull(j/5)} t[5 s + j%5]
-hipError_t launch_bsr_pull(const Plan &p, double c0, const double *src0, const int32_t *map0,
-                           double c1, const double *x, double c2, const double *t, double *out);
+// out[j] = c0 * src0[map0 ? map0[j] : j] + c1 * (B x)[j] + c2 * sum_{s in pull(j/5)} t[5 s + j%5]
+// with B = A_bb (full = true) or the remainder of A_bb not folded into T_e.
+hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *src0,
+                           const int32_t *map0, double c1, const double *x, double c2,
+                           const double *t, double *out);
+// T[dst + v nc + w] += A_bb[src][v][w] for the folded blocks
+hipError_t launch_fold_add(const Plan &p, void *t, bool fp32);
+// 5x5 diagonal blocks of S (remainder + element blocks), inverted; point inverse too
+hipError_t launch_precond_setup(const Plan &p, const void *t, bool fp32);
+// y = a M^-1 x with M = I (mode 0), diag(S) (1) or the 5x5 node blocks of S (2)
+hipError_t launch_precond_apply(const Plan &p, int mode, const double *x, double *y, double a);
 
 hipError_t launch_gather(const double *src, const int32_t *map, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_scatter(const double *src, const int32_t *map, double *dst, int64_t n, hipStream_t s);
@@ -159,7 +182,6 @@ hipError_t launch_multi_axpy(const double *v, int64_t ld, int32_t nv, const doub
 // y = x * dinv (elementwise); dinv may be null (copy)
 hipError_t launch_diag_scale(const double *x, const double *dinv, double *y, int64_t n, double a,
                              hipStream_t s);
-hipError_t launch_diag_schur(const Plan &p, const void *sloc, bool fp32, double *diag);
 hipError_t launch_reciprocal(double *x, int64_t n, hipStream_t s);
 
 // dense path

@@ -17,8 +17,10 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kPanel = 32;
 
+// remainder blocks of A_bb (those not folded into an element block)
 __global__ void dense_fill_bb_kernel(int64_t n_bnodes, const int64_t *__restrict__ rowptr,
                                      const int32_t *__restrict__ col,
+                                     const int32_t *__restrict__ src,
                                      const double *__restrict__ val, double *__restrict__ s,
                                      int64_t ld) {
   const int64_t g = blockIdx.x;
@@ -27,13 +29,13 @@ __global__ void dense_fill_bb_kernel(int64_t n_bnodes, const int64_t *__restrict
     const int64_t h = col[b];
     for (int q = threadIdx.x; q < 25; q += blockDim.x) {
       const int r = q / 5, w = q % 5;
-      s[(5 * g + r) * ld + 5 * h + w] += val[b * 25 + q];
+      s[(5 * g + r) * ld + 5 * h + w] += val[(int64_t)src[b] * 25 + q];
     }
   }
 }
 
-// S[C_e, C_e] -= S_loc(e) for one element (launched element after element so
-// that overlapping entries are summed in a fixed order)
+// S[C_e, C_e] += T_e for one element (launched element after element so that
+// overlapping entries are summed in a fixed order)
 template <typename TM>
 __global__ void dense_sub_elem_kernel(const TM *__restrict__ sloc, int nc,
                                       const int32_t *__restrict__ cmap, double *__restrict__ s,
@@ -42,7 +44,7 @@ __global__ void dense_sub_elem_kernel(const TM *__restrict__ sloc, int nc,
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n2;
        q += (int64_t)gridDim.x * blockDim.x) {
     const int r = (int)(q / nc), c = (int)(q % nc);
-    s[(int64_t)cmap[r] * ld + cmap[c]] -= (double)sloc[q];
+    s[(int64_t)cmap[r] * ld + cmap[c]] += (double)sloc[q];
   }
 }
 
@@ -186,7 +188,7 @@ hipError_t launch_dense_assemble(const Plan &p, double *s) {
   const int64_t n = p.n1;
   hipLaunchKernelGGL(zero_kernel, dim3(2048), dim3(kThreads), 0, p.stream, s, n * n);
   hipLaunchKernelGGL(dense_fill_bb_kernel, dim3((unsigned)p.n_bnodes), dim3(32), 0, p.stream,
-                     p.n_bnodes, p.d_bb_rowptr, p.d_bb_col, p.bb_val, s, n);
+                     p.n_bnodes, p.d_rem_rowptr, p.d_rem_col, p.d_rem_src, p.bb_val, s, n);
   const bool fp32 = p.prec == SCDG_FP32;
   const size_t esz = fp32 ? sizeof(float) : sizeof(double);
   for (int e = 0; e < p.n_elem; ++e) {
@@ -232,9 +234,11 @@ hipError_t launch_dense_lu(Plan &p, double *a, int32_t n, int32_t *piv, int32_t 
     if (rest > 0) {
       hipLaunchKernelGGL(dense_trsm_kernel, dim3((rest + 127) / 128), dim3(128), 0, p.stream, a, n,
                          kb, nbw);
-      const int tiles = ((rest + gemm_tile_m() - 1) / gemm_tile_m()) *
-                        ((rest + gemm_tile_n() - 1) / gemm_tile_n());
-      err = launch_gemm_batched(d_desc + t, nullptr, tiles, a, a, a, -1.0, 1.0, false, p.stream);
+      const int cfg = rest >= 512 ? kGemm128x128 : kGemm64x64;
+      int bm, bn;
+      gemm_tile_shape(cfg, &bm, &bn);
+      const int tiles = ((rest + bm - 1) / bm) * ((rest + bn - 1) / bn);
+      err = launch_gemm_batched(cfg, d_desc + t, nullptr, tiles, a, a, a, -1.0, 1.0, false, p.stream);
     }
     if (err == hipSuccess) err = hipGetLastError();
   }

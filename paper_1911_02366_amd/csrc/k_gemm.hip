@@ -2,16 +2,17 @@
 //   C_p = alpha A_p B_p + beta C_p    for every problem p of the batch,
 // row-major operands with per-problem sizes and leading dimensions.
 //
-// It forms X_e = A_ii(e)^-1 A_ib(e) and the element Schur blocks
-// A_bi(e) X_e of eq. SC_step1, and the trailing updates of the dense LU of S.
+// It forms X_e = A_ii(e)^-1 A_ib(e) and the element blocks -A_bi(e) X_e of the
+// condensed matrix (eq. SC_step1), and the trailing updates of the dense LU of S.
 //
-// Tiling: a 256-thread workgroup computes a 64x64 tile of one problem; its four
-// waves each own a 32x32 quarter made of 2x2 blocks of the 16x16x4 MFMA.  A and
-// B tiles of depth 16 are staged through LDS (A stored k-major so that the 16
-// lanes reading one MFMA operand column hit consecutive addresses).  The tile
-// list is ordered so that consecutive tiles of one problem land on the same XCD
-// (workgroups are dealt to the 8 XCDs round-robin), which keeps an element's
-// operands in that XCD's L2.
+// Tiling: a workgroup computes a BM x BN tile of one problem; its waves form a
+// WM x WN grid, each owning (BM/WM) x (BN/WN) as a block of 16x16x4 MFMAs.  K advances in steps of 16: the next A and B slabs are loaded
+// into registers (coalesced: consecutive lanes read consecutive addresses)
+// while the current slabs, double-buffered in LDS, feed the matrix cores.  A is
+// stored k-major in LDS so the 16 lanes of one MFMA operand column read
+// consecutive words.  The tile list orders tiles so that one problem's tiles
+// share an XCD (workgroups are dealt to the 8 XCDs round-robin), keeping an
+// element's operands in that XCD's L2.
 #include "internal.hpp"
 #include "mfma.hpp"
 
@@ -19,18 +20,30 @@ namespace scdg {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
-constexpr int kThreads = 256;
+constexpr int BK = 16;
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void gemm_batched_kernel(const GemmDesc *__restrict__ desc,
+template <typename T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_batched_kernel(const GemmDesc *__restrict__ desc,
                                                                 const int32_t *__restrict__ tiles,
                                                                 const T *__restrict__ A,
                                                                 const T *__restrict__ B,
                                                                 T *__restrict__ C, T alpha, T beta) {
   using M = Mfma<T>;
-  __shared__ T as[BK][BM + 1];
-  __shared__ T bs[BK][BN + 1];
+  constexpr int kThreads = 64 * WM * WN;
+  constexpr int PA = BM + 4;             // LDS row strides (padding against bank conflicts)
+  constexpr int PB = BN + 4;
+  constexpr int WTM = BM / WM, WTN = BN / WN;          // wave tile
+  constexpr int TM = WTM / 16, TN = WTN / 16;          // MFMA blocks per wave
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be a multiple of 16");
+  static_assert((BM * BK) % kThreads == 0 && kThreads % BK == 0, "A slab split");
+  static_assert((BN * BK) % kThreads == 0 && kThreads % BN == 0, "B slab split");
+  constexpr int A_ELEMS = BM * BK / kThreads;          // per-thread slab loads
+  constexpr int B_ELEMS = BN * BK / kThreads;
+  constexpr int A_ROWS_PER_STEP = kThreads / BK;       // rows of A covered per load step
+  constexpr int B_ROWS_PER_STEP = kThreads / BN;       // k rows of B covered per load step
+  __shared__ T as[2][BK][PA];
+  __shared__ T bs[2][BK][PB];
+
   int prob, tm, tn;
   if (tiles != nullptr) {
     prob = tiles[3 * blockIdx.x];
@@ -53,58 +66,73 @@ __global__ __launch_bounds__(kThreads) void gemm_batched_kernel(const GemmDesc *
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
-  const int wm = wid >> 1, wn = wid & 1;
+  const int wm = wid / WN, wn = wid % WN;
 
-  typename M::acc_t acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
+  // A slab: lane t reads k = t % 16 of rows t / 16 + step * 16
+  const int a_k = tid % BK, a_r = tid / BK;
+  // B slab: lane t reads column t % BN of k rows t / BN + step * (threads / BN)
+  const int b_c = tid % BN, b_k = tid / BN;
 
-  // per-thread load coordinates
-  const int a_row = tid >> 2, a_k = (tid & 3) * 4;      // A: 64 rows x 16 k
-  const int b_k = tid >> 4, b_col = (tid & 15) * 4;     // B: 16 k x 64 cols
-
-  for (int k0 = 0; k0 < d.k; k0 += BK) {
-    {
-      const int gr = m0 + a_row;
+  T ra[A_ELEMS], rb[B_ELEMS];
+  auto load = [&](int k0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gk = k0 + a_k + u;
-        as[a_k + u][a_row] = (gr < d.m && gk < d.k) ? a[(int64_t)gr * d.lda + gk] : T(0);
-      }
-      const int gk = k0 + b_k;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gc = n0 + b_col + u;
-        bs[b_k][b_col + u] = (gk < d.k && gc < d.n) ? b[(int64_t)gk * d.ldb + gc] : T(0);
-      }
+    for (int u = 0; u < A_ELEMS; ++u) {
+      const int row = m0 + a_r + u * A_ROWS_PER_STEP, k = k0 + a_k;
+      ra[u] = (row < d.m && k < d.k) ? a[(int64_t)row * d.lda + k] : T(0);
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < B_ELEMS; ++u) {
+      const int k = k0 + b_k + u * B_ROWS_PER_STEP, col = n0 + b_c;
+      rb[u] = (k < d.k && col < d.n) ? b[(int64_t)k * d.ldb + col] : T(0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < A_ELEMS; ++u) as[buf][a_k][a_r + u * A_ROWS_PER_STEP] = ra[u];
+#pragma unroll
+    for (int u = 0; u < B_ELEMS; ++u) bs[buf][b_k + u * B_ROWS_PER_STEP][b_c] = rb[u];
+  };
+
+  typename M::acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = M::zero();
+
+  const int nk = (d.k + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      T af[2], bf[2];
+      T af[TM], bf[TN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) af[i] = as[kk + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
+      for (int i = 0; i < TM; ++i)
+        af[i] = as[buf][kk + (lane >> 4)][wm * WTM + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bf[j] = bs[kk + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
+      for (int j = 0; j < TN; ++j)
+        bf[j] = bs[buf][kk + (lane >> 4)][wn * WTN + j * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = M::mma(af[i], bf[j], acc[i][j]);
+        for (int j = 0; j < TN; ++j) acc[i][j] = M::mma(af[i], bf[j], acc[i][j]);
     }
+    if (kt + 1 < nk) store(buf ^ 1);
     __syncthreads();
   }
 
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn * WTN + j * 16 + (lane & 15);
       if (col >= d.n) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 32 + i * 16 + M::row(lane, r);
+        const int row = m0 + wm * WTM + i * 16 + M::row(lane, r);
         if (row < d.m) {
           T *dst = c + (int64_t)row * d.ldc + col;
           T v = alpha * acc[i][j][r];
@@ -115,25 +143,50 @@ __global__ __launch_bounds__(kThreads) void gemm_batched_kernel(const GemmDesc *
     }
 }
 
-}  // namespace
-
-int gemm_tile_m() { return BM; }
-int gemm_tile_n() { return BN; }
-
-hipError_t launch_gemm_batched(const GemmDesc *d_desc, const int32_t *d_tiles, int32_t n_tiles,
-                               const void *a, const void *b, void *c, double alpha, double beta,
-                               bool fp32, hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
+template <int BM, int BN, int WM, int WN>
+hipError_t launch_cfg(const GemmDesc *d_desc, const int32_t *d_tiles, int32_t n_tiles,
+                      const void *a, const void *b, void *c, double alpha, double beta, bool fp32,
+                      hipStream_t s) {
+  const dim3 block(64 * WM * WN);
   if (fp32) {
-    hipLaunchKernelGGL(gemm_batched_kernel<float>, dim3(n_tiles), dim3(kThreads), 0, s, d_desc,
-                       d_tiles, static_cast<const float *>(a), static_cast<const float *>(b),
+    hipLaunchKernelGGL((gemm_batched_kernel<float, BM, BN, WM, WN>), dim3(n_tiles), block, 0, s,
+                       d_desc, d_tiles, static_cast<const float *>(a), static_cast<const float *>(b),
                        static_cast<float *>(c), (float)alpha, (float)beta);
   } else {
-    hipLaunchKernelGGL(gemm_batched_kernel<double>, dim3(n_tiles), dim3(kThreads), 0, s, d_desc,
-                       d_tiles, static_cast<const double *>(a), static_cast<const double *>(b),
+    hipLaunchKernelGGL((gemm_batched_kernel<double, BM, BN, WM, WN>), dim3(n_tiles), block, 0, s,
+                       d_desc, d_tiles, static_cast<const double *>(a), static_cast<const double *>(b),
                        static_cast<double *>(c), alpha, beta);
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+// Tile configurations: C tile rows x columns and the wave grid.
+//   0: 64x64 (2x2 waves)    1: 64x128 (2x2)    2: 128x128 (2x2)
+//   3: 128x128 (2x4 waves)  4: 128x64 (2x2)    5: 240x80 (5x1; divides 1200 = n_c at N = 5)
+//   6: 80x80 (5x1 waves)
+void gemm_tile_shape(int cfg, int *bm, int *bn) {
+  static const int shapes[kGemmConfigs][2] = {{64, 64}, {64, 128}, {128, 128}, {128, 128},
+                                              {128, 64}, {240, 80}, {80, 80}};
+  if (cfg < 0 || cfg >= kGemmConfigs) cfg = 0;
+  *bm = shapes[cfg][0];
+  *bn = shapes[cfg][1];
+}
+
+hipError_t launch_gemm_batched(int cfg, const GemmDesc *d_desc, const int32_t *d_tiles,
+                               int32_t n_tiles, const void *a, const void *b, void *c, double alpha,
+                               double beta, bool fp32, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (cfg) {
+    case 1: return launch_cfg<64, 128, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
+    case 2: return launch_cfg<128, 128, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
+    case 3: return launch_cfg<128, 128, 2, 4>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
+    case 4: return launch_cfg<128, 64, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
+    case 5: return launch_cfg<240, 80, 5, 1>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
+    case 6: return launch_cfg<80, 80, 5, 1>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
+    default: return launch_cfg<64, 64, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
+  }
 }
 
 }  // namespace scdg

@@ -1,9 +1,10 @@
 // Memory-bound kernels of the condensed solve: batched element GEMVs with
-// coalesced gathers of the DOFs they read, the A_bb BSR product fused with the
-// "pull" reduction of element Schur contributions, and the Krylov vector
-// operations (deterministic two-stage multi-dot for Gram-Schmidt, multi-AXPY,
-// scaling).  All vectors are FP64; matrices may be FP64 or FP32 (accumulation
-// is always FP64).
+// coalesced gathers of the DOFs they read, the (remainder of the) A_bb BSR
+// product fused with the "pull" reduction of element contributions, the A_bb
+// fold into the element Schur blocks, the Jacobi preconditioners, and the
+// Krylov vector operations (deterministic two-stage multi-dot for Gram-Schmidt,
+// multi-AXPY, scaling).  All vectors are FP64; element matrices may be FP64 or
+// FP32 (accumulation is always FP64).
 #include "internal.hpp"
 #include "mfma.hpp"
 
@@ -13,16 +14,45 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kRowsPerTile = 64;
+constexpr int kRowsPerWave = kRowsPerTile / (kThreads / 64);   // 16
+constexpr int kRowBatch = 8;                                    // rows streamed together
+
+template <typename TM>
+struct Vec;
+template <>
+struct Vec<double> {
+  static constexpr int W = 2;
+  using V = double2;
+  static __device__ __forceinline__ void get(const V &v, double *o) {
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+};
+template <>
+struct Vec<float> {
+  static constexpr int W = 4;
+  using V = float4;
+  static __device__ __forceinline__ void get(const V &v, double *o) {
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+};
 
 // ---------------------------------------------------------------- GEMV
 // One workgroup = 64 rows of one element matrix.  The element's input vector is
-// gathered once into LDS; each wave then streams 16 rows, four at a time, with
-// lanes striding along the row (coalesced), and reduces with cross-lane adds.
+// gathered once into LDS; each wave streams 16 rows, eight at a time, with
+// lanes striding along the rows in 16-byte vectors (coalesced), and reduces
+// with cross-lane adds.  Rows whose length or base is not a multiple of the
+// vector width take the scalar path.
 template <typename TM>
 __global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
     const GemvDesc *__restrict__ desc, const RowTile *__restrict__ tiles, const TM *__restrict__ mat,
     const double *__restrict__ x, const int32_t *__restrict__ xmap, double *__restrict__ y,
     const int32_t *__restrict__ omap, double alpha, double beta, const double *__restrict__ y0) {
+  using VT = Vec<TM>;
+  constexpr int W = VT::W;
   extern __shared__ double xs[];
   const RowTile t = tiles[blockIdx.x];
   const GemvDesc d = desc[t.prob];
@@ -30,24 +60,50 @@ __global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
   for (int c = tid; c < d.cols; c += kThreads) xs[c] = xmap ? x[xmap[d.x_off + c]] : x[d.x_off + c];
   __syncthreads();
   const TM *__restrict__ base = mat + d.m_off;
-  const int r_begin = t.row0 + wid * (kRowsPerTile / 4);
-  const int r_end = min(d.rows, r_begin + kRowsPerTile / 4);
-  for (int r = r_begin; r < r_end; r += 4) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    const TM *rows[4];
+  const int r_begin = t.row0 + wid * kRowsPerWave;
+  const int r_end = min(d.rows, r_begin + kRowsPerWave);
+  const bool vec_ok = (d.cols % W) == 0 && (d.m_off % W) == 0;
+  const int nvec = d.cols / W;
+  for (int r = r_begin; r < r_end; r += kRowBatch) {
+    double s[kRowBatch];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) rows[q] = base + (int64_t)min(r + q, d.rows - 1) * d.cols;
-    for (int c = lane; c < d.cols; c += 64) {
-      const double xv = xs[c];
+    for (int q = 0; q < kRowBatch; ++q) s[q] = 0.0;
+    if (vec_ok) {
+      const typename VT::V *rows[kRowBatch];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s[q] += (double)rows[q][c] * xv;
+      for (int q = 0; q < kRowBatch; ++q)
+        rows[q] = reinterpret_cast<const typename VT::V *>(base + (int64_t)min(r + q, r_end - 1) * d.cols);
+      for (int c = lane; c < nvec; c += 64) {
+        double xv[W];
+#pragma unroll
+        for (int u = 0; u < W; ++u) xv[u] = xs[c * W + u];
+        typename VT::V m[kRowBatch];
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q) m[q] = rows[q][c];
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q) {
+          double mv[W];
+          VT::get(m[q], mv);
+#pragma unroll
+          for (int u = 0; u < W; ++u) s[q] += mv[u] * xv[u];
+        }
+      }
+    } else {
+      const TM *rows[kRowBatch];
+#pragma unroll
+      for (int q = 0; q < kRowBatch; ++q) rows[q] = base + (int64_t)min(r + q, r_end - 1) * d.cols;
+      for (int c = lane; c < d.cols; c += 64) {
+        const double xv = xs[c];
+#pragma unroll
+        for (int q = 0; q < kRowBatch; ++q) s[q] += (double)rows[q][c] * xv;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s[q] = wave_sum(s[q]);
-    if (lane < 4 && r + lane < r_end) {
+    for (int q = 0; q < kRowBatch; ++q) s[q] = wave_sum(s[q]);
+    if (lane < kRowBatch && r + lane < r_end) {
       double v = s[0];
 #pragma unroll
-      for (int q = 1; q < 4; ++q)
+      for (int q = 1; q < kRowBatch; ++q)
         if (lane == q) v = s[q];
       const int yi = d.y_off + r + lane;
       v *= alpha;
@@ -57,52 +113,160 @@ __global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
   }
 }
 
-// ---------------------------------------------------- A_bb product + pull
-// One wave per boundary node g (5 output rows).  Lanes take the BSR blocks of
-// row g in turn; each block is 25 contiguous doubles.
+// ---------------------------------------------------- BSR product + pull
+// One wave per boundary node g (5 output rows).  Lanes 0..59 cover 12 blocks of
+// row g at a time, lane l taking row (l % 5) of block (l / 5); each lane reads
+// 5 contiguous values, so a wave reads 12 whole blocks (2400 bytes) per step.
+// Partial sums meet in LDS (wave-private slice) and lanes 0..4 finish the rows.
 __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
     int64_t n_bnodes, double c0, const double *__restrict__ src0, const int32_t *__restrict__ map0,
     double c1, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-    const double *__restrict__ val, const double *__restrict__ x, double c2,
-    const int32_t *__restrict__ pull_ptr, const int32_t *__restrict__ pull_idx,
-    const double *__restrict__ t, double *__restrict__ out) {
+    const int32_t *__restrict__ src_idx, const double *__restrict__ val,
+    const double *__restrict__ x, double c2, const int32_t *__restrict__ pull_ptr,
+    const int32_t *__restrict__ pull_idx, const double *__restrict__ t, double *__restrict__ out) {
+  __shared__ double part[kThreads];
   const int lane = threadIdx.x & 63;
-  const int64_t g = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  if (g >= n_bnodes) return;
-  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (c1 != 0.0) {
-    for (int64_t blk = rowptr[g] + lane; blk < rowptr[g + 1]; blk += 64) {
-      const double *v = val + blk * 25;
+  const int wid = threadIdx.x >> 6;
+  const int64_t g = (int64_t)blockIdx.x * (kThreads / 64) + wid;
+  const bool active = g < n_bnodes;
+  double s = 0.0;
+  const int v = lane % 5, bq = lane / 5;
+  if (active && c1 != 0.0 && lane < 60) {
+    for (int64_t blk = rowptr[g] + bq; blk < rowptr[g + 1]; blk += 12) {
+      const int64_t vb = src_idx ? (int64_t)src_idx[blk] : blk;
+      const double *vr = val + vb * 25 + v * 5;
       const double *xv = x + (int64_t)col[blk] * 5;
-      double xw[5];
 #pragma unroll
-      for (int w = 0; w < 5; ++w) xw[w] = xv[w];
-#pragma unroll
-      for (int r = 0; r < 5; ++r) {
-        double acc = 0.0;
-#pragma unroll
-        for (int w = 0; w < 5; ++w) acc += v[r * 5 + w] * xw[w];
-        s[r] += acc;
-      }
+      for (int w = 0; w < 5; ++w) s += vr[w] * xv[w];
     }
-#pragma unroll
-    for (int r = 0; r < 5; ++r) s[r] = wave_sum(s[r]);
   }
-  if (lane < 5) {
-    double mine = s[0];
-#pragma unroll
-    for (int r = 1; r < 5; ++r)
-      if (lane == r) mine = s[r];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (active && lane < 5) {
+    const double *pw = part + wid * 64;
+    double acc = 0.0;
+    for (int q = lane; q < 60; q += 5) acc += pw[q];
     const int64_t j = 5 * g + lane;
-    double v = c1 * mine;
-    if (c0 != 0.0) v += c0 * src0[map0 ? map0[j] : j];
+    double o = c1 * acc;
+    if (c0 != 0.0) o += c0 * src0[map0 ? map0[j] : j];
     if (c2 != 0.0) {
       double p = 0.0;
       for (int q = pull_ptr[g]; q < pull_ptr[g + 1]; ++q) p += t[5 * (int64_t)pull_idx[q] + lane];
-      v += c2 * p;
+      o += c2 * p;
     }
-    out[j] = v;
+    out[j] = o;
   }
+}
+
+// T[dst + v nc + w] += A_bb[src][v][w]
+template <typename TM>
+__global__ void fold_add_kernel(int64_t n_fold, const int64_t *__restrict__ dst,
+                                const int32_t *__restrict__ nc, const int32_t *__restrict__ src,
+                                const double *__restrict__ val, TM *__restrict__ t) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n_fold * 25) return;
+  const int64_t f = q / 25;
+  const int k = (int)(q % 25), v = k / 5, w = k % 5;
+  TM *p = t + dst[f] + (int64_t)v * nc[f] + w;
+  *p = (TM)((double)*p + val[(int64_t)src[f] * 25 + k]);
+}
+
+// 5x5 inverse by Gauss-Jordan with partial pivoting, in registers
+__device__ void inv5(const double a[25], double out[25]) {
+  double m[5][10];
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int c = 0; c < 10; ++c) m[r][c] = c < 5 ? a[r * 5 + c] : (c - 5 == r ? 1.0 : 0.0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    int p = k;
+#pragma unroll
+    for (int r = k + 1; r < 5; ++r)
+      if (fabs(m[r][k]) > fabs(m[p][k])) p = r;
+#pragma unroll
+    for (int r = k + 1; r < 5; ++r)
+      if (r == p)
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+          const double tmp = m[k][c];
+          m[k][c] = m[r][c];
+          m[r][c] = tmp;
+        }
+    double d = m[k][k];
+    if (!(d != 0.0) || !isfinite(d)) d = 1.0;
+    const double id = 1.0 / d;
+#pragma unroll
+    for (int c = 0; c < 10; ++c) m[k][c] *= id;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      if (r == k) continue;
+      const double f = m[r][k];
+#pragma unroll
+      for (int c = 0; c < 10; ++c) m[r][c] -= f * m[k][c];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[r * 5 + c] = m[r][c + 5];
+}
+
+// D_g = remainder A_bb(g, g) + sum over elements containing g of T_e's diagonal block
+template <typename TM>
+__global__ void precond_setup_kernel(int64_t n_bnodes, const int64_t *__restrict__ rem_rowptr,
+                                     const int32_t *__restrict__ rem_col,
+                                     const int32_t *__restrict__ rem_src,
+                                     const double *__restrict__ val,
+                                     const int32_t *__restrict__ pull_ptr,
+                                     const int32_t *__restrict__ pull_idx,
+                                     const int64_t *__restrict__ slot_soff,
+                                     const int32_t *__restrict__ slot_nc,
+                                     const int32_t *__restrict__ slot_pos, const TM *__restrict__ t,
+                                     double *__restrict__ pc_blk, double *__restrict__ diag_inv) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= n_bnodes) return;
+  double a[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) a[k] = 0.0;
+  for (int64_t b = rem_rowptr[g]; b < rem_rowptr[g + 1]; ++b)
+    if (rem_col[b] == g)
+#pragma unroll
+      for (int k = 0; k < 25; ++k) a[k] += val[(int64_t)rem_src[b] * 25 + k];
+  for (int q = pull_ptr[g]; q < pull_ptr[g + 1]; ++q) {
+    const int s = pull_idx[q];
+    const int64_t base = slot_soff[s] + (int64_t)(5 * slot_pos[s]) * slot_nc[s] + 5 * slot_pos[s];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int w = 0; w < 5; ++w) a[v * 5 + w] += (double)t[base + (int64_t)v * slot_nc[s] + w];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) diag_inv[5 * g + v] = 1.0 / a[v * 5 + v];
+  double inv[25];
+  inv5(a, inv);
+#pragma unroll
+  for (int k = 0; k < 25; ++k) pc_blk[g * 25 + k] = inv[k];
+}
+
+__global__ void precond_apply_kernel(int mode, int64_t n_bnodes, const double *__restrict__ diag_inv,
+                                     const double *__restrict__ pc_blk,
+                                     const double *__restrict__ x, double *__restrict__ y, double a) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= 5 * n_bnodes) return;
+  double v;
+  if (mode == 2) {
+    const int64_t g = j / 5;
+    const int r = (int)(j % 5);
+    const double *m = pc_blk + g * 25 + r * 5;
+    const double *xv = x + 5 * g;
+    v = m[0] * xv[0] + m[1] * xv[1] + m[2] * xv[2] + m[3] * xv[3] + m[4] * xv[4];
+  } else if (mode == 1) {
+    v = diag_inv[j] * x[j];
+  } else {
+    v = x[j];
+  }
+  y[j] = a * v;
 }
 
 // ------------------------------------------------------------ utilities
@@ -211,31 +375,6 @@ __global__ void multi_axpy_kernel(const double *__restrict__ v, int64_t ld, int 
   }
 }
 
-// diag(S) = diag(A_bb) - sum over elements containing the node of the element block diagonal
-template <typename TM>
-__global__ void diag_schur_kernel(int64_t n_bnodes, const int64_t *__restrict__ rowptr,
-                                  const int32_t *__restrict__ col, const double *__restrict__ val,
-                                  const int32_t *__restrict__ pull_ptr,
-                                  const int32_t *__restrict__ pull_idx,
-                                  const int64_t *__restrict__ slot_elem_off,
-                                  const int32_t *__restrict__ slot_nc,
-                                  const int32_t *__restrict__ slot_pos, const TM *__restrict__ sloc,
-                                  double *__restrict__ diag) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= 5 * n_bnodes) return;
-  const int64_t g = j / 5;
-  const int v = (int)(j % 5);
-  double dval = 0.0;
-  for (int64_t b = rowptr[g]; b < rowptr[g + 1]; ++b)
-    if (col[b] == g) dval += val[b * 25 + v * 5 + v];
-  for (int q = pull_ptr[g]; q < pull_ptr[g + 1]; ++q) {
-    const int s = pull_idx[q];
-    const int64_t row = 5 * (int64_t)slot_pos[s] + v;
-    dval -= (double)sloc[slot_elem_off[s] + row * slot_nc[s] + row];
-  }
-  diag[j] = dval;
-}
-
 inline int grid_for(int64_t n) {
   int64_t b = (n + kThreads - 1) / kThreads;
   if (b > 8192) b = 8192;
@@ -261,13 +400,50 @@ hipError_t launch_gemv_batched(const GemvDesc *d_desc, const RowTile *d_tiles, i
   return hipGetLastError();
 }
 
-hipError_t launch_bsr_pull(const Plan &p, double c0, const double *src0, const int32_t *map0,
-                           double c1, const double *x, double c2, const double *t, double *out) {
+hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *src0,
+                           const int32_t *map0, double c1, const double *x, double c2,
+                           const double *t, double *out) {
   const int64_t nb = p.n_bnodes;
   const int grid = (int)((nb + (kThreads / 64) - 1) / (kThreads / 64));
   hipLaunchKernelGGL(bsr_pull_kernel, dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0,
-                     c1, p.d_bb_rowptr, p.d_bb_col, p.bb_val, x, c2, p.d_pull_ptr, p.d_pull_idx, t,
+                     c1, full ? p.d_bb_rowptr : p.d_rem_rowptr, full ? p.d_bb_col : p.d_rem_col,
+                     full ? nullptr : p.d_rem_src, p.bb_val, x, c2, p.d_pull_ptr, p.d_pull_idx, t,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_add(const Plan &p, void *t, bool fp32) {
+  if (p.n_fold == 0) return hipSuccess;
+  const int64_t n = p.n_fold * 25;
+  const int grid = (int)((n + kThreads - 1) / kThreads);
+  if (fp32)
+    hipLaunchKernelGGL(fold_add_kernel<float>, dim3(grid), dim3(kThreads), 0, p.stream, p.n_fold,
+                       p.d_fold_dst, p.d_fold_nc, p.d_fold_src, p.bb_val, static_cast<float *>(t));
+  else
+    hipLaunchKernelGGL(fold_add_kernel<double>, dim3(grid), dim3(kThreads), 0, p.stream, p.n_fold,
+                       p.d_fold_dst, p.d_fold_nc, p.d_fold_src, p.bb_val, static_cast<double *>(t));
+  return hipGetLastError();
+}
+
+hipError_t launch_precond_setup(const Plan &p, const void *t, bool fp32) {
+  const int grid = (int)((p.n_bnodes + 127) / 128);
+  if (fp32)
+    hipLaunchKernelGGL(precond_setup_kernel<float>, dim3(grid), dim3(128), 0, p.stream, p.n_bnodes,
+                       p.d_rem_rowptr, p.d_rem_col, p.d_rem_src, p.bb_val, p.d_pull_ptr,
+                       p.d_pull_idx, p.d_slot_soff, p.d_slot_nc, p.d_slot_pos,
+                       static_cast<const float *>(t), p.pc_blk, p.diag_s);
+  else
+    hipLaunchKernelGGL(precond_setup_kernel<double>, dim3(grid), dim3(128), 0, p.stream, p.n_bnodes,
+                       p.d_rem_rowptr, p.d_rem_col, p.d_rem_src, p.bb_val, p.d_pull_ptr,
+                       p.d_pull_idx, p.d_slot_soff, p.d_slot_nc, p.d_slot_pos,
+                       static_cast<const double *>(t), p.pc_blk, p.diag_s);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond_apply(const Plan &p, int mode, const double *x, double *y, double a) {
+  const int64_t n = 5 * p.n_bnodes;
+  hipLaunchKernelGGL(precond_apply_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, p.stream, mode, p.n_bnodes, p.diag_s, p.pc_blk, x, y, a);
   return hipGetLastError();
 }
 
@@ -343,23 +519,6 @@ hipError_t launch_multi_axpy(const double *v, int64_t ld, int32_t nv, const doub
   if (n <= 0 || nv <= 0) return hipSuccess;
   hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, v, ld, nv, h, w,
                      n);
-  return hipGetLastError();
-}
-
-hipError_t launch_diag_schur(const Plan &p, const void *sloc, bool fp32, double *diag) {
-  const int64_t n = 5 * p.n_bnodes;
-  const int grid = (int)((n + kThreads - 1) / kThreads);
-  if (fp32) {
-    hipLaunchKernelGGL(diag_schur_kernel<float>, dim3(grid), dim3(kThreads), 0, p.stream,
-                       p.n_bnodes, p.d_bb_rowptr, p.d_bb_col, p.bb_val, p.d_pull_ptr, p.d_pull_idx,
-                       p.d_slot_soff, p.d_slot_nc, p.d_slot_pos, static_cast<const float *>(sloc),
-                       diag);
-  } else {
-    hipLaunchKernelGGL(diag_schur_kernel<double>, dim3(grid), dim3(kThreads), 0, p.stream,
-                       p.n_bnodes, p.d_bb_rowptr, p.d_bb_col, p.bb_val, p.d_pull_ptr, p.d_pull_idx,
-                       p.d_slot_soff, p.d_slot_nc, p.d_slot_pos, static_cast<const double *>(sloc),
-                       diag);
-  }
   return hipGetLastError();
 }
 

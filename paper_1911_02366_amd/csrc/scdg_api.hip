@@ -83,7 +83,9 @@ void local_node_sets(int order, std::vector<int> &interior, std::vector<int> &bo
 // Tile list ordered so that the workgroups of one problem share an XCD: block b
 // runs on XCD b % 8, so block b takes tile (b % 8) * per + b / 8 of the
 // problem-major list.
-std::vector<int32_t> xcd_tile_list(const std::vector<GemmDesc> &descs, int bm, int bn) {
+std::vector<int32_t> xcd_tile_list(const std::vector<GemmDesc> &descs, int cfg) {
+  int bm, bn;
+  gemm_tile_shape(cfg, &bm, &bn);
   std::vector<int32_t> flat;
   for (size_t q = 0; q < descs.size(); ++q) {
     const int tm = (descs[q].m + bm - 1) / bm, tn = (descs[q].n + bn - 1) / bn;
@@ -170,7 +172,7 @@ scdg_status condense_rhs_impl(Plan &p, const double *b, double *bs) {
   const void *abi = fp32(p) ? p.abi_lo : static_cast<const void *>(p.abi);
   HIP_TRY(launch_gemv_batched(p.d_gv_abi, p.d_rt_abi, p.n_rt_abi, p.max_ni, abi, fp32(p), p.w_z,
                               nullptr, p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream));
-  HIP_TRY(launch_bsr_pull(p, 1.0, b, p.d_bmap, 0.0, nullptr, -1.0, p.w_t, bs));
+  HIP_TRY(launch_bsr_pull(p, false, 1.0, b, p.d_bmap, 0.0, nullptr, -1.0, p.w_t, bs));
   return SCDG_OK;
 }
 
@@ -178,7 +180,8 @@ scdg_status schur_apply_impl(Plan &p, const double *x, double *y) {
   PhaseTimer tm(p, SCDG_PHASE_SCHUR_APPLY);
   HIP_TRY(launch_gemv_batched(p.d_gv_s, p.d_rt_s, p.n_rt_s, p.max_nc, p.sloc, fp32(p), x, p.d_cmap,
                               p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream));
-  HIP_TRY(launch_bsr_pull(p, 0.0, nullptr, nullptr, 1.0, x, -1.0, p.w_t, y));
+  // S x = A_bb,rem x + sum_e P_e T_e x[C_e],  T_e = folded A_bb blocks - A_bi(e) X_e
+  HIP_TRY(launch_bsr_pull(p, false, 0.0, nullptr, nullptr, 1.0, x, 1.0, p.w_t, y));
   return SCDG_OK;
 }
 
@@ -204,7 +207,7 @@ scdg_status residual_impl(Plan &p, const double *b, const double *dq, double *r)
   // boundary rows: B_b - A_bb dQ_b - pull(A_bi dQ_i)
   HIP_TRY(launch_gemv_batched(p.d_gv_abi, p.d_rt_abi, p.n_rt_abi, p.max_ni, p.abi, false, dq,
                               p.d_imap, p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream));
-  HIP_TRY(launch_bsr_pull(p, 1.0, b, p.d_bmap, -1.0, p.w_qb, -1.0, p.w_t, p.w_bs));
+  HIP_TRY(launch_bsr_pull(p, true, 1.0, b, p.d_bmap, -1.0, p.w_qb, -1.0, p.w_t, p.w_bs));
   HIP_TRY(launch_scatter(p.w_bs, p.d_bmap, r, p.n1, p.stream));
   return SCDG_OK;
 }
@@ -221,7 +224,7 @@ scdg_status gmres(Plan &p, const double *bs, double *x, const double *x0, const 
   const int64_t n = p.n1;
   const int m = o.restart;
   ST_TRY(ensure_gmres(p, m));
-  const double *dinv = o.precond ? p.diag_s : nullptr;  // diag_s holds 1 / diag(S)
+  const int pmode = o.precond;  // 0 none, 1 point Jacobi, 2 5x5 node-block Jacobi
   double bnorm2;
   ST_TRY(norm2sq(p, bs, n, &bnorm2));
   if (!std::isfinite(bnorm2)) {
@@ -263,7 +266,7 @@ scdg_status gmres(Plan &p, const double *bs, double *x, const double *x0, const 
     for (int j = 0; j < m && it < o.max_iters; ++j) {
       double *vj = p.gm_v + (int64_t)j * n;
       double *w = p.gm_w;
-      HIP_TRY(launch_diag_scale(vj, dinv, p.gm_z, n, 1.0, p.stream));
+      HIP_TRY(launch_precond_apply(p, pmode, vj, p.gm_z, 1.0));
       ST_TRY(schur_apply_impl(p, p.gm_z, w));
       // classical Gram-Schmidt, twice (FP64)
       HIP_TRY(launch_multidot(p.gm_v, n, j + 1, w, n, p.gm_part, p.red_blocks, p.gm_h, p.stream));
@@ -307,8 +310,8 @@ scdg_status gmres(Plan &p, const double *bs, double *x, const double *x0, const 
     HIP_TRY(hipMemcpyAsync(p.gm_h, p.h_pinned, sizeof(double) * jused, hipMemcpyHostToDevice, p.stream));
     HIP_TRY(hipMemsetAsync(p.gm_z, 0, sizeof(double) * n, p.stream));
     HIP_TRY(launch_multi_axpy(p.gm_v, n, jused, p.gm_h, p.gm_z, n, p.stream));
-    HIP_TRY(launch_diag_scale(p.gm_z, dinv, p.gm_z, n, 1.0, p.stream));
-    HIP_TRY(launch_axpby(n, 1.0, p.gm_z, 1.0, x, p.stream));
+    HIP_TRY(launch_precond_apply(p, pmode, p.gm_z, p.gm_w, 1.0));
+    HIP_TRY(launch_axpby(n, 1.0, p.gm_w, 1.0, x, p.stream));
     // true residual
     ST_TRY(schur_apply_impl(p, x, r));
     HIP_TRY(launch_axpby(n, 1.0, bs, -1.0, r, p.stream));
@@ -349,6 +352,7 @@ void defaults(scdg_solve_opts &o) {
   if (o.max_iters <= 0) o.max_iters = 1000;
   if (o.tol <= 0) o.tol = 1e-10;
   if (o.precond < 0) o.precond = 1;
+  if (o.precond > 2) o.precond = 2;
   if (o.ir_max <= 0) o.ir_max = 10;
   if (o.ir_tol <= 0) o.ir_tol = 1e-8;
 }
@@ -407,11 +411,13 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   (void)hipStreamSynchronize(p.stream);
   dfree(p.d_imap); dfree(p.d_bmap); dfree(p.d_cmap); dfree(p.d_pull_ptr); dfree(p.d_pull_idx);
   dfree(p.d_slot_soff); dfree(p.d_slot_nc); dfree(p.d_slot_pos);
+  dfree(p.d_fold_dst); dfree(p.d_fold_nc); dfree(p.d_fold_src);
+  dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk);
   dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_info);
   dfree(p.d_gx); dfree(p.d_gs); dfree(p.d_tiles_x); dfree(p.d_tiles_s);
   dfree(p.d_gv_inv); dfree(p.d_gv_abi); dfree(p.d_gv_aib); dfree(p.d_gv_s);
   dfree(p.d_rt_inv); dfree(p.d_rt_abi); dfree(p.d_rt_aib); dfree(p.d_rt_s);
-  dfree(p.ainv); dfree(p.xmat); dfree(p.sloc); dfree(p.aib_lo); dfree(p.abi_lo); dfree(p.diag_s);
+  dfree(p.ainv); dfree(p.ainv_work); dfree(p.xmat); dfree(p.sloc); dfree(p.aib_lo); dfree(p.abi_lo); dfree(p.diag_s);
   dfree(p.s_dense); dfree(p.s_piv); dfree(p.d_dense_info);
   dfree(p.w_z); dfree(p.w_t); dfree(p.w_bs); dfree(p.w_qb); dfree(p.w_r); dfree(p.w_dq); dfree(p.w_vec);
   dfree(p.gm_v); dfree(p.gm_w); dfree(p.gm_z); dfree(p.gm_part); dfree(p.gm_h);
@@ -541,6 +547,55 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
       slot_pos[slot] = (int32_t)(q - c0);
     }
   }
+  // ---- A_bb fold: block (g, h) goes to the element that owns node g when both
+  // g and h lie in its coupling set, else to the lowest-numbered element whose
+  // coupling set holds both; blocks with no such element form the remainder.
+  std::vector<int32_t> slot_elem(n_slots);
+  for (int e = 0; e < E; ++e)
+    for (int64_t q = s->c_ptr[e]; q < s->c_ptr[e + 1]; ++q)
+      slot_elem[p.off_c[e] / kNvar + (q - s->c_ptr[e])] = e;
+  std::vector<int64_t> fold_dst;
+  std::vector<int32_t> fold_nc, fold_src, rem_col, rem_src;
+  std::vector<int64_t> rem_rowptr(p.n_bnodes + 1, 0);
+  {
+    std::vector<std::pair<int, int>> cand;
+    for (int64_t g = 0; g < p.n_bnodes; ++g) {
+      const int owner = (int)(std::upper_bound(p.bnode_off.begin(), p.bnode_off.end(), g) -
+                              p.bnode_off.begin()) - 1;
+      cand.clear();
+      for (int q = pull_ptr[g]; q < pull_ptr[g + 1]; ++q)
+        cand.emplace_back(slot_elem[pull_idx[q]], slot_pos[pull_idx[q]]);
+      std::sort(cand.begin(), cand.end(), [owner](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+        const bool ao = a.first == owner, bo = b.first == owner;
+        if (ao != bo) return ao;
+        return a.first < b.first;
+      });
+      for (int64_t t = s->bb_rowptr[g]; t < s->bb_rowptr[g + 1]; ++t) {
+        const int32_t h = s->bb_col[t];
+        bool done = false;
+        for (const auto &cp : cand) {
+          const int e = cp.first;
+          const int32_t *cb = s->c_node + s->c_ptr[e], *ce = s->c_node + s->c_ptr[e + 1];
+          const int32_t *it = std::lower_bound(cb, ce, h);
+          if (it != ce && *it == h) {
+            const int64_t pos_h = it - cb;
+            fold_dst.push_back(p.off_cc[e] + (int64_t)(kNvar * cp.second) * p.nc[e] + kNvar * pos_h);
+            fold_nc.push_back(p.nc[e]);
+            fold_src.push_back((int32_t)t);
+            done = true;
+            break;
+          }
+        }
+        if (!done) {
+          rem_col.push_back(h);
+          rem_src.push_back((int32_t)t);
+        }
+      }
+      rem_rowptr[g + 1] = (int64_t)rem_col.size();
+    }
+  }
+  p.n_fold = (int64_t)fold_dst.size();
+  p.n_rem = (int64_t)rem_col.size();
   std::vector<int64_t> bb_rowptr(s->bb_rowptr, s->bb_rowptr + p.n_bnodes + 1);
   std::vector<int32_t> bb_col(s->bb_col, s->bb_col + p.nnzb);
   std::vector<int32_t> inv_n(p.ni.begin(), p.ni.end());
@@ -558,8 +613,14 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
     gv_aib[e] = GemvDesc{p.off_ib[e], ni, nc, (int32_t)p.off_c[e], (int32_t)p.off_i[e]};
     gv_s[e] = GemvDesc{p.off_cc[e], nc, nc, (int32_t)p.off_c[e], (int32_t)p.off_c[e]};
   }
-  std::vector<int32_t> tiles_x = xcd_tile_list(gx, gemm_tile_m(), gemm_tile_n());
-  std::vector<int32_t> tiles_s = xcd_tile_list(gs, gemm_tile_m(), gemm_tile_n());
+  // X_e is n_i x n_c (n_i = 5 (N-1)^3 is a multiple of 64 only for some N): 64-row tiles;
+  // the element Schur blocks are n_c x n_c: 128 x 128 tiles
+  p.gemm_cfg_x = kGemm64x128;
+  p.gemm_cfg_s = kGemm64x64;
+  p.gx_host = gx;
+  p.gs_host = gs;
+  std::vector<int32_t> tiles_x = xcd_tile_list(gx, p.gemm_cfg_x);
+  std::vector<int32_t> tiles_s = xcd_tile_list(gs, p.gemm_cfg_s);
   p.n_tiles_x = (int32_t)(tiles_x.size() / 3);
   p.n_tiles_s = (int32_t)(tiles_s.size() / 3);
   std::vector<RowTile> rt_inv = row_tiles(gv_inv), rt_abi = row_tiles(gv_abi),
@@ -580,6 +641,13 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   chk(upload(p, &p.d_slot_nc, slot_nc));
   chk(upload(p, &p.d_slot_pos, slot_pos));
   chk(upload(p, &p.d_bb_rowptr, bb_rowptr));
+  chk(upload(p, &p.d_fold_dst, fold_dst));
+  chk(upload(p, &p.d_fold_nc, fold_nc));
+  chk(upload(p, &p.d_fold_src, fold_src));
+  chk(upload(p, &p.d_rem_rowptr, rem_rowptr));
+  chk(upload(p, &p.d_rem_col, rem_col));
+  chk(upload(p, &p.d_rem_src, rem_src));
+  chk(dalloc(p, &p.pc_blk, (size_t)p.n_bnodes * 25));
   chk(upload(p, &p.d_bb_col, bb_col));
   chk(upload(p, &p.d_inv_n, inv_n));
   chk(upload(p, &p.d_inv_off, inv_off));
@@ -662,19 +730,22 @@ scdg_status scdg_factor(scdg_plan *pl, scdg_precision prec) {
   }
   if (prec != SCDG_FP64 && prec != SCDG_FP32) return SCDG_ERR_ARG;
   p.prec = prec;
+  if (!gj_supported(p.max_ni, fp32(p))) {
+    p.last_error = "interior block too large for the batched inverse";
+    return SCDG_ERR_UNSUPPORTED;
+  }
   const size_t need = esize(p) * (size_t)p.off_ii[p.n_elem];
   if (need > p.cap_ainv) {
     dfree(p.ainv);
+    dfree(p.ainv_work);
+    p.cap_ainv = 0;
     ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.ainv), need));
+    ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.ainv_work), need));
     p.cap_ainv = need;
   }
-  if (fp32(p))
-    HIP_TRY(launch_cast_f64_to_f32(p.aii, static_cast<float *>(p.ainv), p.off_ii[p.n_elem], p.stream));
-  else
-    HIP_TRY(launch_copy_f64(p.aii, static_cast<double *>(p.ainv), p.off_ii[p.n_elem], p.stream));
   {
     PhaseTimer tm(p, SCDG_PHASE_INVERSE);
-    HIP_TRY(launch_gj_inverse(p, p.ainv, fp32(p)));
+    HIP_TRY(launch_gj_inverse(p, p.ainv_work, p.ainv, fp32(p)));
   }
   p.state = 2;
   p.dense_factored = false;
@@ -739,17 +810,16 @@ scdg_status scdg_condense(scdg_plan *pl) {
   }
   {
     PhaseTimer tm(p, SCDG_PHASE_GEMM_X);
-    HIP_TRY(launch_gemm_batched(p.d_gx, p.d_tiles_x, p.n_tiles_x, p.ainv, aib, p.xmat, 1.0, 0.0,
-                                fp32(p), p.stream));
+    HIP_TRY(launch_gemm_batched(p.gemm_cfg_x, p.d_gx, p.d_tiles_x, p.n_tiles_x, p.ainv, aib, p.xmat,
+                                1.0, 0.0, fp32(p), p.stream));
   }
   {
     PhaseTimer tm(p, SCDG_PHASE_GEMM_S);
-    HIP_TRY(launch_gemm_batched(p.d_gs, p.d_tiles_s, p.n_tiles_s, abi, p.xmat, p.sloc, 1.0, 0.0,
-                                fp32(p), p.stream));
+    HIP_TRY(launch_gemm_batched(p.gemm_cfg_s, p.d_gs, p.d_tiles_s, p.n_tiles_s, abi, p.xmat, p.sloc,
+                                -1.0, 0.0, fp32(p), p.stream));
   }
-  HIP_TRY(launch_diag_schur(p, p.sloc, fp32(p), p.diag_s));
-  // keep 1 / diag(S) for the point-Jacobi preconditioner
-  HIP_TRY(launch_reciprocal(p.diag_s, p.n1, p.stream));
+  HIP_TRY(launch_fold_add(p, p.sloc, fp32(p)));
+  HIP_TRY(launch_precond_setup(p, p.sloc, fp32(p)));
   p.state = 3;
   p.dense_factored = false;
   ST_TRY(sync(p));
@@ -904,6 +974,115 @@ scdg_status scdg_phase_times(scdg_plan *pl, double *ms, int32_t *count, int32_t 
     p.ev_pool.push_back(u.second);
   }
   p.ev_used.clear();
+  return SCDG_OK;
+}
+
+namespace {
+
+scdg_status set_tiles(Plan &p, bool for_s, int cfg) {
+  std::vector<int32_t> tiles = xcd_tile_list(for_s ? p.gs_host : p.gx_host, cfg);
+  if (for_s) {
+    ST_TRY(upload(p, &p.d_tiles_s, tiles));
+    p.n_tiles_s = (int32_t)(tiles.size() / 3);
+    p.gemm_cfg_s = cfg;
+  } else {
+    ST_TRY(upload(p, &p.d_tiles_x, tiles));
+    p.n_tiles_x = (int32_t)(tiles.size() / 3);
+    p.gemm_cfg_x = cfg;
+  }
+  return SCDG_OK;
+}
+
+}  // namespace
+
+scdg_status scdg_set_gemm_config(scdg_plan *pl, int32_t cfg_x, int32_t cfg_s) {
+  if (!pl || cfg_x < 0 || cfg_x >= kGemmConfigs || cfg_s < 0 || cfg_s >= kGemmConfigs)
+    return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  ST_TRY(set_tiles(p, false, cfg_x));
+  ST_TRY(set_tiles(p, true, cfg_s));
+  if (p.state >= 3) p.state = 2;   // the Schur blocks must be recomputed
+  return SCDG_OK;
+}
+
+scdg_status scdg_get_gemm_config(const scdg_plan *pl, int32_t *cfg_x, int32_t *cfg_s) {
+  if (!pl) return SCDG_ERR_ARG;
+  if (cfg_x) *cfg_x = pl->p.gemm_cfg_x;
+  if (cfg_s) *cfg_s = pl->p.gemm_cfg_s;
+  return SCDG_OK;
+}
+
+scdg_status scdg_autotune(scdg_plan *pl, double *ms_x, double *ms_s, int32_t n) {
+  if (!pl) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 2) {
+    p.last_error = "scdg_autotune needs scdg_factor first";
+    return SCDG_ERR_STATE;
+  }
+  const int E = p.n_elem;
+  const size_t nx = esize(p) * (size_t)p.off_ib[E], ns = esize(p) * (size_t)p.off_cc[E];
+  if (nx > p.cap_x) {
+    dfree(p.xmat);
+    ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.xmat), nx));
+    p.cap_x = nx;
+  }
+  if (ns > p.cap_s) {
+    dfree(p.sloc);
+    ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.sloc), ns));
+    p.cap_s = ns;
+  }
+  const void *aib = p.aib, *abi = p.abi;
+  if (fp32(p)) {
+    if (!p.aib_lo) ST_TRY(dalloc(p, reinterpret_cast<float **>(&p.aib_lo), (size_t)p.off_ib[E]));
+    if (!p.abi_lo) ST_TRY(dalloc(p, reinterpret_cast<float **>(&p.abi_lo), (size_t)p.off_ib[E]));
+    HIP_TRY(launch_cast_f64_to_f32(p.aib, static_cast<float *>(p.aib_lo), p.off_ib[E], p.stream));
+    HIP_TRY(launch_cast_f64_to_f32(p.abi, static_cast<float *>(p.abi_lo), p.off_ib[E], p.stream));
+    aib = p.aib_lo;
+    abi = p.abi_lo;
+  }
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  int best[2] = {p.gemm_cfg_x, p.gemm_cfg_s};
+  for (int which = 0; which < 2; ++which) {
+    double best_ms = 1e30;
+    for (int cfg = 0; cfg < kGemmConfigs; ++cfg) {
+      int bm, bn;
+      gemm_tile_shape(cfg, &bm, &bn);
+      const int rows = which == 0 ? p.max_ni : p.max_nc;
+      double ms = -1.0;
+      if (bm <= 2 * rows) {   // skip tiles far taller than the problem
+        ST_TRY(set_tiles(p, which == 1, cfg));
+        float t = 0.f, tmin = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          HIP_TRY(hipEventRecord(t0, p.stream));
+          if (which == 0)
+            HIP_TRY(launch_gemm_batched(cfg, p.d_gx, p.d_tiles_x, p.n_tiles_x, p.ainv, aib, p.xmat,
+                                        1.0, 0.0, fp32(p), p.stream));
+          else
+            HIP_TRY(launch_gemm_batched(cfg, p.d_gs, p.d_tiles_s, p.n_tiles_s, abi, p.xmat, p.sloc,
+                                        -1.0, 0.0, fp32(p), p.stream));
+          HIP_TRY(hipEventRecord(t1, p.stream));
+          HIP_TRY(hipEventSynchronize(t1));
+          HIP_TRY(hipEventElapsedTime(&t, t0, t1));
+          if (rep > 0) tmin = std::min(tmin, t);
+        }
+        ms = tmin;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best[which] = cfg;
+        }
+      }
+      double *dst = which == 0 ? ms_x : ms_s;
+      if (dst && cfg < n) dst[cfg] = ms;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  ST_TRY(set_tiles(p, false, best[0]));
+  ST_TRY(set_tiles(p, true, best[1]));
+  p.state = 2;   // the tuning runs overwrote X and the Schur blocks
   return SCDG_OK;
 }
 

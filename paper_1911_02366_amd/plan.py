@@ -163,6 +163,26 @@ class Plan:
         self._check(self.lib.scdg_phase_times(self.handle, ms, cnt, n), "scdg_phase_times")
         return {name: {"ms": ms[i], "count": cnt[i]} for i, name in enumerate(L.PHASES)}
 
+    def autotune(self) -> dict:
+        """Time every GEMM tile configuration on this plan's problems; keep the fastest."""
+        n = len(L.GEMM_CONFIGS)
+        mx, ms = (C.c_double * n)(), (C.c_double * n)()
+        self._check(self.lib.scdg_autotune(self.handle, mx, ms, n), "scdg_autotune")
+        cx, cs = self.gemm_config()
+        return {"x": L.GEMM_CONFIGS[cx], "s": L.GEMM_CONFIGS[cs],
+                "ms_x": dict(zip(L.GEMM_CONFIGS, list(mx))), "ms_s": dict(zip(L.GEMM_CONFIGS, list(ms)))}
+
+    def gemm_config(self):
+        cx, cs = C.c_int32(), C.c_int32()
+        self._check(self.lib.scdg_get_gemm_config(self.handle, C.byref(cx), C.byref(cs)),
+                    "scdg_get_gemm_config")
+        return cx.value, cs.value
+
+    def set_gemm_config(self, cfg_x, cfg_s):
+        conv = lambda c: L.GEMM_CONFIGS.index(c) if isinstance(c, str) else int(c)
+        self._check(self.lib.scdg_set_gemm_config(self.handle, conv(cfg_x), conv(cfg_s)),
+                    "scdg_set_gemm_config")
+
     def export(self, what: str, count: int, dtype=torch.float64, device="cuda"):
         code = {"aii_inv": L.EXPORT_AII_INV, "schur": L.EXPORT_SCHUR, "x": L.EXPORT_X}[what]
         out = torch.empty(count, dtype=dtype, device=device)

@@ -40,3 +40,46 @@ def make_plan(case, dev, precision="fp64"):
 
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def fold_matrices(case, elems=None):
+    """F_e: the A_bb blocks the library folds into element e's stored Schur block.
+
+    Rule (documented in the C header): block (g, h) goes to the element that owns
+    boundary node g when both g and h are in its coupling set, else to the
+    lowest-numbered element whose coupling set holds both; otherwise it stays in
+    the remainder.  Returns {e: F_e} for the requested elements (default all)."""
+    n_e = case.n_elem
+    nb = case.n_bnodes // n_e
+    elems = range(n_e) if elems is None else elems
+    c_sets = lambda e: case.c_node[case.c_ptr[e]:case.c_ptr[e + 1]]
+    pos_cache = {}
+
+    def pos(e):
+        if e not in pos_cache:
+            pos_cache[e] = {int(g): i for i, g in enumerate(c_sets(e))}
+        return pos_cache[e]
+
+    holders = {}
+    for e in range(n_e):
+        for g in c_sets(e):
+            holders.setdefault(int(g), []).append(e)
+    vals = to_np(case.bb_val)
+    out = {}
+    for e in elems:
+        f = np.zeros((case.n_c, case.n_c))
+        pe = pos(e)
+        for g in c_sets(e):
+            g = int(g)
+            owner = g // nb
+            cands = sorted(holders[g], key=lambda x: (x != owner, x))
+            for t in range(case.bb_rowptr[g], case.bb_rowptr[g + 1]):
+                h = int(case.bb_col[t])
+                if h not in pe:
+                    continue
+                chosen = next(x for x in cands if h in pos(x))
+                if chosen == e:
+                    pg, ph = pe[g], pe[h]
+                    f[5 * pg:5 * pg + 5, 5 * ph:5 * ph + 5] += vals[t]
+        out[e] = f
+    return out

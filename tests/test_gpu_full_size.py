@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_common import DEV, make_plan, rel, to_np
+from gpu_common import DEV, fold_matrices, make_plan, rel, to_np
 from workload.cases import named_case
 
 pytestmark = pytest.mark.gpu
@@ -31,14 +31,17 @@ def test_full_size_fp64(big):
     plan = make_plan(case, dev)
     inv = plan.export("aii_inv", case.n_elem * case.n_i ** 2).view(case.n_elem, case.n_i, case.n_i)
     s = plan.export("schur", case.n_elem * case.n_c ** 2).view(case.n_elem, case.n_c, case.n_c)
+    fold = fold_matrices(case, _sample_elements(case))
     for e in _sample_elements(case):
         aii, aib, abi = to_np(case.aii[e]), to_np(case.aib[e]), to_np(case.abi[e])
         assert rel(to_np(inv[e]), oracle.element_inverse(aii)) <= 1e-11
-        assert rel(to_np(s[e]), oracle.element_schur(aii, aib, abi)) <= 1e-11
+        ref = oracle.element_schur(aii, aib, abi)
+        assert rel(fold[e] - to_np(s[e]), ref) <= 1e-11
     del inv, s
-    dq, info = plan.solve(dev["b"], solver="gmres", tol=1e-10, ir_tol=1e-8)
-    print(info, flush=True)
-    assert info["rel_res_full"] <= 1e-8
+    for precond in (1, 2):
+        dq, info = plan.solve(dev["b"], solver="gmres", precond=precond, tol=1e-10, ir_tol=1e-8)
+        print(precond, info, flush=True)
+        assert info["rel_res_full"] <= 1e-8
     dq_np, b_np = to_np(dq), to_np(dev["b"])
     bnorm = np.linalg.norm(b_np)
     for e in _sample_elements(case):

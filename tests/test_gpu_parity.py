@@ -10,7 +10,8 @@ import pytest
 import torch
 
 import oracle
-from gpu_common import DEV, device_case, make_plan, oracle_arrays, oracle_matrix, rel, to_np
+from gpu_common import (DEV, device_case, fold_matrices, make_plan, oracle_arrays, oracle_matrix,
+                        rel, to_np)
 from workload.cases import build_case, named_case
 
 pytestmark = pytest.mark.gpu
@@ -44,11 +45,13 @@ def test_inverse_parity(setup):
 
 
 def test_schur_block_parity(setup):
+    # stored element block T_e = F_e - A_bi(e) A_ii(e)^-1 A_ib(e), F_e the folded A_bb blocks
     name, case, d, dev, plan = setup
     s = to_np(plan.export("schur", case.n_elem * case.n_c ** 2)).reshape(case.n_elem, case.n_c, case.n_c)
+    fold = fold_matrices(case)
     for e in range(case.n_elem):
         ref = oracle.element_schur(d["aii"][e], d["aib"][e], d["abi"][e])
-        assert rel(s[e], ref) <= 1e-11, (name, e)
+        assert rel(fold[e] - s[e], ref) <= 1e-11, (name, e)
 
 
 def test_condensed_rhs_parity(setup):
@@ -86,11 +89,11 @@ def test_residual_parity(setup):
     assert abs(relv - np.linalg.norm(ref) / np.linalg.norm(d["b"])) <= 1e-12 * relv
 
 
-@pytest.mark.parametrize("solver", ["dense", "gmres"])
-def test_full_solve_parity(setup, solver):
+@pytest.mark.parametrize("solver,precond", [("dense", 1), ("gmres", 1), ("gmres", 2), ("gmres", 0)])
+def test_full_solve_parity(setup, solver, precond):
     name, case, d, dev, plan = setup
     ref = oracle.solve_sparse(oracle_matrix(d), d["b"])
-    dq, info = plan.solve(dev["b"], solver=solver, tol=1e-13, ir_tol=1e-12)
+    dq, info = plan.solve(dev["b"], solver=solver, precond=precond, tol=1e-13, ir_tol=1e-12)
     assert rel(to_np(dq), ref) <= 1e-10, info
     assert info["rel_res_full"] <= 1e-12
     # discrete conservation of the increment: sum_j J_j w_j dQ_{j,v} = 0
@@ -106,3 +109,27 @@ def test_condensed_pipeline_by_stages(setup):
     ref = oracle.condensed_solve_dense(d["order"], d["c_ptr"], d["c_node"], d["bb_rowptr"], d["bb_col"],
                                        d["bb_val"], d["aii"], d["aib"], d["abi"], d["b"])
     assert rel(to_np(dq), ref) <= 1e-10, info
+
+
+@pytest.mark.parametrize("cfg", list(range(7)))
+def test_every_gemm_tile_config(setup, cfg):
+    name, case, d, dev, plan = setup
+    plan.set_gemm_config(cfg, cfg)
+    plan.condense()
+    x = to_np(plan.export("x", case.n_elem * case.n_i * case.n_c)).reshape(case.n_elem, case.n_i, case.n_c)
+    s = to_np(plan.export("schur", case.n_elem * case.n_c ** 2)).reshape(case.n_elem, case.n_c, case.n_c)
+    fold = fold_matrices(case, [0, case.n_elem - 1])
+    for e in (0, case.n_elem - 1):
+        assert rel(x[e], np.linalg.solve(d["aii"][e], d["aib"][e])) <= 1e-11, (name, cfg, e)
+        ref = oracle.element_schur(d["aii"][e], d["aib"][e], d["abi"][e])
+        assert rel(fold[e] - s[e], ref) <= 1e-11, (name, cfg, e)
+
+
+def test_autotune_keeps_results(setup):
+    name, case, d, dev, plan = setup
+    tuned = plan.autotune()
+    assert tuned["x"] in tuned["ms_x"] and tuned["ms_s"][tuned["s"]] > 0
+    plan.condense()
+    ref = oracle.solve_sparse(oracle_matrix(d), d["b"])
+    dq, info = plan.solve(dev["b"], solver="gmres", tol=1e-13, ir_tol=1e-12)
+    assert rel(to_np(dq), ref) <= 1e-10
