@@ -28,8 +28,11 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
 
 
-def algorithmic_work(case, plan_prec: str) -> dict:
-    """Algorithmic flops / bytes per launch of each kernel (unpadded element blocks)."""
+def algorithmic_work(case, plan_prec: str, n_rem: int) -> dict:
+    """Algorithmic flops / bytes per launch of each kernel (unpadded element blocks).
+
+    The condensed product S x streams the element blocks T_e once, the A_bb
+    remainder blocks (values + column index) once, and reads x / writes y."""
     e, ni, nc = case.n_elem, case.n_i, case.n_c
     esz = 8 if plan_prec == "fp64" else 4
     nnzb = int(case.bb_rowptr[-1])
@@ -39,8 +42,8 @@ def algorithmic_work(case, plan_prec: str) -> dict:
         "inverse": {"flops": e * 2 * ni ** 3, "bytes": e * ni * ni * esz * 2},
         "gemm_x": {"flops": e * 2 * ni * ni * nc, "bytes": e * (ni * ni + 2 * ni * nc) * esz},
         "gemm_s": {"flops": e * 2 * nc * nc * ni, "bytes": e * (2 * ni * nc + nc * nc) * esz},
-        "schur_apply": {"flops": e * 2 * nc * nc + nnzb * 50,
-                        "bytes": e * nc * nc * esz + bb_bytes + 2 * n1 * 8},
+        "schur_apply": {"flops": e * 2 * nc * nc + n_rem * 50,
+                        "bytes": e * nc * nc * esz + n_rem * (25 * 8 + 4) + 2 * n1 * 8},
         "rhs": {"flops": e * (2 * ni * ni + 2 * nc * ni),
                 "bytes": e * (ni * ni + nc * ni) * esz + (ndof + n1) * 8},
         "backsolve": {"flops": e * (2 * ni * ni + 2 * ni * nc),
@@ -112,6 +115,8 @@ def main() -> int:
                     help="GMRES right preconditioner: 0 none, 1 point Jacobi, 2 5x5 node-block Jacobi")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 2 GiB FP64 buffer three times (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -123,6 +128,17 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.calibrate_copy:
+        n = (2 << 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 3}))
+        return 0
+
     from paper_1911_02366_amd import Plan
     from workload.cases import WORKLOADS, named_case
 
@@ -161,10 +177,18 @@ def main() -> int:
 
     ms_per_step = (t1 - t0) / args.steps * 1e3
     value = case.n_dof / (ms_per_step / 1e3)
-    work = algorithmic_work(case, args.precision)
+    work = algorithmic_work(case, args.precision, plan.n_remainder)
     kernels = {k: v for k, v in phases.items() if k in work}
     dominant = max(kernels, key=lambda k: kernels[k]["ms"])
     entries = {k: roofline_entry(k, work[k], kernels[k], args.precision) for k in kernels}
+    from paper_1911_02366_amd.profiling import load_traffic
+    csrc = os.path.join(ROOT, "paper_1911_02366_amd", "csrc")
+    for k, srcs in (("schur_apply", ["k_vec.hip"]), ("gemm_s", ["k_gemm.hip"]), ("gemm_x", ["k_gemm.hip"]),
+                    ("inverse", ["k_inverse.hip"])):
+        rec = load_traffic(os.path.join(ROOT, "profiles", f"traffic_{k}_{args.workload}_{args.precision}.json"),
+                           [os.path.join(csrc, f) for f in srcs])
+        if entries.get(k) is not None and rec is not None:
+            entries[k]["traffic"] = rec["traffic_bytes_per_launch"]
     worst = max(i["rel_res_full"] for i in infos)
     cfg = WORKLOADS[args.workload]
     out = {
@@ -194,6 +218,7 @@ def main() -> int:
                        "autotune_ms_s": {k: round(v, 3) for k, v in tuning["ms_s"].items()},
                        "autotune_ms_x": {k: round(v, 3) for k, v in tuning["ms_x"].items()}},
         "gmres_iters_per_step": sum(i["iters"] for i in infos) / len(infos),
+        "a_bb_blocks": {"folded": plan.n_folded, "remainder": plan.n_remainder},
         "ir_sweeps_per_step": sum(i["ir_sweeps"] for i in infos) / len(infos),
     }
     if worst > 1e-8:

@@ -117,6 +117,10 @@ scdg_status scdg_set_stream(scdg_plan *p, void *hip_stream);
 scdg_status scdg_plan_sizes(const scdg_plan *p, int64_t *n_dof, int64_t *n1, int64_t *n2,
                             int64_t *n_bnodes);
 
+/* Number of A_bb node blocks folded into element Schur blocks and left in the
+ * BSR remainder (see scdg_condense). */
+scdg_status scdg_plan_fold_counts(const scdg_plan *p, int64_t *n_folded, int64_t *n_remainder);
+
 /* Register the Jacobian blocks (device pointers, borrowed, FP64). */
 scdg_status scdg_assemble(scdg_plan *p, const double *aii, const double *aib,
                           const double *abi, const double *bb_val);

@@ -25,7 +25,7 @@ EXPORTED = [
     "scdg_solve_condensed", "scdg_backsolve", "scdg_solve", "scdg_residual",
     "scdg_schur_apply", "scdg_export", "scdg_status_string", "scdg_last_error",
     "scdg_enable_timing", "scdg_phase_times", "scdg_autotune", "scdg_set_gemm_config",
-    "scdg_get_gemm_config",
+    "scdg_get_gemm_config", "scdg_plan_fold_counts",
 ]
 GEMM_CONFIGS = ["64x64", "64x128", "128x128", "128x128w8", "128x64", "240x80", "80x80"]
 PHASES = ["inverse", "gemm_x", "gemm_s", "rhs", "schur_apply", "condensed_solve", "backsolve",
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_autotune": (i32, [vp, C.POINTER(d), C.POINTER(d), i32]),
         "scdg_set_gemm_config": (i32, [vp, i32, i32]),
         "scdg_get_gemm_config": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+        "scdg_plan_fold_counts": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

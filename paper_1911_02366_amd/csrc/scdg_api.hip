@@ -708,6 +708,13 @@ scdg_status scdg_plan_sizes(const scdg_plan *pl, int64_t *n_dof, int64_t *n1, in
   return SCDG_OK;
 }
 
+scdg_status scdg_plan_fold_counts(const scdg_plan *pl, int64_t *n_folded, int64_t *n_remainder) {
+  if (!pl) return SCDG_ERR_ARG;
+  if (n_folded) *n_folded = pl->p.n_fold;
+  if (n_remainder) *n_remainder = pl->p.n_rem;
+  return SCDG_OK;
+}
+
 scdg_status scdg_assemble(scdg_plan *pl, const double *aii, const double *aib, const double *abi,
                           const double *bb_val) {
   if (!pl || !aii || !aib || !abi || (pl->p.nnzb > 0 && !bb_val)) return SCDG_ERR_ARG;

@@ -56,6 +56,9 @@ class Plan:
         n_dof, n1, n2, nb = (C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64())
         self.lib.scdg_plan_sizes(handle, C.byref(n_dof), C.byref(n1), C.byref(n2), C.byref(nb))
         self.n_dof, self.n1, self.n2, self.n_bnodes = n_dof.value, n1.value, n2.value, nb.value
+        nf, nr = C.c_int64(), C.c_int64()
+        self.lib.scdg_plan_fold_counts(handle, C.byref(nf), C.byref(nr))
+        self.n_folded, self.n_remainder = nf.value, nr.value
 
     @classmethod
     def from_structure(cls, st: dict, stream=None) -> "Plan":
