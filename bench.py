@@ -115,6 +115,11 @@ def main() -> int:
                     help="GMRES right preconditioner: 0 none, 1 point Jacobi, 2 5x5 node-block Jacobi")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-inner-tol", type=float, default=1e-4,
+                    help="GMRES tolerance inside each refinement sweep of the FP32 variant")
+    ap.add_argument("--fp32-sweep", type=float, nargs="*", default=[],
+                    help="extra inner tolerances to time for the FP32 variant")
+    ap.add_argument("--no-fp32-variant", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 2 GiB FP64 buffer three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -149,33 +154,49 @@ def main() -> int:
     plan = Plan.from_structure(case.structure())
     plan.assemble(case.aii, case.aib, case.abi, case.bb_val)
     dq = torch.empty(case.n_dof, dtype=torch.float64, device=dev)
-    opts = dict(solver="gmres", restart=30, tol=args.tol if args.precision == "fp64" else 1e-6,
-                ir_tol=1e-8, ir_max=10, precond=args.precond)
 
-    def step():
-        plan.factor(args.precision)
-        plan.condense()
-        _, info = plan.solve(b, dq, **opts)
-        return info
+    def measure(precision, tol, steps, warmup):
+        opts = dict(solver="gmres", restart=30, tol=tol, ir_tol=1e-8, ir_max=10, precond=args.precond)
 
-    plan.factor(args.precision)
-    tuning = plan.autotune()
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    plan.enable_timing(True)
-    plan.phase_times()
-    infos = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        infos.append(step())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    phases = plan.phase_times()
-    plan.enable_timing(False)
+        def step():
+            plan.factor(precision)
+            plan.condense()
+            _, info = plan.solve(b, dq, **opts)
+            return info
 
-    ms_per_step = (t1 - t0) / args.steps * 1e3
+        plan.factor(precision)
+        tuning = plan.autotune()
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        plan.enable_timing(True)
+        plan.phase_times()
+        infos = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            infos.append(step())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        phases = plan.phase_times()
+        plan.enable_timing(False)
+        return (t1 - t0) / steps * 1e3, infos, phases, tuning, opts
+
+    fp32_tol = args.fp32_inner_tol
+    ms_per_step, infos, phases, tuning, opts = measure(
+        args.precision, args.tol if args.precision == "fp64" else fp32_tol, args.steps, args.warmup)
+    variants = {}
+    if args.precision == "fp64" and not args.no_fp32_variant:
+        for tol in sorted(set([fp32_tol] + args.fp32_sweep)):
+            ms32, inf32, ph32, tun32, _ = measure("fp32", tol, args.steps, args.warmup)
+            variants[f"fp32_ir_inner_tol_{tol:g}"] = {
+                "ms_per_step": round(ms32, 3), "value_dof_s": round(case.n_dof / (ms32 / 1e3), 1),
+                "speedup_vs_fp64": round(ms_per_step / ms32, 3),
+                "rel_res_full_max": max(i["rel_res_full"] for i in inf32),
+                "gmres_iters_per_step": sum(i["iters"] for i in inf32) / len(inf32),
+                "ir_sweeps_per_step": sum(i["ir_sweeps"] for i in inf32) / len(inf32),
+                "phase_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in ph32.items()},
+                "gemm_tiles": {"x": tun32["x"], "s": tun32["s"]}}
     value = case.n_dof / (ms_per_step / 1e3)
     work = algorithmic_work(case, args.precision, plan.n_remainder)
     kernels = {k: v for k, v in phases.items() if k in work}
@@ -214,6 +235,7 @@ def main() -> int:
         "roofline_all": entries,
         "phase_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in phases.items()},
         "rel_res_full_max": worst,
+        "variants": variants,
         "gemm_tiles": {"x": tuning["x"], "s": tuning["s"],
                        "autotune_ms_s": {k: round(v, 3) for k, v in tuning["ms_s"].items()},
                        "autotune_ms_x": {k: round(v, 3) for k, v in tuning["ms_x"].items()}},
