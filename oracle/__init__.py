@@ -11,7 +11,10 @@ What it computes (each function cites the passage it follows):
     and the uncondensed solution of A dQ = B (eq. NewtonLinSys1) by LAPACK
     dense LU or SuperLU;
   * the Schur-complement quantities of eq. SC_step1 / SC_step2 written out as
-    their definitions, per element, with numpy.
+    their definitions, per element, with numpy;
+  * (module `oracle.dgsem`) the nonlinear residual R(Q) = M (Q - Q_s)/dt + H(Q)
+    of the backward-Euler GL-DGSEM step, with H from the weak form of
+    eq. DGSEMsystem evaluated as Gauss-Lobatto quadrature sums.
 """
 from .linalg import (  # noqa: F401
     NodeSets, node_sets, dof_maps, assemble_global, solve_dense, solve_sparse,
