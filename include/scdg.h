@@ -208,6 +208,51 @@ scdg_status scdg_autotune(scdg_plan *p, double *ms_x, double *ms_s, int32_t n);
 scdg_status scdg_set_gemm_config(scdg_plan *p, int32_t cfg_x, int32_t cfg_s);
 scdg_status scdg_get_gemm_config(const scdg_plan *p, int32_t *cfg_x, int32_t *cfg_s);
 
+/* ------------------------------------------------------------------------
+ * Nonlinear residual of the implicit step (paper, eq. ImplicitDisc with
+ * backward Euler, and eq. DiscretNS):
+ *
+ *     R(Q) = M (Q - Q_s) / dt + H(Q),
+ *
+ * H the GL-DGSEM operator of eq. DGSEMsystem for the compressible
+ * Navier-Stokes equations (Appendix B fluxes, local Lax-Friedrichs advective
+ * flux, Bassi-Rebay 1 viscous flux and lifted gradient), M the diagonal mass
+ * matrix J w_i w_j w_k, on a periodic Cartesian mesh of K^3 cubes of side
+ * length / K with uniform order N.  B = -R(Q~) is the right-hand side of the
+ * Newton system that scdg_solve solves (eq. NewtonLinSys1).
+ *
+ * Nondimensional state: p = (gamma - 1)(rho E - rho |v|^2 / 2), T = gamma
+ * Ma^2 p / rho, Sutherland viscosity mu(T) = (1 + S) T^{3/2} / (T + S),
+ * heat flux (mu gamma / Pr) grad e, Stokes stress with bulk term -2/3 mu div v,
+ * viscous fluxes scaled by 1/Re.
+ *
+ * Vectors are device arrays of doubles in the natural DOF order of this
+ * header: element e = ex + K ey + K^2 ez, node n = i + P j + P^2 k, DOF
+ * 5 (e P^3 + n) + v.  The object owns its gradient workspace (15 doubles per
+ * node); it is not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct scdg_dg scdg_dg;
+typedef struct {
+  int32_t k_elem;           /* elements per direction K >= 2 */
+  int32_t order;            /* N, 2 <= N <= 7 */
+  double length;            /* side of the periodic box (> 0) */
+  double mach, reynolds;    /* reference Mach and Reynolds numbers (> 0) */
+  double gamma, prandtl;    /* <= 0 selects 1.4 / 0.72 */
+  double sutherland_ratio;  /* T_suth / T_ref; <= 0 selects 110.4 / 288.15 */
+} scdg_dg_params;
+/* Create on the current device; HIP stream may be NULL (default stream).
+ * SCDG_ERR_ARG for out-of-range parameters, SCDG_ERR_NOMEM on allocation. */
+scdg_status scdg_dg_create(scdg_dg **out, const scdg_dg_params *prm, void *hip_stream);
+scdg_status scdg_dg_destroy(scdg_dg *dg);
+/* r = M (q - q_s) * inv_dt + H(q); q_s == NULL gives r = H(q).  q, q_s and r
+ * hold 5 K^3 (N+1)^3 doubles; r must not alias q or q_s.  Asynchronous on the
+ * object's stream. */
+scdg_status scdg_dg_residual(scdg_dg *dg, const double *q, const double *q_s, double inv_dt,
+                             double *r);
+/* Copy the lifted gradient of the last scdg_dg_residual call into g (device,
+ * 15 doubles per node: g[(e P^3 + n) 15 + 5 d + v] = d q_v / d x_d). */
+scdg_status scdg_dg_gradient(scdg_dg *dg, double *g);
+
 const char *scdg_status_string(scdg_status s);
 /* Last error text of a plan (or of plan creation when p is NULL). */
 scdg_status scdg_last_error(const scdg_plan *p, char *buf, size_t n);

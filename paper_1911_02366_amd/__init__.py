@@ -6,5 +6,6 @@ library; `Plan(...)` does, and raises ImportError when it has not been built.
 """
 from ._lib import EXPORTED, LIB_PATH, ScdgError, load  # noqa: F401
 from .plan import Plan  # noqa: F401
+from .dg import DgResidual  # noqa: F401
 
-__all__ = ["Plan", "ScdgError", "load", "LIB_PATH", "EXPORTED"]
+__all__ = ["Plan", "DgResidual", "ScdgError", "load", "LIB_PATH", "EXPORTED"]

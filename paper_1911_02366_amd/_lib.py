@@ -26,6 +26,7 @@ EXPORTED = [
     "scdg_schur_apply", "scdg_export", "scdg_status_string", "scdg_last_error",
     "scdg_enable_timing", "scdg_phase_times", "scdg_autotune", "scdg_set_gemm_config",
     "scdg_get_gemm_config", "scdg_plan_fold_counts",
+    "scdg_dg_create", "scdg_dg_destroy", "scdg_dg_residual", "scdg_dg_gradient",
 ]
 GEMM_CONFIGS = ["64x64", "64x128", "128x128", "128x128w8", "128x64", "240x80", "80x80"]
 PHASES = ["inverse", "gemm_x", "gemm_s", "rhs", "schur_apply", "condensed_solve", "backsolve",
@@ -35,6 +36,12 @@ PHASES = ["inverse", "gemm_x", "gemm_s", "rhs", "schur_apply", "condensed_solve"
 class Structure(C.Structure):
     _fields_ = [("n_elem", C.c_int32), ("order", C.c_void_p), ("c_ptr", C.c_void_p),
                 ("c_node", C.c_void_p), ("bb_rowptr", C.c_void_p), ("bb_col", C.c_void_p)]
+
+
+class DgParams(C.Structure):
+    _fields_ = [("k_elem", C.c_int32), ("order", C.c_int32), ("length", C.c_double),
+                ("mach", C.c_double), ("reynolds", C.c_double), ("gamma", C.c_double),
+                ("prandtl", C.c_double), ("sutherland_ratio", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -93,6 +100,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_set_gemm_config": (i32, [vp, i32, i32]),
         "scdg_get_gemm_config": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
         "scdg_plan_fold_counts": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
+        "scdg_dg_create": (i32, [C.POINTER(vp), C.POINTER(DgParams), vp]),
+        "scdg_dg_destroy": (i32, [vp]),
+        "scdg_dg_residual": (i32, [vp, vp, vp, d, vp]),
+        "scdg_dg_gradient": (i32, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

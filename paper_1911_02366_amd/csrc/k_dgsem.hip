@@ -1,0 +1,365 @@
+// Nonlinear residual of the backward-Euler GL-DGSEM step on the device:
+//     R(Q) = M (Q - Q_s) / dt + H(Q)
+// for the compressible Navier-Stokes equations on a periodic Cartesian hex
+// mesh (paper, eq. ImplicitDisc; H from eq. DGSEMsystem: weak form on
+// Gauss-Lobatto nodes, local Lax-Friedrichs advective flux, Bassi-Rebay 1
+// viscous flux with the lifted gradient of eq. DGSEMsystem:2).
+//
+// Two launches, one workgroup per element, one thread per node:
+//   1. lifted gradient g_d (strong form):
+//        g_d = s [ sum_a D[l][a] q_a + (1/w_N) [l = N] (q^+_R - q_N)/2 - (1/w_0) [l = 0] (q^-_L - q_0)/2 ]
+//   2. residual: fluxes F_d = f^a_d(q) - f^nu_d(q, g) staged in LDS, then
+//        H = J s w_i w_j w_k sum_d (1/w_l) [ sum_a Vw[l][a] F_d(a) + [l = N] Fhat_R - [l = 0] Fhat_L ]
+//      with Vw[l][a] = -w_a D[a][l] and Fhat = LLF(q_L, q_R) - (f^nu(q_L, g_L) + f^nu(q_R, g_R)) / 2.
+// A face flux is evaluated by both elements with identical arguments, so the
+// scheme stays conservative to the last bit.
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace scdg {
+
+namespace {
+
+constexpr int kMaxP = kMaxOrder + 1;
+
+struct DgParams {
+  int k_elem, p;
+  double s, jac, gamma, mach2, inv_re, prandtl, suth;
+  double w[kMaxP];
+  double d[kMaxP][kMaxP];    // D[l][a] = l_a'(x_l)
+  double vw[kMaxP][kMaxP];   // -w_a D[a][l]
+};
+
+struct Prim {
+  double rho, u[3], p, e;  // e: specific internal energy
+};
+
+__device__ __forceinline__ Prim prim(const double q[5], double gamma) {
+  Prim r;
+  r.rho = q[0];
+  const double ir = 1.0 / q[0];
+  r.u[0] = q[1] * ir;
+  r.u[1] = q[2] * ir;
+  r.u[2] = q[3] * ir;
+  const double ke = 0.5 * (r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+  r.e = q[4] * ir - ke;
+  r.p = (gamma - 1.0) * q[0] * r.e;
+  return r;
+}
+
+__device__ void flux_adv(const double q[5], int d, double gamma, double f[5]) {
+  const Prim a = prim(q, gamma);
+  const double vd = a.u[d];
+  f[0] = q[0] * vd;
+  f[1] = q[1] * vd;
+  f[2] = q[2] * vd;
+  f[3] = q[3] * vd;
+  f[1 + d] += a.p;
+  f[4] = vd * (q[4] + a.p);
+}
+
+// viscous flux f^nu_d(q, g); g[k*5 + v] = d q_v / d x_k
+__device__ void flux_visc(const double q[5], const double g[15], int d, const DgParams &P,
+                          double f[5]) {
+  const Prim a = prim(q, P.gamma);
+  const double ir = 1.0 / q[0];
+  double dv[3][3];   // dv[i][k] = d u_i / d x_k
+  double de[3];
+  const double eE = q[4] * ir;
+  for (int k = 0; k < 3; ++k) {
+    for (int i = 0; i < 3; ++i) dv[i][k] = (g[k * 5 + 1 + i] - a.u[i] * g[k * 5]) * ir;
+    de[k] = (g[k * 5 + 4] - eE * g[k * 5]) * ir -
+            (a.u[0] * dv[0][k] + a.u[1] * dv[1][k] + a.u[2] * dv[2][k]);
+  }
+  const double temp = P.gamma * P.mach2 * a.p / q[0];
+  const double mu = (1.0 + P.suth) / (temp + P.suth) * temp * sqrt(temp);
+  const double div = dv[0][0] + dv[1][1] + dv[2][2];
+  double tau[3];
+  for (int i = 0; i < 3; ++i) {
+    tau[i] = mu * (dv[i][d] + dv[d][i]);
+    if (i == d) tau[i] -= (2.0 / 3.0) * mu * div;
+  }
+  const double heat = mu * P.gamma / P.prandtl * de[d];
+  f[0] = 0.0;
+  f[1] = tau[0] * P.inv_re;
+  f[2] = tau[1] * P.inv_re;
+  f[3] = tau[2] * P.inv_re;
+  f[4] = (a.u[0] * tau[0] + a.u[1] * tau[1] + a.u[2] * tau[2] + heat) * P.inv_re;
+}
+
+// total numerical flux through a +e_d face: LLF advective minus BR1 viscous
+__device__ void face_flux(const double ql[5], const double gl[15], const double qr[5],
+                          const double gr[15], int d, const DgParams &P, double fh[5]) {
+  double fl[5], fr[5], vl[5], vr[5];
+  flux_adv(ql, d, P.gamma, fl);
+  flux_adv(qr, d, P.gamma, fr);
+  const Prim a = prim(ql, P.gamma), b = prim(qr, P.gamma);
+  const double lam_l = fabs(a.u[d]) + sqrt(P.gamma * a.p / a.rho);
+  const double lam_r = fabs(b.u[d]) + sqrt(P.gamma * b.p / b.rho);
+  const double lam = lam_l >= lam_r ? lam_l : lam_r;
+  flux_visc(ql, gl, d, P, vl);
+  flux_visc(qr, gr, d, P, vr);
+  for (int v = 0; v < 5; ++v)
+    fh[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * lam * (qr[v] - ql[v]) - 0.5 * (vl[v] + vr[v]);
+}
+
+// cooperative copy of the parameter block into LDS (ends with a barrier)
+__device__ __forceinline__ void load_params(const DgParams *__restrict__ src, DgParams *dst) {
+  static_assert(sizeof(DgParams) % 4 == 0, "word copy");
+  const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
+  uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+  for (int t = threadIdx.x; t < (int)(sizeof(DgParams) / 4); t += blockDim.x) d[t] = s[t];
+  __syncthreads();
+}
+
+__device__ __forceinline__ int nbr_elem(int e, int k, int d, int step) {
+  int c[3] = {e % k, (e / k) % k, e / (k * k)};
+  c[d] = (c[d] + step + k) % k;
+  return c[0] + k * c[1] + k * k * c[2];
+}
+
+__device__ __forceinline__ int node_with(int node, int p, int d, int l) {
+  int c[3] = {node % p, (node / p) % p, node / (p * p)};
+  c[d] = l;
+  return c[0] + p * c[1] + p * p * c[2];
+}
+
+__global__ __launch_bounds__(512) void lift_kernel(const DgParams *__restrict__ prm, const double *__restrict__ q,
+                            double *__restrict__ g) {
+  __shared__ DgParams P;
+  __shared__ double qs[kMaxP * kMaxP * kMaxP * 5];
+  load_params(prm, &P);
+  const int p = P.p, p3 = p * p * p, n = p - 1;
+  const int e = blockIdx.x;
+  const double *qe = q + (int64_t)e * p3 * 5;
+  for (int t = threadIdx.x; t < p3 * 5; t += blockDim.x) qs[t] = qe[t];
+  __syncthreads();
+  const int node = threadIdx.x;
+  if (node >= p3) return;
+  const int c[3] = {node % p, (node / p) % p, node / (p * p)};
+  double out[15];
+  for (int d = 0; d < 3; ++d) {
+    const int l = c[d];
+    for (int v = 0; v < 5; ++v) {
+      double acc = 0.0;
+      for (int a = 0; a < p; ++a) acc += P.d[l][a] * qs[node_with(node, p, d, a) * 5 + v];
+      out[d * 5 + v] = acc;
+    }
+    if (l == n) {
+      const double *qn = q + ((int64_t)nbr_elem(e, P.k_elem, d, 1) * p3 + node_with(node, p, d, 0)) * 5;
+      for (int v = 0; v < 5; ++v) out[d * 5 + v] += (0.5 / P.w[n]) * (qn[v] - qs[node * 5 + v]);
+    }
+    if (l == 0) {
+      const double *qn = q + ((int64_t)nbr_elem(e, P.k_elem, d, -1) * p3 + node_with(node, p, d, n)) * 5;
+      for (int v = 0; v < 5; ++v) out[d * 5 + v] -= (0.5 / P.w[0]) * (qn[v] - qs[node * 5 + v]);
+    }
+  }
+  double *ge = g + ((int64_t)e * p3 + node) * 15;
+  for (int t = 0; t < 15; ++t) ge[t] = P.s * out[t];
+}
+
+__global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restrict__ prm, const double *__restrict__ q,
+                                const double *__restrict__ g, const double *__restrict__ q_s,
+                                double inv_dt, double *__restrict__ r) {
+  __shared__ DgParams P;
+  extern __shared__ double fs[];   // [3][p3][5] volume fluxes
+  load_params(prm, &P);
+  const int p = P.p, p3 = p * p * p, n = p - 1;
+  const int e = blockIdx.x;
+  const int node = threadIdx.x;
+  const bool live = node < p3;
+  double qn[5], gn[15];
+  if (live) {
+    const double *qe = q + ((int64_t)e * p3 + node) * 5;
+    const double *ge = g + ((int64_t)e * p3 + node) * 15;
+    for (int v = 0; v < 5; ++v) qn[v] = qe[v];
+    for (int t = 0; t < 15; ++t) gn[t] = ge[t];
+    for (int d = 0; d < 3; ++d) {
+      double fa[5], fv[5];
+      flux_adv(qn, d, P.gamma, fa);
+      flux_visc(qn, gn, d, P, fv);
+      for (int v = 0; v < 5; ++v) fs[(d * p3 + node) * 5 + v] = fa[v] - fv[v];
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  const int c[3] = {node % p, (node / p) % p, node / (p * p)};
+  double h[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int d = 0; d < 3; ++d) {
+    const int l = c[d];
+    double rd[5];
+    for (int v = 0; v < 5; ++v) {
+      double acc = 0.0;
+      for (int a = 0; a < p; ++a) acc += P.vw[l][a] * fs[(d * p3 + node_with(node, p, d, a)) * 5 + v];
+      rd[v] = acc;
+    }
+    if (l == n) {
+      const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, d, 1) * p3 + node_with(node, p, d, 0);
+      double fh[5];
+      face_flux(qn, gn, q + nb * 5, g + nb * 15, d, P, fh);
+      for (int v = 0; v < 5; ++v) rd[v] += fh[v];
+    }
+    if (l == 0) {
+      const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, d, -1) * p3 + node_with(node, p, d, n);
+      double fh[5];
+      face_flux(q + nb * 5, g + nb * 15, qn, gn, d, P, fh);
+      for (int v = 0; v < 5; ++v) rd[v] -= fh[v];
+    }
+    for (int v = 0; v < 5; ++v) h[v] += rd[v] / P.w[l];
+  }
+  const double m = P.jac * P.w[c[0]] * P.w[c[1]] * P.w[c[2]];
+  double *re = r + ((int64_t)e * p3 + node) * 5;
+  for (int v = 0; v < 5; ++v) {
+    double val = m * P.s * h[v];
+    if (q_s) val += m * inv_dt * (qn[v] - q_s[((int64_t)e * p3 + node) * 5 + v]);
+    re[v] = val;
+  }
+}
+
+// Gauss-Lobatto nodes and weights (Newton on L_{N+1} - L_{N-1} from Chebyshev
+// points) and the barycentric derivative matrix with the negative-sum diagonal.
+void gl_operators(int nord, double *x, double *w, double d[kMaxP][kMaxP]) {
+  const int p = nord + 1;
+  auto leg = [](int k, double t, double &lk, double &dk) {
+    double l0 = 1.0, l1 = t, d0 = 0.0, d1 = 1.0;
+    if (k == 0) {
+      lk = 1.0;
+      dk = 0.0;
+      return;
+    }
+    for (int m = 2; m <= k; ++m) {
+      const double l2 = ((2 * m - 1) * t * l1 - (m - 1) * l0) / m;
+      const double d2 = d0 + (2 * m - 1) * l1;
+      l0 = l1;
+      l1 = l2;
+      d0 = d1;
+      d1 = d2;
+    }
+    lk = l1;
+    dk = d1;
+  };
+  for (int j = 0; j < p; ++j) x[j] = -std::cos(M_PI * j / nord);
+  for (int j = 1; j < nord; ++j) {
+    for (int it = 0; it < 100; ++it) {
+      double lp, dp, lm, dm, ln, dn;
+      leg(nord + 1, x[j], lp, dp);
+      leg(nord - 1, x[j], lm, dm);
+      leg(nord, x[j], ln, dn);
+      const double step = (lp - lm) / ((2 * nord + 1) * ln);
+      x[j] -= step;
+      if (std::fabs(step) < 1e-16) break;
+    }
+  }
+  x[0] = -1.0;
+  x[nord] = 1.0;
+  for (int j = 0; j < p; ++j) {
+    double ln, dn;
+    leg(nord, x[j], ln, dn);
+    w[j] = 2.0 / (nord * (nord + 1) * ln * ln);
+  }
+  std::vector<double> lam(p, 1.0);
+  for (int j = 0; j < p; ++j)
+    for (int i = 0; i < p; ++i)
+      if (i != j) lam[j] /= (x[j] - x[i]);
+  for (int i = 0; i < p; ++i) {
+    double sum = 0.0;
+    for (int j = 0; j < p; ++j) {
+      if (i == j) continue;
+      d[i][j] = (lam[j] / lam[i]) / (x[i] - x[j]);
+      sum += d[i][j];
+    }
+    d[i][i] = -sum;
+  }
+}
+
+}  // namespace
+
+struct DgContext {
+  DgParams host;
+  DgParams *dev = nullptr;
+  double *g = nullptr;
+  int64_t n_nodes = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+};
+
+}  // namespace scdg
+
+using scdg::DgContext;
+
+struct scdg_dg {
+  DgContext c;
+};
+
+extern "C" {
+
+scdg_status scdg_dg_create(scdg_dg **out, const scdg_dg_params *prm, void *hip_stream) {
+  if (!out || !prm || prm->k_elem < 2 || prm->order < 2 || prm->order > scdg::kMaxOrder ||
+      prm->length <= 0 || prm->mach <= 0 || prm->reynolds <= 0)
+    return SCDG_ERR_ARG;
+  scdg_dg *dg = new (std::nothrow) scdg_dg();
+  if (!dg) return SCDG_ERR_NOMEM;
+  auto &c = dg->c;
+  auto &P = c.host;
+  P.k_elem = prm->k_elem;
+  P.p = prm->order + 1;
+  const double h = prm->length / prm->k_elem;
+  P.s = 2.0 / h;
+  P.jac = (h / 2) * (h / 2) * (h / 2);
+  P.gamma = prm->gamma > 0 ? prm->gamma : 1.4;
+  P.mach2 = prm->mach * prm->mach;
+  P.inv_re = 1.0 / prm->reynolds;
+  P.prandtl = prm->prandtl > 0 ? prm->prandtl : 0.72;
+  P.suth = prm->sutherland_ratio > 0 ? prm->sutherland_ratio : 110.4 / 288.15;
+  double x[scdg::kMaxP];
+  scdg::gl_operators(prm->order, x, P.w, P.d);
+  for (int l = 0; l < P.p; ++l)
+    for (int a = 0; a < P.p; ++a) P.vw[l][a] = -P.w[a] * P.d[a][l];
+  c.stream = static_cast<hipStream_t>(hip_stream);
+  c.n_nodes = (int64_t)prm->k_elem * prm->k_elem * prm->k_elem * P.p * P.p * P.p;
+  if (hipMalloc(&c.dev, sizeof(scdg::DgParams)) != hipSuccess ||
+      hipMalloc(&c.g, sizeof(double) * 15 * c.n_nodes) != hipSuccess ||
+      hipMemcpy(c.dev, &P, sizeof(scdg::DgParams), hipMemcpyHostToDevice) != hipSuccess) {
+    if (c.dev) (void)hipFree(c.dev);
+    if (c.g) (void)hipFree(c.g);
+    delete dg;
+    return SCDG_ERR_NOMEM;
+  }
+  *out = dg;
+  return SCDG_OK;
+}
+
+scdg_status scdg_dg_destroy(scdg_dg *dg) {
+  if (!dg) return SCDG_OK;
+  (void)hipStreamSynchronize(dg->c.stream);
+  if (dg->c.dev) (void)hipFree(dg->c.dev);
+  if (dg->c.g) (void)hipFree(dg->c.g);
+  delete dg;
+  return SCDG_OK;
+}
+
+scdg_status scdg_dg_residual(scdg_dg *dg, const double *q, const double *q_s, double inv_dt,
+                             double *r) {
+  if (!dg || !q || !r) return SCDG_ERR_ARG;
+  auto &c = dg->c;
+  const int p3 = c.host.p * c.host.p * c.host.p;
+  const int n_elem = c.host.k_elem * c.host.k_elem * c.host.k_elem;
+  const int threads = ((p3 + 63) / 64) * 64;
+  hipLaunchKernelGGL(scdg::lift_kernel, dim3(n_elem), dim3(threads), 0, c.stream, c.dev, q, c.g);
+  hipLaunchKernelGGL(scdg::residual_kernel, dim3(n_elem), dim3(threads),
+                     sizeof(double) * 15 * p3, c.stream, c.dev, q, c.g, q_s, inv_dt, r);
+  return hipGetLastError() == hipSuccess ? SCDG_OK : SCDG_ERR_HIP;
+}
+
+scdg_status scdg_dg_gradient(scdg_dg *dg, double *g_out) {
+  if (!dg || !g_out) return SCDG_ERR_ARG;
+  auto &c = dg->c;
+  if (hipMemcpyAsync(g_out, c.g, sizeof(double) * 15 * c.n_nodes, hipMemcpyDeviceToDevice,
+                     c.stream) != hipSuccess)
+    return SCDG_ERR_HIP;
+  return SCDG_OK;
+}
+
+}  // extern "C"

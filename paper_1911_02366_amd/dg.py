@@ -1,0 +1,69 @@
+"""Binding of the device nonlinear residual (scdg_dg_* in the C ABI).
+
+R(Q) = M (Q - Q_s) / dt + H(Q) for the GL-DGSEM compressible Navier-Stokes
+operator on a periodic Cartesian mesh (paper, eq. ImplicitDisc, eq. DiscretNS,
+eq. DGSEMsystem).  Argument marshalling only: both kernels run in libscdg.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import torch
+
+from . import _lib as L
+from .plan import _ptr, _stream
+
+
+class DgResidual:
+    """Owns one scdg_dg object (parameters + lifted-gradient workspace)."""
+
+    def __init__(self, k_elem: int, order: int, mach: float, reynolds: float,
+                 length: float = 2.0 * math.pi, gamma: float = 1.4, prandtl: float = 0.72,
+                 sutherland_ratio: float = 110.4 / 288.15, stream=None):
+        self.lib = L.load()
+        prm = L.DgParams(k_elem, order, length, mach, reynolds, gamma, prandtl, sutherland_ratio)
+        handle = C.c_void_p()
+        st = self.lib.scdg_dg_create(C.byref(handle), C.byref(prm), _stream(stream))
+        if st != L.SCDG_OK:
+            raise L.ScdgError(st, "scdg_dg_create")
+        self.handle = handle
+        self.k_elem, self.order = k_elem, order
+        self.n_dof = k_elem ** 3 * (order + 1) ** 3 * 5
+
+    def _check(self, t: torch.Tensor, name: str):
+        if t.dtype != torch.float64 or t.numel() != self.n_dof:
+            raise ValueError(f"{name}: expected {self.n_dof} float64 values")
+
+    def residual(self, q: torch.Tensor, q_s: torch.Tensor | None = None, inv_dt: float = 0.0,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+        self._check(q, "q")
+        if q_s is not None:
+            self._check(q_s, "q_s")
+        if out is None:
+            out = torch.empty(self.n_dof, dtype=torch.float64, device=q.device)
+        self._check(out, "out")
+        st = self.lib.scdg_dg_residual(self.handle, _ptr(q), _ptr(q_s), float(inv_dt), _ptr(out))
+        if st != L.SCDG_OK:
+            raise L.ScdgError(st, "scdg_dg_residual")
+        return out
+
+    def gradient(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        n_nodes = self.n_dof // 5
+        if out is None:
+            out = torch.empty(n_nodes * 15, dtype=torch.float64, device="cuda")
+        st = self.lib.scdg_dg_gradient(self.handle, _ptr(out))
+        if st != L.SCDG_OK:
+            raise L.ScdgError(st, "scdg_dg_gradient")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.scdg_dg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
