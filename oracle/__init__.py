@@ -14,7 +14,9 @@ What it computes (each function cites the passage it follows):
     their definitions, per element, with numpy;
   * (module `oracle.dgsem`) the nonlinear residual R(Q) = M (Q - Q_s)/dt + H(Q)
     of the backward-Euler GL-DGSEM step, with H from the weak form of
-    eq. DGSEMsystem evaluated as Gauss-Lobatto quadrature sums.
+    eq. DGSEMsystem evaluated as Gauss-Lobatto quadrature sums;
+  * (module `oracle.mlp`) the learned-initial-guess network in FP64: forward,
+    chain-rule backward, Adam, mean-squared loss and the feature maps.
 """
 from .linalg import (  # noqa: F401
     NodeSets, node_sets, dof_maps, assemble_global, solve_dense, solve_sparse,

@@ -1,0 +1,121 @@
+"""Plain FP64 reference of the learned-initial-guess network (test oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+The paper has no learned component; this is the reference for an addition to
+its Newton-Krylov loop (Section 2.2): a per-element multilayer perceptron
+that predicts the Newton increment of the next implicit step from the
+element's state and its previous increment.
+
+Network: a_0 = x, a_l = tanh(a_{l-1} W_l + b_l) for the hidden layers,
+y = a_L W_out + b_out (rows are samples).  Parameters live in one flat
+vector, layer after layer, W_l [fan_in x fan_out] row-major then b_l.
+Gradients follow the chain rule written out per layer; Adam is the update of
+Kingma and Ba (2015) with bias correction.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def layout(n_in: int, n_hidden: int, n_layers: int, n_out: int):
+    """[(w_offset, fan_in, fan_out, b_offset)] per layer and the parameter count."""
+    out, off = [], 0
+    for layer in range(n_layers + 1):
+        fi = n_in if layer == 0 else n_hidden
+        fo = n_out if layer == n_layers else n_hidden
+        out.append((off, fi, fo, off + fi * fo))
+        off += fi * fo + fo
+    return out, off
+
+
+def _unpack(w, shape):
+    lay, n = layout(*shape)
+    assert w.size == n
+    return [(w[o:o + fi * fo].reshape(fi, fo), w[bo:bo + fo]) for o, fi, fo, bo in lay]
+
+
+def forward(w: np.ndarray, x: np.ndarray, shape):
+    """y and the list of activations a_0 = x, a_1, ..., a_L (FP64)."""
+    layers = _unpack(np.asarray(w, dtype=np.float64), shape)
+    a = [np.asarray(x, dtype=np.float64)]
+    for i, (wl, bl) in enumerate(layers):
+        z = a[-1] @ wl + bl
+        if i < len(layers) - 1:
+            a.append(np.tanh(z))
+        else:
+            return z, a
+    raise AssertionError("unreachable")
+
+
+def backward(w: np.ndarray, acts, dy: np.ndarray, shape):
+    """dLoss/dw (flat) and dLoss/dx given dLoss/dy and the forward activations."""
+    layers = _unpack(np.asarray(w, dtype=np.float64), shape)
+    lay, n = layout(*shape)
+    dw = np.zeros(n)
+    dz = np.asarray(dy, dtype=np.float64)
+    for i in range(len(layers) - 1, -1, -1):
+        wl, _ = layers[i]
+        o, fi, fo, bo = lay[i]
+        dw[o:o + fi * fo] = (acts[i].T @ dz).reshape(-1)
+        dw[bo:bo + fo] = dz.sum(axis=0)
+        da = dz @ wl.T                      # dLoss / d a_{i}
+        if i > 0:
+            dz = da * (1.0 - acts[i] ** 2)  # through a_i = tanh(z_i)
+        else:
+            dx = da
+    return dw, dx
+
+
+def mse(y: np.ndarray, t: np.ndarray):
+    """mean((y - t)^2) and its gradient 2 (y - t) / n."""
+    d = np.asarray(y, dtype=np.float64) - np.asarray(t, dtype=np.float64)
+    return float(np.mean(d * d)), 2.0 * d / d.size
+
+
+def adam(w, g, m1, m2, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step; returns new (w, m1, m2)."""
+    m1 = beta1 * m1 + (1.0 - beta1) * g
+    m2 = beta2 * m2 + (1.0 - beta2) * g * g
+    mhat = m1 / (1.0 - beta1 ** step)
+    vhat = m2 / (1.0 - beta2 ** step)
+    return w - lr * mhat / (np.sqrt(vhat) + eps), m1, m2
+
+
+# --------------------------------------------------------------------------
+# maps between DG vectors (natural DOF order, 5 variables per node) and the
+# network's features and targets
+# --------------------------------------------------------------------------
+
+def field_stats(q: np.ndarray, dq_prev: np.ndarray):
+    """Per-variable mean and population standard deviation of q and root mean
+    square of dq_prev over all nodes; a zero spread becomes 1."""
+    qv = np.asarray(q, dtype=np.float64).reshape(-1, 5)
+    dv = np.asarray(dq_prev, dtype=np.float64).reshape(-1, 5)
+    mean = qv.mean(axis=0)
+    std = qv.std(axis=0)
+    std = np.where((std > 0) & (std > 1e-12 * np.abs(mean)), std, 1.0)
+    rms = np.sqrt((dv * dv).mean(axis=0))
+    rms = np.where(rms > 0, rms, 1.0)
+    return mean, std, rms
+
+
+def features(q, dq_prev, stats, n_elem: int):
+    """Rows [ (Q_e - mean) / std , dQprev_e / rms ] per element."""
+    mean, std, rms = stats
+    qv = np.asarray(q, dtype=np.float64).reshape(n_elem, -1, 5)
+    dv = np.asarray(dq_prev, dtype=np.float64).reshape(n_elem, -1, 5)
+    return np.concatenate([((qv - mean) / std).reshape(n_elem, -1), (dv / rms).reshape(n_elem, -1)],
+                          axis=1)
+
+
+def target(dq, dq_prev, stats, n_elem: int):
+    _, _, rms = stats
+    d = (np.asarray(dq, dtype=np.float64) - np.asarray(dq_prev, dtype=np.float64)).reshape(n_elem, -1, 5)
+    return (d / rms).reshape(n_elem, -1)
+
+
+def apply(dq_prev, y, stats, n_elem: int):
+    _, _, rms = stats
+    dv = np.asarray(dq_prev, dtype=np.float64).reshape(n_elem, -1, 5)
+    return (dv + rms * np.asarray(y, dtype=np.float64).reshape(n_elem, -1, 5)).reshape(-1)

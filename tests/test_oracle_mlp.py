@@ -1,0 +1,143 @@
+"""Pins of the oracle's learned-guess network (oracle/mlp.py): hand-evaluated
+closed forms, central finite differences of the loss for every parameter and
+input, Adam's closed-form first steps, the feature maps' round trip, a
+training sanity check, and planted mistakes that the pins must catch."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as om
+
+SMALL = (6, 5, 2, 4)      # n_in, n_hidden, n_layers, n_out
+
+
+def _params(shape, seed):
+    _, n = om.layout(*shape)
+    return np.random.default_rng(seed).uniform(-0.6, 0.6, n)
+
+
+def test_layout_counts_the_paper_sized_network():
+    # 1250 -> 256 -> 256 -> 625 at order 4: 546,673 weights and biases
+    _, n = om.layout(1250, 256, 2, 625)
+    assert n == 1250 * 256 + 256 + 256 * 256 + 256 + 256 * 625 + 625
+
+
+def test_forward_closed_form():
+    # one hidden unit: y = w2 tanh(w1 x + b1) + b2
+    shape = (1, 1, 1, 1)
+    w = np.array([0.5, -0.25, 2.0, 0.1])          # W1, b1, W2, b2
+    x = np.array([[3.0], [-1.0]])
+    y, acts = om.forward(w, x, shape)
+    np.testing.assert_allclose(y[:, 0], 2.0 * np.tanh(0.5 * x[:, 0] - 0.25) + 0.1, rtol=0, atol=1e-15)
+    assert len(acts) == 2
+
+
+def test_mse_closed_form():
+    loss, dy = om.mse(np.array([[1.0, 2.0]]), np.array([[0.0, 4.0]]))
+    assert loss == pytest.approx(2.5, abs=1e-15)
+    np.testing.assert_allclose(dy, [[1.0, -2.0]], atol=1e-15)
+
+
+def _loss(w, x, t, shape):
+    y, _ = om.forward(w, x, shape)
+    return om.mse(y, t)[0]
+
+
+@pytest.mark.parametrize("shape", [SMALL, (3, 4, 1, 2), (5, 3, 3, 5)])
+def test_gradients_match_central_differences(shape):
+    rng = np.random.default_rng(2)
+    w = _params(shape, 1)
+    x = rng.standard_normal((3, shape[0]))
+    t = rng.standard_normal((3, shape[3]))
+    y, acts = om.forward(w, x, shape)
+    _, dy = om.mse(y, t)
+    dw, dx = om.backward(w, acts, dy, shape)
+    h = 1e-6
+    fd = np.array([(_loss(w + h * e, x, t, shape) - _loss(w - h * e, x, t, shape)) / (2 * h)
+                   for e in np.eye(w.size)])
+    assert np.abs(fd - dw).max() <= 1e-8 * max(1.0, np.abs(dw).max())
+    fdx = np.zeros_like(x)
+    for i in range(x.shape[0]):
+        for j in range(x.shape[1]):
+            e = np.zeros_like(x)
+            e[i, j] = h
+            fdx[i, j] = (_loss(w, x + e, t, shape) - _loss(w, x - e, t, shape)) / (2 * h)
+    assert np.abs(fdx - dx).max() <= 1e-8 * max(1.0, np.abs(dx).max())
+
+
+def test_adam_closed_form_first_steps():
+    w = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    m1 = np.zeros(3)
+    m2 = np.zeros(3)
+    # with bias correction, a constant gradient gives m_hat = g and v_hat = g^2,
+    # so every step moves each weight by lr * g / (|g| + eps)
+    w1, m1, m2 = om.adam(w, g, m1, m2, lr=0.01, step=1)
+    np.testing.assert_allclose(w1, w - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    w2, m1, m2 = om.adam(w1, g, m1, m2, lr=0.01, step=2)
+    np.testing.assert_allclose(w2, w1 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-13)
+
+
+def test_field_stats_and_maps_round_trip():
+    rng = np.random.default_rng(5)
+    n_elem, dpe = 3, 5 * 8
+    q = rng.standard_normal(n_elem * dpe) + np.tile([1.0, 0.0, 0.0, 0.0, 100.0], n_elem * dpe // 5)
+    dq_prev = 1e-3 * rng.standard_normal(n_elem * dpe)
+    dq = dq_prev + 1e-5 * rng.standard_normal(n_elem * dpe)
+    stats = om.field_stats(q, dq_prev)
+    mean, std, rms = stats
+    qv = q.reshape(-1, 5)
+    # two-pass textbook formulas for comparison
+    for v in range(5):
+        col = qv[:, v]
+        assert mean[v] == pytest.approx(sum(col) / len(col), rel=1e-14)
+        assert std[v] == pytest.approx(math.sqrt(sum((c - mean[v]) ** 2 for c in col) / len(col)), rel=1e-12)
+    x = om.features(q, dq_prev, stats, n_elem)
+    assert x.shape == (n_elem, 2 * dpe)
+    np.testing.assert_allclose(x[1, :5], (q[dpe:dpe + 5] - mean) / std, atol=1e-14)
+    t = om.target(dq, dq_prev, stats, n_elem)
+    np.testing.assert_allclose(om.apply(dq_prev, t, stats, n_elem), dq, rtol=0, atol=1e-17)
+    # a constant variable has no spread: std becomes 1
+    qc = np.tile([1.0, 2.0, 3.0, 4.0, 5.0], 10)
+    _, std_c, rms_c = om.field_stats(qc, np.zeros(50))
+    np.testing.assert_array_equal(std_c, np.ones(5))
+    np.testing.assert_array_equal(rms_c, np.ones(5))
+
+
+def test_training_reduces_loss():
+    rng = np.random.default_rng(7)
+    shape = (4, 16, 2, 2)
+    w = _params(shape, 3) * 0.5
+    x = rng.standard_normal((64, 4))
+    t = np.stack([np.sin(x[:, 0] + x[:, 1]), x[:, 2] * x[:, 3]], axis=1)
+    m1, m2 = np.zeros_like(w), np.zeros_like(w)
+    first = _loss(w, x, t, shape)
+    for step in range(1, 301):
+        y, acts = om.forward(w, x, shape)
+        _, dy = om.mse(y, t)
+        dw, _ = om.backward(w, acts, dy, shape)
+        w, m1, m2 = om.adam(w, dw, m1, m2, lr=1e-2, step=step)
+    assert _loss(w, x, t, shape) < 0.1 * first
+
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    good = om.backward
+
+    def dropped_bias_gradients(w, acts, dy, shape):
+        dw, dx = good(w, acts, dy, shape)
+        lay, _ = om.layout(*shape)
+        for _, _, fo, bo in lay:
+            dw[bo:bo + fo] = 0.0
+        return dw, dx
+
+    monkeypatch.setattr(om, "backward", dropped_bias_gradients)
+    with pytest.raises(AssertionError):
+        test_gradients_match_central_differences(SMALL)
+    monkeypatch.setattr(om, "backward", good)
+
+    good_adam = om.adam
+    monkeypatch.setattr(om, "adam", lambda w, g, m1, m2, lr, step, beta1=0.9, beta2=0.999, eps=1e-8:
+                        good_adam(w, g, m1, m2, lr, 1, beta1, beta2, eps))   # bias correction frozen at step 1
+    with pytest.raises(AssertionError):
+        test_adam_closed_form_first_steps()
