@@ -105,6 +105,7 @@ typedef struct {
   int32_t solver_used;  /* scdg_solver actually used */
   double rel_res_S;     /* last ||b_S - S x|| / ||b_S|| (GMRES estimate) */
   double rel_res_full;  /* ||B - A dQ||_2 / ||B||_2 in FP64, or -1 if not computed */
+  int32_t guess_rejected; /* 1 if the initial guess was dropped: ||b_S - S x0|| > ||b_S|| */
 } scdg_solve_info;
 
 /* Build the index maps of the partition (Section 3.2: permutation indexes from
@@ -252,6 +253,71 @@ scdg_status scdg_dg_residual(scdg_dg *dg, const double *q, const double *q_s, do
 /* Copy the lifted gradient of the last scdg_dg_residual call into g (device,
  * 15 doubles per node: g[(e P^3 + n) 15 + 5 d + v] = d q_v / d x_d). */
 scdg_status scdg_dg_gradient(scdg_dg *dg, double *g);
+
+/* ------------------------------------------------------------------------
+ * Learned initial guess.  A per-element multilayer perceptron maps an
+ * element's state and its previous Newton increment to a prediction of the
+ * next increment; its boundary part serves as the initial guess x0 of the
+ * condensed GMRES solve (scdg_solve; the guess is dropped for the zero vector
+ * when ||b_S - S x0|| > ||b_S||, so the solve always converges to the same
+ * tolerance as without it).  The paper has no learned component: this is an
+ * addition to its Newton-Krylov loop (Section 2.2).
+ *
+ * Network (FP32 storage, FP32 matrix-core arithmetic):
+ *   a_0 = x;  a_l = tanh(W_l^T a_{l-1} + b_l), l = 1..n_layers;
+ *   y = W_out^T a_{n_layers} + b_out (linear output).
+ * Parameters: one flat device float vector, layer after layer, each W_l
+ * [fan_in x fan_out] row-major followed by b_l [fan_out]; the caller owns it
+ * and its Adam moments.  Batches are row-major [batch x width].
+ * Features for element e of a DG vector (natural DOF order, d = 5 P^3 DOFs
+ * per element, n_in = 2 d, n_out = d):
+ *   x_e = [ (Q_e - mean_v) / std_v , dQprev_e / rms_v ],
+ *   target t_e = (dQ_e - dQprev_e) / rms_v,  prediction dQ_e = dQprev_e + rms_v y_e,
+ * with per-variable mean and standard deviation of Q and root mean square of
+ * dQprev over the whole field (stats: 15 device doubles mean[5], std[5],
+ * rms[5]; a zero spread is replaced by 1).
+ * The object owns the hidden activations of its last forward call (for
+ * scdg_mlp_backward), scratch for the backward pass and reduction partials.
+ * All calls are asynchronous on the object's stream and bitwise repeatable.
+ * ------------------------------------------------------------------------ */
+typedef struct scdg_mlp scdg_mlp;
+typedef struct {
+  int32_t n_in, n_hidden, n_layers, n_out;  /* n_layers hidden layers (1..16) */
+  int32_t max_batch;                        /* largest batch of any call */
+} scdg_mlp_shape;
+scdg_status scdg_mlp_create(scdg_mlp **out, const scdg_mlp_shape *s, void *hip_stream);
+scdg_status scdg_mlp_destroy(scdg_mlp *m);
+/* number of floats of the flat parameter vector (and of its gradient) */
+scdg_status scdg_mlp_param_count(const scdg_mlp *m, int64_t *n);
+/* y [batch x n_out] = network(x [batch x n_in]); keeps the activations */
+scdg_status scdg_mlp_forward(scdg_mlp *m, const float *w, const float *x, int32_t batch, float *y);
+/* Gradients of a loss with respect to the parameters (dw, overwritten) and,
+ * if dx != NULL, to the input, given dy = dLoss/dy for the batch of the last
+ * scdg_mlp_forward call (same x and batch; SCDG_ERR_STATE otherwise). */
+scdg_status scdg_mlp_backward(scdg_mlp *m, const float *w, const float *x, const float *dy, int32_t batch,
+                              float *dw, float *dx);
+/* One Adam step (Kingma and Ba): m1 = b1 m1 + (1-b1) g, m2 = b2 m2 + (1-b2) g^2,
+ * w -= lr (m1 / (1 - b1^step)) / (sqrt(m2 / (1 - b2^step)) + eps); step >= 1. */
+scdg_status scdg_mlp_adam(scdg_mlp *m, float *w, const float *dw, float *m1, float *m2, float lr, float beta1,
+                          float beta2, float eps, int32_t step);
+/* Mean squared error over n values: *loss (device double) = mean((y - t)^2);
+ * dy (may be NULL) = 2 (y - t) / n. */
+scdg_status scdg_mlp_mse(scdg_mlp *m, const float *y, const float *t, int64_t n, float *dy, double *loss);
+/* dst[r] = src[idx[r]] for rows of width floats (idx: device int32, count rows) */
+scdg_status scdg_mlp_gather(scdg_mlp *m, const float *src, int32_t width, const int32_t *idx, int32_t count,
+                            float *dst);
+/* Field statistics of the features (n_dof = 5 * nodes; q and dq_prev natural order). */
+scdg_status scdg_guess_stats(scdg_mlp *m, const double *q, const double *dq_prev, int64_t n_dof,
+                             double *stats);
+/* x [n_elem x n_in] from Q and dQprev (needs n_in == 2 n_out, n_out % 5 == 0) */
+scdg_status scdg_guess_features(scdg_mlp *m, const double *q, const double *dq_prev, const double *stats,
+                                int32_t n_elem, float *x);
+/* t [n_elem x n_out] = (dQ - dQprev) / rms */
+scdg_status scdg_guess_target(scdg_mlp *m, const double *dq, const double *dq_prev, const double *stats,
+                              int32_t n_elem, float *t);
+/* dQ = dQprev + rms * y (natural order, n_elem * n_out doubles) */
+scdg_status scdg_guess_apply(scdg_mlp *m, const double *dq_prev, const float *y, const double *stats,
+                             int32_t n_elem, double *dq);
 
 const char *scdg_status_string(scdg_status s);
 /* Last error text of a plan (or of plan creation when p is NULL). */

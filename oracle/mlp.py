@@ -75,6 +75,7 @@ def mse(y: np.ndarray, t: np.ndarray):
 
 def adam(w, g, m1, m2, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam step; returns new (w, m1, m2)."""
+    w, g, m1, m2 = (np.asarray(a, dtype=np.float64) for a in (w, g, m1, m2))
     m1 = beta1 * m1 + (1.0 - beta1) * g
     m2 = beta2 * m2 + (1.0 - beta2) * g * g
     mhat = m1 / (1.0 - beta1 ** step)

@@ -27,6 +27,9 @@ EXPORTED = [
     "scdg_enable_timing", "scdg_phase_times", "scdg_autotune", "scdg_set_gemm_config",
     "scdg_get_gemm_config", "scdg_plan_fold_counts",
     "scdg_dg_create", "scdg_dg_destroy", "scdg_dg_residual", "scdg_dg_gradient",
+    "scdg_mlp_create", "scdg_mlp_destroy", "scdg_mlp_param_count", "scdg_mlp_forward",
+    "scdg_mlp_backward", "scdg_mlp_adam", "scdg_mlp_mse", "scdg_mlp_gather", "scdg_guess_stats",
+    "scdg_guess_features", "scdg_guess_target", "scdg_guess_apply",
 ]
 GEMM_CONFIGS = ["64x64", "64x128", "128x128", "128x128w8", "128x64", "240x80", "80x80"]
 PHASES = ["inverse", "gemm_x", "gemm_s", "rhs", "schur_apply", "condensed_solve", "backsolve",
@@ -44,6 +47,11 @@ class DgParams(C.Structure):
                 ("prandtl", C.c_double), ("sutherland_ratio", C.c_double)]
 
 
+class MlpShape(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_hidden", C.c_int32), ("n_layers", C.c_int32),
+                ("n_out", C.c_int32), ("max_batch", C.c_int32)]
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("restart", C.c_int32), ("max_iters", C.c_int32),
                 ("tol", C.c_double), ("precond", C.c_int32), ("ir_max", C.c_int32),
@@ -52,7 +60,8 @@ class SolveOpts(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("ir_sweeps", C.c_int32),
-                ("solver_used", C.c_int32), ("rel_res_S", C.c_double), ("rel_res_full", C.c_double)]
+                ("solver_used", C.c_int32), ("rel_res_S", C.c_double), ("rel_res_full", C.c_double),
+                ("guess_rejected", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -104,6 +113,18 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_dg_destroy": (i32, [vp]),
         "scdg_dg_residual": (i32, [vp, vp, vp, d, vp]),
         "scdg_dg_gradient": (i32, [vp, vp]),
+        "scdg_mlp_create": (i32, [C.POINTER(vp), C.POINTER(MlpShape), vp]),
+        "scdg_mlp_destroy": (i32, [vp]),
+        "scdg_mlp_param_count": (i32, [vp, C.POINTER(i64)]),
+        "scdg_mlp_forward": (i32, [vp, vp, vp, i32, vp]),
+        "scdg_mlp_backward": (i32, [vp, vp, vp, vp, i32, vp, vp]),
+        "scdg_mlp_adam": (i32, [vp, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, i32]),
+        "scdg_mlp_mse": (i32, [vp, vp, vp, i64, vp, vp]),
+        "scdg_mlp_gather": (i32, [vp, vp, i32, vp, i32, vp]),
+        "scdg_guess_stats": (i32, [vp, vp, vp, i64, vp]),
+        "scdg_guess_features": (i32, [vp, vp, vp, vp, i32, vp]),
+        "scdg_guess_target": (i32, [vp, vp, vp, vp, i32, vp]),
+        "scdg_guess_apply": (i32, [vp, vp, vp, vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

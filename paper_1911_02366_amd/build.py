@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscdg.so")
 SOURCES = ["scdg_api.hip", "k_inverse.hip", "k_gemm.hip", "k_vec.hip", "k_dense.hip",
-           "k_dgsem.hip"]
+           "k_dgsem.hip", "k_mlp.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]

@@ -249,6 +249,13 @@ scdg_status gmres(Plan &p, const double *bs, double *x, const double *x0, const 
   double beta2;
   ST_TRY(norm2sq(p, r, n, &beta2));
   double beta = std::sqrt(beta2);
+  if (x0 && !(beta <= bnorm)) {
+    // the guess is worse than none (or not finite): start from zero instead
+    info.guess_rejected = 1;
+    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, p.stream));
+    HIP_TRY(hipMemcpyAsync(r, bs, sizeof(double) * n, hipMemcpyDeviceToDevice, p.stream));
+    beta = bnorm;
+  }
   std::vector<double> h((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   int it = 0;
   const double target = o.tol * bnorm;
