@@ -103,6 +103,114 @@ def cpu_baseline(max_seconds: float) -> dict:
                       f"residual {rel:.1e}"}
 
 
+def learned_guess_experiment(args) -> dict:
+    """Backward-Euler run with the learned initial guess (the Taylor-Green state of
+    the workload, 16^3 elements of order 4 by default): steps 1..train collect
+    (state, previous increment, increment) samples, the network is trained by the
+    library's kernels, and every later step is solved three times from the same
+    state -- zero guess, previous increment, network prediction -- to the same
+    Newton tolerance; the run advances with the network's solution."""
+    import numpy as np
+    import torch
+    from paper_1911_02366_amd.newton import ImplicitStepper, LearnedGuess
+    from workload.cases import WORKLOADS, build_case, jacobian_blocks
+
+    cfg = dict(WORKLOADS[args.lg_workload])
+    if args.lg_k:
+        cfg["k_elem"] = args.lg_k
+    case = build_case(device="cuda", **cfg)
+    mesh, prm, dt = case.mesh, case.prm, case.dt
+    st = ImplicitStepper(case.structure(), mesh.k_elem, mesh.order, prm.mach, prm.reynolds, dt,
+                         lambda q: jacobian_blocks(q, mesh, prm, dt), lin_tol=args.lg_lin_tol,
+                         newton_tol=args.lg_newton_tol)
+    n_elem, dpe = mesh.n_elem, 5 * mesh.p ** 3
+    lg = LearnedGuess(n_elem, dpe, capacity=args.lg_train, seed=args.lg_seed, batch=args.lg_batch)
+    q = case.q_state.reshape(-1).contiguous()
+    dq_prev = torch.zeros_like(q)
+    rc_prev = None
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    t_collect = time.perf_counter()
+    for step in range(1, args.lg_train + 1):
+        st.prepare(q)
+        q1, info = st.solve_step(q, guess=dq_prev if step > 1 else None)
+        if not info["converged"]:
+            raise RuntimeError(f"step {step} did not converge: {info}")
+        dq = q1 - q
+        if step > 1:
+            lg.record(q, dq_prev, dq)
+            rc_prev = lg.correction_rms(q, dq_prev, dq)
+        q, dq_prev = q1, dq
+        log(f"train-phase step {step}: newton {info['newton']} gmres {info['gmres']}")
+    t_collect = time.perf_counter() - t_collect
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    history, hold = lg.train(epochs=args.lg_epochs, lr=args.lg_lr, holdout_rows=n_elem)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    hold_zero = lg.loss_on(lg.count - n_elem, lg.count, zero=True)
+    log(f"trained {args.lg_epochs} epochs in {t_train:.1f} s: loss {history[0]:.3e} -> {history[-1]:.3e}, "
+        f"hold-out {hold:.3e} (previous increment: {hold_zero:.3e})")
+    variants = [("zero", "gmres"), ("previous", "gmres"), ("learned", "gmres"),
+                ("previous_newton_start", "newton"), ("learned_newton_start", "newton")]
+    names = [v for v, _ in variants]
+    rec = {k: {"first": [], "total": [], "newton": [], "seconds": [], "guess_res": [], "rejected": []}
+           for k in names}
+    infer_ms = []
+    for step in range(args.lg_train + 1, args.lg_steps + 1):
+        st.prepare(q)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pred = lg.predict(q, dq_prev, rc_prev)
+        torch.cuda.synchronize()
+        infer_ms.append((time.perf_counter() - t1) * 1e3)
+        out = {}
+        for name, mode in variants:
+            g = None if name == "zero" else (dq_prev if name.startswith("previous") else pred)
+            q1, info = st.solve_step(q, guess=g, mode=mode)
+            if not info["converged"]:
+                raise RuntimeError(f"step {step} ({name}) did not converge: {info}")
+            r = rec[name]
+            r["first"].append(info["first_gmres"])
+            r["total"].append(info["gmres"])
+            r["newton"].append(info["newton"])
+            r["seconds"].append(info["seconds"] + (infer_ms[-1] * 1e-3 if name.startswith("learned") else 0.0))
+            r["guess_res"].append(info["guess_res"])
+            r["rejected"].append(info["guess_rejected"])
+            out[name] = q1
+        log(f"step {step}: GMRES per step " + " ".join(f"{k} {rec[k]['total'][-1]}" for k in names))
+        dq = out["zero"] - q
+        rc_prev = lg.correction_rms(q, dq_prev, dq)
+        dq_prev = dq
+        q = out["zero"]
+    mean = lambda v: float(np.mean(v))
+    result = {
+        "experiment": "learned_initial_guess", "workload": args.lg_workload, "k_elem": mesh.k_elem,
+        "order": mesh.order, "dofs": mesh.n_dof,
+        "steps": args.lg_steps, "train_steps": f"2-{args.lg_train}",
+        "test_steps": f"{args.lg_train + 1}-{args.lg_steps}",
+        "newton_tol": args.lg_newton_tol, "gmres_tol": args.lg_lin_tol,
+        "network": f"{2 * dpe}-256-256-{dpe} tanh, FP32, {lg.net.n_params} parameters",
+        "train": {"samples": lg.count - n_elem, "epochs": args.lg_epochs, "batch": args.lg_batch,
+                  "lr": args.lg_lr, "seconds": t_train, "loss_first_epoch": history[0],
+                  "loss_last_epoch": history[-1], "holdout_loss": hold,
+                  "holdout_loss_previous_increment": hold_zero, "alpha": lg.alpha,
+                  "collect_seconds": t_collect},
+        "inference_ms_mean": mean(infer_ms),
+        "guess_rejected": {k: int(np.sum(rec[k]["rejected"])) for k in names},
+        "forcing": "GMRES tol per Newton iteration = clip(0.5 newton_tol |R0| / |R|, gmres_tol, 0.1)",
+    }
+    for key, field in (("first_solve_gmres_mean", "first"), ("gmres_per_step_mean", "total"),
+                       ("newton_per_step_mean", "newton"), ("solve_seconds_per_step_mean", "seconds"),
+                       ("guess_rel_residual_median", "guess_res")):
+        agg = np.median if field == "guess_res" else np.mean
+        result[key] = {k: float(agg(rec[k][field])) for k in names}
+    z = result["solve_seconds_per_step_mean"]["zero"]
+    result["time_to_solution_vs_zero"] = {k: z / result["solve_seconds_per_step_mean"][k] for k in names}
+    lg.close()
+    st.close()
+    return result
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +230,18 @@ def main() -> int:
     ap.add_argument("--no-fp32-variant", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 2 GiB FP64 buffer three times (HBM counter calibration)")
+    ap.add_argument("--learned-guess", action="store_true",
+                    help="run the learned-initial-guess time-stepping experiment instead")
+    ap.add_argument("--lg-workload", default="tgv_n4_k16")
+    ap.add_argument("--lg-k", type=int, default=0, help="override the elements per direction")
+    ap.add_argument("--lg-steps", type=int, default=200)
+    ap.add_argument("--lg-train", type=int, default=50)
+    ap.add_argument("--lg-epochs", type=int, default=20)
+    ap.add_argument("--lg-batch", type=int, default=1024)
+    ap.add_argument("--lg-lr", type=float, default=1e-3)
+    ap.add_argument("--lg-seed", type=int, default=0)
+    ap.add_argument("--lg-lin-tol", type=float, default=1e-10)
+    ap.add_argument("--lg-newton-tol", type=float, default=1e-8)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -133,6 +253,9 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.learned_guess:
+        print(json.dumps(learned_guess_experiment(args)), flush=True)
+        return 0
     if args.calibrate_copy:
         n = (2 << 30) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

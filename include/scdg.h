@@ -106,6 +106,7 @@ typedef struct {
   double rel_res_S;     /* last ||b_S - S x|| / ||b_S|| (GMRES estimate) */
   double rel_res_full;  /* ||B - A dQ||_2 / ||B||_2 in FP64, or -1 if not computed */
   int32_t guess_rejected; /* 1 if the initial guess was dropped: ||b_S - S x0|| > ||b_S|| */
+  double rel_res_guess;   /* ||b_S - S x0|| / ||b_S|| of the first sweep's guess (1 without one) */
 } scdg_solve_info;
 
 /* Build the index maps of the partition (Section 3.2: permutation indexes from
@@ -271,11 +272,12 @@ scdg_status scdg_dg_gradient(scdg_dg *dg, double *g);
  * and its Adam moments.  Batches are row-major [batch x width].
  * Features for element e of a DG vector (natural DOF order, d = 5 P^3 DOFs
  * per element, n_in = 2 d, n_out = d):
- *   x_e = [ (Q_e - mean_v) / std_v , dQprev_e / rms_v ],
- *   target t_e = (dQ_e - dQprev_e) / rms_v,  prediction dQ_e = dQprev_e + rms_v y_e,
- * with per-variable mean and standard deviation of Q and root mean square of
- * dQprev over the whole field (stats: 15 device doubles mean[5], std[5],
- * rms[5]; a zero spread is replaced by 1).
+ *   x_e = [ (Q_e - mean_v) / std_v , dQprev_e / rp_v ],
+ *   target t_e = (dQ_e - dQprev_e) / rc_v,  prediction dQ_e = dQprev_e + rc_v y_e,
+ * with per-variable mean and standard deviation of Q, root mean square rp of
+ * dQprev and rc of dQ - dQprev over the whole field (stats: 20 device doubles
+ * mean[5], std[5], rp[5], rc[5]; a zero spread is replaced by 1).  The network
+ * thus predicts a correction to the previous increment.
  * The object owns the hidden activations of its last forward call (for
  * scdg_mlp_backward), scratch for the backward pass and reduction partials.
  * All calls are asynchronous on the object's stream and bitwise repeatable.
@@ -306,16 +308,17 @@ scdg_status scdg_mlp_mse(scdg_mlp *m, const float *y, const float *t, int64_t n,
 /* dst[r] = src[idx[r]] for rows of width floats (idx: device int32, count rows) */
 scdg_status scdg_mlp_gather(scdg_mlp *m, const float *src, int32_t width, const int32_t *idx, int32_t count,
                             float *dst);
-/* Field statistics of the features (n_dof = 5 * nodes; q and dq_prev natural order). */
-scdg_status scdg_guess_stats(scdg_mlp *m, const double *q, const double *dq_prev, int64_t n_dof,
-                             double *stats);
+/* Field statistics of the features (n_dof = 5 * nodes, natural order); dq
+ * (the increment that followed dq_prev) may be NULL, then rc = rp. */
+scdg_status scdg_guess_stats(scdg_mlp *m, const double *q, const double *dq_prev, const double *dq,
+                             int64_t n_dof, double *stats);
 /* x [n_elem x n_in] from Q and dQprev (needs n_in == 2 n_out, n_out % 5 == 0) */
 scdg_status scdg_guess_features(scdg_mlp *m, const double *q, const double *dq_prev, const double *stats,
                                 int32_t n_elem, float *x);
-/* t [n_elem x n_out] = (dQ - dQprev) / rms */
+/* t [n_elem x n_out] = (dQ - dQprev) / rc */
 scdg_status scdg_guess_target(scdg_mlp *m, const double *dq, const double *dq_prev, const double *stats,
                               int32_t n_elem, float *t);
-/* dQ = dQprev + rms * y (natural order, n_elem * n_out doubles) */
+/* dQ = dQprev + rc * y (natural order, n_elem * n_out doubles) */
 scdg_status scdg_guess_apply(scdg_mlp *m, const double *dq_prev, const float *y, const double *stats,
                              int32_t n_elem, double *dq);
 

@@ -88,9 +88,10 @@ def adam(w, g, m1, m2, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
 # network's features and targets
 # --------------------------------------------------------------------------
 
-def field_stats(q: np.ndarray, dq_prev: np.ndarray):
-    """Per-variable mean and population standard deviation of q and root mean
-    square of dq_prev over all nodes; a zero spread becomes 1."""
+def field_stats(q: np.ndarray, dq_prev: np.ndarray, dq: np.ndarray | None = None):
+    """Per-variable mean and population standard deviation of q, root mean
+    square rp of dq_prev and rc of dq - dq_prev (rc = rp without dq) over all
+    nodes; a zero spread becomes 1."""
     qv = np.asarray(q, dtype=np.float64).reshape(-1, 5)
     dv = np.asarray(dq_prev, dtype=np.float64).reshape(-1, 5)
     mean = qv.mean(axis=0)
@@ -98,12 +99,18 @@ def field_stats(q: np.ndarray, dq_prev: np.ndarray):
     std = np.where((std > 0) & (std > 1e-12 * np.abs(mean)), std, 1.0)
     rms = np.sqrt((dv * dv).mean(axis=0))
     rms = np.where(rms > 0, rms, 1.0)
-    return mean, std, rms
+    if dq is None:
+        rc = rms.copy()
+    else:
+        cv = np.asarray(dq, dtype=np.float64).reshape(-1, 5) - dv
+        rc = np.sqrt((cv * cv).mean(axis=0))
+        rc = np.where(rc > 0, rc, 1.0)
+    return mean, std, rms, rc
 
 
 def features(q, dq_prev, stats, n_elem: int):
-    """Rows [ (Q_e - mean) / std , dQprev_e / rms ] per element."""
-    mean, std, rms = stats
+    """Rows [ (Q_e - mean) / std , dQprev_e / rp ] per element."""
+    mean, std, rms, _ = stats
     qv = np.asarray(q, dtype=np.float64).reshape(n_elem, -1, 5)
     dv = np.asarray(dq_prev, dtype=np.float64).reshape(n_elem, -1, 5)
     return np.concatenate([((qv - mean) / std).reshape(n_elem, -1), (dv / rms).reshape(n_elem, -1)],
@@ -111,12 +118,14 @@ def features(q, dq_prev, stats, n_elem: int):
 
 
 def target(dq, dq_prev, stats, n_elem: int):
-    _, _, rms = stats
+    """(dQ_e - dQprev_e) / rc: the correction to the previous increment."""
+    _, _, _, rms = stats
     d = (np.asarray(dq, dtype=np.float64) - np.asarray(dq_prev, dtype=np.float64)).reshape(n_elem, -1, 5)
     return (d / rms).reshape(n_elem, -1)
 
 
 def apply(dq_prev, y, stats, n_elem: int):
-    _, _, rms = stats
+    """dQprev_e + rc y_e."""
+    _, _, _, rms = stats
     dv = np.asarray(dq_prev, dtype=np.float64).reshape(n_elem, -1, 5)
     return (dv + rms * np.asarray(y, dtype=np.float64).reshape(n_elem, -1, 5)).reshape(-1)

@@ -61,7 +61,7 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("ir_sweeps", C.c_int32),
                 ("solver_used", C.c_int32), ("rel_res_S", C.c_double), ("rel_res_full", C.c_double),
-                ("guess_rejected", C.c_int32)]
+                ("guess_rejected", C.c_int32), ("rel_res_guess", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -121,7 +121,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_mlp_adam": (i32, [vp, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, i32]),
         "scdg_mlp_mse": (i32, [vp, vp, vp, i64, vp, vp]),
         "scdg_mlp_gather": (i32, [vp, vp, i32, vp, i32, vp]),
-        "scdg_guess_stats": (i32, [vp, vp, vp, i64, vp]),
+        "scdg_guess_stats": (i32, [vp, vp, vp, vp, i64, vp]),
         "scdg_guess_features": (i32, [vp, vp, vp, vp, i32, vp]),
         "scdg_guess_target": (i32, [vp, vp, vp, vp, i32, vp]),
         "scdg_guess_apply": (i32, [vp, vp, vp, vp, i32, vp]),

@@ -235,10 +235,11 @@ __global__ void sum_final_kernel(const double *__restrict__ partial, int n, int 
 
 // Field statistics in two passes (the second sums squared deviations from the
 // mean, which avoids the cancellation of E[q^2] - E[q]^2).  Pass 1 sums q_v and
-// dq_v^2, pass 2 sums (q_v - mean_v)^2; each block writes its partial sums.
-__global__ void stats_partial_kernel(const double *__restrict__ q, const double *__restrict__ dq,
-                                     const double *__restrict__ mean, int64_t n_nodes,
-                                     double *__restrict__ partial) {
+// dqp_v^2 (dqp: previous increment); pass 2 sums (q_v - mean_v)^2 and, when the
+// increment dq is given, (dq_v - dqp_v)^2.  Each block writes its partial sums.
+__global__ void stats_partial_kernel(const double *__restrict__ q, const double *__restrict__ dqp,
+                                     const double *__restrict__ dq, const double *__restrict__ mean,
+                                     int64_t n_nodes, double *__restrict__ partial) {
   __shared__ double red[10][256];
   double s[10];
 #pragma unroll
@@ -247,11 +248,15 @@ __global__ void stats_partial_kernel(const double *__restrict__ q, const double 
        i += (int64_t)gridDim.x * blockDim.x) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
+      const double b = dqp[i * 5 + v];
       if (mean) {
         const double a = q[i * 5 + v] - mean[v];
         s[v] += a * a;
+        if (dq) {
+          const double c = dq[i * 5 + v] - b;
+          s[5 + v] += c * c;
+        }
       } else {
-        const double b = dq[i * 5 + v];
         s[v] += q[i * 5 + v];
         s[5 + v] += b * b;
       }
@@ -269,10 +274,11 @@ __global__ void stats_partial_kernel(const double *__restrict__ q, const double 
   if (threadIdx.x < 10) partial[(int64_t)blockIdx.x * 10 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// pass 1: stats = [mean, -, rms]; pass 2: stats[5..9] = std (a zero spread maps to 1,
-// as does a zero rms)
+// stats = [mean[5], std[5], rms_prev[5], rms_corr[5]].  Pass 1 fills mean and
+// rms_prev; pass 2 fills std and rms_corr (rms_prev when no increment is given).
+// A zero spread or root mean square maps to 1.
 __global__ void stats_final_kernel(const double *__restrict__ partial, int n_blocks, int64_t n_nodes,
-                                   int pass, double *__restrict__ stats) {
+                                   int pass, int have_dq, double *__restrict__ stats) {
   const int v = threadIdx.x;
   if (v >= 5) return;
   double s1 = 0.0, s2 = 0.0;
@@ -288,6 +294,8 @@ __global__ void stats_final_kernel(const double *__restrict__ partial, int n_blo
   } else {
     const double sd = sqrt(s1 / n);
     stats[5 + v] = (sd > 0.0 && sd > 1e-12 * fabs(stats[v])) ? sd : 1.0;
+    const double rc = sqrt(s2 / n);
+    stats[15 + v] = have_dq ? (rc > 0.0 ? rc : 1.0) : stats[10 + v];
   }
 }
 
@@ -307,20 +315,20 @@ __global__ void features_kernel(const double *__restrict__ q, const double *__re
   }
 }
 
-// t = (dq - dq_prev) / rms  (training target)
+// t = (dq - dq_prev) / rms_corr  (training target)
 __global__ void target_kernel(const double *__restrict__ dq, const double *__restrict__ dq_prev,
                               const double *__restrict__ stats, int64_t n, float *__restrict__ t) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    t[i] = (float)((dq[i] - dq_prev[i]) / stats[10 + (int)(i % 5)]);
+    t[i] = (float)((dq[i] - dq_prev[i]) / stats[15 + (int)(i % 5)]);
 }
 
-// dq = dq_prev + rms * y  (prediction)
+// dq = dq_prev + rms_corr * y  (prediction)
 __global__ void apply_kernel(const double *__restrict__ dq_prev, const float *__restrict__ y,
                              const double *__restrict__ stats, int64_t n, double *__restrict__ dq) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    dq[i] = dq_prev[i] + stats[10 + (int)(i % 5)] * (double)y[i];
+    dq[i] = dq_prev[i] + stats[15 + (int)(i % 5)] * (double)y[i];
 }
 
 __global__ void gather_rows_kernel(const float *__restrict__ src, int width, const int32_t *__restrict__ idx,
@@ -521,19 +529,19 @@ scdg_status scdg_mlp_gather(scdg_mlp *m, const float *src, int32_t width, const 
   return hip_status(hipGetLastError());
 }
 
-scdg_status scdg_guess_stats(scdg_mlp *m, const double *q, const double *dq_prev, int64_t n_dof,
-                             double *stats) {
+scdg_status scdg_guess_stats(scdg_mlp *m, const double *q, const double *dq_prev, const double *dq,
+                             int64_t n_dof, double *stats) {
   if (!m || !q || !dq_prev || !stats || n_dof <= 0 || n_dof % 5) return SCDG_ERR_ARG;
   auto &c = m->c;
   const int64_t nodes = n_dof / 5;
   hipLaunchKernelGGL(scdg::stats_partial_kernel, dim3(scdg::kRedBlocks), dim3(256), 0, c.stream, q, dq_prev,
-                     nullptr, nodes, c.red);
+                     nullptr, nullptr, nodes, c.red);
   hipLaunchKernelGGL(scdg::stats_final_kernel, dim3(1), dim3(64), 0, c.stream, c.red, scdg::kRedBlocks, nodes,
-                     1, stats);
+                     1, 0, stats);
   hipLaunchKernelGGL(scdg::stats_partial_kernel, dim3(scdg::kRedBlocks), dim3(256), 0, c.stream, q, dq_prev,
-                     stats, nodes, c.red);
+                     dq, stats, nodes, c.red);
   hipLaunchKernelGGL(scdg::stats_final_kernel, dim3(1), dim3(64), 0, c.stream, c.red, scdg::kRedBlocks, nodes,
-                     2, stats);
+                     2, dq ? 1 : 0, stats);
   return hip_status(hipGetLastError());
 }
 

@@ -249,6 +249,7 @@ scdg_status gmres(Plan &p, const double *bs, double *x, const double *x0, const 
   double beta2;
   ST_TRY(norm2sq(p, r, n, &beta2));
   double beta = std::sqrt(beta2);
+  if (info.rel_res_guess < 0) info.rel_res_guess = x0 ? beta / bnorm : 1.0;
   if (x0 && !(beta <= bnorm)) {
     // the guess is worse than none (or not finite): start from zero instead
     info.guess_rejected = 1;
@@ -352,6 +353,12 @@ scdg_status dense_solve(Plan &p, const double *bs, double *x) {
   if (x != bs) HIP_TRY(hipMemcpyAsync(x, bs, sizeof(double) * p.n1, hipMemcpyDeviceToDevice, p.stream));
   HIP_TRY(launch_dense_solve(p.s_dense, (int32_t)p.n1, p.s_piv, x, p.stream));
   return SCDG_OK;
+}
+
+// a solve that never looked at a guess reports a guess residual of 1
+scdg_solve_info finish_info(scdg_solve_info inf) {
+  if (inf.rel_res_guess < 0) inf.rel_res_guess = 1.0;
+  return inf;
 }
 
 void defaults(scdg_solve_opts &o) {
@@ -865,9 +872,10 @@ scdg_status scdg_solve_condensed(scdg_plan *pl, const double *bs, double *qb, co
   defaults(opts);
   if (opts.restart > 63) return SCDG_ERR_ARG;
   scdg_solve_info inf{};
+  inf.rel_res_guess = -1.0;
   inf.rel_res_full = -1.0;
   scdg_status st = solve_condensed_impl(p, bs, qb, x0, opts, inf);
-  if (info) *info = inf;
+  if (info) *info = finish_info(inf);
   if (st == SCDG_OK) ST_TRY(sync(p));
   return st;
 }
@@ -906,12 +914,13 @@ scdg_status scdg_solve(scdg_plan *pl, const double *b, double *dq, const double 
   defaults(opts);
   if (opts.restart > 63) return SCDG_ERR_ARG;
   scdg_solve_info inf{};
+  inf.rel_res_guess = -1.0;
   inf.rel_res_full = -1.0;
   double bn2;
   ST_TRY(norm2sq(p, b, p.n_dof, &bn2));
   if (!std::isfinite(bn2)) {
     p.last_error = "non-finite right-hand side";
-    if (info) *info = inf;
+    if (info) *info = finish_info(inf);
     return SCDG_ERR_NONFINITE;
   }
   const double bnorm = std::sqrt(bn2);
@@ -930,7 +939,7 @@ scdg_status scdg_solve(scdg_plan *pl, const double *b, double *dq, const double 
     ST_TRY(condense_rhs_impl(p, rhs, p.w_bs));
     scdg_status s1 = solve_condensed_impl(p, p.w_bs, p.w_qb, sweep == 0 ? guess : nullptr, opts, inf);
     if (s1 != SCDG_OK && s1 != SCDG_ERR_NOCONV) {
-      if (info) *info = inf;
+      if (info) *info = finish_info(inf);
       return s1;
     }
     if (s1 == SCDG_ERR_NOCONV) st = s1;
@@ -944,7 +953,7 @@ scdg_status scdg_solve(scdg_plan *pl, const double *b, double *dq, const double 
     inf.rel_res_full = rel;
     if (!std::isfinite(rel)) {
       p.last_error = "non-finite full-system residual";
-      if (info) *info = inf;
+      if (info) *info = finish_info(inf);
       return SCDG_ERR_NONFINITE;
     }
     if (rel <= opts.ir_tol || bnorm == 0.0) {
@@ -956,7 +965,7 @@ scdg_status scdg_solve(scdg_plan *pl, const double *b, double *dq, const double 
     HIP_TRY(hipMemcpyAsync(p.w_vec, p.w_r, sizeof(double) * p.n_dof, hipMemcpyDeviceToDevice, p.stream));
     rhs = p.w_vec;
   }
-  if (info) *info = inf;
+  if (info) *info = finish_info(inf);
   if (st == SCDG_OK && rel > opts.ir_tol) {
     p.last_error = "iterative refinement did not reach ir_tol";
     st = SCDG_ERR_NOCONV;

@@ -48,13 +48,18 @@ class Mlp:
             off += fi * fo + fo
         return out
 
-    def init_params(self, seed: int, device="cuda") -> torch.Tensor:
-        """Glorot-uniform weights, zero biases, from numpy's seeded PCG64 (host)."""
+    def init_params(self, seed: int, device="cuda", zero_output: bool = False) -> torch.Tensor:
+        """Glorot-uniform weights, zero biases, from numpy's seeded PCG64 (host);
+        zero_output leaves the output layer at zero, so the untrained network
+        predicts a zero correction."""
         rng = np.random.default_rng(seed)
         w = np.zeros(self.n_params, dtype=np.float32)
-        for off, fi, fo, _ in self.layer_slices():
+        lay = self.layer_slices()
+        for i, (off, fi, fo, _) in enumerate(lay):
             a = np.sqrt(6.0 / (fi + fo))
-            w[off:off + fi * fo] = rng.uniform(-a, a, fi * fo).astype(np.float32)
+            vals = rng.uniform(-a, a, fi * fo).astype(np.float32)
+            if not (zero_output and i == len(lay) - 1):
+                w[off:off + fi * fo] = vals
         return torch.tensor(w, device=device)
 
     def _ok(self, st, where):
@@ -108,11 +113,11 @@ class Mlp:
         return dst
 
     # ---------------------------------------------------------------- DG maps
-    def guess_stats(self, q, dq_prev, stats=None):
+    def guess_stats(self, q, dq_prev, dq=None, stats=None):
         if stats is None:
-            stats = torch.empty(15, dtype=torch.float64, device=q.device)
-        self._ok(self.lib.scdg_guess_stats(self.handle, _ptr(q), _ptr(dq_prev), q.numel(), _ptr(stats)),
-                 "scdg_guess_stats")
+            stats = torch.empty(20, dtype=torch.float64, device=q.device)
+        self._ok(self.lib.scdg_guess_stats(self.handle, _ptr(q), _ptr(dq_prev), _ptr(dq), q.numel(),
+                                           _ptr(stats)), "scdg_guess_stats")
         return stats
 
     def features(self, q, dq_prev, stats, n_elem: int, x=None):

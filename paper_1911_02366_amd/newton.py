@@ -1,0 +1,247 @@
+"""Backward-Euler time stepping by Newton's method on the condensed system,
+with an optional learned initial guess.
+
+Each implicit step solves R(Q) = M (Q - Q_s)/dt + H(Q) = 0 (paper, eq.
+ImplicitDisc and eq. NeqtonEq) by Newton iterations A dQ = -R(Q~) (eq.
+NewtonLinSys1), where A is the Jacobian at the start of the step (it is
+refreshed once per step and kept for the step's later iterations), every
+linear system is solved by the statically condensed GMRES of the library
+(Section 3), and R is evaluated by the device residual kernels.  The step
+stops when ||R|| <= newton_tol ||R(Q_s)||.  With `forcing`, each linear
+solve is taken only to the relative tolerance that target needs
+(0.5 newton_tol ||R(Q_s)|| / ||R(Q~)||, clipped to [lin_tol, 0.1]), an
+inexact-Newton choice in the spirit of Eisenstat and Walker.  The Jacobian
+itself comes from a caller-supplied function of the state, returning device
+blocks in the layout of scdg_assemble.
+
+The learned guess (an addition; the paper has no learned component) is a
+per-element network trained on the solver's own (state, previous increment,
+increment) triples.  Its prediction enters either as the GMRES initial guess
+of the step's first linear solve (mode "gmres", boundary part only, dropped
+by the library when worse than zero) or as the Newton starting point (mode
+"newton", dropped when R at the predicted state exceeds R at Q_s).  The
+Newton stop test is the same in every mode, so every step converges to the
+same FP64 residual with or without the network.
+
+Host orchestration only: every arithmetic step runs in libscdg.so.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from .dg import DgResidual
+from .mlp import Mlp
+from .plan import Plan
+
+
+class ImplicitStepper:
+    def __init__(self, structure: dict, k_elem: int, order: int, mach: float, reynolds: float, dt: float,
+                 jacobian, lin_tol: float = 1e-10, newton_tol: float = 1e-8, max_newton: int = 10,
+                 restart: int = 30, precond: int = 1, precision: str = "fp64", autotune: bool = True,
+                 forcing: bool = True):
+        self.plan = Plan.from_structure(structure)
+        self.dg = DgResidual(k_elem, order, mach=mach, reynolds=reynolds)
+        self.dt, self.jacobian = dt, jacobian
+        self.lin_tol, self.newton_tol, self.max_newton = lin_tol, newton_tol, max_newton
+        self.restart, self.precond, self.precision = restart, precond, precision
+        self._tune = autotune
+        self.forcing = forcing
+        self._blocks = None
+        self.n_elem = len(structure["order"])
+
+    def prepare(self, q_s: torch.Tensor) -> float:
+        """Jacobian at q_s, factor and condense; returns the factor+condense seconds."""
+        blk = self.jacobian(q_s)
+        self._blocks = blk                       # the plan borrows these until the next assemble
+        self.plan.assemble(blk["aii"], blk["aib"], blk["abi"], blk["bb_val"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.plan.factor(self.precision)
+        if self._tune:
+            self.plan.autotune()
+            self._tune = False
+        self.plan.condense()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def solve_step(self, q_s: torch.Tensor, guess: torch.Tensor | None = None, mode: str = "gmres"):
+        """Newton iterations of one step from a prepared Jacobian; returns (q, info)."""
+        inv_dt = 1.0 / self.dt
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = self.dg.residual(q_s, q_s, inv_dt)
+        r0 = float(torch.linalg.vector_norm(r))
+        q = q_s.clone()
+        rnorm = r0
+        rejected = 0
+        if guess is not None and mode == "newton":
+            q_try = q_s + guess
+            r_try = self.dg.residual(q_try, q_s, inv_dt)
+            n_try = float(torch.linalg.vector_norm(r_try))
+            if n_try < r0:
+                q, r, rnorm = q_try, r_try, n_try
+            else:
+                rejected = 1
+        gmres_iters, first_iters, newton, guess_res = 0, None, 0, 1.0
+        while rnorm > self.newton_tol * r0 and newton < self.max_newton:
+            x0 = guess if (guess is not None and mode == "gmres" and newton == 0) else None
+            tol = self.lin_tol
+            if self.forcing:
+                # inexact Newton: solve only as far as the step's target needs
+                tol = min(0.1, max(self.lin_tol, 0.5 * self.newton_tol * r0 / rnorm))
+            if self.precision == "fp32":
+                ir = dict(ir_tol=tol, ir_max=10)
+            else:
+                ir = dict(ir_tol=1.0, ir_max=1)     # FP64 factors: the GMRES tolerance decides
+            dq, info = self.plan.solve(-r, x0=x0, solver="gmres", tol=tol, restart=self.restart,
+                                       precond=self.precond, check=False, **ir)
+            if info["status"] not in (0,):
+                raise RuntimeError(f"condensed solve failed: {info}")
+            if x0 is not None and info["guess_rejected"]:
+                rejected = 1
+            gmres_iters += info["iters"]
+            if first_iters is None:
+                first_iters = info["iters"]
+                guess_res = info["rel_res_guess"]
+            q += dq
+            r = self.dg.residual(q, q_s, inv_dt)
+            rnorm = float(torch.linalg.vector_norm(r))
+            newton += 1
+        torch.cuda.synchronize()
+        return q, dict(newton=newton, gmres=gmres_iters, first_gmres=first_iters or 0,
+                       rel_res=rnorm / r0 if r0 > 0 else 0.0, guess_rejected=rejected,
+                       guess_res=guess_res,
+                       seconds=time.perf_counter() - t0, converged=rnorm <= self.newton_tol * r0)
+
+    def close(self):
+        self.plan.close()
+        self.dg.close()
+
+
+class LearnedGuess:
+    """Training set, network and optimizer state of the learned initial guess.
+
+    Scales change by orders of magnitude over a run (an initial transient
+    decays), so every step is normalized by its own field statistics: the
+    features by the step's mean/std of Q and rms of dQprev, the target (the
+    correction dQ - dQprev) by the rms rc of that step's correction.  At
+    prediction time the correction of the step is not known yet; the rms of
+    the last known correction stands in for it.  A shrinkage factor alpha in
+    [0, 1], fitted by least squares on the hold-out step, scales the learned
+    correction (alpha = 0 reproduces the previous increment)."""
+
+    def __init__(self, n_elem: int, dofs_per_elem: int, capacity: int, hidden: int = 256, layers: int = 2,
+                 seed: int = 0, batch: int = 1024, device="cuda"):
+        self.n_elem, self.dpe = n_elem, dofs_per_elem
+        self.batch = batch
+        self.net = Mlp(2 * dofs_per_elem, hidden, layers, dofs_per_elem, max_batch=max(n_elem, batch))
+        self.w = self.net.init_params(seed, device, zero_output=True)
+        self.m1 = torch.zeros_like(self.w)
+        self.m2 = torch.zeros_like(self.w)
+        self.adam_step = 0
+        self.rng = np.random.default_rng(seed + 1)
+        self.alpha = 1.0
+        self.capacity = capacity            # number of stored steps
+        self.x = torch.empty(capacity * n_elem * 2 * dofs_per_elem, dtype=torch.float32, device=device)
+        self.t = torch.empty(capacity * n_elem * dofs_per_elem, dtype=torch.float32, device=device)
+        self.count = 0                      # stored rows
+        self.dev = device
+
+    def correction_rms(self, q_s, dq_prev, dq):
+        """Per-variable rms of dq - dq_prev (5 device doubles)."""
+        return self.net.guess_stats(q_s, dq_prev, dq)[15:20].clone()
+
+    def record(self, q_s, dq_prev, dq):
+        """Add one step's (state, previous increment) -> increment samples."""
+        if self.count + self.n_elem > self.capacity * self.n_elem:
+            raise RuntimeError("training set is full")
+        stats = self.net.guess_stats(q_s, dq_prev, dq)
+        nx, nt = 2 * self.dpe, self.dpe
+        self.net.features(q_s, dq_prev, stats, self.n_elem,
+                          x=self.x[self.count * nx:(self.count + self.n_elem) * nx])
+        self.net.target(dq, dq_prev, stats, self.n_elem,
+                        t=self.t[self.count * nt:(self.count + self.n_elem) * nt])
+        self.count += self.n_elem
+
+    def train(self, epochs: int, lr: float = 1e-3, holdout_rows: int = 0):
+        """Adam on minibatches of a seeded permutation; returns per-epoch mean losses
+        (train) and the hold-out loss of the last `holdout_rows` stored rows (after
+        fitting alpha on them, when given)."""
+        n_train = self.count - holdout_rows
+        nx, nt = 2 * self.dpe, self.dpe
+        xb = torch.empty(self.batch * nx, dtype=torch.float32, device=self.dev)
+        tb = torch.empty(self.batch * nt, dtype=torch.float32, device=self.dev)
+        dy = torch.empty(self.batch * nt, dtype=torch.float32, device=self.dev)
+        loss = torch.empty(1, dtype=torch.float64, device=self.dev)
+        history = []
+        for _ in range(epochs):
+            perm = torch.tensor(self.rng.permutation(n_train).astype(np.int32), device=self.dev)
+            total, nb = 0.0, 0
+            for s in range(0, n_train - self.batch + 1, self.batch):
+                idx = perm[s:s + self.batch]
+                self.net.gather(self.x, nx, idx, self.batch, xb)
+                self.net.gather(self.t, nt, idx, self.batch, tb)
+                y = self.net.forward(self.w, xb, self.batch)
+                self.net.mse(y, tb, self.batch * nt, dy=dy, loss=loss)
+                dw = self.net.backward(self.w, xb, dy, self.batch)
+                self.adam_step += 1
+                self.net.adam(self.w, dw, self.m1, self.m2, lr=lr, step=self.adam_step)
+                total += float(loss)
+                nb += 1
+            history.append(total / max(nb, 1))
+        hold = None
+        if holdout_rows:
+            self.alpha = self.fit_alpha(n_train, self.count)
+            hold = self.loss_on(n_train, self.count)
+        return history, hold
+
+    def _sums(self, row0: int, row1: int):
+        """sum t^2, sum y^2 and sum t y over stored rows (from loss kernels)."""
+        nx, nt = 2 * self.dpe, self.dpe
+        loss = torch.empty(1, dtype=torch.float64, device=self.dev)
+        stt = syy = sty = 0.0
+        for s in range(row0, row1, self.batch):
+            b = min(self.batch, row1 - s)
+            n = b * nt
+            t = self.t[s * nt:(s + b) * nt]
+            y = self.net.forward(self.w, self.x[s * nx:(s + b) * nx], b)
+            zero = torch.zeros(n, dtype=torch.float32, device=self.dev)
+            lt = float(self.net.mse(t, zero, n, loss=loss)) * n
+            ly = float(self.net.mse(y, zero, n, loss=loss)) * n
+            lty = float(self.net.mse(y, t, n, loss=loss)) * n
+            stt, syy, sty = stt + lt, syy + ly, sty + 0.5 * (lt + ly - lty)
+        return stt, syy, sty
+
+    def fit_alpha(self, row0: int, row1: int) -> float:
+        _, syy, sty = self._sums(row0, row1)
+        return float(min(1.0, max(0.0, sty / syy))) if syy > 0 else 0.0
+
+    def loss_on(self, row0: int, row1: int, zero: bool = False) -> float:
+        """Mean squared error of alpha * y over stored rows [row0, row1); zero=True
+        scores the zero correction, i.e. the previous increment as the prediction."""
+        stt, syy, sty = self._sums(row0, row1)
+        n = (row1 - row0) * self.dpe
+        if zero:
+            return stt / n
+        a = self.alpha
+        return (stt - 2 * a * sty + a * a * syy) / n
+
+    def predict(self, q_s, dq_prev, rc_prev):
+        """Predicted increment of the step from q_s (natural DOF order); rc_prev is
+        the rms of the last known correction (see correction_rms)."""
+        stats = self.net.guess_stats(q_s, dq_prev)
+        stats[15:20] = self.alpha * rc_prev
+        x = self.net.features(q_s, dq_prev, stats, self.n_elem)
+        y = torch.empty(self.n_elem * self.dpe, dtype=torch.float32, device=self.dev)
+        mb = self.net.max_batch
+        nx, nt = 2 * self.dpe, self.dpe
+        for s in range(0, self.n_elem, mb):
+            b = min(mb, self.n_elem - s)
+            self.net.forward(self.w, x[s * nx:(s + b) * nx], b, y[s * nt:(s + b) * nt])
+        return self.net.apply(dq_prev, y, stats, self.n_elem)
+
+    def close(self):
+        self.net.close()

@@ -115,10 +115,12 @@ def test_guess_maps_match_oracle():
     dq_prev = 1e-4 * rng.standard_normal(n_elem * dpe)
     dq = dq_prev * (1 + 0.01 * rng.standard_normal(n_elem * dpe))
     qd, dpd, dqd = (torch.tensor(a, device=DEV) for a in (q, dq_prev, dq))
-    stats = net.guess_stats(qd, dpd)
-    mean, std, rms = om.field_stats(q, dq_prev)
-    np.testing.assert_allclose(to_np(stats), np.concatenate([mean, std, rms]), rtol=1e-12, atol=0)
-    so = (to_np(stats)[:5], to_np(stats)[5:10], to_np(stats)[10:])   # same statistics on both sides
+    stats = net.guess_stats(qd, dpd, dqd)
+    np.testing.assert_allclose(to_np(stats), np.concatenate(om.field_stats(q, dq_prev, dq)), rtol=1e-12, atol=0)
+    s_np = to_np(net.guess_stats(qd, dpd))            # without dq: rc = rp
+    np.testing.assert_array_equal(s_np[15:], s_np[10:15])
+    sv = to_np(stats)
+    so = (sv[:5], sv[5:10], sv[10:15], sv[15:])        # the same statistics on both sides
     x = to_np(net.features(qd, dpd, stats, n_elem))
     np.testing.assert_array_equal(x, om.features(q, dq_prev, so, n_elem).astype(np.float32).reshape(-1))
     t = to_np(net.target(dqd, dpd, stats, n_elem))

@@ -119,6 +119,18 @@ def build_case(k_elem: int, order: int, reynolds: float, dt: float, mach: float 
                 q_state=q, parts=parts if keep_parts else None)
 
 
+def jacobian_blocks(q: torch.Tensor, mesh: Mesh, prm: FlowParams, dt: float, chunk: int | None = None) -> dict:
+    """Backward-Euler Jacobian A = M/dt + dH/dQ at state q (natural DOF order or
+    mesh layout, on q's device) as per-element blocks: aii, aib, abi, bb_val."""
+    q = q.reshape(mesh.shape())
+    parts = JacobianParts(q, mesh, prm, dt)
+    if chunk is None:
+        per_elem = (mesh.p ** 3 * 5) ** 2 * 8
+        chunk = max(1, min(mesh.n_elem, int(2e9 // per_elem)))
+    blk = partition(parts, chunk=chunk)
+    return dict(aii=blk["aii"], aib=blk["aib"], abi=blk["abi"], bb_val=blk["bb_val"])
+
+
 def named_case(name: str, device="cpu", seed: int = 0, **kw) -> Case:
     cfg = dict(WORKLOADS[name])
     cfg.update(kw)
