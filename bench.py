@@ -230,6 +230,8 @@ def main() -> int:
     ap.add_argument("--no-fp32-variant", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 2 GiB FP64 buffer three times (HBM counter calibration)")
+    ap.add_argument("--inverse-mode", choices=["auto", "single", "blocked"], default="auto",
+                    help="form of the batched inverse (auto: blocked above n_i = 320)")
     ap.add_argument("--learned-guess", action="store_true",
                     help="run the learned-initial-guess time-stepping experiment instead")
     ap.add_argument("--lg-workload", default="tgv_n4_k16")
@@ -275,6 +277,7 @@ def main() -> int:
     torch.cuda.synchronize()
     b = case.rhs
     plan = Plan.from_structure(case.structure())
+    plan.set_inverse_mode(args.inverse_mode)
     plan.assemble(case.aii, case.aib, case.abi, case.bb_val)
     dq = torch.empty(case.n_dof, dtype=torch.float64, device=dev)
 
@@ -364,6 +367,7 @@ def main() -> int:
                        "autotune_ms_x": {k: round(v, 3) for k, v in tuning["ms_x"].items()}},
         "gmres_iters_per_step": sum(i["iters"] for i in infos) / len(infos),
         "a_bb_blocks": {"folded": plan.n_folded, "remainder": plan.n_remainder},
+        "inverse_form": plan.inverse_mode_used(),
         "ir_sweeps_per_step": sum(i["ir_sweeps"] for i in infos) / len(infos),
     }
     if worst > 1e-8:

@@ -132,6 +132,13 @@ scdg_status scdg_assemble(scdg_plan *p, const double *aii, const double *aib,
  * FP64 or FP32.  A zero pivot is recorded per element (see scdg_factor_info)
  * and reported as SCDG_ERR_SINGULAR by scdg_condense. */
 scdg_status scdg_factor(scdg_plan *p, scdg_precision prec);
+/* Form of the batched inverse: 0 automatic (blocked above n_i = 320),
+ * 1 one workgroup per element for the whole elimination, 2 blocked: outer
+ * panels of 128 columns whose update of the rest of the block is a batched
+ * matrix-core GEMM.  Both forms take the same pivots (same elimination).
+ * scdg_get_inverse_mode reports the form used by the last scdg_factor (0 before). */
+scdg_status scdg_set_inverse_mode(scdg_plan *p, int32_t mode);
+scdg_status scdg_get_inverse_mode(const scdg_plan *p, int32_t *mode_used);
 /* First singular element (or -1) and its LAPACK-style info (1-based step). */
 scdg_status scdg_factor_info(scdg_plan *p, int64_t *first_bad_elem, int32_t *info);
 

@@ -13,6 +13,8 @@ namespace scdg {
 
 constexpr int kNvar = 5;
 constexpr int kMaxOrder = 7;
+constexpr int kGjOuter = 128;        // outer panel width of the blocked Gauss-Jordan inverse
+constexpr int kGjAutoBlocked = 320;  // automatic choice: blocked form above this n_i
 
 // One GEMM problem of a batched launch: C = alpha A B + beta C, row-major with
 // leading dimensions; offsets are element offsets into the three base arrays.
@@ -35,7 +37,7 @@ struct GemvDesc {
 };
 
 // GEMM tile configurations (rows x columns of C per workgroup)
-enum { kGemm64x64 = 0, kGemm64x128 = 1, kGemm128x128 = 2, kGemmConfigs = 7 };
+enum { kGemm64x64 = 0, kGemm64x128 = 1, kGemm128x128 = 2, kGemm128x128w8 = 3, kGemmConfigs = 7 };
 
 template <typename T>
 struct DevBuf {
@@ -109,6 +111,21 @@ struct Plan {
   double *pc_blk = nullptr;  // [n_bnodes * 25] inverse 5x5 diagonal blocks of S
   size_t cap_ainv = 0, cap_x = 0, cap_s = 0;  // bytes allocated
 
+  // blocked Gauss-Jordan inverse (outer panels of kGjOuter columns)
+  int inverse_mode = 0;            // 0 automatic, 1 one kernel per element, 2 blocked
+  int inverse_used = 0;            // form used by the last scdg_factor (1 or 2)
+  int64_t sum_ni = 0;
+  int64_t *d_gj_voff = nullptr;    // [n_elem] exclusive prefix of n_i
+  int32_t *d_gj_piv = nullptr;     // [sum n_i] pivot row of each column
+  unsigned char *d_gj_flag = nullptr;  // [sum n_i] row already used as a pivot
+  void *gj_pbuf = nullptr, *gj_rbuf = nullptr;  // [sum n_i * kGjOuter] each
+  size_t cap_gj = 0;
+  GemmDesc *d_gj_desc = nullptr;   // per outer panel, the update GEMMs W += P R
+  int32_t *d_gj_tiles = nullptr;
+  std::vector<int64_t> gj_desc_off, gj_tile_off;
+  std::vector<int32_t> gj_ntiles;
+  int gj_cfg = -1;                 // tile configuration the lists were built for
+
   // dense S path
   double *s_dense = nullptr;
   int32_t *s_piv = nullptr;
@@ -140,6 +157,7 @@ struct Plan {
 
 // ---- kernel launchers (implemented in the .hip files) ----
 hipError_t launch_gj_inverse(Plan &p, void *work, void *out, bool fp32);
+hipError_t launch_gj_inverse_blocked(Plan &p, void *work, void *out, bool fp32);
 bool gj_supported(int max_n, bool fp32);
 hipError_t launch_cast_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, size_t n, hipStream_t s);

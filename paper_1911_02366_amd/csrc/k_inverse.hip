@@ -22,6 +22,8 @@
 // The first panel reads A_ii directly (no separate copy).  Flops: 2 n^3 per
 // element.  A zero or non-finite pivot is recorded LAPACK-style (info = column
 // + 1) and replaced by 1 so the launch always completes.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "mfma.hpp"
 
@@ -48,6 +50,207 @@ size_t gj_lds_bytes(int max_n) {
          sizeof(int) * 2 * (size_t)rp + (size_t)rp;
 }
 
+// Shared memory of one element's workgroup: the panel (all rows x NB columns),
+// a chunk of the panel's pivot rows, the parked pivot rows, pivot bookkeeping.
+template <typename T, int NB>
+struct GjSmem {
+  T *pnl;             // [rp][PS]
+  T *rl;              // [NB][kRStride]
+  T *pend_buf;        // [2][NB] parked pivot rows
+  int *piv;           // [rp] pivot row of column k (single-kernel form)
+  int *qinv;          // [rp] column whose pivot row is m
+  unsigned char *inpanel;  // [rp] row is a pivot row of the current panel
+  __device__ GjSmem(unsigned char *smem, int rp) {
+    pnl = reinterpret_cast<T *>(smem);
+    rl = pnl + (size_t)rp * panel_stride<T>(NB);
+    pend_buf = rl + NB * kRStride;
+    piv = reinterpret_cast<int *>(pend_buf + 2 * NB);
+    qinv = piv + rp;
+    inpanel = reinterpret_cast<unsigned char *>(qinv + rp);
+  }
+};
+
+// Eliminate the panel held in LDS (columns kb .. kb + nbw - 1 of the matrix):
+// for each column, the pivot is the largest |a| among rows not yet used
+// (lowest row on ties); the pivot row is scaled and the column eliminated from
+// every other row (Gauss-Jordan).  One barrier per column: a pivot row is read
+// by every thread right after the barrier, so its owner parks the scaled row in
+// a side buffer (alternating by column parity) and writes it back after the
+// next column's barrier, applying that column's elimination.  piv (LDS or
+// global) receives the pivot row of each column; used[] marks the rows this
+// thread owns that have served as pivots.
+template <typename T, int NB>
+__device__ void gj_eliminate(GjSmem<T, NB> &sm, int n, int kb, int nbw, bool (&used)[kRowsPerThread],
+                             int *piv, unsigned char *flags, int &my_info, double (*red_v)[kWaves],
+                             int (*red_i)[kWaves]) {
+  constexpr int PS = panel_stride<T>(NB);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  T *pnl = sm.pnl;
+  bool pend_valid = false;
+  int pend_row = 0;
+  for (int c = 0; c < nbw; ++c) {
+    const int par = c & 1;
+    double best = -1.0;
+    int bi = n;
+#pragma unroll
+    for (int u = 0; u < kRowsPerThread; ++u) {
+      const int i = tid + u * kThreads;
+      if (i < n && !used[u]) {
+        const double v = fabs((double)pnl[i * PS + c]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_v[par][wid] = best;
+      red_i[par][wid] = bi;
+    }
+    __syncthreads();
+    best = red_v[par][0];
+    bi = red_i[par][0];
+#pragma unroll
+    for (int q = 1; q < kWaves; ++q)
+      if (red_v[par][q] > best || (red_v[par][q] == best && red_i[par][q] < bi)) {
+        best = red_v[par][q];
+        bi = red_i[par][q];
+      }
+    const int pr = bi < n ? bi : 0;
+    T d = pnl[pr * PS + c];
+    if (tid == 0) {
+      piv[kb + c] = pr;
+      sm.inpanel[pr] = 1;
+      if (flags) flags[pr] = 1;
+    }
+    if (!(d != T(0)) || !isfinite((double)d)) {
+      if (my_info == 0) my_info = kb + c + 1;
+      d = T(1);
+    }
+    const T inv_d = T(1) / d;
+    T sp[NB];   // scaled pivot row
+#pragma unroll
+    for (int j = 0; j < NB; ++j) sp[j] = (j == c) ? inv_d : pnl[pr * PS + j] * inv_d;
+    int handled = -1;   // the parked row of the previous column, written back here
+    if (pend_valid) {
+      const T *pend = sm.pend_buf + (par ^ 1) * NB;
+      const T f = pend[c];
+      T *row = pnl + pend_row * PS;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) row[j] = (j == c ? T(0) : pend[j]) - f * sp[j];
+      pend_valid = false;
+      handled = pend_row;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowsPerThread; ++u) {
+      const int i = tid + u * kThreads;
+      if (i >= n || i == handled) continue;
+      if (i == pr) {
+        used[u] = true;
+        pend_valid = true;
+        pend_row = i;
+        T *pend = sm.pend_buf + par * NB;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) pend[j] = sp[j];
+      } else {
+        T *row = pnl + i * PS;
+        const T f = row[c];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) row[j] = (j == c ? T(0) : row[j]) - f * sp[j];
+      }
+    }
+  }
+  __syncthreads();
+  if (pend_valid) {
+    const T *pend = sm.pend_buf + ((nbw - 1) & 1) * NB;
+    T *row = pnl + pend_row * PS;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) row[j] = pend[j];
+  }
+  __syncthreads();
+}
+
+// Rank-NB update of the columns [j_lo, j_hi) outside the panel:
+//   W[i][j] <- (i pivot row of this panel ? 0 : W[i][j]) + sum_c P[i][c] R[c][j]
+// with P the transformed panel (LDS) and R the panel's pivot rows read from src
+// (a0 in double on the first panel of the single-kernel form, else w).
+template <typename T, int NB>
+__device__ void gj_update(GjSmem<T, NB> &sm, const double *__restrict__ a0, bool first, T *__restrict__ w,
+                          int n, int kb, int nbw, const int *piv, int j_lo, int j_hi) {
+  using M = Mfma<T>;
+  constexpr int PS = panel_stride<T>(NB);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int rp = (n + 15) & ~15;
+  const int row_tiles = rp / 16;
+  const int ct = wid & 3;           // 16-column tile of the chunk
+  const int rt0 = wid >> 2;         // row tiles rt0, rt0 + 2, ...
+  for (int j0 = j_lo; j0 < j_hi; j0 += kChunk) {
+    for (int idx = tid; idx < NB * kChunk; idx += kThreads) {
+      const int c = idx / kChunk, jj = idx % kChunk, j = j0 + jj;
+      T v = T(0);
+      if (c < nbw && j < j_hi && !(j >= kb && j < kb + nbw)) {
+        const int64_t at = (int64_t)piv[kb + c] * n + j;
+        v = first ? (T)a0[at] : w[at];
+      }
+      sm.rl[c * kRStride + jj] = v;
+    }
+    __syncthreads();
+    const int jc = j0 + ct * 16 + (lane & 15);
+    const bool col_ok = jc < j_hi && !(jc >= kb && jc < kb + nbw);
+    for (int rtb = rt0; rtb < row_tiles; rtb += 2 * kGroup) {
+      T old[kGroup][4];
+      typename M::acc_t acc[kGroup];
+#pragma unroll
+      for (int g = 0; g < kGroup; ++g) {
+        const int rt = rtb + 2 * g;
+        acc[g] = M::zero();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rt * 16 + M::row(lane, r);
+          T v = T(0);
+          if (col_ok && rt < row_tiles && i < n && !sm.inpanel[i])
+            v = first ? (T)a0[(int64_t)i * n + jc] : w[(int64_t)i * n + jc];
+          old[g][r] = v;
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < NB; kk += 4) {
+        const T bv = sm.rl[(kk + (lane >> 4)) * kRStride + ct * 16 + (lane & 15)];
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+          const int rt = min(rtb + 2 * g, row_tiles - 1);
+          const T av = sm.pnl[(rt * 16 + (lane & 15)) * PS + kk + (lane >> 4)];
+          acc[g] = M::mma(av, bv, acc[g]);
+        }
+      }
+      if (col_ok) {
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+          const int rt = rtb + 2 * g;
+          if (rt >= row_tiles) continue;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = rt * 16 + M::row(lane, r);
+            if (i < n) w[(int64_t)i * n + jc] = old[g][r] + acc[g][r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Single-kernel form: one workgroup runs every panel of its element, updating
+// all columns after each panel, then reads the inverse out.
 template <typename T, int NB>
 __global__ __launch_bounds__(kThreads) void gj_inverse_kernel(const double *__restrict__ src,
                                                               T *__restrict__ work,
@@ -55,7 +258,6 @@ __global__ __launch_bounds__(kThreads) void gj_inverse_kernel(const double *__re
                                                               const int32_t *__restrict__ n_arr,
                                                               const int64_t *__restrict__ off_arr,
                                                               int32_t *__restrict__ info) {
-  using M = Mfma<T>;
   constexpr int PS = panel_stride<T>(NB);
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red_v[2][kWaves];
@@ -67,18 +269,13 @@ __global__ __launch_bounds__(kThreads) void gj_inverse_kernel(const double *__re
   const double *__restrict__ a0 = src + off;
   T *__restrict__ w = work + off;
   const int rp = (n + 15) & ~15;
-  T *pnl = reinterpret_cast<T *>(smem);           // [rp][PS]
-  T *rl = pnl + (size_t)rp * PS;                   // [NB][kRStride]
-  T *pend_buf = rl + NB * kRStride;                // [2][NB] parked pivot rows
-  int *piv = reinterpret_cast<int *>(pend_buf + 2 * NB);   // [rp] pivot row of column k
-  int *qinv = piv + rp;                            // [rp] column whose pivot row is m
-  unsigned char *inpanel = reinterpret_cast<unsigned char *>(qinv + rp);  // [rp]
+  GjSmem<T, NB> sm(smem, rp);
 
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x;
   bool used[kRowsPerThread];
 #pragma unroll
   for (int u = 0; u < kRowsPerThread; ++u) used[u] = false;
-  for (int i = tid; i < rp; i += kThreads) inpanel[i] = 0;
+  for (int i = tid; i < rp; i += kThreads) sm.inpanel[i] = 0;
   int my_info = 0;
 
   for (int kb = 0; kb < n; kb += NB) {
@@ -88,181 +285,164 @@ __global__ __launch_bounds__(kThreads) void gj_inverse_kernel(const double *__re
       const int i = idx / NB, c = idx % NB;
       T v = T(0);
       if (i < n && c < nbw) v = first ? (T)a0[(int64_t)i * n + c] : w[(int64_t)i * n + kb + c];
-      pnl[i * PS + c] = v;
+      sm.pnl[i * PS + c] = v;
     }
     __syncthreads();
-
-    // One barrier per column: a pivot row is read by every thread right after
-    // the barrier, so its owner parks the scaled row in a side buffer (LDS,
-    // alternating by column parity) and writes it back into the panel after the
-    // next column's barrier, applying that column's elimination.
-    bool pend_valid = false;
-    int pend_row = 0;
-    for (int c = 0; c < nbw; ++c) {
-      const int par = c & 1;
-      double best = -1.0;
-      int bi = n;
-#pragma unroll
-      for (int u = 0; u < kRowsPerThread; ++u) {
-        const int i = tid + u * kThreads;
-        if (i < n && !used[u]) {
-          const double v = fabs((double)pnl[i * PS + c]);
-          if (v > best) {
-            best = v;
-            bi = i;
-          }
-        }
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ov > best || (ov == best && oi < bi)) {
-          best = ov;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        red_v[par][wid] = best;
-        red_i[par][wid] = bi;
-      }
-      __syncthreads();
-      best = red_v[par][0];
-      bi = red_i[par][0];
-#pragma unroll
-      for (int q = 1; q < kWaves; ++q)
-        if (red_v[par][q] > best || (red_v[par][q] == best && red_i[par][q] < bi)) {
-          best = red_v[par][q];
-          bi = red_i[par][q];
-        }
-      const int pr = bi < n ? bi : 0;
-      T d = pnl[pr * PS + c];
-      if (tid == 0) {
-        piv[kb + c] = pr;
-        inpanel[pr] = 1;
-      }
-      if (!(d != T(0)) || !isfinite((double)d)) {
-        if (my_info == 0) my_info = kb + c + 1;
-        d = T(1);
-      }
-      const T inv_d = T(1) / d;
-      T sp[NB];   // scaled pivot row
-#pragma unroll
-      for (int j = 0; j < NB; ++j) sp[j] = (j == c) ? inv_d : pnl[pr * PS + j] * inv_d;
-      int handled = -1;   // the parked row of the previous column, written back here
-      if (pend_valid) {
-        const T *pend = pend_buf + (par ^ 1) * NB;
-        const T f = pend[c];
-        T *row = pnl + pend_row * PS;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) row[j] = (j == c ? T(0) : pend[j]) - f * sp[j];
-        pend_valid = false;
-        handled = pend_row;
-      }
-#pragma unroll
-      for (int u = 0; u < kRowsPerThread; ++u) {
-        const int i = tid + u * kThreads;
-        if (i >= n || i == handled) continue;
-        if (i == pr) {
-          used[u] = true;
-          pend_valid = true;
-          pend_row = i;
-          T *pend = pend_buf + par * NB;
-#pragma unroll
-          for (int j = 0; j < NB; ++j) pend[j] = sp[j];
-        } else {
-          T *row = pnl + i * PS;
-          const T f = row[c];
-#pragma unroll
-          for (int j = 0; j < NB; ++j) row[j] = (j == c ? T(0) : row[j]) - f * sp[j];
-        }
-      }
-    }
-    __syncthreads();
-    if (pend_valid) {
-      const T *pend = pend_buf + ((nbw - 1) & 1) * NB;
-      T *row = pnl + pend_row * PS;
-#pragma unroll
-      for (int j = 0; j < NB; ++j) row[j] = pend[j];
-    }
-    __syncthreads();
-
-    // rank-NB update of the columns outside the panel
-    const int row_tiles = rp / 16;
-    const int ct = wid & 3;           // 16-column tile of the chunk
-    const int rt0 = wid >> 2;         // row tiles rt0, rt0 + 2, ...
-    for (int j0 = 0; j0 < n; j0 += kChunk) {
-      for (int idx = tid; idx < NB * kChunk; idx += kThreads) {
-        const int c = idx / kChunk, jj = idx % kChunk, j = j0 + jj;
-        T v = T(0);
-        if (c < nbw && j < n && !(j >= kb && j < kb + nbw)) {
-          const int64_t at = (int64_t)piv[kb + c] * n + j;
-          v = first ? (T)a0[at] : w[at];
-        }
-        rl[c * kRStride + jj] = v;
-      }
-      __syncthreads();
-      const int jc = j0 + ct * 16 + (lane & 15);
-      const bool col_ok = jc < n && !(jc >= kb && jc < kb + nbw);
-      for (int rtb = rt0; rtb < row_tiles; rtb += 2 * kGroup) {
-        T old[kGroup][4];
-        typename M::acc_t acc[kGroup];
-#pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
-          const int rt = rtb + 2 * g;
-          acc[g] = M::zero();
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = rt * 16 + M::row(lane, r);
-            T v = T(0);
-            if (col_ok && rt < row_tiles && i < n && !inpanel[i])
-              v = first ? (T)a0[(int64_t)i * n + jc] : w[(int64_t)i * n + jc];
-            old[g][r] = v;
-          }
-        }
-#pragma unroll
-        for (int kk = 0; kk < NB; kk += 4) {
-          const T bv = rl[(kk + (lane >> 4)) * kRStride + ct * 16 + (lane & 15)];
-#pragma unroll
-          for (int g = 0; g < kGroup; ++g) {
-            const int rt = min(rtb + 2 * g, row_tiles - 1);
-            const T av = pnl[(rt * 16 + (lane & 15)) * PS + kk + (lane >> 4)];
-            acc[g] = M::mma(av, bv, acc[g]);
-          }
-        }
-        if (col_ok) {
-#pragma unroll
-          for (int g = 0; g < kGroup; ++g) {
-            const int rt = rtb + 2 * g;
-            if (rt >= row_tiles) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = rt * 16 + M::row(lane, r);
-              if (i < n) w[(int64_t)i * n + jc] = old[g][r] + acc[g][r];
-            }
-          }
-        }
-      }
-      __syncthreads();
-    }
-
+    gj_eliminate<T, NB>(sm, n, kb, nbw, used, sm.piv, nullptr, my_info, red_v, red_i);
+    gj_update<T, NB>(sm, a0, first, w, n, kb, nbw, sm.piv, 0, n);
     for (int idx = tid; idx < rp * NB; idx += kThreads) {
       const int i = idx / NB, c = idx % NB;
-      if (i < n && c < nbw) w[(int64_t)i * n + kb + c] = pnl[i * PS + c];
+      if (i < n && c < nbw) w[(int64_t)i * n + kb + c] = sm.pnl[i * PS + c];
     }
-    for (int c = tid; c < nbw; c += kThreads) inpanel[piv[kb + c]] = 0;
+    for (int c = tid; c < nbw; c += kThreads) sm.inpanel[sm.piv[kb + c]] = 0;
     __syncthreads();
   }
 
   // read the inverse out through the pivot permutation
-  for (int k = tid; k < n; k += kThreads) qinv[piv[k]] = k;
+  for (int k = tid; k < n; k += kThreads) sm.qinv[sm.piv[k]] = k;
   __syncthreads();
   T *__restrict__ o = out + off;
-  for (int64_t idx = tid; idx < (int64_t)n * n; idx += kThreads) {
-    const int k = (int)(idx / n), m = (int)(idx % n);
-    o[idx] = w[(int64_t)piv[k] * n + qinv[m]];
+  {
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int k = wave; k < n; k += kWaves) {
+      const T *__restrict__ row = w + (int64_t)sm.piv[k] * n;
+      for (int m = lane; m < n; m += 64) o[(int64_t)k * n + m] = row[sm.qinv[m]];
+    }
   }
   if (tid == 0) info[e] = my_info;
+}
+
+// ---------------------------------------------------------------------------
+// Blocked form for large blocks.  Columns are taken in outer panels of
+// kOuter; inside an outer panel, inner panels of NB columns are eliminated
+// by gj_panel_kernel, which updates only the outer panel's other columns.
+// The rest of the matrix then receives the outer panel's transformation at
+// once, as the rank-kOuter update of the same formula,
+//     W[i][j] <- (i pivot row of the outer panel ? 0 : W[i][j]) + sum_c P[i][c] R[c][j],
+// a batched GEMM (W += P R) after gj_outer_gather_kernel has copied the
+// transformed outer panel P, gathered its pivot rows R (zero inside the panel)
+// and cleared those rows outside it.  The composition of the inner steps is
+// the Gauss-Jordan transformation of the whole outer panel, so the result is
+// the same elimination as the single-kernel form (same pivots), with the bulk
+// of the flops in matrix-core GEMMs with K = kOuter.
+// ---------------------------------------------------------------------------
+constexpr int kOuter = kGjOuter;
+
+template <typename T>
+__global__ void gj_prepare_kernel(const double *__restrict__ src, T *__restrict__ work, int64_t total,
+                                  unsigned char *__restrict__ flags, int64_t n_rows, int32_t *__restrict__ info,
+                                  int n_elem) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    work[i] = (T)src[i];
+    if (i < n_rows) flags[i] = 0;
+    if (i < n_elem) info[i] = 0;
+  }
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void gj_panel_kernel(T *__restrict__ work, const int32_t *__restrict__ n_arr,
+                                                            const int64_t *__restrict__ off_arr,
+                                                            const int64_t *__restrict__ voff_arr,
+                                                            int32_t *__restrict__ piv_all,
+                                                            unsigned char *__restrict__ flags_all,
+                                                            int32_t *__restrict__ info, int kb, int ko) {
+  constexpr int PS = panel_stride<T>(NB);
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red_v[2][kWaves];
+  __shared__ int red_i[2][kWaves];
+  const int e = blockIdx.x;
+  const int n = n_arr[e];
+  if (kb >= n) return;
+  const int nbw = min(NB, n - kb);
+  T *__restrict__ w = work + off_arr[e];
+  int *piv = piv_all + voff_arr[e];
+  unsigned char *flags = flags_all + voff_arr[e];
+  const int rp = (n + 15) & ~15;
+  GjSmem<T, NB> sm(smem, rp);
+  const int tid = threadIdx.x;
+  bool used[kRowsPerThread];
+#pragma unroll
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int i = tid + u * kThreads;
+    used[u] = i < n ? flags[i] != 0 : true;
+  }
+  for (int i = tid; i < rp; i += kThreads) sm.inpanel[i] = 0;
+  for (int idx = tid; idx < rp * NB; idx += kThreads) {
+    const int i = idx / NB, c = idx % NB;
+    T v = T(0);
+    if (i < n && c < nbw) v = w[(int64_t)i * n + kb + c];
+    sm.pnl[i * PS + c] = v;
+  }
+  __syncthreads();
+  int my_info = 0;
+  gj_eliminate<T, NB>(sm, n, kb, nbw, used, piv, flags, my_info, red_v, red_i);
+  gj_update<T, NB>(sm, nullptr, false, w, n, kb, nbw, piv, ko, min(n, ko + kOuter));
+  for (int idx = tid; idx < rp * NB; idx += kThreads) {
+    const int i = idx / NB, c = idx % NB;
+    if (i < n && c < nbw) w[(int64_t)i * n + kb + c] = sm.pnl[i * PS + c];
+  }
+  if (tid == 0 && my_info != 0 && info[e] == 0) info[e] = my_info;
+}
+
+// P[i][c] = W[i][ko + c];  R[c][j] = W[p_c][j] outside the outer panel (0 inside),
+// and W[p_c][j] = 0 outside the outer panel.
+template <typename T>
+__global__ void gj_outer_gather_kernel(T *__restrict__ work, const int32_t *__restrict__ n_arr,
+                                       const int64_t *__restrict__ off_arr, const int64_t *__restrict__ voff_arr,
+                                       const int32_t *__restrict__ piv_all, T *__restrict__ pbuf,
+                                       T *__restrict__ rbuf, int ko) {
+  const int e = blockIdx.x;
+  const int n = n_arr[e];
+  if (ko >= n) return;
+  const int nbo = min(kOuter, n - ko);
+  T *__restrict__ w = work + off_arr[e];
+  const int32_t *piv = piv_all + voff_arr[e] + ko;
+  T *__restrict__ pb = pbuf + voff_arr[e] * kOuter;
+  T *__restrict__ rb = rbuf + voff_arr[e] * kOuter;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  // panel copy, a wave per row
+  for (int i = wave; i < n; i += waves)
+    for (int c = lane; c < nbo; c += 64) pb[(int64_t)i * kOuter + c] = w[(int64_t)i * n + ko + c];
+  // pivot rows, a wave per row (the panel columns themselves are not touched here)
+  for (int c = wave; c < nbo; c += waves) {
+    T *__restrict__ src = w + (int64_t)piv[c] * n;
+    T *__restrict__ dst = rb + (int64_t)c * n;
+    for (int j = lane; j < n; j += 64) {
+      if (j >= ko && j < ko + nbo) {
+        dst[j] = T(0);
+      } else {
+        dst[j] = src[j];
+        src[j] = T(0);
+      }
+    }
+  }
+}
+
+// A^-1[k][m] = W[p_k][q_m]
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gj_readout_kernel(const T *__restrict__ work, T *__restrict__ out,
+                                                              const int32_t *__restrict__ n_arr,
+                                                              const int64_t *__restrict__ off_arr,
+                                                              const int64_t *__restrict__ voff_arr,
+                                                              const int32_t *__restrict__ piv_all) {
+  __shared__ int pv[kRowsPerThread * kThreads];
+  __shared__ int qinv[kRowsPerThread * kThreads];
+  const int e = blockIdx.x;
+  const int n = n_arr[e];
+  const int32_t *piv = piv_all + voff_arr[e];
+  for (int k = threadIdx.x; k < n; k += kThreads) {
+    pv[k] = piv[k];
+    qinv[piv[k]] = k;
+  }
+  __syncthreads();
+  const T *__restrict__ w = work + off_arr[e];
+  T *__restrict__ o = out + off_arr[e];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = wave; k < n; k += kWaves) {
+    const T *__restrict__ row = w + (int64_t)pv[k] * n;
+    for (int m = lane; m < n; m += 64) o[(int64_t)k * n + m] = row[qinv[m]];
+  }
 }
 
 template <typename T, int NB>
@@ -285,6 +465,42 @@ hipError_t gj_dispatch(Plan &p, T *work, T *out) {
   return gj_launch<T, 8>(p, work, out);
 }
 
+template <typename T, int NB>
+hipError_t gj_blocked_run(Plan &p, T *work, T *out) {
+  const size_t lds = gj_lds_bytes<T, NB>(p.max_ni);
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(gj_panel_kernel<T, NB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  const int64_t total = p.off_ii[p.n_elem];
+  const int64_t grid = std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL((gj_prepare_kernel<T>), dim3((unsigned)grid), dim3(256), 0, p.stream, p.aii, work, total,
+                     p.d_gj_flag, p.sum_ni, p.d_info, p.n_elem);
+  T *pbuf = static_cast<T *>(p.gj_pbuf), *rbuf = static_cast<T *>(p.gj_rbuf);
+  for (int s = 0; s * kOuter < p.max_ni; ++s) {
+    const int ko = s * kOuter;
+    for (int kb = ko; kb < std::min(p.max_ni, ko + kOuter); kb += NB)
+      hipLaunchKernelGGL((gj_panel_kernel<T, NB>), dim3(p.n_elem), dim3(kThreads), lds, p.stream, work,
+                         p.d_inv_n, p.d_inv_off, p.d_gj_voff, p.d_gj_piv, p.d_gj_flag, p.d_info, kb, ko);
+    if (p.gj_ntiles[s] > 0) {
+      hipLaunchKernelGGL((gj_outer_gather_kernel<T>), dim3(p.n_elem), dim3(512), 0, p.stream, work,
+                         p.d_inv_n, p.d_inv_off, p.d_gj_voff, p.d_gj_piv, pbuf, rbuf, ko);
+      err = launch_gemm_batched(p.gj_cfg, p.d_gj_desc + p.gj_desc_off[s], p.d_gj_tiles + 3 * p.gj_tile_off[s],
+                                p.gj_ntiles[s], pbuf, rbuf, work, 1.0, 1.0, sizeof(T) == 4, p.stream);
+      if (err != hipSuccess) return err;
+    }
+  }
+  hipLaunchKernelGGL((gj_readout_kernel<T>), dim3(p.n_elem), dim3(kThreads), 0, p.stream, work, out, p.d_inv_n,
+                     p.d_inv_off, p.d_gj_voff, p.d_gj_piv);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gj_blocked_dispatch(Plan &p, T *work, T *out) {
+  if (gj_lds_bytes<T, 32>(p.max_ni) <= kLdsLimit) return gj_blocked_run<T, 32>(p, work, out);
+  if (gj_lds_bytes<T, 16>(p.max_ni) <= kLdsLimit) return gj_blocked_run<T, 16>(p, work, out);
+  return gj_blocked_run<T, 8>(p, work, out);
+}
+
 }  // namespace
 
 bool gj_supported(int max_n, bool fp32) {
@@ -296,6 +512,11 @@ bool gj_supported(int max_n, bool fp32) {
 hipError_t launch_gj_inverse(Plan &p, void *work, void *out, bool fp32) {
   if (fp32) return gj_dispatch<float>(p, static_cast<float *>(work), static_cast<float *>(out));
   return gj_dispatch<double>(p, static_cast<double *>(work), static_cast<double *>(out));
+}
+
+hipError_t launch_gj_inverse_blocked(Plan &p, void *work, void *out, bool fp32) {
+  if (fp32) return gj_blocked_dispatch<float>(p, static_cast<float *>(work), static_cast<float *>(out));
+  return gj_blocked_dispatch<double>(p, static_cast<double *>(work), static_cast<double *>(out));
 }
 
 }  // namespace scdg

@@ -431,6 +431,8 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.d_gx); dfree(p.d_gs); dfree(p.d_tiles_x); dfree(p.d_tiles_s);
   dfree(p.d_gv_inv); dfree(p.d_gv_abi); dfree(p.d_gv_aib); dfree(p.d_gv_s);
   dfree(p.d_rt_inv); dfree(p.d_rt_abi); dfree(p.d_rt_aib); dfree(p.d_rt_s);
+  dfree(p.d_gj_voff); dfree(p.d_gj_piv); dfree(p.d_gj_flag); dfree(p.gj_pbuf); dfree(p.gj_rbuf);
+  dfree(p.d_gj_desc); dfree(p.d_gj_tiles);
   dfree(p.ainv); dfree(p.ainv_work); dfree(p.xmat); dfree(p.sloc); dfree(p.aib_lo); dfree(p.abi_lo); dfree(p.diag_s);
   dfree(p.s_dense); dfree(p.s_piv); dfree(p.d_dense_info);
   dfree(p.w_z); dfree(p.w_t); dfree(p.w_bs); dfree(p.w_qb); dfree(p.w_r); dfree(p.w_dq); dfree(p.w_vec);
@@ -742,6 +744,77 @@ scdg_status scdg_assemble(scdg_plan *pl, const double *aii, const double *aib, c
   return SCDG_OK;
 }
 
+// Work lists and buffers of the blocked inverse: for every outer panel, one
+// GEMM W += P R per element whose block has columns outside that panel.
+scdg_status prepare_blocked_inverse(Plan &p) {
+  const int cfg = kGemm128x128w8;
+  if (!p.d_gj_voff) {
+    std::vector<int64_t> voff(p.n_elem);
+    int64_t acc = 0;
+    for (int e = 0; e < p.n_elem; ++e) {
+      voff[e] = acc;
+      acc += p.ni[e];
+    }
+    p.sum_ni = acc;
+    ST_TRY(upload(p, &p.d_gj_voff, voff));
+    ST_TRY(dalloc(p, &p.d_gj_piv, (size_t)std::max<int64_t>(1, acc)));
+    ST_TRY(dalloc(p, &p.d_gj_flag, (size_t)std::max<int64_t>(1, acc)));
+  }
+  const size_t need = sizeof(double) * (size_t)std::max<int64_t>(1, p.sum_ni) * kGjOuter;
+  if (need > p.cap_gj) {
+    dfree(p.gj_pbuf);
+    dfree(p.gj_rbuf);
+    p.cap_gj = 0;
+    ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.gj_pbuf), need));
+    ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.gj_rbuf), need));
+    p.cap_gj = need;
+  }
+  if (p.gj_cfg == cfg) return SCDG_OK;
+  std::vector<GemmDesc> all;
+  std::vector<int32_t> tiles;
+  p.gj_desc_off.clear();
+  p.gj_tile_off.clear();
+  p.gj_ntiles.clear();
+  int64_t voff = 0;
+  std::vector<int64_t> vo(p.n_elem);
+  for (int e = 0; e < p.n_elem; ++e) {
+    vo[e] = voff;
+    voff += p.ni[e];
+  }
+  for (int ko = 0; ko < p.max_ni; ko += kGjOuter) {
+    std::vector<GemmDesc> step;
+    for (int e = 0; e < p.n_elem; ++e) {
+      const int n = p.ni[e];
+      if (n <= kGjOuter || ko >= n) continue;   // nothing outside the outer panel
+      GemmDesc d{};
+      d.a_off = vo[e] * kGjOuter;
+      d.b_off = vo[e] * kGjOuter;
+      d.c_off = p.off_ii[e];
+      d.m = n;
+      d.n = n;
+      d.k = std::min(kGjOuter, n - ko);
+      d.lda = kGjOuter;
+      d.ldb = n;
+      d.ldc = n;
+      step.push_back(d);
+    }
+    std::vector<int32_t> t = xcd_tile_list(step, cfg);
+    p.gj_desc_off.push_back((int64_t)all.size());
+    p.gj_tile_off.push_back((int64_t)tiles.size() / 3);
+    p.gj_ntiles.push_back(step.empty() ? 0 : (int32_t)(t.size() / 3));
+    all.insert(all.end(), step.begin(), step.end());
+    if (!step.empty()) tiles.insert(tiles.end(), t.begin(), t.end());
+  }
+  dfree(p.d_gj_desc);
+  dfree(p.d_gj_tiles);
+  if (all.empty()) all.push_back(GemmDesc{});
+  if (tiles.empty()) tiles.assign(3, -1);
+  ST_TRY(upload(p, &p.d_gj_desc, all));
+  ST_TRY(upload(p, &p.d_gj_tiles, tiles));
+  p.gj_cfg = cfg;
+  return SCDG_OK;
+}
+
 scdg_status scdg_factor(scdg_plan *pl, scdg_precision prec) {
   if (!pl) return SCDG_ERR_ARG;
   Plan &p = pl->p;
@@ -764,12 +837,30 @@ scdg_status scdg_factor(scdg_plan *pl, scdg_precision prec) {
     ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.ainv_work), need));
     p.cap_ainv = need;
   }
+  const bool blocked = p.inverse_mode == 2 || (p.inverse_mode == 0 && p.max_ni > kGjAutoBlocked);
+  if (blocked) ST_TRY(prepare_blocked_inverse(p));
   {
     PhaseTimer tm(p, SCDG_PHASE_INVERSE);
-    HIP_TRY(launch_gj_inverse(p, p.ainv_work, p.ainv, fp32(p)));
+    if (blocked)
+      HIP_TRY(launch_gj_inverse_blocked(p, p.ainv_work, p.ainv, fp32(p)));
+    else
+      HIP_TRY(launch_gj_inverse(p, p.ainv_work, p.ainv, fp32(p)));
   }
+  p.inverse_used = blocked ? 2 : 1;
   p.state = 2;
   p.dense_factored = false;
+  return SCDG_OK;
+}
+
+scdg_status scdg_set_inverse_mode(scdg_plan *pl, int32_t mode) {
+  if (!pl || mode < 0 || mode > 2) return SCDG_ERR_ARG;
+  pl->p.inverse_mode = mode;
+  return SCDG_OK;
+}
+
+scdg_status scdg_get_inverse_mode(const scdg_plan *pl, int32_t *mode_used) {
+  if (!pl || !mode_used) return SCDG_ERR_ARG;
+  *mode_used = pl->p.inverse_used;
   return SCDG_OK;
 }
 

@@ -50,7 +50,8 @@ def fold_matrices(case, elems=None):
     lowest-numbered element whose coupling set holds both; otherwise it stays in
     the remainder.  Returns {e: F_e} for the requested elements (default all)."""
     n_e = case.n_elem
-    nb = case.n_bnodes // n_e
+    orders = np.asarray(case.order)
+    bnode_off = np.concatenate([[0], np.cumsum((orders + 1) ** 3 - (orders - 1) ** 3)])
     elems = range(n_e) if elems is None else elems
     c_sets = lambda e: case.c_node[case.c_ptr[e]:case.c_ptr[e + 1]]
     pos_cache = {}
@@ -64,14 +65,15 @@ def fold_matrices(case, elems=None):
     for e in range(n_e):
         for g in c_sets(e):
             holders.setdefault(int(g), []).append(e)
-    vals = to_np(case.bb_val)
+    vals = to_np(case.bb_val).reshape(-1, 5, 5)
     out = {}
     for e in elems:
-        f = np.zeros((case.n_c, case.n_c))
+        nc = 5 * int(case.c_ptr[e + 1] - case.c_ptr[e])
+        f = np.zeros((nc, nc))
         pe = pos(e)
         for g in c_sets(e):
             g = int(g)
-            owner = g // nb
+            owner = int(np.searchsorted(bnode_off, g, side="right") - 1)
             cands = sorted(holders[g], key=lambda x: (x != owner, x))
             for t in range(case.bb_rowptr[g], case.bb_rowptr[g + 1]):
                 h = int(case.bb_col[t])
