@@ -33,23 +33,27 @@ def algorithmic_work(case, plan_prec: str, n_rem: int) -> dict:
 
     The condensed product S x streams the element blocks T_e once, the A_bb
     remainder blocks (values + column index) once, and reads x / writes y."""
-    e, ni, nc = case.n_elem, case.n_i, case.n_c
+    import numpy as np
+    e = case.n_elem
+    ni = np.broadcast_to(np.asarray(case.n_i, dtype=np.int64), (e,)).astype(np.float64)
+    nc = np.broadcast_to(np.asarray(case.n_c, dtype=np.int64), (e,)).astype(np.float64)
     esz = 8 if plan_prec == "fp64" else 4
     nnzb = int(case.bb_rowptr[-1])
     n1, n2, ndof = case.n1, case.n2, case.n_dof
     bb_bytes = nnzb * 25 * 8 + nnzb * 4 + (case.n_bnodes + 1) * 8
+    t = lambda a: float(np.sum(a))
     return {
-        "inverse": {"flops": e * 2 * ni ** 3, "bytes": e * ni * ni * esz * 2},
-        "gemm_x": {"flops": e * 2 * ni * ni * nc, "bytes": e * (ni * ni + 2 * ni * nc) * esz},
-        "gemm_s": {"flops": e * 2 * nc * nc * ni, "bytes": e * (2 * ni * nc + nc * nc) * esz},
-        "schur_apply": {"flops": e * 2 * nc * nc + n_rem * 50,
-                        "bytes": e * nc * nc * esz + n_rem * (25 * 8 + 4) + 2 * n1 * 8},
-        "rhs": {"flops": e * (2 * ni * ni + 2 * nc * ni),
-                "bytes": e * (ni * ni + nc * ni) * esz + (ndof + n1) * 8},
-        "backsolve": {"flops": e * (2 * ni * ni + 2 * ni * nc),
-                      "bytes": e * (ni * ni + ni * nc) * esz + (2 * ndof + n1) * 8},
-        "residual": {"flops": 2 * e * (ni * ni + 2 * ni * nc) + nnzb * 50,
-                     "bytes": e * (ni * ni + 2 * ni * nc) * 8 + bb_bytes + 3 * ndof * 8},
+        "inverse": {"flops": t(2 * ni ** 3), "bytes": t(ni * ni) * esz * 2},
+        "gemm_x": {"flops": t(2 * ni * ni * nc), "bytes": t(ni * ni + 2 * ni * nc) * esz},
+        "gemm_s": {"flops": t(2 * nc * nc * ni), "bytes": t(2 * ni * nc + nc * nc) * esz},
+        "schur_apply": {"flops": t(2 * nc * nc) + n_rem * 50,
+                        "bytes": t(nc * nc) * esz + n_rem * (25 * 8 + 4) + 2 * n1 * 8},
+        "rhs": {"flops": t(2 * ni * ni + 2 * nc * ni),
+                "bytes": t(ni * ni + nc * ni) * esz + (ndof + n1) * 8},
+        "backsolve": {"flops": t(2 * ni * ni + 2 * ni * nc),
+                      "bytes": t(ni * ni + ni * nc) * esz + (2 * ndof + n1) * 8},
+        "residual": {"flops": t(2 * (ni * ni + 2 * ni * nc)) + nnzb * 50,
+                     "bytes": t(ni * ni + 2 * ni * nc) * 8 + bb_bytes + 3 * ndof * 8},
     }
 
 
@@ -271,9 +275,17 @@ def main() -> int:
 
     from paper_1911_02366_amd import Plan
     from workload.cases import WORKLOADS, named_case
+    from workload.mixed import MIXED_WORKLOADS, mixed_order_case
 
     dev = "cuda"
-    case = named_case(args.workload, device=dev)
+    if args.workload in MIXED_WORKLOADS:
+        k_m, lo_m, hi_m, seed_m = MIXED_WORKLOADS[args.workload]
+        case = mixed_order_case(k_m, lo_m, hi_m, seed_m, device=dev)
+        cfg = {"order": f"{lo_m}..{hi_m} (seeded per element)", "reynolds": None, "dt": None,
+               "values": "synthetic, strictly diagonally dominant"}
+    else:
+        case = named_case(args.workload, device=dev)
+        cfg = dict(WORKLOADS[args.workload])
     torch.cuda.synchronize()
     b = case.rhs
     plan = Plan.from_structure(case.structure())
@@ -337,7 +349,6 @@ def main() -> int:
         if entries.get(k) is not None and rec is not None:
             entries[k]["traffic"] = rec["traffic_bytes_per_launch"]
     worst = max(i["rel_res_full"] for i in infos)
-    cfg = WORKLOADS[args.workload]
     out = {
         "metric": "condensed implicit-step DOF/s at 1e-8 residual",
         "value": round(value, 1),
@@ -353,7 +364,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "elements": case.n_elem, "order": cfg["order"],
                    "dofs": case.n_dof, "n1_condensed": case.n1, "n2_interior": case.n2,
-                   "reynolds": cfg["reynolds"], "mach": 0.1, "dt": cfg["dt"],
+                   "reynolds": cfg["reynolds"], "mach": 0.1 if cfg["reynolds"] else None, "dt": cfg["dt"],
                    "solver": "gmres(30)+" + ["none", "point-jacobi", "block-jacobi-5x5"][args.precond],
                    "gmres_tol": opts["tol"],
                    "precision": args.precision},

@@ -81,6 +81,7 @@ struct Plan {
   int32_t *d_rem_src = nullptr;     // [n_rem] block index into bb_val
   int32_t *d_inv_n = nullptr;     // [n_elem] n_i per element
   int64_t *d_inv_off = nullptr;   // [n_elem] offset of A_ii(e)
+  int32_t *d_inv_order = nullptr; // [n_elem] elements by decreasing n_i (stable)
   int32_t *d_info = nullptr;      // [n_elem] factor info
 
   // batched GEMM descriptors and tile lists (X = Ainv A_ib, S_loc = A_bi X)

@@ -33,40 +33,48 @@ namespace {
 
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
-constexpr int kChunk = 64;           // columns per update chunk
-constexpr int kRStride = kChunk + 16;  // LDS row stride of the pivot-row chunk
 constexpr int kRowsPerThread = 3;    // rows owned per thread (n <= 1536)
 constexpr int kGroup = 5;            // output tiles per wave in flight
 
-template <typename T>
-constexpr int panel_stride(int nb) {
-  return nb + (sizeof(T) == 8 ? 2 : 4);
-}
+// LDS layout of one element's workgroup: panel width NB, panel row stride PS
+// (padded against bank conflicts; the compact layouts use NB + 1), the number
+// of columns per update chunk, and whether the pivot permutation is kept in
+// LDS (the single-kernel form) or in global memory (the blocked form).
+template <typename T_, int NB_, int PS_, int CHUNK_, bool PERM_>
+struct GjLayout {
+  using T = T_;
+  static constexpr int NB = NB_, PS = PS_, CHUNK = CHUNK_, RSTRIDE = CHUNK_ + 16;
+  static constexpr bool PERM = PERM_;
+  static size_t lds_bytes(int max_n) {
+    const int rp = (max_n + 15) & ~15;
+    return sizeof(T) * ((size_t)rp * PS + (size_t)NB * RSTRIDE + 2 * NB) +
+           (PERM ? sizeof(int) * 2 * (size_t)rp : 0) + (size_t)rp;
+  }
+};
 
-template <typename T, int NB>
-size_t gj_lds_bytes(int max_n) {
-  const int rp = (max_n + 15) & ~15;
-  return sizeof(T) * ((size_t)rp * panel_stride<T>(NB) + (size_t)NB * kRStride + 2 * NB) +
-         sizeof(int) * 2 * (size_t)rp + (size_t)rp;
-}
+template <typename T, int NB, bool PERM>
+using GjWide = GjLayout<T, NB, NB + (sizeof(T) == 8 ? 2 : 4), 64, PERM>;
+template <typename T, int NB, bool PERM>
+using GjCompact = GjLayout<T, NB, NB + 1, 32, PERM>;
 
 // Shared memory of one element's workgroup: the panel (all rows x NB columns),
 // a chunk of the panel's pivot rows, the parked pivot rows, pivot bookkeeping.
-template <typename T, int NB>
+template <class L>
 struct GjSmem {
+  using T = typename L::T;
   T *pnl;             // [rp][PS]
-  T *rl;              // [NB][kRStride]
+  T *rl;              // [NB][RSTRIDE]
   T *pend_buf;        // [2][NB] parked pivot rows
-  int *piv;           // [rp] pivot row of column k (single-kernel form)
-  int *qinv;          // [rp] column whose pivot row is m
+  int *piv;           // [rp] pivot row of column k (single-kernel form only)
+  int *qinv;          // [rp] column whose pivot row is m (single-kernel form only)
   unsigned char *inpanel;  // [rp] row is a pivot row of the current panel
   __device__ GjSmem(unsigned char *smem, int rp) {
     pnl = reinterpret_cast<T *>(smem);
-    rl = pnl + (size_t)rp * panel_stride<T>(NB);
-    pend_buf = rl + NB * kRStride;
-    piv = reinterpret_cast<int *>(pend_buf + 2 * NB);
-    qinv = piv + rp;
-    inpanel = reinterpret_cast<unsigned char *>(qinv + rp);
+    rl = pnl + (size_t)rp * L::PS;
+    pend_buf = rl + L::NB * L::RSTRIDE;
+    piv = reinterpret_cast<int *>(pend_buf + 2 * L::NB);
+    qinv = piv + (L::PERM ? rp : 0);
+    inpanel = reinterpret_cast<unsigned char *>(qinv + (L::PERM ? rp : 0));
   }
 };
 
@@ -79,11 +87,12 @@ struct GjSmem {
 // next column's barrier, applying that column's elimination.  piv (LDS or
 // global) receives the pivot row of each column; used[] marks the rows this
 // thread owns that have served as pivots.
-template <typename T, int NB>
-__device__ void gj_eliminate(GjSmem<T, NB> &sm, int n, int kb, int nbw, bool (&used)[kRowsPerThread],
+template <class L>
+__device__ void gj_eliminate(GjSmem<L> &sm, int n, int kb, int nbw, bool (&used)[kRowsPerThread],
                              int *piv, unsigned char *flags, int &my_info, double (*red_v)[kWaves],
                              int (*red_i)[kWaves]) {
-  constexpr int PS = panel_stride<T>(NB);
+  using T = typename L::T;
+  constexpr int NB = L::NB, PS = L::PS;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   T *pnl = sm.pnl;
   bool pend_valid = false;
@@ -183,16 +192,19 @@ __device__ void gj_eliminate(GjSmem<T, NB> &sm, int n, int kb, int nbw, bool (&u
 //   W[i][j] <- (i pivot row of this panel ? 0 : W[i][j]) + sum_c P[i][c] R[c][j]
 // with P the transformed panel (LDS) and R the panel's pivot rows read from src
 // (a0 in double on the first panel of the single-kernel form, else w).
-template <typename T, int NB>
-__device__ void gj_update(GjSmem<T, NB> &sm, const double *__restrict__ a0, bool first, T *__restrict__ w,
+template <class L>
+__device__ void gj_update(GjSmem<L> &sm, const double *__restrict__ a0, bool first, typename L::T *__restrict__ w,
                           int n, int kb, int nbw, const int *piv, int j_lo, int j_hi) {
+  using T = typename L::T;
   using M = Mfma<T>;
-  constexpr int PS = panel_stride<T>(NB);
+  constexpr int NB = L::NB, PS = L::PS, kChunk = L::CHUNK, kRStride = L::RSTRIDE;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int rp = (n + 15) & ~15;
   const int row_tiles = rp / 16;
-  const int ct = wid & 3;           // 16-column tile of the chunk
-  const int rt0 = wid >> 2;         // row tiles rt0, rt0 + 2, ...
+  constexpr int kColTiles = kChunk / 16;              // 16-column tiles per chunk
+  constexpr int kRowLanes = kWaves / kColTiles;       // waves sharing a column tile
+  const int ct = wid % kColTiles;
+  const int rt0 = wid / kColTiles;  // row tiles rt0, rt0 + kRowLanes, ...
   for (int j0 = j_lo; j0 < j_hi; j0 += kChunk) {
     for (int idx = tid; idx < NB * kChunk; idx += kThreads) {
       const int c = idx / kChunk, jj = idx % kChunk, j = j0 + jj;
@@ -206,12 +218,12 @@ __device__ void gj_update(GjSmem<T, NB> &sm, const double *__restrict__ a0, bool
     __syncthreads();
     const int jc = j0 + ct * 16 + (lane & 15);
     const bool col_ok = jc < j_hi && !(jc >= kb && jc < kb + nbw);
-    for (int rtb = rt0; rtb < row_tiles; rtb += 2 * kGroup) {
+    for (int rtb = rt0; rtb < row_tiles; rtb += kRowLanes * kGroup) {
       T old[kGroup][4];
       typename M::acc_t acc[kGroup];
 #pragma unroll
       for (int g = 0; g < kGroup; ++g) {
-        const int rt = rtb + 2 * g;
+        const int rt = rtb + kRowLanes * g;
         acc[g] = M::zero();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -227,7 +239,7 @@ __device__ void gj_update(GjSmem<T, NB> &sm, const double *__restrict__ a0, bool
         const T bv = sm.rl[(kk + (lane >> 4)) * kRStride + ct * 16 + (lane & 15)];
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
-          const int rt = min(rtb + 2 * g, row_tiles - 1);
+          const int rt = min(rtb + kRowLanes * g, row_tiles - 1);
           const T av = sm.pnl[(rt * 16 + (lane & 15)) * PS + kk + (lane >> 4)];
           acc[g] = M::mma(av, bv, acc[g]);
         }
@@ -235,7 +247,7 @@ __device__ void gj_update(GjSmem<T, NB> &sm, const double *__restrict__ a0, bool
       if (col_ok) {
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
-          const int rt = rtb + 2 * g;
+          const int rt = rtb + kRowLanes * g;
           if (rt >= row_tiles) continue;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -251,25 +263,29 @@ __device__ void gj_update(GjSmem<T, NB> &sm, const double *__restrict__ a0, bool
 
 // Single-kernel form: one workgroup runs every panel of its element, updating
 // all columns after each panel, then reads the inverse out.
-template <typename T, int NB>
+template <class L>
 __global__ __launch_bounds__(kThreads) void gj_inverse_kernel(const double *__restrict__ src,
-                                                              T *__restrict__ work,
-                                                              T *__restrict__ out,
+                                                              typename L::T *__restrict__ work,
+                                                              typename L::T *__restrict__ out,
                                                               const int32_t *__restrict__ n_arr,
                                                               const int64_t *__restrict__ off_arr,
+                                                              const int32_t *__restrict__ elem_order,
                                                               int32_t *__restrict__ info) {
-  constexpr int PS = panel_stride<T>(NB);
+  using T = typename L::T;
+  constexpr int NB = L::NB, PS = L::PS;
+  static_assert(L::PERM, "the single-kernel form keeps the permutation in LDS");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red_v[2][kWaves];
   __shared__ int red_i[2][kWaves];
 
-  const int e = blockIdx.x;
+  // elements in longest-first order: XCD blockIdx % 8 receives a balanced share
+  const int e = elem_order[blockIdx.x];
   const int n = n_arr[e];
   const int64_t off = off_arr[e];
   const double *__restrict__ a0 = src + off;
   T *__restrict__ w = work + off;
   const int rp = (n + 15) & ~15;
-  GjSmem<T, NB> sm(smem, rp);
+  GjSmem<L> sm(smem, rp);
 
   const int tid = threadIdx.x;
   bool used[kRowsPerThread];
@@ -288,8 +304,8 @@ __global__ __launch_bounds__(kThreads) void gj_inverse_kernel(const double *__re
       sm.pnl[i * PS + c] = v;
     }
     __syncthreads();
-    gj_eliminate<T, NB>(sm, n, kb, nbw, used, sm.piv, nullptr, my_info, red_v, red_i);
-    gj_update<T, NB>(sm, a0, first, w, n, kb, nbw, sm.piv, 0, n);
+    gj_eliminate<L>(sm, n, kb, nbw, used, sm.piv, nullptr, my_info, red_v, red_i);
+    gj_update<L>(sm, a0, first, w, n, kb, nbw, sm.piv, 0, n);
     for (int idx = tid; idx < rp * NB; idx += kThreads) {
       const int i = idx / NB, c = idx % NB;
       if (i < n && c < nbw) w[(int64_t)i * n + kb + c] = sm.pnl[i * PS + c];
@@ -340,14 +356,16 @@ __global__ void gj_prepare_kernel(const double *__restrict__ src, T *__restrict_
   }
 }
 
-template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) void gj_panel_kernel(T *__restrict__ work, const int32_t *__restrict__ n_arr,
+template <class L>
+__global__ __launch_bounds__(kThreads) void gj_panel_kernel(typename L::T *__restrict__ work,
+                                                            const int32_t *__restrict__ n_arr,
                                                             const int64_t *__restrict__ off_arr,
                                                             const int64_t *__restrict__ voff_arr,
                                                             int32_t *__restrict__ piv_all,
                                                             unsigned char *__restrict__ flags_all,
                                                             int32_t *__restrict__ info, int kb, int ko) {
-  constexpr int PS = panel_stride<T>(NB);
+  using T = typename L::T;
+  constexpr int NB = L::NB, PS = L::PS;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red_v[2][kWaves];
   __shared__ int red_i[2][kWaves];
@@ -359,7 +377,7 @@ __global__ __launch_bounds__(kThreads) void gj_panel_kernel(T *__restrict__ work
   int *piv = piv_all + voff_arr[e];
   unsigned char *flags = flags_all + voff_arr[e];
   const int rp = (n + 15) & ~15;
-  GjSmem<T, NB> sm(smem, rp);
+  GjSmem<L> sm(smem, rp);
   const int tid = threadIdx.x;
   bool used[kRowsPerThread];
 #pragma unroll
@@ -376,8 +394,8 @@ __global__ __launch_bounds__(kThreads) void gj_panel_kernel(T *__restrict__ work
   }
   __syncthreads();
   int my_info = 0;
-  gj_eliminate<T, NB>(sm, n, kb, nbw, used, piv, flags, my_info, red_v, red_i);
-  gj_update<T, NB>(sm, nullptr, false, w, n, kb, nbw, piv, ko, min(n, ko + kOuter));
+  gj_eliminate<L>(sm, n, kb, nbw, used, piv, flags, my_info, red_v, red_i);
+  gj_update<L>(sm, nullptr, false, w, n, kb, nbw, piv, ko, min(n, ko + kOuter));
   for (int idx = tid; idx < rp * NB; idx += kThreads) {
     const int i = idx / NB, c = idx % NB;
     if (i < n && c < nbw) w[(int64_t)i * n + kb + c] = sm.pnl[i * PS + c];
@@ -445,30 +463,32 @@ __global__ __launch_bounds__(kThreads) void gj_readout_kernel(const T *__restric
   }
 }
 
-template <typename T, int NB>
-hipError_t gj_launch(Plan &p, T *work, T *out) {
-  const size_t lds = gj_lds_bytes<T, NB>(p.max_ni);
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(gj_inverse_kernel<T, NB>),
+template <class L>
+hipError_t gj_launch(Plan &p, typename L::T *work, typename L::T *out) {
+  const size_t lds = L::lds_bytes(p.max_ni);
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(gj_inverse_kernel<L>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((gj_inverse_kernel<T, NB>), dim3(p.n_elem), dim3(kThreads), lds, p.stream,
-                     p.aii, work, out, p.d_inv_n, p.d_inv_off, p.d_info);
+  hipLaunchKernelGGL((gj_inverse_kernel<L>), dim3(p.n_elem), dim3(kThreads), lds, p.stream,
+                     p.aii, work, out, p.d_inv_n, p.d_inv_off, p.d_inv_order, p.d_info);
   return hipGetLastError();
 }
 
 constexpr size_t kLdsLimit = 160 * 1024 - 512;
 
+// the widest panel whose layout fits the LDS of one workgroup
 template <typename T>
 hipError_t gj_dispatch(Plan &p, T *work, T *out) {
-  if (gj_lds_bytes<T, 32>(p.max_ni) <= kLdsLimit) return gj_launch<T, 32>(p, work, out);
-  if (gj_lds_bytes<T, 16>(p.max_ni) <= kLdsLimit) return gj_launch<T, 16>(p, work, out);
-  return gj_launch<T, 8>(p, work, out);
+  if (GjWide<T, 32, true>::lds_bytes(p.max_ni) <= kLdsLimit) return gj_launch<GjWide<T, 32, true>>(p, work, out);
+  if (GjWide<T, 16, true>::lds_bytes(p.max_ni) <= kLdsLimit) return gj_launch<GjWide<T, 16, true>>(p, work, out);
+  return gj_launch<GjWide<T, 8, true>>(p, work, out);
 }
 
-template <typename T, int NB>
-hipError_t gj_blocked_run(Plan &p, T *work, T *out) {
-  const size_t lds = gj_lds_bytes<T, NB>(p.max_ni);
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(gj_panel_kernel<T, NB>),
+template <class L>
+hipError_t gj_blocked_run(Plan &p, typename L::T *work, typename L::T *out) {
+  using T = typename L::T;
+  const size_t lds = L::lds_bytes(p.max_ni);
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(gj_panel_kernel<L>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   const int64_t total = p.off_ii[p.n_elem];
@@ -478,8 +498,8 @@ hipError_t gj_blocked_run(Plan &p, T *work, T *out) {
   T *pbuf = static_cast<T *>(p.gj_pbuf), *rbuf = static_cast<T *>(p.gj_rbuf);
   for (int s = 0; s * kOuter < p.max_ni; ++s) {
     const int ko = s * kOuter;
-    for (int kb = ko; kb < std::min(p.max_ni, ko + kOuter); kb += NB)
-      hipLaunchKernelGGL((gj_panel_kernel<T, NB>), dim3(p.n_elem), dim3(kThreads), lds, p.stream, work,
+    for (int kb = ko; kb < std::min(p.max_ni, ko + kOuter); kb += L::NB)
+      hipLaunchKernelGGL((gj_panel_kernel<L>), dim3(p.n_elem), dim3(kThreads), lds, p.stream, work,
                          p.d_inv_n, p.d_inv_off, p.d_gj_voff, p.d_gj_piv, p.d_gj_flag, p.d_info, kb, ko);
     if (p.gj_ntiles[s] > 0) {
       hipLaunchKernelGGL((gj_outer_gather_kernel<T>), dim3(p.n_elem), dim3(512), 0, p.stream, work,
@@ -494,19 +514,25 @@ hipError_t gj_blocked_run(Plan &p, T *work, T *out) {
   return hipGetLastError();
 }
 
+// the widest inner panel that fits: padded layouts first, then the compact ones
 template <typename T>
 hipError_t gj_blocked_dispatch(Plan &p, T *work, T *out) {
-  if (gj_lds_bytes<T, 32>(p.max_ni) <= kLdsLimit) return gj_blocked_run<T, 32>(p, work, out);
-  if (gj_lds_bytes<T, 16>(p.max_ni) <= kLdsLimit) return gj_blocked_run<T, 16>(p, work, out);
-  return gj_blocked_run<T, 8>(p, work, out);
+  const int n = p.max_ni;
+  if (GjWide<T, 32, false>::lds_bytes(n) <= kLdsLimit) return gj_blocked_run<GjWide<T, 32, false>>(p, work, out);
+  if (GjCompact<T, 32, false>::lds_bytes(n) <= kLdsLimit)
+    return gj_blocked_run<GjCompact<T, 32, false>>(p, work, out);
+  if (GjWide<T, 16, false>::lds_bytes(n) <= kLdsLimit) return gj_blocked_run<GjWide<T, 16, false>>(p, work, out);
+  if (GjCompact<T, 16, false>::lds_bytes(n) <= kLdsLimit)
+    return gj_blocked_run<GjCompact<T, 16, false>>(p, work, out);
+  return gj_blocked_run<GjWide<T, 8, false>>(p, work, out);
 }
 
 }  // namespace
 
 bool gj_supported(int max_n, bool fp32) {
   if (max_n > kRowsPerThread * kThreads) return false;
-  return fp32 ? gj_lds_bytes<float, 8>(max_n) <= kLdsLimit
-              : gj_lds_bytes<double, 8>(max_n) <= kLdsLimit;
+  return fp32 ? GjWide<float, 8, true>::lds_bytes(max_n) <= kLdsLimit
+              : GjWide<double, 8, true>::lds_bytes(max_n) <= kLdsLimit;
 }
 
 hipError_t launch_gj_inverse(Plan &p, void *work, void *out, bool fp32) {

@@ -83,26 +83,43 @@ void local_node_sets(int order, std::vector<int> &interior, std::vector<int> &bo
 // Tile list ordered so that the workgroups of one problem share an XCD: block b
 // runs on XCD b % 8, so block b takes tile (b % 8) * per + b / 8 of the
 // problem-major list.
+// Tile list of a batched GEMM for the 8 XCDs (a workgroup runs on XCD
+// blockIdx % 8 and XCDs take their workgroups in blockIdx order): every
+// problem's tiles stay on one XCD (its operands stay in that XCD's L2), problems
+// go to XCDs by longest-processing-time-first (largest remaining cost to the
+// least-loaded XCD; cost = tiles x K), and each XCD runs its largest problems
+// first.  Slots past the end of a shorter XCD list hold -1 (no work).
 std::vector<int32_t> xcd_tile_list(const std::vector<GemmDesc> &descs, int cfg) {
   int bm, bn;
   gemm_tile_shape(cfg, &bm, &bn);
-  std::vector<int32_t> flat;
-  for (size_t q = 0; q < descs.size(); ++q) {
+  const size_t nq = descs.size();
+  std::vector<double> cost(nq);
+  std::vector<size_t> order(nq);
+  for (size_t q = 0; q < nq; ++q) {
+    const double tm = (descs[q].m + bm - 1) / bm, tn = (descs[q].n + bn - 1) / bn;
+    cost[q] = tm * tn * std::max(1, descs[q].k);
+    order[q] = q;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<std::vector<int32_t>> lists(8);
+  std::vector<double> load(8, 0.0);
+  for (size_t q : order) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
     const int tm = (descs[q].m + bm - 1) / bm, tn = (descs[q].n + bn - 1) / bn;
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) {
-        flat.push_back((int32_t)q);
-        flat.push_back(a);
-        flat.push_back(b);
+        lists[x].push_back((int32_t)q);
+        lists[x].push_back(a);
+        lists[x].push_back(b);
       }
+    load[x] += cost[q];
   }
-  const int64_t total = (int64_t)flat.size() / 3;
-  const int64_t per = (total + 7) / 8;
-  std::vector<int32_t> out(3 * 8 * per, -1);
-  for (int64_t blk = 0; blk < 8 * per; ++blk) {
-    const int64_t t = (blk % 8) * per + blk / 8;
-    if (t < total) std::memcpy(&out[3 * blk], &flat[3 * t], 3 * sizeof(int32_t));
-  }
+  size_t longest = 0;
+  for (auto &l : lists) longest = std::max(longest, l.size() / 3);
+  std::vector<int32_t> out(3 * 8 * longest, -1);
+  for (size_t pos = 0; pos < longest; ++pos)
+    for (int x = 0; x < 8; ++x)
+      if (pos < lists[x].size() / 3) std::memcpy(&out[3 * (pos * 8 + x)], &lists[x][3 * pos], 3 * sizeof(int32_t));
   return out;
 }
 
@@ -427,7 +444,7 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.d_slot_soff); dfree(p.d_slot_nc); dfree(p.d_slot_pos);
   dfree(p.d_fold_dst); dfree(p.d_fold_nc); dfree(p.d_fold_src);
   dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk);
-  dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_info);
+  dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_inv_order); dfree(p.d_info);
   dfree(p.d_gx); dfree(p.d_gs); dfree(p.d_tiles_x); dfree(p.d_tiles_s);
   dfree(p.d_gv_inv); dfree(p.d_gv_abi); dfree(p.d_gv_aib); dfree(p.d_gv_s);
   dfree(p.d_rt_inv); dfree(p.d_rt_abi); dfree(p.d_rt_aib); dfree(p.d_rt_s);
@@ -667,6 +684,12 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   chk(upload(p, &p.d_bb_col, bb_col));
   chk(upload(p, &p.d_inv_n, inv_n));
   chk(upload(p, &p.d_inv_off, inv_off));
+  {
+    std::vector<int32_t> ord(p.n_elem);
+    for (int e = 0; e < p.n_elem; ++e) ord[e] = e;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return p.ni[a] > p.ni[b]; });
+    chk(upload(p, &p.d_inv_order, ord));
+  }
   chk(dalloc(p, &p.d_info, (size_t)E));
   chk(upload(p, &p.d_gx, gx));
   chk(upload(p, &p.d_gs, gs));
