@@ -19,10 +19,12 @@ constexpr int kRowBatch = 8;                                    // rows streamed
 
 template <typename TM>
 struct Vec;
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
 template <>
 struct Vec<double> {
   static constexpr int W = 2;
-  using V = double2;
+  using V = dvec2;
   static __device__ __forceinline__ void get(const V &v, double *o) {
     o[0] = v.x;
     o[1] = v.y;
@@ -31,7 +33,7 @@ struct Vec<double> {
 template <>
 struct Vec<float> {
   static constexpr int W = 4;
-  using V = float4;
+  using V = fvec4;
   static __device__ __forceinline__ void get(const V &v, double *o) {
     o[0] = v.x;
     o[1] = v.y;
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
         for (int u = 0; u < W; ++u) xv[u] = xs[c * W + u];
         typename VT::V m[kRowBatch];
 #pragma unroll
-        for (int q = 0; q < kRowBatch; ++q) m[q] = rows[q][c];
+        for (int q = 0; q < kRowBatch; ++q) m[q] = __builtin_nontemporal_load(&rows[q][c]);
 #pragma unroll
         for (int q = 0; q < kRowBatch; ++q) {
           double mv[W];
