@@ -132,6 +132,21 @@ scdg_status scdg_assemble(scdg_plan *p, const double *aii, const double *aib,
  * FP64 or FP32.  A zero pivot is recorded per element (see scdg_factor_info)
  * and reported as SCDG_ERR_SINGULAR by scdg_condense. */
 scdg_status scdg_factor(scdg_plan *p, scdg_precision prec);
+/* Where the GMRES cycle runs (paper, Section 4 uses GMRES on the Newton
+ * systems; this is an execution choice, same arithmetic):
+ *   0  host-driven: one device-to-host transfer and wait per iteration for the
+ *      Hessenberg column; Givens rotations on the host (default);
+ *   1  device-resident: Hessenberg column, Givens rotations, stopping test and
+ *      the next basis vector's scale stay on the device; every kernel of an
+ *      Arnoldi step returns at once when a halt flag is set; the host waits once
+ *      per restart cycle (true residual);
+ *   2  as 1, with the m Arnoldi steps captured once into a HIP graph (on a
+ *      plan-owned stream) and replayed per cycle on the plan's stream.  The
+ *      graph is recaptured when the restart length, preconditioner, factor
+ *      precision or the borrowed A_bb pointer change.  Phase timers do not see
+ *      the kernels inside the graph. */
+scdg_status scdg_set_krylov_mode(scdg_plan *p, int32_t mode);
+
 /* Form of the batched inverse: 0 automatic (blocked above n_i = 320),
  * 1 one workgroup per element for the whole elimination, 2 blocked: outer
  * panels of 128 columns whose update of the rest of the block is a batched

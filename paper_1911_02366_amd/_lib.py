@@ -26,6 +26,7 @@ EXPORTED = [
     "scdg_schur_apply", "scdg_export", "scdg_status_string", "scdg_last_error",
     "scdg_enable_timing", "scdg_phase_times", "scdg_autotune", "scdg_set_gemm_config",
     "scdg_get_gemm_config", "scdg_plan_fold_counts", "scdg_set_inverse_mode", "scdg_get_inverse_mode",
+    "scdg_set_krylov_mode",
     "scdg_dg_create", "scdg_dg_destroy", "scdg_dg_residual", "scdg_dg_gradient",
     "scdg_mlp_create", "scdg_mlp_destroy", "scdg_mlp_param_count", "scdg_mlp_forward",
     "scdg_mlp_backward", "scdg_mlp_adam", "scdg_mlp_mse", "scdg_mlp_gather", "scdg_guess_stats",
@@ -110,6 +111,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_get_gemm_config": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
         "scdg_plan_fold_counts": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
         "scdg_set_inverse_mode": (i32, [vp, i32]),
+        "scdg_set_krylov_mode": (i32, [vp, i32]),
         "scdg_get_inverse_mode": (i32, [vp, C.POINTER(i32)]),
         "scdg_dg_create": (i32, [C.POINTER(vp), C.POINTER(DgParams), vp]),
         "scdg_dg_destroy": (i32, [vp]),

@@ -36,6 +36,17 @@ struct GemvDesc {
   int32_t y_off;   // offset into the y / y0 index space
 };
 
+// What a captured GMRES cycle depends on; a different key means recapture.
+struct KrylovKey {
+  int m = 0, pmode = -1;
+  bool fp32 = false;
+  const void *sloc = nullptr, *bb_val = nullptr, *gm_v = nullptr;
+  bool operator==(const KrylovKey &o) const {
+    return m == o.m && pmode == o.pmode && fp32 == o.fp32 && sloc == o.sloc && bb_val == o.bb_val &&
+           gm_v == o.gm_v;
+  }
+};
+
 // GEMM tile configurations (rows x columns of C per workgroup)
 enum { kGemm64x64 = 0, kGemm64x128 = 1, kGemm128x128 = 2, kGemm128x128w8 = 3, kGemmConfigs = 7 };
 
@@ -148,6 +159,18 @@ struct Plan {
   double *gm_h = nullptr;     // [m+2] device h column
   double *h_pinned = nullptr; // host pinned staging
   int32_t gm_m = 0;
+
+  // device-resident GMRES cycles (krylov_mode 1) and their graph (mode 2)
+  int krylov_mode = 0;            // 0 host Givens, 1 device, 2 device + graph replay
+  const int32_t *halt = nullptr;  // set while enqueueing Arnoldi steps: kernels return when *halt
+  bool capturing = false;
+  double *kr_H = nullptr, *kr_cs = nullptr, *kr_sn = nullptr, *kr_g = nullptr, *kr_dev = nullptr;
+  int32_t *kr_st = nullptr;
+  int kr_m = 0;
+  hipStream_t cap_stream = nullptr;   // plan-owned stream for graph capture
+  hipGraph_t kr_graph = nullptr;
+  hipGraphExec_t kr_exec = nullptr;
+  KrylovKey kr_key{};
   int32_t red_blocks = 0;
 
   // phase timing (events recorded asynchronously, summed on query)
@@ -172,7 +195,8 @@ hipError_t launch_gemm_batched(int cfg, const GemmDesc *d_desc, const int32_t *d
 hipError_t launch_gemv_batched(const GemvDesc *d_desc, const RowTile *d_tiles, int32_t n_tiles,
                                int32_t max_cols, const void *mat, bool fp32, const double *x,
                                const int32_t *xmap, double *y, const int32_t *omap, double alpha,
-                               double beta, const double *y0, hipStream_t s);
+                               double beta, const double *y0, hipStream_t s,
+                               const int32_t *halt = nullptr);
 
 // out[j] = c0 * src0[map0 ? map0[j] : j] + c1 * (B x)[j] + c2 * sum_{s in pull(j/5)} t[5 s + j%5]
 // with B = A_bb (full = true) or the remainder of A_bb not folded into T_e.
@@ -194,14 +218,23 @@ hipError_t launch_scatter_axpby(int64_t n, double a, const double *x, double b, 
 
 // multi-dot: out[k] = sum_i V[k*ld + i] w[i], k < nv (deterministic two-stage)
 hipError_t launch_multidot(const double *v, int64_t ld, int32_t nv, const double *w, int64_t n,
-                           double *partials, int32_t nblocks, double *out, hipStream_t s);
+                           double *partials, int32_t nblocks, double *out, hipStream_t s,
+                           const int32_t *halt = nullptr);
 // w -= sum_k V[k*ld+i] h[k]
 hipError_t launch_multi_axpy(const double *v, int64_t ld, int32_t nv, const double *h, double *w,
-                             int64_t n, hipStream_t s);
+                             int64_t n, hipStream_t s,
+                             const int32_t *nv_dev = nullptr, const int32_t *halt = nullptr);
 // y = x * dinv (elementwise); dinv may be null (copy)
 hipError_t launch_diag_scale(const double *x, const double *dinv, double *y, int64_t n, double a,
-                             hipStream_t s);
+                             hipStream_t s,
+                             const double *a_dev = nullptr, const int32_t *halt = nullptr);
 hipError_t launch_reciprocal(double *x, int64_t n, hipStream_t s);
+hipError_t launch_krylov_start(double beta, double target, int limit, double *g, int32_t *st, double *dev,
+                               hipStream_t s);
+hipError_t launch_krylov_givens(int j, int m, const double *hc, double *H, double *cs, double *sn, double *g,
+                                int32_t *st, double *dev, hipStream_t s);
+hipError_t launch_krylov_solve(int m, const double *H, const double *g, const int32_t *st, double *yneg,
+                               hipStream_t s);
 
 // dense path
 hipError_t launch_dense_assemble(const Plan &p, double *s_dense);

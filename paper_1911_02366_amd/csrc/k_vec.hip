@@ -52,7 +52,9 @@ template <typename TM>
 __global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
     const GemvDesc *__restrict__ desc, const RowTile *__restrict__ tiles, const TM *__restrict__ mat,
     const double *__restrict__ x, const int32_t *__restrict__ xmap, double *__restrict__ y,
-    const int32_t *__restrict__ omap, double alpha, double beta, const double *__restrict__ y0) {
+    const int32_t *__restrict__ omap, double alpha, double beta, const double *__restrict__ y0,
+    const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
   using VT = Vec<TM>;
   constexpr int W = VT::W;
   extern __shared__ double xs[];
@@ -125,7 +127,9 @@ __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
     double c1, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ src_idx, const double *__restrict__ val,
     const double *__restrict__ x, double c2, const int32_t *__restrict__ pull_ptr,
-    const int32_t *__restrict__ pull_idx, const double *__restrict__ t, double *__restrict__ out) {
+    const int32_t *__restrict__ pull_idx, const double *__restrict__ t, double *__restrict__ out,
+    const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
   __shared__ double part[kThreads];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -253,7 +257,9 @@ __global__ void precond_setup_kernel(int64_t n_bnodes, const int64_t *__restrict
 
 __global__ void precond_apply_kernel(int mode, int64_t n_bnodes, const double *__restrict__ diag_inv,
                                      const double *__restrict__ pc_blk,
-                                     const double *__restrict__ x, double *__restrict__ y, double a) {
+                                     const double *__restrict__ x, double *__restrict__ y, double a,
+                                     const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= 5 * n_bnodes) return;
   double v;
@@ -305,7 +311,10 @@ __global__ void scatter_axpby_kernel(int64_t n, double a, const double *__restri
 }
 
 __global__ void diag_scale_kernel(const double *__restrict__ x, const double *__restrict__ dinv,
-                                  double *__restrict__ y, int64_t n, double a) {
+                                  double *__restrict__ y, int64_t n, double a,
+                                  const double *__restrict__ a_dev, const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
+  if (a_dev) a *= *a_dev;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     y[i] = a * x[i] * (dinv ? dinv[i] : 1.0);
@@ -333,7 +342,9 @@ __global__ void copy_kernel(const double *__restrict__ src, double *__restrict__
 __global__ __launch_bounds__(kThreads) void multidot_kernel(const double *__restrict__ v, int64_t ld,
                                                             int nv, const double *__restrict__ w,
                                                             int64_t n,
-                                                            double *__restrict__ partials) {
+                                                            double *__restrict__ partials,
+                                                            const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
   __shared__ double red[kThreads / 64];
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t lo = blockIdx.x * chunk;
@@ -357,7 +368,8 @@ __global__ __launch_bounds__(kThreads) void multidot_kernel(const double *__rest
 
 // stage 2: out[k] = sum_b partials[k * nblocks + b], one wave per k
 __global__ void multidot_finish_kernel(const double *__restrict__ partials, int nblocks, int nv,
-                                       double *__restrict__ out) {
+                                       double *__restrict__ out, const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
   const int lane = threadIdx.x & 63;
   const int k = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (k >= nv) return;
@@ -368,7 +380,10 @@ __global__ void multidot_finish_kernel(const double *__restrict__ partials, int 
 }
 
 __global__ void multi_axpy_kernel(const double *__restrict__ v, int64_t ld, int nv,
-                                  const double *__restrict__ h, double *__restrict__ w, int64_t n) {
+                                  const double *__restrict__ h, double *__restrict__ w, int64_t n,
+                                  const int32_t *__restrict__ nv_dev, const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
+  if (nv_dev) nv = *nv_dev;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     double s = w[i];
@@ -389,15 +404,15 @@ inline int grid_for(int64_t n) {
 hipError_t launch_gemv_batched(const GemvDesc *d_desc, const RowTile *d_tiles, int32_t n_tiles,
                                int32_t max_cols, const void *mat, bool fp32, const double *x,
                                const int32_t *xmap, double *y, const int32_t *omap, double alpha,
-                               double beta, const double *y0, hipStream_t s) {
+                               double beta, const double *y0, hipStream_t s, const int32_t *halt) {
   if (n_tiles <= 0) return hipSuccess;
   const size_t lds = sizeof(double) * (size_t)max_cols;
   if (fp32) {
     hipLaunchKernelGGL(gemv_batched_kernel<float>, dim3(n_tiles), dim3(kThreads), lds, s, d_desc,
-                       d_tiles, static_cast<const float *>(mat), x, xmap, y, omap, alpha, beta, y0);
+                       d_tiles, static_cast<const float *>(mat), x, xmap, y, omap, alpha, beta, y0, halt);
   } else {
     hipLaunchKernelGGL(gemv_batched_kernel<double>, dim3(n_tiles), dim3(kThreads), lds, s, d_desc,
-                       d_tiles, static_cast<const double *>(mat), x, xmap, y, omap, alpha, beta, y0);
+                       d_tiles, static_cast<const double *>(mat), x, xmap, y, omap, alpha, beta, y0, halt);
   }
   return hipGetLastError();
 }
@@ -410,7 +425,7 @@ hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *sr
   hipLaunchKernelGGL(bsr_pull_kernel, dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0,
                      c1, full ? p.d_bb_rowptr : p.d_rem_rowptr, full ? p.d_bb_col : p.d_rem_col,
                      full ? nullptr : p.d_rem_src, p.bb_val, x, c2, p.d_pull_ptr, p.d_pull_idx, t,
-                     out);
+                     out, p.halt);
   return hipGetLastError();
 }
 
@@ -445,7 +460,7 @@ hipError_t launch_precond_setup(const Plan &p, const void *t, bool fp32) {
 hipError_t launch_precond_apply(const Plan &p, int mode, const double *x, double *y, double a) {
   const int64_t n = 5 * p.n_bnodes;
   hipLaunchKernelGGL(precond_apply_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, p.stream, mode, p.n_bnodes, p.diag_s, p.pc_blk, x, y, a);
+                     dim3(kThreads), 0, p.stream, mode, p.n_bnodes, p.diag_s, p.pc_blk, x, y, a, p.halt);
   return hipGetLastError();
 }
 
@@ -478,9 +493,10 @@ hipError_t launch_scatter_axpby(int64_t n, double a, const double *x, double b, 
 }
 
 hipError_t launch_diag_scale(const double *x, const double *dinv, double *y, int64_t n, double a,
-                             hipStream_t s) {
+                             hipStream_t s, const double *a_dev, const int32_t *halt) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(diag_scale_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, x, dinv, y, n, a);
+  hipLaunchKernelGGL(diag_scale_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, x, dinv, y, n, a, a_dev,
+                     halt);
   return hipGetLastError();
 }
 
@@ -505,22 +521,105 @@ hipError_t launch_copy_f64(const double *src, double *dst, size_t n, hipStream_t
 }
 
 hipError_t launch_multidot(const double *v, int64_t ld, int32_t nv, const double *w, int64_t n,
-                           double *partials, int32_t nblocks, double *out, hipStream_t s) {
+                           double *partials, int32_t nblocks, double *out, hipStream_t s,
+                           const int32_t *halt) {
   hipLaunchKernelGGL(multidot_kernel, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n,
-                     partials);
+                     partials, halt);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int waves_per_block = kThreads / 64;
   hipLaunchKernelGGL(multidot_finish_kernel, dim3((nv + waves_per_block - 1) / waves_per_block),
-                     dim3(kThreads), 0, s, partials, nblocks, nv, out);
+                     dim3(kThreads), 0, s, partials, nblocks, nv, out, halt);
   return hipGetLastError();
 }
 
 hipError_t launch_multi_axpy(const double *v, int64_t ld, int32_t nv, const double *h, double *w,
-                             int64_t n, hipStream_t s) {
-  if (n <= 0 || nv <= 0) return hipSuccess;
+                             int64_t n, hipStream_t s, const int32_t *nv_dev, const int32_t *halt) {
+  if (n <= 0 || (nv <= 0 && !nv_dev)) return hipSuccess;
   hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, v, ld, nv, h, w,
-                     n);
+                     n, nv_dev, halt);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ device-resident GMRES
+// State of one restart cycle in device memory (no host round trip per
+// iteration): st[0] = halt (1 once converged, broken down or at the cycle's
+// iteration limit st[2]), st[1] = number of completed iterations; dev[0] =
+// 1 / h_{j+1,j} (scale of the next basis vector), dev[1] = |g_{j+1}| (residual
+// estimate), dev[2] = the absolute stopping target.  H is (m+1) x m row-major,
+// rotated in place; cs, sn the Givens rotations; g the rotated right-hand side.
+__global__ void krylov_start_kernel(double beta, double target, int limit, double *__restrict__ g,
+                                    int32_t *__restrict__ st, double *__restrict__ dev) {
+  for (int i = threadIdx.x; i <= limit; i += blockDim.x) g[i] = i == 0 ? beta : 0.0;
+  if (threadIdx.x == 0) {
+    st[0] = (beta <= target || limit <= 0) ? 1 : 0;
+    st[1] = 0;
+    st[2] = limit;
+    dev[0] = 0.0;
+    dev[1] = beta;
+    dev[2] = target;
+  }
+}
+
+// Iteration j: the Hessenberg column from the two Gram-Schmidt passes and the
+// squared norm of the orthogonalized vector (hc = [pass 1 | pass 2 | norm^2],
+// m+1 entries each), then the Givens update and the stopping test.
+__global__ void krylov_givens_kernel(int j, int m, const double *__restrict__ hc, double *__restrict__ H,
+                                     double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
+                                     int32_t *__restrict__ st, double *__restrict__ dev) {
+  if (threadIdx.x != 0 || st[0]) return;
+  for (int i = 0; i <= j; ++i) H[i * m + j] = hc[i] + hc[(m + 1) + i];
+  const double hn = sqrt(fmax(0.0, hc[2 * (m + 1)]));
+  H[(j + 1) * m + j] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = H[i * m + j], b = H[(i + 1) * m + j];
+    H[i * m + j] = cs[i] * a + sn[i] * b;
+    H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = H[j * m + j];
+  const double den = hypot(a, hn);
+  cs[j] = den > 0 ? a / den : 1.0;
+  sn[j] = den > 0 ? hn / den : 0.0;
+  H[j * m + j] = den;
+  H[(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  st[1] = j + 1;
+  dev[0] = hn > 0 ? 1.0 / hn : 0.0;
+  dev[1] = fabs(g[j + 1]);
+  if (fabs(g[j + 1]) <= dev[2] || hn == 0.0 || j + 1 >= st[2]) st[0] = 1;
+}
+
+// y = H^-1 g over the completed iterations; writes -y (the basis update
+// subtracts, see multi_axpy)
+__global__ void krylov_solve_kernel(int m, const double *__restrict__ H, const double *__restrict__ g,
+                                    const int32_t *__restrict__ st, double *__restrict__ yneg) {
+  if (threadIdx.x != 0) return;
+  const int k = st[1];
+  double y[64];
+  for (int i = k - 1; i >= 0; --i) {
+    double v = g[i];
+    for (int q = i + 1; q < k; ++q) v -= H[i * m + q] * y[q];
+    y[i] = v / H[i * m + i];
+  }
+  for (int i = 0; i < k; ++i) yneg[i] = -y[i];
+}
+
+hipError_t launch_krylov_start(double beta, double target, int limit, double *g, int32_t *st, double *dev,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(krylov_start_kernel, dim3(1), dim3(64), 0, s, beta, target, limit, g, st, dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_krylov_givens(int j, int m, const double *hc, double *H, double *cs, double *sn, double *g,
+                                int32_t *st, double *dev, hipStream_t s) {
+  hipLaunchKernelGGL(krylov_givens_kernel, dim3(1), dim3(64), 0, s, j, m, hc, H, cs, sn, g, st, dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_krylov_solve(int m, const double *H, const double *g, const int32_t *st, double *yneg,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(krylov_solve_kernel, dim3(1), dim3(64), 0, s, m, H, g, st, yneg);
   return hipGetLastError();
 }
 

@@ -136,7 +136,7 @@ struct PhaseTimer {
   int phase;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   PhaseTimer(Plan &pl, int ph) : p(pl), phase(ph) {
-    if (!p.timing) return;
+    if (!p.timing || p.capturing) return;
     if (p.ev_pool.empty()) {
       hipEvent_t a, b;
       if (hipEventCreate(&a) != hipSuccess) return;
@@ -196,7 +196,7 @@ scdg_status condense_rhs_impl(Plan &p, const double *b, double *bs) {
 scdg_status schur_apply_impl(Plan &p, const double *x, double *y) {
   PhaseTimer tm(p, SCDG_PHASE_SCHUR_APPLY);
   HIP_TRY(launch_gemv_batched(p.d_gv_s, p.d_rt_s, p.n_rt_s, p.max_nc, p.sloc, fp32(p), x, p.d_cmap,
-                              p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream));
+                              p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream, p.halt));
   // S x = A_bb,rem x + sum_e P_e T_e x[C_e],  T_e = folded A_bb blocks - A_bi(e) X_e
   HIP_TRY(launch_bsr_pull(p, false, 0.0, nullptr, nullptr, 1.0, x, 1.0, p.w_t, y));
   return SCDG_OK;
@@ -233,6 +233,148 @@ scdg_status ensure_gmres(Plan &p, int m) {
   if (p.gm_v && p.gm_m >= m) return SCDG_OK;
   ST_TRY(dalloc(p, &p.gm_v, (size_t)(m + 1) * p.n1));
   p.gm_m = m;
+  return SCDG_OK;
+}
+
+// One Arnoldi step j of the device-resident cycle: every kernel first reads the
+// halt flag (p.halt) and returns at once after convergence, so the fixed
+// sequence of m steps can be replayed from a graph.
+scdg_status krylov_step(Plan &p, int j, int m, int pmode) {
+  const int64_t n = p.n1;
+  double *vj = p.gm_v + (int64_t)j * n;
+  double *w = p.gm_w;
+  HIP_TRY(launch_precond_apply(p, pmode, vj, p.gm_z, 1.0));
+  ST_TRY(schur_apply_impl(p, p.gm_z, w));
+  HIP_TRY(launch_multidot(p.gm_v, n, j + 1, w, n, p.gm_part, p.red_blocks, p.gm_h, p.stream, p.halt));
+  HIP_TRY(launch_multi_axpy(p.gm_v, n, j + 1, p.gm_h, w, n, p.stream, nullptr, p.halt));
+  HIP_TRY(launch_multidot(p.gm_v, n, j + 1, w, n, p.gm_part, p.red_blocks, p.gm_h + (m + 1), p.stream, p.halt));
+  HIP_TRY(launch_multi_axpy(p.gm_v, n, j + 1, p.gm_h + (m + 1), w, n, p.stream, nullptr, p.halt));
+  HIP_TRY(launch_multidot(w, 0, 1, w, n, p.gm_part, p.red_blocks, p.gm_h + 2 * (m + 1), p.stream, p.halt));
+  HIP_TRY(launch_krylov_givens(j, m, p.gm_h, p.kr_H, p.kr_cs, p.kr_sn, p.kr_g, p.kr_st, p.kr_dev, p.stream));
+  HIP_TRY(launch_diag_scale(w, nullptr, p.gm_v + (int64_t)(j + 1) * n, n, 1.0, p.stream, p.kr_dev, p.halt));
+  return SCDG_OK;
+}
+
+void drop_krylov_graph(Plan &p) {
+  if (p.kr_exec) (void)hipGraphExecDestroy(p.kr_exec);
+  if (p.kr_graph) (void)hipGraphDestroy(p.kr_graph);
+  p.kr_exec = nullptr;
+  p.kr_graph = nullptr;
+}
+
+// The m Arnoldi steps of a cycle as a graph (captured once per configuration).
+scdg_status krylov_graph(Plan &p, int m, int pmode) {
+  KrylovKey key;
+  key.m = m;
+  key.pmode = pmode;
+  key.fp32 = fp32(p);
+  key.sloc = p.sloc;
+  key.bb_val = p.bb_val;
+  key.gm_v = p.gm_v;
+  if (p.kr_exec && p.kr_key == key) return SCDG_OK;
+  drop_krylov_graph(p);
+  if (!p.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
+  // capture on the plan's own stream (the caller's may be the null stream,
+  // which cannot be captured); the graph is launched on the caller's stream
+  hipStream_t user = p.stream;
+  p.stream = p.cap_stream;
+  HIP_TRY(hipStreamBeginCapture(p.stream, hipStreamCaptureModeRelaxed));
+  p.capturing = true;
+  scdg_status st = SCDG_OK;
+  for (int j = 0; j < m && st == SCDG_OK; ++j) st = krylov_step(p, j, m, pmode);
+  p.capturing = false;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(p.stream, &g);
+  p.stream = user;
+  if (st != SCDG_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    p.last_error = "capture of the GMRES cycle failed";
+    return st != SCDG_OK ? st : SCDG_ERR_HIP;
+  }
+  if (hipGraphInstantiate(&p.kr_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    p.kr_exec = nullptr;
+    p.last_error = "instantiation of the GMRES cycle graph failed";
+    return SCDG_ERR_HIP;
+  }
+  p.kr_graph = g;
+  p.kr_key = key;
+  return SCDG_OK;
+}
+
+scdg_status ensure_krylov_state(Plan &p, int m) {
+  if (p.kr_H && p.kr_m >= m) return SCDG_OK;
+  dfree(p.kr_H); dfree(p.kr_cs); dfree(p.kr_sn); dfree(p.kr_g); dfree(p.kr_st); dfree(p.kr_dev);
+  ST_TRY(dalloc(p, &p.kr_H, (size_t)(m + 1) * m));
+  ST_TRY(dalloc(p, &p.kr_cs, (size_t)m));
+  ST_TRY(dalloc(p, &p.kr_sn, (size_t)m));
+  ST_TRY(dalloc(p, &p.kr_g, (size_t)m + 1));
+  ST_TRY(dalloc(p, &p.kr_st, (size_t)4));
+  ST_TRY(dalloc(p, &p.kr_dev, (size_t)4));
+  p.kr_m = m;
+  return SCDG_OK;
+}
+
+// Restart cycles with the Hessenberg column, the Givens rotations and the stopping
+// test on the device; the host waits once per cycle (true residual).  r holds
+// bs - S x on entry, beta its norm.
+scdg_status gmres_device_cycles(Plan &p, const double *bs, double *x, double *r, double bnorm, double beta,
+                                const scdg_solve_opts &o, scdg_solve_info &info) {
+  const int64_t n = p.n1;
+  const int m = o.restart;
+  const int pmode = o.precond;
+  const double target = o.tol * bnorm;
+  ST_TRY(ensure_krylov_state(p, m));
+  const bool use_graph = p.krylov_mode == 2;
+  if (use_graph) {
+    p.halt = p.kr_st;
+    scdg_status st = krylov_graph(p, m, pmode);
+    p.halt = nullptr;
+    if (st != SCDG_OK) return st;
+  }
+  int it = 0;
+  while (it < o.max_iters && beta > target) {
+    if (!std::isfinite(beta)) {
+      p.last_error = "non-finite GMRES residual";
+      return SCDG_ERR_NONFINITE;
+    }
+    ++info.restarts;
+    const int limit = std::min(m, o.max_iters - it);
+    HIP_TRY(launch_diag_scale(r, nullptr, p.gm_v, n, 1.0 / beta, p.stream));
+    HIP_TRY(launch_krylov_start(beta, target, limit, p.kr_g, p.kr_st, p.kr_dev, p.stream));
+    if (use_graph) {
+      HIP_TRY(hipGraphLaunch(p.kr_exec, p.stream));
+    } else {
+      p.halt = p.kr_st;
+      scdg_status st = SCDG_OK;
+      for (int j = 0; j < limit && st == SCDG_OK; ++j) st = krylov_step(p, j, m, pmode);
+      p.halt = nullptr;
+      if (st != SCDG_OK) return st;
+    }
+    // x += Dinv (V y)
+    HIP_TRY(launch_krylov_solve(m, p.kr_H, p.kr_g, p.kr_st, p.gm_h, p.stream));
+    HIP_TRY(hipMemsetAsync(p.gm_z, 0, sizeof(double) * n, p.stream));
+    HIP_TRY(launch_multi_axpy(p.gm_v, n, m, p.gm_h, p.gm_z, n, p.stream, p.kr_st + 1, nullptr));
+    HIP_TRY(launch_precond_apply(p, pmode, p.gm_z, p.gm_w, 1.0));
+    HIP_TRY(launch_axpby(n, 1.0, p.gm_w, 1.0, x, p.stream));
+    HIP_TRY(hipMemcpyAsync(p.h_pinned + 8, p.kr_st, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, p.stream));
+    // true residual
+    ST_TRY(schur_apply_impl(p, x, r));
+    HIP_TRY(launch_axpby(n, 1.0, bs, -1.0, r, p.stream));
+    double beta2;
+    ST_TRY(norm2sq(p, r, n, &beta2));
+    int32_t done[2];
+    std::memcpy(done, p.h_pinned + 8, sizeof(done));
+    it += done[1];
+    beta = std::sqrt(beta2);
+    info.rel_res_S = beta / bnorm;
+    if (done[1] == 0) break;   // no progress possible (breakdown at the first step)
+  }
+  info.iters += it;
+  if (beta > target) {
+    p.last_error = "GMRES did not reach the tolerance";
+    return SCDG_ERR_NOCONV;
+  }
   return SCDG_OK;
 }
 
@@ -274,6 +416,7 @@ scdg_status gmres(Plan &p, const double *bs, double *x, const double *x0, const 
     HIP_TRY(hipMemcpyAsync(r, bs, sizeof(double) * n, hipMemcpyDeviceToDevice, p.stream));
     beta = bnorm;
   }
+  if (p.krylov_mode != 0) return gmres_device_cycles(p, bs, x, r, bnorm, beta, o, info);
   std::vector<double> h((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   int it = 0;
   const double target = o.tol * bnorm;
@@ -448,6 +591,9 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.d_gx); dfree(p.d_gs); dfree(p.d_tiles_x); dfree(p.d_tiles_s);
   dfree(p.d_gv_inv); dfree(p.d_gv_abi); dfree(p.d_gv_aib); dfree(p.d_gv_s);
   dfree(p.d_rt_inv); dfree(p.d_rt_abi); dfree(p.d_rt_aib); dfree(p.d_rt_s);
+  drop_krylov_graph(p);
+  if (p.cap_stream) (void)hipStreamDestroy(p.cap_stream);
+  dfree(p.kr_H); dfree(p.kr_cs); dfree(p.kr_sn); dfree(p.kr_g); dfree(p.kr_st); dfree(p.kr_dev);
   dfree(p.d_gj_voff); dfree(p.d_gj_piv); dfree(p.d_gj_flag); dfree(p.gj_pbuf); dfree(p.gj_rbuf);
   dfree(p.d_gj_desc); dfree(p.d_gj_tiles);
   dfree(p.ainv); dfree(p.ainv_work); dfree(p.xmat); dfree(p.sloc); dfree(p.aib_lo); dfree(p.abi_lo); dfree(p.diag_s);
@@ -872,6 +1018,12 @@ scdg_status scdg_factor(scdg_plan *pl, scdg_precision prec) {
   p.inverse_used = blocked ? 2 : 1;
   p.state = 2;
   p.dense_factored = false;
+  return SCDG_OK;
+}
+
+scdg_status scdg_set_krylov_mode(scdg_plan *pl, int32_t mode) {
+  if (!pl || mode < 0 || mode > 2) return SCDG_ERR_ARG;
+  pl->p.krylov_mode = mode;
   return SCDG_OK;
 }
 

@@ -156,6 +156,12 @@ class Plan:
         self._check(self.lib.scdg_schur_apply(self.handle, _ptr(x), _ptr(y)), "scdg_schur_apply")
         return y
 
+    def set_krylov_mode(self, mode: str):
+        """'host' (Givens on the host), 'device' (device-resident cycle) or 'graph'
+        (device-resident cycle replayed from a HIP graph)."""
+        m = {"host": 0, "device": 1, "graph": 2}[mode]
+        self._check(self.lib.scdg_set_krylov_mode(self.handle, m), "scdg_set_krylov_mode")
+
     def set_inverse_mode(self, mode: str):
         """'auto', 'single' (one workgroup per element) or 'blocked'."""
         m = {"auto": 0, "single": 1, "blocked": 2}[mode]
