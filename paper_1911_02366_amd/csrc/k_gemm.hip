@@ -99,6 +99,10 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_batched_kernel(const GemmDe
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = M::zero();
 
+  // 16x16 blocks of this wave's tile that hold real rows / columns: blocks lying
+  // wholly in the zero padding of a ragged tile skip their MFMAs (wave-uniform)
+  const int tm_valid = min(TM, max(0, (d.m - (m0 + wm * WTM) + 15) / 16));
+  const int tn_valid = min(TN, max(0, (d.n - (n0 + wn * WTN) + 15) / 16));
   const int nk = (d.k + BK - 1) / BK;
   load(0);
   store(0);
@@ -118,7 +122,8 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_batched_kernel(const GemmDe
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = M::mma(af[i], bf[j], acc[i][j]);
+        for (int j = 0; j < TN; ++j)
+          if (i < tm_valid && j < tn_valid) acc[i][j] = M::mma(af[i], bf[j], acc[i][j]);
     }
     if (kt + 1 < nk) store(buf ^ 1);
     __syncthreads();
