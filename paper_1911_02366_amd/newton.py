@@ -41,7 +41,7 @@ class ImplicitStepper:
     def __init__(self, structure: dict, k_elem: int, order: int, mach: float, reynolds: float, dt: float,
                  jacobian, lin_tol: float = 1e-10, newton_tol: float = 1e-8, max_newton: int = 10,
                  restart: int = 30, precond: int = 1, precision: str = "fp64", autotune: bool = True,
-                 forcing: bool = True):
+                 forcing: bool = True, fp32_inner_tol: float = 1e-4):
         self.plan = Plan.from_structure(structure)
         self.dg = DgResidual(k_elem, order, mach=mach, reynolds=reynolds)
         self.dt, self.jacobian = dt, jacobian
@@ -49,12 +49,14 @@ class ImplicitStepper:
         self.restart, self.precond, self.precision = restart, precond, precision
         self._tune = autotune
         self.forcing = forcing
+        self.fp32_inner_tol = fp32_inner_tol
         self._blocks = None
         self.n_elem = len(structure["order"])
 
-    def prepare(self, q_s: torch.Tensor) -> float:
-        """Jacobian at q_s, factor and condense; returns the factor+condense seconds."""
-        blk = self.jacobian(q_s)
+    def prepare(self, q_s: torch.Tensor, blocks: dict | None = None) -> float:
+        """Jacobian at q_s (or the given blocks of it), factor and condense; returns
+        the factor+condense seconds."""
+        blk = self.jacobian(q_s) if blocks is None else blocks
         self._blocks = blk                       # the plan borrows these until the next assemble
         self.plan.assemble(blk["aii"], blk["aib"], blk["abi"], blk["bb_val"])
         torch.cuda.synchronize()
@@ -93,10 +95,13 @@ class ImplicitStepper:
                 # inexact Newton: solve only as far as the step's target needs
                 tol = min(0.1, max(self.lin_tol, 0.5 * self.newton_tol * r0 / rnorm))
             if self.precision == "fp32":
-                ir = dict(ir_tol=tol, ir_max=10)
+                # FP32 factors: loose inner GMRES, FP64 refinement on the full system to tol
+                ir = dict(ir_tol=tol, ir_max=20)
+                inner = max(tol, self.fp32_inner_tol)
             else:
                 ir = dict(ir_tol=1.0, ir_max=1)     # FP64 factors: the GMRES tolerance decides
-            dq, info = self.plan.solve(-r, x0=x0, solver="gmres", tol=tol, restart=self.restart,
+                inner = tol
+            dq, info = self.plan.solve(-r, x0=x0, solver="gmres", tol=inner, restart=self.restart,
                                        precond=self.precond, check=False, **ir)
             if info["status"] not in (0,):
                 raise RuntimeError(f"condensed solve failed: {info}")
