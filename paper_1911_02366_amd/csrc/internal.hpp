@@ -121,6 +121,7 @@ struct Plan {
   void *aib_lo = nullptr, *abi_lo = nullptr;  // FP32 shadows (FP32 mode)
   double *diag_s = nullptr;  // [n1] 1 / diag(S) (point Jacobi)
   double *pc_blk = nullptr;  // [n_bnodes * 25] inverse 5x5 diagonal blocks of S
+  double *rem_val = nullptr; // [n_rem * 25] A_bb remainder blocks in remainder order
   size_t cap_ainv = 0, cap_x = 0, cap_s = 0;  // bytes allocated
 
   // blocked Gauss-Jordan inverse (outer panels of kGjOuter columns)
@@ -211,6 +212,9 @@ hipError_t launch_precond_setup(const Plan &p, const void *t, bool fp32);
 hipError_t launch_precond_apply(const Plan &p, int mode, const double *x, double *y, double a);
 
 hipError_t launch_gather(const double *src, const int32_t *map, double *dst, int64_t n, hipStream_t s);
+// dst[b * 25 + k] = src[idx[b] * 25 + k]  (5x5 blocks)
+hipError_t launch_gather_blocks(const double *src, const int32_t *idx, double *dst, int64_t nblocks,
+                                hipStream_t s);
 hipError_t launch_scatter(const double *src, const int32_t *map, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 hipError_t launch_scatter_axpby(int64_t n, double a, const double *x, double b, const double *yin,

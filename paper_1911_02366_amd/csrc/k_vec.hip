@@ -285,6 +285,13 @@ __global__ void gather_kernel(const double *__restrict__ src, const int32_t *__r
     dst[i] = src[map[i]];
 }
 
+__global__ void gather_blocks_kernel(const double *__restrict__ src, const int32_t *__restrict__ idx,
+                                     double *__restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * 25;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[(int64_t)idx[i / 25] * 25 + i % 25];
+}
+
 __global__ void scatter_kernel(const double *__restrict__ src, const int32_t *__restrict__ map,
                                double *__restrict__ dst, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -424,7 +431,7 @@ hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *sr
   const int grid = (int)((nb + (kThreads / 64) - 1) / (kThreads / 64));
   hipLaunchKernelGGL(bsr_pull_kernel, dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0,
                      c1, full ? p.d_bb_rowptr : p.d_rem_rowptr, full ? p.d_bb_col : p.d_rem_col,
-                     full ? nullptr : p.d_rem_src, p.bb_val, x, c2, p.d_pull_ptr, p.d_pull_idx, t,
+                     nullptr, full ? p.bb_val : p.rem_val, x, c2, p.d_pull_ptr, p.d_pull_idx, t,
                      out, p.halt);
   return hipGetLastError();
 }
@@ -468,6 +475,14 @@ hipError_t launch_gather(const double *src, const int32_t *map, double *dst, int
                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(gather_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, src, map, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_blocks(const double *src, const int32_t *idx, double *dst, int64_t nblocks,
+                                hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_blocks_kernel, dim3(grid_for(nblocks * 25)), dim3(kThreads), 0, s, src, idx, dst,
+                     nblocks);
   return hipGetLastError();
 }
 

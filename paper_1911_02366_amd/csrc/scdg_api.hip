@@ -586,7 +586,7 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.d_imap); dfree(p.d_bmap); dfree(p.d_cmap); dfree(p.d_pull_ptr); dfree(p.d_pull_idx);
   dfree(p.d_slot_soff); dfree(p.d_slot_nc); dfree(p.d_slot_pos);
   dfree(p.d_fold_dst); dfree(p.d_fold_nc); dfree(p.d_fold_src);
-  dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk);
+  dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk); dfree(p.rem_val);
   dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_inv_order); dfree(p.d_info);
   dfree(p.d_gx); dfree(p.d_gs); dfree(p.d_tiles_x); dfree(p.d_tiles_s);
   dfree(p.d_gv_inv); dfree(p.d_gv_abi); dfree(p.d_gv_aib); dfree(p.d_gv_s);
@@ -1106,6 +1106,12 @@ scdg_status scdg_condense(scdg_plan *pl) {
                                 -1.0, 0.0, fp32(p), p.stream));
   }
   HIP_TRY(launch_fold_add(p, p.sloc, fp32(p)));
+  // the A_bb remainder blocks, copied contiguously in remainder order: every
+  // Schur product then streams them instead of gathering from A_bb
+  if (p.n_rem > 0) {
+    if (!p.rem_val) ST_TRY(dalloc(p, &p.rem_val, (size_t)p.n_rem * 25));
+    HIP_TRY(launch_gather_blocks(p.bb_val, p.d_rem_src, p.rem_val, p.n_rem, p.stream));
+  }
   HIP_TRY(launch_precond_setup(p, p.sloc, fp32(p)));
   p.state = 3;
   p.dense_factored = false;
