@@ -278,6 +278,62 @@ scdg_status scdg_dg_residual(scdg_dg *dg, const double *q, const double *q_s, do
 scdg_status scdg_dg_gradient(scdg_dg *dg, double *g);
 
 /* ------------------------------------------------------------------------
+ * Newton iterations of one backward-Euler step, each iteration one replay of
+ * a HIP graph (the Newton linearization of eq. NewtonLinSys1 solved by static
+ * condensation, eq. SC_step1 and SC_step2):
+ *
+ *     B = -R(Q);  b_S = condense(B);  S x = b_S by GMRES(m);
+ *     dQ = backsolve(B, x);  Q += dQ;  R(Q) and ||R(Q)||
+ *
+ * with R from the scdg_dg object and A, S from the plan: the plan must be
+ * condensed (scdg_condense) for a Jacobian supplied by the caller, usually at
+ * Q_s, and that Jacobian is kept for every iteration of the step (a chord
+ * iteration; with FP32 factors the FP64 nonlinear residual drives the
+ * refinement).  Each replay runs `cycles` GMRES restart cycles whose kernels
+ * return at once after the tolerance is met (flags in device memory); the
+ * host reads ||R(Q)|| after each replay and stops when
+ * ||R(Q)|| <= newton_tol ||R(Q_s)||.  The GMRES tolerance of an iteration is
+ * clip(forcing * newton_tol * ||R(Q_s)|| / ||R(Q)||, lin_tol, eta_max)
+ * (inexact Newton; forcing = 0 gives lin_tol).  GMRES starts from zero; a
+ * guess enters as the starting state Q.
+ *
+ * q_s (device, read only) is the state at the previous time level; q (device,
+ * in: starting state, e.g. a copy of q_s or q_s plus a predicted increment;
+ * out: the new state) must not alias q_s.  Both hold n_dof doubles in the
+ * natural DOF order, which must match the dg object's size.  If the starting
+ * state has a larger residual than Q_s it is replaced by Q_s
+ * (info.start_rejected).  The graph is captured on the first call and reused
+ * while q, q_s, dg, inv_dt, the options and the plan's buffers stay the same;
+ * keep them fixed across steps to avoid a new capture.  The call synchronizes
+ * the plan's stream.  Errors: SCDG_ERR_STATE before scdg_condense,
+ * SCDG_ERR_ARG for sizes that differ or restart > 63, SCDG_ERR_NONFINITE when
+ * a residual norm is not finite, SCDG_ERR_NOCONV when max_newton iterations
+ * end above the tolerance (q then holds the last iterate).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double newton_tol;   /* relative to ||R(Q_s)||; <= 0 selects 1e-8 */
+  double lin_tol;      /* floor of the GMRES tolerance; <= 0 selects 1e-10 */
+  double forcing;      /* < 0 selects 0.5; 0 disables the forcing term */
+  double eta_max;      /* cap of the GMRES tolerance; <= 0 selects 0.1 */
+  int32_t restart;     /* GMRES(m), <= 0 selects 30, at most 63 */
+  int32_t cycles;      /* restart cycles per Newton iteration, <= 0 selects 4, at most 64 */
+  int32_t precond;     /* 0 none, 1 point Jacobi, 2 5x5 node-block Jacobi; < 0 selects 1 */
+  int32_t max_newton;  /* <= 0 selects 10 */
+} scdg_newton_opts;
+typedef struct {
+  int32_t newton;          /* Newton iterations (graph replays) */
+  int32_t gmres;           /* GMRES iterations, all Newton iterations */
+  int32_t first_gmres;     /* GMRES iterations of the first Newton iteration */
+  int32_t lin_unconverged; /* iterations whose GMRES ended at the cycle budget above its tolerance */
+  int32_t start_rejected;  /* the starting state was replaced by Q_s */
+  int32_t converged;       /* ||R(Q)|| <= newton_tol ||R(Q_s)|| on return */
+  double r0;               /* ||R(Q_s)|| */
+  double rel_res;          /* ||R(Q)|| / ||R(Q_s)|| on return */
+} scdg_newton_info;
+scdg_status scdg_newton_step(scdg_plan *p, scdg_dg *dg, const double *q_s, double inv_dt, double *q,
+                             const scdg_newton_opts *o, scdg_newton_info *info);
+
+/* ------------------------------------------------------------------------
  * Learned initial guess.  A per-element multilayer perceptron maps an
  * element's state and its previous Newton increment to a prediction of the
  * next increment; its boundary part serves as the initial guess x0 of the

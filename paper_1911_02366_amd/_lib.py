@@ -26,7 +26,7 @@ EXPORTED = [
     "scdg_schur_apply", "scdg_export", "scdg_status_string", "scdg_last_error",
     "scdg_enable_timing", "scdg_phase_times", "scdg_autotune", "scdg_set_gemm_config",
     "scdg_get_gemm_config", "scdg_plan_fold_counts", "scdg_set_inverse_mode", "scdg_get_inverse_mode",
-    "scdg_set_krylov_mode",
+    "scdg_set_krylov_mode", "scdg_newton_step",
     "scdg_dg_create", "scdg_dg_destroy", "scdg_dg_residual", "scdg_dg_gradient",
     "scdg_mlp_create", "scdg_mlp_destroy", "scdg_mlp_param_count", "scdg_mlp_forward",
     "scdg_mlp_backward", "scdg_mlp_adam", "scdg_mlp_mse", "scdg_mlp_gather", "scdg_guess_stats",
@@ -63,6 +63,21 @@ class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("ir_sweeps", C.c_int32),
                 ("solver_used", C.c_int32), ("rel_res_S", C.c_double), ("rel_res_full", C.c_double),
                 ("guess_rejected", C.c_int32), ("rel_res_guess", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("newton_tol", C.c_double), ("lin_tol", C.c_double), ("forcing", C.c_double),
+                ("eta_max", C.c_double), ("restart", C.c_int32), ("cycles", C.c_int32),
+                ("precond", C.c_int32), ("max_newton", C.c_int32)]
+
+
+class NewtonInfo(C.Structure):
+    _fields_ = [("newton", C.c_int32), ("gmres", C.c_int32), ("first_gmres", C.c_int32),
+                ("lin_unconverged", C.c_int32), ("start_rejected", C.c_int32), ("converged", C.c_int32),
+                ("r0", C.c_double), ("rel_res", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -113,6 +128,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_set_inverse_mode": (i32, [vp, i32]),
         "scdg_set_krylov_mode": (i32, [vp, i32]),
         "scdg_get_inverse_mode": (i32, [vp, C.POINTER(i32)]),
+        "scdg_newton_step": (i32, [vp, vp, vp, d, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo)]),
         "scdg_dg_create": (i32, [C.POINTER(vp), C.POINTER(DgParams), vp]),
         "scdg_dg_destroy": (i32, [vp]),
         "scdg_dg_residual": (i32, [vp, vp, vp, d, vp]),

@@ -37,6 +37,25 @@ struct GemvDesc {
 };
 
 // What a captured GMRES cycle depends on; a different key means recapture.
+// Everything a captured Newton iteration depends on: scalars baked into kernel
+// arguments and every device pointer its kernels read or write.
+struct NewtonKey {
+  int m = 0, cycles = 0, pmode = -1;
+  bool fp32 = false;
+  double inv_dt = 0, eta_c = 0, lin_tol = 0, eta_max = 0;
+  const void *q = nullptr, *q_s = nullptr, *dg = nullptr;
+  const void *ptr[18] = {};
+  bool operator==(const NewtonKey &o) const {
+    if (m != o.m || cycles != o.cycles || pmode != o.pmode || fp32 != o.fp32 || inv_dt != o.inv_dt ||
+        eta_c != o.eta_c || lin_tol != o.lin_tol || eta_max != o.eta_max || q != o.q || q_s != o.q_s ||
+        dg != o.dg)
+      return false;
+    for (int i = 0; i < 18; ++i)
+      if (ptr[i] != o.ptr[i]) return false;
+    return true;
+  }
+};
+
 struct KrylovKey {
   int m = 0, pmode = -1;
   bool fp32 = false;
@@ -172,6 +191,14 @@ struct Plan {
   hipGraph_t kr_graph = nullptr;
   hipGraphExec_t kr_exec = nullptr;
   KrylovKey kr_key{};
+
+  // one Newton iteration of a backward-Euler step as a graph (scdg_newton_step)
+  double *nw_r = nullptr;      // [n_dof] nonlinear residual R(Q)
+  double *nw_dq = nullptr;     // [n_dof] minus the Newton increment
+  double *nw_stat = nullptr;   // [8] norms, see newton_gmres_setup_kernel
+  hipGraph_t nw_graph = nullptr;
+  hipGraphExec_t nw_exec = nullptr;
+  NewtonKey nw_key{};
   int32_t red_blocks = 0;
 
   // phase timing (events recorded asynchronously, summed on query)
@@ -216,7 +243,9 @@ hipError_t launch_gather(const double *src, const int32_t *map, double *dst, int
 hipError_t launch_gather_blocks(const double *src, const int32_t *idx, double *dst, int64_t nblocks,
                                 hipStream_t s);
 hipError_t launch_scatter(const double *src, const int32_t *map, double *dst, int64_t n, hipStream_t s);
-hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s,
+                        const int32_t *halt = nullptr);
+hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s, const int32_t *halt = nullptr);
 hipError_t launch_scatter_axpby(int64_t n, double a, const double *x, double b, const double *yin,
                                 const int32_t *map, double *dst, hipStream_t s);
 
@@ -238,7 +267,16 @@ hipError_t launch_krylov_start(double beta, double target, int limit, double *g,
 hipError_t launch_krylov_givens(int j, int m, const double *hc, double *H, double *cs, double *sn, double *g,
                                 int32_t *st, double *dev, hipStream_t s);
 hipError_t launch_krylov_solve(int m, const double *H, const double *g, const int32_t *st, double *yneg,
-                               hipStream_t s);
+                               hipStream_t s, const int32_t *halt = nullptr);
+hipError_t launch_newton_gmres_setup(const double *stat, double eta_c, double lin_tol, double eta_max, int m,
+                                     double *g, int32_t *st, double *dev, hipStream_t s);
+hipError_t launch_newton_gmres_restart(const double *stat, int m, double *g, int32_t *st, double *dev,
+                                       hipStream_t s);
+
+// device residual R(Q) of a scdg_dg object (k_dgsem.hip), enqueued on stream s
+hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, double inv_dt, double *r,
+                          hipStream_t s);
+int64_t dg_dof_count(const scdg_dg *dg);
 
 // dense path
 hipError_t launch_dense_assemble(const Plan &p, double *s_dense);

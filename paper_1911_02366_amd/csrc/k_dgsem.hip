@@ -293,6 +293,24 @@ struct scdg_dg {
   DgContext c;
 };
 
+namespace scdg {
+
+hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, double inv_dt, double *r,
+                          hipStream_t s) {
+  auto &c = dg->c;
+  const int p3 = c.host.p * c.host.p * c.host.p;
+  const int n_elem = c.host.k_elem * c.host.k_elem * c.host.k_elem;
+  const int threads = ((p3 + 63) / 64) * 64;
+  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g);
+  hipLaunchKernelGGL(residual_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
+                     c.g, q_s, inv_dt, r);
+  return hipGetLastError();
+}
+
+int64_t dg_dof_count(const scdg_dg *dg) { return 5 * dg->c.n_nodes; }
+
+}  // namespace scdg
+
 extern "C" {
 
 scdg_status scdg_dg_create(scdg_dg **out, const scdg_dg_params *prm, void *hip_stream) {
@@ -343,14 +361,7 @@ scdg_status scdg_dg_destroy(scdg_dg *dg) {
 scdg_status scdg_dg_residual(scdg_dg *dg, const double *q, const double *q_s, double inv_dt,
                              double *r) {
   if (!dg || !q || !r) return SCDG_ERR_ARG;
-  auto &c = dg->c;
-  const int p3 = c.host.p * c.host.p * c.host.p;
-  const int n_elem = c.host.k_elem * c.host.k_elem * c.host.k_elem;
-  const int threads = ((p3 + 63) / 64) * 64;
-  hipLaunchKernelGGL(scdg::lift_kernel, dim3(n_elem), dim3(threads), 0, c.stream, c.dev, q, c.g);
-  hipLaunchKernelGGL(scdg::residual_kernel, dim3(n_elem), dim3(threads),
-                     sizeof(double) * 15 * p3, c.stream, c.dev, q, c.g, q_s, inv_dt, r);
-  return hipGetLastError() == hipSuccess ? SCDG_OK : SCDG_ERR_HIP;
+  return scdg::dg_residual_on(dg, q, q_s, inv_dt, r, dg->c.stream) == hipSuccess ? SCDG_OK : SCDG_ERR_HIP;
 }
 
 scdg_status scdg_dg_gradient(scdg_dg *dg, double *g_out) {

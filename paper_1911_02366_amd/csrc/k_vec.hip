@@ -300,7 +300,8 @@ __global__ void scatter_kernel(const double *__restrict__ src, const int32_t *__
 }
 
 __global__ void axpby_kernel(int64_t n, double a, const double *__restrict__ x, double b,
-                             double *__restrict__ y) {
+                             double *__restrict__ y, const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     y[i] = a * x[i] + (b != 0.0 ? b * y[i] : 0.0);
@@ -315,6 +316,13 @@ __global__ void scatter_axpby_kernel(int64_t n, double a, const double *__restri
     const int32_t j = map[i];
     dst[j] = a * x[j] + b * yin[i];
   }
+}
+
+__global__ void fill_kernel(double *__restrict__ y, int64_t n, double v, const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
 }
 
 __global__ void diag_scale_kernel(const double *__restrict__ x, const double *__restrict__ dinv,
@@ -493,9 +501,16 @@ hipError_t launch_scatter(const double *src, const int32_t *map, double *dst, in
   return hipGetLastError();
 }
 
-hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
+hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s,
+                        const int32_t *halt) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, n, a, x, b, y);
+  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, n, a, x, b, y, halt);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s, const int32_t *halt) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, y, n, v, halt);
   return hipGetLastError();
 }
 
@@ -608,8 +623,9 @@ __global__ void krylov_givens_kernel(int j, int m, const double *__restrict__ hc
 // y = H^-1 g over the completed iterations; writes -y (the basis update
 // subtracts, see multi_axpy)
 __global__ void krylov_solve_kernel(int m, const double *__restrict__ H, const double *__restrict__ g,
-                                    const int32_t *__restrict__ st, double *__restrict__ yneg) {
-  if (threadIdx.x != 0) return;
+                                    const int32_t *__restrict__ st, double *__restrict__ yneg,
+                                    const int32_t *__restrict__ halt) {
+  if (threadIdx.x != 0 || (halt && *halt)) return;
   const int k = st[1];
   double y[64];
   for (int i = k - 1; i >= 0; --i) {
@@ -633,8 +649,75 @@ hipError_t launch_krylov_givens(int j, int m, const double *hc, double *H, doubl
 }
 
 hipError_t launch_krylov_solve(int m, const double *H, const double *g, const int32_t *st, double *yneg,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(krylov_solve_kernel, dim3(1), dim3(64), 0, s, m, H, g, st, yneg);
+                               hipStream_t s, const int32_t *halt) {
+  hipLaunchKernelGGL(krylov_solve_kernel, dim3(1), dim3(64), 0, s, m, H, g, st, yneg, halt);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ Newton iteration on the device
+// GMRES state of the condensed solve inside one Newton iteration (all in device
+// memory, so that a whole iteration can be replayed from a graph):
+//   stat[0] = ||R(Q)||^2, stat[1] = ||b_S||^2, stat[2] = ||R(Q_s)||,
+//   stat[3] = ||b_S - S x||^2 at the end of a restart cycle;
+//   st[0] Arnoldi halt, st[1] iterations of the current cycle, st[2] cycle
+//   length, st[3] solve finished (gates the end-of-cycle work), st[4] GMRES
+//   iterations of this Newton iteration, st[5] 1 if the tolerance was met.
+// The GMRES tolerance of the iteration is the inexact-Newton forcing term
+// clip(eta_c ||R(Q_s)|| / ||R(Q)||, lin_tol, eta_max) (eta_c <= 0: lin_tol).
+__global__ void newton_gmres_setup_kernel(const double *__restrict__ stat, double eta_c, double lin_tol,
+                                          double eta_max, int m, double *__restrict__ g,
+                                          int32_t *__restrict__ st, double *__restrict__ dev) {
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(stat[0]), beta = sqrt(stat[1]);
+  double tol = lin_tol;
+  if (eta_c > 0.0 && rn > 0.0) tol = fmin(eta_max, fmax(lin_tol, eta_c * stat[2] / rn));
+  const double target = tol * beta;
+  for (int i = 0; i <= m; ++i) g[i] = 0.0;
+  g[0] = beta;
+  const int done = beta > target ? 0 : 1;  // also when beta is not finite
+  st[0] = done;
+  st[1] = 0;
+  st[2] = m;
+  st[3] = done;
+  st[4] = 0;
+  st[5] = beta <= target ? 1 : 0;
+  dev[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+  dev[1] = beta;
+  dev[2] = target;
+}
+
+// After the true residual of a cycle: stop, or set up the next cycle.
+__global__ void newton_gmres_restart_kernel(const double *__restrict__ stat, int m, double *__restrict__ g,
+                                            int32_t *__restrict__ st, double *__restrict__ dev) {
+  if (threadIdx.x != 0 || st[3]) return;
+  const int it = st[1];
+  st[4] += it;
+  const double beta = sqrt(stat[3]);
+  dev[1] = beta;
+  st[1] = 0;
+  if (!(beta > dev[2]) || it == 0) {
+    // met the tolerance, not finite, or no progress possible
+    st[0] = 1;
+    st[3] = 1;
+    st[5] = beta <= dev[2] ? 1 : 0;
+    return;
+  }
+  for (int i = 0; i <= m; ++i) g[i] = 0.0;
+  g[0] = beta;
+  st[0] = 0;
+  dev[0] = 1.0 / beta;
+}
+
+hipError_t launch_newton_gmres_setup(const double *stat, double eta_c, double lin_tol, double eta_max, int m,
+                                     double *g, int32_t *st, double *dev, hipStream_t s) {
+  hipLaunchKernelGGL(newton_gmres_setup_kernel, dim3(1), dim3(64), 0, s, stat, eta_c, lin_tol, eta_max, m, g,
+                     st, dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_newton_gmres_restart(const double *stat, int m, double *g, int32_t *st, double *dev,
+                                       hipStream_t s) {
+  hipLaunchKernelGGL(newton_gmres_restart_kernel, dim3(1), dim3(64), 0, s, stat, m, g, st, dev);
   return hipGetLastError();
 }
 

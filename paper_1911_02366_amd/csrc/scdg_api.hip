@@ -309,7 +309,7 @@ scdg_status ensure_krylov_state(Plan &p, int m) {
   ST_TRY(dalloc(p, &p.kr_cs, (size_t)m));
   ST_TRY(dalloc(p, &p.kr_sn, (size_t)m));
   ST_TRY(dalloc(p, &p.kr_g, (size_t)m + 1));
-  ST_TRY(dalloc(p, &p.kr_st, (size_t)4));
+  ST_TRY(dalloc(p, &p.kr_st, (size_t)8));
   ST_TRY(dalloc(p, &p.kr_dev, (size_t)4));
   p.kr_m = m;
   return SCDG_OK;
@@ -495,6 +495,119 @@ scdg_status gmres(Plan &p, const double *bs, double *x, const double *x0, const 
   return SCDG_OK;
 }
 
+// ---- one Newton iteration of the implicit step, captured as a graph ----
+
+void drop_newton_graph(Plan &p) {
+  if (p.nw_exec) (void)hipGraphExecDestroy(p.nw_exec);
+  if (p.nw_graph) (void)hipGraphDestroy(p.nw_graph);
+  p.nw_exec = nullptr;
+  p.nw_graph = nullptr;
+}
+
+struct NewtonSetup {
+  int m, cycles, pmode;
+  double eta_c, lin_tol, eta_max, inv_dt;
+};
+
+NewtonKey newton_key(const Plan &p, scdg_dg *dg, const double *q_s, const double *q, const NewtonSetup &ns) {
+  NewtonKey k;
+  k.m = ns.m;
+  k.cycles = ns.cycles;
+  k.pmode = ns.pmode;
+  k.fp32 = fp32(p);
+  k.inv_dt = ns.inv_dt;
+  k.eta_c = ns.eta_c;
+  k.lin_tol = ns.lin_tol;
+  k.eta_max = ns.eta_max;
+  k.q = q;
+  k.q_s = q_s;
+  k.dg = dg;
+  const void *ptrs[18] = {p.ainv, p.xmat, p.sloc,  p.abi,  p.abi_lo, p.bb_val, p.rem_val, p.gm_v,  p.nw_r,
+                          p.nw_dq, p.diag_s, p.pc_blk, p.kr_H, p.kr_cs, p.kr_sn,  p.kr_g,   p.kr_st,  p.kr_dev};
+  for (int i = 0; i < 18; ++i) k.ptr[i] = ptrs[i];
+  return k;
+}
+
+// Enqueue one Newton iteration on p.stream.  On entry nw_r holds R(Q) and
+// nw_stat[0] its squared norm, nw_stat[2] = ||R(Q_s)||; on exit q is updated and
+// nw_r, nw_stat[0] hold the new residual.  The linear system is solved for the
+// right-hand side R (not -R): x = S^-1 condense(R), nw_dq = backsolve(R, x) = -dQ.
+scdg_status newton_iteration(Plan &p, scdg_dg *dg, const double *q_s, double *q, const NewtonSetup &ns) {
+  const int64_t n = p.n1;
+  const int m = ns.m;
+  double *bs = p.w_bs, *x = p.w_qb, *rg = p.gm_w;
+  int32_t *st = p.kr_st;
+  const int32_t *done = p.kr_st + 3;
+  p.halt = nullptr;
+  ST_TRY(condense_rhs_impl(p, p.nw_r, bs));
+  HIP_TRY(launch_multidot(bs, 0, 1, bs, n, p.gm_part, p.red_blocks, p.nw_stat + 1, p.stream));
+  HIP_TRY(launch_fill(x, n, 0.0, p.stream));
+  HIP_TRY(launch_newton_gmres_setup(p.nw_stat, ns.eta_c, ns.lin_tol, ns.eta_max, m, p.kr_g, st, p.kr_dev,
+                                    p.stream));
+  HIP_TRY(launch_diag_scale(bs, nullptr, p.gm_v, n, 1.0, p.stream, p.kr_dev, done));
+  for (int c = 0; c < ns.cycles; ++c) {
+    p.halt = st;
+    scdg_status s1 = SCDG_OK;
+    for (int j = 0; j < m && s1 == SCDG_OK; ++j) s1 = krylov_step(p, j, m, ns.pmode);
+    if (s1 != SCDG_OK) {
+      p.halt = nullptr;
+      return s1;
+    }
+    // end of the cycle: x += Dinv V y, true residual, restart or stop
+    p.halt = done;
+    HIP_TRY(launch_krylov_solve(m, p.kr_H, p.kr_g, st, p.gm_h, p.stream, done));
+    HIP_TRY(launch_fill(p.gm_z, n, 0.0, p.stream, done));
+    HIP_TRY(launch_multi_axpy(p.gm_v, n, m, p.gm_h, p.gm_z, n, p.stream, st + 1, done));
+    HIP_TRY(launch_precond_apply(p, ns.pmode, p.gm_z, rg, 1.0));
+    HIP_TRY(launch_axpby(n, 1.0, rg, 1.0, x, p.stream, done));
+    s1 = schur_apply_impl(p, x, rg);
+    if (s1 != SCDG_OK) {
+      p.halt = nullptr;
+      return s1;
+    }
+    HIP_TRY(launch_axpby(n, 1.0, bs, -1.0, rg, p.stream, done));
+    HIP_TRY(launch_multidot(rg, 0, 1, rg, n, p.gm_part, p.red_blocks, p.nw_stat + 3, p.stream, done));
+    HIP_TRY(launch_newton_gmres_restart(p.nw_stat, m, p.kr_g, st, p.kr_dev, p.stream));
+    HIP_TRY(launch_diag_scale(rg, nullptr, p.gm_v, n, 1.0, p.stream, p.kr_dev, done));
+  }
+  p.halt = nullptr;
+  ST_TRY(backsolve_impl(p, p.nw_r, x, p.nw_dq));
+  HIP_TRY(launch_axpby(p.n_dof, -1.0, p.nw_dq, 1.0, q, p.stream));
+  HIP_TRY(dg_residual_on(dg, q, q_s, ns.inv_dt, p.nw_r, p.stream));
+  HIP_TRY(launch_multidot(p.nw_r, 0, 1, p.nw_r, p.n_dof, p.gm_part, p.red_blocks, p.nw_stat, p.stream));
+  return SCDG_OK;
+}
+
+scdg_status newton_graph(Plan &p, scdg_dg *dg, const double *q_s, double *q, const NewtonSetup &ns) {
+  const NewtonKey key = newton_key(p, dg, q_s, q, ns);
+  if (p.nw_exec && p.nw_key == key) return SCDG_OK;
+  drop_newton_graph(p);
+  if (!p.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
+  hipStream_t user = p.stream;
+  p.stream = p.cap_stream;
+  HIP_TRY(hipStreamBeginCapture(p.stream, hipStreamCaptureModeRelaxed));
+  p.capturing = true;
+  const scdg_status st = newton_iteration(p, dg, q_s, q, ns);
+  p.capturing = false;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(p.stream, &g);
+  p.stream = user;
+  if (st != SCDG_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    p.last_error = "capture of the Newton iteration failed";
+    return st != SCDG_OK ? st : SCDG_ERR_HIP;
+  }
+  if (hipGraphInstantiate(&p.nw_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    p.nw_exec = nullptr;
+    p.last_error = "instantiation of the Newton iteration graph failed";
+    return SCDG_ERR_HIP;
+  }
+  p.nw_graph = g;
+  p.nw_key = key;
+  return SCDG_OK;
+}
+
 scdg_status dense_solve(Plan &p, const double *bs, double *x) {
   if (!p.dense_factored) {
     ST_TRY(dalloc(p, &p.s_dense, (size_t)p.n1 * p.n1));
@@ -594,6 +707,8 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   drop_krylov_graph(p);
   if (p.cap_stream) (void)hipStreamDestroy(p.cap_stream);
   dfree(p.kr_H); dfree(p.kr_cs); dfree(p.kr_sn); dfree(p.kr_g); dfree(p.kr_st); dfree(p.kr_dev);
+  drop_newton_graph(p);
+  dfree(p.nw_r); dfree(p.nw_dq); dfree(p.nw_stat);
   dfree(p.d_gj_voff); dfree(p.d_gj_piv); dfree(p.d_gj_flag); dfree(p.gj_pbuf); dfree(p.gj_rbuf);
   dfree(p.d_gj_desc); dfree(p.d_gj_tiles);
   dfree(p.ainv); dfree(p.ainv_work); dfree(p.xmat); dfree(p.sloc); dfree(p.aib_lo); dfree(p.abi_lo); dfree(p.diag_s);
@@ -1244,6 +1359,94 @@ scdg_status scdg_solve(scdg_plan *pl, const double *b, double *dq, const double 
   }
   ST_TRY(sync(p));
   return st;
+}
+
+scdg_status scdg_newton_step(scdg_plan *pl, scdg_dg *dg, const double *q_s, double inv_dt, double *q,
+                             const scdg_newton_opts *o, scdg_newton_info *info) {
+  if (!pl || !dg || !q_s || !q || q == q_s) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (p.state < 3) {
+    p.last_error = "scdg_newton_step before scdg_condense";
+    return SCDG_ERR_STATE;
+  }
+  if (dg_dof_count(dg) != p.n_dof) {
+    p.last_error = "residual object and plan differ in size";
+    return SCDG_ERR_ARG;
+  }
+  scdg_newton_opts opt{};
+  if (o) opt = *o;
+  else opt.forcing = -1, opt.precond = -1;
+  const double newton_tol = opt.newton_tol > 0 ? opt.newton_tol : 1e-8;
+  NewtonSetup ns;
+  ns.m = opt.restart > 0 ? opt.restart : 30;
+  ns.cycles = opt.cycles > 0 ? opt.cycles : 4;
+  ns.pmode = opt.precond < 0 ? 1 : std::min(opt.precond, 2);
+  ns.lin_tol = opt.lin_tol > 0 ? opt.lin_tol : 1e-10;
+  ns.eta_c = (opt.forcing < 0 ? 0.5 : opt.forcing) * newton_tol;
+  ns.eta_max = opt.eta_max > 0 ? opt.eta_max : 0.1;
+  ns.inv_dt = inv_dt;
+  const int max_newton = opt.max_newton > 0 ? opt.max_newton : 10;
+  if (ns.m > 63 || ns.cycles > 64 || !std::isfinite(inv_dt)) return SCDG_ERR_ARG;
+  ST_TRY(ensure_gmres(p, ns.m));
+  ST_TRY(ensure_krylov_state(p, ns.m));
+  if (!p.nw_r) ST_TRY(dalloc(p, &p.nw_r, (size_t)p.n_dof));
+  if (!p.nw_dq) ST_TRY(dalloc(p, &p.nw_dq, (size_t)p.n_dof));
+  if (!p.nw_stat) ST_TRY(dalloc(p, &p.nw_stat, (size_t)8));
+  scdg_newton_info inf{};
+  // ||R(Q_s)|| (R(Q_s) kept in nw_dq in case the starting state is rejected)
+  double r0sq, rsq;
+  HIP_TRY(dg_residual_on(dg, q_s, q_s, inv_dt, p.nw_dq, p.stream));
+  ST_TRY(norm2sq(p, p.nw_dq, p.n_dof, &r0sq));
+  HIP_TRY(dg_residual_on(dg, q, q_s, inv_dt, p.nw_r, p.stream));
+  ST_TRY(norm2sq(p, p.nw_r, p.n_dof, &rsq));
+  inf.r0 = std::sqrt(r0sq);
+  if (!std::isfinite(inf.r0)) {
+    p.last_error = "non-finite residual at Q_s";
+    if (info) *info = inf;
+    return SCDG_ERR_NONFINITE;
+  }
+  if (!(rsq <= r0sq)) {
+    inf.start_rejected = 1;
+    HIP_TRY(hipMemcpyAsync(q, q_s, sizeof(double) * p.n_dof, hipMemcpyDeviceToDevice, p.stream));
+    HIP_TRY(hipMemcpyAsync(p.nw_r, p.nw_dq, sizeof(double) * p.n_dof, hipMemcpyDeviceToDevice, p.stream));
+    rsq = r0sq;
+  }
+  double rn = std::sqrt(rsq);
+  const double target = newton_tol * inf.r0;
+  double *stage = p.h_pinned + 160;
+  stage[0] = rsq;
+  stage[1] = 0.0;
+  stage[2] = inf.r0;
+  stage[3] = 0.0;
+  HIP_TRY(hipMemcpyAsync(p.nw_stat, stage, sizeof(double) * 4, hipMemcpyHostToDevice, p.stream));
+  ST_TRY(newton_graph(p, dg, q_s, q, ns));
+  while (rn > target && inf.newton < max_newton) {
+    HIP_TRY(hipGraphLaunch(p.nw_exec, p.stream));
+    HIP_TRY(hipMemcpyAsync(stage, p.nw_stat, sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    HIP_TRY(hipMemcpyAsync(stage + 4, p.kr_st, sizeof(int32_t) * 8, hipMemcpyDeviceToHost, p.stream));
+    ST_TRY(sync(p));
+    int32_t kst[8];
+    std::memcpy(kst, stage + 4, sizeof(kst));
+    rn = std::sqrt(stage[0]);
+    if (inf.newton == 0) inf.first_gmres = kst[4];
+    inf.gmres += kst[4];
+    inf.lin_unconverged += kst[5] ? 0 : 1;
+    ++inf.newton;
+    if (!std::isfinite(rn)) {
+      p.last_error = "non-finite residual in a Newton iteration";
+      inf.rel_res = rn;
+      if (info) *info = inf;
+      return SCDG_ERR_NONFINITE;
+    }
+  }
+  inf.rel_res = inf.r0 > 0 ? rn / inf.r0 : rn;
+  inf.converged = rn <= target ? 1 : 0;
+  if (info) *info = inf;
+  if (!inf.converged) {
+    p.last_error = "Newton iterations did not reach newton_tol";
+    return SCDG_ERR_NOCONV;
+  }
+  return SCDG_OK;
 }
 
 scdg_status scdg_enable_timing(scdg_plan *pl, int on) {

@@ -41,7 +41,8 @@ class ImplicitStepper:
     def __init__(self, structure: dict, k_elem: int, order: int, mach: float, reynolds: float, dt: float,
                  jacobian, lin_tol: float = 1e-10, newton_tol: float = 1e-8, max_newton: int = 10,
                  restart: int = 30, precond: int = 1, precision: str = "fp64", autotune: bool = True,
-                 forcing: bool = True, fp32_inner_tol: float = 1e-4):
+                 forcing: bool = True, fp32_inner_tol: float = 1e-4, graph: bool = False,
+                 graph_cycles: int = 4):
         self.plan = Plan.from_structure(structure)
         self.dg = DgResidual(k_elem, order, mach=mach, reynolds=reynolds)
         self.dt, self.jacobian = dt, jacobian
@@ -52,11 +53,23 @@ class ImplicitStepper:
         self.fp32_inner_tol = fp32_inner_tol
         self._blocks = None
         self.n_elem = len(structure["order"])
+        # graph path: one captured Newton iteration replayed per iteration; the
+        # Jacobian blocks and the state vectors live in buffers that keep their
+        # addresses from step to step, so the graph is captured once
+        self.graph, self.graph_cycles = graph, graph_cycles
+        self._persist = None
+        self._q_buf = self._qs_buf = None
 
     def prepare(self, q_s: torch.Tensor, blocks: dict | None = None) -> float:
         """Jacobian at q_s (or the given blocks of it), factor and condense; returns
         the factor+condense seconds."""
         blk = self.jacobian(q_s) if blocks is None else blocks
+        if self.graph:
+            if self._persist is None:
+                self._persist = {k: torch.empty_like(blk[k]) for k in ("aii", "aib", "abi", "bb_val")}
+            for k, v in self._persist.items():
+                v.copy_(blk[k])
+            blk = self._persist
         self._blocks = blk                       # the plan borrows these until the next assemble
         self.plan.assemble(blk["aii"], blk["aib"], blk["abi"], blk["bb_val"])
         torch.cuda.synchronize()
@@ -69,8 +82,14 @@ class ImplicitStepper:
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    def solve_step(self, q_s: torch.Tensor, guess: torch.Tensor | None = None, mode: str = "gmres"):
-        """Newton iterations of one step from a prepared Jacobian; returns (q, info)."""
+    def solve_step(self, q_s: torch.Tensor, guess: torch.Tensor | None = None, mode: str = "gmres",
+                   graph: bool | None = None):
+        """Newton iterations of one step from a prepared Jacobian; returns (q, info).
+        graph (default: the stepper's setting) runs every Newton iteration as one
+        replay of the library's captured iteration (scdg_newton_step); there the
+        guess can only enter as the Newton starting state."""
+        if self.graph if graph is None else graph:
+            return self._solve_step_graph(q_s, guess, mode)
         inv_dt = 1.0 / self.dt
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -120,6 +139,34 @@ class ImplicitStepper:
                        rel_res=rnorm / r0 if r0 > 0 else 0.0, guess_rejected=rejected,
                        guess_res=guess_res,
                        seconds=time.perf_counter() - t0, converged=rnorm <= self.newton_tol * r0)
+
+    def _solve_step_graph(self, q_s: torch.Tensor, guess: torch.Tensor | None, mode: str):
+        if guess is not None and mode != "newton":
+            raise ValueError("the captured Newton iteration takes a guess only as the starting state")
+        if self._q_buf is None:
+            self._q_buf = torch.empty_like(q_s)
+            self._qs_buf = torch.empty_like(q_s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self._qs_buf.copy_(q_s)
+        if guess is None:
+            self._q_buf.copy_(q_s)
+        else:
+            torch.add(q_s, guess, out=self._q_buf)
+        lin_tol = self.lin_tol if self.precision == "fp64" else max(self.lin_tol, self.fp32_inner_tol)
+        info = self.plan.newton_step(self.dg, self._qs_buf, 1.0 / self.dt, self._q_buf, check=False,
+                                     newton_tol=self.newton_tol, lin_tol=lin_tol,
+                                     forcing=0.5 if self.forcing else 0.0, restart=self.restart,
+                                     cycles=self.graph_cycles, precond=self.precond,
+                                     max_newton=self.max_newton)
+        if info["status"] not in (0, -6):
+            raise RuntimeError(f"scdg_newton_step failed: {info}")
+        q = self._q_buf.clone()
+        torch.cuda.synchronize()
+        return q, dict(newton=info["newton"], gmres=info["gmres"], first_gmres=info["first_gmres"],
+                       rel_res=info["rel_res"], guess_rejected=info["start_rejected"] if guess is not None else 0,
+                       guess_res=1.0, lin_unconverged=info["lin_unconverged"],
+                       seconds=time.perf_counter() - t0, converged=bool(info["converged"]))
 
     def close(self):
         self.plan.close()

@@ -156,6 +156,27 @@ class Plan:
         self._check(self.lib.scdg_schur_apply(self.handle, _ptr(x), _ptr(y)), "scdg_schur_apply")
         return y
 
+    def newton_step(self, dg, q_s, inv_dt: float, q, check=True, **opts):
+        """Newton iterations of one backward-Euler step (scdg_newton_step): each
+        iteration is one replay of a captured graph.  q holds the starting state on
+        entry and the new state on return (updated in place); q_s is unchanged.
+        Options: newton_tol, lin_tol, forcing, eta_max, restart, cycles, precond,
+        max_newton (unset ones take the library defaults)."""
+        for t, name in ((q_s, "q_s"), (q, "q")):
+            if t.dtype != torch.float64 or t.numel() != self.n_dof or not t.is_contiguous():
+                raise ValueError(f"{name}: expected {self.n_dof} contiguous float64 values")
+        o = L.NewtonOpts()
+        o.forcing = -1.0
+        o.precond = -1
+        for k, v in opts.items():
+            setattr(o, k, v)
+        info = L.NewtonInfo()
+        st = self.lib.scdg_newton_step(self.handle, dg.handle, _ptr(q_s), float(inv_dt), _ptr(q), C.byref(o),
+                                       C.byref(info))
+        if check:
+            self._check(st, "scdg_newton_step")
+        return info.as_dict() | {"status": st}
+
     def set_krylov_mode(self, mode: str):
         """'host' (Givens on the host), 'device' (device-resident cycle) or 'graph'
         (device-resident cycle replayed from a HIP graph)."""
