@@ -228,6 +228,77 @@ def learned_guess_experiment(args) -> dict:
     return result
 
 
+def time_stepping_experiment(args) -> dict:
+    """Backward-Euler steps of the Taylor-Green workload with the Newton loop
+    driven from the host (one library call per linear solve, norms read back)
+    and with every Newton iteration replayed from the library's captured graph
+    (scdg_newton_step), in FP64 and with FP32 factors.  Every variant solves
+    each step from the same state, with the previous increment as the Newton
+    starting state, to the same Newton tolerance; the run advances with the
+    host FP64 solution."""
+    import numpy as np
+    import torch
+    from paper_1911_02366_amd.newton import ImplicitStepper
+    from workload.cases import WORKLOADS, build_case, jacobian_blocks
+
+    case = build_case(device="cuda", **WORKLOADS[args.ts_workload])
+    mesh, prm, dt = case.mesh, case.prm, case.dt
+    mk = lambda prec: ImplicitStepper(case.structure(), mesh.k_elem, mesh.order, prm.mach, prm.reynolds, dt,
+                                      lambda q: jacobian_blocks(q, mesh, prm, dt), lin_tol=args.lg_lin_tol,
+                                      newton_tol=args.lg_newton_tol, precision=prec, graph=True)
+    steppers = {"fp64": mk("fp64"), "fp32": mk("fp32")}
+    variants = [("host_fp64", "fp64", False), ("graph_fp64", "fp64", True),
+                ("host_fp32", "fp32", False), ("graph_fp32", "fp32", True)]
+    rec = {v: {"seconds": [], "newton": [], "gmres": [], "lin_unconverged": []} for v, _, _ in variants}
+    prep = {"fp64": [], "fp32": []}
+    diff = {"graph_fp64": [], "host_fp32": [], "graph_fp32": []}
+    q = case.q_state.reshape(-1).contiguous()
+    dq_prev = None
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    for step in range(1, args.ts_steps + 1):
+        prep["fp64"].append(steppers["fp64"].prepare(q))
+        prep["fp32"].append(steppers["fp32"].prepare(q, blocks=steppers["fp64"]._blocks))
+        out = {}
+        for name, prec, graph in variants:
+            q1, info = steppers[prec].solve_step(q, guess=dq_prev, mode="newton", graph=graph)
+            if not info["converged"]:
+                raise RuntimeError(f"step {step} ({name}) did not converge: {info}")
+            r = rec[name]
+            r["seconds"].append(info["seconds"])
+            r["newton"].append(info["newton"])
+            r["gmres"].append(info["gmres"])
+            r["lin_unconverged"].append(info.get("lin_unconverged", 0))
+            out[name] = q1
+        ref = out["host_fp64"] - q
+        for k in diff:
+            diff[k].append(float((out[k] - q - ref).norm() / ref.norm()))
+        log(f"step {step}: " + " ".join(f"{k} {rec[k]['seconds'][-1] * 1e3:.1f} ms/{rec[k]['gmres'][-1]} it"
+                                        for k in rec))
+        dq_prev = ref
+        q = out["host_fp64"]
+    mean = lambda v: float(np.mean(v[1:] if len(v) > 1 else v))    # the first step captures / autotunes
+    names = [v for v, _, _ in variants]
+    pm = {p: mean(v) for p, v in prep.items()}
+    result = {
+        "experiment": "newton_graph_time_stepping", "workload": args.ts_workload, "k_elem": mesh.k_elem,
+        "order": mesh.order, "dofs": mesh.n_dof, "steps": args.ts_steps, "newton_tol": args.lg_newton_tol,
+        "gmres_tol": args.lg_lin_tol, "graph_cycles": steppers["fp64"].graph_cycles,
+        "newton_start": "previous increment (zero at step 1)",
+        "factor_condense_seconds_per_step": pm,
+        "solve_seconds_per_step_mean": {k: mean(rec[k]["seconds"]) for k in names},
+        "newton_per_step_mean": {k: float(np.mean(rec[k]["newton"])) for k in names},
+        "gmres_per_step_mean": {k: float(np.mean(rec[k]["gmres"])) for k in names},
+        "lin_unconverged_total": {k: int(np.sum(rec[k]["lin_unconverged"])) for k in names},
+        "max_rel_diff_vs_host_fp64_increment": {k: float(np.max(v)) for k, v in diff.items()},
+    }
+    result["step_seconds_mean"] = {k: result["solve_seconds_per_step_mean"][k] + pm[k[-4:]] for k in names}
+    z = result["step_seconds_mean"]["host_fp64"]
+    result["speedup_vs_host_fp64"] = {k: z / result["step_seconds_mean"][k] for k in names}
+    for s_ in steppers.values():
+        s_.close()
+    return result
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +332,12 @@ def main() -> int:
     ap.add_argument("--lg-seed", type=int, default=0)
     ap.add_argument("--lg-lin-tol", type=float, default=1e-10)
     ap.add_argument("--lg-newton-tol", type=float, default=1e-8)
+    ap.add_argument("--autotune-cache", default=None,
+                    help="JSON file of tile choices per problem signature (default: $SCDG_AUTOTUNE_CACHE)")
+    ap.add_argument("--time-stepping", action="store_true",
+                    help="host-driven vs graph-replayed Newton iterations over implicit steps")
+    ap.add_argument("--ts-workload", default="tgv_n4_k16")
+    ap.add_argument("--ts-steps", type=int, default=8)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -274,6 +351,9 @@ def main() -> int:
         return 2
     if args.learned_guess:
         print(json.dumps(learned_guess_experiment(args)), flush=True)
+        return 0
+    if args.time_stepping:
+        print(json.dumps(time_stepping_experiment(args)), flush=True)
         return 0
     if args.calibrate_copy:
         n = (2 << 30) // 8
@@ -316,7 +396,7 @@ def main() -> int:
             return info
 
         plan.factor(precision)
-        tuning = plan.autotune()
+        tuning = plan.autotune(cache=args.autotune_cache)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -386,9 +466,9 @@ def main() -> int:
         "phase_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in phases.items()},
         "rel_res_full_max": worst,
         "variants": variants,
-        "gemm_tiles": {"x": tuning["x"], "s": tuning["s"],
-                       "autotune_ms_s": {k: round(v, 3) for k, v in tuning["ms_s"].items()},
-                       "autotune_ms_x": {k: round(v, 3) for k, v in tuning["ms_x"].items()}},
+        "gemm_tiles": {"x": tuning["x"], "s": tuning["s"], "from_cache": tuning["cached"],
+                       "autotune_ms_s": {k: round(v, 3) for k, v in tuning.get("ms_s", {}).items()},
+                       "autotune_ms_x": {k: round(v, 3) for k, v in tuning.get("ms_x", {}).items()}},
         "gmres_iters_per_step": sum(i["iters"] for i in infos) / len(infos),
         "a_bb_blocks": {"folded": plan.n_folded, "remainder": plan.n_remainder},
         "inverse_form": plan.inverse_mode_used(),

@@ -42,13 +42,14 @@ class ImplicitStepper:
                  jacobian, lin_tol: float = 1e-10, newton_tol: float = 1e-8, max_newton: int = 10,
                  restart: int = 30, precond: int = 1, precision: str = "fp64", autotune: bool = True,
                  forcing: bool = True, fp32_inner_tol: float = 1e-4, graph: bool = False,
-                 graph_cycles: int = 4):
+                 graph_cycles: int = 4, autotune_cache: str | None = None):
         self.plan = Plan.from_structure(structure)
         self.dg = DgResidual(k_elem, order, mach=mach, reynolds=reynolds)
         self.dt, self.jacobian = dt, jacobian
         self.lin_tol, self.newton_tol, self.max_newton = lin_tol, newton_tol, max_newton
         self.restart, self.precond, self.precision = restart, precond, precision
         self._tune = autotune
+        self.autotune_cache = autotune_cache
         self.forcing = forcing
         self.fp32_inner_tol = fp32_inner_tol
         self._blocks = None
@@ -76,7 +77,7 @@ class ImplicitStepper:
         t0 = time.perf_counter()
         self.plan.factor(self.precision)
         if self._tune:
-            self.plan.autotune()
+            self.plan.autotune(cache=self.autotune_cache)
             self._tune = False
         self.plan.condense()
         torch.cuda.synchronize()

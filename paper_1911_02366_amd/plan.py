@@ -11,6 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
+from . import tuning
 
 
 def _ptr(t) -> int | None:
@@ -203,14 +204,34 @@ class Plan:
         self._check(self.lib.scdg_phase_times(self.handle, ms, cnt, n), "scdg_phase_times")
         return {name: {"ms": ms[i], "count": cnt[i]} for i, name in enumerate(L.PHASES)}
 
-    def autotune(self) -> dict:
-        """Time every GEMM tile configuration on this plan's problems; keep the fastest."""
+    def problem_signature(self) -> str:
+        """Key of this plan's GEMM problems in the autotune cache (sizes, factor
+        precision, device, configuration list)."""
+        order = self._host["order"].astype(np.int64)
+        n_i = 5 * (order - 1) ** 3
+        n_c = 5 * np.diff(self._host["c_ptr"])
+        dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "none"
+        return tuning.problem_signature(n_i, n_c, getattr(self, "precision", "fp64"), dev, L.GEMM_CONFIGS)
+
+    def autotune(self, cache: str | None = None) -> dict:
+        """Time every GEMM tile configuration on this plan's problems; keep the
+        fastest.  With a cache file (argument, else $SCDG_AUTOTUNE_CACHE), a plan
+        whose problem signature is stored takes the stored choice untimed, and a
+        new choice is stored."""
+        cache = cache or tuning.default_path()
+        key = self.problem_signature()
+        hit = tuning.lookup(cache, key)
+        if hit is not None and hit["x"] in L.GEMM_CONFIGS and hit["s"] in L.GEMM_CONFIGS:
+            self.set_gemm_config(hit["x"], hit["s"])
+            return dict(hit, cached=True)
         n = len(L.GEMM_CONFIGS)
         mx, ms = (C.c_double * n)(), (C.c_double * n)()
         self._check(self.lib.scdg_autotune(self.handle, mx, ms, n), "scdg_autotune")
         cx, cs = self.gemm_config()
-        return {"x": L.GEMM_CONFIGS[cx], "s": L.GEMM_CONFIGS[cs],
-                "ms_x": dict(zip(L.GEMM_CONFIGS, list(mx))), "ms_s": dict(zip(L.GEMM_CONFIGS, list(ms)))}
+        out = {"x": L.GEMM_CONFIGS[cx], "s": L.GEMM_CONFIGS[cs],
+               "ms_x": dict(zip(L.GEMM_CONFIGS, list(mx))), "ms_s": dict(zip(L.GEMM_CONFIGS, list(ms)))}
+        tuning.store(cache, key, out)
+        return dict(out, cached=False)
 
     def gemm_config(self):
         cx, cs = C.c_int32(), C.c_int32()

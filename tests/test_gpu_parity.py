@@ -125,10 +125,19 @@ def test_every_gemm_tile_config(setup, cfg):
         assert rel(fold[e] - s[e], ref) <= 1e-11, (name, cfg, e)
 
 
-def test_autotune_keeps_results(setup):
+def test_autotune_keeps_results(setup, tmp_path):
     name, case, d, dev, plan = setup
-    tuned = plan.autotune()
+    cache = str(tmp_path / "autotune.json")
+    tuned = plan.autotune(cache=cache)
+    assert not tuned["cached"]
     assert tuned["x"] in tuned["ms_x"] and tuned["ms_s"][tuned["s"]] > 0
+    # a second plan of the same problems takes the stored choice without timing
+    other = make_plan(case, dev)
+    other.set_gemm_config(0, 0)
+    again = other.autotune(cache=cache)
+    assert again["cached"] and (again["x"], again["s"]) == (tuned["x"], tuned["s"])
+    assert other.gemm_config() == plan.gemm_config()
+    other.close()
     plan.condense()
     ref = oracle.solve_sparse(oracle_matrix(d), d["b"])
     dq, info = plan.solve(dev["b"], solver="gmres", tol=1e-13, ir_tol=1e-12)
