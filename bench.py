@@ -155,16 +155,26 @@ def learned_guess_experiment(args) -> dict:
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     hold_zero = lg.loss_on(lg.count - n_elem, lg.count, zero=True)
+    # the same network trained with bfloat16 matrix products on the same samples
+    lg16 = LearnedGuess(n_elem, dpe, capacity=args.lg_train, seed=args.lg_seed, batch=args.lg_batch,
+                        compute="bf16")
+    lg16.copy_samples(lg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    history16, hold16 = lg16.train(epochs=args.lg_epochs, lr=args.lg_lr, holdout_rows=n_elem)
+    torch.cuda.synchronize()
+    t_train16 = time.perf_counter() - t0
     log(f"trained {args.lg_epochs} epochs in {t_train:.1f} s: loss {history[0]:.3e} -> {history[-1]:.3e}, "
         f"hold-out {hold:.3e} (previous increment: {hold_zero:.3e})")
     variants = [("zero", "gmres"), ("previous", "gmres"), ("learned", "gmres"),
                 ("previous_newton_start", "newton"), ("learned_newton_start", "newton"),
+                ("learned_bf16_newton_start", "newton"),
                 ("fp32_ir_zero", "gmres"), ("fp32_ir_previous_newton_start", "newton"),
                 ("fp32_ir_learned_newton_start", "newton")]
     names = [v for v, _ in variants]
     rec = {k: {"first": [], "total": [], "newton": [], "seconds": [], "guess_res": [], "rejected": []}
            for k in names}
-    infer_ms = []
+    infer_ms, infer16_ms = [], []
     prep = {"fp64": [], "fp32": []}
     for step in range(args.lg_train + 1, args.lg_steps + 1):
         prep["fp64"].append(st.prepare(q))
@@ -174,9 +184,14 @@ def learned_guess_experiment(args) -> dict:
         pred = lg.predict(q, dq_prev, rc_prev)
         torch.cuda.synchronize()
         infer_ms.append((time.perf_counter() - t1) * 1e3)
+        t1 = time.perf_counter()
+        pred16 = lg16.predict(q, dq_prev, rc_prev)
+        torch.cuda.synchronize()
+        infer16_ms.append((time.perf_counter() - t1) * 1e3)
         out = {}
         for name, mode in variants:
-            g = None if name.endswith("zero") else (dq_prev if "previous" in name else pred)
+            g = None if name.endswith("zero") else (dq_prev if "previous" in name else
+                                                    (pred16 if "bf16" in name else pred))
             q1, info = (st32 if name.startswith("fp32") else st).solve_step(q, guess=g, mode=mode)
             if not info["converged"]:
                 raise RuntimeError(f"step {step} ({name}) did not converge: {info}")
@@ -184,7 +199,8 @@ def learned_guess_experiment(args) -> dict:
             r["first"].append(info["first_gmres"])
             r["total"].append(info["gmres"])
             r["newton"].append(info["newton"])
-            r["seconds"].append(info["seconds"] + (infer_ms[-1] * 1e-3 if "learned" in name else 0.0))
+            infer = infer16_ms[-1] if "bf16" in name else infer_ms[-1]
+            r["seconds"].append(info["seconds"] + (infer * 1e-3 if "learned" in name else 0.0))
             r["guess_res"].append(info["guess_res"])
             r["rejected"].append(info["guess_rejected"])
             out[name] = q1
@@ -206,7 +222,10 @@ def learned_guess_experiment(args) -> dict:
                   "loss_last_epoch": history[-1], "holdout_loss": hold,
                   "holdout_loss_previous_increment": hold_zero, "alpha": lg.alpha,
                   "collect_seconds": t_collect},
+        "train_bf16": {"seconds": t_train16, "loss_first_epoch": history16[0], "loss_last_epoch": history16[-1],
+                       "holdout_loss": hold16, "alpha": lg16.alpha},
         "inference_ms_mean": mean(infer_ms),
+        "inference_bf16_ms_mean": mean(infer16_ms),
         "guess_rejected": {k: int(np.sum(rec[k]["rejected"])) for k in names},
         "forcing": "GMRES tol per Newton iteration = clip(0.5 newton_tol |R0| / |R|, gmres_tol, 0.1)",
     }
@@ -223,6 +242,7 @@ def learned_guess_experiment(args) -> dict:
     z = result["step_seconds_mean"]["zero"]
     result["time_to_solution_vs_plain_fp64"] = {k: z / result["step_seconds_mean"][k] for k in names}
     lg.close()
+    lg16.close()
     st.close()
     st32.close()
     return result

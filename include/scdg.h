@@ -278,8 +278,8 @@ scdg_status scdg_dg_residual(scdg_dg *dg, const double *q, const double *q_s, do
 scdg_status scdg_dg_gradient(scdg_dg *dg, double *g);
 
 /* ------------------------------------------------------------------------
- * Newton iterations of one backward-Euler step, each iteration one replay of
- * a HIP graph (the Newton linearization of eq. NewtonLinSys1 solved by static
+ * Newton iterations of one backward-Euler step replayed from captured HIP
+ * graphs (the Newton linearization of eq. NewtonLinSys1 solved by static
  * condensation, eq. SC_step1 and SC_step2):
  *
  *     B = -R(Q);  b_S = condense(B);  S x = b_S by GMRES(m);
@@ -289,10 +289,13 @@ scdg_status scdg_dg_gradient(scdg_dg *dg, double *g);
  * condensed (scdg_condense) for a Jacobian supplied by the caller, usually at
  * Q_s, and that Jacobian is kept for every iteration of the step (a chord
  * iteration; with FP32 factors the FP64 nonlinear residual drives the
- * refinement).  Each replay runs `cycles` GMRES restart cycles whose kernels
- * return at once after the tolerance is met (flags in device memory); the
- * host reads ||R(Q)|| after each replay and stops when
- * ||R(Q)|| <= newton_tol ||R(Q_s)||.  The GMRES tolerance of an iteration is
+ * refinement).  An iteration is three graphs: the condensed right-hand side
+ * and GMRES set-up; one GMRES restart cycle, replayed until a flag in device
+ * memory reports the solve finished (the host reads it after each cycle; at
+ * most `cycles` cycles, after which the iteration goes on with the partial
+ * solution); and back-substitution, update and residual.  Within a cycle the
+ * kernels of the steps after convergence return at once.  The host reads
+ * ||R(Q)|| after each iteration and stops when ||R(Q)|| <= newton_tol ||R(Q_s)||.  The GMRES tolerance of an iteration is
  * clip(forcing * newton_tol * ||R(Q_s)|| / ||R(Q)||, lin_tol, eta_max)
  * (inexact Newton; forcing = 0 gives lin_tol).  GMRES starts from zero; a
  * guess enters as the starting state Q.
@@ -302,7 +305,7 @@ scdg_status scdg_dg_gradient(scdg_dg *dg, double *g);
  * out: the new state) must not alias q_s.  Both hold n_dof doubles in the
  * natural DOF order, which must match the dg object's size.  If the starting
  * state has a larger residual than Q_s it is replaced by Q_s
- * (info.start_rejected).  The graph is captured on the first call and reused
+ * (info.start_rejected).  The graphs are captured on the first call and reused
  * while q, q_s, dg, inv_dt, the options and the plan's buffers stay the same;
  * keep them fixed across steps to avoid a new capture.  The call synchronizes
  * the plan's stream.  Errors: SCDG_ERR_STATE before scdg_condense,
@@ -316,7 +319,7 @@ typedef struct {
   double forcing;      /* < 0 selects 0.5; 0 disables the forcing term */
   double eta_max;      /* cap of the GMRES tolerance; <= 0 selects 0.1 */
   int32_t restart;     /* GMRES(m), <= 0 selects 30, at most 63 */
-  int32_t cycles;      /* restart cycles per Newton iteration, <= 0 selects 4, at most 64 */
+  int32_t cycles;      /* restart cycles per Newton iteration at most, <= 0 selects 8, at most 64 */
   int32_t precond;     /* 0 none, 1 point Jacobi, 2 5x5 node-block Jacobi; < 0 selects 1 */
   int32_t max_newton;  /* <= 0 selects 10 */
 } scdg_newton_opts;
@@ -362,13 +365,21 @@ scdg_status scdg_newton_step(scdg_plan *p, scdg_dg *dg, const double *q_s, doubl
  * ------------------------------------------------------------------------ */
 typedef struct scdg_mlp scdg_mlp;
 typedef struct {
-  int32_t n_in, n_hidden, n_layers, n_out;  /* n_layers hidden layers (1..16) */
+  int32_t n_in, n_hidden, n_layers, n_out;  /* n_layers hidden layers (0..16; 0: one linear map) */
   int32_t max_batch;                        /* largest batch of any call */
 } scdg_mlp_shape;
 scdg_status scdg_mlp_create(scdg_mlp **out, const scdg_mlp_shape *s, void *hip_stream);
 scdg_status scdg_mlp_destroy(scdg_mlp *m);
 /* number of floats of the flat parameter vector (and of its gradient) */
 scdg_status scdg_mlp_param_count(const scdg_mlp *m, int64_t *n);
+/* Arithmetic of the matrix products of forward and backward:
+ * SCDG_MLP_FP32 (default) multiplies FP32 operands; SCDG_MLP_BF16 rounds both
+ * operands of every product (weights, activations, gradients) to the nearest
+ * bfloat16, ties to even, and multiplies them on the bf16 matrix cores; both
+ * accumulate in FP32, and parameters, biases, activations, gradients and Adam
+ * stay FP32.  SCDG_ERR_ARG for another mode. */
+enum { SCDG_MLP_FP32 = 0, SCDG_MLP_BF16 = 1 };
+scdg_status scdg_mlp_set_compute(scdg_mlp *m, int32_t mode);
 /* y [batch x n_out] = network(x [batch x n_in]); keeps the activations */
 scdg_status scdg_mlp_forward(scdg_mlp *m, const float *w, const float *x, int32_t batch, float *y);
 /* Gradients of a loss with respect to the parameters (dw, overwritten) and,

@@ -11,7 +11,9 @@ Network: a_0 = x, a_l = tanh(a_{l-1} W_l + b_l) for the hidden layers,
 y = a_L W_out + b_out (rows are samples).  Parameters live in one flat
 vector, layer after layer, W_l [fan_in x fan_out] row-major then b_l.
 Gradients follow the chain rule written out per layer; Adam is the update of
-Kingma and Ba (2015) with bias correction.
+Kingma and Ba (2015) with bias correction.  The BF16 compute mode rounds both
+operands of every matrix product to bfloat16 (a storage format with FP32's
+exponent range and an 8-bit significand); everything else stays exact.
 """
 from __future__ import annotations
 
@@ -35,12 +37,32 @@ def _unpack(w, shape):
     return [(w[o:o + fi * fo].reshape(fi, fo), w[bo:bo + fo]) for o, fi, fo, bo in lay]
 
 
-def forward(w: np.ndarray, x: np.ndarray, shape):
-    """y and the list of activations a_0 = x, a_1, ..., a_L (FP64)."""
+def bf16_round(a) -> np.ndarray:
+    """Nearest bfloat16 of each value taken as FP32 (ties to even), as FP64.
+
+    bfloat16 keeps the sign, the 8 exponent bits and the 7 leading mantissa
+    bits of an FP32 number; rounding to nearest-even adds 0x7FFF plus the
+    lowest kept bit to the FP32 bit pattern and clears the 16 dropped bits
+    (finite inputs)."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _operand(bf16: bool):
+    """How a matrix-product operand enters: as is (FP64), or as the nearest
+    bfloat16 of its FP32 value (the BF16 compute mode)."""
+    return bf16_round if bf16 else (lambda t: t)
+
+
+def forward(w: np.ndarray, x: np.ndarray, shape, bf16: bool = False):
+    """y and the list of activations a_0 = x, a_1, ..., a_L (FP64).  bf16: both
+    operands of every product rounded to bfloat16, the rest in FP64."""
     layers = _unpack(np.asarray(w, dtype=np.float64), shape)
+    op = _operand(bf16)
     a = [np.asarray(x, dtype=np.float64)]
     for i, (wl, bl) in enumerate(layers):
-        z = a[-1] @ wl + bl
+        z = op(a[-1]) @ op(wl) + bl
         if i < len(layers) - 1:
             a.append(np.tanh(z))
         else:
@@ -48,18 +70,20 @@ def forward(w: np.ndarray, x: np.ndarray, shape):
     raise AssertionError("unreachable")
 
 
-def backward(w: np.ndarray, acts, dy: np.ndarray, shape):
-    """dLoss/dw (flat) and dLoss/dx given dLoss/dy and the forward activations."""
+def backward(w: np.ndarray, acts, dy: np.ndarray, shape, bf16: bool = False):
+    """dLoss/dw (flat) and dLoss/dx given dLoss/dy and the forward activations
+    (bf16: product operands rounded as in forward)."""
     layers = _unpack(np.asarray(w, dtype=np.float64), shape)
+    op = _operand(bf16)
     lay, n = layout(*shape)
     dw = np.zeros(n)
     dz = np.asarray(dy, dtype=np.float64)
     for i in range(len(layers) - 1, -1, -1):
         wl, _ = layers[i]
         o, fi, fo, bo = lay[i]
-        dw[o:o + fi * fo] = (acts[i].T @ dz).reshape(-1)
+        dw[o:o + fi * fo] = (op(acts[i]).T @ op(dz)).reshape(-1)
         dw[bo:bo + fo] = dz.sum(axis=0)
-        da = dz @ wl.T                      # dLoss / d a_{i}
+        da = op(dz) @ op(wl).T              # dLoss / d a_{i}
         if i > 0:
             dz = da * (1.0 - acts[i] ** 2)  # through a_i = tanh(z_i)
         else:

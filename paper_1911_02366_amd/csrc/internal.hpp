@@ -196,8 +196,8 @@ struct Plan {
   double *nw_r = nullptr;      // [n_dof] nonlinear residual R(Q)
   double *nw_dq = nullptr;     // [n_dof] minus the Newton increment
   double *nw_stat = nullptr;   // [8] norms, see newton_gmres_setup_kernel
-  hipGraph_t nw_graph = nullptr;
-  hipGraphExec_t nw_exec = nullptr;
+  hipGraph_t nw_graph[3] = {};        // 0: right-hand side and GMRES set-up, 1: one restart
+  hipGraphExec_t nw_exec[3] = {};     //    cycle, 2: back-substitution, update and residual
   NewtonKey nw_key{};
   int32_t red_blocks = 0;
 

@@ -1,7 +1,9 @@
 // Per-element multilayer perceptron for the learned initial guess of the
 // implicit-step solve, with its training kernels (forward, backward, Adam,
 // mean-squared loss) and the feature/target maps between DG vectors and the
-// network.  FP32 storage, FP32 MFMA with FP32 accumulation.
+// network.  FP32 storage; the matrix products run on FP32 MFMA, or with
+// operands rounded to bfloat16 on the bf16 MFMA (scdg_mlp_set_compute), both
+// with FP32 accumulation.
 //
 // Network: x (n_in) -> tanh(W_1^T x + b_1) -> ... (n_layers hidden layers of
 // width n_hidden) -> W_out^T a + b_out (n_out, linear).  Row-major batches:
@@ -31,8 +33,24 @@ constexpr int kRedBlocks = 256;
 
 enum Epilogue { kEpiNone = 0, kEpiTanh = 1 };
 
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+// Nearest bfloat16 of an FP32 value (ties to even), kept as an FP32 bit pattern
+// whose low 16 bits are zero; NaN stays NaN.
+__device__ __forceinline__ float bf16_round(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return __uint_as_float((u & 0x007fffffu) ? ((u | 0x00400000u) & 0xffff0000u) : u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
+__device__ __forceinline__ short bf16_bits(float x) { return (short)(__float_as_uint(x) >> 16); }
+
 // C = op(A) op(B) (+ bias[col]) (tanh) (* (1 - D^2)); op(A) is M x K, op(B) K x N.
-template <bool TA, bool TB>
+// BF: the operands are rounded to bfloat16 when staged in LDS and multiplied
+// by the 16x16x16 bf16 MFMA with FP32 accumulation (products of two bf16
+// values are exact in FP32); otherwise FP32 operands and the 16x16x4 FP32 MFMA.
+template <bool TA, bool TB, bool BF>
 __global__ __launch_bounds__(kThreads) void mlp_gemm_kernel(int M, int N, int K,
                                                             const float *__restrict__ A, int lda,
                                                             const float *__restrict__ B, int ldb,
@@ -82,14 +100,16 @@ __global__ __launch_bounds__(kThreads) void mlp_gemm_kernel(int M, int N, int K,
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
+      const float va = BF ? bf16_round(ra[u]) : ra[u];
+      const float vb = BF ? bf16_round(rb[u]) : rb[u];
       if (TA)
-        as[buf][tid / kTile + 4 * u][tid % kTile] = ra[u];
+        as[buf][tid / kTile + 4 * u][tid % kTile] = va;
       else
-        as[buf][tid % kBK][tid / kBK + 16 * u] = ra[u];
+        as[buf][tid % kBK][tid / kBK + 16 * u] = va;
       if (TB)
-        bs[buf][tid % kBK][tid / kBK + 16 * u] = rb[u];
+        bs[buf][tid % kBK][tid / kBK + 16 * u] = vb;
       else
-        bs[buf][tid / kTile + 4 * u][tid % kTile] = rb[u];
+        bs[buf][tid / kTile + 4 * u][tid % kTile] = vb;
     }
   };
 
@@ -106,17 +126,35 @@ __global__ __launch_bounds__(kThreads) void mlp_gemm_kernel(int M, int N, int K,
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) load((kt + 1) * kBK);
+    if constexpr (BF) {
+      // 16x16x16: lane l holds A[l % 16][4 (l / 16) + t] and B[4 (l / 16) + t][l % 16], t = 0..3
+      bf16x4 af[2], bf[2];
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 4) {
-      float af[2], bf[2];
+      for (int t = 0; t < 4; ++t) {
+        const int k = 4 * (lane >> 4) + t;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) af[i] = as[buf][kk + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
+        for (int i = 0; i < 2; ++i) af[i][t] = bf16_bits(as[buf][k][wm * 32 + i * 16 + (lane & 15)]);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bf[j] = bs[buf][kk + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
+        for (int j = 0; j < 2; ++j) bf[j][t] = bf16_bits(bs[buf][k][wn * 32 + j * 16 + (lane & 15)]);
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = MF::mma(af[i], bf[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < kBK; kk += 4) {
+        float af[2], bf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[i] = as[buf][kk + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bf[j] = bs[buf][kk + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = MF::mma(af[i], bf[j], acc[i][j]);
+      }
     }
     if (kt + 1 < nk) store(buf ^ 1);
     __syncthreads();
@@ -144,23 +182,30 @@ __global__ __launch_bounds__(kThreads) void mlp_gemm_kernel(int M, int N, int K,
     }
 }
 
-hipError_t gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
-                float *C, int ldc, const float *bias, int epi, const float *dact, int ldd,
-                hipStream_t s) {
-  if (M <= 0 || N <= 0) return hipSuccess;
+template <bool BF>
+hipError_t gemm_typed(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
+                      float *C, int ldc, const float *bias, int epi, const float *dact, int ldd, hipStream_t s) {
   const dim3 grid((M + kTile - 1) / kTile, (N + kTile - 1) / kTile);
   if (!ta && !tb)
-    hipLaunchKernelGGL((mlp_gemm_kernel<false, false>), grid, dim3(kThreads), 0, s, M, N, K, A, lda, B,
+    hipLaunchKernelGGL((mlp_gemm_kernel<false, false, BF>), grid, dim3(kThreads), 0, s, M, N, K, A, lda, B,
                        ldb, C, ldc, bias, epi, dact, ldd);
   else if (ta && !tb)
-    hipLaunchKernelGGL((mlp_gemm_kernel<true, false>), grid, dim3(kThreads), 0, s, M, N, K, A, lda, B,
+    hipLaunchKernelGGL((mlp_gemm_kernel<true, false, BF>), grid, dim3(kThreads), 0, s, M, N, K, A, lda, B,
                        ldb, C, ldc, bias, epi, dact, ldd);
   else if (!ta && tb)
-    hipLaunchKernelGGL((mlp_gemm_kernel<false, true>), grid, dim3(kThreads), 0, s, M, N, K, A, lda, B,
+    hipLaunchKernelGGL((mlp_gemm_kernel<false, true, BF>), grid, dim3(kThreads), 0, s, M, N, K, A, lda, B,
                        ldb, C, ldc, bias, epi, dact, ldd);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+hipError_t gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
+                float *C, int ldc, const float *bias, int epi, const float *dact, int ldd, bool bf16,
+                hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  return bf16 ? gemm_typed<true>(ta, tb, M, N, K, A, lda, B, ldb, C, ldc, bias, epi, dact, ldd, s)
+              : gemm_typed<false>(ta, tb, M, N, K, A, lda, B, ldb, C, ldc, bias, epi, dact, ldd, s);
 }
 
 // Column sums of a row-major [rows x cols] matrix in two fixed-order stages:
@@ -357,6 +402,7 @@ struct MlpContext {
   float *colpart = nullptr;   // kColChunks x max width
   double *red = nullptr;      // reduction partials
   int last_batch = -1;
+  bool bf16 = false;          // GEMM operands rounded to bfloat16 (FP32 accumulation)
   std::vector<int64_t> w_off, b_off;
   std::vector<int> fan_in, fan_out;
   int64_t n_params = 0;
@@ -388,7 +434,7 @@ void free_ctx(MlpContext &c) {
 extern "C" {
 
 scdg_status scdg_mlp_create(scdg_mlp **out, const scdg_mlp_shape *s, void *hip_stream) {
-  if (!out || !s || s->n_in <= 0 || s->n_hidden <= 0 || s->n_layers <= 0 || s->n_out <= 0 ||
+  if (!out || !s || s->n_in <= 0 || s->n_hidden <= 0 || s->n_layers < 0 || s->n_out <= 0 ||
       s->max_batch <= 0 || s->n_layers > 16)
     return SCDG_ERR_ARG;
   scdg_mlp *m = new (std::nothrow) scdg_mlp();
@@ -413,7 +459,7 @@ scdg_status scdg_mlp_create(scdg_mlp **out, const scdg_mlp_shape *s, void *hip_s
   }
   c.n_params = off;
   const int64_t wmax = std::max(std::max(c.n_hidden, c.n_out), c.n_in);
-  bool ok = hipMalloc(&c.act, sizeof(float) * (size_t)c.n_layers * c.max_batch * c.n_hidden) == hipSuccess &&
+  bool ok = hipMalloc(&c.act, sizeof(float) * (size_t)std::max(1, c.n_layers) * c.max_batch * c.n_hidden) == hipSuccess &&
             hipMalloc(&c.dz, sizeof(float) * 2 * (size_t)c.max_batch * wmax) == hipSuccess &&
             hipMalloc(&c.colpart, sizeof(float) * scdg::kColChunks * (size_t)wmax) == hipSuccess &&
             hipMalloc(&c.red, sizeof(double) * 15 * scdg::kRedBlocks) == hipSuccess;
@@ -434,6 +480,12 @@ scdg_status scdg_mlp_destroy(scdg_mlp *m) {
   return SCDG_OK;
 }
 
+scdg_status scdg_mlp_set_compute(scdg_mlp *m, int32_t mode) {
+  if (!m || (mode != SCDG_MLP_FP32 && mode != SCDG_MLP_BF16)) return SCDG_ERR_ARG;
+  m->c.bf16 = mode == SCDG_MLP_BF16;
+  return SCDG_OK;
+}
+
 scdg_status scdg_mlp_param_count(const scdg_mlp *m, int64_t *n) {
   if (!m || !n) return SCDG_ERR_ARG;
   *n = m->c.n_params;
@@ -451,7 +503,7 @@ scdg_status scdg_mlp_forward(scdg_mlp *m, const float *w, const float *x, int32_
     const int ld_out = last ? c.n_out : c.n_hidden;
     hipError_t e = scdg::gemm(false, false, batch, c.fan_out[l], c.fan_in[l], in, ld_in, w + c.w_off[l],
                               c.fan_out[l], out, ld_out, w + c.b_off[l],
-                              last ? scdg::kEpiNone : scdg::kEpiTanh, nullptr, 0, c.stream);
+                              last ? scdg::kEpiNone : scdg::kEpiTanh, nullptr, 0, c.bf16, c.stream);
     if (e != hipSuccess) return SCDG_ERR_HIP;
     in = out;
     ld_in = ld_out;
@@ -474,7 +526,7 @@ scdg_status scdg_mlp_backward(scdg_mlp *m, const float *w, const float *x, const
     const int fi = c.fan_in[l], fo = c.fan_out[l];
     // dW_l = A_{l-1}^T dZ_l  [fi x fo]
     hipError_t e = scdg::gemm(true, false, fi, fo, batch, a_prev, fi, dz, fo, dw + c.w_off[l], fo, nullptr,
-                              scdg::kEpiNone, nullptr, 0, c.stream);
+                              scdg::kEpiNone, nullptr, 0, c.bf16, c.stream);
     if (e != hipSuccess) return SCDG_ERR_HIP;
     // db_l = column sums of dZ_l
     hipLaunchKernelGGL(scdg::colsum_partial_kernel, dim3((fo + 255) / 256, scdg::kColChunks), dim3(256), 0,
@@ -485,13 +537,13 @@ scdg_status scdg_mlp_backward(scdg_mlp *m, const float *w, const float *x, const
       // dZ_{l-1} = (dZ_l W_l^T) * (1 - A_{l-1}^2)
       float *next = buf[cur];
       e = scdg::gemm(false, true, batch, fi, fo, dz, fo, w + c.w_off[l], fo, next, fi, nullptr,
-                     scdg::kEpiNone, a_prev, fi, c.stream);
+                     scdg::kEpiNone, a_prev, fi, c.bf16, c.stream);
       if (e != hipSuccess) return SCDG_ERR_HIP;
       dz = next;
       cur ^= 1;
     } else if (dx) {
       e = scdg::gemm(false, true, batch, fi, fo, dz, fo, w + c.w_off[l], fo, dx, fi, nullptr, scdg::kEpiNone,
-                     nullptr, 0, c.stream);
+                     nullptr, 0, c.bf16, c.stream);
       if (e != hipSuccess) return SCDG_ERR_HIP;
     }
   }

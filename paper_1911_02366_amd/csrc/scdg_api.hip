@@ -498,10 +498,12 @@ scdg_status gmres(Plan &p, const double *bs, double *x, const double *x0, const 
 // ---- one Newton iteration of the implicit step, captured as a graph ----
 
 void drop_newton_graph(Plan &p) {
-  if (p.nw_exec) (void)hipGraphExecDestroy(p.nw_exec);
-  if (p.nw_graph) (void)hipGraphDestroy(p.nw_graph);
-  p.nw_exec = nullptr;
-  p.nw_graph = nullptr;
+  for (int i = 0; i < 3; ++i) {
+    if (p.nw_exec[i]) (void)hipGraphExecDestroy(p.nw_exec[i]);
+    if (p.nw_graph[i]) (void)hipGraphDestroy(p.nw_graph[i]);
+    p.nw_exec[i] = nullptr;
+    p.nw_graph[i] = nullptr;
+  }
 }
 
 struct NewtonSetup {
@@ -512,7 +514,7 @@ struct NewtonSetup {
 NewtonKey newton_key(const Plan &p, scdg_dg *dg, const double *q_s, const double *q, const NewtonSetup &ns) {
   NewtonKey k;
   k.m = ns.m;
-  k.cycles = ns.cycles;
+  k.cycles = 0;   // the cycle budget is a host loop bound, not part of any graph
   k.pmode = ns.pmode;
   k.fp32 = fp32(p);
   k.inv_dt = ns.inv_dt;
@@ -528,82 +530,96 @@ NewtonKey newton_key(const Plan &p, scdg_dg *dg, const double *q_s, const double
   return k;
 }
 
-// Enqueue one Newton iteration on p.stream.  On entry nw_r holds R(Q) and
-// nw_stat[0] its squared norm, nw_stat[2] = ||R(Q_s)||; on exit q is updated and
-// nw_r, nw_stat[0] hold the new residual.  The linear system is solved for the
-// right-hand side R (not -R): x = S^-1 condense(R), nw_dq = backsolve(R, x) = -dQ.
-scdg_status newton_iteration(Plan &p, scdg_dg *dg, const double *q_s, double *q, const NewtonSetup &ns) {
+// One Newton iteration is enqueued as three pieces, each captured as a graph.
+// The linear system is solved for the right-hand side R (not -R):
+// x = S^-1 condense(R), nw_dq = backsolve(R, x) = -dQ.
+// Piece 0: on entry nw_r holds R(Q), nw_stat[0] its squared norm and
+// nw_stat[2] = ||R(Q_s)||; condensed right-hand side, x = 0, GMRES set-up.
+scdg_status newton_piece_setup(Plan &p, const NewtonSetup &ns) {
+  const int64_t n = p.n1;
+  p.halt = nullptr;
+  ST_TRY(condense_rhs_impl(p, p.nw_r, p.w_bs));
+  HIP_TRY(launch_multidot(p.w_bs, 0, 1, p.w_bs, n, p.gm_part, p.red_blocks, p.nw_stat + 1, p.stream));
+  HIP_TRY(launch_fill(p.w_qb, n, 0.0, p.stream));
+  HIP_TRY(launch_newton_gmres_setup(p.nw_stat, ns.eta_c, ns.lin_tol, ns.eta_max, ns.m, p.kr_g, p.kr_st,
+                                    p.kr_dev, p.stream));
+  HIP_TRY(launch_diag_scale(p.w_bs, nullptr, p.gm_v, n, 1.0, p.stream, p.kr_dev, p.kr_st + 3));
+  return SCDG_OK;
+}
+
+// Piece 1: one restart cycle (m Arnoldi steps that stop on the device flag),
+// x += Dinv V y, the true residual, and the set-up of the next cycle; every
+// kernel returns at once once the solve has finished (kr_st[3]).
+scdg_status newton_piece_cycle(Plan &p, const NewtonSetup &ns) {
   const int64_t n = p.n1;
   const int m = ns.m;
-  double *bs = p.w_bs, *x = p.w_qb, *rg = p.gm_w;
   int32_t *st = p.kr_st;
   const int32_t *done = p.kr_st + 3;
-  p.halt = nullptr;
-  ST_TRY(condense_rhs_impl(p, p.nw_r, bs));
-  HIP_TRY(launch_multidot(bs, 0, 1, bs, n, p.gm_part, p.red_blocks, p.nw_stat + 1, p.stream));
-  HIP_TRY(launch_fill(x, n, 0.0, p.stream));
-  HIP_TRY(launch_newton_gmres_setup(p.nw_stat, ns.eta_c, ns.lin_tol, ns.eta_max, m, p.kr_g, st, p.kr_dev,
-                                    p.stream));
-  HIP_TRY(launch_diag_scale(bs, nullptr, p.gm_v, n, 1.0, p.stream, p.kr_dev, done));
-  for (int c = 0; c < ns.cycles; ++c) {
-    p.halt = st;
-    scdg_status s1 = SCDG_OK;
-    for (int j = 0; j < m && s1 == SCDG_OK; ++j) s1 = krylov_step(p, j, m, ns.pmode);
-    if (s1 != SCDG_OK) {
-      p.halt = nullptr;
-      return s1;
-    }
-    // end of the cycle: x += Dinv V y, true residual, restart or stop
-    p.halt = done;
+  double *rg = p.gm_w;
+  p.halt = st;
+  scdg_status s1 = SCDG_OK;
+  for (int j = 0; j < m && s1 == SCDG_OK; ++j) s1 = krylov_step(p, j, m, ns.pmode);
+  p.halt = done;
+  if (s1 == SCDG_OK) {
     HIP_TRY(launch_krylov_solve(m, p.kr_H, p.kr_g, st, p.gm_h, p.stream, done));
     HIP_TRY(launch_fill(p.gm_z, n, 0.0, p.stream, done));
     HIP_TRY(launch_multi_axpy(p.gm_v, n, m, p.gm_h, p.gm_z, n, p.stream, st + 1, done));
     HIP_TRY(launch_precond_apply(p, ns.pmode, p.gm_z, rg, 1.0));
-    HIP_TRY(launch_axpby(n, 1.0, rg, 1.0, x, p.stream, done));
-    s1 = schur_apply_impl(p, x, rg);
-    if (s1 != SCDG_OK) {
-      p.halt = nullptr;
-      return s1;
-    }
-    HIP_TRY(launch_axpby(n, 1.0, bs, -1.0, rg, p.stream, done));
+    HIP_TRY(launch_axpby(n, 1.0, rg, 1.0, p.w_qb, p.stream, done));
+    s1 = schur_apply_impl(p, p.w_qb, rg);
+  }
+  if (s1 == SCDG_OK) {
+    HIP_TRY(launch_axpby(n, 1.0, p.w_bs, -1.0, rg, p.stream, done));
     HIP_TRY(launch_multidot(rg, 0, 1, rg, n, p.gm_part, p.red_blocks, p.nw_stat + 3, p.stream, done));
     HIP_TRY(launch_newton_gmres_restart(p.nw_stat, m, p.kr_g, st, p.kr_dev, p.stream));
     HIP_TRY(launch_diag_scale(rg, nullptr, p.gm_v, n, 1.0, p.stream, p.kr_dev, done));
   }
   p.halt = nullptr;
-  ST_TRY(backsolve_impl(p, p.nw_r, x, p.nw_dq));
+  return s1;
+}
+
+// Piece 2: back-substitution, Q += dQ, R(Q) and its squared norm.
+scdg_status newton_piece_update(Plan &p, scdg_dg *dg, const double *q_s, double *q, const NewtonSetup &ns) {
+  p.halt = nullptr;
+  ST_TRY(backsolve_impl(p, p.nw_r, p.w_qb, p.nw_dq));
   HIP_TRY(launch_axpby(p.n_dof, -1.0, p.nw_dq, 1.0, q, p.stream));
   HIP_TRY(dg_residual_on(dg, q, q_s, ns.inv_dt, p.nw_r, p.stream));
   HIP_TRY(launch_multidot(p.nw_r, 0, 1, p.nw_r, p.n_dof, p.gm_part, p.red_blocks, p.nw_stat, p.stream));
   return SCDG_OK;
 }
 
-scdg_status newton_graph(Plan &p, scdg_dg *dg, const double *q_s, double *q, const NewtonSetup &ns) {
+scdg_status newton_graphs(Plan &p, scdg_dg *dg, const double *q_s, double *q, const NewtonSetup &ns) {
   const NewtonKey key = newton_key(p, dg, q_s, q, ns);
-  if (p.nw_exec && p.nw_key == key) return SCDG_OK;
+  if (p.nw_exec[0] && p.nw_key == key) return SCDG_OK;
   drop_newton_graph(p);
   if (!p.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
-  hipStream_t user = p.stream;
-  p.stream = p.cap_stream;
-  HIP_TRY(hipStreamBeginCapture(p.stream, hipStreamCaptureModeRelaxed));
-  p.capturing = true;
-  const scdg_status st = newton_iteration(p, dg, q_s, q, ns);
-  p.capturing = false;
-  hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(p.stream, &g);
-  p.stream = user;
-  if (st != SCDG_OK || e != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    p.last_error = "capture of the Newton iteration failed";
-    return st != SCDG_OK ? st : SCDG_ERR_HIP;
+  for (int piece = 0; piece < 3; ++piece) {
+    hipStream_t user = p.stream;
+    p.stream = p.cap_stream;
+    HIP_TRY(hipStreamBeginCapture(p.stream, hipStreamCaptureModeRelaxed));
+    p.capturing = true;
+    const scdg_status st = piece == 0   ? newton_piece_setup(p, ns)
+                           : piece == 1 ? newton_piece_cycle(p, ns)
+                                        : newton_piece_update(p, dg, q_s, q, ns);
+    p.capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p.stream, &g);
+    p.stream = user;
+    if (st != SCDG_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      drop_newton_graph(p);
+      p.last_error = "capture of the Newton iteration failed";
+      return st != SCDG_OK ? st : SCDG_ERR_HIP;
+    }
+    if (hipGraphInstantiate(&p.nw_exec[piece], g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      p.nw_exec[piece] = nullptr;
+      drop_newton_graph(p);
+      p.last_error = "instantiation of the Newton iteration graph failed";
+      return SCDG_ERR_HIP;
+    }
+    p.nw_graph[piece] = g;
   }
-  if (hipGraphInstantiate(&p.nw_exec, g, nullptr, nullptr, 0) != hipSuccess) {
-    (void)hipGraphDestroy(g);
-    p.nw_exec = nullptr;
-    p.last_error = "instantiation of the Newton iteration graph failed";
-    return SCDG_ERR_HIP;
-  }
-  p.nw_graph = g;
   p.nw_key = key;
   return SCDG_OK;
 }
@@ -1379,7 +1395,7 @@ scdg_status scdg_newton_step(scdg_plan *pl, scdg_dg *dg, const double *q_s, doub
   const double newton_tol = opt.newton_tol > 0 ? opt.newton_tol : 1e-8;
   NewtonSetup ns;
   ns.m = opt.restart > 0 ? opt.restart : 30;
-  ns.cycles = opt.cycles > 0 ? opt.cycles : 4;
+  ns.cycles = opt.cycles > 0 ? opt.cycles : 8;
   ns.pmode = opt.precond < 0 ? 1 : std::min(opt.precond, 2);
   ns.lin_tol = opt.lin_tol > 0 ? opt.lin_tol : 1e-10;
   ns.eta_c = (opt.forcing < 0 ? 0.5 : opt.forcing) * newton_tol;
@@ -1419,14 +1435,21 @@ scdg_status scdg_newton_step(scdg_plan *pl, scdg_dg *dg, const double *q_s, doub
   stage[2] = inf.r0;
   stage[3] = 0.0;
   HIP_TRY(hipMemcpyAsync(p.nw_stat, stage, sizeof(double) * 4, hipMemcpyHostToDevice, p.stream));
-  ST_TRY(newton_graph(p, dg, q_s, q, ns));
+  ST_TRY(newton_graphs(p, dg, q_s, q, ns));
+  int32_t kst[8];
   while (rn > target && inf.newton < max_newton) {
-    HIP_TRY(hipGraphLaunch(p.nw_exec, p.stream));
+    HIP_TRY(hipGraphLaunch(p.nw_exec[0], p.stream));
+    // restart cycles until the device flag reports the solve finished
+    for (int c = 0; c < ns.cycles; ++c) {
+      HIP_TRY(hipGraphLaunch(p.nw_exec[1], p.stream));
+      HIP_TRY(hipMemcpyAsync(stage + 4, p.kr_st, sizeof(int32_t) * 8, hipMemcpyDeviceToHost, p.stream));
+      ST_TRY(sync(p));
+      std::memcpy(kst, stage + 4, sizeof(kst));
+      if (kst[3]) break;
+    }
+    HIP_TRY(hipGraphLaunch(p.nw_exec[2], p.stream));
     HIP_TRY(hipMemcpyAsync(stage, p.nw_stat, sizeof(double), hipMemcpyDeviceToHost, p.stream));
-    HIP_TRY(hipMemcpyAsync(stage + 4, p.kr_st, sizeof(int32_t) * 8, hipMemcpyDeviceToHost, p.stream));
     ST_TRY(sync(p));
-    int32_t kst[8];
-    std::memcpy(kst, stage + 4, sizeof(kst));
     rn = std::sqrt(stage[0]);
     if (inf.newton == 0) inf.first_gmres = kst[4];
     inf.gmres += kst[4];

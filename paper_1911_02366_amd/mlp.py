@@ -33,9 +33,16 @@ class Mlp:
         self.handle = handle
         self.n_in, self.n_hidden, self.n_layers, self.n_out = n_in, n_hidden, n_layers, n_out
         self.max_batch = max_batch
+        self.compute = "fp32"
         n = C.c_int64()
         self.lib.scdg_mlp_param_count(handle, C.byref(n))
         self.n_params = n.value
+
+    def set_compute(self, mode: str):
+        """'fp32' (FP32 operands) or 'bf16' (operands rounded to bfloat16), both
+        with FP32 accumulation."""
+        self._ok(self.lib.scdg_mlp_set_compute(self.handle, {"fp32": 0, "bf16": 1}[mode]), "scdg_mlp_set_compute")
+        self.compute = mode
 
     # ---------------------------------------------------------------- layout
     def layer_slices(self):

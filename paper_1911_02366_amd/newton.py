@@ -42,7 +42,7 @@ class ImplicitStepper:
                  jacobian, lin_tol: float = 1e-10, newton_tol: float = 1e-8, max_newton: int = 10,
                  restart: int = 30, precond: int = 1, precision: str = "fp64", autotune: bool = True,
                  forcing: bool = True, fp32_inner_tol: float = 1e-4, graph: bool = False,
-                 graph_cycles: int = 4, autotune_cache: str | None = None):
+                 graph_cycles: int = 8, autotune_cache: str | None = None):
         self.plan = Plan.from_structure(structure)
         self.dg = DgResidual(k_elem, order, mach=mach, reynolds=reynolds)
         self.dt, self.jacobian = dt, jacobian
@@ -187,10 +187,11 @@ class LearnedGuess:
     correction (alpha = 0 reproduces the previous increment)."""
 
     def __init__(self, n_elem: int, dofs_per_elem: int, capacity: int, hidden: int = 256, layers: int = 2,
-                 seed: int = 0, batch: int = 1024, device="cuda"):
+                 seed: int = 0, batch: int = 1024, device="cuda", compute: str = "fp32"):
         self.n_elem, self.dpe = n_elem, dofs_per_elem
         self.batch = batch
         self.net = Mlp(2 * dofs_per_elem, hidden, layers, dofs_per_elem, max_batch=max(n_elem, batch))
+        self.net.set_compute(compute)          # 'fp32' or 'bf16' matrix products
         self.w = self.net.init_params(seed, device, zero_output=True)
         self.m1 = torch.zeros_like(self.w)
         self.m2 = torch.zeros_like(self.w)
@@ -218,6 +219,15 @@ class LearnedGuess:
         self.net.target(dq, dq_prev, stats, self.n_elem,
                         t=self.t[self.count * nt:(self.count + self.n_elem) * nt])
         self.count += self.n_elem
+
+    def copy_samples(self, other: "LearnedGuess"):
+        """Take over another instance's stored training rows (same sizes)."""
+        if (other.n_elem, other.dpe) != (self.n_elem, self.dpe) or other.count > self.capacity * self.n_elem:
+            raise ValueError("sample sets differ in size")
+        nx, nt = 2 * self.dpe, self.dpe
+        self.x[:other.count * nx].copy_(other.x[:other.count * nx])
+        self.t[:other.count * nt].copy_(other.t[:other.count * nt])
+        self.count = other.count
 
     def train(self, epochs: int, lr: float = 1e-3, holdout_rows: int = 0):
         """Adam on minibatches of a seeded permutation; returns per-epoch mean losses

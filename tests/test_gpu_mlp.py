@@ -173,3 +173,99 @@ def test_bitwise_repeatable():
         net.close()
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+# ---------------------------------------------------------------- bfloat16 compute mode
+# Both sides round the same FP32 operands to bfloat16 (ties to even), so for a
+# single linear map (the operands are the inputs themselves) the only
+# difference left is FP32 versus FP64 accumulation of exact products: the FP32
+# tolerances above apply.  Between layers the kernel rounds its own FP32
+# activations and gradients while the oracle rounds its FP64 ones cast to FP32;
+# the two FP32 values can differ in the last bits, which moves a bfloat16
+# rounding across a tie in a small fraction of the elements (about 1e-3 of
+# them); each such element changes one product operand by one bfloat16 step
+# (2^-8 relative).  The multi-layer bound is therefore norm-wise 2e-3 and
+# element-wise 2e-2 of the largest magnitude.
+
+@pytest.mark.parametrize("shape", [(70, 1, 0, 45, 130), (1250, 1, 0, 625, 300)])
+def test_bf16_linear_map_matches_oracle(shape):
+    print(f"bf16 linear map {shape}", flush=True)
+    n_in, n_h, n_l, n_out, batch = shape
+    net, w, x, t = _setup(shape, 5)
+    net.set_compute("bf16")
+    xd = torch.tensor(x.reshape(-1), device=DEV)
+    td = torch.tensor(t.reshape(-1), device=DEV)
+    y = net.forward(w, xd, batch)
+    dy = torch.empty_like(y)
+    net.mse(y, td, batch * n_out, dy=dy)
+    dx = torch.empty_like(xd)
+    dw = net.backward(w, xd, dy, batch, dx=dx)
+    torch.cuda.synchronize()
+    sh = (n_in, n_h, n_l, n_out)
+    y_o, acts = om.forward(to_np(w), x, sh, bf16=True)
+    _close(to_np(y), y_o)
+    y_32, _ = om.forward(to_np(w), x, sh)
+    assert np.linalg.norm(to_np(y) - y_32.reshape(-1)) > 1e-4 * np.linalg.norm(y_32)   # the rounding is active
+    dw_o, dx_o = om.backward(to_np(w), acts, to_np(dy).reshape(batch, n_out), sh, bf16=True)
+    off, fi, fo, bo = om.layout(*sh)[0][0]
+    _close(to_np(dw)[off:off + fi * fo], dw_o[off:off + fi * fo])
+    _close(to_np(dw)[bo:bo + fo], dw_o[bo:bo + fo])
+    _close(to_np(dx), dx_o)
+    net.close()
+
+
+def test_bf16_network_matches_oracle():
+    shape = (1250, 256, 2, 625, 300)
+    n_in, n_h, n_l, n_out, batch = shape
+    net, w, x, t = _setup(shape, 6)
+    net.set_compute("bf16")
+    xd = torch.tensor(x.reshape(-1), device=DEV)
+    td = torch.tensor(t.reshape(-1), device=DEV)
+    y = net.forward(w, xd, batch)
+    dy = torch.empty_like(y)
+    net.mse(y, td, batch * n_out, dy=dy)
+    dw = net.backward(w, xd, dy, batch)
+    torch.cuda.synchronize()
+    sh = (n_in, n_h, n_l, n_out)
+    y_o, acts = om.forward(to_np(w), x, sh, bf16=True)
+    _close(to_np(y), y_o, 2e-3, 2e-2)
+    dw_o, _ = om.backward(to_np(w), acts, to_np(dy).reshape(batch, n_out), sh, bf16=True)
+    for off, fi, fo, bo in om.layout(*sh)[0]:
+        _close(to_np(dw)[off:off + fi * fo], dw_o[off:off + fi * fo], 2e-3, 2e-2)
+        _close(to_np(dw)[bo:bo + fo], dw_o[bo:bo + fo], 2e-3, 2e-2)
+    # switching back gives the FP32 products again
+    net.set_compute("fp32")
+    y32 = net.forward(w, xd, batch)
+    y_32o, _ = om.forward(to_np(w), x, sh)
+    _close(to_np(y32), y_32o)
+    with pytest.raises(ScdgError):
+        net._ok(net.lib.scdg_mlp_set_compute(net.handle, 2), "scdg_mlp_set_compute")
+    net.close()
+
+
+def test_bf16_training_reduces_loss_like_fp32():
+    rng = np.random.default_rng(8)
+    n_in, n_out, batch = 40, 20, 256
+    x = rng.standard_normal((batch, n_in)).astype(np.float32)
+    proj = rng.standard_normal((n_in, n_out)) / np.sqrt(n_in)
+    t = np.tanh(x @ proj).astype(np.float32)
+    xd, td = torch.tensor(x.reshape(-1), device=DEV), torch.tensor(t.reshape(-1), device=DEV)
+    final = {}
+    for mode in ("fp32", "bf16"):
+        net = Mlp(n_in, 64, 2, n_out, max_batch=batch)
+        net.set_compute(mode)
+        w = net.init_params(9, DEV)
+        m1, m2 = torch.zeros_like(w), torch.zeros_like(w)
+        losses = []
+        for step in range(1, 301):
+            y = net.forward(w, xd, batch)
+            dy = torch.empty_like(y)
+            losses.append(float(net.mse(y, td, batch * n_out, dy=dy)))
+            dw = net.backward(w, xd, dy, batch)
+            net.adam(w, dw, m1, m2, 3e-3, step)
+        final[mode] = (losses[0], losses[-1])
+        net.close()
+    print("training losses", final, flush=True)
+    for first, last in final.values():
+        assert last < 0.1 * first
+    assert final["bf16"][1] < 2.0 * final["fp32"][1] + 1e-3

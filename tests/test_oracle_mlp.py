@@ -149,3 +149,64 @@ def test_planted_mistakes_are_caught(monkeypatch):
                         good_adam(w, g, m1, m2, lr, 1, beta1, beta2, eps))   # bias correction frozen at step 1
     with pytest.raises(AssertionError):
         test_adam_closed_form_first_steps()
+
+
+# ---------------------------------------------------------------- bfloat16 mode
+
+def test_bf16_round_hand_values():
+    one = 1.0
+    cases = [(one, one), (1 + 2 ** -8, one),                    # tie between 1 and 1 + 2^-7: even is 1
+             (1 + 3 * 2 ** -8, 1 + 2 ** -6),                    # tie between odd 1 + 2^-7 and even 1 + 2^-6
+             (1 + 2 ** -8 + 2 ** -20, 1 + 2 ** -7),             # just above the tie
+             (-(1 + 2 ** -8), -one), (0.0, 0.0), (3.0, 3.0), (2.0 ** -126, 2.0 ** -126),
+             (65535.0, 65536.0), (255.5, 256.0)]
+    got = om.bf16_round(np.array([c for c, _ in cases]))
+    assert got.tolist() == [r for _, r in cases]
+
+
+def test_bf16_round_matches_torch_conversion():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(3)
+    x = (rng.standard_normal(20000) * np.exp(rng.uniform(-40, 40, 20000))).astype(np.float32)
+    ties = (np.arange(1, 2001, dtype=np.uint32) << 16 | 0x8000).view(np.float32)   # exact ties
+    x = np.concatenate([x, ties, -ties])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+    assert np.array_equal(om.bf16_round(x), ref)
+
+
+def test_bf16_forward_is_exact_on_representable_operands():
+    shape = (8, 6, 0, 5)                        # one linear map: no tanh between products
+    _, n = om.layout(*shape)
+    rng = np.random.default_rng(4)
+    # values with at most 8 significant bits are their own bfloat16
+    w = rng.integers(-127, 128, n) / 128.0
+    x = rng.integers(-127, 128, (3, 8)) / 64.0
+    y0, a0 = om.forward(w, x, shape)
+    y1, a1 = om.forward(w, x, shape, bf16=True)
+    assert np.array_equal(y0, y1)
+    dy = rng.integers(-127, 128, y0.shape) / 32.0
+    d0 = om.backward(w, a0, dy, shape)
+    d1 = om.backward(w, a1, dy, shape, bf16=True)
+    assert np.array_equal(d0[0], d1[0]) and np.array_equal(d0[1], d1[1])
+
+
+def test_bf16_forward_within_the_rounding_bound():
+    shape = (40, 16, 0, 12)
+    _, n = om.layout(*shape)
+    rng = np.random.default_rng(5)
+    w, x = rng.standard_normal(n), rng.standard_normal((7, 40))
+    y, _ = om.forward(w, x, shape)
+    yb, _ = om.forward(w, x, shape, bf16=True)
+    wl = w[:40 * 12].reshape(40, 12)
+    bound = (2 * 2.0 ** -8 + 2.0 ** -16) * (np.abs(x) @ np.abs(wl))
+    assert np.all(np.abs(yb - y) <= bound)
+    assert np.any(yb != y)                      # the rounding is not a no-op
+
+
+def test_bf16_planted_truncation_is_caught(monkeypatch):
+    def truncate(a):
+        u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32) & np.uint32(0xFFFF0000)
+        return u.view(np.float32).astype(np.float64)
+    monkeypatch.setattr(om, "bf16_round", truncate)
+    with pytest.raises(AssertionError):
+        test_bf16_round_hand_values()
