@@ -129,7 +129,7 @@ def learned_guess_experiment(args) -> dict:
                          newton_tol=args.lg_newton_tol)
     st32 = ImplicitStepper(case.structure(), mesh.k_elem, mesh.order, prm.mach, prm.reynolds, dt,
                            lambda q: jacobian_blocks(q, mesh, prm, dt), lin_tol=args.lg_lin_tol,
-                           newton_tol=args.lg_newton_tol, precision="fp32")
+                           newton_tol=args.lg_newton_tol, precision="fp32", graph=True)
     n_elem, dpe = mesh.n_elem, 5 * mesh.p ** 3
     lg = LearnedGuess(n_elem, dpe, capacity=args.lg_train, seed=args.lg_seed, batch=args.lg_batch)
     q = case.q_state.reshape(-1).contiguous()
@@ -170,7 +170,8 @@ def learned_guess_experiment(args) -> dict:
                 ("previous_newton_start", "newton"), ("learned_newton_start", "newton"),
                 ("learned_bf16_newton_start", "newton"),
                 ("fp32_ir_zero", "gmres"), ("fp32_ir_previous_newton_start", "newton"),
-                ("fp32_ir_learned_newton_start", "newton")]
+                ("fp32_ir_learned_newton_start", "newton"),
+                ("fp32_graph_previous_newton_start", "newton"), ("fp32_graph_learned_newton_start", "newton")]
     names = [v for v, _ in variants]
     rec = {k: {"first": [], "total": [], "newton": [], "seconds": [], "guess_res": [], "rejected": []}
            for k in names}
@@ -192,7 +193,8 @@ def learned_guess_experiment(args) -> dict:
         for name, mode in variants:
             g = None if name.endswith("zero") else (dq_prev if "previous" in name else
                                                     (pred16 if "bf16" in name else pred))
-            q1, info = (st32 if name.startswith("fp32") else st).solve_step(q, guess=g, mode=mode)
+            q1, info = (st32 if name.startswith("fp32") else st).solve_step(q, guess=g, mode=mode,
+                                                                            graph="graph" in name)
             if not info["converged"]:
                 raise RuntimeError(f"step {step} ({name}) did not converge: {info}")
             r = rec[name]
