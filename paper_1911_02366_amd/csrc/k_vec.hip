@@ -381,6 +381,47 @@ __global__ __launch_bounds__(kThreads) void multidot_kernel(const double *__rest
   }
 }
 
+// Stage 1 for up to NV vectors at once: each thread reads w[i] once and keeps
+// the nv running dot products in registers; one reduction per workgroup
+// (cross-lane adds, then the four waves' sums through LDS) writes
+// partials[k * nblocks + block].  Same chunks and the same summation tree for
+// every k, so results are bitwise repeatable.
+template <int NV>
+__global__ __launch_bounds__(kThreads) void multidot_regs_kernel(const double *__restrict__ v, int64_t ld,
+                                                                 int nv, const double *__restrict__ w,
+                                                                 int64_t n, double *__restrict__ partials,
+                                                                 const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
+  __shared__ double red[kThreads / 64][NV];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * chunk;
+  const int64_t hi = min(n, lo + chunk);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (int64_t i = lo + tid; i < hi; i += kThreads) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nv) acc[k] += v[(int64_t)k * ld + i] * wi;
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < nv) {
+      const double t = wave_sum(acc[k]);
+      if (lane == 0) red[wid][k] = t;
+    }
+  }
+  __syncthreads();
+  if (tid < nv) {
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < kThreads / 64; ++q) tot += red[q][tid];
+    partials[(int64_t)tid * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
 // stage 2: out[k] = sum_b partials[k * nblocks + b], one wave per k
 __global__ void multidot_finish_kernel(const double *__restrict__ partials, int nblocks, int nv,
                                        double *__restrict__ out, const int32_t *__restrict__ halt) {
@@ -553,8 +594,17 @@ hipError_t launch_copy_f64(const double *src, double *dst, size_t n, hipStream_t
 hipError_t launch_multidot(const double *v, int64_t ld, int32_t nv, const double *w, int64_t n,
                            double *partials, int32_t nblocks, double *out, hipStream_t s,
                            const int32_t *halt) {
-  hipLaunchKernelGGL(multidot_kernel, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n,
-                     partials, halt);
+  if (nv <= 8)
+    hipLaunchKernelGGL(multidot_regs_kernel<8>, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n, partials,
+                       halt);
+  else if (nv <= 16)
+    hipLaunchKernelGGL(multidot_regs_kernel<16>, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n,
+                       partials, halt);
+  else if (nv <= 32)
+    hipLaunchKernelGGL(multidot_regs_kernel<32>, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n,
+                       partials, halt);
+  else
+    hipLaunchKernelGGL(multidot_kernel, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n, partials, halt);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int waves_per_block = kThreads / 64;
