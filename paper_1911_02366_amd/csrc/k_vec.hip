@@ -120,8 +120,11 @@ __global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
 // ---------------------------------------------------- BSR product + pull
 // One wave per boundary node g (5 output rows).  Lanes 0..59 cover 12 blocks of
 // row g at a time, lane l taking row (l % 5) of block (l / 5); each lane reads
-// 5 contiguous values, so a wave reads 12 whole blocks (2400 bytes) per step.
-// Partial sums meet in LDS (wave-private slice) and lanes 0..4 finish the rows.
+// 5 contiguous values, so a wave reads 12 whole blocks (2400 bytes) per step,
+// two steps per loop trip.  The pull of element contributions (lanes 0..4) is
+// loaded before the block loop so its dependent loads overlap it, and the 12
+// partial sums of each output row meet through cross-lane adds (lanes l, l+5,
+// ..., l+55 hold row l % 5): no LDS and no workgroup barrier.
 __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
     int64_t n_bnodes, double c0, const double *__restrict__ src0, const int32_t *__restrict__ map0,
     double c1, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
@@ -130,37 +133,59 @@ __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
     const int32_t *__restrict__ pull_idx, const double *__restrict__ t, double *__restrict__ out,
     const int32_t *__restrict__ halt) {
   if (halt && *halt) return;
-  __shared__ double part[kThreads];
   const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  const int64_t g = (int64_t)blockIdx.x * (kThreads / 64) + wid;
-  const bool active = g < n_bnodes;
+  const int64_t g = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (g >= n_bnodes) return;   // whole waves leave together: no barrier below
+  double p = 0.0, o0 = 0.0;
+  if (lane < 5) {
+    const int64_t j = 5 * g + lane;
+    if (c2 != 0.0)
+      for (int q = pull_ptr[g]; q < pull_ptr[g + 1]; ++q) p += t[5 * (int64_t)pull_idx[q] + lane];
+    if (c0 != 0.0) o0 = src0[map0 ? map0[j] : j];
+  }
   double s = 0.0;
   const int v = lane % 5, bq = lane / 5;
-  if (active && c1 != 0.0 && lane < 60) {
-    for (int64_t blk = rowptr[g] + bq; blk < rowptr[g + 1]; blk += 12) {
-      const int64_t vb = src_idx ? (int64_t)src_idx[blk] : blk;
-      const double *vr = val + vb * 25 + v * 5;
-      const double *xv = x + (int64_t)col[blk] * 5;
+  if (c1 != 0.0 && lane < 60) {
+    const int64_t b0 = rowptr[g], b1 = rowptr[g + 1];
+    double s2 = 0.0;
+    int64_t blk = b0 + bq;
+    for (; blk + 12 < b1; blk += 24) {
+      const int64_t va = src_idx ? (int64_t)src_idx[blk] : blk;
+      const int64_t vb = src_idx ? (int64_t)src_idx[blk + 12] : blk + 12;
+      const double *ra = val + va * 25 + v * 5, *rb = val + vb * 25 + v * 5;
+      const double *xa = x + (int64_t)col[blk] * 5, *xb = x + (int64_t)col[blk + 12] * 5;
+      double ma[5], mb[5], ya[5], yb[5];
 #pragma unroll
-      for (int w = 0; w < 5; ++w) s += vr[w] * xv[w];
+      for (int w = 0; w < 5; ++w) {
+        ma[w] = ra[w];
+        mb[w] = rb[w];
+        ya[w] = xa[w];
+        yb[w] = xb[w];
+      }
+#pragma unroll
+      for (int w = 0; w < 5; ++w) {
+        s += ma[w] * ya[w];
+        s2 += mb[w] * yb[w];
+      }
     }
+    if (blk < b1) {
+      const int64_t va = src_idx ? (int64_t)src_idx[blk] : blk;
+      const double *ra = val + va * 25 + v * 5;
+      const double *xa = x + (int64_t)col[blk] * 5;
+#pragma unroll
+      for (int w = 0; w < 5; ++w) s += ra[w] * xa[w];
+    }
+    s += s2;
   }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (active && lane < 5) {
-    const double *pw = part + wid * 64;
-    double acc = 0.0;
-    for (int q = lane; q < 60; q += 5) acc += pw[q];
-    const int64_t j = 5 * g + lane;
-    double o = c1 * acc;
-    if (c0 != 0.0) o += c0 * src0[map0 ? map0[j] : j];
-    if (c2 != 0.0) {
-      double p = 0.0;
-      for (int q = pull_ptr[g]; q < pull_ptr[g + 1]; ++q) p += t[5 * (int64_t)pull_idx[q] + lane];
-      o += c2 * p;
-    }
-    out[j] = o;
+  // row sums: lanes l < 30 add lane l + 30, l < 15 add l + 15, then l < 5 add l + 5 and l + 10
+  s += __shfl_down(s, 30);
+  s += __shfl_down(s, 15);
+  const double s5 = __shfl_down(s, 5), s10 = __shfl_down(s, 10);
+  if (lane < 5) {
+    double o = c1 * (s + s5 + s10);
+    if (c0 != 0.0) o += c0 * o0;
+    if (c2 != 0.0) o += c2 * p;
+    out[5 * g + lane] = o;
   }
 }
 
