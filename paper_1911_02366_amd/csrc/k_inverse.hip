@@ -34,7 +34,7 @@ namespace {
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kRowsPerThread = 3;    // rows owned per thread (n <= 1536)
-constexpr int kGroup = 5;            // output tiles per wave in flight
+constexpr int kGroup = 2;            // output tiles per wave in flight (keeps VGPRs <= 128: two workgroups per CU)
 
 // LDS layout of one element's workgroup: panel width NB, panel row stride PS
 // (padded against bank conflicts; the compact layouts use NB + 1), the number
@@ -479,8 +479,13 @@ constexpr size_t kLdsLimit = 160 * 1024 - 512;
 // the widest panel whose layout fits the LDS of one workgroup
 template <typename T>
 hipError_t gj_dispatch(Plan &p, T *work, T *out) {
-  if (GjWide<T, 32, true>::lds_bytes(p.max_ni) <= kLdsLimit) return gj_launch<GjWide<T, 32, true>>(p, work, out);
-  if (GjWide<T, 16, true>::lds_bytes(p.max_ni) <= kLdsLimit) return gj_launch<GjWide<T, 16, true>>(p, work, out);
+  // the widest panel with which two workgroups share a CU (latency hiding beats
+  // fewer passes over the block), else the widest that fits at all
+  const int n = p.max_ni;
+  if (GjWide<T, 32, true>::lds_bytes(n) <= kLdsLimit / 2) return gj_launch<GjWide<T, 32, true>>(p, work, out);
+  if (GjWide<T, 16, true>::lds_bytes(n) <= kLdsLimit / 2) return gj_launch<GjWide<T, 16, true>>(p, work, out);
+  if (GjWide<T, 32, true>::lds_bytes(n) <= kLdsLimit) return gj_launch<GjWide<T, 32, true>>(p, work, out);
+  if (GjWide<T, 16, true>::lds_bytes(n) <= kLdsLimit) return gj_launch<GjWide<T, 16, true>>(p, work, out);
   return gj_launch<GjWide<T, 8, true>>(p, work, out);
 }
 
