@@ -455,6 +455,20 @@ def main() -> int:
     kernels = {k: v for k, v in phases.items() if k in work}
     dominant = max(kernels, key=lambda k: kernels[k]["ms"])
     entries = {k: roofline_entry(k, work[k], kernels[k], args.precision) for k in kernels}
+    # the three factor/condense kernels together, against the FP64 (or FP32) matrix-core peak:
+    # LU-equivalent flops (2/3) n_i^3 + 2 n_i^2 n_c + 2 n_c^2 n_i per element over their summed time
+    fc_keys = ("inverse", "gemm_x", "gemm_s")
+    if all(entries.get(k) for k in fc_keys):
+        fc_ms = sum(entries[k]["avg_launch_ms"] for k in fc_keys)
+        fc_flops = work["inverse"]["flops"] / 3.0 + work["gemm_x"]["flops"] + work["gemm_s"]["flops"]
+        peak = PEAK["fp64_mfma_tflops"] if args.precision == "fp64" else PEAK["fp32_mfma_tflops"]
+        ach = fc_flops / (fc_ms / 1e3) / 1e12
+        entries["factor_condense"] = {"kernel": "factor_condense (inverse + gemm_x + gemm_s)", "bound": "mfma",
+                                      "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                                      "frac": round(ach / peak, 4), "traffic": None, "avg_launch_ms": round(fc_ms, 4),
+                                      "launches": entries["inverse"]["launches"],
+                                      "algorithmic_flops_per_launch": fc_flops,
+                                      "flop_count": "LU-equivalent: (2/3) n_i^3 + 2 n_i^2 n_c + 2 n_c^2 n_i per element"}
     from paper_1911_02366_amd.profiling import load_traffic
     csrc = os.path.join(ROOT, "paper_1911_02366_amd", "csrc")
     for k, srcs in (("schur_apply", ["k_vec.hip"]), ("gemm_s", ["k_gemm.hip"]), ("gemm_x", ["k_gemm.hip"]),
