@@ -523,6 +523,14 @@ hipError_t gj_blocked_run(Plan &p, typename L::T *work, typename L::T *out) {
 template <typename T>
 hipError_t gj_blocked_dispatch(Plan &p, T *work, T *out) {
   const int n = p.max_ni;
+  // as in the single-kernel form: first the widest layout with which two
+  // workgroups share a CU, then the widest that fits
+  if (GjWide<T, 32, false>::lds_bytes(n) <= kLdsLimit / 2) return gj_blocked_run<GjWide<T, 32, false>>(p, work, out);
+  if (GjCompact<T, 32, false>::lds_bytes(n) <= kLdsLimit / 2)
+    return gj_blocked_run<GjCompact<T, 32, false>>(p, work, out);
+  if (GjWide<T, 16, false>::lds_bytes(n) <= kLdsLimit / 2) return gj_blocked_run<GjWide<T, 16, false>>(p, work, out);
+  if (GjCompact<T, 16, false>::lds_bytes(n) <= kLdsLimit / 2)
+    return gj_blocked_run<GjCompact<T, 16, false>>(p, work, out);
   if (GjWide<T, 32, false>::lds_bytes(n) <= kLdsLimit) return gj_blocked_run<GjWide<T, 32, false>>(p, work, out);
   if (GjCompact<T, 32, false>::lds_bytes(n) <= kLdsLimit)
     return gj_blocked_run<GjCompact<T, 32, false>>(p, work, out);
