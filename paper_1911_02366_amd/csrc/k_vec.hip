@@ -425,11 +425,18 @@ __global__ __launch_bounds__(kThreads) void multidot_regs_kernel(const double *_
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  // rows past nv repeat row nv - 1 (always in bounds, served from cache) so that
+  // the NV loads of an element carry no branch and are all in flight together
+  const double *__restrict__ rows[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) rows[k] = v + (int64_t)(k < nv ? k : nv - 1) * ld;
   for (int64_t i = lo + tid; i < hi; i += kThreads) {
     const double wi = w[i];
+    double vk[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-      if (k < nv) acc[k] += v[(int64_t)k * ld + i] * wi;
+    for (int k = 0; k < NV; ++k) vk[k] = rows[k][i];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] += vk[k] * wi;
   }
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -619,17 +626,29 @@ hipError_t launch_copy_f64(const double *src, double *dst, size_t n, hipStream_t
 hipError_t launch_multidot(const double *v, int64_t ld, int32_t nv, const double *w, int64_t n,
                            double *partials, int32_t nblocks, double *out, hipStream_t s,
                            const int32_t *halt) {
-  if (nv <= 8)
-    hipLaunchKernelGGL(multidot_regs_kernel<8>, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n, partials,
-                       halt);
-  else if (nv <= 16)
-    hipLaunchKernelGGL(multidot_regs_kernel<16>, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n,
-                       partials, halt);
-  else if (nv <= 32)
-    hipLaunchKernelGGL(multidot_regs_kernel<32>, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n,
-                       partials, halt);
-  else
+#define SCDG_MULTIDOT(NVB)                                                                                      \
+  hipLaunchKernelGGL(multidot_regs_kernel<NVB>, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n, partials, \
+                     halt)
+  if (nv <= 0) return hipSuccess;
+  if (nv <= 4) {
+    SCDG_MULTIDOT(4);
+  } else if (nv <= 8) {
+    SCDG_MULTIDOT(8);
+  } else if (nv <= 12) {
+    SCDG_MULTIDOT(12);
+  } else if (nv <= 16) {
+    SCDG_MULTIDOT(16);
+  } else if (nv <= 20) {
+    SCDG_MULTIDOT(20);
+  } else if (nv <= 24) {
+    SCDG_MULTIDOT(24);
+  } else if (nv <= 28) {
+    SCDG_MULTIDOT(28);
+  } else if (nv <= 32) {
+    SCDG_MULTIDOT(32);
+  } else
     hipLaunchKernelGGL(multidot_kernel, dim3(nblocks), dim3(kThreads), 0, s, v, ld, nv, w, n, partials, halt);
+#undef SCDG_MULTIDOT
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int waves_per_block = kThreads / 64;
