@@ -132,6 +132,10 @@ def learned_guess_experiment(args) -> dict:
                            newton_tol=args.lg_newton_tol, precision="fp32", graph=True)
     n_elem, dpe = mesh.n_elem, 5 * mesh.p ** 3
     lg = LearnedGuess(n_elem, dpe, capacity=args.lg_train, seed=args.lg_seed, batch=args.lg_batch)
+    # the same network with the step's right-hand side R(Q_s) as a third input block
+    lgr = LearnedGuess(n_elem, dpe, capacity=args.lg_train, seed=args.lg_seed, batch=args.lg_batch,
+                       use_residual=True)
+    inv_dt = 1.0 / dt
     q = case.q_state.reshape(-1).contiguous()
     dq_prev = torch.zeros_like(q)
     rc_prev = None
@@ -139,12 +143,14 @@ def learned_guess_experiment(args) -> dict:
     t_collect = time.perf_counter()
     for step in range(1, args.lg_train + 1):
         st.prepare(q)
+        r_s = st.dg.residual(q, q, inv_dt)
         q1, info = st.solve_step(q, guess=dq_prev if step > 1 else None)
         if not info["converged"]:
             raise RuntimeError(f"step {step} did not converge: {info}")
         dq = q1 - q
         if step > 1:
             lg.record(q, dq_prev, dq)
+            lgr.record(q, dq_prev, dq, r_s)
             rc_prev = lg.correction_rms(q, dq_prev, dq)
         q, dq_prev = q1, dq
         log(f"train-phase step {step}: newton {info['newton']} gmres {info['gmres']}")
@@ -164,18 +170,25 @@ def learned_guess_experiment(args) -> dict:
     history16, hold16 = lg16.train(epochs=args.lg_epochs, lr=args.lg_lr, holdout_rows=n_elem)
     torch.cuda.synchronize()
     t_train16 = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    history_r, hold_r = lgr.train(epochs=args.lg_epochs, lr=args.lg_lr, holdout_rows=n_elem)
+    torch.cuda.synchronize()
+    t_train_r = time.perf_counter() - t0
+    log(f"residual-input network: loss {history_r[0]:.3e} -> {history_r[-1]:.3e}, hold-out {hold_r:.3e}")
     log(f"trained {args.lg_epochs} epochs in {t_train:.1f} s: loss {history[0]:.3e} -> {history[-1]:.3e}, "
         f"hold-out {hold:.3e} (previous increment: {hold_zero:.3e})")
     variants = [("zero", "gmres"), ("previous", "gmres"), ("learned", "gmres"),
                 ("previous_newton_start", "newton"), ("learned_newton_start", "newton"),
-                ("learned_bf16_newton_start", "newton"),
+                ("learned_bf16_newton_start", "newton"), ("learned_r_newton_start", "newton"),
                 ("fp32_ir_zero", "gmres"), ("fp32_ir_previous_newton_start", "newton"),
                 ("fp32_ir_learned_newton_start", "newton"),
-                ("fp32_graph_previous_newton_start", "newton"), ("fp32_graph_learned_newton_start", "newton")]
+                ("fp32_graph_previous_newton_start", "newton"), ("fp32_graph_learned_newton_start", "newton"),
+                ("fp32_graph_learned_r_newton_start", "newton")]
     names = [v for v, _ in variants]
     rec = {k: {"first": [], "total": [], "newton": [], "seconds": [], "guess_res": [], "rejected": []}
            for k in names}
-    infer_ms, infer16_ms = [], []
+    infer_ms, infer16_ms, infer_r_ms = [], [], []
     prep = {"fp64": [], "fp32": []}
     for step in range(args.lg_train + 1, args.lg_steps + 1):
         prep["fp64"].append(st.prepare(q))
@@ -189,10 +202,15 @@ def learned_guess_experiment(args) -> dict:
         pred16 = lg16.predict(q, dq_prev, rc_prev)
         torch.cuda.synchronize()
         infer16_ms.append((time.perf_counter() - t1) * 1e3)
+        t1 = time.perf_counter()
+        pred_r = lgr.predict(q, dq_prev, rc_prev, st.dg.residual(q, q, inv_dt))
+        torch.cuda.synchronize()
+        infer_r_ms.append((time.perf_counter() - t1) * 1e3)
         out = {}
         for name, mode in variants:
             g = None if name.endswith("zero") else (dq_prev if "previous" in name else
-                                                    (pred16 if "bf16" in name else pred))
+                                                    (pred16 if "bf16" in name else
+                                                     (pred_r if "learned_r" in name else pred)))
             q1, info = (st32 if name.startswith("fp32") else st).solve_step(q, guess=g, mode=mode,
                                                                             graph="graph" in name)
             if not info["converged"]:
@@ -201,7 +219,7 @@ def learned_guess_experiment(args) -> dict:
             r["first"].append(info["first_gmres"])
             r["total"].append(info["gmres"])
             r["newton"].append(info["newton"])
-            infer = infer16_ms[-1] if "bf16" in name else infer_ms[-1]
+            infer = infer16_ms[-1] if "bf16" in name else (infer_r_ms[-1] if "learned_r" in name else infer_ms[-1])
             r["seconds"].append(info["seconds"] + (infer * 1e-3 if "learned" in name else 0.0))
             r["guess_res"].append(info["guess_res"])
             r["rejected"].append(info["guess_rejected"])
@@ -228,6 +246,10 @@ def learned_guess_experiment(args) -> dict:
                        "holdout_loss": hold16, "alpha": lg16.alpha},
         "inference_ms_mean": mean(infer_ms),
         "inference_bf16_ms_mean": mean(infer16_ms),
+        "train_residual_input": {"seconds": t_train_r, "loss_first_epoch": history_r[0],
+                                 "loss_last_epoch": history_r[-1], "holdout_loss": hold_r, "alpha": lgr.alpha,
+                                 "network": f"{3 * dpe}-256-256-{dpe} tanh, FP32, {lgr.net.n_params} parameters"},
+        "inference_residual_input_ms_mean": mean(infer_r_ms),
         "guess_rejected": {k: int(np.sum(rec[k]["rejected"])) for k in names},
         "forcing": "GMRES tol per Newton iteration = clip(0.5 newton_tol |R0| / |R|, gmres_tol, 0.1)",
     }
@@ -245,6 +267,7 @@ def learned_guess_experiment(args) -> dict:
     result["time_to_solution_vs_plain_fp64"] = {k: z / result["step_seconds_mean"][k] for k in names}
     lg.close()
     lg16.close()
+    lgr.close()
     st.close()
     st32.close()
     return result

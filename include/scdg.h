@@ -352,13 +352,16 @@ scdg_status scdg_newton_step(scdg_plan *p, scdg_dg *dg, const double *q_s, doubl
  * [fan_in x fan_out] row-major followed by b_l [fan_out]; the caller owns it
  * and its Adam moments.  Batches are row-major [batch x width].
  * Features for element e of a DG vector (natural DOF order, d = 5 P^3 DOFs
- * per element, n_in = 2 d, n_out = d):
- *   x_e = [ (Q_e - mean_v) / std_v , dQprev_e / rp_v ],
+ * per element, n_out = d, n_in = 2 d or 3 d):
+ *   x_e = [ (Q_e - mean_v) / std_v , dQprev_e / rp_v ( , R_e / rr_v ) ],
  *   target t_e = (dQ_e - dQprev_e) / rc_v,  prediction dQ_e = dQprev_e + rc_v y_e,
  * with per-variable mean and standard deviation of Q, root mean square rp of
- * dQprev and rc of dQ - dQprev over the whole field (stats: 20 device doubles
- * mean[5], std[5], rp[5], rc[5]; a zero spread is replaced by 1).  The network
- * thus predicts a correction to the previous increment.
+ * dQprev, rc of dQ - dQprev and rr of R over the whole field (stats: 25 device
+ * doubles mean[5], std[5], rp[5], rc[5], rr[5]; a zero spread is replaced by
+ * 1).  R is the nonlinear residual at the start of the step, R(Q_s) = H(Q_s),
+ * the right-hand side the step's increment answers; the third block is used
+ * when n_in = 3 d.  The network thus predicts a correction to the previous
+ * increment.
  * The object owns the hidden activations of its last forward call (for
  * scdg_mlp_backward), scratch for the backward pass and reduction partials.
  * All calls are asynchronous on the object's stream and bitwise repeatable.
@@ -397,13 +400,15 @@ scdg_status scdg_mlp_mse(scdg_mlp *m, const float *y, const float *t, int64_t n,
 /* dst[r] = src[idx[r]] for rows of width floats (idx: device int32, count rows) */
 scdg_status scdg_mlp_gather(scdg_mlp *m, const float *src, int32_t width, const int32_t *idx, int32_t count,
                             float *dst);
-/* Field statistics of the features (n_dof = 5 * nodes, natural order); dq
- * (the increment that followed dq_prev) may be NULL, then rc = rp. */
+/* Field statistics of the features (n_dof = 5 * nodes, natural order; stats:
+ * 25 device doubles); dq (the increment that followed dq_prev) may be NULL,
+ * then rc = rp; r (the residual R(Q_s)) may be NULL, then rr = 1. */
 scdg_status scdg_guess_stats(scdg_mlp *m, const double *q, const double *dq_prev, const double *dq,
-                             int64_t n_dof, double *stats);
-/* x [n_elem x n_in] from Q and dQprev (needs n_in == 2 n_out, n_out % 5 == 0) */
-scdg_status scdg_guess_features(scdg_mlp *m, const double *q, const double *dq_prev, const double *stats,
-                                int32_t n_elem, float *x);
+                             const double *r, int64_t n_dof, double *stats);
+/* x [n_elem x n_in] from Q, dQprev and, when n_in == 3 n_out, R (r may be NULL
+ * when n_in == 2 n_out; n_out % 5 == 0; SCDG_ERR_ARG otherwise) */
+scdg_status scdg_guess_features(scdg_mlp *m, const double *q, const double *dq_prev, const double *r,
+                                const double *stats, int32_t n_elem, float *x);
 /* t [n_elem x n_out] = (dQ - dQprev) / rc */
 scdg_status scdg_guess_target(scdg_mlp *m, const double *dq, const double *dq_prev, const double *stats,
                               int32_t n_elem, float *t);

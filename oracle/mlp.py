@@ -112,10 +112,11 @@ def adam(w, g, m1, m2, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
 # network's features and targets
 # --------------------------------------------------------------------------
 
-def field_stats(q: np.ndarray, dq_prev: np.ndarray, dq: np.ndarray | None = None):
+def field_stats(q: np.ndarray, dq_prev: np.ndarray, dq: np.ndarray | None = None,
+                r: np.ndarray | None = None):
     """Per-variable mean and population standard deviation of q, root mean
-    square rp of dq_prev and rc of dq - dq_prev (rc = rp without dq) over all
-    nodes; a zero spread becomes 1."""
+    square rp of dq_prev, rc of dq - dq_prev (rc = rp without dq) and rr of the
+    residual r (1 without r) over all nodes; a zero spread becomes 1."""
     qv = np.asarray(q, dtype=np.float64).reshape(-1, 5)
     dv = np.asarray(dq_prev, dtype=np.float64).reshape(-1, 5)
     mean = qv.mean(axis=0)
@@ -129,27 +130,36 @@ def field_stats(q: np.ndarray, dq_prev: np.ndarray, dq: np.ndarray | None = None
         cv = np.asarray(dq, dtype=np.float64).reshape(-1, 5) - dv
         rc = np.sqrt((cv * cv).mean(axis=0))
         rc = np.where(rc > 0, rc, 1.0)
-    return mean, std, rms, rc
+    if r is None:
+        rr = np.ones(5)
+    else:
+        rv = np.asarray(r, dtype=np.float64).reshape(-1, 5)
+        rr = np.sqrt((rv * rv).mean(axis=0))
+        rr = np.where(rr > 0, rr, 1.0)
+    return mean, std, rms, rc, rr
 
 
-def features(q, dq_prev, stats, n_elem: int):
-    """Rows [ (Q_e - mean) / std , dQprev_e / rp ] per element."""
-    mean, std, rms, _ = stats
+def features(q, dq_prev, stats, n_elem: int, r=None):
+    """Rows [ (Q_e - mean) / std , dQprev_e / rp ( , R_e / rr ) ] per element
+    (the residual block when r is given)."""
+    mean, std, rms, _, rr = stats
     qv = np.asarray(q, dtype=np.float64).reshape(n_elem, -1, 5)
     dv = np.asarray(dq_prev, dtype=np.float64).reshape(n_elem, -1, 5)
-    return np.concatenate([((qv - mean) / std).reshape(n_elem, -1), (dv / rms).reshape(n_elem, -1)],
-                          axis=1)
+    blocks = [((qv - mean) / std).reshape(n_elem, -1), (dv / rms).reshape(n_elem, -1)]
+    if r is not None:
+        blocks.append((np.asarray(r, dtype=np.float64).reshape(n_elem, -1, 5) / rr).reshape(n_elem, -1))
+    return np.concatenate(blocks, axis=1)
 
 
 def target(dq, dq_prev, stats, n_elem: int):
     """(dQ_e - dQprev_e) / rc: the correction to the previous increment."""
-    _, _, _, rms = stats
+    rms = stats[3]
     d = (np.asarray(dq, dtype=np.float64) - np.asarray(dq_prev, dtype=np.float64)).reshape(n_elem, -1, 5)
     return (d / rms).reshape(n_elem, -1)
 
 
 def apply(dq_prev, y, stats, n_elem: int):
     """dQprev_e + rc y_e."""
-    _, _, _, rms = stats
+    rms = stats[3]
     dv = np.asarray(dq_prev, dtype=np.float64).reshape(n_elem, -1, 5)
     return (dv + rms * np.asarray(y, dtype=np.float64).reshape(n_elem, -1, 5)).reshape(-1)

@@ -142,8 +142,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_mlp_adam": (i32, [vp, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, i32]),
         "scdg_mlp_mse": (i32, [vp, vp, vp, i64, vp, vp]),
         "scdg_mlp_gather": (i32, [vp, vp, i32, vp, i32, vp]),
-        "scdg_guess_stats": (i32, [vp, vp, vp, vp, i64, vp]),
-        "scdg_guess_features": (i32, [vp, vp, vp, vp, i32, vp]),
+        "scdg_guess_stats": (i32, [vp, vp, vp, vp, vp, i64, vp]),
+        "scdg_guess_features": (i32, [vp, vp, vp, vp, vp, i32, vp]),
         "scdg_guess_target": (i32, [vp, vp, vp, vp, i32, vp]),
         "scdg_guess_apply": (i32, [vp, vp, vp, vp, i32, vp]),
     }

@@ -279,16 +279,18 @@ __global__ void sum_final_kernel(const double *__restrict__ partial, int n, int 
 }
 
 // Field statistics in two passes (the second sums squared deviations from the
-// mean, which avoids the cancellation of E[q^2] - E[q]^2).  Pass 1 sums q_v and
-// dqp_v^2 (dqp: previous increment); pass 2 sums (q_v - mean_v)^2 and, when the
-// increment dq is given, (dq_v - dqp_v)^2.  Each block writes its partial sums.
+// mean, which avoids the cancellation of E[q^2] - E[q]^2).  Pass 1 sums q_v,
+// dqp_v^2 (dqp: previous increment) and r_v^2 (r: residual, when given); pass 2
+// sums (q_v - mean_v)^2 and, when the increment dq is given, (dq_v - dqp_v)^2.
+// Each block writes its 15 partial sums.
 __global__ void stats_partial_kernel(const double *__restrict__ q, const double *__restrict__ dqp,
-                                     const double *__restrict__ dq, const double *__restrict__ mean,
-                                     int64_t n_nodes, double *__restrict__ partial) {
-  __shared__ double red[10][256];
-  double s[10];
+                                     const double *__restrict__ dq, const double *__restrict__ r,
+                                     const double *__restrict__ mean, int64_t n_nodes,
+                                     double *__restrict__ partial) {
+  __shared__ double red[15][256];
+  double s[15];
 #pragma unroll
-  for (int k = 0; k < 10; ++k) s[k] = 0.0;
+  for (int k = 0; k < 15; ++k) s[k] = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_nodes;
        i += (int64_t)gridDim.x * blockDim.x) {
 #pragma unroll
@@ -304,38 +306,45 @@ __global__ void stats_partial_kernel(const double *__restrict__ q, const double 
       } else {
         s[v] += q[i * 5 + v];
         s[5 + v] += b * b;
+        if (r) {
+          const double c = r[i * 5 + v];
+          s[10 + v] += c * c;
+        }
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < 10; ++k) red[k][threadIdx.x] = s[k];
+  for (int k = 0; k < 15; ++k) red[k][threadIdx.x] = s[k];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w)
 #pragma unroll
-      for (int k = 0; k < 10; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+      for (int k = 0; k < 15; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x < 10) partial[(int64_t)blockIdx.x * 10 + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 15) partial[(int64_t)blockIdx.x * 15 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// stats = [mean[5], std[5], rms_prev[5], rms_corr[5]].  Pass 1 fills mean and
-// rms_prev; pass 2 fills std and rms_corr (rms_prev when no increment is given).
-// A zero spread or root mean square maps to 1.
+// stats = [mean[5], std[5], rms_prev[5], rms_corr[5], rms_res[5]].  Pass 1 fills
+// mean, rms_prev and rms_res; pass 2 fills std and rms_corr (rms_prev when no
+// increment is given).  A zero spread or root mean square maps to 1.
 __global__ void stats_final_kernel(const double *__restrict__ partial, int n_blocks, int64_t n_nodes,
                                    int pass, int have_dq, double *__restrict__ stats) {
   const int v = threadIdx.x;
   if (v >= 5) return;
-  double s1 = 0.0, s2 = 0.0;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int k = 0; k < n_blocks; ++k) {
-    s1 += partial[(int64_t)k * 10 + v];
-    s2 += partial[(int64_t)k * 10 + 5 + v];
+    s1 += partial[(int64_t)k * 15 + v];
+    s2 += partial[(int64_t)k * 15 + 5 + v];
+    s3 += partial[(int64_t)k * 15 + 10 + v];
   }
   const double n = (double)n_nodes;
   if (pass == 1) {
     stats[v] = s1 / n;
     const double rms = sqrt(s2 / n);
     stats[10 + v] = rms > 0.0 ? rms : 1.0;
+    const double rr = sqrt(s3 / n);
+    stats[20 + v] = rr > 0.0 ? rr : 1.0;
   } else {
     const double sd = sqrt(s1 / n);
     stats[5 + v] = (sd > 0.0 && sd > 1e-12 * fabs(stats[v])) ? sd : 1.0;
@@ -344,19 +353,21 @@ __global__ void stats_final_kernel(const double *__restrict__ partial, int n_blo
   }
 }
 
-// x[e] = [(q_e - mean) / std, dq_prev_e / rms] in FP32
+// x[e] = [(q_e - mean) / std, dq_prev_e / rms_prev (, r_e / rms_res)] in FP32;
+// nb = 2 or 3 blocks of dpe values per element
 __global__ void features_kernel(const double *__restrict__ q, const double *__restrict__ dq,
-                                const double *__restrict__ stats, int64_t n_elem, int dpe,
-                                float *__restrict__ x) {
+                                const double *__restrict__ r, const double *__restrict__ stats, int64_t n_elem,
+                                int dpe, int nb, float *__restrict__ x) {
   const int64_t total = n_elem * dpe;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = i / dpe;
     const int j = (int)(i - e * dpe);
     const int v = j % 5;
-    float *xe = x + e * 2 * dpe;
+    float *xe = x + e * nb * dpe;
     xe[j] = (float)((q[i] - stats[v]) / stats[5 + v]);
     xe[dpe + j] = (float)(dq[i] / stats[10 + v]);
+    if (nb == 3) xe[2 * dpe + j] = (float)(r[i] / stats[20 + v]);
   }
 }
 
@@ -582,29 +593,30 @@ scdg_status scdg_mlp_gather(scdg_mlp *m, const float *src, int32_t width, const 
 }
 
 scdg_status scdg_guess_stats(scdg_mlp *m, const double *q, const double *dq_prev, const double *dq,
-                             int64_t n_dof, double *stats) {
+                             const double *r, int64_t n_dof, double *stats) {
   if (!m || !q || !dq_prev || !stats || n_dof <= 0 || n_dof % 5) return SCDG_ERR_ARG;
   auto &c = m->c;
   const int64_t nodes = n_dof / 5;
   hipLaunchKernelGGL(scdg::stats_partial_kernel, dim3(scdg::kRedBlocks), dim3(256), 0, c.stream, q, dq_prev,
-                     nullptr, nullptr, nodes, c.red);
+                     nullptr, r, nullptr, nodes, c.red);
   hipLaunchKernelGGL(scdg::stats_final_kernel, dim3(1), dim3(64), 0, c.stream, c.red, scdg::kRedBlocks, nodes,
                      1, 0, stats);
   hipLaunchKernelGGL(scdg::stats_partial_kernel, dim3(scdg::kRedBlocks), dim3(256), 0, c.stream, q, dq_prev,
-                     dq, stats, nodes, c.red);
+                     dq, nullptr, stats, nodes, c.red);
   hipLaunchKernelGGL(scdg::stats_final_kernel, dim3(1), dim3(64), 0, c.stream, c.red, scdg::kRedBlocks, nodes,
                      2, dq ? 1 : 0, stats);
   return hip_status(hipGetLastError());
 }
 
-scdg_status scdg_guess_features(scdg_mlp *m, const double *q, const double *dq_prev, const double *stats,
-                                int32_t n_elem, float *x) {
+scdg_status scdg_guess_features(scdg_mlp *m, const double *q, const double *dq_prev, const double *r,
+                                const double *stats, int32_t n_elem, float *x) {
   if (!m || !q || !dq_prev || !stats || !x || n_elem <= 0) return SCDG_ERR_ARG;
   auto &c = m->c;
   const int dpe = c.n_out;
-  if (c.n_in != 2 * dpe || dpe % 5) return SCDG_ERR_ARG;
+  const int nb = c.n_in / dpe;
+  if (dpe % 5 || c.n_in != nb * dpe || (nb != 2 && nb != 3) || (nb == 3 && !r)) return SCDG_ERR_ARG;
   hipLaunchKernelGGL(scdg::features_kernel, dim3(scdg::grid_for((int64_t)n_elem * dpe)), dim3(256), 0,
-                     c.stream, q, dq_prev, stats, (int64_t)n_elem, dpe, x);
+                     c.stream, q, dq_prev, r, stats, (int64_t)n_elem, dpe, nb, x);
   return hip_status(hipGetLastError());
 }
 

@@ -120,17 +120,18 @@ class Mlp:
         return dst
 
     # ---------------------------------------------------------------- DG maps
-    def guess_stats(self, q, dq_prev, dq=None, stats=None):
+    def guess_stats(self, q, dq_prev, dq=None, r=None, stats=None):
+        """25 field statistics [mean, std, rms_prev, rms_corr, rms_res] x 5 variables."""
         if stats is None:
-            stats = torch.empty(20, dtype=torch.float64, device=q.device)
-        self._ok(self.lib.scdg_guess_stats(self.handle, _ptr(q), _ptr(dq_prev), _ptr(dq), q.numel(),
+            stats = torch.empty(25, dtype=torch.float64, device=q.device)
+        self._ok(self.lib.scdg_guess_stats(self.handle, _ptr(q), _ptr(dq_prev), _ptr(dq), _ptr(r), q.numel(),
                                            _ptr(stats)), "scdg_guess_stats")
         return stats
 
-    def features(self, q, dq_prev, stats, n_elem: int, x=None):
+    def features(self, q, dq_prev, stats, n_elem: int, x=None, r=None):
         if x is None:
             x = torch.empty(n_elem * self.n_in, dtype=torch.float32, device=q.device)
-        self._ok(self.lib.scdg_guess_features(self.handle, _ptr(q), _ptr(dq_prev), _ptr(stats), n_elem,
+        self._ok(self.lib.scdg_guess_features(self.handle, _ptr(q), _ptr(dq_prev), _ptr(r), _ptr(stats), n_elem,
                                               _ptr(x)), "scdg_guess_features")
         return x
 

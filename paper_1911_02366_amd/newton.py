@@ -179,7 +179,8 @@ class LearnedGuess:
 
     Scales change by orders of magnitude over a run (an initial transient
     decays), so every step is normalized by its own field statistics: the
-    features by the step's mean/std of Q and rms of dQprev, the target (the
+    features by the step's mean/std of Q and rms of dQprev (and of R(Q_s), the
+    step's right-hand side, for a network that takes it), the target (the
     correction dQ - dQprev) by the rms rc of that step's correction.  At
     prediction time the correction of the step is not known yet; the rms of
     the last known correction stands in for it.  A shrinkage factor alpha in
@@ -187,10 +188,14 @@ class LearnedGuess:
     correction (alpha = 0 reproduces the previous increment)."""
 
     def __init__(self, n_elem: int, dofs_per_elem: int, capacity: int, hidden: int = 256, layers: int = 2,
-                 seed: int = 0, batch: int = 1024, device="cuda", compute: str = "fp32"):
+                 seed: int = 0, batch: int = 1024, device="cuda", compute: str = "fp32",
+                 use_residual: bool = False):
         self.n_elem, self.dpe = n_elem, dofs_per_elem
         self.batch = batch
-        self.net = Mlp(2 * dofs_per_elem, hidden, layers, dofs_per_elem, max_batch=max(n_elem, batch))
+        # inputs: state and previous increment, plus R(Q_s) when use_residual
+        self.use_residual = use_residual
+        self.nx = (3 if use_residual else 2) * dofs_per_elem
+        self.net = Mlp(self.nx, hidden, layers, dofs_per_elem, max_batch=max(n_elem, batch))
         self.net.set_compute(compute)          # 'fp32' or 'bf16' matrix products
         self.w = self.net.init_params(seed, device, zero_output=True)
         self.m1 = torch.zeros_like(self.w)
@@ -199,7 +204,7 @@ class LearnedGuess:
         self.rng = np.random.default_rng(seed + 1)
         self.alpha = 1.0
         self.capacity = capacity            # number of stored steps
-        self.x = torch.empty(capacity * n_elem * 2 * dofs_per_elem, dtype=torch.float32, device=device)
+        self.x = torch.empty(capacity * n_elem * self.nx, dtype=torch.float32, device=device)
         self.t = torch.empty(capacity * n_elem * dofs_per_elem, dtype=torch.float32, device=device)
         self.count = 0                      # stored rows
         self.dev = device
@@ -208,23 +213,30 @@ class LearnedGuess:
         """Per-variable rms of dq - dq_prev (5 device doubles)."""
         return self.net.guess_stats(q_s, dq_prev, dq)[15:20].clone()
 
-    def record(self, q_s, dq_prev, dq):
-        """Add one step's (state, previous increment) -> increment samples."""
+    def _r(self, r):
+        if self.use_residual and r is None:
+            raise ValueError("this network takes the residual R(Q_s) as an input")
+        return r if self.use_residual else None
+
+    def record(self, q_s, dq_prev, dq, r=None):
+        """Add one step's (state, previous increment[, residual R(Q_s)]) -> increment samples."""
         if self.count + self.n_elem > self.capacity * self.n_elem:
             raise RuntimeError("training set is full")
-        stats = self.net.guess_stats(q_s, dq_prev, dq)
-        nx, nt = 2 * self.dpe, self.dpe
+        r = self._r(r)
+        stats = self.net.guess_stats(q_s, dq_prev, dq, r)
+        nx, nt = self.nx, self.dpe
         self.net.features(q_s, dq_prev, stats, self.n_elem,
-                          x=self.x[self.count * nx:(self.count + self.n_elem) * nx])
+                          x=self.x[self.count * nx:(self.count + self.n_elem) * nx], r=r)
         self.net.target(dq, dq_prev, stats, self.n_elem,
                         t=self.t[self.count * nt:(self.count + self.n_elem) * nt])
         self.count += self.n_elem
 
     def copy_samples(self, other: "LearnedGuess"):
         """Take over another instance's stored training rows (same sizes)."""
-        if (other.n_elem, other.dpe) != (self.n_elem, self.dpe) or other.count > self.capacity * self.n_elem:
+        if ((other.n_elem, other.dpe, other.nx) != (self.n_elem, self.dpe, self.nx)
+                or other.count > self.capacity * self.n_elem):
             raise ValueError("sample sets differ in size")
-        nx, nt = 2 * self.dpe, self.dpe
+        nx, nt = self.nx, self.dpe
         self.x[:other.count * nx].copy_(other.x[:other.count * nx])
         self.t[:other.count * nt].copy_(other.t[:other.count * nt])
         self.count = other.count
@@ -234,7 +246,7 @@ class LearnedGuess:
         (train) and the hold-out loss of the last `holdout_rows` stored rows (after
         fitting alpha on them, when given)."""
         n_train = self.count - holdout_rows
-        nx, nt = 2 * self.dpe, self.dpe
+        nx, nt = self.nx, self.dpe
         xb = torch.empty(self.batch * nx, dtype=torch.float32, device=self.dev)
         tb = torch.empty(self.batch * nt, dtype=torch.float32, device=self.dev)
         dy = torch.empty(self.batch * nt, dtype=torch.float32, device=self.dev)
@@ -263,7 +275,7 @@ class LearnedGuess:
 
     def _sums(self, row0: int, row1: int):
         """sum t^2, sum y^2 and sum t y over stored rows (from loss kernels)."""
-        nx, nt = 2 * self.dpe, self.dpe
+        nx, nt = self.nx, self.dpe
         loss = torch.empty(1, dtype=torch.float64, device=self.dev)
         stt = syy = sty = 0.0
         for s in range(row0, row1, self.batch):
@@ -292,15 +304,17 @@ class LearnedGuess:
         a = self.alpha
         return (stt - 2 * a * sty + a * a * syy) / n
 
-    def predict(self, q_s, dq_prev, rc_prev):
+    def predict(self, q_s, dq_prev, rc_prev, r=None):
         """Predicted increment of the step from q_s (natural DOF order); rc_prev is
-        the rms of the last known correction (see correction_rms)."""
-        stats = self.net.guess_stats(q_s, dq_prev)
+        the rms of the last known correction (see correction_rms); r = R(Q_s) for a
+        network with the residual input."""
+        r = self._r(r)
+        stats = self.net.guess_stats(q_s, dq_prev, r=r)
         stats[15:20] = self.alpha * rc_prev
-        x = self.net.features(q_s, dq_prev, stats, self.n_elem)
+        x = self.net.features(q_s, dq_prev, stats, self.n_elem, r=r)
         y = torch.empty(self.n_elem * self.dpe, dtype=torch.float32, device=self.dev)
         mb = self.net.max_batch
-        nx, nt = 2 * self.dpe, self.dpe
+        nx, nt = self.nx, self.dpe
         for s in range(0, self.n_elem, mb):
             b = min(mb, self.n_elem - s)
             self.net.forward(self.w, x[s * nx:(s + b) * nx], b, y[s * nt:(s + b) * nt])

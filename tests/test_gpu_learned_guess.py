@@ -8,7 +8,9 @@ the device residual) and the learned initial guess.
   the library's own kernels and then predicts the increment of later steps;
   every step converges to the same FP64 residual with or without it, and the
   learned guess needs fewer GMRES iterations than the zero guess (the method
-  without it).  The gain over the previous increment is reported, not asserted.
+  without it), with the state and previous increment as inputs and with the
+  step's residual R(Q_s) as a third input.  The gain over the previous
+  increment is reported, not asserted.
 """
 import numpy as np
 import pytest
@@ -62,41 +64,51 @@ def test_learned_guess_beats_zero_guess():
     n_elem, dpe = case.mesh.n_elem, 5 * case.mesh.p ** 3
     st = _stepper(case, newton_tol=1e-8, lin_tol=1e-10)
     lg = LearnedGuess(n_elem, dpe, capacity=16, seed=1, batch=64)
+    lgr = LearnedGuess(n_elem, dpe, capacity=16, seed=1, batch=64, use_residual=True)
+    inv_dt = 1.0 / case.dt
     q = case.q_state.reshape(-1).contiguous()
     dq_prev = torch.zeros_like(q)
     rc_prev = None
     n_train, n_test = 13, 8
     for step in range(n_train):
         st.prepare(q)
+        r_s = st.dg.residual(q, q, inv_dt)
         q1, info = st.solve_step(q)
         assert info["converged"], (step, info)
         dq = q1 - q
         if step > 0:
             lg.record(q, dq_prev, dq)
+            lgr.record(q, dq_prev, dq, r_s)
             rc_prev = lg.correction_rms(q, dq_prev, dq)
         q, dq_prev = q1, dq
     history, hold = lg.train(epochs=150, lr=5e-4, holdout_rows=n_elem)
+    history_r, hold_r = lgr.train(epochs=150, lr=5e-4, holdout_rows=n_elem)
+    print(f"residual-input network: train loss {history_r[0]:.3e} -> {history_r[-1]:.3e} holdout {hold_r:.3e}",
+          flush=True)
+    assert history_r[-1] < 0.5 * history_r[0]
     hold_prev = lg.loss_on(lg.count - n_elem, lg.count, zero=True)
     print(f"train loss first/last {history[0]:.3e} {history[-1]:.3e} holdout {hold:.3e} "
           f"(previous increment {hold_prev:.3e}, alpha {lg.alpha:.3f})", flush=True)
     assert history[-1] < 0.5 * history[0]
     assert hold <= hold_prev * (1 + 1e-9)      # the fitted shrinkage never makes the hold-out worse
-    its = {"zero": [], "previous": [], "learned": []}
+    its = {"zero": [], "previous": [], "learned": [], "learned_r": []}
     rejected = 0
     for step in range(n_test):
         st.prepare(q)
-        guesses = {"zero": None, "previous": dq_prev, "learned": lg.predict(q, dq_prev, rc_prev)}
+        r_s = st.dg.residual(q, q, inv_dt)
+        guesses = {"zero": None, "previous": dq_prev, "learned": lg.predict(q, dq_prev, rc_prev),
+                   "learned_r": lgr.predict(q, dq_prev, rc_prev, r_s)}
         results = {}
         for name, g in guesses.items():
             q1, info = st.solve_step(q, guess=g, mode="gmres")
             assert info["converged"], (name, step, info)
             its[name].append(info["first_gmres"])
             results[name] = q1
-            if name == "learned":
+            if name.startswith("learned"):
                 rejected += info["guess_rejected"]
         # the converged states agree whatever the guess
         scale = float((results["zero"] - q).norm())
-        for name in ("previous", "learned"):
+        for name in ("previous", "learned", "learned_r"):
             assert float((results[name] - results["zero"]).norm()) <= 1e-6 * scale
         dq = results["learned"] - q
         rc_prev = lg.correction_rms(q, dq_prev, dq)
@@ -105,6 +117,8 @@ def test_learned_guess_beats_zero_guess():
     tot = {k: sum(v) for k, v in its.items()}
     print(f"first-solve GMRES iterations over {n_test} steps: {tot}", flush=True)
     assert tot["learned"] < tot["zero"]
+    assert tot["learned_r"] < tot["zero"]
     assert rejected == 0
     lg.close()
+    lgr.close()
     st.close()

@@ -109,20 +109,29 @@ def test_gather_is_exact_and_backward_needs_matching_forward():
 def test_guess_maps_match_oracle():
     n_elem, dpe = 27, 5 * 64
     net = Mlp(2 * dpe, 16, 1, dpe, max_batch=n_elem)
+    net3 = Mlp(3 * dpe, 16, 1, dpe, max_batch=n_elem)    # with the residual block
     rng = np.random.default_rng(8)
     base = np.tile([1.0, 0.1, -0.2, 0.05, 71.9], n_elem * dpe // 5)
     q = base + 1e-2 * rng.standard_normal(n_elem * dpe)
     dq_prev = 1e-4 * rng.standard_normal(n_elem * dpe)
     dq = dq_prev * (1 + 0.01 * rng.standard_normal(n_elem * dpe))
-    qd, dpd, dqd = (torch.tensor(a, device=DEV) for a in (q, dq_prev, dq))
-    stats = net.guess_stats(qd, dpd, dqd)
-    np.testing.assert_allclose(to_np(stats), np.concatenate(om.field_stats(q, dq_prev, dq)), rtol=1e-12, atol=0)
-    s_np = to_np(net.guess_stats(qd, dpd))            # without dq: rc = rp
-    np.testing.assert_array_equal(s_np[15:], s_np[10:15])
+    r = 3.0 * rng.standard_normal(n_elem * dpe)
+    qd, dpd, dqd, rd = (torch.tensor(a, device=DEV) for a in (q, dq_prev, dq, r))
+    stats = net.guess_stats(qd, dpd, dqd, rd)
+    np.testing.assert_allclose(to_np(stats), np.concatenate(om.field_stats(q, dq_prev, dq, r)), rtol=1e-12,
+                               atol=0)
+    s_np = to_np(net.guess_stats(qd, dpd))            # without dq: rc = rp; without r: rr = 1
+    np.testing.assert_array_equal(s_np[15:20], s_np[10:15])
+    np.testing.assert_array_equal(s_np[20:], np.ones(5))
     sv = to_np(stats)
-    so = (sv[:5], sv[5:10], sv[10:15], sv[15:])        # the same statistics on both sides
+    so = (sv[:5], sv[5:10], sv[10:15], sv[15:20], sv[20:])   # the same statistics on both sides
     x = to_np(net.features(qd, dpd, stats, n_elem))
     np.testing.assert_array_equal(x, om.features(q, dq_prev, so, n_elem).astype(np.float32).reshape(-1))
+    x3 = to_np(net3.features(qd, dpd, stats, n_elem, r=rd))
+    np.testing.assert_array_equal(x3, om.features(q, dq_prev, so, n_elem, r).astype(np.float32).reshape(-1))
+    with pytest.raises(ScdgError):
+        net3.features(qd, dpd, stats, n_elem)          # a residual block needs r
+    net3.close()
     t = to_np(net.target(dqd, dpd, stats, n_elem))
     np.testing.assert_array_equal(t, om.target(dq, dq_prev, so, n_elem).astype(np.float32).reshape(-1))
     y = torch.tensor(t, device=DEV)

@@ -85,8 +85,9 @@ def test_field_stats_and_maps_round_trip():
     q = rng.standard_normal(n_elem * dpe) + np.tile([1.0, 0.0, 0.0, 0.0, 100.0], n_elem * dpe // 5)
     dq_prev = 1e-3 * rng.standard_normal(n_elem * dpe)
     dq = dq_prev + 1e-5 * rng.standard_normal(n_elem * dpe)
-    stats = om.field_stats(q, dq_prev, dq)
-    mean, std, rms, rc = stats
+    r = 50.0 * rng.standard_normal(n_elem * dpe)
+    stats = om.field_stats(q, dq_prev, dq, r)
+    mean, std, rms, rc, rr = stats
     qv = q.reshape(-1, 5)
     # two-pass textbook formulas for comparison
     for v in range(5):
@@ -98,19 +99,25 @@ def test_field_stats_and_maps_round_trip():
         assert rms[v] == pytest.approx(math.sqrt(sum(c * c for c in dq_prev.reshape(-1, 5)[:, v]) / len(cv)),
                                        rel=1e-13)
         assert rc[v] == pytest.approx(math.sqrt(sum(c * c for c in cv[:, v]) / len(cv)), rel=1e-13)
+        assert rr[v] == pytest.approx(math.sqrt(sum(c * c for c in r.reshape(-1, 5)[:, v]) / len(cv)), rel=1e-13)
     x = om.features(q, dq_prev, stats, n_elem)
     assert x.shape == (n_elem, 2 * dpe)
     np.testing.assert_allclose(x[1, :5], (q[dpe:dpe + 5] - mean) / std, atol=1e-14)
     np.testing.assert_allclose(x[2, dpe:dpe + 5], dq_prev[2 * dpe:2 * dpe + 5] / rms, atol=1e-14)
+    x3 = om.features(q, dq_prev, stats, n_elem, r)
+    assert x3.shape == (n_elem, 3 * dpe)
+    np.testing.assert_array_equal(x3[:, :2 * dpe], x)
+    np.testing.assert_allclose(x3[1, 2 * dpe:2 * dpe + 5], r[dpe:dpe + 5] / rr, atol=1e-14)
     t = om.target(dq, dq_prev, stats, n_elem)
     np.testing.assert_allclose(t[0, :5], (dq[:5] - dq_prev[:5]) / rc, atol=1e-14)
     np.testing.assert_allclose(om.apply(dq_prev, t, stats, n_elem), dq, rtol=0, atol=1e-17)
     # a constant variable has no spread: std becomes 1
     qc = np.tile([1.0, 2.0, 3.0, 4.0, 5.0], 10)
-    _, std_c, rms_c, rc_c = om.field_stats(qc, np.zeros(50))
+    _, std_c, rms_c, rc_c, rr_c = om.field_stats(qc, np.zeros(50))
     np.testing.assert_array_equal(std_c, np.ones(5))
     np.testing.assert_array_equal(rms_c, np.ones(5))
     np.testing.assert_array_equal(rc_c, np.ones(5))
+    np.testing.assert_array_equal(rr_c, np.ones(5))       # no residual given
 
 
 def test_training_reduces_loss():
