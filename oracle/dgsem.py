@@ -19,7 +19,10 @@ strong (summation-by-parts) rewrite, so a test that compares against a
 strong-form evaluation checks both.
 
 Mesh: K^3 cubes of side h = length / K, periodic; x = x_e + (h/2)(xi + 1),
-so J = (h/2)^3, the face Jacobian is (h/2)^2 and d xi / dx = 2 / h.
+so J = (h/2)^3, the face Jacobian is (h/2)^2 and d xi / dx = 2 / h.  The
+*_curved functions take any periodic mesh of curved hexahedra given by its
+node positions (high-order mapping sampled at the GL nodes): metric terms in
+the conservative curl form, contravariant fluxes, face fluxes along J a^i.
 Arrays have shape [K, K, K, P, P, P, 5] = (ez, ey, ex, k, j, i, v): Cartesian
 direction d (0 = x, 1 = y, 2 = z) runs along element axis 2 - d and node axis
 5 - d.  Flattening gives the DOF order 5 (e P^3 + n) + v with
@@ -261,3 +264,129 @@ def residual(q: np.ndarray, grid: Grid, flow: Flow, q_s: np.ndarray | None = Non
     if q_s is None:
         return h
     return mass(grid)[..., None] * (q - q_s) / dt + h
+
+
+# --------------------------------------------------------------------------
+# Curvilinear elements: high-order mapping x(xi) sampled at the GL nodes and
+# its metric terms.  H keeps the weak form of eq. DGSEMsystem, with the
+# contravariant fluxes F^i = sum_n (J a^i)_n f_n in reference space and the
+# face normal J a^i (its length is the face area element).
+# --------------------------------------------------------------------------
+
+def _d_along(a: np.ndarray, axis: int, dm: np.ndarray) -> np.ndarray:
+    """out[.., l, ..] = sum_a D[l, a] a[.., a, ..] along the given node axis."""
+    out = np.moveaxis(a, axis, -1) @ dm.T
+    return np.moveaxis(out, -1, axis)
+
+
+def metric_terms(xyz: np.ndarray, grid: Grid):
+    """(J a^i)_n in the conservative curl form and J, from node positions.
+
+    xyz [K, K, K, P, P, P, 3].  With X the element's node coordinates and
+    (n, m, l) cyclic, (J a^i)_n = - e_i . curl_xi( X_l grad_xi X_m ), every
+    derivative taken with the GL derivative matrix on the element's nodes
+    (Kopriva 2006).  The discrete divergence sum_i d/dxi_i (J a^i)_n then
+    vanishes identically, which is what keeps a uniform state steady.  J is
+    the determinant of the discrete d x / d xi.  Returns ja [..., 3 (i), 3 (n)]
+    and jac [...].  Each element is shifted to its first node first, which
+    leaves the curl form unchanged (the curl of a discrete gradient is zero)."""
+    x, _ = gl_rule(grid.order)
+    dm = lagrange_derivative(x)
+    X = xyz - xyz[:, :, :, :1, :1, :1, :]
+    # dX[..., j, m] = d X_m / d xi_j   (xi_j runs along node axis 5 - j)
+    dX = np.stack([_d_along(X, 5 - j, dm) for j in range(3)], axis=-2)
+    ja = np.zeros(X.shape[:-1] + (3, 3))
+    for n in range(3):
+        m, l = (n + 1) % 3, (n + 2) % 3
+        v = X[..., l][..., None] * dX[..., :, m]                 # v_j = X_l d X_m / d xi_j
+        for i in range(3):
+            j, k = (i + 1) % 3, (i + 2) % 3
+            curl_i = _d_along(v[..., k], 5 - j, dm) - _d_along(v[..., j], 5 - k, dm)
+            ja[..., i, n] = -curl_i
+    return ja, np.linalg.det(dX)
+
+
+def curved_mass(grid: Grid, jac: np.ndarray) -> np.ndarray:
+    """Diagonal mass J_j w_i w_j w_k per node."""
+    _, w = gl_rule(grid.order)
+    return jac * np.einsum("k,j,i->kji", w, w, w)
+
+
+def lax_friedrichs_normal(q_minus, q_plus, nvec, flow: Flow):
+    """Rusanov flux along the (unnormalized) normal nvec [..., 3], scaled by |nvec|."""
+    s = np.linalg.norm(nvec, axis=-1)
+    nh = nvec / s[..., None]
+    speeds = []
+    for q in (q_minus, q_plus):
+        rho, vel, p, _, _ = primitive(q, flow)
+        speeds.append(np.abs(np.sum(vel * nh, axis=-1)) + np.sqrt(flow.gamma * p / rho))
+    lam = np.maximum(speeds[0], speeds[1])
+    f = sum(nvec[..., d, None] * (euler_flux(q_minus, d, flow) + euler_flux(q_plus, d, flow)) for d in range(3))
+    return 0.5 * f - 0.5 * (lam * s)[..., None] * (q_plus - q_minus)
+
+
+def _face_metric(ja: np.ndarray, i: int, l: int) -> np.ndarray:
+    """(J a^i) at the nodes l of the line along xi_i: [K, K, K, P, P, 3]."""
+    return np.moveaxis(ja[..., i, :], 5 - i, -2)[..., l, :]
+
+
+def lifted_gradient_curved(q: np.ndarray, grid: Grid, ja: np.ndarray, jac: np.ndarray) -> np.ndarray:
+    """BR1 gradient of eq. DGSEMsystem:2 on curved elements:
+    J_j w_j g_{n,j} = sum_i [ - int (J a^i)_n q d(phi_j)/d xi_i + oint phi_j q_hat (J a^i)_n ]."""
+    x, w = gl_rule(grid.order)
+    dm = lagrange_derivative(x)
+    n = grid.order
+    wt = _transverse_weights(w)
+    g = np.zeros(q.shape[:-1] + (3, NVAR))
+    for i in range(3):
+        ql = _line_last(q, i)
+        right = _line_last(_neighbour(q, i, +1), i)[..., 0, :]
+        left = _line_last(_neighbour(q, i, -1), i)[..., n, :]
+        for c in range(3):
+            jl = _line_last(ja[..., i, c][..., None], i)              # [..., P, 1]
+            vol = -np.einsum("a,al,...av->...lv", w, dm, jl * ql) * wt[:, :, None, None]
+            surf = np.zeros_like(vol)
+            surf[..., n, :] += wt[:, :, None] * jl[..., n, :] * 0.5 * (ql[..., n, :] + right)
+            surf[..., 0, :] -= wt[:, :, None] * jl[..., 0, :] * 0.5 * (ql[..., 0, :] + left)
+            g[..., c, :] += _line_back(vol + surf, i)
+    return g / curved_mass(grid, jac)[..., None, None]
+
+
+def operator_h_curved(q: np.ndarray, grid: Grid, flow: Flow, ja: np.ndarray, jac: np.ndarray) -> np.ndarray:
+    """H(Q) on curved elements: per reference direction i, the weak form of
+    eq. DGSEMsystem:1 with F^i = sum_n (J a^i)_n f_n and the face flux along
+    J a^i of the element that owns the +xi_i face."""
+    x, w = gl_rule(grid.order)
+    dm = lagrange_derivative(x)
+    n = grid.order
+    wt = _transverse_weights(w)
+    g = lifted_gradient_curved(q, grid, ja, jac)
+    f = [euler_flux(q, c, flow) - viscous_flux(q, g, c, flow) for c in range(3)]
+    h = np.zeros_like(q)
+    for i in range(3):
+        ft = sum(ja[..., i, c][..., None] * f[c] for c in range(3))
+        fl = _line_last(ft, i)
+        vol = -np.einsum("a,al,...av->...lv", w, dm, fl) * wt[:, :, None, None]
+        q_in = _line_last(q, i)[..., n, :]
+        q_out = _line_last(_neighbour(q, i, +1), i)[..., 0, :]
+        g_in = np.moveaxis(g, 5 - i, -3)[..., n, :, :]
+        g_out = np.moveaxis(_neighbour(g, i, +1), 5 - i, -3)[..., 0, :, :]
+        nvec = _face_metric(ja, i, n)
+        visc = sum(nvec[..., c, None] * (viscous_flux(q_in, g_in, c, flow) + viscous_flux(q_out, g_out, c, flow))
+                   for c in range(3))
+        f_hat = lax_friedrichs_normal(q_in, q_out, nvec, flow) - 0.5 * visc
+        f_hat_left = _neighbour(f_hat, i, -1)
+        surf = np.zeros_like(vol)
+        surf[..., n, :] += wt[:, :, None] * f_hat
+        surf[..., 0, :] -= wt[:, :, None] * f_hat_left
+        h += _line_back(vol + surf, i)
+    return h
+
+
+def residual_curved(q: np.ndarray, grid: Grid, flow: Flow, ja: np.ndarray, jac: np.ndarray,
+                    q_s: np.ndarray | None = None, dt: float | None = None) -> np.ndarray:
+    """R(Q) = M (Q - Q_s) / dt + H(Q) on curved elements; without q_s, H(Q)."""
+    h = operator_h_curved(q, grid, flow, ja, jac)
+    if q_s is None:
+        return h
+    return curved_mass(grid, jac)[..., None] * (q - q_s) / dt + h

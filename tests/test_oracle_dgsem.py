@@ -325,3 +325,115 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(od, "lagrange_derivative", lambda x: good_dm(x).T)
     with pytest.raises(AssertionError):
         test_advected_density_wave_converges()
+
+
+# ---------------------------------------------------------------- curvilinear elements
+# The perturbed map x = xi + A L s(xi) (1, 1, 1), s = sin xi_x sin xi_y sin xi_z
+# (L = 2 pi), has d x / d xi_ref = (h/2) (I + 1 u^T) with u = A L grad s, so
+#   J = (h/2)^3 (1 + sum u),   (J a^i)_n = (h/2)^2 ((1 + sum u) delta_in - u_n).
+
+def _flow_params(reynolds):
+    from workload.physics import FlowParams
+    return FlowParams(mach=0.1, reynolds=reynolds)
+
+
+def _curved(k, order, amplitude=0.05, kind="sine"):
+    from workload.dgsem import Mesh, curved_node_coordinates, node_coordinates
+    mesh = Mesh(k, order)
+    return mesh, curved_node_coordinates(mesh, amplitude, kind), node_coordinates(mesh)
+
+
+def _exact_metrics(xi, h, amplitude):
+    L = 2.0 * math.pi
+    s = [np.sin(xi[..., d]) for d in range(3)]
+    c = [np.cos(xi[..., d]) for d in range(3)]
+    u = amplitude * L * np.stack([c[0] * s[1] * s[2], s[0] * c[1] * s[2], s[0] * s[1] * c[2]], axis=-1)
+    su = u.sum(axis=-1)
+    jac = (h / 2) ** 3 * (1 + su)
+    ja = (h / 2) ** 2 * ((1 + su)[..., None, None] * np.eye(3) - u[..., None, :])
+    return ja, jac
+
+
+def test_curved_affine_map_reduces_to_cartesian():
+    mesh, _, xi = _curved(2, 3)
+    grid, flow = od.Grid(2, 3), od.Flow(0.1, 100.0)
+    ja, jac = od.metric_terms(xi, grid)
+    c = grid.h / 2
+    np.testing.assert_allclose(ja, np.broadcast_to(c * c * np.eye(3), ja.shape), atol=1e-13 * c * c)
+    np.testing.assert_allclose(jac, c ** 3, rtol=1e-13)
+    from workload.dgsem import taylor_green_state
+    q = taylor_green_state(mesh, _flow_params(100.0), seed=3)
+    ref = od.operator_h(q, grid, flow)
+    assert np.abs(od.operator_h_curved(q, grid, flow, ja, jac) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("order", [3, 4, 5, 7])
+def test_curved_metrics_converge_to_the_map(order):
+    _, xc, xi = _curved(3, order)
+    grid = od.Grid(3, order)
+    ja, jac = od.metric_terms(xc, grid)
+    ja_x, jac_x = _exact_metrics(xi, grid.h, 0.05)
+    assert jac.min() > 0
+    # spectral convergence of the interpolated geometry; measured J: 3.6e-2,
+    # 5.6e-3, 6.2e-4, 4.7e-6 and J a: 8.5e-2, 1.7e-2, 3.0e-3, 6.7e-5 (N = 3, 4, 5, 7)
+    bound_j = {3: 5e-2, 4: 8e-3, 5: 1e-3, 7: 1e-5}[order]
+    bound_ja = {3: 0.15, 4: 3e-2, 5: 6e-3, 7: 1.5e-4}[order]
+    assert np.abs(jac - jac_x).max() <= bound_j * np.abs(jac_x).max()
+    assert np.abs(ja - ja_x).max() <= bound_ja * np.abs(ja_x).max()
+
+
+@pytest.mark.parametrize("kind", ["sine", "skew"])
+def test_curved_metric_identities_hold_discretely(kind):
+    _, xc, _ = _curved(3, 5, kind=kind)
+    grid = od.Grid(3, 5)
+    ja, _ = od.metric_terms(xc, grid)
+    x, _ = od.gl_rule(5)
+    dm = od.lagrange_derivative(x)
+    div = sum(od._d_along(ja[..., i, :], 5 - i, dm) for i in range(3))
+    assert np.abs(div).max() <= 1e-12 * np.abs(ja).max()
+    # a rigid shift of the mesh changes nothing
+    ja2, jac2 = od.metric_terms(xc + np.array([0.3, -1.7, 2.9]), grid)
+    np.testing.assert_allclose(ja2, ja, rtol=0, atol=1e-12 * np.abs(ja).max())
+
+
+@pytest.mark.parametrize("k,order,kind", [(2, 3, "sine"), (3, 4, "sine"), (3, 4, "skew")])
+def test_curved_free_stream_is_preserved(k, order, kind):
+    from workload.dgsem import uniform_state
+    mesh, xc, _ = _curved(k, order, kind=kind)
+    grid, flow = od.Grid(k, order), od.Flow(0.1, 100.0)
+    ja, jac = od.metric_terms(xc, grid)
+    q = uniform_state(mesh, _flow_params(100.0))
+    h = od.operator_h_curved(q, grid, flow, ja, jac)
+    p = 1.0 / (1.4 * 0.01)
+    assert np.abs(h).max() <= 1e-12 * p * np.abs(ja).max()
+    g = od.lifted_gradient_curved(q, grid, ja, jac)
+    assert np.abs(g).max() <= 1e-12 * (np.abs(q).max() / grid.h)
+
+
+def test_curved_residual_is_conservative():
+    from workload.dgsem import taylor_green_state
+    mesh, xc, _ = _curved(3, 4)
+    grid, flow = od.Grid(3, 4), od.Flow(0.1, 1600.0)
+    ja, jac = od.metric_terms(xc, grid)
+    q = taylor_green_state(mesh, _flow_params(1600.0), seed=2, coords=xc)
+    h = od.operator_h_curved(q, grid, flow, ja, jac).reshape(-1, 5)
+    assert np.all(np.abs(h.sum(axis=0)) <= 1e-12 * np.abs(h).sum(axis=0))
+
+
+def test_curved_planted_cross_product_metrics_break_the_free_stream(monkeypatch):
+    good = od.metric_terms
+
+    def cross_product(xyz, grid):
+        ja, jac = good(xyz, grid)
+        x, _ = od.gl_rule(grid.order)
+        dm = od.lagrange_derivative(x)
+        dX = np.stack([od._d_along(xyz, 5 - j, dm) for j in range(3)], axis=-2)
+        for i in range(3):
+            ja[..., i, :] = np.cross(dX[..., (i + 1) % 3, :], dX[..., (i + 2) % 3, :])
+        return ja, jac
+
+    monkeypatch.setattr(od, "metric_terms", cross_product)
+    # on the "sine" map the cross products happen to satisfy the identities as
+    # well (they are linear in grad s); the skew map tells the two forms apart
+    with pytest.raises(AssertionError):
+        test_curved_free_stream_is_preserved(3, 4, "skew")

@@ -93,6 +93,30 @@ def node_coordinates(mesh: Mesh) -> np.ndarray:
                      np.broadcast_to(zs, full)], axis=-1)
 
 
+def curved_node_coordinates(mesh: Mesh, amplitude: float = 0.05, kind: str = "sine") -> np.ndarray:
+    """Nodes of a smoothly perturbed periodic mesh, [Kz, Ky, Kx, P, P, P, 3].
+
+    kind "sine": every coordinate of the Cartesian node position xi (in
+    [0, L)^3) is shifted by amplitude * L * sin(t xi_x) sin(t xi_y) sin(t xi_z),
+    t = 2 pi / L (the same shift for x, y and z).  kind "skew": coordinate d is
+    shifted by amplitude * L * sin(t xi_x + a_d) sin(t xi_y + 2 a_d)
+    sin(t xi_z + 3 a_d), a_d = 0.7 (d + 1), a different shift per coordinate.
+    Both shifts are L-periodic, so the mesh stays periodic."""
+    xi = node_coordinates(mesh)
+    t = 2.0 * np.pi / mesh.length
+    if kind == "sine":
+        s = np.sin(t * xi[..., 0]) * np.sin(t * xi[..., 1]) * np.sin(t * xi[..., 2])
+        return xi + (amplitude * mesh.length * s)[..., None]
+    if kind != "skew":
+        raise ValueError(kind)
+    out = xi.copy()
+    for d in range(3):
+        a = 0.7 * (d + 1)
+        out[..., d] += amplitude * mesh.length * (np.sin(t * xi[..., 0] + a) * np.sin(t * xi[..., 1] + 2 * a)
+                                                  * np.sin(t * xi[..., 2] + 3 * a))
+    return out
+
+
 def mass_diagonal(mesh: Mesh) -> np.ndarray:
     """Diagonal of M per node, J w_i w_j w_k, shape [Kz, Ky, Kx, P, P, P]."""
     _, w = gl.gl_nodes_weights(mesh.order)
@@ -101,7 +125,8 @@ def mass_diagonal(mesh: Mesh) -> np.ndarray:
     return np.broadcast_to(m, (k, k, k) + m.shape).copy()
 
 
-def taylor_green_state(mesh: Mesh, prm: FlowParams, seed: int, amplitude: float = 1e-3) -> np.ndarray:
+def taylor_green_state(mesh: Mesh, prm: FlowParams, seed: int, amplitude: float = 1e-3,
+                       coords: np.ndarray | None = None) -> np.ndarray:
     """Taylor-Green-like conserved state with a seeded perturbation.
 
     Velocity in units of the reference speed: u = sin x cos y cos z,
@@ -109,8 +134,9 @@ def taylor_green_state(mesh: Mesh, prm: FlowParams, seed: int, amplitude: float 
     p = 1/(gamma Ma^2) + (cos 2x + cos 2y)(cos 2z + 2)/16.
     Perturbation: rho *= 1 + a xi_1, u_k += a xi_{k+1}, p *= 1 + a xi_5 with
     xi ~ U(-1, 1) i.i.d. per node from numpy's PCG64 seeded generator.
+    coords: the node positions to evaluate at (default: the Cartesian nodes).
     """
-    xyz = node_coordinates(mesh)
+    xyz = node_coordinates(mesh) if coords is None else coords
     x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
     rho = np.ones_like(x)
     u = np.sin(x) * np.cos(y) * np.cos(z)
