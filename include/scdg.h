@@ -273,6 +273,18 @@ scdg_status scdg_dg_destroy(scdg_dg *dg);
  * object's stream. */
 scdg_status scdg_dg_residual(scdg_dg *dg, const double *q, const double *q_s, double inv_dt,
                              double *r);
+/* Curved hexahedra: xyz (host, 3 doubles per node, natural node order, the
+ * physical position of every GL node, i.e. the element mapping sampled at its
+ * nodes) replaces the Cartesian cubes.  The library forms the metric terms in
+ * the conservative curl form, (J a^i)_n = - e_i . curl_xi(X_l grad_xi X_m) for
+ * (n, m, l) cyclic (so a uniform state stays steady), and J = det(dx/dxi); H
+ * then uses the contravariant fluxes sum_n (J a^i)_n f_n, face fluxes along
+ * J a^i and the mass J w_i w_j w_k (the paper's eq. DGSEMsystem on mapped
+ * elements).  The mesh must stay periodic with watertight faces (shared face
+ * nodes at the same positions, up to a period).  xyz == NULL returns to the
+ * Cartesian cubes.  Synchronizes the object's stream; SCDG_ERR_ARG if some J
+ * is not positive and finite (the previous geometry is kept). */
+scdg_status scdg_dg_set_geometry(scdg_dg *dg, const double *xyz);
 /* Copy the lifted gradient of the last scdg_dg_residual call into g (device,
  * 15 doubles per node: g[(e P^3 + n) 15 + 5 d + v] = d q_v / d x_d). */
 scdg_status scdg_dg_gradient(scdg_dg *dg, double *g);

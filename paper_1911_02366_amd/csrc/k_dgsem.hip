@@ -105,6 +105,31 @@ __device__ void face_flux(const double ql[5], const double gl[15], const double 
     fh[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * lam * (qr[v] - ql[v]) - 0.5 * (vl[v] + vr[v]);
 }
 
+// total numerical flux along the unnormalized face normal nv (curved faces):
+// sum_d nv_d {{f^a_d}} - lambda |nv| [[q]] / 2 - sum_d nv_d {{f^nu_d}},
+// lambda the larger of |v . nv| / |nv| + c on the two sides
+__device__ void face_flux_normal(const double ql[5], const double gl[15], const double qr[5],
+                                 const double gr[15], const double nv[3], const DgParams &P, double fh[5]) {
+  const double sn = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+  const double inv = 1.0 / sn;
+  const Prim a = prim(ql, P.gamma), b = prim(qr, P.gamma);
+  const double un_l = (a.u[0] * nv[0] + a.u[1] * nv[1] + a.u[2] * nv[2]) * inv;
+  const double un_r = (b.u[0] * nv[0] + b.u[1] * nv[1] + b.u[2] * nv[2]) * inv;
+  const double lam_l = fabs(un_l) + sqrt(P.gamma * a.p / a.rho);
+  const double lam_r = fabs(un_r) + sqrt(P.gamma * b.p / b.rho);
+  const double lam = lam_l >= lam_r ? lam_l : lam_r;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int d = 0; d < 3; ++d) {
+    double fl[5], fr[5], vl[5], vr[5];
+    flux_adv(ql, d, P.gamma, fl);
+    flux_adv(qr, d, P.gamma, fr);
+    flux_visc(ql, gl, d, P, vl);
+    flux_visc(qr, gr, d, P, vr);
+    for (int v = 0; v < 5; ++v) acc[v] += nv[d] * (0.5 * (fl[v] + fr[v]) - 0.5 * (vl[v] + vr[v]));
+  }
+  for (int v = 0; v < 5; ++v) fh[v] = acc[v] - 0.5 * lam * sn * (qr[v] - ql[v]);
+}
+
 // cooperative copy of the parameter block into LDS (ends with a barrier)
 __device__ __forceinline__ void load_params(const DgParams *__restrict__ src, DgParams *dst) {
   static_assert(sizeof(DgParams) % 4 == 0, "word copy");
@@ -158,6 +183,128 @@ __global__ __launch_bounds__(512) void lift_kernel(const DgParams *__restrict__ 
   }
   double *ge = g + ((int64_t)e * p3 + node) * 15;
   for (int t = 0; t < 15; ++t) ge[t] = P.s * out[t];
+}
+
+// Lifted gradient on curved elements (metric met: 10 doubles per node, (J a^i)_n
+// at 3 i + n and J at 9):
+//   g_n = (1/J) sum_i [ sum_a D[l][a] ((J a^i)_n q)_a
+//                      + (1/w_N) [l = N] (J a^i)_n (q^+ - q) / 2 - (1/w_0) [l = 0] (J a^i)_n (q^- - q) / 2 ]
+__global__ __launch_bounds__(512) void lift_curved_kernel(const DgParams *__restrict__ prm,
+                                                          const double *__restrict__ q,
+                                                          const double *__restrict__ met,
+                                                          double *__restrict__ g) {
+  __shared__ DgParams P;
+  __shared__ double qs[kMaxP * kMaxP * kMaxP * 5];
+  extern __shared__ double ms[];   // [p3][10] metric of the element
+  load_params(prm, &P);
+  const int p = P.p, p3 = p * p * p, n = p - 1;
+  const int e = blockIdx.x;
+  const double *qe = q + (int64_t)e * p3 * 5;
+  const double *me = met + (int64_t)e * p3 * 10;
+  for (int t = threadIdx.x; t < p3 * 5; t += blockDim.x) qs[t] = qe[t];
+  for (int t = threadIdx.x; t < p3 * 10; t += blockDim.x) ms[t] = me[t];
+  __syncthreads();
+  const int node = threadIdx.x;
+  if (node >= p3) return;
+  const int c[3] = {node % p, (node / p) % p, node / (p * p)};
+  double out[15];
+  for (int t = 0; t < 15; ++t) out[t] = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    const int l = c[i];
+    for (int a = 0; a < p; ++a) {
+      const int na = node_with(node, p, i, a);
+      const double dl = P.d[l][a];
+      for (int m = 0; m < 3; ++m) {
+        const double f = dl * ms[na * 10 + 3 * i + m];
+        for (int v = 0; v < 5; ++v) out[m * 5 + v] += f * qs[na * 5 + v];
+      }
+    }
+    if (l == n || l == 0) {
+      const int step = l == n ? 1 : -1;
+      const double *qn = q + ((int64_t)nbr_elem(e, P.k_elem, i, step) * p3 + node_with(node, p, i, l == n ? 0 : n)) * 5;
+      const double sgn = l == n ? 0.5 / P.w[n] : -0.5 / P.w[0];
+      for (int m = 0; m < 3; ++m) {
+        const double f = sgn * ms[node * 10 + 3 * i + m];
+        for (int v = 0; v < 5; ++v) out[m * 5 + v] += f * (qn[v] - qs[node * 5 + v]);
+      }
+    }
+  }
+  const double inv_j = 1.0 / ms[node * 10 + 9];
+  double *ge = g + ((int64_t)e * p3 + node) * 15;
+  for (int t = 0; t < 15; ++t) ge[t] = inv_j * out[t];
+}
+
+// Residual on curved elements: contravariant fluxes F^i = sum_n (J a^i)_n f_n in
+// LDS, the weak volume term and the face fluxes along J a^i of this element's
+// face node, mass J w_i w_j w_k:
+//   H = w_i w_j w_k sum_i (1/w_l) [ sum_a Vw[l][a] F^i(a) + [l = N] Fhat_R - [l = 0] Fhat_L ]
+__global__ __launch_bounds__(512) void residual_curved_kernel(const DgParams *__restrict__ prm,
+                                                              const double *__restrict__ q,
+                                                              const double *__restrict__ g,
+                                                              const double *__restrict__ met,
+                                                              const double *__restrict__ q_s, double inv_dt,
+                                                              double *__restrict__ r) {
+  __shared__ DgParams P;
+  extern __shared__ double fs[];   // [3][p3][5] contravariant fluxes
+  load_params(prm, &P);
+  const int p = P.p, p3 = p * p * p, n = p - 1;
+  const int e = blockIdx.x;
+  const int node = threadIdx.x;
+  const bool live = node < p3;
+  double qn[5], gn[15], mn[10];
+  if (live) {
+    const int64_t id = (int64_t)e * p3 + node;
+    for (int v = 0; v < 5; ++v) qn[v] = q[id * 5 + v];
+    for (int t = 0; t < 15; ++t) gn[t] = g[id * 15 + t];
+    for (int t = 0; t < 10; ++t) mn[t] = met[id * 10 + t];
+    double ft[3][5];
+    for (int i = 0; i < 3; ++i)
+      for (int v = 0; v < 5; ++v) ft[i][v] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      double fa[5], fv[5];
+      flux_adv(qn, d, P.gamma, fa);
+      flux_visc(qn, gn, d, P, fv);
+      for (int i = 0; i < 3; ++i)
+        for (int v = 0; v < 5; ++v) ft[i][v] += mn[3 * i + d] * (fa[v] - fv[v]);
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int v = 0; v < 5; ++v) fs[(i * p3 + node) * 5 + v] = ft[i][v];
+  }
+  __syncthreads();
+  if (!live) return;
+  const int c[3] = {node % p, (node / p) % p, node / (p * p)};
+  double h[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < 3; ++i) {
+    const int l = c[i];
+    double rd[5];
+    for (int v = 0; v < 5; ++v) {
+      double acc = 0.0;
+      for (int a = 0; a < p; ++a) acc += P.vw[l][a] * fs[(i * p3 + node_with(node, p, i, a)) * 5 + v];
+      rd[v] = acc;
+    }
+    const double nv[3] = {mn[3 * i], mn[3 * i + 1], mn[3 * i + 2]};
+    if (l == n) {
+      const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, i, 1) * p3 + node_with(node, p, i, 0);
+      double fh[5];
+      face_flux_normal(qn, gn, q + nb * 5, g + nb * 15, nv, P, fh);
+      for (int v = 0; v < 5; ++v) rd[v] += fh[v];
+    }
+    if (l == 0) {
+      const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, i, -1) * p3 + node_with(node, p, i, n);
+      double fh[5];
+      face_flux_normal(q + nb * 5, g + nb * 15, qn, gn, nv, P, fh);
+      for (int v = 0; v < 5; ++v) rd[v] -= fh[v];
+    }
+    for (int v = 0; v < 5; ++v) h[v] += rd[v] / P.w[l];
+  }
+  const double w3 = P.w[c[0]] * P.w[c[1]] * P.w[c[2]];
+  const double m = mn[9] * w3;
+  double *re = r + ((int64_t)e * p3 + node) * 5;
+  for (int v = 0; v < 5; ++v) {
+    double val = w3 * h[v];
+    if (q_s) val += m * inv_dt * (qn[v] - q_s[((int64_t)e * p3 + node) * 5 + v]);
+    re[v] = val;
+  }
 }
 
 __global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restrict__ prm, const double *__restrict__ q,
@@ -276,10 +423,63 @@ void gl_operators(int nord, double *x, double *w, double d[kMaxP][kMaxP]) {
 
 }  // namespace
 
+// Metric terms of curved elements from the node positions xyz (3 doubles per
+// node, natural node order), on the host: with X the element's coordinates
+// relative to its first node, dX[j][m] = d X_m / d xi_j by the GL derivative
+// matrix, and for (n, m, l) cyclic
+//   (J a^i)_n = - e_i . curl_xi( X_l grad_xi X_m ),
+// the conservative curl form, whose discrete divergence vanishes identically;
+// J = det(dX).  out: 10 doubles per node, (J a^i)_n at 3 i + n, J at 9.
+// Returns false if some J is not positive and finite.
+bool curved_metrics(const DgParams &P, int64_t n_elem, const double *xyz, std::vector<double> &out) {
+  const int p = P.p, p3 = p * p * p;
+  out.assign((size_t)n_elem * p3 * 10, 0.0);
+  std::vector<double> X((size_t)p3 * 3), dX((size_t)p3 * 9), V((size_t)p3 * 3);
+  auto with = [&](int node, int d, int l) {
+    int c[3] = {node % p, (node / p) % p, node / (p * p)};
+    c[d] = l;
+    return c[0] + p * c[1] + p * p * c[2];
+  };
+  auto deriv = [&](const std::vector<double> &f, int stride, int comp, int node, int d) {
+    const int l = d == 0 ? node % p : d == 1 ? (node / p) % p : node / (p * p);
+    double acc = 0.0;
+    for (int a = 0; a < p; ++a) acc += P.d[l][a] * f[(size_t)with(node, d, a) * stride + comp];
+    return acc;
+  };
+  for (int64_t e = 0; e < n_elem; ++e) {
+    const double *xe = xyz + (size_t)e * p3 * 3;
+    for (int t = 0; t < p3; ++t)
+      for (int m = 0; m < 3; ++m) X[(size_t)t * 3 + m] = xe[t * 3 + m] - xe[m];
+    for (int t = 0; t < p3; ++t)
+      for (int j = 0; j < 3; ++j)
+        for (int m = 0; m < 3; ++m) dX[(size_t)t * 9 + 3 * j + m] = deriv(X, 3, m, t, j);
+    double *oe = out.data() + (size_t)e * p3 * 10;
+    for (int nn = 0; nn < 3; ++nn) {
+      const int m = (nn + 1) % 3, l = (nn + 2) % 3;
+      for (int t = 0; t < p3; ++t)
+        for (int j = 0; j < 3; ++j) V[(size_t)t * 3 + j] = X[(size_t)t * 3 + l] * dX[(size_t)t * 9 + 3 * j + m];
+      for (int t = 0; t < p3; ++t)
+        for (int i = 0; i < 3; ++i) {
+          const int j = (i + 1) % 3, k = (i + 2) % 3;
+          oe[(size_t)t * 10 + 3 * i + nn] = -(deriv(V, 3, k, t, j) - deriv(V, 3, j, t, k));
+        }
+    }
+    for (int t = 0; t < p3; ++t) {
+      const double *a = dX.data() + (size_t)t * 9;
+      const double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                         a[2] * (a[3] * a[7] - a[4] * a[6]);
+      if (!(det > 0.0) || !std::isfinite(det)) return false;
+      oe[(size_t)t * 10 + 9] = det;
+    }
+  }
+  return true;
+}
+
 struct DgContext {
   DgParams host;
   DgParams *dev = nullptr;
   double *g = nullptr;
+  double *met = nullptr;   // curved elements: 10 doubles per node (NULL: Cartesian cubes)
   int64_t n_nodes = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
@@ -301,6 +501,13 @@ hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, doubl
   const int p3 = c.host.p * c.host.p * c.host.p;
   const int n_elem = c.host.k_elem * c.host.k_elem * c.host.k_elem;
   const int threads = ((p3 + 63) / 64) * 64;
+  if (c.met) {
+    hipLaunchKernelGGL(lift_curved_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 10 * p3, s, c.dev, q,
+                       c.met, c.g);
+    hipLaunchKernelGGL(residual_curved_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev,
+                       q, c.g, c.met, q_s, inv_dt, r);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g);
   hipLaunchKernelGGL(residual_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
                      c.g, q_s, inv_dt, r);
@@ -354,6 +561,7 @@ scdg_status scdg_dg_destroy(scdg_dg *dg) {
   (void)hipStreamSynchronize(dg->c.stream);
   if (dg->c.dev) (void)hipFree(dg->c.dev);
   if (dg->c.g) (void)hipFree(dg->c.g);
+  if (dg->c.met) (void)hipFree(dg->c.met);
   delete dg;
   return SCDG_OK;
 }
@@ -362,6 +570,30 @@ scdg_status scdg_dg_residual(scdg_dg *dg, const double *q, const double *q_s, do
                              double *r) {
   if (!dg || !q || !r) return SCDG_ERR_ARG;
   return scdg::dg_residual_on(dg, q, q_s, inv_dt, r, dg->c.stream) == hipSuccess ? SCDG_OK : SCDG_ERR_HIP;
+}
+
+scdg_status scdg_dg_set_geometry(scdg_dg *dg, const double *xyz) {
+  if (!dg) return SCDG_ERR_ARG;
+  auto &c = dg->c;
+  if (hipStreamSynchronize(c.stream) != hipSuccess) return SCDG_ERR_HIP;
+  if (!xyz) {
+    if (c.met) (void)hipFree(c.met);
+    c.met = nullptr;
+    return SCDG_OK;
+  }
+  const int64_t n_elem = (int64_t)c.host.k_elem * c.host.k_elem * c.host.k_elem;
+  std::vector<double> met;
+  if (!scdg::curved_metrics(c.host, n_elem, xyz, met)) {
+    c.last_error = "node positions give a non-positive or non-finite Jacobian";
+    return SCDG_ERR_ARG;
+  }
+  if (!c.met && hipMalloc(&c.met, sizeof(double) * met.size()) != hipSuccess) {
+    c.met = nullptr;
+    return SCDG_ERR_NOMEM;
+  }
+  if (hipMemcpy(c.met, met.data(), sizeof(double) * met.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return SCDG_ERR_HIP;
+  return SCDG_OK;
 }
 
 scdg_status scdg_dg_gradient(scdg_dg *dg, double *g_out) {

@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes as C
 import math
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -47,6 +48,19 @@ class DgResidual:
         if st != L.SCDG_OK:
             raise L.ScdgError(st, "scdg_dg_residual")
         return out
+
+    def set_geometry(self, xyz=None):
+        """Curved elements from the node positions (numpy, 3 per node in the natural
+        node order, e.g. [K, K, K, P, P, P, 3]); None returns to Cartesian cubes."""
+        if xyz is None:
+            st = self.lib.scdg_dg_set_geometry(self.handle, None)
+        else:
+            arr = np.ascontiguousarray(xyz, dtype=np.float64)
+            if arr.size != 3 * (self.n_dof // 5):
+                raise ValueError(f"xyz: expected {3 * (self.n_dof // 5)} values")
+            st = self.lib.scdg_dg_set_geometry(self.handle, arr.ctypes.data)
+        if st != L.SCDG_OK:
+            raise L.ScdgError(st, "scdg_dg_set_geometry")
 
     def gradient(self, out: torch.Tensor | None = None) -> torch.Tensor:
         n_nodes = self.n_dof // 5

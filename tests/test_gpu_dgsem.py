@@ -125,3 +125,70 @@ def test_newton_step_with_device_residual():
     assert float(r1.norm()) < 1e-3 * float(b.norm())
     plan.close()
     dg.close()
+
+
+# ---------------------------------------------------------------- curved elements
+# The library forms its own metric terms from the node positions (the oracle
+# forms its own); same tolerance as above.  Both periodic maps of the generator:
+# "sine" (the same shift of all three coordinates) and "skew" (a different
+# shift per coordinate, where only the conservative curl form of the metric
+# terms keeps a uniform state steady).
+
+CURVED = [(2, 3, 100.0, 0.1, 1, "sine"), (3, 4, 1600.0, 0.1, 2, "sine"), (2, 5, 400.0, 0.2, 3, "skew"),
+          (3, 4, 1600.0, 0.1, 4, "skew"), (2, 7, 1600.0, 0.1, 5, "skew")]
+
+
+def _curved_inputs(k, n, re, mach, seed, kind, dt=0.25):
+    mesh = wd.Mesh(k, n)
+    xyz = wd.curved_node_coordinates(mesh, 0.05, kind)
+    q = wd.taylor_green_state(mesh, FlowParams(mach, re), seed, coords=xyz)
+    rng = np.random.default_rng(seed + 100)
+    q_s = q * (1.0 + 1e-3 * rng.uniform(-1, 1, q.shape))
+    return xyz, q, q_s, dt
+
+
+@pytest.mark.parametrize("k,n,re,mach,seed,kind", CURVED)
+def test_curved_residual_and_gradient_match_oracle(k, n, re, mach, seed, kind):
+    print(f"dg residual curved {kind} K={k} N={n} Re={re} Ma={mach} seed={seed}", flush=True)
+    xyz, q, q_s, dt = _curved_inputs(k, n, re, mach, seed, kind)
+    grid, flow = od.Grid(k, n), od.Flow(mach, re)
+    ja, jac = od.metric_terms(xyz, grid)
+    want_r = od.residual_curved(q, grid, flow, ja, jac, q_s, dt)
+    want_g = od.lifted_gradient_curved(q, grid, ja, jac)
+    dg = DgResidual(k, n, mach=mach, reynolds=re)
+    dg.set_geometry(xyz)
+    qd = torch.tensor(q.reshape(-1), device=DEV)
+    qsd = torch.tensor(q_s.reshape(-1), device=DEV)
+    r = dg.residual(qd, qsd, 1.0 / dt)
+    g = dg.gradient()
+    torch.cuda.synchronize()
+    assert _max_rel(to_np(g), want_g) <= RTOL
+    assert _max_rel(to_np(r), want_r) <= RTOL
+    h = dg.residual(qd)
+    assert _max_rel(to_np(h), od.operator_h_curved(q, grid, flow, ja, jac)) <= RTOL
+    dg.close()
+
+
+def test_curved_free_stream_and_back_to_cartesian():
+    k, n, re, mach = 3, 4, 1600.0, 0.1
+    mesh = wd.Mesh(k, n)
+    prm = FlowParams(mach, re)
+    dg = DgResidual(k, n, mach=mach, reynolds=re)
+    dg.set_geometry(wd.curved_node_coordinates(mesh, 0.05, "skew"))
+    qu = torch.tensor(wd.uniform_state(mesh, prm).reshape(-1), device=DEV)
+    h = to_np(dg.residual(qu))
+    assert np.abs(h).max() <= 1e-12 * (1.0 / (1.4 * mach ** 2)) * 2.0      # |J a| <= about 2 here
+    # NULL geometry: the Cartesian cubes again, bit for bit
+    q = torch.tensor(wd.taylor_green_state(mesh, prm, 7).reshape(-1), device=DEV)
+    dg.set_geometry(None)
+    got = to_np(dg.residual(q))
+    ref = DgResidual(k, n, mach=mach, reynolds=re)
+    np.testing.assert_array_equal(got, to_np(ref.residual(q)))
+    # a folded mesh (negative Jacobian) is refused and the geometry kept
+    xyz = wd.node_coordinates(mesh).copy()
+    xyz[..., 0] = -xyz[..., 0]
+    with pytest.raises(ScdgError):
+        dg.set_geometry(xyz)
+    np.testing.assert_array_equal(to_np(dg.residual(q)), got)
+    ref.close()
+    dg.close()
