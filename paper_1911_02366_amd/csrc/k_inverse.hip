@@ -56,6 +56,10 @@ template <typename T, int NB, bool PERM>
 using GjWide = GjLayout<T, NB, NB + (sizeof(T) == 8 ? 2 : 4), 64, PERM>;
 template <typename T, int NB, bool PERM>
 using GjCompact = GjLayout<T, NB, NB + 1, 32, PERM>;
+// 24 columns with 32-column update chunks: the widest FP64 panel with which
+// two n_i = 320 workgroups share a CU (79 KB of LDS each)
+template <typename T, bool PERM>
+using GjWide24 = GjLayout<T, 24, 26, 32, PERM>;
 
 // Shared memory of one element's workgroup: the panel (all rows x NB columns),
 // a chunk of the panel's pivot rows, the parked pivot rows, pivot bookkeeping.
@@ -483,6 +487,8 @@ hipError_t gj_dispatch(Plan &p, T *work, T *out) {
   // fewer passes over the block), else the widest that fits at all
   const int n = p.max_ni;
   if (GjWide<T, 32, true>::lds_bytes(n) <= kLdsLimit / 2) return gj_launch<GjWide<T, 32, true>>(p, work, out);
+  if (sizeof(T) == 8 && GjWide24<T, true>::lds_bytes(n) <= kLdsLimit / 2)
+    return gj_launch<GjWide24<T, true>>(p, work, out);
   if (GjWide<T, 16, true>::lds_bytes(n) <= kLdsLimit / 2) return gj_launch<GjWide<T, 16, true>>(p, work, out);
   if (GjWide<T, 32, true>::lds_bytes(n) <= kLdsLimit) return gj_launch<GjWide<T, 32, true>>(p, work, out);
   if (GjWide<T, 16, true>::lds_bytes(n) <= kLdsLimit) return gj_launch<GjWide<T, 16, true>>(p, work, out);
