@@ -28,6 +28,11 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
 
 
+def progress(msg: str) -> None:
+    """A progress line on stderr (never inside a timed region)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_work(case, plan_prec: str, n_rem: int) -> dict:
     """Algorithmic flops / bytes per launch of each kernel (unpadded element blocks).
 
@@ -442,8 +447,12 @@ def main() -> int:
 
         plan.factor(precision)
         tuning = plan.autotune(cache=args.autotune_cache)
-        for _ in range(warmup):
+        progress(f"{precision}: tiles x {tuning['x']} s {tuning['s']}"
+                 f"{' (from cache)' if tuning['cached'] else ''}")
+        for i in range(warmup):
             step()
+            torch.cuda.synchronize()
+            progress(f"{precision}: warm-up step {i + 1} of {warmup}")
         torch.cuda.synchronize()
         plan.enable_timing(True)
         plan.phase_times()
@@ -454,6 +463,7 @@ def main() -> int:
             infos.append(step())
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        progress(f"{precision}: {steps} timed steps, {(t1 - t0) / steps * 1e3:.2f} ms each")
         phases = plan.phase_times()
         plan.enable_timing(False)
         return (t1 - t0) / steps * 1e3, infos, phases, tuning, opts
