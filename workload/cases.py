@@ -22,7 +22,8 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from .dgsem import Mesh, mass_diagonal, residual, taylor_green_state, uniform_state
+from .curved import CurvedGeometry, CurvedJacobianParts, operator_h
+from .dgsem import Mesh, curved_node_coordinates, mass_diagonal, residual, taylor_green_state, uniform_state
 from .jacobian import JacobianParts
 from .partition import partition
 from .physics import FlowParams
@@ -57,6 +58,7 @@ class Case:
     n_bnodes: int
     q_state: torch.Tensor | None = None
     parts: JacobianParts | None = field(default=None, repr=False)
+    xyz: np.ndarray | None = None  # node positions [K, K, K, P, P, P, 3] of a curved mesh
 
     @property
     def n_elem(self) -> int:
@@ -83,7 +85,7 @@ class Case:
         return Case(self.mesh, self.prm, self.dt, self.seed, self.order, self.c_ptr, self.c_node,
                     self.bb_rowptr, self.bb_col, mv(self.bb_val), mv(self.aii), mv(self.aib),
                     mv(self.abi), mv(self.rhs), self.mass, self.n_i, self.n_c, self.n_bnodes,
-                    mv(self.q_state), None)
+                    mv(self.q_state), None, self.xyz)
 
 
 def build_case(k_elem: int, order: int, reynolds: float, dt: float, mach: float = 0.1,
@@ -128,6 +130,47 @@ def jacobian_blocks(q: torch.Tensor, mesh: Mesh, prm: FlowParams, dt: float, chu
         per_elem = (mesh.p ** 3 * 5) ** 2 * 8
         chunk = max(1, min(mesh.n_elem, int(2e9 // per_elem)))
     blk = partition(parts, chunk=chunk)
+    return dict(aii=blk["aii"], aib=blk["aib"], abi=blk["abi"], bb_val=blk["bb_val"])
+
+
+def _chunk(mesh: Mesh) -> int:
+    per_elem = (mesh.p ** 3 * 5) ** 2 * 8
+    return max(1, min(mesh.n_elem, int(2e9 // per_elem)))
+
+
+def build_curved_case(k_elem: int, order: int, reynolds: float, dt: float, mach: float = 0.1,
+                      seed: int = 0, device="cpu", amplitude: float = 0.05, kind: str = "sine") -> Case:
+    """The same system on the periodic perturbed mesh of curved_node_coordinates
+    (kind "sine" or "skew"): the Taylor-Green state evaluated at the curved
+    nodes, A = M/dt + dH/dQ(Q_s) with the curved H and mass J w_i w_j w_k,
+    B = -H(Q_s).  The node positions are kept in case.xyz."""
+    if k_elem < 2:
+        raise ValueError("need at least 2 elements per direction")
+    if order < 2:
+        raise ValueError("static condensation needs interior nodes: N >= 2")
+    mesh = Mesh(k_elem, order)
+    prm = FlowParams(mach=mach, reynolds=reynolds)
+    xyz = curved_node_coordinates(mesh, amplitude, kind)
+    q = torch.tensor(taylor_green_state(mesh, prm, seed, coords=xyz), dtype=torch.float64, device=device)
+    geo = CurvedGeometry(mesh, xyz, device=device)
+    h = operator_h(q, geo, prm)
+    blk = partition(CurvedJacobianParts(q, geo, prm, dt), chunk=_chunk(mesh))
+    return Case(mesh=mesh, prm=prm, dt=dt, seed=seed,
+                order=np.full(mesh.n_elem, order, dtype=np.int32),
+                c_ptr=blk["c_ptr"], c_node=blk["c_node"],
+                bb_rowptr=blk["bb_rowptr"], bb_col=blk["bb_col"], bb_val=blk["bb_val"],
+                aii=blk["aii"], aib=blk["aib"], abi=blk["abi"],
+                rhs=(-h).reshape(-1).contiguous(),
+                mass=geo.mass.reshape(-1).cpu().numpy(),
+                n_i=blk["n_i"], n_c=blk["n_c"], n_bnodes=blk["n_bnodes"],
+                q_state=q, xyz=xyz)
+
+
+def curved_jacobian_blocks(q: torch.Tensor, geo: CurvedGeometry, prm: FlowParams, dt: float) -> dict:
+    """Backward-Euler Jacobian on a curved mesh at state q (natural DOF order or
+    mesh layout, on geo's device) as per-element blocks: aii, aib, abi, bb_val."""
+    q = q.reshape(geo.mesh.shape()).to(geo.jac.device)
+    blk = partition(CurvedJacobianParts(q, geo, prm, dt), chunk=_chunk(geo.mesh))
     return dict(aii=blk["aii"], aib=blk["aib"], abi=blk["abi"], bb_val=blk["bb_val"])
 
 

@@ -69,9 +69,10 @@ def viscosity(t: torch.Tensor, prm: FlowParams) -> torch.Tensor:
     return (1.0 + prm.suth) / (t + prm.suth) * t * torch.sqrt(t)
 
 
-def flux_visc(q: torch.Tensor, g: tuple[torch.Tensor, torch.Tensor, torch.Tensor],
-              d: int, prm: FlowParams) -> torch.Tensor:
-    """Viscous flux f^nu_d(q, grad q); g[k] holds d q / d x_k (conserved variables)."""
+def viscous_stress(q: torch.Tensor, g: tuple[torch.Tensor, torch.Tensor, torch.Tensor], prm: FlowParams):
+    """Velocities, the viscous stress tensor tau[i][k] and the heat flux
+    (mu gamma / Pr) de/dx_k at every node; g[k] holds d q / d x_k (conserved
+    variables).  Shared by the viscous fluxes of all three directions."""
     rho, u, v, w, p = primitives(q, prm)
     vel = (u, v, w)
     temp = prm.gamma * prm.mach ** 2 * p / rho
@@ -83,18 +84,32 @@ def flux_visc(q: torch.Tensor, g: tuple[torch.Tensor, torch.Tensor, torch.Tensor
     de = [(g[k][..., 4] - ee * g[k][..., 0]) / rho
           - (vel[0] * dv[0][k] + vel[1] * dv[1][k] + vel[2] * dv[2][k]) for k in range(3)]
     div = dv[0][0] + dv[1][1] + dv[2][2]
-    tau_d = []
-    for i in range(3):
-        t = mu * (dv[i][d] + dv[d][i])
-        if i == d:
-            t = t - (2.0 / 3.0) * mu * div
-        tau_d.append(t)
-    heat = mu * prm.gamma / prm.prandtl * de[d]
-    energy = vel[0] * tau_d[0] + vel[1] * tau_d[1] + vel[2] * tau_d[2] + heat
+    tau = [[None] * 3 for _ in range(3)]
+    for d in range(3):
+        for i in range(3):
+            t = mu * (dv[i][d] + dv[d][i])
+            if i == d:
+                t = t - (2.0 / 3.0) * mu * div
+            tau[i][d] = t
+    heat = [mu * prm.gamma / prm.prandtl * de[d] for d in range(3)]
+    return vel, tau, heat, rho
+
+
+def viscous_flux_of(stress, d: int, prm: FlowParams) -> torch.Tensor:
+    """f^nu_d from the output of viscous_stress."""
+    vel, tau, heat, rho = stress
+    tau_d = [tau[i][d] for i in range(3)]
+    energy = vel[0] * tau_d[0] + vel[1] * tau_d[1] + vel[2] * tau_d[2] + heat[d]
     inv_re = 1.0 / prm.reynolds
     zero = torch.zeros_like(rho)
     return torch.stack([zero, tau_d[0] * inv_re, tau_d[1] * inv_re, tau_d[2] * inv_re,
                         energy * inv_re], dim=-1)
+
+
+def flux_visc(q: torch.Tensor, g: tuple[torch.Tensor, torch.Tensor, torch.Tensor],
+              d: int, prm: FlowParams) -> torch.Tensor:
+    """Viscous flux f^nu_d(q, grad q); g[k] holds d q / d x_k (conserved variables)."""
+    return viscous_flux_of(viscous_stress(q, g, prm), d, prm)
 
 
 def wave_speed(q: torch.Tensor, d: int, prm: FlowParams) -> torch.Tensor:
