@@ -12,7 +12,9 @@ solve is taken only to the relative tolerance that target needs
 (0.5 newton_tol ||R(Q_s)|| / ||R(Q~)||, clipped to [lin_tol, 0.1]), an
 inexact-Newton choice in the spirit of Eisenstat and Walker.  The Jacobian
 itself comes from a caller-supplied function of the state, returning device
-blocks in the layout of scdg_assemble.
+blocks in the layout of scdg_assemble.  Given node positions `xyz`, the
+residual runs on curved hexahedra (metric terms and the mass J w_i w_j w_k);
+the condensed solve is the same, since it takes the Jacobian blocks as given.
 
 The learned guess (an addition; the paper has no learned component) is a
 per-element network trained on the solver's own (state, previous increment,
@@ -42,9 +44,11 @@ class ImplicitStepper:
                  jacobian, lin_tol: float = 1e-10, newton_tol: float = 1e-8, max_newton: int = 10,
                  restart: int = 30, precond: int = 1, precision: str = "fp64", autotune: bool = True,
                  forcing: bool = True, fp32_inner_tol: float = 1e-4, graph: bool = False,
-                 graph_cycles: int = 8, autotune_cache: str | None = None):
+                 graph_cycles: int = 8, autotune_cache: str | None = None, xyz=None):
         self.plan = Plan.from_structure(structure)
         self.dg = DgResidual(k_elem, order, mach=mach, reynolds=reynolds)
+        if xyz is not None:
+            self.dg.set_geometry(xyz)            # curved hexahedra: the residual takes the metric terms
         self.dt, self.jacobian = dt, jacobian
         self.lin_tol, self.newton_tol, self.max_newton = lin_tol, newton_tol, max_newton
         self.restart, self.precond, self.precision = restart, precond, precision
