@@ -357,6 +357,7 @@ def main() -> int:
     ap.add_argument("--workload", default="tgv_n5_k8")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--restart", type=int, default=30, help="GMRES restart length (1..63)")
     ap.add_argument("--precond", type=int, default=1, choices=[0, 1, 2],
                     help="GMRES right preconditioner: 0 none, 1 point Jacobi, 2 5x5 node-block Jacobi")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -437,7 +438,7 @@ def main() -> int:
     dq = torch.empty(case.n_dof, dtype=torch.float64, device=dev)
 
     def measure(precision, tol, steps, warmup):
-        opts = dict(solver="gmres", restart=30, tol=tol, ir_tol=1e-8, ir_max=10, precond=args.precond)
+        opts = dict(solver="gmres", restart=args.restart, tol=tol, ir_tol=1e-8, ir_max=10, precond=args.precond)
 
         def step():
             plan.factor(precision)
@@ -527,7 +528,7 @@ def main() -> int:
         "config": {"workload": args.workload, "elements": case.n_elem, "order": cfg["order"],
                    "dofs": case.n_dof, "n1_condensed": case.n1, "n2_interior": case.n2,
                    "reynolds": cfg["reynolds"], "mach": 0.1 if cfg["reynolds"] else None, "dt": cfg["dt"],
-                   "solver": "gmres(30)+" + ["none", "point-jacobi", "block-jacobi-5x5"][args.precond],
+                   "solver": f"gmres({args.restart})+" + ["none", "point-jacobi", "block-jacobi-5x5"][args.precond],
                    "gmres_tol": opts["tol"],
                    "precision": args.precision},
         "roofline": entries[dominant],
