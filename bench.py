@@ -81,35 +81,66 @@ def roofline_entry(name, work, phase, prec):
 
 
 def cpu_baseline(max_seconds: float) -> dict:
-    """The FP64 oracle (uncondensed brute force: assemble A, LAPACK dense LU) on a
-    bounded sample: the 2^3-element instance of the same order-5 workload."""
+    """The FP64 oracle on a bounded sample, the 2^3-element instance of the same
+    order-5 workload: the uncondensed brute force (assemble A, LAPACK dense LU)
+    gives `value`; the oracle's condensed route (dense A_ii solves, dense S, LU
+    of S, back-substitution) and both routes on one core are reported beside it
+    (`legs`, DOF/s)."""
     import numpy as np
     import oracle
+    from oracle import linalg as ol
     from workload.cases import build_case
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = len(os.sched_getaffinity(0))
     case = build_case(2, 5, 1600.0, 5e-3, seed=0)
     t = lambda x: x.cpu().numpy()
     args = (case.order, case.c_ptr, case.c_node, case.bb_rowptr, case.bb_col, t(case.bb_val),
             t(case.aii), t(case.aib), t(case.abi))
     b = t(case.rhs)
-    solves, t0 = 0, time.perf_counter()
-    while True:
+
+    def uncondensed():
         a = oracle.assemble_global(*args)
-        x = oracle.solve_dense(a, b)
-        solves += 1
-        el = time.perf_counter() - t0
-        if el >= max_seconds or solves >= 20:
-            break
+        return a, oracle.solve_dense(a, b)
+
+    def condensed():
+        return None, ol.condensed_solve_dense(*args, b)
+
+    def run(fn, seconds, limit=20):
+        solves, t0 = 0, time.perf_counter()
+        while True:
+            a, x = fn()
+            solves += 1
+            el = time.perf_counter() - t0
+            if el >= seconds or solves >= limit:
+                return a, x, solves, el
+
+    a, x, solves, el = run(uncondensed, max_seconds)
     rel = float(np.linalg.norm(b - a @ x) / np.linalg.norm(b))
-    return {"value": round(case.n_dof * solves / el, 2), "unit": "DOF/s", "cores": int(threads),
+    legs = {f"uncondensed_{threads}_cores": round(case.n_dof * solves / el, 2)}
+    _, xc, n_c, el_c = run(condensed, max_seconds / 3)
+    legs[f"condensed_{threads}_cores"] = round(case.n_dof * n_c / el_c, 2)
+    rel_c = float(np.linalg.norm(b - a @ xc) / np.linalg.norm(b))
+    if threadpool_limits is not None:
+        with threadpool_limits(1):
+            for name, fn in (("uncondensed_1_core", uncondensed), ("condensed_1_core", condensed)):
+                _, _, n1, el1 = run(fn, max_seconds / 3, limit=1)
+                legs[name] = round(case.n_dof * n1 / el1, 2)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": legs[f"uncondensed_{threads}_cores"], "unit": "DOF/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"oracle assemble + LAPACK dense LU solve of the 2^3-element order-5 instance "
                       f"of the same workload ({case.n_dof} DOFs), {solves} solves in {el:.1f} s, "
-                      f"residual {rel:.1e}"}
+                      f"residual {rel:.1e}; condensed route residual {rel_c:.1e}",
+            "legs": legs, "cpu_model": model}
 
 
 def learned_guess_experiment(args) -> dict:
@@ -362,6 +393,7 @@ def main() -> int:
                     help="GMRES right preconditioner: 0 none, 1 point Jacobi, 2 5x5 node-block Jacobi")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true", help="skip the measured MFMA / HBM ceilings")
     ap.add_argument("--fp32-inner-tol", type=float, default=1e-4,
                     help="GMRES tolerance inside each refinement sweep of the FP32 variant")
     ap.add_argument("--fp32-sweep", type=float, nargs="*", default=[],
@@ -511,6 +543,27 @@ def main() -> int:
                            [os.path.join(csrc, f) for f in srcs])
         if entries.get(k) is not None and rec is not None:
             entries[k]["traffic"] = rec["traffic_bytes_per_launch"]
+    measured = None
+    if not args.no_probe:
+        # measured ceilings beside the vendor peaks (context; `frac` stays against the vendor figure)
+        from paper_1911_02366_amd import probe
+        measured = {"fp64_mfma_tflops": round(probe.mfma_tflops("fp64"), 2),
+                    "fp32_mfma_tflops": round(probe.mfma_tflops("fp32"), 2),
+                    "hbm_read_gbs": round(probe.hbm_read_gbs(4 << 30), 1),
+                    "how": "scdg_probe_mfma: back-to-back 16x16x4 MFMAs on register operands, "
+                           "8 workgroups of 4 waves per CU; scdg_probe_hbm_read: 16-byte nontemporal "
+                           "streaming read of a 4 GiB buffer; best of 3 / 5 launches"}
+        progress(f"measured ceilings: {measured['fp64_mfma_tflops']} TF/s FP64 MFMA, "
+                 f"{measured['fp32_mfma_tflops']} TF/s FP32 MFMA, {measured['hbm_read_gbs']} GB/s read")
+        for e in entries.values():
+            if e is None:
+                continue
+            if e["bound"] == "mfma":
+                m = measured["fp64_mfma_tflops" if args.precision == "fp64" else "fp32_mfma_tflops"]
+            else:
+                m = measured["hbm_read_gbs"]
+            e["peak_measured"] = m
+            e["frac_of_measured"] = round(e["achieved"] / m, 4)
     worst = max(i["rel_res_full"] for i in infos)
     out = {
         "metric": "condensed implicit-step DOF/s at 1e-8 residual",
@@ -533,6 +586,7 @@ def main() -> int:
                    "precision": args.precision},
         "roofline": entries[dominant],
         "roofline_all": entries,
+        "measured_peaks": measured,
         "phase_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in phases.items()},
         "rel_res_full_max": worst,
         "variants": variants,

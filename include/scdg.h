@@ -428,6 +428,25 @@ scdg_status scdg_guess_target(scdg_mlp *m, const double *dq, const double *dq_pr
 scdg_status scdg_guess_apply(scdg_mlp *m, const double *dq_prev, const float *y, const double *stats,
                              int32_t n_elem, double *dq);
 
+/* ---- Measured ceilings (measurement utilities, no part of the solve) ----
+ * The rooflines of the contraction and streaming kernels are quoted against
+ * the vendor peaks; these probes measure what a kernel reaches on the part at
+ * hand, for context beside them.  Both run on hip_stream (NULL: the null
+ * stream), allocate and free their own device buffers, and synchronize.
+ *
+ * scdg_probe_mfma: back-to-back 16x16x4 MFMAs on register operands (FP64 when
+ * precision == 0, FP32 when 1), 8 workgroups of 4 waves per compute unit, four
+ * independent accumulators per wave, `iters` rounds (1..2^20) per wave; writes
+ * the dense TFLOP/s (2*16*16*4 flops per MFMA), best of three launches.
+ * scdg_probe_hbm_read: fills a buffer of `bytes` (64 MiB..16 GiB, a multiple
+ * of 16) and reads it with 16-byte nontemporal loads; writes the read GB/s
+ * (1e9 bytes/s), best of five launches.
+ * SCDG_ERR_ARG for arguments outside those ranges or a NULL output,
+ * SCDG_ERR_NOMEM when the buffers cannot be allocated, SCDG_ERR_HIP on a
+ * runtime error. */
+scdg_status scdg_probe_mfma(int32_t precision, int32_t iters, void *hip_stream, double *tflops);
+scdg_status scdg_probe_hbm_read(int64_t bytes, void *hip_stream, double *gbs);
+
 const char *scdg_status_string(scdg_status s);
 /* Last error text of a plan (or of plan creation when p is NULL). */
 scdg_status scdg_last_error(const scdg_plan *p, char *buf, size_t n);

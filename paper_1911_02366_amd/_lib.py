@@ -31,6 +31,7 @@ EXPORTED = [
     "scdg_mlp_create", "scdg_mlp_destroy", "scdg_mlp_param_count", "scdg_mlp_set_compute", "scdg_mlp_forward",
     "scdg_mlp_backward", "scdg_mlp_adam", "scdg_mlp_mse", "scdg_mlp_gather", "scdg_guess_stats",
     "scdg_guess_features", "scdg_guess_target", "scdg_guess_apply",
+    "scdg_probe_mfma", "scdg_probe_hbm_read",
 ]
 GEMM_CONFIGS = ["64x64", "64x128", "128x128", "128x128w8", "128x64", "240x80", "80x80"]
 PHASES = ["inverse", "gemm_x", "gemm_s", "rhs", "schur_apply", "condensed_solve", "backsolve",
@@ -147,6 +148,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_guess_features": (i32, [vp, vp, vp, vp, vp, i32, vp]),
         "scdg_guess_target": (i32, [vp, vp, vp, vp, i32, vp]),
         "scdg_guess_apply": (i32, [vp, vp, vp, vp, i32, vp]),
+        "scdg_probe_mfma": (i32, [i32, i32, vp, C.POINTER(d)]),
+        "scdg_probe_hbm_read": (i32, [i64, vp, C.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

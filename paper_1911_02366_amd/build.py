@@ -10,9 +10,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscdg.so")
 SOURCES = ["scdg_api.hip", "k_inverse.hip", "k_gemm.hip", "k_vec.hip", "k_dense.hip",
-           "k_dgsem.hip", "k_mlp.hip"]
+           "k_dgsem.hip", "k_mlp.hip", "k_probe.hip"]
+# -amdgpu-mfma-vgpr-form: MFMA accumulators in architectural VGPRs (gfx950 has one
+# register file for both); with the AGPR form the compiler copied every
+# accumulator to and from AGPRs on each K step in several GEMM tiles and in the
+# network kernels.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-Wall", "-Wno-unused-function"]
 
 
