@@ -389,6 +389,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--restart", type=int, default=30, help="GMRES restart length (1..63)")
+    ap.add_argument("--krylov-mode", choices=["host", "device", "graph"], default="host",
+                    help="where the GMRES cycle runs (the phase timers do not see kernels inside a graph)")
     ap.add_argument("--precond", type=int, default=1, choices=[0, 1, 2],
                     help="GMRES right preconditioner: 0 none, 1 point Jacobi, 2 5x5 node-block Jacobi")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -466,6 +468,7 @@ def main() -> int:
     b = case.rhs
     plan = Plan.from_structure(case.structure())
     plan.set_inverse_mode(args.inverse_mode)
+    plan.set_krylov_mode(args.krylov_mode)
     plan.assemble(case.aii, case.aib, case.abi, case.bb_val)
     dq = torch.empty(case.n_dof, dtype=torch.float64, device=dev)
 
@@ -583,7 +586,7 @@ def main() -> int:
                    "reynolds": cfg["reynolds"], "mach": 0.1 if cfg["reynolds"] else None, "dt": cfg["dt"],
                    "solver": f"gmres({args.restart})+" + ["none", "point-jacobi", "block-jacobi-5x5"][args.precond],
                    "gmres_tol": opts["tol"],
-                   "precision": args.precision},
+                   "precision": args.precision, "krylov_mode": args.krylov_mode},
         "roofline": entries[dominant],
         "roofline_all": entries,
         "measured_peaks": measured,
