@@ -146,6 +146,22 @@ scdg_status scdg_factor(scdg_plan *p, scdg_precision prec);
  *      precision or the borrowed A_bb pointer change.  Phase timers do not see
  *      the kernels inside the graph. */
 scdg_status scdg_set_krylov_mode(scdg_plan *p, int32_t mode);
+/* Form of the Schur products S x inside the GMRES solve.  The paper assembles
+ * S (Section 2.2, eq. SC_step1); applying it through its factors instead is
+ * an execution choice with the same operator:
+ *   0  assembled (default): scdg_condense forms the element blocks
+ *      T_e = F_e - A_bi(e) X_e and every product streams them plus the A_bb
+ *      remainder;
+ *   1  matrix-free: scdg_condense forms X_e = A_ii(e)^-1 A_ib(e) only, plus the
+ *      Jacobi blocks of S from the diagonal blocks of A_bb and of A_bi(e) X_e;
+ *      every product is S x = A_bb x - sum_e P_e A_bi(e) (X_e x[C_e]), reading
+ *      X_e, A_bi(e) and all of A_bb instead of T_e and the remainder.
+ * Changing the form sends a condensed plan back to the factored state (call
+ * scdg_condense again).  The dense solve of S and scdg_export(SCDG_EXPORT_SCHUR)
+ * need form 0: in form 1 they return SCDG_ERR_STATE, and SCDG_SOLVER_AUTO
+ * selects GMRES.  SCDG_ERR_ARG for a mode other than 0 or 1. */
+scdg_status scdg_set_schur_mode(scdg_plan *p, int32_t mode);
+scdg_status scdg_get_schur_mode(const scdg_plan *p, int32_t *mode);
 
 /* Form of the batched inverse: 0 automatic (blocked above n_i = 320),
  * 1 one workgroup per element for the whole elimination, 2 blocked: outer

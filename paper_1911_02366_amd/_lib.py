@@ -26,7 +26,7 @@ EXPORTED = [
     "scdg_schur_apply", "scdg_export", "scdg_status_string", "scdg_last_error",
     "scdg_enable_timing", "scdg_phase_times", "scdg_autotune", "scdg_set_gemm_config",
     "scdg_get_gemm_config", "scdg_plan_fold_counts", "scdg_set_inverse_mode", "scdg_get_inverse_mode",
-    "scdg_set_krylov_mode", "scdg_newton_step",
+    "scdg_set_krylov_mode", "scdg_set_schur_mode", "scdg_get_schur_mode", "scdg_newton_step",
     "scdg_dg_create", "scdg_dg_destroy", "scdg_dg_residual", "scdg_dg_gradient", "scdg_dg_set_geometry",
     "scdg_mlp_create", "scdg_mlp_destroy", "scdg_mlp_param_count", "scdg_mlp_set_compute", "scdg_mlp_forward",
     "scdg_mlp_backward", "scdg_mlp_adam", "scdg_mlp_mse", "scdg_mlp_gather", "scdg_guess_stats",
@@ -128,6 +128,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_plan_fold_counts": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
         "scdg_set_inverse_mode": (i32, [vp, i32]),
         "scdg_set_krylov_mode": (i32, [vp, i32]),
+        "scdg_set_schur_mode": (i32, [vp, i32]),
+        "scdg_get_schur_mode": (i32, [vp, C.POINTER(i32)]),
         "scdg_get_inverse_mode": (i32, [vp, C.POINTER(i32)]),
         "scdg_newton_step": (i32, [vp, vp, vp, d, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo)]),
         "scdg_dg_create": (i32, [C.POINTER(vp), C.POINTER(DgParams), vp]),

@@ -40,13 +40,14 @@ struct GemvDesc {
 // Everything a captured Newton iteration depends on: scalars baked into kernel
 // arguments and every device pointer its kernels read or write.
 struct NewtonKey {
-  int m = 0, cycles = 0, pmode = -1;
+  int m = 0, cycles = 0, pmode = -1, smode = 0;
   bool fp32 = false;
   double inv_dt = 0, eta_c = 0, lin_tol = 0, eta_max = 0;
   const void *q = nullptr, *q_s = nullptr, *dg = nullptr;
   const void *ptr[18] = {};
   bool operator==(const NewtonKey &o) const {
-    if (m != o.m || cycles != o.cycles || pmode != o.pmode || fp32 != o.fp32 || inv_dt != o.inv_dt ||
+    if (m != o.m || cycles != o.cycles || pmode != o.pmode || smode != o.smode || fp32 != o.fp32 ||
+        inv_dt != o.inv_dt ||
         eta_c != o.eta_c || lin_tol != o.lin_tol || eta_max != o.eta_max || q != o.q || q_s != o.q_s ||
         dg != o.dg)
       return false;
@@ -57,12 +58,12 @@ struct NewtonKey {
 };
 
 struct KrylovKey {
-  int m = 0, pmode = -1;
+  int m = 0, pmode = -1, smode = 0;
   bool fp32 = false;
   const void *sloc = nullptr, *bb_val = nullptr, *gm_v = nullptr;
   bool operator==(const KrylovKey &o) const {
-    return m == o.m && pmode == o.pmode && fp32 == o.fp32 && sloc == o.sloc && bb_val == o.bb_val &&
-           gm_v == o.gm_v;
+    return m == o.m && pmode == o.pmode && smode == o.smode && fp32 == o.fp32 && sloc == o.sloc &&
+           bb_val == o.bb_val && gm_v == o.gm_v;
   }
 };
 
@@ -80,6 +81,10 @@ struct Plan {
   int device = 0;
   std::string last_error;
   int state = 0;  // 0 created, 1 assembled, 2 factored, 3 condensed
+  // Schur products: 0 through the element blocks T_e and the A_bb remainder
+  // (S assembled), 1 matrix-free through X_e, A_bi and the full A_bb
+  int schur_mode = 0;
+  double *mf_dblk = nullptr;  // [sum |C_e| * 25] diagonal 5x5 blocks of A_bi(e) X_e per slot (mode 1)
   scdg_precision prec = SCDG_FP64;
 
   // structure
@@ -99,6 +104,8 @@ struct Plan {
   int64_t *d_slot_soff = nullptr; // [sum |C_e|] S_loc offset of the slot's element
   int32_t *d_slot_nc = nullptr;   // [sum |C_e|] n_c of the slot's element
   int32_t *d_slot_pos = nullptr;  // [sum |C_e|] position of the slot within C_e
+  int64_t *d_slot_ib = nullptr;   // [sum |C_e|] A_bi / X offset of the slot's element
+  int32_t *d_slot_ni = nullptr;   // [sum |C_e|] n_i of the slot's element
   int64_t *d_bb_rowptr = nullptr; // [n_bnodes+1]
   int32_t *d_bb_col = nullptr;    // [nnzb]
   // A_bb blocks folded into the element Schur blocks T_e, and the remainder
@@ -234,6 +241,10 @@ hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *sr
 // T[dst + v nc + w] += A_bb[src][v][w] for the folded blocks
 hipError_t launch_fold_add(const Plan &p, void *t, bool fp32);
 // 5x5 diagonal blocks of S (remainder + element blocks), inverted; point inverse too
+// Matrix-free mode: diagonal 5x5 blocks of A_bi(e) X_e per slot, and the
+// Jacobi preconditioners from diag(A_bb) minus their pulled sums.
+hipError_t launch_mf_diag_blocks(const Plan &p, const void *abi, bool fp32);
+hipError_t launch_precond_setup_mf(const Plan &p);
 hipError_t launch_precond_setup(const Plan &p, const void *t, bool fp32);
 // y = a M^-1 x with M = I (mode 0), diag(S) (1) or the 5x5 node blocks of S (2)
 hipError_t launch_precond_apply(const Plan &p, int mode, const double *x, double *y, double a);

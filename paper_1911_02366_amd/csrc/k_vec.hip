@@ -280,6 +280,71 @@ __global__ void precond_setup_kernel(int64_t n_bnodes, const int64_t *__restrict
   for (int k = 0; k < 25; ++k) pc_blk[g * 25 + k] = inv[k];
 }
 
+// Matrix-free mode: the diagonal 5x5 block of A_bi(e) X_e at every slot (rows
+// 5 pos .. 5 pos + 4 of A_bi, columns 5 pos .. 5 pos + 4 of X), one wave per
+// slot with the lanes striding over the interior index k.
+template <typename TM>
+__global__ __launch_bounds__(kThreads) void mf_diag_blocks_kernel(
+    int64_t n_slots, const int64_t *__restrict__ slot_ib, const int32_t *__restrict__ slot_ni,
+    const int32_t *__restrict__ slot_nc, const int32_t *__restrict__ slot_pos, const TM *__restrict__ abi,
+    const TM *__restrict__ xmat, double *__restrict__ dblk) {
+  const int lane = threadIdx.x & 63;
+  const int64_t s = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (s >= n_slots) return;   // whole waves leave together
+  const int64_t ib = slot_ib[s];
+  const int ni = slot_ni[s], nc = slot_nc[s], pos = slot_pos[s];
+  const TM *a = abi + ib + (int64_t)(5 * pos) * ni;
+  const TM *x = xmat + ib + 5 * pos;
+  double acc[25];
+#pragma unroll
+  for (int q = 0; q < 25; ++q) acc[q] = 0.0;
+  for (int k = lane; k < ni; k += 64) {
+    double av[5], xv[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) av[v] = (double)a[(int64_t)v * ni + k];
+#pragma unroll
+    for (int w = 0; w < 5; ++w) xv[w] = (double)x[(int64_t)k * nc + w];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int w = 0; w < 5; ++w) acc[v * 5 + w] += av[v] * xv[w];
+  }
+#pragma unroll
+  for (int q = 0; q < 25; ++q) acc[q] = wave_sum(acc[q]);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < 25; ++q) dblk[s * 25 + q] = acc[q];
+}
+
+// Matrix-free mode: diagonal block of S at node g = A_bb(g, g) minus the
+// pulled diagonal blocks of A_bi(e) X_e; point and 5x5 block Jacobi from it.
+__global__ void precond_setup_mf_kernel(int64_t n_bnodes, const int64_t *__restrict__ bb_rowptr,
+                                        const int32_t *__restrict__ bb_col, const double *__restrict__ val,
+                                        const int32_t *__restrict__ pull_ptr,
+                                        const int32_t *__restrict__ pull_idx, const double *__restrict__ dblk,
+                                        double *__restrict__ pc_blk, double *__restrict__ diag_inv) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= n_bnodes) return;
+  double a[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) a[k] = 0.0;
+  for (int64_t b = bb_rowptr[g]; b < bb_rowptr[g + 1]; ++b)
+    if (bb_col[b] == g)
+#pragma unroll
+      for (int k = 0; k < 25; ++k) a[k] += val[b * 25 + k];
+  for (int q = pull_ptr[g]; q < pull_ptr[g + 1]; ++q) {
+    const int64_t s = pull_idx[q];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) a[k] -= dblk[s * 25 + k];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) diag_inv[5 * g + v] = 1.0 / a[v * 5 + v];
+  double inv[25];
+  inv5(a, inv);
+#pragma unroll
+  for (int k = 0; k < 25; ++k) pc_blk[g * 25 + k] = inv[k];
+}
+
 __global__ void precond_apply_kernel(int mode, int64_t n_bnodes, const double *__restrict__ diag_inv,
                                      const double *__restrict__ pc_blk,
                                      const double *__restrict__ x, double *__restrict__ y, double a,
@@ -542,6 +607,29 @@ hipError_t launch_precond_setup(const Plan &p, const void *t, bool fp32) {
                        p.d_rem_rowptr, p.d_rem_col, p.d_rem_src, p.bb_val, p.d_pull_ptr,
                        p.d_pull_idx, p.d_slot_soff, p.d_slot_nc, p.d_slot_pos,
                        static_cast<const double *>(t), p.pc_blk, p.diag_s);
+  return hipGetLastError();
+}
+
+hipError_t launch_mf_diag_blocks(const Plan &p, const void *abi, bool fp32) {
+  const int64_t n_slots = p.off_c[p.n_elem] / 5;
+  if (n_slots <= 0) return hipSuccess;
+  const int grid = (int)((n_slots + (kThreads / 64) - 1) / (kThreads / 64));
+  if (fp32)
+    hipLaunchKernelGGL(mf_diag_blocks_kernel<float>, dim3(grid), dim3(kThreads), 0, p.stream, n_slots, p.d_slot_ib,
+                       p.d_slot_ni, p.d_slot_nc, p.d_slot_pos, static_cast<const float *>(abi),
+                       static_cast<const float *>(p.xmat), p.mf_dblk);
+  else
+    hipLaunchKernelGGL(mf_diag_blocks_kernel<double>, dim3(grid), dim3(kThreads), 0, p.stream, n_slots,
+                       p.d_slot_ib, p.d_slot_ni, p.d_slot_nc, p.d_slot_pos, static_cast<const double *>(abi),
+                       static_cast<const double *>(p.xmat), p.mf_dblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond_setup_mf(const Plan &p) {
+  if (p.n_bnodes <= 0) return hipSuccess;
+  const int grid = (int)((p.n_bnodes + 127) / 128);
+  hipLaunchKernelGGL(precond_setup_mf_kernel, dim3(grid), dim3(128), 0, p.stream, p.n_bnodes, p.d_bb_rowptr,
+                     p.d_bb_col, p.bb_val, p.d_pull_ptr, p.d_pull_idx, p.mf_dblk, p.pc_blk, p.diag_s);
   return hipGetLastError();
 }
 

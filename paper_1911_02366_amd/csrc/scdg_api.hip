@@ -195,6 +195,16 @@ scdg_status condense_rhs_impl(Plan &p, const double *b, double *bs) {
 
 scdg_status schur_apply_impl(Plan &p, const double *x, double *y) {
   PhaseTimer tm(p, SCDG_PHASE_SCHUR_APPLY);
+  if (p.schur_mode == 1) {
+    // S x = A_bb x - sum_e P_e A_bi(e) (X_e x[C_e]), S never formed
+    const void *abi = fp32(p) ? p.abi_lo : static_cast<const void *>(p.abi);
+    HIP_TRY(launch_gemv_batched(p.d_gv_aib, p.d_rt_aib, p.n_rt_aib, p.max_nc, p.xmat, fp32(p), x, p.d_cmap,
+                                p.w_z, nullptr, 1.0, 0.0, nullptr, p.stream, p.halt));
+    HIP_TRY(launch_gemv_batched(p.d_gv_abi, p.d_rt_abi, p.n_rt_abi, p.max_ni, abi, fp32(p), p.w_z, nullptr,
+                                p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream, p.halt));
+    HIP_TRY(launch_bsr_pull(p, true, 0.0, nullptr, nullptr, 1.0, x, -1.0, p.w_t, y));
+    return SCDG_OK;
+  }
   HIP_TRY(launch_gemv_batched(p.d_gv_s, p.d_rt_s, p.n_rt_s, p.max_nc, p.sloc, fp32(p), x, p.d_cmap,
                               p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream, p.halt));
   // S x = A_bb,rem x + sum_e P_e T_e x[C_e],  T_e = folded A_bb blocks - A_bi(e) X_e
@@ -271,6 +281,7 @@ scdg_status krylov_graph(Plan &p, int m, int pmode) {
   key.sloc = p.sloc;
   key.bb_val = p.bb_val;
   key.gm_v = p.gm_v;
+  key.smode = p.schur_mode;
   if (p.kr_exec && p.kr_key == key) return SCDG_OK;
   drop_krylov_graph(p);
   if (!p.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
@@ -516,6 +527,7 @@ NewtonKey newton_key(const Plan &p, scdg_dg *dg, const double *q_s, const double
   k.m = ns.m;
   k.cycles = 0;   // the cycle budget is a host loop bound, not part of any graph
   k.pmode = ns.pmode;
+  k.smode = p.schur_mode;
   k.fp32 = fp32(p);
   k.inv_dt = ns.inv_dt;
   k.eta_c = ns.eta_c;
@@ -664,8 +676,13 @@ scdg_status solve_condensed_impl(Plan &p, const double *bs, double *qb, const do
                                  const scdg_solve_opts &o, scdg_solve_info &info) {
   PhaseTimer tm(p, SCDG_PHASE_CONDENSED);
   int solver = o.solver;
-  if (solver == SCDG_SOLVER_AUTO) solver = p.n1 <= 8192 ? SCDG_SOLVER_DENSE : SCDG_SOLVER_GMRES;
+  if (solver == SCDG_SOLVER_AUTO)
+    solver = p.n1 <= 8192 && p.schur_mode == 0 ? SCDG_SOLVER_DENSE : SCDG_SOLVER_GMRES;
   info.solver_used = solver;
+  if (solver == SCDG_SOLVER_DENSE && p.schur_mode == 1) {
+    p.last_error = "the dense solve needs the assembled S (scdg_set_schur_mode 0)";
+    return SCDG_ERR_STATE;
+  }
   if (solver == SCDG_SOLVER_DENSE) {
     if (p.n1 > 40000) {
       p.last_error = "dense solve of S limited to n1 <= 40000";
@@ -713,7 +730,8 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   Plan &p = pl->p;
   (void)hipStreamSynchronize(p.stream);
   dfree(p.d_imap); dfree(p.d_bmap); dfree(p.d_cmap); dfree(p.d_pull_ptr); dfree(p.d_pull_idx);
-  dfree(p.d_slot_soff); dfree(p.d_slot_nc); dfree(p.d_slot_pos);
+  dfree(p.d_slot_soff); dfree(p.d_slot_nc); dfree(p.d_slot_pos); dfree(p.d_slot_ib); dfree(p.d_slot_ni);
+  dfree(p.mf_dblk);
   dfree(p.d_fold_dst); dfree(p.d_fold_nc); dfree(p.d_fold_src);
   dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk); dfree(p.rem_val);
   dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_inv_order); dfree(p.d_info);
@@ -845,8 +863,8 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   std::vector<int32_t> pull_ptr(p.n_bnodes + 1, 0), pull_idx(n_slots);
   for (int64_t g = 0; g < p.n_bnodes; ++g) pull_ptr[g + 1] = pull_ptr[g] + pull_cnt[g + 1];
   std::vector<int32_t> fill(pull_ptr.begin(), pull_ptr.end() - 1);
-  std::vector<int64_t> slot_soff(n_slots);
-  std::vector<int32_t> slot_nc(n_slots), slot_pos(n_slots);
+  std::vector<int64_t> slot_soff(n_slots), slot_ib(n_slots);
+  std::vector<int32_t> slot_nc(n_slots), slot_pos(n_slots), slot_ni(n_slots);
   for (int e = 0; e < E; ++e) {
     const int64_t c0 = s->c_ptr[e];
     for (int64_t q = c0; q < s->c_ptr[e + 1]; ++q) {
@@ -855,6 +873,8 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
       slot_soff[slot] = p.off_cc[e];
       slot_nc[slot] = p.nc[e];
       slot_pos[slot] = (int32_t)(q - c0);
+      slot_ib[slot] = p.off_ib[e];
+      slot_ni[slot] = p.ni[e];
     }
   }
   // ---- A_bb fold: block (g, h) goes to the element that owns node g when both
@@ -950,6 +970,8 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   chk(upload(p, &p.d_slot_soff, slot_soff));
   chk(upload(p, &p.d_slot_nc, slot_nc));
   chk(upload(p, &p.d_slot_pos, slot_pos));
+  chk(upload(p, &p.d_slot_ib, slot_ib));
+  chk(upload(p, &p.d_slot_ni, slot_ni));
   chk(upload(p, &p.d_bb_rowptr, bb_rowptr));
   chk(upload(p, &p.d_fold_dst, fold_dst));
   chk(upload(p, &p.d_fold_nc, fold_nc));
@@ -1158,6 +1180,23 @@ scdg_status scdg_set_krylov_mode(scdg_plan *pl, int32_t mode) {
   return SCDG_OK;
 }
 
+scdg_status scdg_set_schur_mode(scdg_plan *pl, int32_t mode) {
+  if (!pl || mode < 0 || mode > 1) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  if (mode != p.schur_mode) {
+    p.schur_mode = mode;
+    if (p.state > 2) p.state = 2;   // condense again in the new form
+    p.dense_factored = false;
+  }
+  return SCDG_OK;
+}
+
+scdg_status scdg_get_schur_mode(const scdg_plan *pl, int32_t *mode) {
+  if (!pl || !mode) return SCDG_ERR_ARG;
+  *mode = pl->p.schur_mode;
+  return SCDG_OK;
+}
+
 scdg_status scdg_set_inverse_mode(scdg_plan *pl, int32_t mode) {
   if (!pl || mode < 0 || mode > 2) return SCDG_ERR_ARG;
   pl->p.inverse_mode = mode;
@@ -1212,7 +1251,7 @@ scdg_status scdg_condense(scdg_plan *pl) {
     ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.xmat), nx));
     p.cap_x = nx;
   }
-  if (ns > p.cap_s) {
+  if (p.schur_mode == 0 && ns > p.cap_s) {   // the matrix-free form never stores T_e
     dfree(p.sloc);
     ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.sloc), ns));
     p.cap_s = ns;
@@ -1230,6 +1269,17 @@ scdg_status scdg_condense(scdg_plan *pl) {
     PhaseTimer tm(p, SCDG_PHASE_GEMM_X);
     HIP_TRY(launch_gemm_batched(p.gemm_cfg_x, p.d_gx, p.d_tiles_x, p.n_tiles_x, p.ainv, aib, p.xmat,
                                 1.0, 0.0, fp32(p), p.stream));
+  }
+  if (p.schur_mode == 1) {
+    // matrix-free Schur products: only the Jacobi blocks of S are formed, from
+    // diag(A_bb) and the diagonal 5x5 blocks of A_bi(e) X_e
+    if (!p.mf_dblk) ST_TRY(dalloc(p, &p.mf_dblk, (size_t)p.off_c[E] / kNvar * 25));
+    HIP_TRY(launch_mf_diag_blocks(p, abi, fp32(p)));
+    HIP_TRY(launch_precond_setup_mf(p));
+    p.state = 3;
+    p.dense_factored = false;
+    ST_TRY(sync(p));
+    return SCDG_OK;
   }
   {
     PhaseTimer tm(p, SCDG_PHASE_GEMM_S);
@@ -1617,7 +1667,7 @@ scdg_status scdg_export(scdg_plan *pl, int what, void *dst, size_t dst_bytes) {
     src = p.ainv;
     bytes = esize(p) * (size_t)p.off_ii[p.n_elem];
   } else if (what == SCDG_EXPORT_SCHUR) {
-    if (p.state < 3) return SCDG_ERR_STATE;
+    if (p.state < 3 || p.schur_mode == 1) return SCDG_ERR_STATE;
     src = p.sloc;
     bytes = esize(p) * (size_t)p.off_cc[p.n_elem];
   } else if (what == SCDG_EXPORT_X) {

@@ -184,6 +184,18 @@ class Plan:
         m = {"host": 0, "device": 1, "graph": 2}[mode]
         self._check(self.lib.scdg_set_krylov_mode(self.handle, m), "scdg_set_krylov_mode")
 
+    def set_schur_mode(self, mode: str):
+        """'assembled' (Schur products through the element blocks T_e) or
+        'matrix_free' (through X_e, A_bi and A_bb; T_e never formed).  A
+        condensed plan needs condense() again after a change."""
+        m = {"assembled": 0, "matrix_free": 1}[mode]
+        self._check(self.lib.scdg_set_schur_mode(self.handle, m), "scdg_set_schur_mode")
+
+    def schur_mode(self) -> str:
+        out = C.c_int32()
+        self._check(self.lib.scdg_get_schur_mode(self.handle, C.byref(out)), "scdg_get_schur_mode")
+        return ["assembled", "matrix_free"][out.value]
+
     def set_inverse_mode(self, mode: str):
         """'auto', 'single' (one workgroup per element) or 'blocked'."""
         m = {"auto": 0, "single": 1, "blocked": 2}[mode]
