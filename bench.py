@@ -324,21 +324,26 @@ def time_stepping_experiment(args) -> dict:
 
     case = build_case(device="cuda", **WORKLOADS[args.ts_workload])
     mesh, prm, dt = case.mesh, case.prm, case.dt
-    mk = lambda prec: ImplicitStepper(case.structure(), mesh.k_elem, mesh.order, prm.mach, prm.reynolds, dt,
-                                      lambda q: jacobian_blocks(q, mesh, prm, dt), lin_tol=args.lg_lin_tol,
-                                      newton_tol=args.lg_newton_tol, precision=prec, graph=True)
-    steppers = {"fp64": mk("fp64"), "fp32": mk("fp32")}
+    mk = lambda prec, sm="assembled": ImplicitStepper(
+        case.structure(), mesh.k_elem, mesh.order, prm.mach, prm.reynolds, dt,
+        lambda q: jacobian_blocks(q, mesh, prm, dt), lin_tol=args.lg_lin_tol, newton_tol=args.lg_newton_tol,
+        precision=prec, graph=True, schur_mode=sm)
+    # the *_mf steppers apply S through X_e, A_bi and A_bb (T_e never formed)
+    steppers = {"fp64": mk("fp64"), "fp32": mk("fp32"), "fp64_mf": mk("fp64", "matrix_free"),
+                "fp32_mf": mk("fp32", "matrix_free")}
     variants = [("host_fp64", "fp64", False), ("graph_fp64", "fp64", True),
-                ("host_fp32", "fp32", False), ("graph_fp32", "fp32", True)]
+                ("host_fp32", "fp32", False), ("graph_fp32", "fp32", True),
+                ("graph_fp64_mf", "fp64_mf", True), ("graph_fp32_mf", "fp32_mf", True)]
     rec = {v: {"seconds": [], "newton": [], "gmres": [], "lin_unconverged": []} for v, _, _ in variants}
-    prep = {"fp64": [], "fp32": []}
-    diff = {"graph_fp64": [], "host_fp32": [], "graph_fp32": []}
+    prep = {k: [] for k in steppers}
+    diff = {"graph_fp64": [], "host_fp32": [], "graph_fp32": [], "graph_fp64_mf": [], "graph_fp32_mf": []}
     q = case.q_state.reshape(-1).contiguous()
     dq_prev = None
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
     for step in range(1, args.ts_steps + 1):
         prep["fp64"].append(steppers["fp64"].prepare(q))
-        prep["fp32"].append(steppers["fp32"].prepare(q, blocks=steppers["fp64"]._blocks))
+        for k in ("fp32", "fp64_mf", "fp32_mf"):
+            prep[k].append(steppers[k].prepare(q, blocks=steppers["fp64"]._blocks))
         out = {}
         for name, prec, graph in variants:
             q1, info = steppers[prec].solve_step(q, guess=dq_prev, mode="newton", graph=graph)
@@ -372,7 +377,8 @@ def time_stepping_experiment(args) -> dict:
         "lin_unconverged_total": {k: int(np.sum(rec[k]["lin_unconverged"])) for k in names},
         "max_rel_diff_vs_host_fp64_increment": {k: float(np.max(v)) for k, v in diff.items()},
     }
-    result["step_seconds_mean"] = {k: result["solve_seconds_per_step_mean"][k] + pm[k[-4:]] for k in names}
+    which = {v: st for v, st, _ in variants}
+    result["step_seconds_mean"] = {k: result["solve_seconds_per_step_mean"][k] + pm[which[k]] for k in names}
     z = result["step_seconds_mean"]["host_fp64"]
     result["speedup_vs_host_fp64"] = {k: z / result["step_seconds_mean"][k] for k in names}
     for s_ in steppers.values():
