@@ -69,7 +69,7 @@ typedef enum {
   SCDG_ERR_SINGULAR = -5,   /* zero / non-finite pivot in some A_ii(e) or S */
   SCDG_ERR_NOCONV = -6,     /* iteration budget exhausted; outputs hold the best iterate */
   SCDG_ERR_NONFINITE = -7,  /* NaN / Inf met in a right-hand side or residual */
-  SCDG_ERR_UNSUPPORTED = -8 /* order or size outside what this build handles */
+  SCDG_ERR_UNSUPPORTED = -8 /* order or size outside what the library handles */
 } scdg_status;
 
 typedef enum { SCDG_FP64 = 0, SCDG_FP32 = 1 } scdg_precision;
