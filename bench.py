@@ -528,29 +528,45 @@ def main() -> int:
                 "phase_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in ph32.items()},
                 "gemm_tiles": {"x": tun32["x"], "s": tun32["s"]}}
     if args.precision == "fp64" and not args.no_matrix_free_variant:
-        # Schur products through X_e, A_bi and the full A_bb, T_e never formed
+        # Schur products without T_e: through X_e, A_bi and the full A_bb (matrix_free), or
+        # through the nonzero 5x5 blocks of A_ib and A_bi and A_ii^-1 (matrix_free_sparse)
         import numpy as np
-        nix = float(np.sum(np.broadcast_to(np.asarray(case.n_i, dtype=np.float64), (case.n_elem,)) *
-                           np.broadcast_to(np.asarray(case.n_c, dtype=np.float64), (case.n_elem,))))
+        nb_e = lambda a: np.broadcast_to(np.asarray(a, dtype=np.float64), (case.n_elem,))
+        nix = float(np.sum(nb_e(case.n_i) * nb_e(case.n_c)))
+        nii = float(np.sum(nb_e(case.n_i) ** 2))
         nnzb = int(case.bb_rowptr[-1])
-        plan.set_schur_mode("matrix_free")
-        for prec, tol in (("fp64", args.tol), ("fp32", fp32_tol)):
-            ms_mf, inf_mf, ph_mf, _, _ = measure(prec, tol, args.steps, args.warmup)
-            sa = ph_mf.get("schur_apply", {"ms": 0.0, "count": 0})
-            per_launch = sa["ms"] / max(sa["count"], 1)
-            # X_e and A_bi(e) in the factor precision, all of A_bb (values + columns), x, y, z, t
-            mf_bytes = 2 * nix * (8 if prec == "fp64" else 4) + nnzb * (25 * 8 + 4) + 2 * case.n1 * 8 \
-                + 2 * (case.n2 + 5 * case.n_bnodes) * 8
-            variants[f"matrix_free_{prec}" + ("" if prec == "fp64" else f"_ir_inner_tol_{tol:g}")] = {
-                "ms_per_step": round(ms_mf, 3), "value_dof_s": round(case.n_dof / (ms_mf / 1e3), 1),
-                "speedup_vs_assembled_fp64": round(ms_per_step / ms_mf, 3),
-                "rel_res_full_max": max(i["rel_res_full"] for i in inf_mf),
-                "gmres_iters_per_step": sum(i["iters"] for i in inf_mf) / len(inf_mf),
-                "ir_sweeps_per_step": sum(i["ir_sweeps"] for i in inf_mf) / len(inf_mf),
-                "schur_apply_ms_per_launch": round(per_launch, 4),
-                "schur_apply_algorithmic_bytes": mf_bytes,
-                "schur_apply_gbs": round(mf_bytes / (per_launch / 1e3) / 1e9, 1) if per_launch > 0 else None,
-                "phase_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in ph_mf.items()}}
+        nz_blocks = None
+        if case.aib.dim() == 3:                  # uniform order: count the nonzero blocks
+            ne_, ni_, nc_ = case.aib.shape
+            nzb = lambda m, r, c: int((m.reshape(ne_, r // 5, 5, c // 5, 5).abs().amax(dim=(2, 4)) > 0).sum())
+            nz_blocks = nzb(case.aib, ni_, nc_) + nzb(case.abi, nc_, ni_)
+        vec_bytes = 2 * case.n1 * 8 + 2 * (case.n2 + 5 * case.n_bnodes) * 8
+        for smode in ("matrix_free", "matrix_free_sparse"):
+            plan.set_schur_mode(smode)
+            for prec, tol in (("fp64", args.tol), ("fp32", fp32_tol)):
+                esz = 8 if prec == "fp64" else 4
+                ms_mf, inf_mf, ph_mf, _, _ = measure(prec, tol, args.steps, args.warmup)
+                sa = ph_mf.get("schur_apply", {"ms": 0.0, "count": 0})
+                per_launch = sa["ms"] / max(sa["count"], 1)
+                if smode == "matrix_free":
+                    # X_e and A_bi(e) dense in the factor precision, all of A_bb, vectors
+                    mf_bytes = 2 * nix * esz + nnzb * (25 * 8 + 4) + vec_bytes
+                elif nz_blocks is not None:
+                    # nonzero blocks of A_ib and A_bi (values + node index), A_ii^-1, A_bb, vectors
+                    mf_bytes = nz_blocks * (25 * esz + 4) + nii * esz + nnzb * (25 * 8 + 4) + vec_bytes
+                else:
+                    mf_bytes = None
+                variants[f"{smode}_{prec}" + ("" if prec == "fp64" else f"_ir_inner_tol_{tol:g}")] = {
+                    "ms_per_step": round(ms_mf, 3), "value_dof_s": round(case.n_dof / (ms_mf / 1e3), 1),
+                    "speedup_vs_assembled_fp64": round(ms_per_step / ms_mf, 3),
+                    "rel_res_full_max": max(i["rel_res_full"] for i in inf_mf),
+                    "gmres_iters_per_step": sum(i["iters"] for i in inf_mf) / len(inf_mf),
+                    "ir_sweeps_per_step": sum(i["ir_sweeps"] for i in inf_mf) / len(inf_mf),
+                    "schur_apply_ms_per_launch": round(per_launch, 4),
+                    "schur_apply_algorithmic_bytes": mf_bytes,
+                    "schur_apply_gbs": round(mf_bytes / (per_launch / 1e3) / 1e9, 1)
+                    if per_launch > 0 and mf_bytes else None,
+                    "phase_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in ph_mf.items()}}
         plan.set_schur_mode("assembled")
     value = case.n_dof / (ms_per_step / 1e3)
     work = algorithmic_work(case, args.precision, plan.n_remainder)

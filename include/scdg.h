@@ -155,11 +155,18 @@ scdg_status scdg_set_krylov_mode(scdg_plan *p, int32_t mode);
  *   1  matrix-free: scdg_condense forms X_e = A_ii(e)^-1 A_ib(e) only, plus the
  *      Jacobi blocks of S from the diagonal blocks of A_bb and of A_bi(e) X_e;
  *      every product is S x = A_bb x - sum_e P_e A_bi(e) (X_e x[C_e]), reading
- *      X_e, A_bi(e) and all of A_bb instead of T_e and the remainder.
+ *      X_e, A_bi(e) and all of A_bb instead of T_e and the remainder;
+ *   2  matrix-free and block-sparse: as 1, but every product is
+ *      S x = A_bb x - sum_e P_e A_bi(e) (A_ii(e)^-1 (A_ib(e) x[C_e])) through
+ *      the nonzero 5x5 blocks of A_ib and A_bi only (the paper notes the
+ *      tensor-product sparsity of these blocks, Section 3.1).  scdg_condense
+ *      finds the nonzero blocks from the values (zero blocks are skipped
+ *      exactly), rebuilds its block lists when that pattern changed, and
+ *      copies the nonzero blocks in the factor precision.
  * Changing the form sends a condensed plan back to the factored state (call
  * scdg_condense again).  The dense solve of S and scdg_export(SCDG_EXPORT_SCHUR)
- * need form 0: in form 1 they return SCDG_ERR_STATE, and SCDG_SOLVER_AUTO
- * selects GMRES.  SCDG_ERR_ARG for a mode other than 0 or 1. */
+ * need form 0: in forms 1 and 2 they return SCDG_ERR_STATE, and
+ * SCDG_SOLVER_AUTO selects GMRES.  SCDG_ERR_ARG for a mode other than 0..2. */
 scdg_status scdg_set_schur_mode(scdg_plan *p, int32_t mode);
 scdg_status scdg_get_schur_mode(const scdg_plan *p, int32_t *mode);
 

@@ -44,14 +44,14 @@ struct NewtonKey {
   bool fp32 = false;
   double inv_dt = 0, eta_c = 0, lin_tol = 0, eta_max = 0;
   const void *q = nullptr, *q_s = nullptr, *dg = nullptr;
-  const void *ptr[18] = {};
+  const void *ptr[23] = {};
   bool operator==(const NewtonKey &o) const {
     if (m != o.m || cycles != o.cycles || pmode != o.pmode || smode != o.smode || fp32 != o.fp32 ||
         inv_dt != o.inv_dt ||
         eta_c != o.eta_c || lin_tol != o.lin_tol || eta_max != o.eta_max || q != o.q || q_s != o.q_s ||
         dg != o.dg)
       return false;
-    for (int i = 0; i < 18; ++i)
+    for (int i = 0; i < 23; ++i)
       if (ptr[i] != o.ptr[i]) return false;
     return true;
   }
@@ -61,10 +61,28 @@ struct KrylovKey {
   int m = 0, pmode = -1, smode = 0;
   bool fp32 = false;
   const void *sloc = nullptr, *bb_val = nullptr, *gm_v = nullptr;
+  const void *sp[5] = {};   // block-sparse operators of the sparse matrix-free form
   bool operator==(const KrylovKey &o) const {
+    for (int i = 0; i < 5; ++i)
+      if (sp[i] != o.sp[i]) return false;
     return m == o.m && pmode == o.pmode && smode == o.smode && fp32 == o.fp32 && sloc == o.sloc &&
            bb_val == o.bb_val && gm_v == o.gm_v;
   }
+};
+
+// A block-sparse element operator (rows of 5x5 blocks): the nonzero blocks of
+// A_ib (block rows = interior nodes, x = boundary vector) or of A_bi (block
+// rows = coupling-set nodes, x = interior vector), found from the values.
+struct SparseOp {
+  int64_t n_rows = 0, n_blocks = 0;
+  int64_t *d_rowptr = nullptr;   // [n_rows + 1]
+  int32_t *d_xnode = nullptr;    // [n_blocks] node of x the block multiplies (x index 5 xnode + w)
+  int64_t *d_ybase = nullptr;    // [n_rows] first y index of the block row
+  int64_t *d_src = nullptr;      // [n_blocks] offset of the block's entry (0, 0) in the dense blocks
+  int32_t *d_ld = nullptr;       // [n_blocks] row length of the dense element matrix
+  void *val = nullptr;           // [n_blocks * 25] compacted values in the factor precision
+  size_t cap_val = 0;
+  std::vector<uint8_t> mask;     // block mask the lists were built from
 };
 
 // GEMM tile configurations (rows x columns of C per workgroup)
@@ -84,7 +102,13 @@ struct Plan {
   // Schur products: 0 through the element blocks T_e and the A_bb remainder
   // (S assembled), 1 matrix-free through X_e, A_bi and the full A_bb
   int schur_mode = 0;
-  double *mf_dblk = nullptr;  // [sum |C_e| * 25] diagonal 5x5 blocks of A_bi(e) X_e per slot (mode 1)
+  double *mf_dblk = nullptr;  // [sum |C_e| * 25] diagonal 5x5 blocks of A_bi(e) X_e per slot (modes 1, 2)
+  // mode 2: products through the nonzero blocks of A_ib and A_bi and A_ii^-1
+  SparseOp sp_ib, sp_bi;
+  uint8_t *d_mask = nullptr;        // [sum (n_i / 5)(n_c / 5)] block mask (one matrix at a time)
+  int64_t *d_e_offib = nullptr, *d_e_maskoff = nullptr;  // [n_elem] A_ib / A_bi offset, mask offset
+  int32_t *d_e_ri = nullptr, *d_e_rc = nullptr;          // [n_elem] n_i / 5, n_c / 5
+  double *w_z2 = nullptr;           // [n2]
   scdg_precision prec = SCDG_FP64;
 
   // structure
@@ -92,6 +116,8 @@ struct Plan {
   std::vector<int32_t> order;
   int64_t n_dof = 0, n1 = 0, n2 = 0, n_bnodes = 0, nnzb = 0;
   std::vector<int32_t> ni, nc;          // DOF counts per element
+  std::vector<int64_t> h_c_ptr;         // host copy of the coupling sets
+  std::vector<int32_t> h_c_node;
   std::vector<int64_t> off_q, off_ii, off_ib, off_cc, off_i, off_c, bnode_off;
   int32_t max_ni = 0, max_nc = 0;
 
@@ -245,6 +271,14 @@ hipError_t launch_fold_add(const Plan &p, void *t, bool fp32);
 // Jacobi preconditioners from diag(A_bb) minus their pulled sums.
 hipError_t launch_mf_diag_blocks(const Plan &p, const void *abi, bool fp32);
 hipError_t launch_precond_setup_mf(const Plan &p);
+// Block-sparse element products (Schur form 2)
+hipError_t launch_block_mask(const double *mat, const int64_t *m_off, const int32_t *rb_n, const int32_t *cb_n,
+                             const int64_t *mask_off, uint8_t *mask, int n_elem, hipStream_t s);
+hipError_t launch_gather_blocks_ld(const void *src, const int64_t *src_off, const int32_t *ld, int64_t n, void *dst,
+                                   bool fp32, hipStream_t s);
+hipError_t launch_bsr5_rows(int64_t n_rows, const int64_t *rowptr, const int32_t *xnode, const void *val,
+                            bool fp32, const double *x, const int64_t *ybase, double *y, hipStream_t s,
+                            const int32_t *halt);
 hipError_t launch_precond_setup(const Plan &p, const void *t, bool fp32);
 // y = a M^-1 x with M = I (mode 0), diag(S) (1) or the 5x5 node blocks of S (2)
 hipError_t launch_precond_apply(const Plan &p, int mode, const double *x, double *y, double a);

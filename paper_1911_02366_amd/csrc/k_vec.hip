@@ -345,6 +345,94 @@ __global__ void precond_setup_mf_kernel(int64_t n_bnodes, const int64_t *__restr
   for (int k = 0; k < 25; ++k) pc_blk[g * 25 + k] = inv[k];
 }
 
+// ------------------------------------------ block-sparse element products
+// Nonzero 5x5 blocks of row-major element matrices (5 R rows x 5 C columns,
+// element after element): mask[mask_off[e] + rb C + cb] = 1 when an entry of
+// block (rb, cb) is nonzero.  blockIdx.y is the element; consecutive threads
+// take consecutive blocks of a block row, so each of the 25 loads reads
+// neighbouring 40-byte segments.
+__global__ void block_mask_kernel(const double *__restrict__ mat, const int64_t *__restrict__ m_off,
+                                  const int32_t *__restrict__ rb_n, const int32_t *__restrict__ cb_n,
+                                  const int64_t *__restrict__ mask_off, uint8_t *__restrict__ mask) {
+  const int e = blockIdx.y;
+  const int cn = cb_n[e];
+  const int64_t nb = (int64_t)rb_n[e] * cn;
+  const int64_t ld = 5 * (int64_t)cn;
+  const double *a = mat + m_off[e];
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rb = b / cn, cb = b % cn;
+    const double *blk = a + 5 * rb * ld + 5 * cb;
+    bool nz = false;
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int w = 0; w < 5; ++w) nz = nz || blk[v * ld + w] != 0.0;
+    mask[mask_off[e] + b] = nz ? 1 : 0;
+  }
+}
+
+// dst[25 b + 5 v + w] = src[src_off[b] + v ld[b] + w]: the listed 5x5 blocks,
+// compacted in list order
+template <typename TM>
+__global__ void gather_blocks_ld_kernel(const TM *__restrict__ src, const int64_t *__restrict__ src_off,
+                                        const int32_t *__restrict__ ld, int64_t n, TM *__restrict__ dst) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * 25;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / 25;
+    const int k = (int)(i % 25);
+    dst[i] = src[src_off[b] + (int64_t)(k / 5) * ld[b] + k % 5];
+  }
+}
+
+// y[ybase[r] + v] = sum over the blocks b of block row r of
+// val[b][v][w] x[5 xnode[b] + w]: one wave per block row, lanes as in the
+// BSR product below (12 blocks per step, two steps per trip, cross-lane sums).
+template <typename TM>
+__global__ __launch_bounds__(kThreads) void bsr5_rows_kernel(
+    int64_t n_rows, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ xnode,
+    const TM *__restrict__ val, const double *__restrict__ x, const int64_t *__restrict__ ybase,
+    double *__restrict__ y, const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (r >= n_rows) return;   // whole waves leave together
+  const int v = lane % 5, bq = lane / 5;
+  double s = 0.0;
+  if (lane < 60) {
+    const int64_t b0 = rowptr[r], b1 = rowptr[r + 1];
+    double s2 = 0.0;
+    int64_t blk = b0 + bq;
+    for (; blk + 12 < b1; blk += 24) {
+      const TM *ra = val + blk * 25 + v * 5, *rb = val + (blk + 12) * 25 + v * 5;
+      const double *xa = x + (int64_t)xnode[blk] * 5, *xb = x + (int64_t)xnode[blk + 12] * 5;
+      double ma[5], mb[5], ya[5], yb[5];
+#pragma unroll
+      for (int w = 0; w < 5; ++w) {
+        ma[w] = (double)ra[w];
+        mb[w] = (double)rb[w];
+        ya[w] = xa[w];
+        yb[w] = xb[w];
+      }
+#pragma unroll
+      for (int w = 0; w < 5; ++w) {
+        s += ma[w] * ya[w];
+        s2 += mb[w] * yb[w];
+      }
+    }
+    if (blk < b1) {
+      const TM *ra = val + blk * 25 + v * 5;
+      const double *xa = x + (int64_t)xnode[blk] * 5;
+#pragma unroll
+      for (int w = 0; w < 5; ++w) s += (double)ra[w] * xa[w];
+    }
+    s += s2;
+  }
+  s += __shfl_down(s, 30);
+  s += __shfl_down(s, 15);
+  const double s5 = __shfl_down(s, 5), s10 = __shfl_down(s, 10);
+  if (lane < 5) y[ybase[r] + lane] = s + s5 + s10;
+}
+
 __global__ void precond_apply_kernel(int mode, int64_t n_bnodes, const double *__restrict__ diag_inv,
                                      const double *__restrict__ pc_blk,
                                      const double *__restrict__ x, double *__restrict__ y, double a,
@@ -630,6 +718,40 @@ hipError_t launch_precond_setup_mf(const Plan &p) {
   const int grid = (int)((p.n_bnodes + 127) / 128);
   hipLaunchKernelGGL(precond_setup_mf_kernel, dim3(grid), dim3(128), 0, p.stream, p.n_bnodes, p.d_bb_rowptr,
                      p.d_bb_col, p.bb_val, p.d_pull_ptr, p.d_pull_idx, p.mf_dblk, p.pc_blk, p.diag_s);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_mask(const double *mat, const int64_t *m_off, const int32_t *rb_n, const int32_t *cb_n,
+                             const int64_t *mask_off, uint8_t *mask, int n_elem, hipStream_t s) {
+  if (n_elem <= 0) return hipSuccess;
+  hipLaunchKernelGGL(block_mask_kernel, dim3(16, n_elem), dim3(kThreads), 0, s, mat, m_off, rb_n, cb_n, mask_off,
+                     mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_blocks_ld(const void *src, const int64_t *src_off, const int32_t *ld, int64_t n, void *dst,
+                                   bool fp32, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(gather_blocks_ld_kernel<float>, dim3(grid_for(n * 25)), dim3(kThreads), 0, s,
+                       static_cast<const float *>(src), src_off, ld, n, static_cast<float *>(dst));
+  else
+    hipLaunchKernelGGL(gather_blocks_ld_kernel<double>, dim3(grid_for(n * 25)), dim3(kThreads), 0, s,
+                       static_cast<const double *>(src), src_off, ld, n, static_cast<double *>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_bsr5_rows(int64_t n_rows, const int64_t *rowptr, const int32_t *xnode, const void *val,
+                            bool fp32, const double *x, const int64_t *ybase, double *y, hipStream_t s,
+                            const int32_t *halt) {
+  if (n_rows <= 0) return hipSuccess;
+  const int grid = (int)((n_rows + (kThreads / 64) - 1) / (kThreads / 64));
+  if (fp32)
+    hipLaunchKernelGGL(bsr5_rows_kernel<float>, dim3(grid), dim3(kThreads), 0, s, n_rows, rowptr, xnode,
+                       static_cast<const float *>(val), x, ybase, y, halt);
+  else
+    hipLaunchKernelGGL(bsr5_rows_kernel<double>, dim3(grid), dim3(kThreads), 0, s, n_rows, rowptr, xnode,
+                       static_cast<const double *>(val), x, ybase, y, halt);
   return hipGetLastError();
 }
 

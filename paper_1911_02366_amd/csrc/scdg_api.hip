@@ -193,8 +193,78 @@ scdg_status condense_rhs_impl(Plan &p, const double *b, double *bs) {
   return SCDG_OK;
 }
 
+// Block-sparse copy of A_ib (which == 0) or A_bi (which == 1) for the sparse
+// matrix-free form.  The block mask comes from the FP64 values on the device;
+// the block lists are rebuilt on the host only when the mask changed (new
+// lists mean new device arrays, which the graph keys see); the values are
+// compacted in the factor precision at every condense.
+scdg_status sparse_op_update(Plan &p, int which, const void *vals) {
+  SparseOp &op = which == 0 ? p.sp_ib : p.sp_bi;
+  const int E = p.n_elem;
+  int64_t mask_n = 0;
+  for (int e = 0; e < E; ++e) mask_n += (int64_t)(p.ni[e] / kNvar) * (p.nc[e] / kNvar);
+  if (!p.d_mask) ST_TRY(dalloc(p, &p.d_mask, (size_t)std::max<int64_t>(mask_n, 1)));
+  // A_ib(e) is n_i x n_c (block rows n_i / 5); A_bi(e) is n_c x n_i
+  HIP_TRY(launch_block_mask(which == 0 ? p.aib : p.abi, p.d_e_offib, which == 0 ? p.d_e_ri : p.d_e_rc,
+                            which == 0 ? p.d_e_rc : p.d_e_ri, p.d_e_maskoff, p.d_mask, E, p.stream));
+  std::vector<uint8_t> mask((size_t)mask_n);
+  HIP_TRY(hipMemcpyAsync(mask.data(), p.d_mask, (size_t)mask_n, hipMemcpyDeviceToHost, p.stream));
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  if (!op.d_rowptr || mask != op.mask) {
+    std::vector<int64_t> rowptr(1, 0), ybase, src;
+    std::vector<int32_t> xnode, ld;
+    int64_t mo = 0;
+    for (int e = 0; e < E; ++e) {
+      const int ri = p.ni[e] / kNvar, rc = p.nc[e] / kNvar;
+      const int rows = which == 0 ? ri : rc, cols = which == 0 ? rc : ri;
+      for (int rb = 0; rb < rows; ++rb) {
+        ybase.push_back(which == 0 ? p.off_i[e] + kNvar * rb : p.off_c[e] + kNvar * rb);
+        for (int cb = 0; cb < cols; ++cb) {
+          if (!mask[(size_t)(mo + (int64_t)rb * cols + cb)]) continue;
+          xnode.push_back(which == 0 ? p.h_c_node[(size_t)(p.h_c_ptr[e] + cb)]
+                                     : (int32_t)(p.off_i[e] / kNvar + cb));
+          src.push_back(p.off_ib[e] + (int64_t)(kNvar * rb) * (kNvar * cols) + kNvar * cb);
+          ld.push_back(kNvar * cols);
+        }
+        rowptr.push_back((int64_t)xnode.size());
+      }
+      mo += (int64_t)rows * cols;
+    }
+    dfree(op.d_rowptr); dfree(op.d_xnode); dfree(op.d_ybase); dfree(op.d_src); dfree(op.d_ld);
+    op.n_rows = (int64_t)ybase.size();
+    op.n_blocks = (int64_t)xnode.size();
+    ST_TRY(upload(p, &op.d_rowptr, rowptr));
+    ST_TRY(upload(p, &op.d_ybase, ybase));
+    if (op.n_blocks > 0) {
+      ST_TRY(upload(p, &op.d_xnode, xnode));
+      ST_TRY(upload(p, &op.d_src, src));
+      ST_TRY(upload(p, &op.d_ld, ld));
+    }
+    op.mask.swap(mask);
+  }
+  const size_t need = esize(p) * (size_t)std::max<int64_t>(op.n_blocks, 1) * 25;
+  if (need > op.cap_val) {
+    dfree(op.val);
+    ST_TRY(dalloc(p, reinterpret_cast<char **>(&op.val), need));
+    op.cap_val = need;
+  }
+  HIP_TRY(launch_gather_blocks_ld(vals, op.d_src, op.d_ld, op.n_blocks, op.val, fp32(p), p.stream));
+  return SCDG_OK;
+}
+
 scdg_status schur_apply_impl(Plan &p, const double *x, double *y) {
   PhaseTimer tm(p, SCDG_PHASE_SCHUR_APPLY);
+  if (p.schur_mode == 2) {
+    // S x = A_bb x - sum_e P_e A_bi(e) (A_ii(e)^-1 (A_ib(e) x[C_e])) through the nonzero blocks
+    HIP_TRY(launch_bsr5_rows(p.sp_ib.n_rows, p.sp_ib.d_rowptr, p.sp_ib.d_xnode, p.sp_ib.val, fp32(p), x,
+                             p.sp_ib.d_ybase, p.w_z, p.stream, p.halt));
+    HIP_TRY(launch_gemv_batched(p.d_gv_inv, p.d_rt_inv, p.n_rt_inv, p.max_ni, p.ainv, fp32(p), p.w_z, nullptr,
+                                p.w_z2, nullptr, 1.0, 0.0, nullptr, p.stream, p.halt));
+    HIP_TRY(launch_bsr5_rows(p.sp_bi.n_rows, p.sp_bi.d_rowptr, p.sp_bi.d_xnode, p.sp_bi.val, fp32(p), p.w_z2,
+                             p.sp_bi.d_ybase, p.w_t, p.stream, p.halt));
+    HIP_TRY(launch_bsr_pull(p, true, 0.0, nullptr, nullptr, 1.0, x, -1.0, p.w_t, y));
+    return SCDG_OK;
+  }
   if (p.schur_mode == 1) {
     // S x = A_bb x - sum_e P_e A_bi(e) (X_e x[C_e]), S never formed
     const void *abi = fp32(p) ? p.abi_lo : static_cast<const void *>(p.abi);
@@ -282,6 +352,8 @@ scdg_status krylov_graph(Plan &p, int m, int pmode) {
   key.bb_val = p.bb_val;
   key.gm_v = p.gm_v;
   key.smode = p.schur_mode;
+  const void *sp[5] = {p.sp_ib.val, p.sp_ib.d_rowptr, p.sp_bi.val, p.sp_bi.d_rowptr, p.w_z2};
+  for (int i = 0; i < 5; ++i) key.sp[i] = sp[i];
   if (p.kr_exec && p.kr_key == key) return SCDG_OK;
   drop_krylov_graph(p);
   if (!p.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
@@ -536,9 +608,11 @@ NewtonKey newton_key(const Plan &p, scdg_dg *dg, const double *q_s, const double
   k.q = q;
   k.q_s = q_s;
   k.dg = dg;
-  const void *ptrs[18] = {p.ainv, p.xmat, p.sloc,  p.abi,  p.abi_lo, p.bb_val, p.rem_val, p.gm_v,  p.nw_r,
-                          p.nw_dq, p.diag_s, p.pc_blk, p.kr_H, p.kr_cs, p.kr_sn,  p.kr_g,   p.kr_st,  p.kr_dev};
-  for (int i = 0; i < 18; ++i) k.ptr[i] = ptrs[i];
+  const void *ptrs[23] = {p.ainv, p.xmat, p.sloc,  p.abi,  p.abi_lo, p.bb_val, p.rem_val, p.gm_v,
+                          p.nw_r, p.nw_dq, p.diag_s, p.pc_blk, p.kr_H, p.kr_cs, p.kr_sn,  p.kr_g,
+                          p.kr_st, p.kr_dev, p.sp_ib.val, p.sp_ib.d_rowptr, p.sp_bi.val, p.sp_bi.d_rowptr,
+                          p.w_z2};
+  for (int i = 0; i < 23; ++i) k.ptr[i] = ptrs[i];
   return k;
 }
 
@@ -679,7 +753,7 @@ scdg_status solve_condensed_impl(Plan &p, const double *bs, double *qb, const do
   if (solver == SCDG_SOLVER_AUTO)
     solver = p.n1 <= 8192 && p.schur_mode == 0 ? SCDG_SOLVER_DENSE : SCDG_SOLVER_GMRES;
   info.solver_used = solver;
-  if (solver == SCDG_SOLVER_DENSE && p.schur_mode == 1) {
+  if (solver == SCDG_SOLVER_DENSE && p.schur_mode != 0) {
     p.last_error = "the dense solve needs the assembled S (scdg_set_schur_mode 0)";
     return SCDG_ERR_STATE;
   }
@@ -732,6 +806,11 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.d_imap); dfree(p.d_bmap); dfree(p.d_cmap); dfree(p.d_pull_ptr); dfree(p.d_pull_idx);
   dfree(p.d_slot_soff); dfree(p.d_slot_nc); dfree(p.d_slot_pos); dfree(p.d_slot_ib); dfree(p.d_slot_ni);
   dfree(p.mf_dblk);
+  for (SparseOp *op : {&p.sp_ib, &p.sp_bi}) {
+    dfree(op->d_rowptr); dfree(op->d_xnode); dfree(op->d_ybase); dfree(op->d_src); dfree(op->d_ld);
+    dfree(op->val);
+  }
+  dfree(p.d_mask); dfree(p.d_e_offib); dfree(p.d_e_maskoff); dfree(p.d_e_ri); dfree(p.d_e_rc); dfree(p.w_z2);
   dfree(p.d_fold_dst); dfree(p.d_fold_nc); dfree(p.d_fold_src);
   dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk); dfree(p.rem_val);
   dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_inv_order); dfree(p.d_info);
@@ -860,6 +939,8 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
     }
   }
   const int64_t n_slots = p.off_c[E] / kNvar;
+  p.h_c_ptr.assign(s->c_ptr, s->c_ptr + E + 1);
+  p.h_c_node.assign(s->c_node, s->c_node + s->c_ptr[E]);
   std::vector<int32_t> pull_ptr(p.n_bnodes + 1, 0), pull_idx(n_slots);
   for (int64_t g = 0; g < p.n_bnodes; ++g) pull_ptr[g + 1] = pull_ptr[g] + pull_cnt[g + 1];
   std::vector<int32_t> fill(pull_ptr.begin(), pull_ptr.end() - 1);
@@ -983,6 +1064,23 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   chk(upload(p, &p.d_bb_col, bb_col));
   chk(upload(p, &p.d_inv_n, inv_n));
   chk(upload(p, &p.d_inv_off, inv_off));
+  {
+    // per-element sizes for the block masks of the sparse matrix-free form
+    std::vector<int64_t> offib(E), maskoff(E);
+    std::vector<int32_t> ri(E), rc(E);
+    int64_t mo = 0;
+    for (int e = 0; e < E; ++e) {
+      offib[e] = p.off_ib[e];
+      ri[e] = p.ni[e] / kNvar;
+      rc[e] = p.nc[e] / kNvar;
+      maskoff[e] = mo;
+      mo += (int64_t)ri[e] * rc[e];
+    }
+    chk(upload(p, &p.d_e_offib, offib));
+    chk(upload(p, &p.d_e_maskoff, maskoff));
+    chk(upload(p, &p.d_e_ri, ri));
+    chk(upload(p, &p.d_e_rc, rc));
+  }
   {
     std::vector<int32_t> ord(p.n_elem);
     for (int e = 0; e < p.n_elem; ++e) ord[e] = e;
@@ -1181,7 +1279,7 @@ scdg_status scdg_set_krylov_mode(scdg_plan *pl, int32_t mode) {
 }
 
 scdg_status scdg_set_schur_mode(scdg_plan *pl, int32_t mode) {
-  if (!pl || mode < 0 || mode > 1) return SCDG_ERR_ARG;
+  if (!pl || mode < 0 || mode > 2) return SCDG_ERR_ARG;
   Plan &p = pl->p;
   if (mode != p.schur_mode) {
     p.schur_mode = mode;
@@ -1251,7 +1349,7 @@ scdg_status scdg_condense(scdg_plan *pl) {
     ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.xmat), nx));
     p.cap_x = nx;
   }
-  if (p.schur_mode == 0 && ns > p.cap_s) {   // the matrix-free form never stores T_e
+  if (p.schur_mode == 0 && ns > p.cap_s) {   // the matrix-free forms never store T_e
     dfree(p.sloc);
     ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.sloc), ns));
     p.cap_s = ns;
@@ -1270,12 +1368,17 @@ scdg_status scdg_condense(scdg_plan *pl) {
     HIP_TRY(launch_gemm_batched(p.gemm_cfg_x, p.d_gx, p.d_tiles_x, p.n_tiles_x, p.ainv, aib, p.xmat,
                                 1.0, 0.0, fp32(p), p.stream));
   }
-  if (p.schur_mode == 1) {
+  if (p.schur_mode != 0) {
     // matrix-free Schur products: only the Jacobi blocks of S are formed, from
     // diag(A_bb) and the diagonal 5x5 blocks of A_bi(e) X_e
     if (!p.mf_dblk) ST_TRY(dalloc(p, &p.mf_dblk, (size_t)p.off_c[E] / kNvar * 25));
     HIP_TRY(launch_mf_diag_blocks(p, abi, fp32(p)));
     HIP_TRY(launch_precond_setup_mf(p));
+    if (p.schur_mode == 2) {
+      if (!p.w_z2) ST_TRY(dalloc(p, &p.w_z2, (size_t)std::max<int64_t>(p.n2, 1)));
+      ST_TRY(sparse_op_update(p, 0, aib));
+      ST_TRY(sparse_op_update(p, 1, abi));
+    }
     p.state = 3;
     p.dense_factored = false;
     ST_TRY(sync(p));
@@ -1667,7 +1770,7 @@ scdg_status scdg_export(scdg_plan *pl, int what, void *dst, size_t dst_bytes) {
     src = p.ainv;
     bytes = esize(p) * (size_t)p.off_ii[p.n_elem];
   } else if (what == SCDG_EXPORT_SCHUR) {
-    if (p.state < 3 || p.schur_mode == 1) return SCDG_ERR_STATE;
+    if (p.state < 3 || p.schur_mode != 0) return SCDG_ERR_STATE;
     src = p.sloc;
     bytes = esize(p) * (size_t)p.off_cc[p.n_elem];
   } else if (what == SCDG_EXPORT_X) {

@@ -185,16 +185,18 @@ class Plan:
         self._check(self.lib.scdg_set_krylov_mode(self.handle, m), "scdg_set_krylov_mode")
 
     def set_schur_mode(self, mode: str):
-        """'assembled' (Schur products through the element blocks T_e) or
-        'matrix_free' (through X_e, A_bi and A_bb; T_e never formed).  A
-        condensed plan needs condense() again after a change."""
-        m = {"assembled": 0, "matrix_free": 1}[mode]
+        """'assembled' (Schur products through the element blocks T_e),
+        'matrix_free' (through X_e, A_bi and A_bb; T_e never formed) or
+        'matrix_free_sparse' (through the nonzero 5x5 blocks of A_ib and A_bi,
+        A_ii^-1 and A_bb).  A condensed plan needs condense() again after a
+        change."""
+        m = {"assembled": 0, "matrix_free": 1, "matrix_free_sparse": 2}[mode]
         self._check(self.lib.scdg_set_schur_mode(self.handle, m), "scdg_set_schur_mode")
 
     def schur_mode(self) -> str:
         out = C.c_int32()
         self._check(self.lib.scdg_get_schur_mode(self.handle, C.byref(out)), "scdg_get_schur_mode")
-        return ["assembled", "matrix_free"][out.value]
+        return ["assembled", "matrix_free", "matrix_free_sparse"][out.value]
 
     def set_inverse_mode(self, mode: str):
         """'auto', 'single' (one workgroup per element) or 'blocked'."""

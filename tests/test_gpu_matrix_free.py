@@ -1,5 +1,6 @@
-"""Matrix-free Schur products (scdg_set_schur_mode 1): S x = A_bb x -
-sum_e P_e A_bi(e) (X_e x[C_e]) without forming T_e.
+"""Matrix-free Schur products without forming T_e: form 1, S x = A_bb x -
+sum_e P_e A_bi(e) (X_e x[C_e]); form 2, the same through the nonzero 5x5
+blocks of A_ib and A_bi and A_ii^-1 (the block pattern found from the values).
 
 * One product equals the assembled product to rounding, on random vectors.
 * Solves equal the oracle's sparse LU to the FP64 bar, with the same GMRES
@@ -10,6 +11,7 @@ sum_e P_e A_bi(e) (X_e x[C_e]) without forming T_e.
   and the state rules (re-condense after a change; dense solve and the Schur
   export refused).
 """
+import numpy as np
 import pytest
 import torch
 
@@ -32,14 +34,18 @@ def _plan(case, dev, mode, precision="fp64", krylov="host"):
     return plan
 
 
+MF = ["matrix_free", "matrix_free_sparse"]
+
+
+@pytest.mark.parametrize("mode", MF)
 @pytest.mark.parametrize("k,n", [(2, 3), (2, 5), (3, 4)])
-def test_product_equals_assembled(k, n):
-    print(f"matrix-free product K={k} N={n}", flush=True)
+def test_product_equals_assembled(k, n, mode):
+    print(f"{mode} product K={k} N={n}", flush=True)
     case = build_case(k, n, 1600.0, 5e-3, seed=4)
     dev = device_case(case)
     asm = _plan(case, dev, "assembled")
-    mf = _plan(case, dev, "matrix_free")
-    assert mf.schur_mode() == "matrix_free" and asm.schur_mode() == "assembled"
+    mf = _plan(case, dev, mode)
+    assert mf.schur_mode() == mode and asm.schur_mode() == "assembled"
     gen = torch.Generator(device=DEV)
     gen.manual_seed(3)
     for _ in range(3):
@@ -54,13 +60,13 @@ def test_product_equals_assembled(k, n):
 @pytest.mark.parametrize("precond", [1, 2])
 @pytest.mark.parametrize("k,n", [(2, 3), (2, 5)])
 def test_solve_matches_oracle_and_assembled_iterations(k, n, precond):
-    print(f"matrix-free solve K={k} N={n} precond {precond}", flush=True)
+    print(f"matrix-free solves K={k} N={n} precond {precond}", flush=True)
     case = build_case(k, n, 1600.0, 5e-3, seed=2)
     d = oracle_arrays(case)
     dev = device_case(case)
     ref = oracle.solve_sparse(oracle_matrix(d), d["b"])
     its = {}
-    for mode in ("assembled", "matrix_free"):
+    for mode in ["assembled"] + MF:
         plan = _plan(case, dev, mode)
         dq, info = plan.solve(dev["b"], solver="gmres", tol=1e-12, precond=precond)
         assert rel(to_np(dq), ref) <= 1e-10, (mode, info)
@@ -68,14 +74,16 @@ def test_solve_matches_oracle_and_assembled_iterations(k, n, precond):
         its[mode] = info["iters"]
         plan.close()
     assert abs(its["matrix_free"] - its["assembled"]) <= 1, its
+    assert abs(its["matrix_free_sparse"] - its["assembled"]) <= 1, its
 
 
-def test_fp32_refinement_and_mixed_orders():
+@pytest.mark.parametrize("mode", MF)
+def test_fp32_refinement_and_mixed_orders(mode):
     case = build_case(2, 5, 1600.0, 5e-3, seed=7)
     d = oracle_arrays(case)
     dev = device_case(case)
     ref = oracle.solve_sparse(oracle_matrix(d), d["b"])
-    plan = _plan(case, dev, "matrix_free", precision="fp32")
+    plan = _plan(case, dev, mode, precision="fp32")
     dq, info = plan.solve(dev["b"], solver="gmres", tol=1e-6, ir_tol=1e-10)
     print("fp32 matrix-free", info, flush=True)
     assert info["rel_res_full"] <= 1e-10 and rel(to_np(dq), ref) <= 1e-7
@@ -87,7 +95,7 @@ def test_fp32_refinement_and_mixed_orders():
                                bb_col=c.bb_col, **c.element_blocks())
     mref = oracle.solve_sparse(a, to_np(c.rhs))
     plan = Plan.from_structure(cd.structure())
-    plan.set_schur_mode("matrix_free")
+    plan.set_schur_mode(mode)
     plan.assemble(cd.aii, cd.aib, cd.abi, cd.bb_val)
     plan.factor("fp64")
     plan.condense()
@@ -96,12 +104,13 @@ def test_fp32_refinement_and_mixed_orders():
     plan.close()
 
 
-def test_captured_cycle_and_state_rules():
+@pytest.mark.parametrize("mode", MF)
+def test_captured_cycle_and_state_rules(mode):
     case = build_case(2, 4, 1600.0, 5e-3, seed=6)
     d = oracle_arrays(case)
     dev = device_case(case)
     ref = oracle.solve_sparse(oracle_matrix(d), d["b"])
-    plan = _plan(case, dev, "matrix_free", krylov="graph")
+    plan = _plan(case, dev, mode, krylov="graph")
     for _ in range(2):
         dq, info = plan.solve(dev["b"], solver="gmres", tol=1e-12, restart=8)
         assert info["restarts"] >= 2 and rel(to_np(dq), ref) <= 1e-10, info
@@ -120,7 +129,7 @@ def test_captured_cycle_and_state_rules():
     plan.condense()
     dq, info = plan.solve(dev["b"], solver="gmres", tol=1e-12, restart=8)
     assert rel(to_np(dq), ref) <= 1e-10, info
-    plan.set_schur_mode("matrix_free")
+    plan.set_schur_mode(mode)
     plan.condense()
     dq, info = plan.solve(dev["b"], solver="auto", tol=1e-12)
     assert info["solver_used"] == 2 and rel(to_np(dq), ref) <= 1e-10, info
@@ -129,7 +138,8 @@ def test_captured_cycle_and_state_rules():
     plan.close()
 
 
-def test_newton_steps_in_matrix_free_form():
+@pytest.mark.parametrize("mode", MF)
+def test_newton_steps_in_matrix_free_form(mode):
     """Captured Newton iterations (scdg_newton_step) with matrix-free products
     equal the host-driven ones and the assembled form's step."""
     from paper_1911_02366_amd.newton import ImplicitStepper
@@ -144,8 +154,8 @@ def test_newton_steps_in_matrix_free_form():
     q_ref, info_ref = ref.solve_step(q)
     ref.close()
     st = ImplicitStepper(case.structure(), mesh.k_elem, mesh.order, prm.mach, prm.reynolds, dt, jac,
-                         newton_tol=1e-10, lin_tol=1e-12, autotune=False, graph=True, schur_mode="matrix_free")
-    assert st.plan.schur_mode() == "matrix_free"
+                         newton_tol=1e-10, lin_tol=1e-12, autotune=False, graph=True, schur_mode=mode)
+    assert st.plan.schur_mode() == mode
     for step in range(2):
         st.prepare(q)
         q_h, info_h = st.solve_step(q, graph=False)
@@ -157,3 +167,32 @@ def test_newton_steps_in_matrix_free_form():
             assert rel(to_np(q_g - q), to_np(q_ref - q)) <= 1e-8, (info_g, info_ref)
         q = q_g
     st.close()
+
+
+def test_sparse_form_follows_a_changed_block_pattern():
+    """New blocks with a different zero pattern (one nonzero block of every
+    element's A_ib and A_bi zeroed) are found at the next condense, the block
+    lists are rebuilt and the captured cycle is recaptured."""
+    case = build_case(2, 4, 1600.0, 5e-3, seed=9)
+    d = oracle_arrays(case)
+    dev = device_case(case)
+    plan = _plan(case, dev, "matrix_free_sparse", krylov="graph")
+    dq, _ = plan.solve(dev["b"], solver="gmres", tol=1e-12, restart=8)
+    assert rel(to_np(dq), oracle.solve_sparse(oracle_matrix(d), d["b"])) <= 1e-10
+    aib, abi = d["aib"].copy(), d["abi"].copy()
+    for e in range(aib.shape[0]):
+        nz = np.argwhere(np.abs(aib[e].reshape(aib.shape[1] // 5, 5, -1, 5)).max(axis=(1, 3)) > 0)
+        rb, cb = nz[len(nz) // 2]
+        aib[e, 5 * rb:5 * rb + 5, 5 * cb:5 * cb + 5] = 0.0
+        nz = np.argwhere(np.abs(abi[e].reshape(abi.shape[1] // 5, 5, -1, 5)).max(axis=(1, 3)) > 0)
+        rb, cb = nz[len(nz) // 3]
+        abi[e, 5 * rb:5 * rb + 5, 5 * cb:5 * cb + 5] = 0.0
+    d2 = dict(d, aib=aib, abi=abi)
+    aib_d = torch.tensor(aib, device=DEV)
+    abi_d = torch.tensor(abi, device=DEV)
+    plan.assemble(dev["aii"], aib_d, abi_d, dev["bb_val"])
+    plan.factor("fp64")
+    plan.condense()
+    dq2, info = plan.solve(dev["b"], solver="gmres", tol=1e-12, restart=8)
+    assert rel(to_np(dq2), oracle.solve_sparse(oracle_matrix(d2), d["b"])) <= 1e-10, info
+    plan.close()
