@@ -41,12 +41,14 @@ struct GemvDesc {
 // arguments and every device pointer its kernels read or write.
 struct NewtonKey {
   int m = 0, cycles = 0, pmode = -1, smode = 0;
+  uint64_t sp_gen = 0;
   bool fp32 = false;
   double inv_dt = 0, eta_c = 0, lin_tol = 0, eta_max = 0;
   const void *q = nullptr, *q_s = nullptr, *dg = nullptr;
   const void *ptr[23] = {};
   bool operator==(const NewtonKey &o) const {
-    if (m != o.m || cycles != o.cycles || pmode != o.pmode || smode != o.smode || fp32 != o.fp32 ||
+    if (m != o.m || cycles != o.cycles || pmode != o.pmode || smode != o.smode || sp_gen != o.sp_gen ||
+        fp32 != o.fp32 ||
         inv_dt != o.inv_dt ||
         eta_c != o.eta_c || lin_tol != o.lin_tol || eta_max != o.eta_max || q != o.q || q_s != o.q_s ||
         dg != o.dg)
@@ -59,13 +61,17 @@ struct NewtonKey {
 
 struct KrylovKey {
   int m = 0, pmode = -1, smode = 0;
+  uint64_t sp_gen = 0;
   bool fp32 = false;
   const void *sloc = nullptr, *bb_val = nullptr, *gm_v = nullptr;
-  const void *sp[5] = {};   // block-sparse operators of the sparse matrix-free form
+  // the matrix-free forms' operands: block-sparse lists, work vector, and the
+  // caller's A_ib / A_bi (their addresses can change with every assemble)
+  const void *sp[7] = {};
   bool operator==(const KrylovKey &o) const {
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 7; ++i)
       if (sp[i] != o.sp[i]) return false;
-    return m == o.m && pmode == o.pmode && smode == o.smode && fp32 == o.fp32 && sloc == o.sloc &&
+    return m == o.m && pmode == o.pmode && smode == o.smode && sp_gen == o.sp_gen && fp32 == o.fp32 &&
+           sloc == o.sloc &&
            bb_val == o.bb_val && gm_v == o.gm_v;
   }
 };
@@ -82,7 +88,7 @@ struct SparseOp {
   int32_t *d_ld = nullptr;       // [n_blocks] row length of the dense element matrix
   void *val = nullptr;           // [n_blocks * 25] compacted values in the factor precision
   size_t cap_val = 0;
-  std::vector<uint8_t> mask;     // block mask the lists were built from
+  uint8_t *d_mask_ref = nullptr; // block mask the lists were built from
 };
 
 // GEMM tile configurations (rows x columns of C per workgroup)
@@ -105,7 +111,9 @@ struct Plan {
   double *mf_dblk = nullptr;  // [sum |C_e| * 25] diagonal 5x5 blocks of A_bi(e) X_e per slot (modes 1, 2)
   // mode 2: products through the nonzero blocks of A_ib and A_bi and A_ii^-1
   SparseOp sp_ib, sp_bi;
+  uint64_t sp_gen = 0;              // count of block-list rebuilds (part of the graph keys)
   uint8_t *d_mask = nullptr;        // [sum (n_i / 5)(n_c / 5)] block mask (one matrix at a time)
+  int32_t *d_mask_flag = nullptr;   // [1] masks differ
   int64_t *d_e_offib = nullptr, *d_e_maskoff = nullptr;  // [n_elem] A_ib / A_bi offset, mask offset
   int32_t *d_e_ri = nullptr, *d_e_rc = nullptr;          // [n_elem] n_i / 5, n_c / 5
   double *w_z2 = nullptr;           // [n2]
@@ -276,6 +284,7 @@ hipError_t launch_block_mask(const double *mat, const int64_t *m_off, const int3
                              const int64_t *mask_off, uint8_t *mask, int n_elem, hipStream_t s);
 hipError_t launch_gather_blocks_ld(const void *src, const int64_t *src_off, const int32_t *ld, int64_t n, void *dst,
                                    bool fp32, hipStream_t s);
+hipError_t launch_mask_diff(const uint8_t *a, const uint8_t *b, int64_t n, int32_t *flag, hipStream_t s);
 hipError_t launch_bsr5_rows(int64_t n_rows, const int64_t *rowptr, const int32_t *xnode, const void *val,
                             bool fp32, const double *x, const int64_t *ybase, double *y, hipStream_t s,
                             const int32_t *halt);

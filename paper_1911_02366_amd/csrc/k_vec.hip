@@ -371,6 +371,15 @@ __global__ void block_mask_kernel(const double *__restrict__ mat, const int64_t 
   }
 }
 
+// flag[0] = 1 when the two masks differ anywhere (every writer stores 1)
+__global__ void mask_diff_kernel(const uint8_t *__restrict__ a, const uint8_t *__restrict__ b, int64_t n,
+                                 int32_t *__restrict__ flag) {
+  bool diff = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    diff = diff || a[i] != b[i];
+  if (diff) flag[0] = 1;
+}
+
 // dst[25 b + 5 v + w] = src[src_off[b] + v ld[b] + w]: the listed 5x5 blocks,
 // compacted in list order
 template <typename TM>
@@ -726,6 +735,12 @@ hipError_t launch_block_mask(const double *mat, const int64_t *m_off, const int3
   if (n_elem <= 0) return hipSuccess;
   hipLaunchKernelGGL(block_mask_kernel, dim3(16, n_elem), dim3(kThreads), 0, s, mat, m_off, rb_n, cb_n, mask_off,
                      mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_diff(const uint8_t *a, const uint8_t *b, int64_t n, int32_t *flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mask_diff_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, a, b, n, flag);
   return hipGetLastError();
 }
 

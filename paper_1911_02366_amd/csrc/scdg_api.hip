@@ -193,6 +193,9 @@ scdg_status condense_rhs_impl(Plan &p, const double *b, double *bs) {
   return SCDG_OK;
 }
 
+void drop_krylov_graph(Plan &p);
+void drop_newton_graph(Plan &p);
+
 // Block-sparse copy of A_ib (which == 0) or A_bi (which == 1) for the sparse
 // matrix-free form.  The block mask comes from the FP64 values on the device;
 // the block lists are rebuilt on the host only when the mask changed (new
@@ -207,10 +210,28 @@ scdg_status sparse_op_update(Plan &p, int which, const void *vals) {
   // A_ib(e) is n_i x n_c (block rows n_i / 5); A_bi(e) is n_c x n_i
   HIP_TRY(launch_block_mask(which == 0 ? p.aib : p.abi, p.d_e_offib, which == 0 ? p.d_e_ri : p.d_e_rc,
                             which == 0 ? p.d_e_rc : p.d_e_ri, p.d_e_maskoff, p.d_mask, E, p.stream));
-  std::vector<uint8_t> mask((size_t)mask_n);
-  HIP_TRY(hipMemcpyAsync(mask.data(), p.d_mask, (size_t)mask_n, hipMemcpyDeviceToHost, p.stream));
-  HIP_TRY(hipStreamSynchronize(p.stream));
-  if (!op.d_rowptr || mask != op.mask) {
+  bool rebuild = op.d_mask_ref == nullptr;
+  if (!rebuild) {
+    // compare with the mask the lists were built from on the device: only a flag comes back
+    if (!p.d_mask_flag) ST_TRY(dalloc(p, &p.d_mask_flag, 1));
+    HIP_TRY(hipMemsetAsync(p.d_mask_flag, 0, sizeof(int32_t), p.stream));
+    HIP_TRY(launch_mask_diff(p.d_mask, op.d_mask_ref, mask_n, p.d_mask_flag, p.stream));
+    int32_t flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, p.d_mask_flag, sizeof(int32_t), hipMemcpyDeviceToHost, p.stream));
+    HIP_TRY(hipStreamSynchronize(p.stream));
+    rebuild = flag != 0;
+  }
+  if (rebuild) {
+    // the captured GMRES cycle and Newton pieces hold the old list pointers as
+    // kernel arguments: drop them (the next use recaptures), and count the
+    // rebuild in the graph keys, since a new list may reuse a freed address
+    HIP_TRY(hipStreamSynchronize(p.stream));
+    drop_krylov_graph(p);
+    drop_newton_graph(p);
+    ++p.sp_gen;
+    std::vector<uint8_t> mask((size_t)mask_n);
+    HIP_TRY(hipMemcpyAsync(mask.data(), p.d_mask, (size_t)mask_n, hipMemcpyDeviceToHost, p.stream));
+    HIP_TRY(hipStreamSynchronize(p.stream));
     std::vector<int64_t> rowptr(1, 0), ybase, src;
     std::vector<int32_t> xnode, ld;
     int64_t mo = 0;
@@ -240,7 +261,8 @@ scdg_status sparse_op_update(Plan &p, int which, const void *vals) {
       ST_TRY(upload(p, &op.d_src, src));
       ST_TRY(upload(p, &op.d_ld, ld));
     }
-    op.mask.swap(mask);
+    if (!op.d_mask_ref) ST_TRY(dalloc(p, &op.d_mask_ref, (size_t)std::max<int64_t>(mask_n, 1)));
+    HIP_TRY(hipMemcpyAsync(op.d_mask_ref, p.d_mask, (size_t)mask_n, hipMemcpyDeviceToDevice, p.stream));
   }
   const size_t need = esize(p) * (size_t)std::max<int64_t>(op.n_blocks, 1) * 25;
   if (need > op.cap_val) {
@@ -352,8 +374,9 @@ scdg_status krylov_graph(Plan &p, int m, int pmode) {
   key.bb_val = p.bb_val;
   key.gm_v = p.gm_v;
   key.smode = p.schur_mode;
-  const void *sp[5] = {p.sp_ib.val, p.sp_ib.d_rowptr, p.sp_bi.val, p.sp_bi.d_rowptr, p.w_z2};
-  for (int i = 0; i < 5; ++i) key.sp[i] = sp[i];
+  const void *sp[7] = {p.sp_ib.val, p.sp_ib.d_rowptr, p.sp_bi.val, p.sp_bi.d_rowptr, p.w_z2, p.aib, p.abi};
+  for (int i = 0; i < 7; ++i) key.sp[i] = sp[i];
+  key.sp_gen = p.sp_gen;
   if (p.kr_exec && p.kr_key == key) return SCDG_OK;
   drop_krylov_graph(p);
   if (!p.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
@@ -600,6 +623,7 @@ NewtonKey newton_key(const Plan &p, scdg_dg *dg, const double *q_s, const double
   k.cycles = 0;   // the cycle budget is a host loop bound, not part of any graph
   k.pmode = ns.pmode;
   k.smode = p.schur_mode;
+  k.sp_gen = p.sp_gen;
   k.fp32 = fp32(p);
   k.inv_dt = ns.inv_dt;
   k.eta_c = ns.eta_c;
@@ -808,8 +832,9 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.mf_dblk);
   for (SparseOp *op : {&p.sp_ib, &p.sp_bi}) {
     dfree(op->d_rowptr); dfree(op->d_xnode); dfree(op->d_ybase); dfree(op->d_src); dfree(op->d_ld);
-    dfree(op->val);
+    dfree(op->val); dfree(op->d_mask_ref);
   }
+  dfree(p.d_mask_flag);
   dfree(p.d_mask); dfree(p.d_e_offib); dfree(p.d_e_maskoff); dfree(p.d_e_ri); dfree(p.d_e_rc); dfree(p.w_z2);
   dfree(p.d_fold_dst); dfree(p.d_fold_nc); dfree(p.d_fold_src);
   dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk); dfree(p.rem_val);
