@@ -328,21 +328,24 @@ def time_stepping_experiment(args) -> dict:
         case.structure(), mesh.k_elem, mesh.order, prm.mach, prm.reynolds, dt,
         lambda q: jacobian_blocks(q, mesh, prm, dt), lin_tol=args.lg_lin_tol, newton_tol=args.lg_newton_tol,
         precision=prec, graph=True, schur_mode=sm)
-    # the *_mf steppers apply S through X_e, A_bi and A_bb (T_e never formed)
+    # the *_mf steppers apply S through X_e, A_bi and A_bb (T_e never formed), the *_mfs
+    # steppers through the nonzero blocks of A_ib and A_bi and A_ii^-1
     steppers = {"fp64": mk("fp64"), "fp32": mk("fp32"), "fp64_mf": mk("fp64", "matrix_free"),
-                "fp32_mf": mk("fp32", "matrix_free")}
+                "fp32_mf": mk("fp32", "matrix_free"), "fp64_mfs": mk("fp64", "matrix_free_sparse"),
+                "fp32_mfs": mk("fp32", "matrix_free_sparse")}
     variants = [("host_fp64", "fp64", False), ("graph_fp64", "fp64", True),
                 ("host_fp32", "fp32", False), ("graph_fp32", "fp32", True),
-                ("graph_fp64_mf", "fp64_mf", True), ("graph_fp32_mf", "fp32_mf", True)]
+                ("graph_fp64_mf", "fp64_mf", True), ("graph_fp32_mf", "fp32_mf", True),
+                ("graph_fp64_mfs", "fp64_mfs", True), ("graph_fp32_mfs", "fp32_mfs", True)]
     rec = {v: {"seconds": [], "newton": [], "gmres": [], "lin_unconverged": []} for v, _, _ in variants}
     prep = {k: [] for k in steppers}
-    diff = {"graph_fp64": [], "host_fp32": [], "graph_fp32": [], "graph_fp64_mf": [], "graph_fp32_mf": []}
+    diff = {v: [] for v, _, _ in variants if v != "host_fp64"}
     q = case.q_state.reshape(-1).contiguous()
     dq_prev = None
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
     for step in range(1, args.ts_steps + 1):
         prep["fp64"].append(steppers["fp64"].prepare(q))
-        for k in ("fp32", "fp64_mf", "fp32_mf"):
+        for k in ("fp32", "fp64_mf", "fp32_mf", "fp64_mfs", "fp32_mfs"):
             prep[k].append(steppers[k].prepare(q, blocks=steppers["fp64"]._blocks))
         out = {}
         for name, prec, graph in variants:

@@ -196,3 +196,23 @@ def test_sparse_form_follows_a_changed_block_pattern():
     dq2, info = plan.solve(dev["b"], solver="gmres", tol=1e-12, restart=8)
     assert rel(to_np(dq2), oracle.solve_sparse(oracle_matrix(d2), d["b"])) <= 1e-10, info
     plan.close()
+
+
+def test_captured_cycle_follows_new_caller_blocks():
+    """The plain matrix-free form reads the caller's A_bi inside the captured
+    GMRES cycle: new blocks in new buffers recapture it (the cycle's key holds
+    the caller's block addresses)."""
+    case = build_case(2, 4, 1600.0, 5e-3, seed=10)
+    dev = device_case(case)
+    plan = _plan(case, dev, "matrix_free", krylov="graph")
+    plan.solve(dev["b"], solver="gmres", tol=1e-12, restart=8)
+    case2 = build_case(2, 4, 1600.0, 5e-3, seed=11)
+    d2 = oracle_arrays(case2)
+    dev2 = device_case(case2)
+    plan.assemble(dev2["aii"], dev2["aib"], dev2["abi"], dev2["bb_val"])
+    plan.factor("fp64")
+    plan.condense()
+    dq, info = plan.solve(dev2["b"], solver="gmres", tol=1e-12, restart=8)
+    assert info["restarts"] >= 2
+    assert rel(to_np(dq), oracle.solve_sparse(oracle_matrix(d2), d2["b"])) <= 1e-10, info
+    plan.close()
