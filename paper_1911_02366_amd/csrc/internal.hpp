@@ -112,6 +112,9 @@ struct Plan {
   // mode 2: products through the nonzero blocks of A_ib and A_bi and A_ii^-1
   SparseOp sp_ib, sp_bi;
   uint64_t sp_gen = 0;              // count of block-list rebuilds (part of the graph keys)
+  // FP32 copies of A_bb (matrix-free forms) and of its remainder (assembled form)
+  // used inside the Schur products when the factors are FP32
+  float *bb_lo = nullptr, *rem_lo = nullptr;
   uint8_t *d_mask = nullptr;        // [sum (n_i / 5)(n_c / 5)] block mask (one matrix at a time)
   int32_t *d_mask_flag = nullptr;   // [1] masks differ
   int64_t *d_e_offib = nullptr, *d_e_maskoff = nullptr;  // [n_elem] A_ib / A_bi offset, mask offset
@@ -271,7 +274,7 @@ hipError_t launch_gemv_batched(const GemvDesc *d_desc, const RowTile *d_tiles, i
 // with B = A_bb (full = true) or the remainder of A_bb not folded into T_e.
 hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *src0,
                            const int32_t *map0, double c1, const double *x, double c2,
-                           const double *t, double *out);
+                           const double *t, double *out, bool lo = false);
 // T[dst + v nc + w] += A_bb[src][v][w] for the folded blocks
 hipError_t launch_fold_add(const Plan &p, void *t, bool fp32);
 // 5x5 diagonal blocks of S (remainder + element blocks), inverted; point inverse too

@@ -124,11 +124,14 @@ __global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
 // two steps per loop trip.  The pull of element contributions (lanes 0..4) is
 // loaded before the block loop so its dependent loads overlap it, and the 12
 // partial sums of each output row meet through cross-lane adds (lanes l, l+5,
-// ..., l+55 hold row l % 5): no LDS and no workgroup barrier.
+// ..., l+55 hold row l % 5): no LDS and no workgroup barrier.  The block
+// values are FP64, or an FP32 copy inside the products of the FP32 forms
+// (accumulation in FP64 either way).
+template <typename TV>
 __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
     int64_t n_bnodes, double c0, const double *__restrict__ src0, const int32_t *__restrict__ map0,
     double c1, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ src_idx, const double *__restrict__ val,
+    const int32_t *__restrict__ src_idx, const TV *__restrict__ val,
     const double *__restrict__ x, double c2, const int32_t *__restrict__ pull_ptr,
     const int32_t *__restrict__ pull_idx, const double *__restrict__ t, double *__restrict__ out,
     const int32_t *__restrict__ halt) {
@@ -152,13 +155,13 @@ __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
     for (; blk + 12 < b1; blk += 24) {
       const int64_t va = src_idx ? (int64_t)src_idx[blk] : blk;
       const int64_t vb = src_idx ? (int64_t)src_idx[blk + 12] : blk + 12;
-      const double *ra = val + va * 25 + v * 5, *rb = val + vb * 25 + v * 5;
+      const TV *ra = val + va * 25 + v * 5, *rb = val + vb * 25 + v * 5;
       const double *xa = x + (int64_t)col[blk] * 5, *xb = x + (int64_t)col[blk + 12] * 5;
       double ma[5], mb[5], ya[5], yb[5];
 #pragma unroll
       for (int w = 0; w < 5; ++w) {
-        ma[w] = ra[w];
-        mb[w] = rb[w];
+        ma[w] = (double)ra[w];
+        mb[w] = (double)rb[w];
         ya[w] = xa[w];
         yb[w] = xb[w];
       }
@@ -170,10 +173,10 @@ __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
     }
     if (blk < b1) {
       const int64_t va = src_idx ? (int64_t)src_idx[blk] : blk;
-      const double *ra = val + va * 25 + v * 5;
+      const TV *ra = val + va * 25 + v * 5;
       const double *xa = x + (int64_t)col[blk] * 5;
 #pragma unroll
-      for (int w = 0; w < 5; ++w) s += ra[w] * xa[w];
+      for (int w = 0; w < 5; ++w) s += (double)ra[w] * xa[w];
     }
     s += s2;
   }
@@ -669,13 +672,21 @@ hipError_t launch_gemv_batched(const GemvDesc *d_desc, const RowTile *d_tiles, i
 
 hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *src0,
                            const int32_t *map0, double c1, const double *x, double c2,
-                           const double *t, double *out) {
+                           const double *t, double *out, bool lo) {
   const int64_t nb = p.n_bnodes;
   const int grid = (int)((nb + (kThreads / 64) - 1) / (kThreads / 64));
-  hipLaunchKernelGGL(bsr_pull_kernel, dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0,
-                     c1, full ? p.d_bb_rowptr : p.d_rem_rowptr, full ? p.d_bb_col : p.d_rem_col,
-                     nullptr, full ? p.bb_val : p.rem_val, x, c2, p.d_pull_ptr, p.d_pull_idx, t,
-                     out, p.halt);
+  const int64_t *rp = full ? p.d_bb_rowptr : p.d_rem_rowptr;
+  const int32_t *cl = full ? p.d_bb_col : p.d_rem_col;
+  if (lo) {
+    const float *v = full ? p.bb_lo : p.rem_lo;
+    if (c1 != 0.0 && !v && (full ? p.nnzb : p.n_rem) > 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bsr_pull_kernel<float>, dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0, c1,
+                       rp, cl, nullptr, v, x, c2, p.d_pull_ptr, p.d_pull_idx, t, out, p.halt);
+  } else {
+    hipLaunchKernelGGL(bsr_pull_kernel<double>, dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0, c1,
+                       rp, cl, nullptr, full ? p.bb_val : p.rem_val, x, c2, p.d_pull_ptr, p.d_pull_idx, t, out,
+                       p.halt);
+  }
   return hipGetLastError();
 }
 

@@ -284,7 +284,7 @@ scdg_status schur_apply_impl(Plan &p, const double *x, double *y) {
                                 p.w_z2, nullptr, 1.0, 0.0, nullptr, p.stream, p.halt));
     HIP_TRY(launch_bsr5_rows(p.sp_bi.n_rows, p.sp_bi.d_rowptr, p.sp_bi.d_xnode, p.sp_bi.val, fp32(p), p.w_z2,
                              p.sp_bi.d_ybase, p.w_t, p.stream, p.halt));
-    HIP_TRY(launch_bsr_pull(p, true, 0.0, nullptr, nullptr, 1.0, x, -1.0, p.w_t, y));
+    HIP_TRY(launch_bsr_pull(p, true, 0.0, nullptr, nullptr, 1.0, x, -1.0, p.w_t, y, fp32(p)));
     return SCDG_OK;
   }
   if (p.schur_mode == 1) {
@@ -294,13 +294,13 @@ scdg_status schur_apply_impl(Plan &p, const double *x, double *y) {
                                 p.w_z, nullptr, 1.0, 0.0, nullptr, p.stream, p.halt));
     HIP_TRY(launch_gemv_batched(p.d_gv_abi, p.d_rt_abi, p.n_rt_abi, p.max_ni, abi, fp32(p), p.w_z, nullptr,
                                 p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream, p.halt));
-    HIP_TRY(launch_bsr_pull(p, true, 0.0, nullptr, nullptr, 1.0, x, -1.0, p.w_t, y));
+    HIP_TRY(launch_bsr_pull(p, true, 0.0, nullptr, nullptr, 1.0, x, -1.0, p.w_t, y, fp32(p)));
     return SCDG_OK;
   }
   HIP_TRY(launch_gemv_batched(p.d_gv_s, p.d_rt_s, p.n_rt_s, p.max_nc, p.sloc, fp32(p), x, p.d_cmap,
                               p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream, p.halt));
   // S x = A_bb,rem x + sum_e P_e T_e x[C_e],  T_e = folded A_bb blocks - A_bi(e) X_e
-  HIP_TRY(launch_bsr_pull(p, false, 0.0, nullptr, nullptr, 1.0, x, 1.0, p.w_t, y));
+  HIP_TRY(launch_bsr_pull(p, false, 0.0, nullptr, nullptr, 1.0, x, 1.0, p.w_t, y, fp32(p)));
   return SCDG_OK;
 }
 
@@ -834,7 +834,7 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
     dfree(op->d_rowptr); dfree(op->d_xnode); dfree(op->d_ybase); dfree(op->d_src); dfree(op->d_ld);
     dfree(op->val); dfree(op->d_mask_ref);
   }
-  dfree(p.d_mask_flag);
+  dfree(p.d_mask_flag); dfree(p.bb_lo); dfree(p.rem_lo);
   dfree(p.d_mask); dfree(p.d_e_offib); dfree(p.d_e_maskoff); dfree(p.d_e_ri); dfree(p.d_e_rc); dfree(p.w_z2);
   dfree(p.d_fold_dst); dfree(p.d_fold_nc); dfree(p.d_fold_src);
   dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk); dfree(p.rem_val);
@@ -1399,6 +1399,10 @@ scdg_status scdg_condense(scdg_plan *pl) {
     if (!p.mf_dblk) ST_TRY(dalloc(p, &p.mf_dblk, (size_t)p.off_c[E] / kNvar * 25));
     HIP_TRY(launch_mf_diag_blocks(p, abi, fp32(p)));
     HIP_TRY(launch_precond_setup_mf(p));
+    if (fp32(p) && p.nnzb > 0) {
+      if (!p.bb_lo) ST_TRY(dalloc(p, &p.bb_lo, (size_t)p.nnzb * 25));
+      HIP_TRY(launch_cast_f64_to_f32(p.bb_val, p.bb_lo, (size_t)p.nnzb * 25, p.stream));
+    }
     if (p.schur_mode == 2) {
       if (!p.w_z2) ST_TRY(dalloc(p, &p.w_z2, (size_t)std::max<int64_t>(p.n2, 1)));
       ST_TRY(sparse_op_update(p, 0, aib));
@@ -1420,6 +1424,10 @@ scdg_status scdg_condense(scdg_plan *pl) {
   if (p.n_rem > 0) {
     if (!p.rem_val) ST_TRY(dalloc(p, &p.rem_val, (size_t)p.n_rem * 25));
     HIP_TRY(launch_gather_blocks(p.bb_val, p.d_rem_src, p.rem_val, p.n_rem, p.stream));
+    if (fp32(p)) {
+      if (!p.rem_lo) ST_TRY(dalloc(p, &p.rem_lo, (size_t)p.n_rem * 25));
+      HIP_TRY(launch_cast_f64_to_f32(p.rem_val, p.rem_lo, (size_t)p.n_rem * 25, p.stream));
+    }
   }
   HIP_TRY(launch_precond_setup(p, p.sloc, fp32(p)));
   p.state = 3;

@@ -216,3 +216,25 @@ def test_captured_cycle_follows_new_caller_blocks():
     assert info["restarts"] >= 2
     assert rel(to_np(dq), oracle.solve_sparse(oracle_matrix(d2), d2["b"])) <= 1e-10, info
     plan.close()
+
+
+@pytest.mark.parametrize("mode", ["assembled"] + MF)
+def test_fp32_products_match_fp64_to_single_precision(mode):
+    """With FP32 factors every form streams FP32 blocks (T_e and the A_bb
+    remainder; X_e, A_bi and A_bb; or the nonzero blocks, A_ii^-1 and A_bb),
+    accumulating in FP64: the product agrees with the FP64 assembled one to a
+    few FP32 roundings of the blocks."""
+    case = build_case(2, 5, 1600.0, 5e-3, seed=12)
+    dev = device_case(case)
+    ref = _plan(case, dev, "assembled")
+    p32 = _plan(case, dev, mode, precision="fp32")
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(5)
+    x = torch.randn(case.n1, generator=gen, dtype=torch.float64, device=DEV)
+    y64, y32 = ref.schur_apply(x), p32.schur_apply(x)
+    torch.cuda.synchronize()
+    err = rel(to_np(y32), to_np(y64))
+    print(f"{mode}: FP32 product rel. error {err:.2e}", flush=True)
+    assert 1e-9 < err <= 2e-5
+    ref.close()
+    p32.close()
