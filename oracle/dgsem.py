@@ -12,7 +12,12 @@ What it computes, with the paper's notation:
   * g_j = ( - int q grad(phi_j) + oint phi_j q_hat n ) / (J w_j)   (eq. DGSEMsystem:2);
   * f_hat = local Lax-Friedrichs advective flux minus the Bassi-Rebay 1
     viscous flux {{f^nu(q, g)}}; q_hat = {{q}} (Section 2.1);
-  * the nondimensional Navier-Stokes fluxes of Appendix B.
+  * the nondimensional Navier-Stokes fluxes of Appendix B;
+  * A v = (M / dt + dH/dQ) v, the Newton matrix of eq. NewtonLinSys1 applied to
+    a vector, by complex-step differentiation of R (jacobian_apply*): |x| and
+    max are written so that a complex argument carries their derivative
+    (x sign(Re x), comparison of real parts), with the same values as np.abs
+    and np.maximum on real input.
 
 The weak forms above are written as quadrature sums; nothing here uses the
 strong (summation-by-parts) rewrite, so a test that compares against a
@@ -164,13 +169,24 @@ def viscous_flux(q: np.ndarray, grad: np.ndarray, d: int, flow: Flow) -> np.ndar
     return f
 
 
+def _abs(x: np.ndarray) -> np.ndarray:
+    """|x| written as x sign(Re x): the same value for real x, and on a
+    complex-step argument its imaginary part carries sign(x) x' (zero at 0)."""
+    return x * np.sign(x.real)
+
+
+def _larger(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """max(a, b) by the real parts, a at a tie (the same value for real input)."""
+    return np.where(a.real >= b.real, a, b)
+
+
 def lax_friedrichs(q_minus: np.ndarray, q_plus: np.ndarray, d: int, flow: Flow) -> np.ndarray:
     """Rusanov flux through a face of normal +e_d, q_minus on the side the normal leaves."""
     speeds = []
     for q in (q_minus, q_plus):
         rho, vel, p, _, _ = primitive(q, flow)
-        speeds.append(np.abs(vel[..., d]) + np.sqrt(flow.gamma * p / rho))
-    lam = np.maximum(speeds[0], speeds[1])
+        speeds.append(_abs(vel[..., d]) + np.sqrt(flow.gamma * p / rho))
+    lam = _larger(speeds[0], speeds[1])
     return 0.5 * (euler_flux(q_minus, d, flow) + euler_flux(q_plus, d, flow)) \
         - 0.5 * lam[..., None] * (q_plus - q_minus)
 
@@ -210,7 +226,7 @@ def lifted_gradient(q: np.ndarray, grid: Grid) -> np.ndarray:
     jac_face = (grid.h / 2.0) ** 2
     scale = 2.0 / grid.h
     mw = mass(grid)
-    g = np.zeros(q.shape[:-1] + (3, NVAR))
+    g = np.zeros(q.shape[:-1] + (3, NVAR), dtype=q.dtype)
     for d in range(3):
         ql = _line_last(q, d)                                   # [..., P, 5]
         wt = _transverse_weights(w)
@@ -266,6 +282,20 @@ def residual(q: np.ndarray, grid: Grid, flow: Flow, q_s: np.ndarray | None = Non
     return mass(grid)[..., None] * (q - q_s) / dt + h
 
 
+CS_STEP = 1e-30
+
+
+def jacobian_apply(q: np.ndarray, v: np.ndarray, grid: Grid, flow: Flow, dt: float | None = None) -> np.ndarray:
+    """A v = (M / dt + dH/dQ(q)) v, the Newton matrix of eq. NewtonLinSys1 at q
+    applied to v (without dt: dH/dQ(q) v), by complex-step differentiation of
+    the residual: Im R(q + i h v) / h with h = 1e-30, exact to rounding (no
+    subtraction of nearby values)."""
+    qc = q.astype(np.complex128) + 1j * CS_STEP * v
+    if dt is None:
+        return operator_h(qc, grid, flow).imag / CS_STEP
+    return residual(qc, grid, flow, q_s=q, dt=dt).imag / CS_STEP
+
+
 # --------------------------------------------------------------------------
 # Curvilinear elements: high-order mapping x(xi) sampled at the GL nodes and
 # its metric terms.  H keeps the weak form of eq. DGSEMsystem, with the
@@ -319,8 +349,8 @@ def lax_friedrichs_normal(q_minus, q_plus, nvec, flow: Flow):
     speeds = []
     for q in (q_minus, q_plus):
         rho, vel, p, _, _ = primitive(q, flow)
-        speeds.append(np.abs(np.sum(vel * nh, axis=-1)) + np.sqrt(flow.gamma * p / rho))
-    lam = np.maximum(speeds[0], speeds[1])
+        speeds.append(_abs(np.sum(vel * nh, axis=-1)) + np.sqrt(flow.gamma * p / rho))
+    lam = _larger(speeds[0], speeds[1])
     f = sum(nvec[..., d, None] * (euler_flux(q_minus, d, flow) + euler_flux(q_plus, d, flow)) for d in range(3))
     return 0.5 * f - 0.5 * (lam * s)[..., None] * (q_plus - q_minus)
 
@@ -337,7 +367,7 @@ def lifted_gradient_curved(q: np.ndarray, grid: Grid, ja: np.ndarray, jac: np.nd
     dm = lagrange_derivative(x)
     n = grid.order
     wt = _transverse_weights(w)
-    g = np.zeros(q.shape[:-1] + (3, NVAR))
+    g = np.zeros(q.shape[:-1] + (3, NVAR), dtype=q.dtype)
     for i in range(3):
         ql = _line_last(q, i)
         right = _line_last(_neighbour(q, i, +1), i)[..., 0, :]
@@ -390,3 +420,12 @@ def residual_curved(q: np.ndarray, grid: Grid, flow: Flow, ja: np.ndarray, jac: 
     if q_s is None:
         return h
     return curved_mass(grid, jac)[..., None] * (q - q_s) / dt + h
+
+
+def jacobian_apply_curved(q: np.ndarray, v: np.ndarray, grid: Grid, flow: Flow, ja: np.ndarray,
+                          jac: np.ndarray, dt: float | None = None) -> np.ndarray:
+    """A v on curved elements, by the same complex step as jacobian_apply."""
+    qc = q.astype(np.complex128) + 1j * CS_STEP * v
+    if dt is None:
+        return operator_h_curved(qc, grid, flow, ja, jac).imag / CS_STEP
+    return residual_curved(qc, grid, flow, ja, jac, q_s=q, dt=dt).imag / CS_STEP
