@@ -311,6 +311,24 @@ scdg_status scdg_dg_set_geometry(scdg_dg *dg, const double *xyz);
 /* Copy the lifted gradient of the last scdg_dg_residual call into g (device,
  * 15 doubles per node: g[(e P^3 + n) 15 + 5 d + v] = d q_v / d x_d). */
 scdg_status scdg_dg_gradient(scdg_dg *dg, double *g);
+/* The Newton matrix of the implicit step (eq. NewtonLinSys1: A = dR/dQ at q,
+ * the same operator whose element blocks scdg_assemble takes) applied to v:
+ *
+ *     out = A v = M v * inv_dt + dH/dQ(q) v,
+ *
+ * exact to rounding, by forward-mode differentiation of the residual sums on
+ * dual numbers (no difference step).  Where H is not differentiable the
+ * derivative follows the branch the residual takes: |v . n| contributes
+ * sign(v . n) at a nonzero argument and nothing at zero, and the larger
+ * Lax-Friedrichs speed is the left state's at a tie.  Cartesian or curved, as
+ * set by scdg_dg_set_geometry.  q, v and out hold 5 K^3 (N+1)^3 doubles
+ * (device, natural DOF order); out must not alias q or v; inv_dt >= 0 (0 gives
+ * dH/dQ v alone).  The first call allocates a second gradient workspace (15
+ * doubles per node, freed by scdg_dg_destroy); the gradient workspace that
+ * scdg_dg_gradient reads then holds the lifted gradient of q.  Asynchronous
+ * on the object's stream.  SCDG_ERR_ARG for NULL pointers or a negative or
+ * non-finite inv_dt, SCDG_ERR_NOMEM if the workspace cannot be allocated. */
+scdg_status scdg_dg_jacobian_apply(scdg_dg *dg, const double *q, const double *v, double inv_dt, double *out);
 
 /* ------------------------------------------------------------------------
  * Newton iterations of one backward-Euler step replayed from captured HIP

@@ -13,7 +13,14 @@
 //      with Vw[l][a] = -w_a D[a][l] and Fhat = LLF(q_L, q_R) - (f^nu(q_L, g_L) + f^nu(q_R, g_R)) / 2.
 // A face flux is evaluated by both elements with identical arguments, so the
 // scheme stays conservative to the last bit.
+//
+// The Newton matrix of eq. NewtonLinSys1 applied to a vector,
+//     A v = M v / dt + dH/dQ(Q) v,
+// runs the same two launches on dual numbers (forward-mode differentiation):
+// the lifting is linear, so the direction's gradient is the lifting of v, and
+// the residual sums carry value and derivative; only the derivative is kept.
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -32,26 +39,75 @@ struct DgParams {
   double vw[kMaxP][kMaxP];   // -w_a D[a][l]
 };
 
+// Forward-mode dual number: a value and its derivative along one direction
+// of the state.  Evaluating the residual on duals gives dH/dQ v exactly to
+// rounding, with no step size.  |x| passes on sign(x) x' (zero at x = 0) and
+// the larger of the two Lax-Friedrichs speeds passes on the derivative of the
+// one selected (the left one at a tie), the same branches as the residual.
+struct Dual {
+  double v, d;
+  Dual() = default;
+  __device__ Dual(double a) : v(a), d(0.0) {}
+  __device__ Dual(double a, double b) : v(a), d(b) {}
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  const double r = a.v / b.v;
+  return Dual(r, (a.d - r * b.d) / b.v);
+}
+__device__ __forceinline__ Dual &operator+=(Dual &a, Dual b) { return a = a + b; }
+__device__ __forceinline__ Dual &operator-=(Dual &a, Dual b) { return a = a - b; }
+__device__ __forceinline__ bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+__device__ __forceinline__ double vsqrt(double x) { return ::sqrt(x); }
+__device__ __forceinline__ Dual vsqrt(Dual x) {
+  const double r = ::sqrt(x.v);
+  return Dual(r, 0.5 * x.d / r);
+}
+__device__ __forceinline__ double vabs(double x) { return ::fabs(x); }
+__device__ __forceinline__ Dual vabs(Dual x) {
+  const double sg = x.v > 0.0 ? 1.0 : (x.v < 0.0 ? -1.0 : 0.0);
+  return Dual(sg * x.v, sg * x.d);
+}
+// what the volume and surface sums carry: the value, or the derivative alone
+__device__ __forceinline__ double part(double x) { return x; }
+__device__ __forceinline__ double part(Dual x) { return x.d; }
+// element i of a state-like array: the value, or value and direction
+template <class T>
+__device__ __forceinline__ T at(const double *x, const double *dx, int64_t i);
+template <>
+__device__ __forceinline__ double at<double>(const double *x, const double *, int64_t i) {
+  return x[i];
+}
+template <>
+__device__ __forceinline__ Dual at<Dual>(const double *x, const double *dx, int64_t i) {
+  return Dual(x[i], dx[i]);
+}
+
+template <class T>
 struct Prim {
-  double rho, u[3], p, e;  // e: specific internal energy
+  T rho, u[3], p, e;  // e: specific internal energy
 };
 
-__device__ __forceinline__ Prim prim(const double q[5], double gamma) {
-  Prim r;
+template <class T>
+__device__ __forceinline__ Prim<T> prim(const T q[5], double gamma) {
+  Prim<T> r;
   r.rho = q[0];
-  const double ir = 1.0 / q[0];
+  const T ir = 1.0 / q[0];
   r.u[0] = q[1] * ir;
   r.u[1] = q[2] * ir;
   r.u[2] = q[3] * ir;
-  const double ke = 0.5 * (r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+  const T ke = 0.5 * (r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
   r.e = q[4] * ir - ke;
   r.p = (gamma - 1.0) * q[0] * r.e;
   return r;
 }
 
-__device__ void flux_adv(const double q[5], int d, double gamma, double f[5]) {
-  const Prim a = prim(q, gamma);
-  const double vd = a.u[d];
+template <class T>
+__device__ void flux_adv(const T q[5], int d, double gamma, T f[5]) {
+  const Prim<T> a = prim(q, gamma);
+  const T vd = a.u[d];
   f[0] = q[0] * vd;
   f[1] = q[1] * vd;
   f[2] = q[2] * vd;
@@ -61,27 +117,27 @@ __device__ void flux_adv(const double q[5], int d, double gamma, double f[5]) {
 }
 
 // viscous flux f^nu_d(q, g); g[k*5 + v] = d q_v / d x_k
-__device__ void flux_visc(const double q[5], const double g[15], int d, const DgParams &P,
-                          double f[5]) {
-  const Prim a = prim(q, P.gamma);
-  const double ir = 1.0 / q[0];
-  double dv[3][3];   // dv[i][k] = d u_i / d x_k
-  double de[3];
-  const double eE = q[4] * ir;
+template <class T>
+__device__ void flux_visc(const T q[5], const T g[15], int d, const DgParams &P, T f[5]) {
+  const Prim<T> a = prim(q, P.gamma);
+  const T ir = 1.0 / q[0];
+  T dv[3][3];   // dv[i][k] = d u_i / d x_k
+  T de[3];
+  const T eE = q[4] * ir;
   for (int k = 0; k < 3; ++k) {
     for (int i = 0; i < 3; ++i) dv[i][k] = (g[k * 5 + 1 + i] - a.u[i] * g[k * 5]) * ir;
     de[k] = (g[k * 5 + 4] - eE * g[k * 5]) * ir -
             (a.u[0] * dv[0][k] + a.u[1] * dv[1][k] + a.u[2] * dv[2][k]);
   }
-  const double temp = P.gamma * P.mach2 * a.p / q[0];
-  const double mu = (1.0 + P.suth) / (temp + P.suth) * temp * sqrt(temp);
-  const double div = dv[0][0] + dv[1][1] + dv[2][2];
-  double tau[3];
+  const T temp = P.gamma * P.mach2 * a.p / q[0];
+  const T mu = (1.0 + P.suth) / (temp + P.suth) * temp * vsqrt(temp);
+  const T div = dv[0][0] + dv[1][1] + dv[2][2];
+  T tau[3];
   for (int i = 0; i < 3; ++i) {
     tau[i] = mu * (dv[i][d] + dv[d][i]);
     if (i == d) tau[i] -= (2.0 / 3.0) * mu * div;
   }
-  const double heat = mu * P.gamma / P.prandtl * de[d];
+  const T heat = mu * P.gamma / P.prandtl * de[d];
   f[0] = 0.0;
   f[1] = tau[0] * P.inv_re;
   f[2] = tau[1] * P.inv_re;
@@ -90,15 +146,16 @@ __device__ void flux_visc(const double q[5], const double g[15], int d, const Dg
 }
 
 // total numerical flux through a +e_d face: LLF advective minus BR1 viscous
-__device__ void face_flux(const double ql[5], const double gl[15], const double qr[5],
-                          const double gr[15], int d, const DgParams &P, double fh[5]) {
-  double fl[5], fr[5], vl[5], vr[5];
+template <class T>
+__device__ void face_flux(const T ql[5], const T gl[15], const T qr[5], const T gr[15], int d,
+                          const DgParams &P, T fh[5]) {
+  T fl[5], fr[5], vl[5], vr[5];
   flux_adv(ql, d, P.gamma, fl);
   flux_adv(qr, d, P.gamma, fr);
-  const Prim a = prim(ql, P.gamma), b = prim(qr, P.gamma);
-  const double lam_l = fabs(a.u[d]) + sqrt(P.gamma * a.p / a.rho);
-  const double lam_r = fabs(b.u[d]) + sqrt(P.gamma * b.p / b.rho);
-  const double lam = lam_l >= lam_r ? lam_l : lam_r;
+  const Prim<T> a = prim(ql, P.gamma), b = prim(qr, P.gamma);
+  const T lam_l = vabs(a.u[d]) + vsqrt(P.gamma * a.p / a.rho);
+  const T lam_r = vabs(b.u[d]) + vsqrt(P.gamma * b.p / b.rho);
+  const T lam = lam_l >= lam_r ? lam_l : lam_r;
   flux_visc(ql, gl, d, P, vl);
   flux_visc(qr, gr, d, P, vr);
   for (int v = 0; v < 5; ++v)
@@ -108,19 +165,20 @@ __device__ void face_flux(const double ql[5], const double gl[15], const double 
 // total numerical flux along the unnormalized face normal nv (curved faces):
 // sum_d nv_d {{f^a_d}} - lambda |nv| [[q]] / 2 - sum_d nv_d {{f^nu_d}},
 // lambda the larger of |v . nv| / |nv| + c on the two sides
-__device__ void face_flux_normal(const double ql[5], const double gl[15], const double qr[5],
-                                 const double gr[15], const double nv[3], const DgParams &P, double fh[5]) {
+template <class T>
+__device__ void face_flux_normal(const T ql[5], const T gl[15], const T qr[5], const T gr[15],
+                                 const double nv[3], const DgParams &P, T fh[5]) {
   const double sn = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
   const double inv = 1.0 / sn;
-  const Prim a = prim(ql, P.gamma), b = prim(qr, P.gamma);
-  const double un_l = (a.u[0] * nv[0] + a.u[1] * nv[1] + a.u[2] * nv[2]) * inv;
-  const double un_r = (b.u[0] * nv[0] + b.u[1] * nv[1] + b.u[2] * nv[2]) * inv;
-  const double lam_l = fabs(un_l) + sqrt(P.gamma * a.p / a.rho);
-  const double lam_r = fabs(un_r) + sqrt(P.gamma * b.p / b.rho);
-  const double lam = lam_l >= lam_r ? lam_l : lam_r;
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const Prim<T> a = prim(ql, P.gamma), b = prim(qr, P.gamma);
+  const T un_l = (a.u[0] * nv[0] + a.u[1] * nv[1] + a.u[2] * nv[2]) * inv;
+  const T un_r = (b.u[0] * nv[0] + b.u[1] * nv[1] + b.u[2] * nv[2]) * inv;
+  const T lam_l = vabs(un_l) + vsqrt(P.gamma * a.p / a.rho);
+  const T lam_r = vabs(un_r) + vsqrt(P.gamma * b.p / b.rho);
+  const T lam = lam_l >= lam_r ? lam_l : lam_r;
+  T acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int d = 0; d < 3; ++d) {
-    double fl[5], fr[5], vl[5], vr[5];
+    T fl[5], fr[5], vl[5], vr[5];
     flux_adv(ql, d, P.gamma, fl);
     flux_adv(qr, d, P.gamma, fr);
     flux_visc(ql, gl, d, P, vl);
@@ -238,9 +296,16 @@ __global__ __launch_bounds__(512) void lift_curved_kernel(const DgParams *__rest
 // LDS, the weak volume term and the face fluxes along J a^i of this element's
 // face node, mass J w_i w_j w_k:
 //   H = w_i w_j w_k sum_i (1/w_l) [ sum_a Vw[l][a] F^i(a) + [l = N] Fhat_R - [l = 0] Fhat_L ]
+//
+// With T = Dual the same sums give the directional derivative: q and g carry
+// the direction dq and the lifted gradient of dq (the lifting is linear), and
+// r = M inv_dt dq + dH/dQ(q) dq (q_s unused).
+template <class T>
 __global__ __launch_bounds__(512) void residual_curved_kernel(const DgParams *__restrict__ prm,
                                                               const double *__restrict__ q,
+                                                              const double *__restrict__ dq,
                                                               const double *__restrict__ g,
+                                                              const double *__restrict__ dg,
                                                               const double *__restrict__ met,
                                                               const double *__restrict__ q_s, double inv_dt,
                                                               double *__restrict__ r) {
@@ -251,21 +316,22 @@ __global__ __launch_bounds__(512) void residual_curved_kernel(const DgParams *__
   const int e = blockIdx.x;
   const int node = threadIdx.x;
   const bool live = node < p3;
-  double qn[5], gn[15], mn[10];
+  T qn[5], gn[15];
+  double mn[10];
   if (live) {
     const int64_t id = (int64_t)e * p3 + node;
-    for (int v = 0; v < 5; ++v) qn[v] = q[id * 5 + v];
-    for (int t = 0; t < 15; ++t) gn[t] = g[id * 15 + t];
+    for (int v = 0; v < 5; ++v) qn[v] = at<T>(q, dq, id * 5 + v);
+    for (int t = 0; t < 15; ++t) gn[t] = at<T>(g, dg, id * 15 + t);
     for (int t = 0; t < 10; ++t) mn[t] = met[id * 10 + t];
     double ft[3][5];
     for (int i = 0; i < 3; ++i)
       for (int v = 0; v < 5; ++v) ft[i][v] = 0.0;
     for (int d = 0; d < 3; ++d) {
-      double fa[5], fv[5];
+      T fa[5], fv[5];
       flux_adv(qn, d, P.gamma, fa);
       flux_visc(qn, gn, d, P, fv);
       for (int i = 0; i < 3; ++i)
-        for (int v = 0; v < 5; ++v) ft[i][v] += mn[3 * i + d] * (fa[v] - fv[v]);
+        for (int v = 0; v < 5; ++v) ft[i][v] += mn[3 * i + d] * part(fa[v] - fv[v]);
     }
     for (int i = 0; i < 3; ++i)
       for (int v = 0; v < 5; ++v) fs[(i * p3 + node) * 5 + v] = ft[i][v];
@@ -285,30 +351,42 @@ __global__ __launch_bounds__(512) void residual_curved_kernel(const DgParams *__
     const double nv[3] = {mn[3 * i], mn[3 * i + 1], mn[3 * i + 2]};
     if (l == n) {
       const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, i, 1) * p3 + node_with(node, p, i, 0);
-      double fh[5];
-      face_flux_normal(qn, gn, q + nb * 5, g + nb * 15, nv, P, fh);
-      for (int v = 0; v < 5; ++v) rd[v] += fh[v];
+      T qb[5], gb[15], fh[5];
+      for (int v = 0; v < 5; ++v) qb[v] = at<T>(q, dq, nb * 5 + v);
+      for (int t = 0; t < 15; ++t) gb[t] = at<T>(g, dg, nb * 15 + t);
+      face_flux_normal(qn, gn, qb, gb, nv, P, fh);
+      for (int v = 0; v < 5; ++v) rd[v] += part(fh[v]);
     }
     if (l == 0) {
       const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, i, -1) * p3 + node_with(node, p, i, n);
-      double fh[5];
-      face_flux_normal(q + nb * 5, g + nb * 15, qn, gn, nv, P, fh);
-      for (int v = 0; v < 5; ++v) rd[v] -= fh[v];
+      T qb[5], gb[15], fh[5];
+      for (int v = 0; v < 5; ++v) qb[v] = at<T>(q, dq, nb * 5 + v);
+      for (int t = 0; t < 15; ++t) gb[t] = at<T>(g, dg, nb * 15 + t);
+      face_flux_normal(qb, gb, qn, gn, nv, P, fh);
+      for (int v = 0; v < 5; ++v) rd[v] -= part(fh[v]);
     }
     for (int v = 0; v < 5; ++v) h[v] += rd[v] / P.w[l];
   }
   const double w3 = P.w[c[0]] * P.w[c[1]] * P.w[c[2]];
   const double m = mn[9] * w3;
-  double *re = r + ((int64_t)e * p3 + node) * 5;
+  const int64_t id = (int64_t)e * p3 + node;
+  double *re = r + id * 5;
   for (int v = 0; v < 5; ++v) {
     double val = w3 * h[v];
-    if (q_s) val += m * inv_dt * (qn[v] - q_s[((int64_t)e * p3 + node) * 5 + v]);
+    if constexpr (std::is_same<T, Dual>::value) {
+      val += m * inv_dt * dq[id * 5 + v];
+    } else {
+      if (q_s) val += m * inv_dt * (qn[v] - q_s[id * 5 + v]);
+    }
     re[v] = val;
   }
 }
 
+// With T = Dual: r = M inv_dt dq + dH/dQ(q) dq, dg the lifted gradient of dq.
+template <class T>
 __global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restrict__ prm, const double *__restrict__ q,
-                                const double *__restrict__ g, const double *__restrict__ q_s,
+                                const double *__restrict__ dq, const double *__restrict__ g,
+                                const double *__restrict__ dg, const double *__restrict__ q_s,
                                 double inv_dt, double *__restrict__ r) {
   __shared__ DgParams P;
   extern __shared__ double fs[];   // [3][p3][5] volume fluxes
@@ -317,17 +395,16 @@ __global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restric
   const int e = blockIdx.x;
   const int node = threadIdx.x;
   const bool live = node < p3;
-  double qn[5], gn[15];
+  T qn[5], gn[15];
   if (live) {
-    const double *qe = q + ((int64_t)e * p3 + node) * 5;
-    const double *ge = g + ((int64_t)e * p3 + node) * 15;
-    for (int v = 0; v < 5; ++v) qn[v] = qe[v];
-    for (int t = 0; t < 15; ++t) gn[t] = ge[t];
+    const int64_t id = (int64_t)e * p3 + node;
+    for (int v = 0; v < 5; ++v) qn[v] = at<T>(q, dq, id * 5 + v);
+    for (int t = 0; t < 15; ++t) gn[t] = at<T>(g, dg, id * 15 + t);
     for (int d = 0; d < 3; ++d) {
-      double fa[5], fv[5];
+      T fa[5], fv[5];
       flux_adv(qn, d, P.gamma, fa);
       flux_visc(qn, gn, d, P, fv);
-      for (int v = 0; v < 5; ++v) fs[(d * p3 + node) * 5 + v] = fa[v] - fv[v];
+      for (int v = 0; v < 5; ++v) fs[(d * p3 + node) * 5 + v] = part(fa[v] - fv[v]);
     }
   }
   __syncthreads();
@@ -344,23 +421,32 @@ __global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restric
     }
     if (l == n) {
       const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, d, 1) * p3 + node_with(node, p, d, 0);
-      double fh[5];
-      face_flux(qn, gn, q + nb * 5, g + nb * 15, d, P, fh);
-      for (int v = 0; v < 5; ++v) rd[v] += fh[v];
+      T qb[5], gb[15], fh[5];
+      for (int v = 0; v < 5; ++v) qb[v] = at<T>(q, dq, nb * 5 + v);
+      for (int t = 0; t < 15; ++t) gb[t] = at<T>(g, dg, nb * 15 + t);
+      face_flux(qn, gn, qb, gb, d, P, fh);
+      for (int v = 0; v < 5; ++v) rd[v] += part(fh[v]);
     }
     if (l == 0) {
       const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, d, -1) * p3 + node_with(node, p, d, n);
-      double fh[5];
-      face_flux(q + nb * 5, g + nb * 15, qn, gn, d, P, fh);
-      for (int v = 0; v < 5; ++v) rd[v] -= fh[v];
+      T qb[5], gb[15], fh[5];
+      for (int v = 0; v < 5; ++v) qb[v] = at<T>(q, dq, nb * 5 + v);
+      for (int t = 0; t < 15; ++t) gb[t] = at<T>(g, dg, nb * 15 + t);
+      face_flux(qb, gb, qn, gn, d, P, fh);
+      for (int v = 0; v < 5; ++v) rd[v] -= part(fh[v]);
     }
     for (int v = 0; v < 5; ++v) h[v] += rd[v] / P.w[l];
   }
   const double m = P.jac * P.w[c[0]] * P.w[c[1]] * P.w[c[2]];
-  double *re = r + ((int64_t)e * p3 + node) * 5;
+  const int64_t id = (int64_t)e * p3 + node;
+  double *re = r + id * 5;
   for (int v = 0; v < 5; ++v) {
     double val = m * P.s * h[v];
-    if (q_s) val += m * inv_dt * (qn[v] - q_s[((int64_t)e * p3 + node) * 5 + v]);
+    if constexpr (std::is_same<T, Dual>::value) {
+      val += m * inv_dt * dq[id * 5 + v];
+    } else {
+      if (q_s) val += m * inv_dt * (qn[v] - q_s[id * 5 + v]);
+    }
     re[v] = val;
   }
 }
@@ -479,6 +565,7 @@ struct DgContext {
   DgParams host;
   DgParams *dev = nullptr;
   double *g = nullptr;
+  double *gd = nullptr;    // lifted gradient of a direction (allocated by the first Newton-matrix product)
   double *met = nullptr;   // curved elements: 10 doubles per node (NULL: Cartesian cubes)
   int64_t n_nodes = 0;
   hipStream_t stream = nullptr;
@@ -504,13 +591,38 @@ hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, doubl
   if (c.met) {
     hipLaunchKernelGGL(lift_curved_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 10 * p3, s, c.dev, q,
                        c.met, c.g);
-    hipLaunchKernelGGL(residual_curved_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev,
-                       q, c.g, c.met, q_s, inv_dt, r);
+    hipLaunchKernelGGL(residual_curved_kernel<double>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
+                       c.dev, q, nullptr, c.g, nullptr, c.met, q_s, inv_dt, r);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g);
-  hipLaunchKernelGGL(residual_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
-                     c.g, q_s, inv_dt, r);
+  hipLaunchKernelGGL(residual_kernel<double>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
+                     nullptr, c.g, nullptr, q_s, inv_dt, r);
+  return hipGetLastError();
+}
+
+// out = M inv_dt v + dH/dQ(q) v: the lifted gradients of q and of v (the
+// lifting is linear), then the residual sums on dual numbers (value q,
+// direction v).  c.gd must hold 15 doubles per node.
+hipError_t dg_jacobian_apply_on(scdg_dg *dg, const double *q, const double *v, double inv_dt, double *out,
+                                hipStream_t s) {
+  auto &c = dg->c;
+  const int p3 = c.host.p * c.host.p * c.host.p;
+  const int n_elem = c.host.k_elem * c.host.k_elem * c.host.k_elem;
+  const int threads = ((p3 + 63) / 64) * 64;
+  if (c.met) {
+    hipLaunchKernelGGL(lift_curved_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 10 * p3, s, c.dev, q,
+                       c.met, c.g);
+    hipLaunchKernelGGL(lift_curved_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 10 * p3, s, c.dev, v,
+                       c.met, c.gd);
+    hipLaunchKernelGGL(residual_curved_kernel<Dual>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
+                       c.dev, q, v, c.g, c.gd, c.met, nullptr, inv_dt, out);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g);
+  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, v, c.gd);
+  hipLaunchKernelGGL(residual_kernel<Dual>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
+                     v, c.g, c.gd, nullptr, inv_dt, out);
   return hipGetLastError();
 }
 
@@ -561,6 +673,7 @@ scdg_status scdg_dg_destroy(scdg_dg *dg) {
   (void)hipStreamSynchronize(dg->c.stream);
   if (dg->c.dev) (void)hipFree(dg->c.dev);
   if (dg->c.g) (void)hipFree(dg->c.g);
+  if (dg->c.gd) (void)hipFree(dg->c.gd);
   if (dg->c.met) (void)hipFree(dg->c.met);
   delete dg;
   return SCDG_OK;
@@ -570,6 +683,16 @@ scdg_status scdg_dg_residual(scdg_dg *dg, const double *q, const double *q_s, do
                              double *r) {
   if (!dg || !q || !r) return SCDG_ERR_ARG;
   return scdg::dg_residual_on(dg, q, q_s, inv_dt, r, dg->c.stream) == hipSuccess ? SCDG_OK : SCDG_ERR_HIP;
+}
+
+scdg_status scdg_dg_jacobian_apply(scdg_dg *dg, const double *q, const double *v, double inv_dt, double *out) {
+  if (!dg || !q || !v || !out || !(inv_dt >= 0.0) || !std::isfinite(inv_dt)) return SCDG_ERR_ARG;
+  auto &c = dg->c;
+  if (!c.gd && hipMalloc(&c.gd, sizeof(double) * 15 * c.n_nodes) != hipSuccess) {
+    c.gd = nullptr;
+    return SCDG_ERR_NOMEM;
+  }
+  return scdg::dg_jacobian_apply_on(dg, q, v, inv_dt, out, c.stream) == hipSuccess ? SCDG_OK : SCDG_ERR_HIP;
 }
 
 scdg_status scdg_dg_set_geometry(scdg_dg *dg, const double *xyz) {

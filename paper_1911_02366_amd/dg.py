@@ -49,6 +49,22 @@ class DgResidual:
             raise L.ScdgError(st, "scdg_dg_residual")
         return out
 
+    def jacobian_apply(self, q: torch.Tensor, v: torch.Tensor, inv_dt: float = 0.0,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+        """A v = M v inv_dt + dH/dQ(q) v, the Newton matrix at q applied to v
+        (scdg_dg_jacobian_apply)."""
+        self._check(q, "q")
+        self._check(v, "v")
+        if out is None:
+            out = torch.empty(self.n_dof, dtype=torch.float64, device=q.device)
+        self._check(out, "out")
+        if out.data_ptr() in (q.data_ptr(), v.data_ptr()):
+            raise ValueError("out must not alias q or v")
+        st = self.lib.scdg_dg_jacobian_apply(self.handle, _ptr(q), _ptr(v), float(inv_dt), _ptr(out))
+        if st != L.SCDG_OK:
+            raise L.ScdgError(st, "scdg_dg_jacobian_apply")
+        return out
+
     def set_geometry(self, xyz=None):
         """Curved elements from the node positions (numpy, 3 per node in the natural
         node order, e.g. [K, K, K, P, P, P, 3]); None returns to Cartesian cubes."""
