@@ -80,6 +80,50 @@ def roofline_entry(name, work, phase, prec):
             "algorithmic_bytes_per_launch": work["bytes"]}
 
 
+def dg_operator_timing(case, calls: int = 20) -> dict:
+    """Event-timed device residual R(Q) and Newton-matrix product A v
+    (scdg_dg_residual, scdg_dg_jacobian_apply: two lifts and the residual sums
+    on dual numbers) at the state of the step, with a seeded direction.  Both
+    run FP64 flux arithmetic per node (every face flux evaluated by both
+    neighbours), so they are bound by the vector ALUs, not HBM: the bytes below
+    count one read of each input, one write of each output and the gradient
+    workspace written once and read once."""
+    import torch
+    from paper_1911_02366_amd import DgResidual
+    mesh, prm = case.mesh, case.prm
+    q = case.q_state.to("cuda").reshape(-1).contiguous()
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    v = torch.randn(q.shape, dtype=torch.float64, device="cuda", generator=gen)
+    out = torch.empty_like(q)
+    dg = DgResidual(mesh.k_elem, mesh.order, mach=prm.mach, reynolds=prm.reynolds)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(calls):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / calls
+
+    ms_r = timed(lambda: dg.residual(q, q, 1.0 / case.dt, out=out))
+    ms_a = timed(lambda: dg.jacobian_apply(q, v, 1.0 / case.dt, out=out))
+    dg.close()
+    nodes = q.numel() // 5
+    bytes_r = nodes * 8 * (5 + 15 + 15 + 5 + 5 + 5)          # q (lift), g w/r, q, q_s, r
+    bytes_a = nodes * 8 * (10 + 30 + 30 + 10 + 5)            # q, v (lifts), g and gd w/r, q, v, out
+    return {"calls": calls, "residual_ms": round(ms_r, 4), "jacobian_apply_ms": round(ms_a, 4),
+            "jacobian_apply_over_residual": round(ms_a / ms_r, 3),
+            "residual_dof_s": round(q.numel() / (ms_r / 1e3), 1),
+            "jacobian_apply_dof_s": round(q.numel() / (ms_a / 1e3), 1),
+            "bound": "alu",
+            "hbm_gbs": {"residual": round(bytes_r / (ms_r / 1e3) / 1e9, 1),
+                        "jacobian_apply": round(bytes_a / (ms_a / 1e3) / 1e9, 1)}}
+
+
 def cpu_baseline(max_seconds: float) -> dict:
     """The FP64 oracle on a bounded sample, the 2^3-element instance of the same
     order-5 workload: the uncondensed brute force (assemble A, LAPACK dense LU)
@@ -405,6 +449,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the measured MFMA / HBM ceilings")
+    ap.add_argument("--no-dg-timing", action="store_true",
+                    help="skip the timing of the device residual and Newton-matrix product")
     ap.add_argument("--fp32-inner-tol", type=float, default=1e-4,
                     help="GMRES tolerance inside each refinement sweep of the FP32 variant")
     ap.add_argument("--fp32-sweep", type=float, nargs="*", default=[],
@@ -655,6 +701,8 @@ def main() -> int:
     }
     if worst > 1e-8:
         out["warning"] = "full-system residual above 1e-8"
+    if not args.no_dg_timing and args.workload not in MIXED_WORKLOADS:
+        out["dg_operators"] = dg_operator_timing(case)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     plan.close()
