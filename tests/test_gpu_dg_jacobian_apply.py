@@ -106,3 +106,27 @@ def test_linear_in_the_direction_and_zero_direction():
     with pytest.raises(ValueError):
         dg.jacobian_apply(qd, vd, 1.0, out=vd)
     dg.close()
+
+
+@pytest.mark.parametrize("curved", [False, True])
+def test_plan_blocks_are_the_derivative_of_the_device_residual(curved):
+    """The element blocks a plan condenses (here from the generator, applied by
+    scdg_residual with B = 0, r = -A v) and the device product agree: the
+    linear solve and the nonlinear residual of a Newton step see one matrix."""
+    from gpu_common import device_case, make_plan
+    from workload.cases import build_case, build_curved_case
+    dt = 1e-2
+    case = build_curved_case(2, 3, 100.0, dt, seed=3, kind="skew") if curved else build_case(2, 3, 100.0, dt, seed=1)
+    print(f"plan blocks vs dg product, curved={curved}", flush=True)
+    plan = make_plan(case, device_case(case))
+    q = case.q_state.to(DEV).reshape(-1).contiguous()
+    v = torch.tensor(np.random.default_rng(21).standard_normal(case.n_dof), device=DEV)
+    r = torch.empty_like(v)
+    plan.residual(torch.zeros_like(v), v, r)
+    dg = DgResidual(case.mesh.k_elem, case.mesh.order, mach=case.prm.mach, reynolds=case.prm.reynolds)
+    if curved:
+        dg.set_geometry(case.xyz)
+    av = dg.jacobian_apply(q, v, 1.0 / dt)
+    assert _rel(to_np(av), -to_np(r)) <= 1e-11
+    dg.close()
+    plan.close()
