@@ -359,7 +359,8 @@ scdg_status scdg_dg_jacobian_apply(scdg_dg *dg, const double *q, const double *v
  * natural DOF order, which must match the dg object's size.  If the starting
  * state has a larger residual than Q_s it is replaced by Q_s
  * (info.start_rejected).  The graphs are captured on the first call and reused
- * while q, q_s, dg, inv_dt, the options and the plan's buffers stay the same;
+ * while q, q_s, dg, inv_dt, the options, the plan's buffers and the dg
+ * object's geometry (any scdg_dg_set_geometry call forces a new capture) stay the same;
  * keep them fixed across steps to avoid a new capture.  The call synchronizes
  * the plan's stream.  Errors: SCDG_ERR_STATE before scdg_condense,
  * SCDG_ERR_ARG for sizes that differ or restart > 63, SCDG_ERR_NONFINITE when

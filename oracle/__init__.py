@@ -11,7 +11,9 @@ What it computes (each function cites the passage it follows):
     and the uncondensed solution of A dQ = B (eq. NewtonLinSys1) by LAPACK
     dense LU or SuperLU;
   * the Schur-complement quantities of eq. SC_step1 / SC_step2 written out as
-    their definitions, per element, with numpy;
+    their definitions, per element, with numpy, and the paper's condensed CPU
+    route at full size (LAPACK LU of every A_ii, element Schur blocks, GMRES
+    with point Jacobi on S, back-substitution) for timing and large parity runs;
   * (module `oracle.dgsem`) the nonlinear residual R(Q) = M (Q - Q_s)/dt + H(Q)
     of the backward-Euler GL-DGSEM step, with H from the weak form of
     eq. DGSEMsystem evaluated as Gauss-Lobatto quadrature sums;
@@ -24,4 +26,6 @@ from .linalg import (  # noqa: F401
     NodeSets, node_sets, dof_maps, assemble_global, solve_dense, solve_sparse,
     element_inverse, element_schur, condensed_matrix_dense, condensed_rhs,
     back_substitute, full_residual, gmres_mgs, condensed_solve_dense, element_interior_residual,
+    full_residual_blocks, CondensedCPU, condense_cpu, schur_matvec_cpu, condensed_gmres_solve,
+    solve_gmres_element_jacobi,
 )

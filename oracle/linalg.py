@@ -182,16 +182,20 @@ def full_residual(a, x: np.ndarray, b: np.ndarray) -> np.ndarray:
 
 
 def gmres_mgs(matvec, b: np.ndarray, tol: float, restart: int = 30, max_iter: int = 2000,
-              precond_diag: np.ndarray | None = None, x0: np.ndarray | None = None):
+              precond_diag: np.ndarray | None = None, x0: np.ndarray | None = None,
+              precond=None):
     """Restarted GMRES(m), modified Gram-Schmidt, Givens rotations, optional right
-    point-Jacobi preconditioner; stops when ||b - A x|| <= tol ||b||.
+    preconditioner M^-1 (point Jacobi from precond_diag, or any linear map
+    `precond`); stops when ||b - A x|| <= tol ||b||.
 
     The paper's Krylov runs use GMRES with a point-Jacobi preconditioner (Section 4).
     Returns (x, iterations, final relative residual).
     """
     n = b.shape[0]
     x = np.zeros(n) if x0 is None else x0.astype(np.float64).copy()
-    dinv = np.ones(n) if precond_diag is None else 1.0 / precond_diag
+    if precond is None:
+        dinv = np.ones(n) if precond_diag is None else 1.0 / precond_diag
+        precond = lambda v: dinv * v
     bnorm = np.linalg.norm(b)
     if bnorm == 0.0:
         return np.zeros(n), 0, 0.0
@@ -209,7 +213,7 @@ def gmres_mgs(matvec, b: np.ndarray, tol: float, restart: int = 30, max_iter: in
         v[0] = r / beta
         j_used = 0
         for j in range(restart):
-            w = matvec(dinv * v[j])
+            w = matvec(precond(v[j]))
             for i in range(j + 1):
                 h[i, j] = np.dot(v[i], w)
                 w = w - h[i, j] * v[i]
@@ -231,7 +235,7 @@ def gmres_mgs(matvec, b: np.ndarray, tol: float, restart: int = 30, max_iter: in
             if abs(g[j + 1]) <= tol * bnorm or it >= max_iter:
                 break
         y = sla.solve_triangular(h[:j_used, :j_used], g[:j_used])
-        x = x + dinv * (v[:j_used].T @ y)
+        x = x + precond(v[:j_used].T @ y)
         r = b - matvec(x)
         beta = np.linalg.norm(r)
     return x, it, beta / bnorm
@@ -244,3 +248,114 @@ def element_interior_residual(e: int, order, c_ptr, c_node, aii_e, aib_e, b: np.
     qb = dq[bnode_dofs.reshape(-1)]
     idx = _b_index(None, e, c_ptr, c_node)
     return b[interior_dofs[e]] - aii_e @ dq[interior_dofs[e]] - aib_e @ qb[idx]
+
+
+def full_residual_blocks(order, c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi,
+                         b: np.ndarray, dq: np.ndarray) -> np.ndarray:
+    """r = B - A dQ on the full system, formed element by element from the blocks
+    (no global matrix): interior rows B_i - A_ii dQ_i - A_ib dQ_b[C_e], boundary rows
+    B_b - A_bb dQ_b - sum_e P_e A_bi(e) dQ_i(e) (eq. StaticDGSEM_QbQiSystem, row-column
+    subscripts).  Returns r in the natural DOF order."""
+    interior_dofs, bnode_dofs = dof_maps(order)
+    n_b = len(bb_rowptr) - 1
+    flat_b = bnode_dofs.reshape(-1)
+    qb = dq[flat_b]
+    abb = sp.bsr_matrix((np.asarray(bb_val).reshape(-1, NVAR, NVAR), np.asarray(bb_col),
+                         np.asarray(bb_rowptr)), shape=(NVAR * n_b, NVAR * n_b))
+    rb = b[flat_b] - abb @ qb
+    r = np.empty_like(b)
+    for e in range(len(order)):
+        ii = interior_dofs[e]
+        idx = _b_index(None, e, c_ptr, c_node)
+        r[ii] = b[ii] - aii[e] @ dq[ii] - aib[e] @ qb[idx]
+        rb[idx] -= abi[e] @ dq[ii]
+    r[flat_b] = rb
+    return r
+
+
+@dataclass
+class CondensedCPU:
+    """The once-per-Jacobian products of the condensed route, kept for the per-step solves."""
+    order: np.ndarray
+    c_ptr: np.ndarray
+    c_node: np.ndarray
+    lu: list            # LAPACK (lu, piv) of every A_ii(e)
+    aib: np.ndarray
+    abi: np.ndarray
+    schur: np.ndarray   # [E, n_c, n_c] A_bi(e) A_ii(e)^-1 A_ib(e)
+    abb: sp.bsr_matrix  # A_bb over the boundary nodes
+    cidx: np.ndarray    # [E, n_c] positions of C_e's DOFs in the boundary vector
+    diag: np.ndarray    # diag(S), the point-Jacobi preconditioner
+    n1: int
+
+
+def condense_cpu(order, c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi) -> CondensedCPU:
+    """The paper's once-per-Jacobian condensation on the CPU (Section 3.2; the
+    'matrix condensation operations' of Table Advantages): an LU factorization
+    (LAPACK getrf) of every A_ii(e), the element Schur blocks
+    A_bi(e) A_ii(e)^-1 A_ib(e), and S = A_bb - sum_e P_e (A_bi A_ii^-1 A_ib)(e) P_e^T
+    kept as A_bb (BSR) plus the element blocks, with diag(S) for point Jacobi.
+    Uniform element sizes (one order per mesh)."""
+    n_e = len(order)
+    n_b = len(bb_rowptr) - 1
+    lus = [sla.lu_factor(aii[e]) for e in range(n_e)]
+    schur = np.empty((n_e, abi.shape[1], abi.shape[1]))
+    for e in range(n_e):
+        schur[e] = abi[e] @ sla.lu_solve(lus[e], aib[e])
+    abb = sp.bsr_matrix((np.asarray(bb_val).reshape(-1, NVAR, NVAR), np.asarray(bb_col),
+                         np.asarray(bb_rowptr)), shape=(NVAR * n_b, NVAR * n_b))
+    cidx = np.stack([_b_index(None, e, c_ptr, c_node) for e in range(n_e)])
+    diag = abb.diagonal() - np.bincount(cidx.reshape(-1),
+                                        weights=np.diagonal(schur, axis1=1, axis2=2).reshape(-1),
+                                        minlength=NVAR * n_b)
+    return CondensedCPU(np.asarray(order), np.asarray(c_ptr), np.asarray(c_node), lus, aib, abi,
+                        schur, abb, cidx, diag, NVAR * n_b)
+
+
+def schur_matvec_cpu(c: CondensedCPU, x: np.ndarray) -> np.ndarray:
+    """S x = A_bb x - sum_e P_e (A_bi A_ii^-1 A_ib)(e) x[C_e] (eq. SC_step1)."""
+    z = np.matmul(c.schur, x[c.cidx][..., None])[..., 0]
+    return c.abb @ x - np.bincount(c.cidx.reshape(-1), weights=z.reshape(-1), minlength=c.n1)
+
+
+def condensed_gmres_solve(c: CondensedCPU, b: np.ndarray, tol: float, restart: int = 30,
+                          max_iter: int = 3000, x0_b: np.ndarray | None = None):
+    """Per-step phase of the condensed route (Table Advantages2): the condensed
+    right-hand side b_S = B_b - sum_e P_e A_bi A_ii^-1 B_i (eq. SC_step1), GMRES(m)
+    with right point-Jacobi on S (the paper's Krylov set-up, Section 4), and the
+    back-substitution Q_i = A_ii^-1 (B_i - A_ib Q_b[C_e]) (eq. SC_step2).
+    Returns (dQ in natural order, GMRES iterations, relative residual on S)."""
+    interior_dofs, bnode_dofs = dof_maps(c.order)
+    flat_b = bnode_dofs.reshape(-1)
+    bs = b[flat_b].copy()
+    for e in range(len(c.order)):
+        y = c.abi[e] @ sla.lu_solve(c.lu[e], b[interior_dofs[e]])
+        np.add.at(bs, c.cidx[e], -y)
+    qb, it, relres = gmres_mgs(lambda v: schur_matvec_cpu(c, v), bs, tol=tol, restart=restart,
+                               max_iter=max_iter, precond_diag=c.diag, x0=x0_b)
+    dq = np.zeros_like(b)
+    dq[flat_b] = qb
+    for e in range(len(c.order)):
+        ii = interior_dofs[e]
+        dq[ii] = sla.lu_solve(c.lu[e], b[ii] - c.aib[e] @ qb[c.cidx[e]])
+    return dq, it, relres
+
+
+def solve_gmres_element_jacobi(a, b: np.ndarray, order, tol: float, restart: int = 30,
+                               max_iter: int = 3000):
+    """Uncondensed iterative solve of A dQ = B (eq. NewtonLinSys1): GMRES(m) on the
+    global matrix with right element-block Jacobi, M = the diagonal block of every
+    element (all 5 (N_e + 1)^3 DOFs of e, contiguous in the natural order), each
+    factorized by LAPACK LU.  Returns (dQ, iterations, relative residual)."""
+    a = sp.csr_matrix(a)
+    sizes = [NVAR * (int(n) + 1) ** 3 for n in order]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    lus = [sla.lu_factor(a[offs[e]:offs[e + 1], offs[e]:offs[e + 1]].toarray()) for e in range(len(order))]
+
+    def minv(v):
+        out = np.empty_like(v)
+        for e in range(len(order)):
+            out[offs[e]:offs[e + 1]] = sla.lu_solve(lus[e], v[offs[e]:offs[e + 1]])
+        return out
+
+    return gmres_mgs(lambda v: a @ v, b, tol=tol, restart=restart, max_iter=max_iter, precond=minv)

@@ -41,13 +41,15 @@ struct GemvDesc {
 // arguments and every device pointer its kernels read or write.
 struct NewtonKey {
   int m = 0, cycles = 0, pmode = -1, smode = 0;
-  uint64_t sp_gen = 0;
+  uint64_t sp_gen = 0, dg_gen = 0;
   bool fp32 = false;
   double inv_dt = 0, eta_c = 0, lin_tol = 0, eta_max = 0;
   const void *q = nullptr, *q_s = nullptr, *dg = nullptr;
+  const void *dg_g = nullptr, *dg_met = nullptr, *dg_params = nullptr;
   const void *ptr[23] = {};
   bool operator==(const NewtonKey &o) const {
     if (m != o.m || cycles != o.cycles || pmode != o.pmode || smode != o.smode || sp_gen != o.sp_gen ||
+        dg_gen != o.dg_gen || dg_g != o.dg_g || dg_met != o.dg_met || dg_params != o.dg_params ||
         fp32 != o.fp32 ||
         inv_dt != o.inv_dt ||
         eta_c != o.eta_c || lin_tol != o.lin_tol || eta_max != o.eta_max || q != o.q || q_s != o.q_s ||
@@ -334,6 +336,7 @@ hipError_t launch_newton_gmres_restart(const double *stat, int m, double *g, int
 hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, double inv_dt, double *r,
                           hipStream_t s);
 int64_t dg_dof_count(const scdg_dg *dg);
+void dg_graph_state(const scdg_dg *dg, uint64_t *gen, const void **g, const void **met, const void **params);
 
 // dense path
 hipError_t launch_dense_assemble(const Plan &p, double *s_dense);

@@ -567,6 +567,7 @@ struct DgContext {
   double *g = nullptr;
   double *gd = nullptr;    // lifted gradient of a direction (allocated by the first Newton-matrix product)
   double *met = nullptr;   // curved elements: 10 doubles per node (NULL: Cartesian cubes)
+  uint64_t geo_gen = 0;    // bumped by every geometry change: captured graphs keyed on it recapture
   int64_t n_nodes = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
@@ -627,6 +628,16 @@ hipError_t dg_jacobian_apply_on(scdg_dg *dg, const double *q, const double *v, d
 }
 
 int64_t dg_dof_count(const scdg_dg *dg) { return 5 * dg->c.n_nodes; }
+
+// What a captured residual launch depends on beyond the caller's vectors: the
+// geometry generation (which kernels run, and on which metric buffer) and the
+// object's own buffers.
+void dg_graph_state(const scdg_dg *dg, uint64_t *gen, const void **g, const void **met, const void **params) {
+  *gen = dg->c.geo_gen;
+  *g = dg->c.g;
+  *met = dg->c.met;
+  *params = dg->c.dev;
+}
 
 }  // namespace scdg
 
@@ -702,6 +713,7 @@ scdg_status scdg_dg_set_geometry(scdg_dg *dg, const double *xyz) {
   if (!xyz) {
     if (c.met) (void)hipFree(c.met);
     c.met = nullptr;
+    ++c.geo_gen;
     return SCDG_OK;
   }
   const int64_t n_elem = (int64_t)c.host.k_elem * c.host.k_elem * c.host.k_elem;
@@ -710,6 +722,7 @@ scdg_status scdg_dg_set_geometry(scdg_dg *dg, const double *xyz) {
     c.last_error = "node positions give a non-positive or non-finite Jacobian";
     return SCDG_ERR_ARG;
   }
+  ++c.geo_gen;
   if (!c.met && hipMalloc(&c.met, sizeof(double) * met.size()) != hipSuccess) {
     c.met = nullptr;
     return SCDG_ERR_NOMEM;

@@ -632,6 +632,7 @@ NewtonKey newton_key(const Plan &p, scdg_dg *dg, const double *q_s, const double
   k.q = q;
   k.q_s = q_s;
   k.dg = dg;
+  dg_graph_state(dg, &k.dg_gen, &k.dg_g, &k.dg_met, &k.dg_params);
   const void *ptrs[23] = {p.ainv, p.xmat, p.sloc,  p.abi,  p.abi_lo, p.bb_val, p.rem_val, p.gm_v,
                           p.nw_r, p.nw_dq, p.diag_s, p.pc_blk, p.kr_H, p.kr_cs, p.kr_sn,  p.kr_g,
                           p.kr_st, p.kr_dev, p.sp_ib.val, p.sp_ib.d_rowptr, p.sp_bi.val, p.sp_bi.d_rowptr,

@@ -190,8 +190,9 @@ class LearnedGuess:
     correction dQ - dQprev) by the rms rc of that step's correction.  At
     prediction time the correction of the step is not known yet; the rms of
     the last known correction stands in for it.  A shrinkage factor alpha in
-    [0, 1], fitted by least squares on the hold-out step, scales the learned
-    correction (alpha = 0 reproduces the previous increment)."""
+    [0, 1], fitted by least squares on a validation step that training did not
+    use, scales the learned correction (alpha = 0 reproduces the previous
+    increment); the hold-out step after it is scored only."""
 
     def __init__(self, n_elem: int, dofs_per_elem: int, capacity: int, hidden: int = 256, layers: int = 2,
                  seed: int = 0, batch: int = 1024, device="cuda", compute: str = "fp32",
@@ -247,11 +248,21 @@ class LearnedGuess:
         self.t[:other.count * nt].copy_(other.t[:other.count * nt])
         self.count = other.count
 
-    def train(self, epochs: int, lr: float = 1e-3, holdout_rows: int = 0):
+    def train(self, epochs: int, lr: float = 1e-3, holdout_rows: int = 0, alpha_rows: int | None = None):
         """Adam on minibatches of a seeded permutation; returns per-epoch mean losses
-        (train) and the hold-out loss of the last `holdout_rows` stored rows (after
-        fitting alpha on them, when given)."""
-        n_train = self.count - holdout_rows
+        (train) and the hold-out loss of the last `holdout_rows` stored rows.
+
+        With a hold-out, the stored rows split into three disjoint parts: the
+        training rows, then `alpha_rows` validation rows (default: as many as the
+        hold-out) on which the shrinkage alpha is fitted, then the hold-out rows,
+        which neither the network nor alpha has seen and which alone are scored."""
+        if alpha_rows is None:
+            alpha_rows = holdout_rows
+        if not holdout_rows:
+            alpha_rows = 0
+        n_train = self.count - holdout_rows - alpha_rows
+        if n_train < self.batch:
+            raise ValueError("too few stored rows for training after the validation and hold-out splits")
         nx, nt = self.nx, self.dpe
         xb = torch.empty(self.batch * nx, dtype=torch.float32, device=self.dev)
         tb = torch.empty(self.batch * nt, dtype=torch.float32, device=self.dev)
@@ -275,8 +286,8 @@ class LearnedGuess:
             history.append(total / max(nb, 1))
         hold = None
         if holdout_rows:
-            self.alpha = self.fit_alpha(n_train, self.count)
-            hold = self.loss_on(n_train, self.count)
+            self.alpha = self.fit_alpha(n_train, n_train + alpha_rows)
+            hold = self.loss_on(self.count - holdout_rows, self.count)
         return history, hold
 
     def _sums(self, row0: int, row1: int):

@@ -101,3 +101,45 @@ def test_curved_fp32_factors_reach_fp64_tolerance():
     assert info["converged"] and info["rel_res"] <= 1e-8
     assert _rel(q1 - q_s, q_ref - q_s) <= 1e-5
     st.close()
+
+
+def test_graph_follows_geometry_changes():
+    """Captured Newton iterations must be recaptured when the residual's geometry
+    changes under the same scdg_dg object, plan and buffers: Cartesian, then
+    curved (scdg_dg_set_geometry(xyz)), then Cartesian again (set_geometry(NULL)
+    frees the metric terms).  Each graph step equals the host-driven step and
+    zeroes the oracle's residual of the geometry in force."""
+    from workload.cases import jacobian_blocks
+    case = _case(2, 3, 100.0, 1e-2, 5, "sine")
+    geo = CurvedGeometry(case.mesh, case.xyz)
+    cart = lambda q: jacobian_blocks(q, case.mesh, case.prm, case.dt)
+
+    def curved(q):
+        blk = curved_jacobian_blocks(q.cpu(), geo, case.prm, case.dt)
+        return {k: v.to(DEV) for k, v in blk.items()}
+
+    st = ImplicitStepper(case.structure(), case.mesh.k_elem, case.mesh.order, case.prm.mach,
+                         case.prm.reynolds, case.dt, cart, newton_tol=1e-10, lin_tol=1e-12, graph=True,
+                         autotune=False)
+    grid, flow = od.Grid(2, 3), od.Flow(case.prm.mach, case.prm.reynolds)
+    ja, jac = od.metric_terms(case.xyz, grid)
+    q_s = case.q_state.reshape(-1).to(DEV).contiguous()
+    qs_np = to_np(q_s).reshape(case.mesh.shape())
+    for phase, xyz in (("cartesian", None), ("curved", case.xyz), ("cartesian again", None)):
+        print("geometry phase:", phase, flush=True)
+        st.dg.set_geometry(xyz)
+        st.jacobian = curved if xyz is not None else cart
+        st.prepare(q_s)
+        q_h, info_h = st.solve_step(q_s, graph=False)
+        q_g, info_g = st.solve_step(q_s, graph=True)
+        print(phase, info_h, info_g, flush=True)
+        assert info_h["converged"] and info_g["converged"]
+        assert _rel(q_g - q_s, q_h - q_s) <= 1e-8
+        qg = to_np(q_g).reshape(case.mesh.shape())
+        if xyz is None:
+            r, r0 = od.residual(qg, grid, flow, qs_np, case.dt), od.residual(qs_np, grid, flow, qs_np, case.dt)
+        else:
+            r = od.residual_curved(qg, grid, flow, ja, jac, qs_np, case.dt)
+            r0 = od.residual_curved(qs_np, grid, flow, ja, jac, qs_np, case.dt)
+        assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(r0), phase
+    st.close()

@@ -9,8 +9,10 @@ the device residual) and the learned initial guess.
   every step converges to the same FP64 residual with or without it, and the
   learned guess needs fewer GMRES iterations than the zero guess (the method
   without it), with the state and previous increment as inputs and with the
-  step's residual R(Q_s) as a third input.  The gain over the previous
-  increment is reported, not asserted.
+  step's residual R(Q_s) as a third input.  On a hold-out step that neither
+  training nor the shrinkage fit has seen, the trained correction beats the
+  previous increment (the untrained network's prediction, checked bitwise);
+  the GMRES gain over the previous increment is reported, not asserted.
 """
 import numpy as np
 import pytest
@@ -90,7 +92,13 @@ def test_learned_guess_beats_zero_guess():
     print(f"train loss first/last {history[0]:.3e} {history[-1]:.3e} holdout {hold:.3e} "
           f"(previous increment {hold_prev:.3e}, alpha {lg.alpha:.3f})", flush=True)
     assert history[-1] < 0.5 * history[0]
-    assert hold <= hold_prev * (1 + 1e-9)      # the fitted shrinkage never makes the hold-out worse
+    # the hold-out step is unseen by training and by the alpha fit (the step
+    # before it): the trained correction must beat the previous increment there
+    assert hold < hold_prev
+    # the untrained network (output layer at zero) reproduces the previous increment
+    untrained = LearnedGuess(n_elem, dpe, capacity=1, seed=1, batch=64)
+    assert torch.equal(untrained.predict(q, dq_prev, rc_prev), dq_prev)
+    untrained.close()
     its = {"zero": [], "previous": [], "learned": [], "learned_r": []}
     rejected = 0
     for step in range(n_test):
@@ -115,7 +123,9 @@ def test_learned_guess_beats_zero_guess():
         dq_prev = dq
         q = results["learned"]
     tot = {k: sum(v) for k, v in its.items()}
-    print(f"first-solve GMRES iterations over {n_test} steps: {tot}", flush=True)
+    # trained against untrained (= the previous increment): reported, not asserted
+    print(f"first-solve GMRES iterations over {n_test} steps: {tot} "
+          f"(trained {tot['learned']} vs untrained {tot['previous']})", flush=True)
     assert tot["learned"] < tot["zero"]
     assert tot["learned_r"] < tot["zero"]
     assert rejected == 0
