@@ -96,10 +96,14 @@ def assemble_global(order, c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, a
         put(ii, ii, aii[e])
         put(ii, cc, aib[e])
         put(cc, ii, abi[e])
+    # A_bb: block t of row g couples the DOFs of boundary nodes g and bb_col[t]
     n_b = len(bb_rowptr) - 1
-    for g in range(n_b):
-        for t in range(bb_rowptr[g], bb_rowptr[g + 1]):
-            put(bnode_dofs[g], bnode_dofs[bb_col[t]], bb_val[t])
+    g_of_t = np.repeat(np.arange(n_b), np.diff(np.asarray(bb_rowptr)))
+    rr = bnode_dofs[g_of_t][:, :, None] + 0 * bnode_dofs[g_of_t][:, None, :]
+    cc = bnode_dofs[np.asarray(bb_col)][:, None, :] + 0 * bnode_dofs[g_of_t][:, :, None]
+    rows.append(rr.reshape(-1))
+    cols.append(cc.reshape(-1))
+    vals.append(np.asarray(bb_val).reshape(-1))
     a = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n_dof, n_dof)).tocsr()
     a.eliminate_zeros()
