@@ -329,6 +329,25 @@ scdg_status scdg_dg_gradient(scdg_dg *dg, double *g);
  * on the object's stream.  SCDG_ERR_ARG for NULL pointers or a negative or
  * non-finite inv_dt, SCDG_ERR_NOMEM if the workspace cannot be allocated. */
 scdg_status scdg_dg_jacobian_apply(scdg_dg *dg, const double *q, const double *v, double inv_dt, double *out);
+/* Allocation-free form of scdg_dg_jacobian_apply, for callers that cannot
+ * allocate device memory during the call: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same operator, same kernels,
+ * same arguments and results; the lifted gradient of the direction v is kept
+ * in a fixed device array of SCDG_NOALLOC_SCRATCH_BYTES compiled into the
+ * library (one copy per GPU, resident until the process ends, its address
+ * looked up once per device when a scdg_dg object is created) instead of a
+ * workspace allocated on the first call.  The call allocates and frees
+ * nothing.  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (different streams, or different host threads) race and give
+ * undefined results; calls ordered on one stream are safe (the array needs no
+ * clearing: each call writes all of the part it reads).
+ * SCDG_ERR_UNSUPPORTED when the mesh needs more than the array holds
+ * (15 * 8 bytes per node: at most 559 240 nodes, e.g. 16^3 elements of order 4);
+ * SCDG_ERR_ARG as for scdg_dg_jacobian_apply; SCDG_ERR_HIP if the array's
+ * address could not be found on the object's device. */
+#define SCDG_NOALLOC_SCRATCH_BYTES (64ll << 20)
+scdg_status scdg_dg_jacobian_apply_noalloc(scdg_dg *dg, const double *q, const double *v, double inv_dt,
+                                           double *out);
 
 /* ------------------------------------------------------------------------
  * Newton iterations of one backward-Euler step replayed from captured HIP

@@ -20,6 +20,7 @@
 // the lifting is linear, so the direction's gradient is the lifting of v, and
 // the residual sums carry value and derivative; only the derivative is kept.
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -568,6 +569,7 @@ struct DgContext {
   double *gd = nullptr;    // lifted gradient of a direction (allocated by the first Newton-matrix product)
   double *met = nullptr;   // curved elements: 10 doubles per node (NULL: Cartesian cubes)
   uint64_t geo_gen = 0;    // bumped by every geometry change: captured graphs keyed on it recapture
+  int device = 0;          // the HIP device the object was created on
   int64_t n_nodes = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
@@ -606,7 +608,7 @@ hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, doubl
 // lifting is linear), then the residual sums on dual numbers (value q,
 // direction v).  c.gd must hold 15 doubles per node.
 hipError_t dg_jacobian_apply_on(scdg_dg *dg, const double *q, const double *v, double inv_dt, double *out,
-                                hipStream_t s) {
+                                hipStream_t s, double *gd) {
   auto &c = dg->c;
   const int p3 = c.host.p * c.host.p * c.host.p;
   const int n_elem = c.host.k_elem * c.host.k_elem * c.host.k_elem;
@@ -615,19 +617,53 @@ hipError_t dg_jacobian_apply_on(scdg_dg *dg, const double *q, const double *v, d
     hipLaunchKernelGGL(lift_curved_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 10 * p3, s, c.dev, q,
                        c.met, c.g);
     hipLaunchKernelGGL(lift_curved_kernel, dim3(n_elem), dim3(threads), sizeof(double) * 10 * p3, s, c.dev, v,
-                       c.met, c.gd);
+                       c.met, gd);
     hipLaunchKernelGGL(residual_curved_kernel<Dual>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
-                       c.dev, q, v, c.g, c.gd, c.met, nullptr, inv_dt, out);
+                       c.dev, q, v, c.g, gd, c.met, nullptr, inv_dt, out);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g);
-  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, v, c.gd);
+  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, v, gd);
   hipLaunchKernelGGL(residual_kernel<Dual>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
-                     v, c.g, c.gd, nullptr, inv_dt, out);
+                     v, c.g, gd, nullptr, inv_dt, out);
   return hipGetLastError();
 }
 
 int64_t dg_dof_count(const scdg_dg *dg) { return 5 * dg->c.n_nodes; }
+
+// ---- allocation-free Newton-matrix product ----
+// The direction's lifted gradient (15 doubles per node) of
+// scdg_dg_jacobian_apply_noalloc lives in this file-scope device array, one copy
+// per GPU, held until the process ends.  Its host-side name is not a device
+// address: host code only ever uses the address hipGetSymbolAddress returns for
+// the current device, kept per device in noalloc_ptr.
+constexpr int64_t kNoAllocDoubles = SCDG_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+double *noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Resolve this device's copy of the scratch array; the caller has made `device`
+// current.  Idempotent.
+hipError_t noalloc_resolve(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if (noalloc_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  noalloc_ptr[device] = static_cast<double *>(ptr);
+  return hipSuccess;
+}
+
+double *noalloc_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  return noalloc_ptr[device];
+}
 
 // What a captured residual launch depends on beyond the caller's vectors: the
 // geometry generation (which kernels run, and on which metric buffer) and the
@@ -667,6 +703,13 @@ scdg_status scdg_dg_create(scdg_dg **out, const scdg_dg_params *prm, void *hip_s
     for (int a = 0; a < P.p; ++a) P.vw[l][a] = -P.w[a] * P.d[a][l];
   c.stream = static_cast<hipStream_t>(hip_stream);
   c.n_nodes = (int64_t)prm->k_elem * prm->k_elem * prm->k_elem * P.p * P.p * P.p;
+  if (hipGetDevice(&c.device) != hipSuccess) {
+    delete dg;
+    return SCDG_ERR_HIP;
+  }
+  // set-up of the allocation-free product: this device's scratch address (no
+  // allocation; a failure is reported by scdg_dg_jacobian_apply_noalloc)
+  (void)scdg::noalloc_resolve(c.device);
   if (hipMalloc(&c.dev, sizeof(scdg::DgParams)) != hipSuccess ||
       hipMalloc(&c.g, sizeof(double) * 15 * c.n_nodes) != hipSuccess ||
       hipMemcpy(c.dev, &P, sizeof(scdg::DgParams), hipMemcpyHostToDevice) != hipSuccess) {
@@ -703,7 +746,31 @@ scdg_status scdg_dg_jacobian_apply(scdg_dg *dg, const double *q, const double *v
     c.gd = nullptr;
     return SCDG_ERR_NOMEM;
   }
-  return scdg::dg_jacobian_apply_on(dg, q, v, inv_dt, out, c.stream) == hipSuccess ? SCDG_OK : SCDG_ERR_HIP;
+  return scdg::dg_jacobian_apply_on(dg, q, v, inv_dt, out, c.stream, c.gd) == hipSuccess ? SCDG_OK
+                                                                                        : SCDG_ERR_HIP;
+}
+
+scdg_status scdg_dg_jacobian_apply_noalloc(scdg_dg *dg, const double *q, const double *v, double inv_dt,
+                                           double *out) {
+  if (!dg || !q || !v || !out || !(inv_dt >= 0.0) || !std::isfinite(inv_dt)) return SCDG_ERR_ARG;
+  auto &c = dg->c;
+  if (15 * c.n_nodes > scdg::kNoAllocDoubles) {
+    c.last_error = "scdg_dg_jacobian_apply_noalloc: the mesh needs " + std::to_string(15 * 8 * c.n_nodes) +
+                   " bytes of gradient scratch, above the fixed " +
+                   std::to_string((long long)SCDG_NOALLOC_SCRATCH_BYTES) + "-byte array";
+    return SCDG_ERR_UNSUPPORTED;
+  }
+  double *gd = scdg::noalloc_lookup(c.device);
+  if (!gd) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != c.device || scdg::noalloc_resolve(c.device) != hipSuccess ||
+        !(gd = scdg::noalloc_lookup(c.device))) {
+      c.last_error = "scdg_dg_jacobian_apply_noalloc: no address for the scratch array on this device";
+      return SCDG_ERR_HIP;
+    }
+  }
+  return scdg::dg_jacobian_apply_on(dg, q, v, inv_dt, out, c.stream, gd) == hipSuccess ? SCDG_OK
+                                                                                     : SCDG_ERR_HIP;
 }
 
 scdg_status scdg_dg_set_geometry(scdg_dg *dg, const double *xyz) {
