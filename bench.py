@@ -524,6 +524,8 @@ def main() -> int:
     ap.add_argument("--lg-newton-tol", type=float, default=1e-8)
     ap.add_argument("--autotune-cache", default=None,
                     help="JSON file of tile choices per problem signature (default: $SCDG_AUTOTUNE_CACHE)")
+    ap.add_argument("--wall-batch", type=int, default=96,
+                    help="complex-step directions per residual evaluation when generating a wall workload")
     ap.add_argument("--time-stepping", action="store_true",
                     help="host-driven vs graph-replayed Newton iterations over implicit steps")
     ap.add_argument("--ts-workload", default="tgv_n4_k16")
@@ -560,8 +562,25 @@ def main() -> int:
     from workload.cases import WORKLOADS, named_case
     from workload.mixed import MIXED_WORKLOADS, mixed_order_case
 
+    from workload.walls import WALL_WORKLOADS, build_wall_case
+
     dev = "cuda"
-    if args.workload in MIXED_WORKLOADS:
+    wall = args.workload in WALL_WORKLOADS
+    if wall:
+        wcfg = WALL_WORKLOADS[args.workload]
+        t_gen = time.perf_counter()
+        case = build_wall_case(device=dev, seed=0, max_batch=args.wall_batch,
+                               progress=lambda c, n: progress(f"wall Jacobian: colour {c + 1} of {n}")
+                               if c % 4 == 0 else None, **wcfg)
+        torch.cuda.synchronize()
+        progress(f"wall workload generated in {time.perf_counter() - t_gen:.1f} s")
+        k_w, n_w = wcfg["k_elem"], wcfg["order"]
+        cfg = dict(wcfg)
+        cfg["walls"] = ("isothermal no-slip walls on the two faces normal to z (Section 2.1.1 outer state), "
+                        "wall-face DOFs in Q_i")
+        cfg["condensed_ratio"] = round(case.n1 / case.n_dof, 6)
+        cfg["condensed_ratio_without_walls"] = round(((n_w + 1) ** 3 - (n_w - 1) ** 3) / (n_w + 1) ** 3, 6)
+    elif args.workload in MIXED_WORKLOADS:
         k_m, lo_m, hi_m, seed_m = MIXED_WORKLOADS[args.workload]
         case = mixed_order_case(k_m, lo_m, hi_m, seed_m, device=dev)
         cfg = {"order": f"{lo_m}..{hi_m} (seeded per element)", "reynolds": None, "dt": None,
@@ -748,7 +767,9 @@ def main() -> int:
                    "reynolds": cfg["reynolds"], "mach": 0.1 if cfg["reynolds"] else None, "dt": cfg["dt"],
                    "solver": f"gmres({args.restart})+" + ["none", "point-jacobi", "block-jacobi-5x5"][args.precond],
                    "gmres_tol": opts["tol"],
-                   "precision": args.precision, "krylov_mode": args.krylov_mode},
+                   "precision": args.precision, "krylov_mode": args.krylov_mode,
+                   **({k: cfg[k] for k in ("walls", "condensed_ratio", "condensed_ratio_without_walls")}
+                      if wall else {})},
         "roofline": entries[dominant],
         "roofline_all": entries,
         "measured_peaks": measured,
@@ -765,7 +786,7 @@ def main() -> int:
     }
     if worst > 1e-8:
         out["warning"] = "full-system residual above 1e-8"
-    if not args.no_dg_timing and args.workload not in MIXED_WORKLOADS:
+    if not args.no_dg_timing and args.workload not in MIXED_WORKLOADS and not wall:
         out["dg_operators"] = dg_operator_timing(case)
     if not args.no_cpu_baseline and case.aii.dim() == 3:      # one order per mesh
         out["cpu_baseline"] = cpu_baseline(case, args.tol, args.cpu_seconds)

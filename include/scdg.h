@@ -24,7 +24,10 @@
  *   - Natural vectors (B, dQ, r, x0): device, double, DOF index
  *     (sum_{e'<e} 5 P_{e'}^3) + 5 n + v.
  *   - Interior nodes of e: i, j, k all in [1, N_e-1], in increasing n;
- *     n_i(e) = 5 (N_e - 1)^3 DOFs.
+ *     n_i(e) = 5 (N_e - 1)^3 DOFs.  With physical boundaries (phys_faces in
+ *     scdg_structure) a node also counts as interior when every element face
+ *     it lies on is physical: such DOFs couple to no other element, so they
+ *     join Q_i (the achievable ratio of Section 3.2).
  *   - Boundary nodes of e: the other nodes in increasing n; the r-th one has
  *     global boundary id bnode_off[e] + r, bnode_off = exclusive prefix sum of
  *     (P^3 - (N_e-1)^3).  Boundary vectors (b_S, Q_b): device, double,
@@ -82,6 +85,10 @@ typedef struct {
   const int32_t *c_node;    /* [c_ptr[n_elem]] C_e as ascending global boundary ids */
   const int64_t *bb_rowptr; /* [n_bnodes+1] BSR row pointer of A_bb */
   const int32_t *bb_col;    /* [bb_rowptr[n_bnodes]] BSR block columns of A_bb */
+  const uint8_t *phys_faces; /* [n_elem] or NULL (no physical boundary): bit 2 d + s is set when the
+                                element face of direction d (0: i, 1: j, 2: k) on side s (0: index 0,
+                                1: index N_e) lies on a physical boundary (Section 2.1.1: its outer
+                                state is a boundary condition, not a neighbour); bits 6, 7 must be 0 */
 } scdg_structure;
 
 typedef enum { SCDG_SOLVER_AUTO = 0, SCDG_SOLVER_DENSE = 1, SCDG_SOLVER_GMRES = 2 } scdg_solver;

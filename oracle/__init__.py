@@ -27,5 +27,5 @@ from .linalg import (  # noqa: F401
     element_inverse, element_schur, condensed_matrix_dense, condensed_rhs,
     back_substitute, full_residual, gmres_mgs, condensed_solve_dense, element_interior_residual,
     full_residual_blocks, CondensedCPU, condense_cpu, schur_matvec_cpu, condensed_gmres_solve,
-    solve_gmres_element_jacobi,
+    solve_gmres_element_jacobi, achievable_ratio,
 )

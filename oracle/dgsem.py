@@ -19,6 +19,15 @@ What it computes, with the paper's notation:
     (x sign(Re x), comparison of real parts), with the same values as np.abs
     and np.maximum on real input.
 
+  * optional isothermal no-slip walls (Walls) on the two domain faces normal
+    to one direction, the mesh staying periodic in the other two: the outer
+    state of a wall face is the function q^-(q^+) of Section 2.1.1 (the
+    Dirichlet condition; see wall_ghost), the BR1 surface value of the lifting
+    is 1/2 (q^+ + q^-(q^+)), the advective flux is the Lax-Friedrichs flux
+    between q^+ and q^-(q^+), and the viscous flux is that of the wall state
+    1/2 (q^+ + q^-) with the inner gradient (the Neumann part of the
+    condition, Section 2.1.2).
+
 The weak forms above are written as quadrature sums; nothing here uses the
 strong (summation-by-parts) rewrite, so a test that compares against a
 strong-form evaluation checks both.
@@ -67,6 +76,36 @@ class Grid:
     @property
     def h(self) -> float:
         return self.length / self.k_elem
+
+
+@dataclass(frozen=True)
+class Walls:
+    """Isothermal no-slip walls on the domain faces x_d = 0 and x_d = length
+    (elements 0 and K-1 along d); periodic in the other two directions."""
+    d: int = 2
+    t_wall: float = 1.0
+
+
+def wall_ghost(q: np.ndarray, flow: Flow, t_wall: float) -> np.ndarray:
+    """Outer state q^-(q^+) of an isothermal no-slip wall: the same density, the
+    momentum reversed, and rho E^- = 2 rho e_w - rho E^+ with e_w the specific
+    internal energy at the wall temperature, so that the average
+    1/2 (q^+ + q^-) is exactly the wall state (zero velocity, temperature
+    t_wall) for every q^+.  Linear in q^+ (the Jacobian q^-_{q^+} of
+    Section 2.1.1 is a constant matrix)."""
+    e_w = t_wall / (flow.gamma * (flow.gamma - 1.0) * flow.mach ** 2)
+    out = np.empty_like(q)
+    out[..., 0] = q[..., 0]
+    out[..., 1:4] = -q[..., 1:4]
+    out[..., 4] = 2.0 * q[..., 0] * e_w - q[..., 4]
+    return out
+
+
+def _layer(a: np.ndarray, d: int, index: int) -> tuple:
+    """Index tuple selecting the elements at position `index` along direction d."""
+    sl = [slice(None)] * 3          # element axes lead every array
+    sl[2 - d] = index
+    return tuple(sl)
 
 
 # --------------------------------------------------------------------------
@@ -217,8 +256,11 @@ def _neighbour(a: np.ndarray, d: int, step: int) -> np.ndarray:
     return np.roll(a, -step, axis=2 - d)
 
 
-def lifted_gradient(q: np.ndarray, grid: Grid) -> np.ndarray:
-    """BR1 gradient of eq. DGSEMsystem:2 in weak form; returns [..., 3, 5]."""
+def lifted_gradient(q: np.ndarray, grid: Grid, walls: Walls | None = None,
+                    flow: Flow | None = None) -> np.ndarray:
+    """BR1 gradient of eq. DGSEMsystem:2 in weak form; returns [..., 3, 5].
+    With walls (flow needed for the wall state), the outer value at a wall face
+    is q^-(q^+) (wall_ghost)."""
     x, w = gl_rule(grid.order)
     dm = lagrange_derivative(x)
     n = grid.order
@@ -237,21 +279,47 @@ def lifted_gradient(q: np.ndarray, grid: Grid) -> np.ndarray:
         surf = np.zeros_like(vol)
         right = _line_last(_neighbour(q, d, +1), d)[..., 0, :]
         left = _line_last(_neighbour(q, d, -1), d)[..., n, :]
+        if walls is not None and walls.d == d:
+            right, left = right.copy(), left.copy()
+            hi, lo = _layer(right, d, -1), _layer(left, d, 0)
+            right[hi] = wall_ghost(ql[..., n, :][hi], flow, walls.t_wall)
+            left[lo] = wall_ghost(ql[..., 0, :][lo], flow, walls.t_wall)
         surf[..., n, :] += jac_face * wt[:, :, None] * 0.5 * (ql[..., n, :] + right)
         surf[..., 0, :] -= jac_face * wt[:, :, None] * 0.5 * (ql[..., 0, :] + left)
         g[..., d, :] = _line_back(vol + surf, d) / mw[..., None]
     return g
 
 
-def operator_h(q: np.ndarray, grid: Grid, flow: Flow) -> np.ndarray:
-    """H(Q) of eq. DiscretNS from eq. DGSEMsystem:1 (mass-weighted, same layout as q)."""
+def wall_fluxes(q: np.ndarray, g: np.ndarray, d: int, flow: Flow, walls: Walls):
+    """Numerical fluxes along +e_d through the two wall faces of the elements
+    next to them: (through the +d face of the last layer, through the -d face
+    of the first layer), each [.., P, P, 5] on those elements' face nodes.
+    Lax-Friedrichs between the inner state and q^-(q^+) (the normal +e_d leaves
+    the inner side at the upper wall and enters it at the lower one), minus the
+    viscous flux of the wall state 1/2 (q^+ + q^-) with the inner gradient."""
+    n = q.shape[3] - 1
+    out = []
+    for side, l in ((-1, n), (0, 0)):
+        sel = _layer(q, d, side)
+        q_in = _line_last(q, d)[..., l, :][sel]
+        g_in = np.moveaxis(g, 5 - d, -3)[..., l, :, :][sel]
+        q_gh = wall_ghost(q_in, flow, walls.t_wall)
+        q_w = 0.5 * (q_in + q_gh)
+        adv = lax_friedrichs(q_in, q_gh, d, flow) if side == -1 else lax_friedrichs(q_gh, q_in, d, flow)
+        out.append(adv - viscous_flux(q_w, g_in, d, flow))
+    return out[0], out[1]
+
+
+def operator_h(q: np.ndarray, grid: Grid, flow: Flow, walls: Walls | None = None) -> np.ndarray:
+    """H(Q) of eq. DiscretNS from eq. DGSEMsystem:1 (mass-weighted, same layout as q);
+    optional isothermal no-slip walls (wall_fluxes on their faces)."""
     x, w = gl_rule(grid.order)
     dm = lagrange_derivative(x)
     n = grid.order
     jac = (grid.h / 2.0) ** 3
     jac_face = (grid.h / 2.0) ** 2
     scale = 2.0 / grid.h
-    g = lifted_gradient(q, grid)
+    g = lifted_gradient(q, grid, walls, flow)
     h = np.zeros_like(q)
     for d in range(3):
         f = euler_flux(q, d, flow) - viscous_flux(q, g, d, flow)
@@ -266,6 +334,11 @@ def operator_h(q: np.ndarray, grid: Grid, flow: Flow) -> np.ndarray:
         f_hat = lax_friedrichs(q_in, q_out, d, flow) \
             - 0.5 * (viscous_flux(q_in, g_in, d, flow) + viscous_flux(q_out, g_out, d, flow))
         f_hat_left = _neighbour(f_hat, d, -1)       # each element's -e_d face is its left neighbour's +e_d face
+        if walls is not None and walls.d == d:
+            f_hi, f_lo = wall_fluxes(q, g, d, flow, walls)
+            f_hat, f_hat_left = f_hat.copy(), f_hat_left.copy()
+            f_hat[_layer(f_hat, d, -1)] = f_hi
+            f_hat_left[_layer(f_hat_left, d, 0)] = f_lo
         surf = np.zeros_like(vol)
         surf[..., n, :] += jac_face * wt[:, :, None] * f_hat
         surf[..., 0, :] -= jac_face * wt[:, :, None] * f_hat_left
@@ -274,9 +347,9 @@ def operator_h(q: np.ndarray, grid: Grid, flow: Flow) -> np.ndarray:
 
 
 def residual(q: np.ndarray, grid: Grid, flow: Flow, q_s: np.ndarray | None = None,
-             dt: float | None = None) -> np.ndarray:
+             dt: float | None = None, walls: Walls | None = None) -> np.ndarray:
     """R(Q) = M (Q - Q_s) / dt + H(Q); without q_s, H(Q)."""
-    h = operator_h(q, grid, flow)
+    h = operator_h(q, grid, flow, walls)
     if q_s is None:
         return h
     return mass(grid)[..., None] * (q - q_s) / dt + h
@@ -285,15 +358,28 @@ def residual(q: np.ndarray, grid: Grid, flow: Flow, q_s: np.ndarray | None = Non
 CS_STEP = 1e-30
 
 
-def jacobian_apply(q: np.ndarray, v: np.ndarray, grid: Grid, flow: Flow, dt: float | None = None) -> np.ndarray:
+def jacobian_apply(q: np.ndarray, v: np.ndarray, grid: Grid, flow: Flow, dt: float | None = None,
+                   walls: Walls | None = None) -> np.ndarray:
     """A v = (M / dt + dH/dQ(q)) v, the Newton matrix of eq. NewtonLinSys1 at q
     applied to v (without dt: dH/dQ(q) v), by complex-step differentiation of
     the residual: Im R(q + i h v) / h with h = 1e-30, exact to rounding (no
     subtraction of nearby values)."""
     qc = q.astype(np.complex128) + 1j * CS_STEP * v
     if dt is None:
-        return operator_h(qc, grid, flow).imag / CS_STEP
-    return residual(qc, grid, flow, q_s=q, dt=dt).imag / CS_STEP
+        return operator_h(qc, grid, flow, walls).imag / CS_STEP
+    return residual(qc, grid, flow, q_s=q, dt=dt, walls=walls).imag / CS_STEP
+
+
+def wall_face_mask(k_elem: int, walls: Walls | None) -> np.ndarray:
+    """Physical faces of every element (natural element order e = ex + K ey + K^2 ez):
+    bit 2 d' + s is set when the face of direction d' on side s (0: the -d'
+    face, node index 0; 1: the +d' face, node index N) lies on a wall."""
+    mask = np.zeros((k_elem, k_elem, k_elem), dtype=np.uint8)
+    if walls is not None:
+        d = walls.d
+        mask[_layer(mask, d, 0)] |= np.uint8(1 << (2 * d))
+        mask[_layer(mask, d, -1)] |= np.uint8(1 << (2 * d + 1))
+    return mask.reshape(-1)
 
 
 # --------------------------------------------------------------------------

@@ -27,12 +27,16 @@ class NodeSets:
     boundary: list      # remaining local node ids, increasing
 
 
-def node_sets(order: int) -> NodeSets:
+def node_sets(order: int, phys: int = 0) -> NodeSets:
     """Interior / element-boundary nodes of a GL hex element (paper, Section 3.1).
 
     On Gauss-Lobatto nodes a basis function is nonzero on a face only if its
     node lies on that face, so the element-boundary DOFs are exactly the nodes
-    with some index equal to 0 or N.
+    with some index equal to 0 or N.  Faces on a physical boundary couple to no
+    other element, so their DOFs need not be condensed into Q_b (the paper's
+    'achievable ratio', Section 3.2): with `phys` (bit 2 d + s set when the face
+    of direction d on side s, 0 for index 0 and 1 for index N, is physical) a
+    node counts as interior when every face it lies on is physical.
     """
     p = order + 1
     interior, boundary = [], []
@@ -40,24 +44,31 @@ def node_sets(order: int) -> NodeSets:
         for j in range(p):
             for i in range(p):
                 n = i + p * j + p * p * k
-                if 1 <= i <= order - 1 and 1 <= j <= order - 1 and 1 <= k <= order - 1:
+                inside = True
+                for d, a in enumerate((i, j, k)):
+                    if a == 0 and not (phys >> (2 * d)) & 1:
+                        inside = False
+                    if a == order and not (phys >> (2 * d + 1)) & 1:
+                        inside = False
+                if inside:
                     interior.append(n)
                 else:
                     boundary.append(n)
     return NodeSets(interior, boundary)
 
 
-def dof_maps(order: np.ndarray):
+def dof_maps(order: np.ndarray, phys=None):
     """Natural-order DOF indices of every element's interior and of every global boundary node.
 
     Returns (interior_dofs: list of arrays [5 nI(e)], bnode_dofs: array [n_bnodes, 5]).
     Global boundary node ids run element by element over each element's boundary
-    nodes in increasing local node id.
+    nodes in increasing local node id.  phys: per-element physical-face masks
+    (node_sets), or None for none.
     """
     interior_dofs, bnode = [], []
     off = 0
-    for n_e in order:
-        ns = node_sets(int(n_e))
+    for e, n_e in enumerate(order):
+        ns = node_sets(int(n_e), 0 if phys is None else int(phys[e]))
         interior_dofs.append(np.array([off + NVAR * n + v for n in ns.interior for v in range(NVAR)],
                                       dtype=np.int64))
         for n in ns.boundary:
@@ -77,10 +88,10 @@ def _b_index(bnode_dofs: np.ndarray, e: int, c_ptr, c_node) -> np.ndarray:
     return (nodes[:, None] * NVAR + np.arange(NVAR)[None, :]).reshape(-1)
 
 
-def assemble_global(order, c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi) -> sp.csr_matrix:
+def assemble_global(order, c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi, phys=None) -> sp.csr_matrix:
     """Scatter the per-element blocks and A_bb back into the global Jacobian A
     (natural DOF order).  Every entry of A lives in exactly one block."""
-    interior_dofs, bnode_dofs = dof_maps(order)
+    interior_dofs, bnode_dofs = dof_maps(order, phys)
     n_dof = int(sum(NVAR * (int(n) + 1) ** 3 for n in order))
     rows, cols, vals = [], [], []
 
@@ -151,9 +162,9 @@ def condensed_matrix_dense(c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, a
     return s
 
 
-def condensed_rhs(order, c_ptr, c_node, aii, abi, b: np.ndarray) -> np.ndarray:
+def condensed_rhs(order, c_ptr, c_node, aii, abi, b: np.ndarray, phys=None) -> np.ndarray:
     """b_S = B_b - sum_e P_e A_bi(e) A_ii(e)^-1 B_i(e) (eq. SC_step1, right-hand side)."""
-    interior_dofs, bnode_dofs = dof_maps(order)
+    interior_dofs, bnode_dofs = dof_maps(order, phys)
     bs = b[bnode_dofs].reshape(-1).copy()
     for e in range(len(order)):
         idx = _b_index(None, e, c_ptr, c_node)
@@ -161,9 +172,9 @@ def condensed_rhs(order, c_ptr, c_node, aii, abi, b: np.ndarray) -> np.ndarray:
     return bs
 
 
-def back_substitute(order, c_ptr, c_node, aii, aib, b: np.ndarray, qb: np.ndarray) -> np.ndarray:
+def back_substitute(order, c_ptr, c_node, aii, aib, b: np.ndarray, qb: np.ndarray, phys=None) -> np.ndarray:
     """Q_i(e) = A_ii(e)^-1 (B_i(e) - A_ib(e) Q_b[C_e]) (eq. SC_step2); returns dQ in natural order."""
-    interior_dofs, bnode_dofs = dof_maps(order)
+    interior_dofs, bnode_dofs = dof_maps(order, phys)
     dq = np.zeros_like(b)
     dq[bnode_dofs.reshape(-1)] = qb
     for e in range(len(order)):
@@ -172,12 +183,12 @@ def back_substitute(order, c_ptr, c_node, aii, aib, b: np.ndarray, qb: np.ndarra
     return dq
 
 
-def condensed_solve_dense(order, c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi, b):
+def condensed_solve_dense(order, c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi, b, phys=None):
     """Both condensation steps with a dense LU of S (the paper's direct route, Section 2.2)."""
     s = condensed_matrix_dense(c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi)
-    bs = condensed_rhs(order, c_ptr, c_node, aii, abi, b)
+    bs = condensed_rhs(order, c_ptr, c_node, aii, abi, b, phys)
     qb = sla.lu_solve(sla.lu_factor(s), bs)
-    return back_substitute(order, c_ptr, c_node, aii, aib, b, qb)
+    return back_substitute(order, c_ptr, c_node, aii, aib, b, qb, phys)
 
 
 def full_residual(a, x: np.ndarray, b: np.ndarray) -> np.ndarray:
@@ -246,21 +257,21 @@ def gmres_mgs(matvec, b: np.ndarray, tol: float, restart: int = 30, max_iter: in
 
 
 def element_interior_residual(e: int, order, c_ptr, c_node, aii_e, aib_e, b: np.ndarray,
-                              dq: np.ndarray) -> np.ndarray:
+                              dq: np.ndarray, phys=None) -> np.ndarray:
     """Interior rows of r = B - A dQ for one element: B_i - A_ii dQ_i - A_ib dQ_b[C_e]."""
-    interior_dofs, bnode_dofs = dof_maps(order)
+    interior_dofs, bnode_dofs = dof_maps(order, phys)
     qb = dq[bnode_dofs.reshape(-1)]
     idx = _b_index(None, e, c_ptr, c_node)
     return b[interior_dofs[e]] - aii_e @ dq[interior_dofs[e]] - aib_e @ qb[idx]
 
 
 def full_residual_blocks(order, c_ptr, c_node, bb_rowptr, bb_col, bb_val, aii, aib, abi,
-                         b: np.ndarray, dq: np.ndarray) -> np.ndarray:
+                         b: np.ndarray, dq: np.ndarray, phys=None) -> np.ndarray:
     """r = B - A dQ on the full system, formed element by element from the blocks
     (no global matrix): interior rows B_i - A_ii dQ_i - A_ib dQ_b[C_e], boundary rows
     B_b - A_bb dQ_b - sum_e P_e A_bi(e) dQ_i(e) (eq. StaticDGSEM_QbQiSystem, row-column
     subscripts).  Returns r in the natural DOF order."""
-    interior_dofs, bnode_dofs = dof_maps(order)
+    interior_dofs, bnode_dofs = dof_maps(order, phys)
     n_b = len(bb_rowptr) - 1
     flat_b = bnode_dofs.reshape(-1)
     qb = dq[flat_b]
@@ -363,3 +374,31 @@ def solve_gmres_element_jacobi(a, b: np.ndarray, order, tol: float, restart: int
         return out
 
     return gmres_mgs(lambda v: a @ v, b, tol=tol, restart=restart, max_iter=max_iter, precond=minv)
+
+
+def achievable_ratio(k_elem: int, order: int, wall_dirs=(2,)) -> float:
+    """n1 / (n1 + n2) on a K^3 hex mesh of order N whose two domain faces normal
+    to each direction in wall_dirs are physical (the rest periodic), when the
+    DOFs of nodes lying only on physical faces join Q_i (Section 3.2, the
+    achievable ratio; Table ratio is the case of no physical face).  Counted per
+    element: a node on a physical face stays in Q_b exactly when it also lies on
+    an element face that is not physical."""
+    n = order
+    total, n1 = 0, 0
+    for ez in range(k_elem):
+        for ey in range(k_elem):
+            for ex in range(k_elem):
+                pos = (ex, ey, ez)
+                for k in range(n + 1):
+                    for j in range(n + 1):
+                        for i in range(n + 1):
+                            total += 1
+                            on_open_face = False
+                            for d, a in enumerate((i, j, k)):
+                                if a in (0, n):
+                                    at_wall = d in wall_dirs and ((a == 0 and pos[d] == 0) or
+                                                                  (a == n and pos[d] == k_elem - 1))
+                                    if not at_wall:
+                                        on_open_face = True
+                            n1 += on_open_face
+    return n1 / total

@@ -42,7 +42,8 @@ PHASES = ["inverse", "gemm_x", "gemm_s", "rhs", "schur_apply", "condensed_solve"
 
 class Structure(C.Structure):
     _fields_ = [("n_elem", C.c_int32), ("order", C.c_void_p), ("c_ptr", C.c_void_p),
-                ("c_node", C.c_void_p), ("bb_rowptr", C.c_void_p), ("bb_col", C.c_void_p)]
+                ("c_node", C.c_void_p), ("bb_rowptr", C.c_void_p), ("bb_col", C.c_void_p),
+                ("phys_faces", C.c_void_p)]
 
 
 class DgParams(C.Structure):

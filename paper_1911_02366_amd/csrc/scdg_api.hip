@@ -66,7 +66,10 @@ void dfree(T *&ptr) {
   ptr = nullptr;
 }
 
-void local_node_sets(int order, std::vector<int> &interior, std::vector<int> &boundary) {
+// Interior / boundary nodes of an element of the given order.  A node is interior
+// when, in every direction, its index is strictly inside or sits on a face that
+// `phys` marks physical (bit 2 d for index 0, bit 2 d + 1 for index N).
+void local_node_sets(int order, int phys, std::vector<int> &interior, std::vector<int> &boundary) {
   const int p = order + 1;
   interior.clear();
   boundary.clear();
@@ -74,8 +77,12 @@ void local_node_sets(int order, std::vector<int> &interior, std::vector<int> &bo
     for (int j = 0; j < p; ++j)
       for (int i = 0; i < p; ++i) {
         const int n = i + p * j + p * p * k;
-        const bool in = i >= 1 && i <= order - 1 && j >= 1 && j <= order - 1 && k >= 1 &&
-                        k <= order - 1;
+        const int idx[3] = {i, j, k};
+        bool in = true;
+        for (int d = 0; d < 3; ++d) {
+          if (idx[d] == 0 && !((phys >> (2 * d)) & 1)) in = false;
+          if (idx[d] == order && !((phys >> (2 * d + 1)) & 1)) in = false;
+        }
         (in ? interior : boundary).push_back(n);
       }
 }
@@ -896,7 +903,15 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
       return SCDG_ERR_ARG;
     }
     const int P = N + 1;
-    p.ni[e] = kNvar * (N - 1) * (N - 1) * (N - 1);
+    const int phys = s->phys_faces ? s->phys_faces[e] : 0;
+    if (phys & 0xC0) {
+      g_create_error = "phys_faces: bits 6 and 7 must be zero";
+      delete pl;
+      return SCDG_ERR_ARG;
+    }
+    std::vector<int> in_n, b_n;
+    local_node_sets(N, phys, in_n, b_n);
+    p.ni[e] = kNvar * (int32_t)in_n.size();
     p.nc[e] = (int32_t)(kNvar * cnt);
     p.off_q[e + 1] = p.off_q[e] + (int64_t)kNvar * P * P * P;
     p.off_ii[e + 1] = p.off_ii[e] + (int64_t)p.ni[e] * p.ni[e];
@@ -904,7 +919,7 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
     p.off_cc[e + 1] = p.off_cc[e] + (int64_t)p.nc[e] * p.nc[e];
     p.off_i[e + 1] = p.off_i[e] + p.ni[e];
     p.off_c[e + 1] = p.off_c[e] + p.nc[e];
-    p.bnode_off[e + 1] = p.bnode_off[e] + (int64_t)P * P * P - (int64_t)(N - 1) * (N - 1) * (N - 1);
+    p.bnode_off[e + 1] = p.bnode_off[e] + (int64_t)b_n.size();
     p.max_ni = std::max(p.max_ni, p.ni[e]);
     p.max_nc = std::max(p.max_nc, p.nc[e]);
   }
@@ -940,11 +955,13 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   std::vector<int32_t> imap(p.n2), bmap(p.n1), cmap(p.off_c[E]);
   std::vector<int> in_nodes, b_nodes;
   std::vector<int32_t> pull_cnt(p.n_bnodes + 1, 0);
-  int cur_order = -1;
+  int cur_order = -1, cur_phys = -1;
   for (int e = 0; e < E; ++e) {
-    if (p.order[e] != cur_order) {
-      local_node_sets(p.order[e], in_nodes, b_nodes);
+    const int phys = s->phys_faces ? s->phys_faces[e] : 0;
+    if (p.order[e] != cur_order || phys != cur_phys) {
+      local_node_sets(p.order[e], phys, in_nodes, b_nodes);
       cur_order = p.order[e];
+      cur_phys = phys;
     }
     for (size_t t = 0; t < in_nodes.size(); ++t)
       for (int v = 0; v < kNvar; ++v)

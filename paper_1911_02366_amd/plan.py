@@ -35,7 +35,7 @@ def _stream(stream) -> int:
 class Plan:
     """Owns one scdg_plan.  Call order: assemble -> factor -> condense -> solve*."""
 
-    def __init__(self, order, c_ptr, c_node, bb_rowptr, bb_col, stream=None):
+    def __init__(self, order, c_ptr, c_node, bb_rowptr, bb_col, stream=None, phys_faces=None):
         self.lib = L.load()
         self._host = dict(
             order=np.ascontiguousarray(order, dtype=np.int32),
@@ -45,9 +45,14 @@ class Plan:
             bb_col=np.ascontiguousarray(bb_col, dtype=np.int32),
         )
         h = self._host
+        if phys_faces is not None:
+            h["phys_faces"] = np.ascontiguousarray(phys_faces, dtype=np.uint8)
+            if h["phys_faces"].shape != h["order"].shape:
+                raise ValueError("phys_faces: one mask per element")
         s = L.Structure(len(h["order"]), h["order"].ctypes.data, h["c_ptr"].ctypes.data,
                         h["c_node"].ctypes.data, h["bb_rowptr"].ctypes.data,
-                        h["bb_col"].ctypes.data if len(h["bb_col"]) else None)
+                        h["bb_col"].ctypes.data if len(h["bb_col"]) else None,
+                        h["phys_faces"].ctypes.data if phys_faces is not None else None)
         handle = C.c_void_p()
         st = self.lib.scdg_plan_create(C.byref(handle), C.byref(s), _stream(stream))
         if st != L.SCDG_OK:
@@ -63,7 +68,8 @@ class Plan:
 
     @classmethod
     def from_structure(cls, st: dict, stream=None) -> "Plan":
-        return cls(st["order"], st["c_ptr"], st["c_node"], st["bb_rowptr"], st["bb_col"], stream)
+        return cls(st["order"], st["c_ptr"], st["c_node"], st["bb_rowptr"], st["bb_col"], stream,
+                   st.get("phys_faces"))
 
     def _check(self, st: int, where: str):
         if st != L.SCDG_OK:

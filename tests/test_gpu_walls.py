@@ -1,0 +1,104 @@
+"""Condensed solves with physical boundaries through the C ABI: isothermal
+no-slip walls on the two faces normal to z, the wall-face DOFs in Q_i (the
+achievable ratio, Section 3.2), element sizes that differ between wall and
+inner elements (the plan reads them from scdg_structure.phys_faces).
+
+Expected values come from the oracle: the global matrix assembled from the
+blocks with the same physical-face masks, solved by SuperLU (eq.
+NewtonLinSys1).  FP64: relative error <= 1e-10; FP32 factors with FP64
+refinement: host full residual <= 1e-8 and error <= 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import DEV, rel, to_np
+from paper_1911_02366_amd import Plan
+from workload.walls import build_wall_case
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "k2n3": dict(k_elem=2, order=3, reynolds=100.0, dt=1e-2),     # every element touches both walls
+    "k3n4": dict(k_elem=3, order=4, reynolds=400.0, dt=1e-2),     # wall and inner elements mixed
+    "k2n5": dict(k_elem=2, order=5, reynolds=1600.0, dt=5e-3),    # n_i = 480: blocked inverse
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def setup(request):
+    torch.cuda.init()
+    print(f"\n[wall case {request.param}: generation on the device]", flush=True)
+    case = build_wall_case(seed=3, device=DEV, **CASES[request.param])
+    eb = case.element_blocks()
+    h = dict(order=case.order, c_ptr=case.c_ptr, c_node=case.c_node, bb_rowptr=case.bb_rowptr,
+             bb_col=case.bb_col, bb_val=eb["bb_val"], aii=eb["aii"], aib=eb["aib"], abi=eb["abi"])
+    a = oracle.assemble_global(*[h[k] for k in ("order", "c_ptr", "c_node", "bb_rowptr", "bb_col", "bb_val",
+                                                "aii", "aib", "abi")], phys=case.phys_faces)
+    b = to_np(case.rhs)
+    ref = oracle.solve_sparse(a, b)
+    yield request.param, case, h, a, b, ref
+
+
+def _plan(case, precision="fp64"):
+    plan = Plan.from_structure(case.structure())
+    plan.assemble(case.aii, case.aib, case.abi, case.bb_val)
+    plan.factor(precision)
+    plan.condense()
+    return plan
+
+
+def test_wall_plan_sizes_follow_the_physical_faces(setup):
+    name, case, h, a, b, ref = setup
+    plan = _plan(case)
+    assert (plan.n_dof, plan.n1, plan.n2, plan.n_bnodes) == (case.n_dof, case.n1, case.n2, case.n_bnodes)
+    ratio = plan.n1 / plan.n_dof
+    k, n = case.mesh.k_elem, case.mesh.order
+    assert ratio == pytest.approx(oracle.achievable_ratio(k, n), rel=1e-15)
+    assert ratio < oracle.achievable_ratio(k, n, ())
+    print(f"{name}: n1 / (n1 + n2) = {ratio:.4f} (no walls {oracle.achievable_ratio(k, n, ()):.4f}), "
+          f"n_i {sorted(set(case.n_i.tolist()))}, inverse form {plan.inverse_mode_used()}", flush=True)
+    plan.close()
+
+
+@pytest.mark.parametrize("solver,precond", [("dense", 1), ("gmres", 1), ("gmres", 2)])
+def test_wall_fp64_solve(setup, solver, precond):
+    name, case, h, a, b, ref = setup
+    if solver == "dense" and case.n1 > 8192:
+        pytest.skip("dense LU of S only for small condensed systems")
+    plan = _plan(case)
+    dq, info = plan.solve(case.rhs, solver=solver, precond=precond, tol=1e-13, ir_tol=1e-12)
+    print(name, solver, precond, info, flush=True)
+    x = to_np(dq)
+    assert rel(x, ref) <= 1e-10, info
+    r = oracle.full_residual(a, x, b)
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b)
+    # mass: no mass crosses a wall, so the increment keeps the total mass
+    m = case.mass * x.reshape(-1, 5)[:, 0]
+    assert abs(m.sum()) <= 1e-11 * np.abs(m).sum()
+    plan.close()
+
+
+def test_wall_residual_and_schur_parity(setup):
+    name, case, h, a, b, ref = setup
+    plan = _plan(case)
+    x = np.random.default_rng(5).standard_normal(case.n_dof)
+    r = torch.empty(case.n_dof, dtype=torch.float64, device=DEV)
+    plan.residual(case.rhs, torch.tensor(x, device=DEV), r)
+    assert rel(to_np(r), oracle.full_residual(a, x, b)) <= 1e-13
+    bs = plan.condense_rhs(case.rhs)
+    ref_bs = oracle.condensed_rhs(h["order"], h["c_ptr"], h["c_node"], h["aii"], h["abi"], b, phys=case.phys_faces)
+    assert rel(to_np(bs), ref_bs) <= 1e-12
+    plan.close()
+
+
+def test_wall_fp32_refinement(setup):
+    name, case, h, a, b, ref = setup
+    plan = _plan(case, "fp32")
+    dq, info = plan.solve(case.rhs, solver="gmres", tol=1e-6, ir_tol=1e-8)
+    x = to_np(dq)
+    res = float(np.linalg.norm(oracle.full_residual(a, x, b)) / np.linalg.norm(b))
+    print(name, info, f"host residual {res:.2e}", flush=True)
+    assert info["rel_res_full"] <= 1e-8 and res <= 1e-8
+    assert rel(x, ref) <= 1e-5
+    plan.close()

@@ -105,6 +105,33 @@ class CurvedGeometry:
         self.wt = w[:, None] * w[None, :]                                # transverse weights
 
 
+def wall_ghost(q: torch.Tensor, prm: FlowParams, t_wall: float) -> torch.Tensor:
+    """Outer state of an isothermal no-slip wall (the Dirichlet condition
+    q^-(q^+) of Section 2.1.1): density kept, momentum reversed,
+    rho E^- = 2 rho e_w - rho E^+ (e_w: internal energy at t_wall), so that
+    1/2 (q^+ + q^-) is the wall state (at rest, temperature t_wall)."""
+    e_w = t_wall / (prm.gamma * (prm.gamma - 1.0) * prm.mach ** 2)
+    return torch.stack([q[..., 0], -q[..., 1], -q[..., 2], -q[..., 3], 2.0 * e_w * q[..., 0] - q[..., 4]],
+                       dim=-1)
+
+
+def _with_walls(face: torch.Tensor, d: int, wall_lo, wall_hi) -> torch.Tensor:
+    """Replace the face values [..., Kz, Ky, Kx, P, P, 5] of the first (wall_lo)
+    and last (wall_hi) element layers along d; None leaves a layer unchanged."""
+    ax = _ELEM[d] + 1                       # face arrays lack the node axis of d
+    parts = list(torch.unbind(face, dim=ax))
+    if wall_lo is not None:
+        parts[0] = wall_lo
+    if wall_hi is not None:
+        parts[-1] = wall_hi
+    return torch.stack(parts, dim=ax)
+
+
+def _layer(a: torch.Tensor, d: int, index: int, face: bool = True) -> torch.Tensor:
+    """Elements at position `index` along d of a face array (face=True) or node field."""
+    return a.select(_ELEM[d] + (1 if face else 0), index)
+
+
 def _normal_speed(q: torch.Tensor, nh: torch.Tensor, prm: FlowParams) -> torch.Tensor:
     """|v . n_hat| + c, with |.| and its complex-step derivative through Re."""
     rho, u, v, w, p = primitives(q, prm)
@@ -123,8 +150,10 @@ def llf_normal(q_in: torch.Tensor, q_out: torch.Tensor, nvec: torch.Tensor, prm:
     return 0.5 * f - 0.5 * (lam * s)[..., None] * (q_out - q_in)
 
 
-def lifted_gradient(q: torch.Tensor, geo: CurvedGeometry):
-    """BR1 gradient on curved elements: (dq/dx, dq/dy, dq/dz), each shaped like q."""
+def lifted_gradient(q: torch.Tensor, geo: CurvedGeometry, walls=None, prm: FlowParams | None = None):
+    """BR1 gradient on curved elements: (dq/dx, dq/dy, dq/dz), each shaped like q.
+    walls = (d, t_wall): isothermal no-slip walls on the domain faces normal to
+    d, whose outer value is wall_ghost of the inner one (prm needed)."""
     n = geo.mesh.order
     vw = geo.vw.to(q.dtype)
     wt = geo.wt[:, :, None, None]
@@ -133,6 +162,9 @@ def lifted_gradient(q: torch.Tensor, geo: CurvedGeometry):
         ql = _along(q, i)
         right = _along(_shift(q, i, +1), i)[..., 0, :]
         left = _along(_shift(q, i, -1), i)[..., n, :]
+        if walls is not None and walls[0] == i:
+            right = _with_walls(right, i, None, wall_ghost(_layer(ql[..., n, :], i, -1), prm, walls[1]))
+            left = _with_walls(left, i, wall_ghost(_layer(ql[..., 0, :], i, 0), prm, walls[1]), None)
         for c in range(3):
             jl = _along(geo.ja[..., i, c][..., None], i)                 # [K,K,K,P,P,P(l),1]
             t = (vw @ (jl * ql)) * wt
@@ -144,12 +176,16 @@ def lifted_gradient(q: torch.Tensor, geo: CurvedGeometry):
     return tuple(gc / m for gc in g)
 
 
-def operator_h(q: torch.Tensor, geo: CurvedGeometry, prm: FlowParams) -> torch.Tensor:
-    """H(Q) on curved elements (mass-weighted, same shape as q)."""
+def operator_h(q: torch.Tensor, geo: CurvedGeometry, prm: FlowParams, walls=None) -> torch.Tensor:
+    """H(Q) on curved elements (mass-weighted, same shape as q).  walls = (d,
+    t_wall): on the two wall faces normal to d the face flux is the
+    Lax-Friedrichs flux between the inner state and its wall_ghost minus the
+    viscous flux of the wall state 1/2 (q^+ + q^-) with the inner gradient,
+    along the face vector J a^d of the element itself."""
     n = geo.mesh.order
     vw = geo.vw.to(q.dtype)
     wt = geo.wt[:, :, None, None]
-    g = lifted_gradient(q, geo)
+    g = lifted_gradient(q, geo, walls, prm)
     st = viscous_stress(q, g, prm)
     f = [flux_adv(q, c, prm) - viscous_flux_of(st, c, prm) for c in range(3)]
     h = torch.zeros_like(q)
@@ -166,6 +202,18 @@ def operator_h(q: torch.Tensor, geo: CurvedGeometry, prm: FlowParams) -> torch.T
                    for c in range(3))
         f_hat = llf_normal(q_in, q_out, nvec, prm) - 0.5 * visc
         f_left = torch.roll(f_hat, 1, dims=_ELEM[i] + 1)                 # face arrays lack the d node axis
+        if walls is not None and walls[0] == i:
+            fw = []
+            for l, idx in ((n, -1), (0, 0)):
+                qi = _layer(_along(q, i)[..., l, :], i, idx)
+                gi = tuple(_layer(_along(gc, i)[..., l, :], i, idx) for gc in g)
+                nv = _layer(_along(geo.ja[..., i, :], i)[..., l, :], i, idx)
+                qg = wall_ghost(qi, prm, walls[1])
+                adv = llf_normal(qi, qg, nv, prm) if l == n else llf_normal(qg, qi, nv, prm)
+                stw = viscous_stress(0.5 * (qi + qg), gi, prm)
+                fw.append(adv - sum(nv[..., c, None] * viscous_flux_of(stw, c, prm) for c in range(3)))
+            f_hat = _with_walls(f_hat, i, None, fw[0])
+            f_left = _with_walls(f_left, i, fw[1], None)
         t = t.clone()
         t[..., n, :] += geo.wt[:, :, None] * f_hat
         t[..., 0, :] -= geo.wt[:, :, None] * f_left
@@ -185,19 +233,22 @@ class CurvedJacobianParts:
     couplings to other elements (the input format of the block partition)."""
 
     def __init__(self, q: torch.Tensor, geo: CurvedGeometry, prm: FlowParams, dt: float,
-                 max_batch: int | None = None):
+                 max_batch: int | None = None, walls=None, progress=None):
         mesh = geo.mesh
         self.mesh, self.prm, self.dt, self.device = mesh, prm, dt, q.device
         k, p = mesh.k_elem, mesh.p
         p3, ne = p ** 3, mesh.n_elem
         nloc = 5 * p3
         q = q.reshape(mesh.shape()).to(torch.float64)
-        m = _colour_modulus(k)
+        # colour moduli per direction (x, y, z): a divisor >= 3 of K where the mesh
+        # wraps around, any m >= 3 across walls (elements there do not wrap)
+        mods = [3 if (walls is not None and walls[0] == d and k >= 3) else _colour_modulus(k) for d in range(3)]
         dev = q.device
         idx = torch.arange(k, device=dev)
         iz, iy, ix = torch.meshgrid(idx, idx, idx, indexing="ij")
-        colour = ((iz % m) * m + (iy % m)) * m + (ix % m)
+        colour = ((iz % mods[2]) * mods[1] + (iy % mods[1])) * mods[0] + (ix % mods[0])
         colour = colour.reshape(-1)
+        n_colours = mods[0] * mods[1] * mods[2]
         # distinct neighbour offsets after the periodic wrap
         offs, seen = [], set()
         for oz in (-1, 0, 1):
@@ -216,8 +267,10 @@ class CurvedJacobianParts:
         rows, cols, vals = [], [], []
         nid = torch.arange(ne * p3, device=dev).reshape(ne, p3)
         qc = q.to(torch.complex128)
-        for col in range(m ** 3):
+        for col in range(n_colours):
             elems = torch.nonzero(colour == col).reshape(-1)
+            if progress is not None:
+                progress(col, n_colours)
             if elems.numel() == 0:
                 continue
             for j0 in range(0, nloc, max_batch):
@@ -226,7 +279,7 @@ class CurvedJacobianParts:
                 x = qc.expand((b,) + tuple(qc.shape)).clone().reshape(b, ne, p3 * 5)
                 jj = torch.arange(j0, j1, device=dev)
                 x[jj[:, None] - j0, elems[None, :], jj[:, None]] += 1j * CS_STEP
-                hd = operator_h(x.reshape((b,) + mesh.shape()), geo, prm).imag / CS_STEP
+                hd = operator_h(x.reshape((b,) + mesh.shape()), geo, prm, walls).imag / CS_STEP
                 hd = hd.reshape(b, ne, p3 * 5)                           # [cols j, row elem, row (n, v)]
                 self.own[elems, :, j0:j1] = hd[:, elems, :].permute(1, 2, 0)
                 for nb in nbr:
