@@ -270,7 +270,7 @@ scdg_status scdg_get_gemm_config(const scdg_plan *p, int32_t *cfg_x, int32_t *cf
  *
  * H the GL-DGSEM operator of eq. DGSEMsystem for the compressible
  * Navier-Stokes equations (Appendix B fluxes, local Lax-Friedrichs advective
- * flux, Bassi-Rebay 1 viscous flux and lifted gradient), M the diagonal mass
+ * flux, Bassi-Rebay 1 or interior-penalty viscous flux and lifted gradient), M the diagonal mass
  * matrix J w_i w_j w_k, on a periodic Cartesian mesh of K^3 cubes of side
  * length / K with uniform order N.  B = -R(Q~) is the right-hand side of the
  * Newton system that scdg_solve solves (eq. NewtonLinSys1).
@@ -293,7 +293,20 @@ typedef struct {
   double mach, reynolds;    /* reference Mach and Reynolds numbers (> 0) */
   double gamma, prandtl;    /* <= 0 selects 1.4 / 0.72 */
   double sutherland_ratio;  /* T_suth / T_ref; <= 0 selects 110.4 / 288.15 */
+  int32_t viscous_flux;     /* SCDG_VISCOUS_BR1 (0) or SCDG_VISCOUS_SIPG (1), see below */
+  double sipg_eta;          /* interior-penalty factor eta (>= 0; 0 selects 1) */
 } scdg_dg_params;
+/* Face viscous flux.  BR1 (Bassi-Rebay 1): {{f^nu(q, g)}} with the lifted
+ * gradients g of both sides.  SIPG (symmetric interior penalty, the paper's
+ * choice for its example, Section 4; a compact flux, Section 3.1): the volume
+ * term keeps the lifted gradient, whose surface value {{q}} supplies the
+ * symmetric term, and the face flux is
+ *     {{f^nu(q, grad q)}} + sigma f^nu({{q}}, [[q]] n),
+ * with grad q each side's broken gradient (the derivative of its own
+ * interpolant), [[q]] = q^- - q^+ taken as a gradient along the face normal n,
+ * sigma = eta (N + 1)^2 / h.  SIPG needs Cartesian cubes (scdg_dg_set_geometry
+ * returns SCDG_ERR_UNSUPPORTED) and keeps a second gradient workspace. */
+enum { SCDG_VISCOUS_BR1 = 0, SCDG_VISCOUS_SIPG = 1 };
 /* Create on the current device; HIP stream may be NULL (default stream).
  * SCDG_ERR_ARG for out-of-range parameters, SCDG_ERR_NOMEM on allocation. */
 scdg_status scdg_dg_create(scdg_dg **out, const scdg_dg_params *prm, void *hip_stream);
@@ -349,7 +362,8 @@ scdg_status scdg_dg_jacobian_apply(scdg_dg *dg, const double *q, const double *v
  * undefined results; calls ordered on one stream are safe (the array needs no
  * clearing: each call writes all of the part it reads).
  * SCDG_ERR_UNSUPPORTED when the mesh needs more than the array holds
- * (15 * 8 bytes per node: at most 559 240 nodes, e.g. 16^3 elements of order 4);
+ * (15 * 8 bytes per node: at most 559 240 nodes, e.g. 16^3 elements of order 4)
+ * or the object uses the interior-penalty flux (SCDG_VISCOUS_SIPG);
  * SCDG_ERR_ARG as for scdg_dg_jacobian_apply; SCDG_ERR_HIP if the array's
  * address could not be found on the object's device. */
 #define SCDG_NOALLOC_SCRATCH_BYTES (64ll << 20)

@@ -19,6 +19,15 @@ What it computes, with the paper's notation:
     (x sign(Re x), comparison of real parts), with the same values as np.abs
     and np.maximum on real input.
 
+  * optionally (viscous="sipg") the symmetric interior penalty viscous flux,
+    the paper's choice for its example (Section 4): the volume term keeps the
+    lifted gradient (whose surface value {{q}} carries the symmetric term),
+    and the face flux is compact,
+        f_hat^nu = {{f^nu(q, grad q)}} + sigma f^nu({{q}}, [[q]] n),
+    the average of each side's viscous flux with its own (broken) gradient
+    of the nodal interpolant, plus a penalty: the viscous flux of the mean
+    state applied to the jump q^- - q^+ taken as a gradient along the face
+    normal, scaled by sigma = eta (N + 1)^2 / h;
   * optional isothermal no-slip walls (Walls) on the two domain faces normal
     to one direction, the mesh staying periodic in the other two: the outer
     state of a wall face is the function q^-(q^+) of Section 2.1.1 (the
@@ -310,9 +319,44 @@ def wall_fluxes(q: np.ndarray, g: np.ndarray, d: int, flow: Flow, walls: Walls):
     return out[0], out[1]
 
 
-def operator_h(q: np.ndarray, grid: Grid, flow: Flow, walls: Walls | None = None) -> np.ndarray:
+def broken_gradient(q: np.ndarray, grid: Grid) -> np.ndarray:
+    """Element-local gradient of the nodal interpolant at the nodes (no surface
+    term): along each direction d, (2/h) sum_a D[l][a] q_a on the d-line; [..., 3, 5]."""
+    x, _ = gl_rule(grid.order)
+    dm = lagrange_derivative(x)
+    scale = 2.0 / grid.h
+    g = np.zeros(q.shape[:-1] + (3, NVAR), dtype=q.dtype)
+    for d in range(3):
+        g[..., d, :] = _line_back(scale * np.einsum("la,...av->...lv", dm, _line_last(q, d)), d)
+    return g
+
+
+SIPG_ETA = 1.0
+
+
+def sipg_penalty(grid: Grid, eta: float | None = None) -> float:
+    """sigma = eta (N + 1)^2 / h (eta: SIPG_ETA unless given)."""
+    return (SIPG_ETA if eta is None else eta) * (grid.order + 1) ** 2 / grid.h
+
+
+def sipg_viscous_flux(q_in, gb_in, q_out, gb_out, d: int, flow: Flow, sigma: float) -> np.ndarray:
+    """Compact viscous flux through a +e_d face (q_in on the side the normal leaves):
+    {{f^nu_d(q, grad q)}} + sigma f^nu_d({{q}}, [[q]] e_d), [[q]] = q_out - q_in."""
+    jump = np.zeros(q_in.shape[:-1] + (3, NVAR), dtype=np.result_type(q_in, q_out))
+    jump[..., d, :] = q_out - q_in
+    return 0.5 * (viscous_flux(q_in, gb_in, d, flow) + viscous_flux(q_out, gb_out, d, flow)) \
+        + sigma * viscous_flux(0.5 * (q_in + q_out), jump, d, flow)
+
+
+def operator_h(q: np.ndarray, grid: Grid, flow: Flow, walls: Walls | None = None,
+               viscous: str = "br1") -> np.ndarray:
     """H(Q) of eq. DiscretNS from eq. DGSEMsystem:1 (mass-weighted, same layout as q);
-    optional isothermal no-slip walls (wall_fluxes on their faces)."""
+    optional isothermal no-slip walls (wall_fluxes on their faces); viscous face
+    flux "br1" (Bassi-Rebay 1) or "sipg" (symmetric interior penalty)."""
+    if viscous not in ("br1", "sipg"):
+        raise ValueError(viscous)
+    if viscous == "sipg" and walls is not None:
+        raise NotImplementedError("walls with the interior-penalty flux")
     x, w = gl_rule(grid.order)
     dm = lagrange_derivative(x)
     n = grid.order
@@ -320,6 +364,7 @@ def operator_h(q: np.ndarray, grid: Grid, flow: Flow, walls: Walls | None = None
     jac_face = (grid.h / 2.0) ** 2
     scale = 2.0 / grid.h
     g = lifted_gradient(q, grid, walls, flow)
+    gb = broken_gradient(q, grid) if viscous == "sipg" else None
     h = np.zeros_like(q)
     for d in range(3):
         f = euler_flux(q, d, flow) - viscous_flux(q, g, d, flow)
@@ -331,8 +376,14 @@ def operator_h(q: np.ndarray, grid: Grid, flow: Flow, walls: Walls | None = None
         q_out = _line_last(_neighbour(q, d, +1), d)[..., 0, :]
         g_in = np.moveaxis(g, 5 - d, -3)[..., n, :, :]
         g_out = np.moveaxis(_neighbour(g, d, +1), 5 - d, -3)[..., 0, :, :]
-        f_hat = lax_friedrichs(q_in, q_out, d, flow) \
-            - 0.5 * (viscous_flux(q_in, g_in, d, flow) + viscous_flux(q_out, g_out, d, flow))
+        if viscous == "sipg":
+            gb_in = np.moveaxis(gb, 5 - d, -3)[..., n, :, :]
+            gb_out = np.moveaxis(_neighbour(gb, d, +1), 5 - d, -3)[..., 0, :, :]
+            f_hat = lax_friedrichs(q_in, q_out, d, flow) \
+                - sipg_viscous_flux(q_in, gb_in, q_out, gb_out, d, flow, sipg_penalty(grid))
+        else:
+            f_hat = lax_friedrichs(q_in, q_out, d, flow) \
+                - 0.5 * (viscous_flux(q_in, g_in, d, flow) + viscous_flux(q_out, g_out, d, flow))
         f_hat_left = _neighbour(f_hat, d, -1)       # each element's -e_d face is its left neighbour's +e_d face
         if walls is not None and walls.d == d:
             f_hi, f_lo = wall_fluxes(q, g, d, flow, walls)
@@ -347,9 +398,9 @@ def operator_h(q: np.ndarray, grid: Grid, flow: Flow, walls: Walls | None = None
 
 
 def residual(q: np.ndarray, grid: Grid, flow: Flow, q_s: np.ndarray | None = None,
-             dt: float | None = None, walls: Walls | None = None) -> np.ndarray:
+             dt: float | None = None, walls: Walls | None = None, viscous: str = "br1") -> np.ndarray:
     """R(Q) = M (Q - Q_s) / dt + H(Q); without q_s, H(Q)."""
-    h = operator_h(q, grid, flow, walls)
+    h = operator_h(q, grid, flow, walls, viscous)
     if q_s is None:
         return h
     return mass(grid)[..., None] * (q - q_s) / dt + h
@@ -359,15 +410,15 @@ CS_STEP = 1e-30
 
 
 def jacobian_apply(q: np.ndarray, v: np.ndarray, grid: Grid, flow: Flow, dt: float | None = None,
-                   walls: Walls | None = None) -> np.ndarray:
+                   walls: Walls | None = None, viscous: str = "br1") -> np.ndarray:
     """A v = (M / dt + dH/dQ(q)) v, the Newton matrix of eq. NewtonLinSys1 at q
     applied to v (without dt: dH/dQ(q) v), by complex-step differentiation of
     the residual: Im R(q + i h v) / h with h = 1e-30, exact to rounding (no
     subtraction of nearby values)."""
     qc = q.astype(np.complex128) + 1j * CS_STEP * v
     if dt is None:
-        return operator_h(qc, grid, flow, walls).imag / CS_STEP
-    return residual(qc, grid, flow, q_s=q, dt=dt, walls=walls).imag / CS_STEP
+        return operator_h(qc, grid, flow, walls, viscous).imag / CS_STEP
+    return residual(qc, grid, flow, q_s=q, dt=dt, walls=walls, viscous=viscous).imag / CS_STEP
 
 
 def wall_face_mask(k_elem: int, walls: Walls | None) -> np.ndarray:

@@ -49,7 +49,8 @@ class Structure(C.Structure):
 class DgParams(C.Structure):
     _fields_ = [("k_elem", C.c_int32), ("order", C.c_int32), ("length", C.c_double),
                 ("mach", C.c_double), ("reynolds", C.c_double), ("gamma", C.c_double),
-                ("prandtl", C.c_double), ("sutherland_ratio", C.c_double)]
+                ("prandtl", C.c_double), ("sutherland_ratio", C.c_double), ("viscous_flux", C.c_int32),
+                ("sipg_eta", C.c_double)]
 
 
 class MlpShape(C.Structure):

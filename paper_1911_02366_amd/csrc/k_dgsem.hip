@@ -34,7 +34,9 @@ constexpr int kMaxP = kMaxOrder + 1;
 
 struct DgParams {
   int k_elem, p;
+  int sipg;                  // 1: interior-penalty face viscous flux (else Bassi-Rebay 1)
   double s, jac, gamma, mach2, inv_re, prandtl, suth;
+  double sigma;              // interior-penalty factor eta (N + 1)^2 / h
   double w[kMaxP];
   double d[kMaxP][kMaxP];    // D[l][a] = l_a'(x_l)
   double vw[kMaxP][kMaxP];   // -w_a D[a][l]
@@ -163,6 +165,33 @@ __device__ void face_flux(const T ql[5], const T gl[15], const T qr[5], const T 
     fh[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * lam * (qr[v] - ql[v]) - 0.5 * (vl[v] + vr[v]);
 }
 
+// total numerical flux through a +e_d face with the symmetric interior penalty
+// viscous flux: LLF advective minus
+//   {{f^nu_d(q, grad q)}} + sigma f^nu_d({{q}}, [[q]] e_d),
+// grad q the broken (element-local) gradients bl, br of the two sides and
+// [[q]] = qr - ql taken as a gradient along the face normal
+template <class T>
+__device__ void face_flux_sipg(const T ql[5], const T bl[15], const T qr[5], const T br[15], int d,
+                               const DgParams &P, T fh[5]) {
+  T fl[5], fr[5], vl[5], vr[5], vp[5], qm[5], jg[15];
+  flux_adv(ql, d, P.gamma, fl);
+  flux_adv(qr, d, P.gamma, fr);
+  const Prim<T> a = prim(ql, P.gamma), b = prim(qr, P.gamma);
+  const T lam_l = vabs(a.u[d]) + vsqrt(P.gamma * a.p / a.rho);
+  const T lam_r = vabs(b.u[d]) + vsqrt(P.gamma * b.p / b.rho);
+  const T lam = lam_l >= lam_r ? lam_l : lam_r;
+  flux_visc(ql, bl, d, P, vl);
+  flux_visc(qr, br, d, P, vr);
+  for (int t = 0; t < 15; ++t) jg[t] = 0.0;
+  for (int v = 0; v < 5; ++v) {
+    qm[v] = 0.5 * (ql[v] + qr[v]);
+    jg[d * 5 + v] = qr[v] - ql[v];
+  }
+  flux_visc(qm, jg, d, P, vp);
+  for (int v = 0; v < 5; ++v)
+    fh[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * lam * (qr[v] - ql[v]) - 0.5 * (vl[v] + vr[v]) - P.sigma * vp[v];
+}
+
 // total numerical flux along the unnormalized face normal nv (curved faces):
 // sum_d nv_d {{f^a_d}} - lambda |nv| [[q]] / 2 - sum_d nv_d {{f^nu_d}},
 // lambda the larger of |v . nv| / |nv| + c on the two sides
@@ -210,8 +239,10 @@ __device__ __forceinline__ int node_with(int node, int p, int d, int l) {
   return c[0] + p * c[1] + p * p * c[2];
 }
 
+// BR1 lifted gradient g; with gb != NULL also the broken gradient of each
+// element's own interpolant (the same line derivatives without the surface term)
 __global__ __launch_bounds__(512) void lift_kernel(const DgParams *__restrict__ prm, const double *__restrict__ q,
-                            double *__restrict__ g) {
+                            double *__restrict__ g, double *__restrict__ gb) {
   __shared__ DgParams P;
   __shared__ double qs[kMaxP * kMaxP * kMaxP * 5];
   load_params(prm, &P);
@@ -230,6 +261,10 @@ __global__ __launch_bounds__(512) void lift_kernel(const DgParams *__restrict__ 
       double acc = 0.0;
       for (int a = 0; a < p; ++a) acc += P.d[l][a] * qs[node_with(node, p, d, a) * 5 + v];
       out[d * 5 + v] = acc;
+    }
+    if (gb) {
+      double *gbe = gb + ((int64_t)e * p3 + node) * 15 + d * 5;
+      for (int v = 0; v < 5; ++v) gbe[v] = P.s * out[d * 5 + v];
     }
     if (l == n) {
       const double *qn = q + ((int64_t)nbr_elem(e, P.k_elem, d, 1) * p3 + node_with(node, p, d, 0)) * 5;
@@ -387,7 +422,8 @@ __global__ __launch_bounds__(512) void residual_curved_kernel(const DgParams *__
 template <class T>
 __global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restrict__ prm, const double *__restrict__ q,
                                 const double *__restrict__ dq, const double *__restrict__ g,
-                                const double *__restrict__ dg, const double *__restrict__ q_s,
+                                const double *__restrict__ dg, const double *__restrict__ gbq,
+                                const double *__restrict__ dgb, const double *__restrict__ q_s,
                                 double inv_dt, double *__restrict__ r) {
   __shared__ DgParams P;
   extern __shared__ double fs[];   // [3][p3][5] volume fluxes
@@ -424,16 +460,30 @@ __global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restric
       const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, d, 1) * p3 + node_with(node, p, d, 0);
       T qb[5], gb[15], fh[5];
       for (int v = 0; v < 5; ++v) qb[v] = at<T>(q, dq, nb * 5 + v);
-      for (int t = 0; t < 15; ++t) gb[t] = at<T>(g, dg, nb * 15 + t);
-      face_flux(qn, gn, qb, gb, d, P, fh);
+      if (P.sipg) {
+        T bn[15];
+        for (int t = 0; t < 15; ++t) bn[t] = at<T>(gbq, dgb, ((int64_t)e * p3 + node) * 15 + t);
+        for (int t = 0; t < 15; ++t) gb[t] = at<T>(gbq, dgb, nb * 15 + t);
+        face_flux_sipg(qn, bn, qb, gb, d, P, fh);
+      } else {
+        for (int t = 0; t < 15; ++t) gb[t] = at<T>(g, dg, nb * 15 + t);
+        face_flux(qn, gn, qb, gb, d, P, fh);
+      }
       for (int v = 0; v < 5; ++v) rd[v] += part(fh[v]);
     }
     if (l == 0) {
       const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, d, -1) * p3 + node_with(node, p, d, n);
       T qb[5], gb[15], fh[5];
       for (int v = 0; v < 5; ++v) qb[v] = at<T>(q, dq, nb * 5 + v);
-      for (int t = 0; t < 15; ++t) gb[t] = at<T>(g, dg, nb * 15 + t);
-      face_flux(qb, gb, qn, gn, d, P, fh);
+      if (P.sipg) {
+        T bn[15];
+        for (int t = 0; t < 15; ++t) bn[t] = at<T>(gbq, dgb, ((int64_t)e * p3 + node) * 15 + t);
+        for (int t = 0; t < 15; ++t) gb[t] = at<T>(gbq, dgb, nb * 15 + t);
+        face_flux_sipg(qb, gb, qn, bn, d, P, fh);
+      } else {
+        for (int t = 0; t < 15; ++t) gb[t] = at<T>(g, dg, nb * 15 + t);
+        face_flux(qb, gb, qn, gn, d, P, fh);
+      }
       for (int v = 0; v < 5; ++v) rd[v] -= part(fh[v]);
     }
     for (int v = 0; v < 5; ++v) h[v] += rd[v] / P.w[l];
@@ -567,6 +617,8 @@ struct DgContext {
   DgParams *dev = nullptr;
   double *g = nullptr;
   double *gd = nullptr;    // lifted gradient of a direction (allocated by the first Newton-matrix product)
+  double *gb = nullptr;    // interior-penalty flux: broken gradient of the state (15 doubles per node)
+  double *gbd = nullptr;   // ... and of a direction (with gd)
   double *met = nullptr;   // curved elements: 10 doubles per node (NULL: Cartesian cubes)
   uint64_t geo_gen = 0;    // bumped by every geometry change: captured graphs keyed on it recapture
   int device = 0;          // the HIP device the object was created on
@@ -598,9 +650,9 @@ hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, doubl
                        c.dev, q, nullptr, c.g, nullptr, c.met, q_s, inv_dt, r);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g);
+  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g, c.gb);
   hipLaunchKernelGGL(residual_kernel<double>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
-                     nullptr, c.g, nullptr, q_s, inv_dt, r);
+                     nullptr, c.g, nullptr, c.gb, nullptr, q_s, inv_dt, r);
   return hipGetLastError();
 }
 
@@ -608,7 +660,7 @@ hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, doubl
 // lifting is linear), then the residual sums on dual numbers (value q,
 // direction v).  c.gd must hold 15 doubles per node.
 hipError_t dg_jacobian_apply_on(scdg_dg *dg, const double *q, const double *v, double inv_dt, double *out,
-                                hipStream_t s, double *gd) {
+                                hipStream_t s, double *gd, double *gbd) {
   auto &c = dg->c;
   const int p3 = c.host.p * c.host.p * c.host.p;
   const int n_elem = c.host.k_elem * c.host.k_elem * c.host.k_elem;
@@ -622,10 +674,10 @@ hipError_t dg_jacobian_apply_on(scdg_dg *dg, const double *q, const double *v, d
                        c.dev, q, v, c.g, gd, c.met, nullptr, inv_dt, out);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g);
-  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, v, gd);
+  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g, c.gb);
+  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, v, gd, gbd);
   hipLaunchKernelGGL(residual_kernel<Dual>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
-                     v, c.g, gd, nullptr, inv_dt, out);
+                     v, c.g, gd, c.gb, gbd, nullptr, inv_dt, out);
   return hipGetLastError();
 }
 
@@ -681,7 +733,9 @@ extern "C" {
 
 scdg_status scdg_dg_create(scdg_dg **out, const scdg_dg_params *prm, void *hip_stream) {
   if (!out || !prm || prm->k_elem < 2 || prm->order < 2 || prm->order > scdg::kMaxOrder ||
-      prm->length <= 0 || prm->mach <= 0 || prm->reynolds <= 0)
+      prm->length <= 0 || prm->mach <= 0 || prm->reynolds <= 0 ||
+      (prm->viscous_flux != SCDG_VISCOUS_BR1 && prm->viscous_flux != SCDG_VISCOUS_SIPG) ||
+      !(prm->sipg_eta >= 0.0) || !std::isfinite(prm->sipg_eta))
     return SCDG_ERR_ARG;
   scdg_dg *dg = new (std::nothrow) scdg_dg();
   if (!dg) return SCDG_ERR_NOMEM;
@@ -697,6 +751,8 @@ scdg_status scdg_dg_create(scdg_dg **out, const scdg_dg_params *prm, void *hip_s
   P.inv_re = 1.0 / prm->reynolds;
   P.prandtl = prm->prandtl > 0 ? prm->prandtl : 0.72;
   P.suth = prm->sutherland_ratio > 0 ? prm->sutherland_ratio : 110.4 / 288.15;
+  P.sipg = prm->viscous_flux == SCDG_VISCOUS_SIPG ? 1 : 0;
+  P.sigma = (prm->sipg_eta > 0 ? prm->sipg_eta : 1.0) * (prm->order + 1) * (prm->order + 1) / h;
   double x[scdg::kMaxP];
   scdg::gl_operators(prm->order, x, P.w, P.d);
   for (int l = 0; l < P.p; ++l)
@@ -712,9 +768,11 @@ scdg_status scdg_dg_create(scdg_dg **out, const scdg_dg_params *prm, void *hip_s
   (void)scdg::noalloc_resolve(c.device);
   if (hipMalloc(&c.dev, sizeof(scdg::DgParams)) != hipSuccess ||
       hipMalloc(&c.g, sizeof(double) * 15 * c.n_nodes) != hipSuccess ||
+      (P.sipg && hipMalloc(&c.gb, sizeof(double) * 15 * c.n_nodes) != hipSuccess) ||
       hipMemcpy(c.dev, &P, sizeof(scdg::DgParams), hipMemcpyHostToDevice) != hipSuccess) {
     if (c.dev) (void)hipFree(c.dev);
     if (c.g) (void)hipFree(c.g);
+    if (c.gb) (void)hipFree(c.gb);
     delete dg;
     return SCDG_ERR_NOMEM;
   }
@@ -728,6 +786,8 @@ scdg_status scdg_dg_destroy(scdg_dg *dg) {
   if (dg->c.dev) (void)hipFree(dg->c.dev);
   if (dg->c.g) (void)hipFree(dg->c.g);
   if (dg->c.gd) (void)hipFree(dg->c.gd);
+  if (dg->c.gb) (void)hipFree(dg->c.gb);
+  if (dg->c.gbd) (void)hipFree(dg->c.gbd);
   if (dg->c.met) (void)hipFree(dg->c.met);
   delete dg;
   return SCDG_OK;
@@ -746,14 +806,22 @@ scdg_status scdg_dg_jacobian_apply(scdg_dg *dg, const double *q, const double *v
     c.gd = nullptr;
     return SCDG_ERR_NOMEM;
   }
-  return scdg::dg_jacobian_apply_on(dg, q, v, inv_dt, out, c.stream, c.gd) == hipSuccess ? SCDG_OK
-                                                                                        : SCDG_ERR_HIP;
+  if (c.host.sipg && !c.gbd && hipMalloc(&c.gbd, sizeof(double) * 15 * c.n_nodes) != hipSuccess) {
+    c.gbd = nullptr;
+    return SCDG_ERR_NOMEM;
+  }
+  return scdg::dg_jacobian_apply_on(dg, q, v, inv_dt, out, c.stream, c.gd, c.gbd) == hipSuccess ? SCDG_OK
+                                                                                                : SCDG_ERR_HIP;
 }
 
 scdg_status scdg_dg_jacobian_apply_noalloc(scdg_dg *dg, const double *q, const double *v, double inv_dt,
                                            double *out) {
   if (!dg || !q || !v || !out || !(inv_dt >= 0.0) || !std::isfinite(inv_dt)) return SCDG_ERR_ARG;
   auto &c = dg->c;
+  if (c.host.sipg) {
+    c.last_error = "scdg_dg_jacobian_apply_noalloc: Bassi-Rebay 1 flux only";
+    return SCDG_ERR_UNSUPPORTED;
+  }
   if (15 * c.n_nodes > scdg::kNoAllocDoubles) {
     c.last_error = "scdg_dg_jacobian_apply_noalloc: the mesh needs " + std::to_string(15 * 8 * c.n_nodes) +
                    " bytes of gradient scratch, above the fixed " +
@@ -769,8 +837,8 @@ scdg_status scdg_dg_jacobian_apply_noalloc(scdg_dg *dg, const double *q, const d
       return SCDG_ERR_HIP;
     }
   }
-  return scdg::dg_jacobian_apply_on(dg, q, v, inv_dt, out, c.stream, gd) == hipSuccess ? SCDG_OK
-                                                                                     : SCDG_ERR_HIP;
+  return scdg::dg_jacobian_apply_on(dg, q, v, inv_dt, out, c.stream, gd, nullptr) == hipSuccess ? SCDG_OK
+                                                                                              : SCDG_ERR_HIP;
 }
 
 scdg_status scdg_dg_set_geometry(scdg_dg *dg, const double *xyz) {
@@ -782,6 +850,10 @@ scdg_status scdg_dg_set_geometry(scdg_dg *dg, const double *xyz) {
     c.met = nullptr;
     ++c.geo_gen;
     return SCDG_OK;
+  }
+  if (c.host.sipg) {
+    c.last_error = "curved elements with the interior-penalty flux are not supported";
+    return SCDG_ERR_UNSUPPORTED;
   }
   const int64_t n_elem = (int64_t)c.host.k_elem * c.host.k_elem * c.host.k_elem;
   std::vector<double> met;

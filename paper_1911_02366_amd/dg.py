@@ -21,9 +21,13 @@ class DgResidual:
 
     def __init__(self, k_elem: int, order: int, mach: float, reynolds: float,
                  length: float = 2.0 * math.pi, gamma: float = 1.4, prandtl: float = 0.72,
-                 sutherland_ratio: float = 110.4 / 288.15, stream=None):
+                 sutherland_ratio: float = 110.4 / 288.15, stream=None, viscous: str = "br1",
+                 sipg_eta: float = 1.0):
+        """viscous: face viscous flux, "br1" (Bassi-Rebay 1) or "sipg" (symmetric
+        interior penalty with sigma = sipg_eta (N + 1)^2 / h; Cartesian cubes only)."""
         self.lib = L.load()
-        prm = L.DgParams(k_elem, order, length, mach, reynolds, gamma, prandtl, sutherland_ratio)
+        vf = {"br1": 0, "sipg": 1}[viscous]
+        prm = L.DgParams(k_elem, order, length, mach, reynolds, gamma, prandtl, sutherland_ratio, vf, sipg_eta)
         handle = C.c_void_p()
         st = self.lib.scdg_dg_create(C.byref(handle), C.byref(prm), _stream(stream))
         if st != L.SCDG_OK:

@@ -45,10 +45,10 @@ class ImplicitStepper:
                  restart: int = 30, precond: int = 1, precision: str = "fp64", autotune: bool = True,
                  forcing: bool = True, fp32_inner_tol: float = 1e-4, graph: bool = False,
                  graph_cycles: int = 8, autotune_cache: str | None = None, xyz=None,
-                 schur_mode: str = "assembled"):
+                 schur_mode: str = "assembled", viscous: str = "br1"):
         self.plan = Plan.from_structure(structure)
         self.plan.set_schur_mode(schur_mode)     # "matrix_free": Schur products through X_e, A_bi, A_bb
-        self.dg = DgResidual(k_elem, order, mach=mach, reynolds=reynolds)
+        self.dg = DgResidual(k_elem, order, mach=mach, reynolds=reynolds, viscous=viscous)
         if xyz is not None:
             self.dg.set_geometry(xyz)            # curved hexahedra: the residual takes the metric terms
         self.dt, self.jacobian = dt, jacobian

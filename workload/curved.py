@@ -150,10 +150,14 @@ def llf_normal(q_in: torch.Tensor, q_out: torch.Tensor, nvec: torch.Tensor, prm:
     return 0.5 * f - 0.5 * (lam * s)[..., None] * (q_out - q_in)
 
 
-def lifted_gradient(q: torch.Tensor, geo: CurvedGeometry, walls=None, prm: FlowParams | None = None):
+def lifted_gradient(q: torch.Tensor, geo: CurvedGeometry, walls=None, prm: FlowParams | None = None,
+                    broken: bool = False):
     """BR1 gradient on curved elements: (dq/dx, dq/dy, dq/dz), each shaped like q.
     walls = (d, t_wall): isothermal no-slip walls on the domain faces normal to
-    d, whose outer value is wall_ghost of the inner one (prm needed)."""
+    d, whose outer value is wall_ghost of the inner one (prm needed).
+    broken=True: the element's own face values in place of the surface value
+    {{q}}, which by summation by parts is the gradient of the element's own
+    interpolant (no lifting)."""
     n = geo.mesh.order
     vw = geo.vw.to(q.dtype)
     wt = geo.wt[:, :, None, None]
@@ -162,6 +166,8 @@ def lifted_gradient(q: torch.Tensor, geo: CurvedGeometry, walls=None, prm: FlowP
         ql = _along(q, i)
         right = _along(_shift(q, i, +1), i)[..., 0, :]
         left = _along(_shift(q, i, -1), i)[..., n, :]
+        if broken:
+            right, left = ql[..., n, :], ql[..., 0, :]
         if walls is not None and walls[0] == i:
             right = _with_walls(right, i, None, wall_ghost(_layer(ql[..., n, :], i, -1), prm, walls[1]))
             left = _with_walls(left, i, wall_ghost(_layer(ql[..., 0, :], i, 0), prm, walls[1]), None)
@@ -176,16 +182,28 @@ def lifted_gradient(q: torch.Tensor, geo: CurvedGeometry, walls=None, prm: FlowP
     return tuple(gc / m for gc in g)
 
 
-def operator_h(q: torch.Tensor, geo: CurvedGeometry, prm: FlowParams, walls=None) -> torch.Tensor:
+SIPG_ETA = 1.0
+
+
+def operator_h(q: torch.Tensor, geo: CurvedGeometry, prm: FlowParams, walls=None,
+               viscous: str = "br1") -> torch.Tensor:
     """H(Q) on curved elements (mass-weighted, same shape as q).  walls = (d,
     t_wall): on the two wall faces normal to d the face flux is the
     Lax-Friedrichs flux between the inner state and its wall_ghost minus the
     viscous flux of the wall state 1/2 (q^+ + q^-) with the inner gradient,
-    along the face vector J a^d of the element itself."""
+    along the face vector J a^d of the element itself.  viscous="sipg": the face viscous flux is
+    the symmetric interior penalty flux of a Cartesian mesh, the average of each
+    side's viscous flux with its own broken gradient plus sigma times the
+    viscous flux of the mean state applied to the jump taken as a gradient
+    along the face normal, sigma = eta (N + 1)^2 / h (walls not supported)."""
+    if viscous not in ("br1", "sipg") or (viscous == "sipg" and walls is not None):
+        raise ValueError(f"viscous flux {viscous} with walls={walls}")
     n = geo.mesh.order
     vw = geo.vw.to(q.dtype)
     wt = geo.wt[:, :, None, None]
     g = lifted_gradient(q, geo, walls, prm)
+    gb = lifted_gradient(q, geo, broken=True) if viscous == "sipg" else None
+    sigma = SIPG_ETA * (n + 1) ** 2 / geo.mesh.h
     st = viscous_stress(q, g, prm)
     f = [flux_adv(q, c, prm) - viscous_flux_of(st, c, prm) for c in range(3)]
     h = torch.zeros_like(q)
@@ -197,9 +215,17 @@ def operator_h(q: torch.Tensor, geo: CurvedGeometry, prm: FlowParams, walls=None
         g_in = tuple(_along(gc, i)[..., n, :] for gc in g)
         g_out = tuple(_along(_shift(gc, i, +1), i)[..., 0, :] for gc in g)
         nvec = _along(geo.ja[..., i, :], i)[..., n, :]                   # (J a^i) at the +xi_i face nodes
+        if viscous == "sipg":
+            g_in = tuple(_along(gc, i)[..., n, :] for gc in gb)
+            g_out = tuple(_along(_shift(gc, i, +1), i)[..., 0, :] for gc in gb)
         st_in, st_out = viscous_stress(q_in, g_in, prm), viscous_stress(q_out, g_out, prm)
         visc = sum(nvec[..., c, None] * (viscous_flux_of(st_in, c, prm) + viscous_flux_of(st_out, c, prm))
                    for c in range(3))
+        if viscous == "sipg":
+            nh = nvec / torch.linalg.norm(nvec, dim=-1)[..., None]
+            jump = q_out - q_in
+            st_p = viscous_stress(0.5 * (q_in + q_out), tuple(nh[..., c, None] * jump for c in range(3)), prm)
+            visc = visc + 2.0 * sigma * sum(nvec[..., c, None] * viscous_flux_of(st_p, c, prm) for c in range(3))
         f_hat = llf_normal(q_in, q_out, nvec, prm) - 0.5 * visc
         f_left = torch.roll(f_hat, 1, dims=_ELEM[i] + 1)                 # face arrays lack the d node axis
         if walls is not None and walls[0] == i:
@@ -233,7 +259,7 @@ class CurvedJacobianParts:
     couplings to other elements (the input format of the block partition)."""
 
     def __init__(self, q: torch.Tensor, geo: CurvedGeometry, prm: FlowParams, dt: float,
-                 max_batch: int | None = None, walls=None, progress=None):
+                 max_batch: int | None = None, walls=None, progress=None, viscous: str = "br1"):
         mesh = geo.mesh
         self.mesh, self.prm, self.dt, self.device = mesh, prm, dt, q.device
         k, p = mesh.k_elem, mesh.p
@@ -279,7 +305,7 @@ class CurvedJacobianParts:
                 x = qc.expand((b,) + tuple(qc.shape)).clone().reshape(b, ne, p3 * 5)
                 jj = torch.arange(j0, j1, device=dev)
                 x[jj[:, None] - j0, elems[None, :], jj[:, None]] += 1j * CS_STEP
-                hd = operator_h(x.reshape((b,) + mesh.shape()), geo, prm, walls).imag / CS_STEP
+                hd = operator_h(x.reshape((b,) + mesh.shape()), geo, prm, walls, viscous).imag / CS_STEP
                 hd = hd.reshape(b, ne, p3 * 5)                           # [cols j, row elem, row (n, v)]
                 self.own[elems, :, j0:j1] = hd[:, elems, :].permute(1, 2, 0)
                 for nb in nbr:
