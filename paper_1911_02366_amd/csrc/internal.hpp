@@ -216,6 +216,7 @@ struct Plan {
   double *w_bs = nullptr;     // [n1]
   double *w_qb = nullptr;     // [n1]
   double *w_r = nullptr;      // [n_dof]
+  double *w_rx = nullptr;     // [n1] A_bb remainder product of the assembled Schur product
   double *w_dq = nullptr;     // [n_dof]
   double *w_vec = nullptr;    // [n_dof] scratch
   double *gm_v = nullptr;     // [(m+1) * n1] Krylov basis
@@ -274,6 +275,8 @@ hipError_t launch_gemv_batched(const GemvDesc *d_desc, const RowTile *d_tiles, i
 
 // out[j] = c0 * src0[map0 ? map0[j] : j] + c1 * (B x)[j] + c2 * sum_{s in pull(j/5)} t[5 s + j%5]
 // with B = A_bb (full = true) or the remainder of A_bb not folded into T_e.
+// Assembled Schur product, first launch: t = T_e x[C_e] per slot and rx = R x.
+hipError_t launch_schur_gemv_rem(const Plan &p, const double *x, double *t, double *rx, bool lo);
 hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *src0,
                            const int32_t *map0, double c1, const double *x, double c2,
                            const double *t, double *out, bool lo = false);

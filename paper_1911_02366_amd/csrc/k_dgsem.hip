@@ -419,7 +419,10 @@ __global__ __launch_bounds__(512) void residual_curved_kernel(const DgParams *__
 }
 
 // With T = Dual: r = M inv_dt dq + dH/dQ(q) dq, dg the lifted gradient of dq.
-template <class T>
+// SIPG: the face viscous flux is the interior-penalty flux on the broken
+// gradients gbq (dgb for the direction); a template argument, so that the
+// Bassi-Rebay 1 kernels carry none of its code.
+template <class T, bool SIPG>
 __global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restrict__ prm, const double *__restrict__ q,
                                 const double *__restrict__ dq, const double *__restrict__ g,
                                 const double *__restrict__ dg, const double *__restrict__ gbq,
@@ -460,7 +463,7 @@ __global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restric
       const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, d, 1) * p3 + node_with(node, p, d, 0);
       T qb[5], gb[15], fh[5];
       for (int v = 0; v < 5; ++v) qb[v] = at<T>(q, dq, nb * 5 + v);
-      if (P.sipg) {
+      if constexpr (SIPG) {
         T bn[15];
         for (int t = 0; t < 15; ++t) bn[t] = at<T>(gbq, dgb, ((int64_t)e * p3 + node) * 15 + t);
         for (int t = 0; t < 15; ++t) gb[t] = at<T>(gbq, dgb, nb * 15 + t);
@@ -475,7 +478,7 @@ __global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restric
       const int64_t nb = (int64_t)nbr_elem(e, P.k_elem, d, -1) * p3 + node_with(node, p, d, n);
       T qb[5], gb[15], fh[5];
       for (int v = 0; v < 5; ++v) qb[v] = at<T>(q, dq, nb * 5 + v);
-      if (P.sipg) {
+      if constexpr (SIPG) {
         T bn[15];
         for (int t = 0; t < 15; ++t) bn[t] = at<T>(gbq, dgb, ((int64_t)e * p3 + node) * 15 + t);
         for (int t = 0; t < 15; ++t) gb[t] = at<T>(gbq, dgb, nb * 15 + t);
@@ -651,8 +654,12 @@ hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, doubl
     return hipGetLastError();
   }
   hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g, c.gb);
-  hipLaunchKernelGGL(residual_kernel<double>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
-                     nullptr, c.g, nullptr, c.gb, nullptr, q_s, inv_dt, r);
+  if (c.host.sipg)
+    hipLaunchKernelGGL((residual_kernel<double, true>), dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
+                       c.dev, q, nullptr, c.g, nullptr, c.gb, nullptr, q_s, inv_dt, r);
+  else
+    hipLaunchKernelGGL((residual_kernel<double, false>), dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
+                       c.dev, q, nullptr, c.g, nullptr, nullptr, nullptr, q_s, inv_dt, r);
   return hipGetLastError();
 }
 
@@ -676,8 +683,12 @@ hipError_t dg_jacobian_apply_on(scdg_dg *dg, const double *q, const double *v, d
   }
   hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g, c.gb);
   hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, v, gd, gbd);
-  hipLaunchKernelGGL(residual_kernel<Dual>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
-                     v, c.g, gd, c.gb, gbd, nullptr, inv_dt, out);
+  if (c.host.sipg)
+    hipLaunchKernelGGL((residual_kernel<Dual, true>), dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
+                       c.dev, q, v, c.g, gd, c.gb, gbd, nullptr, inv_dt, out);
+  else
+    hipLaunchKernelGGL((residual_kernel<Dual, false>), dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
+                       c.dev, q, v, c.g, gd, nullptr, nullptr, nullptr, inv_dt, out);
   return hipGetLastError();
 }
 

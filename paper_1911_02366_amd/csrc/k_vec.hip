@@ -49,16 +49,15 @@ struct Vec<float> {
 // with cross-lane adds.  Rows whose length or base is not a multiple of the
 // vector width take the scalar path.
 template <typename TM>
-__global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
-    const GemvDesc *__restrict__ desc, const RowTile *__restrict__ tiles, const TM *__restrict__ mat,
-    const double *__restrict__ x, const int32_t *__restrict__ xmap, double *__restrict__ y,
-    const int32_t *__restrict__ omap, double alpha, double beta, const double *__restrict__ y0,
-    const int32_t *__restrict__ halt) {
-  if (halt && *halt) return;
+__device__ __forceinline__ void gemv_tile(int tile, const GemvDesc *__restrict__ desc,
+                                          const RowTile *__restrict__ tiles, const TM *__restrict__ mat,
+                                          const double *__restrict__ x, const int32_t *__restrict__ xmap,
+                                          double *__restrict__ y, const int32_t *__restrict__ omap, double alpha,
+                                          double beta, const double *__restrict__ y0) {
   using VT = Vec<TM>;
   constexpr int W = VT::W;
   extern __shared__ double xs[];
-  const RowTile t = tiles[blockIdx.x];
+  const RowTile t = tiles[tile];
   const GemvDesc d = desc[t.prob];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int c = tid; c < d.cols; c += kThreads) xs[c] = xmap ? x[xmap[d.x_off + c]] : x[d.x_off + c];
@@ -115,6 +114,16 @@ __global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
       y[omap ? omap[yi] : yi] = v;
     }
   }
+}
+
+template <typename TM>
+__global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
+    const GemvDesc *__restrict__ desc, const RowTile *__restrict__ tiles, const TM *__restrict__ mat,
+    const double *__restrict__ x, const int32_t *__restrict__ xmap, double *__restrict__ y,
+    const int32_t *__restrict__ omap, double alpha, double beta, const double *__restrict__ y0,
+    const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
+  gemv_tile<TM>(blockIdx.x, desc, tiles, mat, x, xmap, y, omap, alpha, beta, y0);
 }
 
 // ---------------------------------------------------- BSR product + pull
@@ -190,6 +199,76 @@ __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
     if (c2 != 0.0) o += c2 * p;
     out[5 * g + lane] = o;
   }
+}
+
+// y[5 g + v] = sum over the BSR blocks of row g of (block x), one wave per
+// boundary node g, laid out as in bsr_pull_kernel (12 blocks per step, two
+// steps per trip, cross-lane row sums).
+template <typename TV>
+__device__ __forceinline__ void bsr_rows_wave(int64_t g, const int64_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                              const double *__restrict__ x, double *__restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  const int v = lane % 5, bq = lane / 5;
+  if (lane < 60) {
+    const int64_t b0 = rowptr[g], b1 = rowptr[g + 1];
+    double s2 = 0.0;
+    int64_t blk = b0 + bq;
+    for (; blk + 12 < b1; blk += 24) {
+      const TV *ra = val + blk * 25 + v * 5, *rb = val + (blk + 12) * 25 + v * 5;
+      const double *xa = x + (int64_t)col[blk] * 5, *xb = x + (int64_t)col[blk + 12] * 5;
+      double ma[5], mb[5], ya[5], yb[5];
+#pragma unroll
+      for (int w = 0; w < 5; ++w) {
+        ma[w] = (double)ra[w];
+        mb[w] = (double)rb[w];
+        ya[w] = xa[w];
+        yb[w] = xb[w];
+      }
+#pragma unroll
+      for (int w = 0; w < 5; ++w) {
+        s += ma[w] * ya[w];
+        s2 += mb[w] * yb[w];
+      }
+    }
+    if (blk < b1) {
+      const TV *ra = val + blk * 25 + v * 5;
+      const double *xa = x + (int64_t)col[blk] * 5;
+#pragma unroll
+      for (int w = 0; w < 5; ++w) s += (double)ra[w] * xa[w];
+    }
+    s += s2;
+  }
+  s += __shfl_down(s, 30);
+  s += __shfl_down(s, 15);
+  const double s5 = __shfl_down(s, 5), s10 = __shfl_down(s, 10);
+  if (lane < 5) y[5 * g + lane] = s + s5 + s10;
+}
+
+// The assembled Schur product's two streams in one launch: the element-block
+// GEMV tiles (t = T_e x[C_e], HBM-bound) and the rows of the A_bb remainder
+// (rx = R x, bound by dependent-load latency: about two dozen blocks per row
+// behind the column-index loads) interleaved in one grid, every `ratio`-th
+// workgroup a GEMV tile (ratio odd, so tiles dealt to one XCD stay together),
+// so that the remainder's latency hides behind the streaming.  A pull then
+// adds the element contributions to rx.
+template <typename TM, typename TV>
+__global__ __launch_bounds__(kThreads) void schur_gemv_rem_kernel(
+    const GemvDesc *__restrict__ desc, const RowTile *__restrict__ tiles, int32_t n_tiles, const TM *__restrict__ mat,
+    const double *__restrict__ x, const int32_t *__restrict__ xmap, double *__restrict__ t, int64_t ratio,
+    int64_t n_bnodes, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+    const TV *__restrict__ val, double *__restrict__ rx, const int32_t *__restrict__ halt) {
+  if (halt && *halt) return;
+  const int64_t b = blockIdx.x, grp = b / ratio, pos = b % ratio;
+  if (pos == 0 && grp < n_tiles) {
+    gemv_tile<TM>((int)grp, desc, tiles, mat, x, xmap, t, nullptr, 1.0, 0.0, nullptr);
+    return;
+  }
+  const int64_t j = grp < n_tiles ? b - (grp + 1) : b - n_tiles;     // remainder workgroup index
+  const int64_t g = j * (kThreads / 64) + (threadIdx.x >> 6);
+  if (g >= n_bnodes) return;
+  bsr_rows_wave<TV>(g, rowptr, col, val, x, rx);
 }
 
 // T[dst + v nc + w] += A_bb[src][v][w]
@@ -686,6 +765,29 @@ hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *sr
     hipLaunchKernelGGL(bsr_pull_kernel<double>, dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0, c1,
                        rp, cl, nullptr, full ? p.bb_val : p.rem_val, x, c2, p.d_pull_ptr, p.d_pull_idx, t, out,
                        p.halt);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_schur_gemv_rem(const Plan &p, const double *x, double *t, double *rx, bool lo) {
+  const int64_t nb = p.n_bnodes;
+  const int64_t rem_wg = (nb + (kThreads / 64) - 1) / (kThreads / 64);
+  // one GEMV tile every `ratio` workgroups, ratio odd and at most
+  // 1 + rem_wg / n_tiles so that the grid of n_tiles + rem_wg workgroups places
+  // every tile (the remainder takes the rest, and the tail once tiles run out)
+  int64_t ratio = p.n_rt_s > 0 ? 1 + rem_wg / p.n_rt_s : 1;
+  if (ratio % 2 == 0) --ratio;
+  const int64_t grid = (int64_t)p.n_rt_s + rem_wg;
+  const size_t lds = sizeof(double) * (size_t)p.max_nc;
+  if (lo) {
+    if (!p.rem_lo && p.n_rem > 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((schur_gemv_rem_kernel<float, float>), dim3((unsigned)grid), dim3(kThreads), lds, p.stream,
+                       p.d_gv_s, p.d_rt_s, p.n_rt_s, static_cast<const float *>(p.sloc), x, p.d_cmap, t, ratio, nb,
+                       p.d_rem_rowptr, p.d_rem_col, p.rem_lo, rx, p.halt);
+  } else {
+    hipLaunchKernelGGL((schur_gemv_rem_kernel<double, double>), dim3((unsigned)grid), dim3(kThreads), lds,
+                       p.stream, p.d_gv_s, p.d_rt_s, p.n_rt_s, static_cast<const double *>(p.sloc), x, p.d_cmap, t,
+                       ratio, nb, p.d_rem_rowptr, p.d_rem_col, p.rem_val, rx, p.halt);
   }
   return hipGetLastError();
 }

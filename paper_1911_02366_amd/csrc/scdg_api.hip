@@ -304,10 +304,10 @@ scdg_status schur_apply_impl(Plan &p, const double *x, double *y) {
     HIP_TRY(launch_bsr_pull(p, true, 0.0, nullptr, nullptr, 1.0, x, -1.0, p.w_t, y, fp32(p)));
     return SCDG_OK;
   }
-  HIP_TRY(launch_gemv_batched(p.d_gv_s, p.d_rt_s, p.n_rt_s, p.max_nc, p.sloc, fp32(p), x, p.d_cmap,
-                              p.w_t, nullptr, 1.0, 0.0, nullptr, p.stream, p.halt));
-  // S x = A_bb,rem x + sum_e P_e T_e x[C_e],  T_e = folded A_bb blocks - A_bi(e) X_e
-  HIP_TRY(launch_bsr_pull(p, false, 0.0, nullptr, nullptr, 1.0, x, 1.0, p.w_t, y, fp32(p)));
+  // S x = A_bb,rem x + sum_e P_e T_e x[C_e],  T_e = folded A_bb blocks - A_bi(e) X_e:
+  // the element GEMVs and the remainder rows in one launch, then the pull
+  HIP_TRY(launch_schur_gemv_rem(p, x, p.w_t, p.w_rx, fp32(p)));
+  HIP_TRY(launch_bsr_pull(p, false, 1.0, p.w_rx, nullptr, 0.0, x, 1.0, p.w_t, y, fp32(p)));
   return SCDG_OK;
 }
 
@@ -859,7 +859,7 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.d_gj_desc); dfree(p.d_gj_tiles);
   dfree(p.ainv); dfree(p.ainv_work); dfree(p.xmat); dfree(p.sloc); dfree(p.aib_lo); dfree(p.abi_lo); dfree(p.diag_s);
   dfree(p.s_dense); dfree(p.s_piv); dfree(p.d_dense_info);
-  dfree(p.w_z); dfree(p.w_t); dfree(p.w_bs); dfree(p.w_qb); dfree(p.w_r); dfree(p.w_dq); dfree(p.w_vec);
+  dfree(p.w_z); dfree(p.w_t); dfree(p.w_bs); dfree(p.w_qb); dfree(p.w_r); dfree(p.w_rx); dfree(p.w_dq); dfree(p.w_vec);
   dfree(p.gm_v); dfree(p.gm_w); dfree(p.gm_z); dfree(p.gm_part); dfree(p.gm_h);
   if (p.h_pinned) (void)hipHostFree(p.h_pinned);
   for (auto &u : p.ev_used) p.ev_pool.push_back(u.second);
@@ -1148,6 +1148,7 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   chk(dalloc(p, &p.w_bs, (size_t)p.n1));
   chk(dalloc(p, &p.w_qb, (size_t)p.n1));
   chk(dalloc(p, &p.w_r, (size_t)p.n_dof));
+  chk(dalloc(p, &p.w_rx, (size_t)p.n1));
   chk(dalloc(p, &p.w_dq, (size_t)p.n_dof));
   chk(dalloc(p, &p.w_vec, (size_t)p.n_dof));
   chk(dalloc(p, &p.gm_w, (size_t)p.n1));
