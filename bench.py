@@ -95,12 +95,15 @@ def roofline_entry(name, work, phase, prec):
 
 def dg_operator_timing(case, calls: int = 20) -> dict:
     """Event-timed device residual R(Q) and Newton-matrix product A v
-    (scdg_dg_residual, scdg_dg_jacobian_apply: two lifts and the residual sums
-    on dual numbers) at the state of the step, with a seeded direction.  Both
-    run FP64 flux arithmetic per node (every face flux evaluated by both
-    neighbours), so they are bound by the vector ALUs, not HBM: the bytes below
-    count one read of each input, one write of each output and the gradient
-    workspace written once and read once."""
+    (scdg_dg_residual, scdg_dg_jacobian_apply: lifts, the volume sums and the
+    face fluxes once per face, on dual numbers for the product) at the state of
+    the step, with a seeded direction.  Counters (rocprofv3, same workload)
+    place them at neither roofline: ~1 TB/s of HBM traffic and the vector ALU
+    active for about a third of the busy cycles, at two waves per SIMD (one
+    512- or 256-thread workgroup per element, 512 elements): short kernels
+    bound by latency at low occupancy.  The bytes below count one read of each
+    input, one write of each output and the gradient workspace written once
+    and read once."""
     import torch
     from paper_1911_02366_amd import DgResidual
     mesh, prm = case.mesh, case.prm
@@ -132,7 +135,7 @@ def dg_operator_timing(case, calls: int = 20) -> dict:
             "jacobian_apply_over_residual": round(ms_a / ms_r, 3),
             "residual_dof_s": round(q.numel() / (ms_r / 1e3), 1),
             "jacobian_apply_dof_s": round(q.numel() / (ms_a / 1e3), 1),
-            "bound": "alu",
+            "bound": "latency",
             "hbm_gbs": {"residual": round(bytes_r / (ms_r / 1e3) / 1e9, 1),
                         "jacobian_apply": round(bytes_a / (ms_a / 1e3) / 1e9, 1)}}
 

@@ -505,6 +505,135 @@ __global__ __launch_bounds__(512) void residual_kernel(const DgParams *__restric
   }
 }
 
+// The same operator in two parts, for the Newton-matrix product on dual
+// numbers, where the fused kernel holds a node's state, gradient, its face
+// neighbour's state and gradient and the flux temporaries at once and spills:
+//   volume_kernel: r = M inv_dt dq + the volume sums (every node);
+//   face_kernel (one launch per direction d): every +e_d face node pair
+//     evaluates its numerical flux once and adds it to the node on the
+//     minus side and subtracts it from the node on the plus side.
+// Within one launch no two face pairs share a node; the launches follow each
+// other on the stream.  Equal to residual_kernel up to the order of the sums.
+template <class T>
+__global__ __launch_bounds__(512) void volume_kernel(const DgParams *__restrict__ prm, const double *__restrict__ q,
+                                                     const double *__restrict__ dq, const double *__restrict__ g,
+                                                     const double *__restrict__ dg, const double *__restrict__ q_s,
+                                                     double inv_dt, double *__restrict__ r) {
+  __shared__ DgParams P;
+  extern __shared__ double fs[];   // [3][p3][5] volume fluxes
+  load_params(prm, &P);
+  const int p = P.p, p3 = p * p * p;
+  const int e = blockIdx.x;
+  const int node = threadIdx.x;
+  const bool live = node < p3;
+  const int64_t id = (int64_t)e * p3 + node;
+  if (live) {
+    T qn[5], gn[15];
+    for (int v = 0; v < 5; ++v) qn[v] = at<T>(q, dq, id * 5 + v);
+    for (int t = 0; t < 15; ++t) gn[t] = at<T>(g, dg, id * 15 + t);
+    for (int d = 0; d < 3; ++d) {
+      T fa[5], fv[5];
+      flux_adv(qn, d, P.gamma, fa);
+      flux_visc(qn, gn, d, P, fv);
+      for (int v = 0; v < 5; ++v) fs[(d * p3 + node) * 5 + v] = part(fa[v] - fv[v]);
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  const int c[3] = {node % p, (node / p) % p, node / (p * p)};
+  double h[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int d = 0; d < 3; ++d) {
+    const int l = c[d];
+    for (int v = 0; v < 5; ++v) {
+      double acc = 0.0;
+      for (int a = 0; a < p; ++a) acc += P.vw[l][a] * fs[(d * p3 + node_with(node, p, d, a)) * 5 + v];
+      h[v] += acc / P.w[l];
+    }
+  }
+  const double m = P.jac * P.w[c[0]] * P.w[c[1]] * P.w[c[2]];
+  double *re = r + id * 5;
+  for (int v = 0; v < 5; ++v) {
+    double val = m * P.s * h[v];
+    if constexpr (std::is_same<T, Dual>::value) {
+      val += m * inv_dt * dq[id * 5 + v];
+    } else {
+      if (q_s) val += m * inv_dt * (q[id * 5 + v] - q_s[id * 5 + v]);
+    }
+    re[v] = val;
+  }
+}
+
+template <class T, bool SIPG, int d>
+__global__ __launch_bounds__(256) void face_kernel(const DgParams *__restrict__ prm, int64_t n_pairs,
+                                                   const double *__restrict__ q, const double *__restrict__ dq,
+                                                   const double *__restrict__ g, const double *__restrict__ dg,
+                                                   const double *__restrict__ gbq, const double *__restrict__ dgb,
+                                                   double *__restrict__ r) {
+  __shared__ DgParams P;
+  load_params(prm, &P);
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_pairs) return;
+  const int p = P.p, p2 = p * p, p3 = p2 * p, n = p - 1;
+  const int e = (int)(idx / p2), tt = (int)(idx % p2), t1 = tt % p, t2 = tt / p;
+  // transverse directions of d in increasing order take (t1, t2)
+  int c[3];
+  c[d] = n;
+  c[d == 0 ? 1 : 0] = t1;
+  c[d == 2 ? 1 : 2] = t2;
+  const int node_l = c[0] + p * c[1] + p2 * c[2];
+  const int node_r = node_with(node_l, p, d, 0);
+  const int64_t il = (int64_t)e * p3 + node_l;
+  const int64_t ir = (int64_t)nbr_elem(e, P.k_elem, d, 1) * p3 + node_r;
+  // the flux term by term, one side's gradient live at a time (fewer registers
+  // than face_flux / face_flux_sipg, the same terms)
+  T ql[5], qr[5], fh[5];
+  for (int v = 0; v < 5; ++v) {
+    ql[v] = at<T>(q, dq, il * 5 + v);
+    qr[v] = at<T>(q, dq, ir * 5 + v);
+  }
+  const double *gsrc = SIPG ? gbq : g, *dgsrc = SIPG ? dgb : dg;
+  {
+    T gs[15], fv[5];
+    for (int t = 0; t < 15; ++t) gs[t] = at<T>(gsrc, dgsrc, il * 15 + t);
+    flux_visc(ql, gs, d, P, fv);
+    for (int v = 0; v < 5; ++v) fh[v] = -0.5 * fv[v];
+  }
+  {
+    T gs[15], fv[5];
+    for (int t = 0; t < 15; ++t) gs[t] = at<T>(gsrc, dgsrc, ir * 15 + t);
+    flux_visc(qr, gs, d, P, fv);
+    for (int v = 0; v < 5; ++v) fh[v] -= 0.5 * fv[v];
+  }
+  if constexpr (SIPG) {
+    T qm[5], jg[15], fv[5];
+    for (int t = 0; t < 15; ++t) jg[t] = 0.0;
+    for (int v = 0; v < 5; ++v) {
+      qm[v] = 0.5 * (ql[v] + qr[v]);
+      jg[d * 5 + v] = qr[v] - ql[v];
+    }
+    flux_visc(qm, jg, d, P, fv);
+    for (int v = 0; v < 5; ++v) fh[v] -= P.sigma * fv[v];
+  }
+  {
+    T fa[5];
+    flux_adv(ql, d, P.gamma, fa);
+    for (int v = 0; v < 5; ++v) fh[v] += 0.5 * fa[v];
+    flux_adv(qr, d, P.gamma, fa);
+    for (int v = 0; v < 5; ++v) fh[v] += 0.5 * fa[v];
+    const Prim<T> a = prim(ql, P.gamma), b = prim(qr, P.gamma);
+    const T lam_l = vabs(a.u[d]) + vsqrt(P.gamma * a.p / a.rho);
+    const T lam_r = vabs(b.u[d]) + vsqrt(P.gamma * b.p / b.rho);
+    const T lam = lam_l >= lam_r ? lam_l : lam_r;
+    for (int v = 0; v < 5; ++v) fh[v] -= 0.5 * lam * (qr[v] - ql[v]);
+  }
+  const double cf = P.jac * P.s * P.w[t1] * P.w[t2];
+  for (int v = 0; v < 5; ++v) {
+    const double f = cf * part(fh[v]);
+    r[il * 5 + v] += f;
+    r[ir * 5 + v] -= f;
+  }
+}
+
 // Gauss-Lobatto nodes and weights (Newton on L_{N+1} - L_{N-1} from Chebyshev
 // points) and the barycentric derivative matrix with the negative-sum diagonal.
 void gl_operators(int nord, double *x, double *w, double d[kMaxP][kMaxP]) {
@@ -624,6 +753,7 @@ struct DgContext {
   double *gbd = nullptr;   // ... and of a direction (with gd)
   double *met = nullptr;   // curved elements: 10 doubles per node (NULL: Cartesian cubes)
   uint64_t geo_gen = 0;    // bumped by every geometry change: captured graphs keyed on it recapture
+  bool fused_residual = false;  // residual in one kernel (faces evaluated by both sides) instead of split
   int device = 0;          // the HIP device the object was created on
   int64_t n_nodes = 0;
   hipStream_t stream = nullptr;
@@ -640,6 +770,31 @@ struct scdg_dg {
 
 namespace scdg {
 
+// The three face launches of the split operator (the direction is a template
+// argument: the flux code indexes arrays by it).
+template <class T>
+hipError_t launch_faces(const DgContext &c, int n_elem, const double *q, const double *v, const double *gd,
+                        const double *gbd, double *out, hipStream_t s) {
+  const int64_t pairs = (int64_t)n_elem * c.host.p * c.host.p;
+  const unsigned fgrid = (unsigned)((pairs + 255) / 256);
+  if (c.host.sipg) {
+    hipLaunchKernelGGL((face_kernel<T, true, 0>), dim3(fgrid), dim3(256), 0, s, c.dev, pairs, q, v, c.g, gd, c.gb,
+                       gbd, out);
+    hipLaunchKernelGGL((face_kernel<T, true, 1>), dim3(fgrid), dim3(256), 0, s, c.dev, pairs, q, v, c.g, gd, c.gb,
+                       gbd, out);
+    hipLaunchKernelGGL((face_kernel<T, true, 2>), dim3(fgrid), dim3(256), 0, s, c.dev, pairs, q, v, c.g, gd, c.gb,
+                       gbd, out);
+  } else {
+    hipLaunchKernelGGL((face_kernel<T, false, 0>), dim3(fgrid), dim3(256), 0, s, c.dev, pairs, q, v, c.g, gd,
+                       nullptr, nullptr, out);
+    hipLaunchKernelGGL((face_kernel<T, false, 1>), dim3(fgrid), dim3(256), 0, s, c.dev, pairs, q, v, c.g, gd,
+                       nullptr, nullptr, out);
+    hipLaunchKernelGGL((face_kernel<T, false, 2>), dim3(fgrid), dim3(256), 0, s, c.dev, pairs, q, v, c.g, gd,
+                       nullptr, nullptr, out);
+  }
+  return hipGetLastError();
+}
+
 hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, double inv_dt, double *r,
                           hipStream_t s) {
   auto &c = dg->c;
@@ -654,13 +809,18 @@ hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, doubl
     return hipGetLastError();
   }
   hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g, c.gb);
-  if (c.host.sipg)
-    hipLaunchKernelGGL((residual_kernel<double, true>), dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
-                       c.dev, q, nullptr, c.g, nullptr, c.gb, nullptr, q_s, inv_dt, r);
-  else
-    hipLaunchKernelGGL((residual_kernel<double, false>), dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
-                       c.dev, q, nullptr, c.g, nullptr, nullptr, nullptr, q_s, inv_dt, r);
-  return hipGetLastError();
+  if (c.fused_residual) {
+    if (c.host.sipg)
+      hipLaunchKernelGGL((residual_kernel<double, true>), dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
+                         c.dev, q, nullptr, c.g, nullptr, c.gb, nullptr, q_s, inv_dt, r);
+    else
+      hipLaunchKernelGGL((residual_kernel<double, false>), dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3,
+                         s, c.dev, q, nullptr, c.g, nullptr, nullptr, nullptr, q_s, inv_dt, r);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(volume_kernel<double>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q,
+                     nullptr, c.g, nullptr, q_s, inv_dt, r);
+  return launch_faces<double>(c, n_elem, q, nullptr, nullptr, nullptr, r, s);
 }
 
 // out = M inv_dt v + dH/dQ(q) v: the lifted gradients of q and of v (the
@@ -683,12 +843,10 @@ hipError_t dg_jacobian_apply_on(scdg_dg *dg, const double *q, const double *v, d
   }
   hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g, c.gb);
   hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, v, gd, gbd);
-  if (c.host.sipg)
-    hipLaunchKernelGGL((residual_kernel<Dual, true>), dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
-                       c.dev, q, v, c.g, gd, c.gb, gbd, nullptr, inv_dt, out);
-  else
-    hipLaunchKernelGGL((residual_kernel<Dual, false>), dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s,
-                       c.dev, q, v, c.g, gd, nullptr, nullptr, nullptr, inv_dt, out);
+  // volume sums, then the face fluxes once per face (see volume_kernel)
+  hipLaunchKernelGGL(volume_kernel<Dual>, dim3(n_elem), dim3(threads), sizeof(double) * 15 * p3, s, c.dev, q, v,
+                     c.g, gd, nullptr, inv_dt, out);
+  return launch_faces<Dual>(c, n_elem, q, v, gd, gbd, out, s);
   return hipGetLastError();
 }
 
