@@ -511,8 +511,9 @@ def main() -> int:
                     help="skip the FP64 variant with matrix-free Schur products")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 2 GiB FP64 buffer three times (HBM counter calibration)")
-    ap.add_argument("--inverse-mode", choices=["auto", "single", "blocked"], default="auto",
-                    help="form of the batched inverse (auto: blocked above n_i = 320)")
+    ap.add_argument("--inverse-mode", choices=["auto", "single", "blocked", "resident"], default="auto",
+                    help="form of the batched inverse (auto: resident panel up to n_i = 352, blocked above 320 "
+                         "otherwise)")
     ap.add_argument("--learned-guess", action="store_true",
                     help="run the learned-initial-guess time-stepping experiment instead")
     ap.add_argument("--lg-workload", default="tgv_n4_k16")

@@ -190,8 +190,8 @@ struct Plan {
   size_t cap_ainv = 0, cap_x = 0, cap_s = 0;  // bytes allocated
 
   // blocked Gauss-Jordan inverse (outer panels of kGjOuter columns)
-  int inverse_mode = 0;            // 0 automatic, 1 one kernel per element, 2 blocked
-  int inverse_used = 0;            // form used by the last scdg_factor (1 or 2)
+  int inverse_mode = 0;            // 0 automatic, 1 one kernel per element, 2 blocked, 3 resident panel
+  int inverse_used = 0;            // form used by the last scdg_factor (1, 2 or 3)
   int64_t sum_ni = 0;
   int64_t *d_gj_voff = nullptr;    // [n_elem] exclusive prefix of n_i
   int32_t *d_gj_piv = nullptr;     // [sum n_i] pivot row of each column
@@ -258,6 +258,8 @@ struct Plan {
 hipError_t launch_gj_inverse(Plan &p, void *work, void *out, bool fp32);
 hipError_t launch_gj_inverse_blocked(Plan &p, void *work, void *out, bool fp32);
 bool gj_supported(int max_n, bool fp32);
+hipError_t launch_gj_inverse_resident(Plan &p, void *work, void *out, bool fp32);
+bool gj_resident_supported(int max_n, bool fp32);
 hipError_t launch_cast_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, size_t n, hipStream_t s);
 void gemm_tile_shape(int cfg, int *bm, int *bn);

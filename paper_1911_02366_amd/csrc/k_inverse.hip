@@ -23,6 +23,7 @@
 // element.  A zero or non-finite pivot is recorded LAPACK-style (info = column
 // + 1) and replaced by 1 so the launch always completes.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "mfma.hpp"
@@ -333,6 +334,491 @@ __global__ __launch_bounds__(kThreads) void gj_inverse_kernel(const double *__re
 }
 
 // ---------------------------------------------------------------------------
+// Resident-panel form (n_i <= kResMaxN).  One workgroup per element, as in the
+// single-kernel form, but the LDS holds an outer panel of NBO columns (48 in
+// FP64, up to 112 in FP32), so the rest of the block in global memory is read
+// and written once per NBO columns instead of once per 24 or 32.
+//   * The block is bordered to rp = n rounded up to 16 with an identity block
+//     (rows and columns n..rp-1).  Its inverse is the inverse of A bordered
+//     with the same identity, the border never mixes with A (its rows and
+//     columns stay zero outside the diagonal block, and no row of the border
+//     can win a pivot search of a column of A while a row of A is unused), and
+//     every inner panel is a whole 16 columns.
+//   * Inside the outer panel, inner panels of 16 columns are eliminated by the
+//     first four waves, each lane holding two rows (128 w + l and
+//     128 w + 64 + l) in registers.  One barrier per column: each wave finds
+//     its candidate pivot (the largest |a| among its unused rows, lowest row
+//     on ties) with DPP row reductions and ballots, and the winning lane
+//     publishes its 16-value row next to the candidate value, so the row
+//     that wins is read straight from LDS after the barrier.
+//   * The inner panel's transformation reaches the other columns of the outer
+//     panel as a rank-16 update on the matrix cores, inside LDS.
+//   * The outer panel's transformation reaches the rest of the block as one
+//     rank-NBO matrix-core pass: every wave loads the outer panel's pivot rows
+//     for its column tiles into registers (the B operands) before a barrier,
+//     after which those rows may be overwritten, then streams its contiguous
+//     share of the output tiles (A operands from the LDS panel), loading the
+//     next group of tiles while the matrix cores work on the current one.
+// Same formulas, pivot rule and read-out as the single-kernel form.
+// ---------------------------------------------------------------------------
+constexpr int kResThreads = 512;
+constexpr int kResWaves = kResThreads / 64;
+constexpr int kResElimWaves = 4;                     // waves holding rows during the column steps
+constexpr int kResMaxN = 352;                        // 22 column tiles; 2 rows per lane of 4 waves
+constexpr int kResInner = 16;
+
+// column tiles one wave's contiguous share of an outer pass can span: its
+// share is at most ceil(out / W) tiles in column-major order over n_rt-tile
+// columns, so it spans at most floor(out / W) + 2 column tiles, with out the
+// column tiles outside the outer panel (worst case over every padded size)
+constexpr int res_slots(int panel_tiles, int max_tiles, int waves) {
+  int worst = 0;
+  for (int nt = 1; nt <= max_tiles; ++nt)
+    for (int kt = 0; kt < nt; kt += panel_tiles) {
+      const int pt = panel_tiles < nt - kt ? panel_tiles : nt - kt;
+      worst = worst > nt - pt ? worst : nt - pt;
+    }
+  return worst / waves + 2;
+}
+
+template <typename T_, int NBO_, int G_, int MAXN_>
+struct GjRes {
+  using T = T_;
+  static constexpr int NBO = NBO_, G = G_, MAXN = MAXN_;
+  static constexpr int SLOTS = res_slots(NBO_ / 16, (MAXN_ + 15) / 16, kResWaves);
+  static constexpr int PS = NBO_ + (sizeof(T_) == 8 ? 2 : 4);   // 400 B rows at 48 / 96: conflict-free A reads
+  static size_t lds_bytes(int max_n) {
+    const size_t rp = (size_t)((max_n + 15) & ~15);
+    return sizeof(T) * (rp * PS + 2 * kResElimWaves * kResInner + 4 * kResElimWaves) +
+           sizeof(int) * (2 * kResElimWaves + 2 * rp) + rp;
+  }
+};
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+// maximum over the 64 lanes (no NaN among the inputs), uniform
+template <typename T>
+__device__ __forceinline__ T wave_max_dpp(T v) {
+  v = fmax(v, dpp_mov<0xB1>(v));    // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_mov<0x4E>(v));    // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_mov<0x141>(v));   // row_half_mirror
+  v = fmax(v, dpp_mov<0x140>(v));   // row_mirror: every lane holds its 16-lane row's maximum
+  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+}
+
+// search value of a row: |a| if unused, -1 if used; a NaN wins (and is then
+// reported as a bad pivot)
+template <typename T>
+__device__ __forceinline__ T pivot_key(T a, bool live) {
+  T v = live ? fabs(a) : T(-1);
+  return v != v ? T(INFINITY) : v;
+}
+
+template <class L>
+__global__ __launch_bounds__(kResThreads) void gj_resident_kernel(const double *__restrict__ src,
+                                                                  typename L::T *__restrict__ work,
+                                                                  typename L::T *__restrict__ out,
+                                                                  const int32_t *__restrict__ n_arr,
+                                                                  const int64_t *__restrict__ off_arr,
+                                                                  const int32_t *__restrict__ elem_order,
+                                                                  int32_t *__restrict__ info) {
+  using T = typename L::T;
+  using M = Mfma<T>;
+  constexpr int NBO = L::NBO, PS = L::PS, G = L::G, W = kResWaves, EW = kResElimWaves, NI = kResInner;
+  constexpr int NQ = NBO / 4;                                          // K steps of the outer pass
+  constexpr int NLD = (L::MAXN * NBO + kResThreads - 1) / kResThreads;   // panel values per thread
+  constexpr int NLB = NLD < 40 ? NLD : 40;                             // loaded per batch
+  constexpr int SL = L::SLOTS;
+  extern __shared__ __align__(16) unsigned char smem[];
+
+  const int e = elem_order[blockIdx.x];
+  const int n = n_arr[e];
+  const int64_t off = off_arr[e];
+  const double *__restrict__ a0 = src + off;
+  T *__restrict__ w = work + off;
+  const int rp = (n + 15) & ~15;
+  const int n_rt = rp / 16, n_ct = rp / 16;
+
+  T *pnl = reinterpret_cast<T *>(smem);          // [rp][PS] outer panel
+  T *cand_row = pnl + (size_t)rp * PS;           // [2][EW][NI] candidate rows
+  T *cand_v = cand_row + 2 * EW * NI;             // [2][EW] candidate |a|
+  T *cand_inv = cand_v + 2 * EW;                  // [2][EW] reciprocal of the candidate pivot
+  int *cand_r = reinterpret_cast<int *>(cand_inv + 2 * EW);   // [2][EW] candidate row
+  int *piv = cand_r + 2 * EW;                     // [rp] pivot row of each column
+  int *qinv = piv + rp;                           // [rp] column whose pivot row is m
+  unsigned char *pflag = reinterpret_cast<unsigned char *>(qinv + rp);  // [rp] inner panel + 1 if a pivot row of this outer panel
+
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const bool elim = wid < EW;
+  const int r0 = 128 * wid + lane, r1 = r0 + 64;   // rows held during the column steps (waves 0..3)
+  const bool own0 = elim && r0 < rp, own1 = elim && r1 < rp;
+  bool used0 = false, used1 = false;
+  int my_info = 0;
+
+  for (int kb = 0; kb < rp; kb += NBO) {
+    const int nbo = min(NBO, rp - kb);
+    const bool first = kb == 0;
+    // load the outer panel (all loads in flight before the LDS stores); the
+    // border holds the identity
+    {
+      // the thread index passes through an empty asm statement so that the
+      // per-value indices are formed here, not hoisted out of the kb loop and
+      // kept live across the whole kernel
+#pragma unroll 1
+      for (int u0 = 0; u0 < NLD; u0 += NLB) {
+        int tl = tid + u0 * kResThreads;
+        asm volatile("" : "+v"(tl));
+        T tmp[NLB];
+#pragma unroll
+        for (int u = 0; u < NLB; ++u) {
+          const int idx = tl + u * kResThreads;
+          const int i = idx / NBO, c = idx % NBO, col = kb + c;
+          T v = T(0);
+          if (idx < rp * NBO) {
+            if (i < n && col < n)
+              v = first ? (T)a0[(int64_t)i * n + col] : w[(int64_t)i * n + col];
+            else if (col >= n && col < rp && i == col)
+              v = T(1);
+          }
+          tmp[u] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < NLB; ++u) {
+          const int idx = tl + u * kResThreads;
+          if (idx < rp * NBO) pnl[(idx / NBO) * PS + idx % NBO] = tmp[u];
+        }
+      }
+    }
+    for (int i = tid; i < rp; i += kResThreads) pflag[i] = 0;
+    __syncthreads();
+
+    for (int c0 = 0; c0 < nbo; c0 += NI) {
+      const int sp1 = c0 / NI + 1;
+      T x0[NI], x1[NI];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        x0[j] = own0 ? pnl[r0 * PS + c0 + j] : T(0);
+        x1[j] = own1 ? pnl[r1 * PS + c0 + j] : T(0);
+      }
+#pragma unroll
+      for (int c = 0; c < NI; ++c) {
+        const int par = c & 1;
+        if (elim) {
+          const T v0 = pivot_key(x0[c], own0 && !used0);
+          const T v1 = pivot_key(x1[c], own1 && !used1);
+          const bool take1 = v1 > v0;          // ties keep the lower row
+          const T v = take1 ? v1 : v0;
+          // reciprocal of this lane's candidate, formed beside the reduction
+          // (1 for a zero or non-finite pivot, which is reported instead)
+          const T xd = take1 ? x1[c] : x0[c];
+          const T rcp = (xd != T(0) && isfinite((double)xd)) ? T(1) / xd : T(1);
+          const T m = wave_max_dpp(v);
+          const unsigned long long b0 = __ballot(v == m && !take1);
+          const unsigned long long b1 = __ballot(v == m && take1);
+          const bool hi = b0 == 0ull;          // first-half rows are the lower rows of the wave
+          const unsigned long long bw = hi ? b1 : b0;
+          const int wl = bw ? __ffsll((long long)bw) - 1 : 0;
+          if (lane == wl) {
+            T *dst = cand_row + (par * EW + wid) * NI;
+            if (hi) {
+#pragma unroll
+              for (int j = 0; j < NI; ++j) dst[j] = x1[j];
+            } else {
+#pragma unroll
+              for (int j = 0; j < NI; ++j) dst[j] = x0[j];
+            }
+          }
+          if (lane == wl) {
+            cand_inv[par * EW + wid] = rcp;
+            cand_v[par * EW + wid] = m;
+            cand_r[par * EW + wid] = 128 * wid + wl + (hi ? 64 : 0);
+          }
+        }
+        __syncthreads();
+        if (elim) {
+          T cv[EW];
+          int cr[EW];
+#pragma unroll
+          for (int q = 0; q < EW; ++q) {
+            cv[q] = cand_v[par * EW + q];
+            cr[q] = cand_r[par * EW + q];
+          }
+          T best = cv[0];
+          int ws = 0, pr = cr[0];
+#pragma unroll
+          for (int q = 1; q < EW; ++q) {
+            if (cv[q] > best) {
+              best = cv[q];
+              ws = q;
+              pr = cr[q];
+            }
+          }
+          const T *prow = cand_row + (par * EW + ws) * NI;
+          const T d = prow[c];
+          T inv_d = cand_inv[par * EW + ws];
+          if (pr >= rp) {   // cannot happen while unused rows remain; keeps every index in range
+            pr = rp - 1;
+            inv_d = T(1);
+            if (my_info == 0) my_info = kb + c0 + c + 1;
+          }
+          if (!(d != T(0)) || !isfinite((double)d)) {
+            if (my_info == 0) my_info = kb + c0 + c + 1;
+          }
+          if (tid == 0) piv[kb + c0 + c] = pr;
+          // the scaled pivot row, once per column; every held row loses f times
+          // it (the pivot row too), then the pivot row's lane overwrites its row
+          T sp[NI];
+#pragma unroll
+          for (int j = 0; j < NI; ++j) sp[j] = (j == c) ? inv_d : prow[j] * inv_d;
+          {
+            const T f0 = x0[c], f1 = x1[c];
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+              x0[j] = (j == c ? T(0) : x0[j]) - f0 * sp[j];
+              x1[j] = (j == c ? T(0) : x1[j]) - f1 * sp[j];
+            }
+          }
+          if (own0 && r0 == pr) {
+#pragma unroll
+            for (int j = 0; j < NI; ++j) x0[j] = sp[j];
+            used0 = true;
+            pflag[r0] = (unsigned char)sp1;
+          }
+          if (own1 && r1 == pr) {
+#pragma unroll
+            for (int j = 0; j < NI; ++j) x1[j] = sp[j];
+            used1 = true;
+            pflag[r1] = (unsigned char)sp1;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        if (own0) pnl[r0 * PS + c0 + j] = x0[j];
+        if (own1) pnl[r1 * PS + c0 + j] = x1[j];
+      }
+      __syncthreads();
+      // rank-16 update of the outer panel's other column tiles, in LDS.  The
+      // B operands (the inner panel's pivot rows, read before any of them is
+      // overwritten) go to registers ahead of a barrier; every column tile is
+      // then updated in straight-line code, the inner panel's own tile
+      // computed but not stored (its B operands are not zero).  Columns past a
+      // short last panel hold zeros and stay zero.
+      {
+        constexpr int kCt = NBO / 16;
+        const int ct_in = c0 / NI;
+        T bi[kCt][NI / 4];
+#pragma unroll
+        for (int q = 0; q < NI / 4; ++q) {
+          const int prow_k = piv[kb + c0 + 4 * q + (lane >> 4)];
+#pragma unroll
+          for (int ct = 0; ct < kCt; ++ct) bi[ct][q] = pnl[prow_k * PS + ct * 16 + (lane & 15)];
+        }
+        __syncthreads();
+        for (int rt = wid; rt < n_rt; rt += W) {
+          T av[NI / 4];
+#pragma unroll
+          for (int q = 0; q < NI / 4; ++q) av[q] = pnl[(rt * 16 + (lane & 15)) * PS + c0 + 4 * q + (lane >> 4)];
+          bool keep[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) keep[r] = pflag[rt * 16 + M::row(lane, r)] != sp1;
+#pragma unroll
+          for (int ct = 0; ct < kCt; ++ct) {
+            const int col = ct * 16 + (lane & 15);
+            typename M::acc_t acc = M::zero();
+#pragma unroll
+            for (int q = 0; q < NI / 4; ++q) acc = M::mma(av[q], bi[ct][q], acc);
+            T old[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) old[r] = keep[r] ? pnl[(rt * 16 + M::row(lane, r)) * PS + col] : T(0);
+            if (ct != ct_in) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) pnl[(rt * 16 + M::row(lane, r)) * PS + col] = old[r] + acc[r];
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // rank-NBO pass over the column tiles outside the outer panel.  The lane
+    // index passes through an empty asm statement so that the pass's operand
+    // offsets are formed here instead of being hoisted out of the kb loop and
+    // held in registers across the whole kernel.
+    int lane_g = lane;
+    asm volatile("" : "+v"(lane_g));
+    const int pt0 = kb / 16, pt1 = min(n_ct, (kb + NBO) / 16);
+    const int n_ct_out = n_ct - (pt1 - pt0);
+    const int tiles = n_ct_out * n_rt;
+    const int t0 = (int)((int64_t)wid * tiles / W), t1 = (int)((int64_t)(wid + 1) * tiles / W);
+    const int g0 = t0 / n_rt;
+    // the pass is compiled twice: the first reads A_ii (FP64) directly, the
+    // others the working block; loaded values stay raw until the final add
+    // (masking and conversion there), so nothing waits on a load early
+    auto pass = [&](auto first_c) {
+      constexpr bool FIRST = decltype(first_c)::value;
+      using LT = typename std::conditional<FIRST, double, T>::type;
+      const LT *__restrict__ gsrc;
+      if constexpr (FIRST)
+        gsrc = a0;
+      else
+        gsrc = w;
+      T bf[SL][NQ];
+#pragma unroll
+      for (int s = 0; s < SL; ++s) {
+        const int g = g0 + s;
+        const bool live = t0 < t1 && g * n_rt < t1;
+        const int ct = g < pt0 ? g : g + (pt1 - pt0);
+        const int col = ct * 16 + (lane_g & 15);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int k = 4 * q + (lane_g >> 4);
+          T v = T(0);
+          if (live && k < nbo && col < n) {
+            const int pk = piv[kb + k];
+            if (pk < n) v = (T)gsrc[pk * n + col];
+          }
+          bf[s][q] = v;
+        }
+      }
+      // the transformed outer panel goes back to global memory (columns of A only)
+      for (int idx = tid; idx < n * NBO; idx += kResThreads) {
+        const int i = idx / NBO, c = idx % NBO;
+        if (kb + c < n) w[i * n + kb + c] = pnl[i * PS + c];
+      }
+      // every B operand is in registers before any pivot row is overwritten
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < SL; ++s) {
+        const int g = g0 + s;
+        if (t0 < t1 && g * n_rt < t1) {
+          const int ct = g < pt0 ? g : g + (pt1 - pt0);
+          const int col = ct * 16 + (lane_g & 15);
+          const bool col_ok = col < n;
+          const int rlo = max(t0, g * n_rt) - g * n_rt, rhi = min(t1, (g + 1) * n_rt) - g * n_rt;
+          // unconditional loads from in-range addresses; keep marks the values
+          // that enter the update (inside the block, not a pivot row of the panel)
+          auto load_group = [&](int rt, LT (&raw)[G][4], unsigned &keep) {
+            keep = 0u;
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = (rt + gi) * 16 + M::row(lane_g, r);
+                const bool in = (rt + gi < rhi) & col_ok & (i < n);
+                // per-lane clamped address: a uniform one would become a scalar
+                // load, whose wait also drains the vector loads in flight
+                raw[gi][r] = gsrc[min(i, n - 1) * n + min(col, n - 1)];
+                const bool kp = in & (pflag[min(i, rp - 1)] == 0);
+                keep |= kp ? 1u << (4 * gi + r) : 0u;
+              }
+            }
+          };
+          // the padded K steps of a short last panel multiply exact zeros
+          auto update_group = [&](int rt, const LT (&raw)[G][4], unsigned keep) {
+            typename M::acc_t acc[G];
+            int arow[G];
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) {
+              acc[gi] = M::zero();
+              arow[gi] = (min(rt + gi, rhi - 1) * 16 + (lane_g & 15)) * PS + (lane_g >> 4);
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+              for (int gi = 0; gi < G; ++gi) acc[gi] = M::mma(pnl[arow[gi] + 4 * q], bf[s][q], acc[gi]);
+              // bounds how far the LDS reads run ahead of the matrix cores
+              if (q % 4 == 3) asm volatile("" ::: "memory");
+            }
+            const bool full = rt + G <= rhi && (ct + 1) * 16 <= n && (rt + G) * 16 <= n;
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = (rt + gi) * 16 + M::row(lane_g, r);
+                const T old = ((keep >> (4 * gi + r)) & 1u) ? (T)raw[gi][r] : T(0);
+                if (full || (rt + gi < rhi && col_ok && i < n)) w[i * n + col] = old + acc[gi][r];
+              }
+            }
+          };
+          // two groups of loads in flight: load the next while updating this one
+          LT ra[G][4], rb[G][4];
+          unsigned ka, kb2;
+          int rt = rlo;
+          load_group(rt, ra, ka);
+          while (true) {
+            if (rt + G < rhi) load_group(rt + G, rb, kb2);
+            update_group(rt, ra, ka);
+            rt += G;
+            if (rt >= rhi) break;
+            if (rt + G < rhi) load_group(rt + G, ra, ka);
+            update_group(rt, rb, kb2);
+            rt += G;
+            if (rt >= rhi) break;
+          }
+        }
+      }
+    };
+    if (first)
+      pass(std::true_type{});
+    else
+      pass(std::false_type{});
+    __syncthreads();
+  }
+
+  // read the inverse out through the pivot permutation: A^-1[k][m] = W[p_k][q_m]
+  for (int k = tid; k < rp; k += kResThreads) qinv[piv[k]] = k;
+  __syncthreads();
+  {
+    constexpr int kCols = (kResMaxN + 63) / 64, kRows = 4;
+    int qc[kCols];
+#pragma unroll
+    for (int t = 0; t < kCols; ++t) {
+      const int m = lane + 64 * t;
+      qc[t] = m < n ? qinv[m] : n;
+    }
+    T *__restrict__ o = out + off;
+    for (int k0 = wid * kRows; k0 < n; k0 += W * kRows) {
+      T v[kRows][kCols];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {
+        const int k = k0 + r;
+        const int pk = k < n ? piv[k] : n;
+#pragma unroll
+        for (int t = 0; t < kCols; ++t)
+          v[r][t] = (pk < n && qc[t] < n) ? w[(int64_t)pk * n + qc[t]] : T(0);
+      }
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {
+        const int k = k0 + r;
+#pragma unroll
+        for (int t = 0; t < kCols; ++t) {
+          const int m = lane + 64 * t;
+          if (k < n && m < n) o[(int64_t)k * n + m] = v[r][t];
+        }
+      }
+    }
+  }
+  if (tid == 0) info[e] = my_info;
+}
+
+// ---------------------------------------------------------------------------
 // Blocked form for large blocks.  Columns are taken in outer panels of
 // kOuter; inside an outer panel, inner panels of NB columns are eliminated
 // by gj_panel_kernel, which updates only the outer panel's other columns.
@@ -546,7 +1032,37 @@ hipError_t gj_blocked_dispatch(Plan &p, T *work, T *out) {
   return gj_blocked_run<GjWide<T, 8, false>>(p, work, out);
 }
 
+template <class L>
+hipError_t gj_res_launch(Plan &p, typename L::T *work, typename L::T *out) {
+  const size_t lds = L::lds_bytes(p.max_ni);
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(gj_resident_kernel<L>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((gj_resident_kernel<L>), dim3(p.n_elem), dim3(kResThreads), lds, p.stream, p.aii, work, out,
+                     p.d_inv_n, p.d_inv_off, p.d_inv_order, p.d_info);
+  return hipGetLastError();
+}
+
+// FP64: 48-column outer panels; FP32: the widest of 112 / 96 / 48 that fits
+using GjRes64 = GjRes<double, 48, 2, kResMaxN>;
+using GjRes32w = GjRes<float, 112, 2, 320>;
+using GjRes32m = GjRes<float, 96, 2, kResMaxN>;
+using GjRes32s = GjRes<float, 48, 2, kResMaxN>;
+
 }  // namespace
+
+bool gj_resident_supported(int max_n, bool fp32) {
+  if (max_n > kResMaxN) return false;
+  return fp32 ? GjRes32s::lds_bytes(max_n) <= kLdsLimit : GjRes64::lds_bytes(max_n) <= kLdsLimit;
+}
+
+hipError_t launch_gj_inverse_resident(Plan &p, void *work, void *out, bool fp32) {
+  if (!fp32) return gj_res_launch<GjRes64>(p, static_cast<double *>(work), static_cast<double *>(out));
+  float *wf = static_cast<float *>(work), *of = static_cast<float *>(out);
+  if (p.max_ni <= GjRes32w::MAXN && GjRes32w::lds_bytes(p.max_ni) <= kLdsLimit) return gj_res_launch<GjRes32w>(p, wf, of);
+  if (GjRes32m::lds_bytes(p.max_ni) <= kLdsLimit) return gj_res_launch<GjRes32m>(p, wf, of);
+  return gj_res_launch<GjRes32s>(p, wf, of);
+}
 
 bool gj_supported(int max_n, bool fp32) {
   if (max_n > kRowsPerThread * kThreads) return false;

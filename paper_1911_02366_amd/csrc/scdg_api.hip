@@ -1301,16 +1301,24 @@ scdg_status scdg_factor(scdg_plan *pl, scdg_precision prec) {
     ST_TRY(dalloc(p, reinterpret_cast<char **>(&p.ainv_work), need));
     p.cap_ainv = need;
   }
-  const bool blocked = p.inverse_mode == 2 || (p.inverse_mode == 0 && p.max_ni > kGjAutoBlocked);
-  if (blocked) ST_TRY(prepare_blocked_inverse(p));
+  const bool res_ok = gj_resident_supported(p.max_ni, fp32(p));
+  if (p.inverse_mode == 3 && !res_ok) {
+    p.last_error = "interior block too large for the resident-panel inverse";
+    return SCDG_ERR_UNSUPPORTED;
+  }
+  int form = p.inverse_mode;
+  if (form == 0) form = res_ok ? 3 : (p.max_ni > kGjAutoBlocked ? 2 : 1);
+  if (form == 2) ST_TRY(prepare_blocked_inverse(p));
   {
     PhaseTimer tm(p, SCDG_PHASE_INVERSE);
-    if (blocked)
+    if (form == 2)
       HIP_TRY(launch_gj_inverse_blocked(p, p.ainv_work, p.ainv, fp32(p)));
+    else if (form == 3)
+      HIP_TRY(launch_gj_inverse_resident(p, p.ainv_work, p.ainv, fp32(p)));
     else
       HIP_TRY(launch_gj_inverse(p, p.ainv_work, p.ainv, fp32(p)));
   }
-  p.inverse_used = blocked ? 2 : 1;
+  p.inverse_used = form;
   p.state = 2;
   p.dense_factored = false;
   return SCDG_OK;
@@ -1340,7 +1348,7 @@ scdg_status scdg_get_schur_mode(const scdg_plan *pl, int32_t *mode) {
 }
 
 scdg_status scdg_set_inverse_mode(scdg_plan *pl, int32_t mode) {
-  if (!pl || mode < 0 || mode > 2) return SCDG_ERR_ARG;
+  if (!pl || mode < 0 || mode > 3) return SCDG_ERR_ARG;
   pl->p.inverse_mode = mode;
   return SCDG_OK;
 }

@@ -205,14 +205,15 @@ class Plan:
         return ["assembled", "matrix_free", "matrix_free_sparse"][out.value]
 
     def set_inverse_mode(self, mode: str):
-        """'auto', 'single' (one workgroup per element) or 'blocked'."""
-        m = {"auto": 0, "single": 1, "blocked": 2}[mode]
+        """'auto', 'single' (one workgroup per element), 'blocked' or 'resident'
+        (one workgroup per element with a wide outer panel in LDS)."""
+        m = {"auto": 0, "single": 1, "blocked": 2, "resident": 3}[mode]
         self._check(self.lib.scdg_set_inverse_mode(self.handle, m), "scdg_set_inverse_mode")
 
     def inverse_mode_used(self) -> str:
         v = C.c_int32()
         self._check(self.lib.scdg_get_inverse_mode(self.handle, C.byref(v)), "scdg_get_inverse_mode")
-        return {0: "none", 1: "single", 2: "blocked"}[v.value]
+        return {0: "none", 1: "single", 2: "blocked", 3: "resident"}[v.value]
 
     def enable_timing(self, on: bool = True):
         self._check(self.lib.scdg_enable_timing(self.handle, int(on)), "scdg_enable_timing")
