@@ -93,7 +93,7 @@ def roofline_entry(name, work, phase, prec):
             "algorithmic_bytes_per_launch": work["bytes"]}
 
 
-def dg_operator_timing(case, calls: int = 20) -> dict:
+def dg_operator_timing(case, plan=None, calls: int = 20) -> dict:
     """Event-timed device residual R(Q) and Newton-matrix product A v
     (scdg_dg_residual, scdg_dg_jacobian_apply: lifts, the volume sums and the
     face fluxes once per face, on dual numbers for the product) at the state of
@@ -127,6 +127,25 @@ def dg_operator_timing(case, calls: int = 20) -> dict:
 
     ms_r = timed(lambda: dg.residual(q, q, 1.0 / case.dt, out=out))
     ms_a = timed(lambda: dg.jacobian_apply(q, v, 1.0 / case.dt, out=out))
+    blocks = None
+    if plan is not None and getattr(case, "xyz", None) is None:
+        # the element blocks of the Newton matrix formed by the library itself
+        # (scdg_dg_jacobian_blocks; returns after its stream, so host-timed)
+        import time
+        dg.jacobian_blocks(plan, q, 1.0 / case.dt)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            blk = dg.jacobian_blocks(plan, q, 1.0 / case.dt)
+        ms_b = (time.perf_counter() - t0) / reps * 1e3
+        out_bytes = 8 * sum(blk[k].numel() for k in ("aii", "aib", "abi", "bb_val"))
+        same = max(float((blk[k] - getattr(case, k).reshape(-1)).abs().max() /
+                         getattr(case, k).abs().max()) for k in ("aii", "aib", "abi", "bb_val"))
+        del blk
+        blocks = {"ms": round(ms_b, 3), "output_gb": round(out_bytes / 1e9, 3),
+                  "written_gbs": round(out_bytes / (ms_b / 1e3) / 1e9, 1),
+                  "max_rel_diff_vs_generator": same}
     dg.close()
     nodes = q.numel() // 5
     bytes_r = nodes * 8 * (5 + 15 + 15 + 5 + 5 + 5)          # q (lift), g w/r, q, q_s, r
@@ -137,7 +156,8 @@ def dg_operator_timing(case, calls: int = 20) -> dict:
             "jacobian_apply_dof_s": round(q.numel() / (ms_a / 1e3), 1),
             "bound": "latency",
             "hbm_gbs": {"residual": round(bytes_r / (ms_r / 1e3) / 1e9, 1),
-                        "jacobian_apply": round(bytes_a / (ms_a / 1e3) / 1e9, 1)}}
+                        "jacobian_apply": round(bytes_a / (ms_a / 1e3) / 1e9, 1)},
+            "jacobian_blocks": blocks}
 
 
 def cpu_baseline(case, tol: float, max_seconds: float) -> dict:
@@ -791,7 +811,7 @@ def main() -> int:
     if worst > 1e-8:
         out["warning"] = "full-system residual above 1e-8"
     if not args.no_dg_timing and args.workload not in MIXED_WORKLOADS and not wall:
-        out["dg_operators"] = dg_operator_timing(case)
+        out["dg_operators"] = dg_operator_timing(case, plan)
     if not args.no_cpu_baseline and case.aii.dim() == 3:      # one order per mesh
         out["cpu_baseline"] = cpu_baseline(case, args.tol, args.cpu_seconds)
     plan.close()

@@ -377,6 +377,34 @@ scdg_status scdg_dg_jacobian_apply(scdg_dg *dg, const double *q, const double *v
 scdg_status scdg_dg_jacobian_apply_noalloc(scdg_dg *dg, const double *q, const double *v, double inv_dt,
                                            double *out);
 
+/* Element blocks of the backward-Euler Newton matrix A = M inv_dt + dH/dQ(q)
+ * (eq. NewtonLinSys1), formed on the device from the state q by the chain
+ * rule: the linearised Lax-Friedrichs advective flux (Section 2.1.1) and the
+ * linearised Bassi-Rebay 1 viscous flux through the lifted gradient
+ * (Section 2.1.2, eq. GradDGImp).  Pointwise 5x5 flux Jacobians are taken on
+ * dual numbers (the same branches as scdg_dg_jacobian_apply at the kinks of
+ * |u| and of the larger face speed); every node block of A is their linear
+ * combination with coefficients of the mesh (Gauss-Lobatto weights, the
+ * derivative matrix, the element size), built once per order on the host.
+ * The blocks are written in the plan's format (interior / element-boundary
+ * partition of Section 3.1, the layout scdg_assemble takes):
+ *   aii [n_elem n_i^2], aib [n_elem n_i n_c], abi [n_elem n_c n_i]
+ *   (row-major, node-major with the 5 variables fastest), and
+ *   bb_val [nnzb * 25] over the plan's A_bb pattern;
+ * every entry of the four arrays is overwritten (device pointers).  q holds
+ * 5 K^3 (N+1)^3 doubles in the DG object's layout.  Requirements: the DG
+ * object describes Cartesian cubes (no scdg_dg_set_geometry) with the
+ * Bassi-Rebay 1 flux, and the plan is its periodic K^3 mesh of the same
+ * uniform order with no physical faces; otherwise SCDG_ERR_UNSUPPORTED.
+ * SCDG_ERR_ARG for NULL pointers, a negative or non-finite inv_dt, or a
+ * nonzero block outside the plan's coupling sets or A_bb pattern (the
+ * outputs are then incomplete).  Runs on the DG object's stream and returns
+ * after it (one synchronisation, for that check).  Workspaces (the term
+ * template and about 3.4 KB of pointwise Jacobians per node) are allocated on
+ * the first call and freed by scdg_dg_destroy. */
+scdg_status scdg_dg_jacobian_blocks(scdg_dg *dg, scdg_plan *plan, const double *q, double inv_dt, double *aii,
+                                    double *aib, double *abi, double *bb_val);
+
 /* ------------------------------------------------------------------------
  * Newton iterations of one backward-Euler step replayed from captured HIP
  * graphs (the Newton linearization of eq. NewtonLinSys1 solved by static

@@ -159,6 +159,7 @@ struct Plan {
   int64_t *d_inv_off = nullptr;   // [n_elem] offset of A_ii(e)
   int32_t *d_inv_order = nullptr; // [n_elem] elements by decreasing n_i (stable)
   int32_t *d_info = nullptr;      // [n_elem] factor info
+  int32_t *d_jac_cnode = nullptr; // [sum |C_e|] device copy of the coupling sets (device Jacobian blocks)
 
   // batched GEMM descriptors and tile lists (X = Ainv A_ib, S_loc = A_bi X)
   GemmDesc *d_gx = nullptr, *d_gs = nullptr;
@@ -342,6 +343,18 @@ hipError_t dg_residual_on(scdg_dg *dg, const double *q, const double *q_s, doubl
                           hipStream_t s);
 int64_t dg_dof_count(const scdg_dg *dg);
 void dg_graph_state(const scdg_dg *dg, uint64_t *gen, const void **g, const void **met, const void **params);
+// device Jacobian blocks (k_dgsem.hip): the plan's structure as the assembly sees it
+struct JacPlanView {
+  int ni, nc, ncn, nb;           // n_i, n_c (DOFs), |C_e| (nodes), boundary nodes per element
+  int64_t nnzb;
+  const int32_t *c_node;         // [n_elem * ncn] device copy of the coupling sets
+  const int64_t *bb_rowptr;
+  const int32_t *bb_col;
+};
+bool dg_jacobian_shape(const scdg_dg *dg, int *k_elem, int *order, bool *cartesian_br1);
+std::string dg_last_error(const scdg_dg *dg);
+scdg_status dg_jacobian_blocks_on(scdg_dg *dg, const JacPlanView &v, const double *q, double inv_dt, double *aii,
+                                  double *aib, double *abi, double *bb_val);
 
 // dense path
 hipError_t launch_dense_assemble(const Plan &p, double *s_dense);

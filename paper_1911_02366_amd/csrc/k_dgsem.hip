@@ -19,6 +19,7 @@
 // runs the same two launches on dual numbers (forward-mode differentiation):
 // the lifting is linear, so the direction's gradient is the lifting of v, and
 // the residual sums carry value and derivative; only the derivative is kept.
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <type_traits>
@@ -744,6 +745,399 @@ bool curved_metrics(const DgParams &P, int64_t n_elem, const double *xyz, std::v
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Element blocks of the backward-Euler Newton matrix A = M/dt + dH/dQ on the
+// device (Sections 2.1.1 and 2.1.2: the linearised Lax-Friedrichs advective
+// flux and the linearised BR1 viscous flux through the lifted gradient,
+// eq. GradDGImp; eq. NewtonLinSys1).  Every 5x5 node block of dH/dQ is a
+// linear combination of pointwise 5x5 Jacobians
+//   Ja_d  = d f^a_d / d q,   Jv_d = d f^nu_d / d q (gradient held),
+//   G_dd' = d f^nu_d / d g_d'  (g_d' the lifted gradient along d'),
+//   PL_d, PR_d = d Fhat_d / d q^-, d q^+  (the advective face flux of a +d face),
+// whose coefficients depend only on the mesh: the Gauss-Lobatto weights w,
+// the derivative matrix D and the element size (s = 2/h).  With
+//   c_t = J s w_t1 w_t2,  Vw[l][a] = -w_a D[a][l],
+//   B[l][a] = Vw[l][a] + [l = a = N]/2 - [l = a = 0]/2,
+//   L[b][a] = s (D[b][a] - [b = a = N]/(2 w_N) + [b = a = 0]/(2 w_0)),
+// row (t, l) of direction d's line and column (t, a) of the same element get
+//   c_t (Vw[l][a] Ja_d(a) - B[l][a] Jv_d(a) - sum_b B[l][b] L[b][a] G_dd(b)),
+// the plane couplings get -c_(b,c) B[l][a] L[b][b'] G_dd'(a, b, c), and the
+// face nodes pick up the face Jacobians and the lifting across the face
+// (+-s/(2w) to the node across it).  The host writes that linear map once per
+// order as a list of terms (destination node pair relative to the row's
+// element, source Jacobian relative to the same element, coefficient); the
+// device forms the pointwise Jacobians on dual numbers and sums the terms of
+// every destination block into A_ii, A_ib, A_bi and the A_bb pattern.
+// ---------------------------------------------------------------------------
+constexpr int kPjNode = 15;   // node Jacobians: Ja_d at d, Jv_d at 3 + d, G_dd' at 6 + 3 d + d'
+
+struct JacTerm {
+  int32_t rn, col_off, cn, src_off, slot;   // slot -1: the mass term (identity times inv_dt)
+  double coef;
+};
+
+// offsets (dx, dy, dz) in {-1, 0, 1}^3 as 0..26
+static inline int off_code(int dx, int dy, int dz) { return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1); }
+
+// every term of dH/dQ + M/dt for elements of order N = p - 1 on Cartesian
+// cubes (jac = (h/2)^3, s = 2/h) of a K^3 periodic mesh, merged and sorted by
+// destination
+std::vector<JacTerm> jac_terms(const DgParams &P) {
+  const int p = P.p, n = p - 1;
+  std::vector<JacTerm> t;
+  double bh[kMaxP][kMaxP], lo[kMaxP][kMaxP];
+  for (int l = 0; l < p; ++l)
+    for (int a = 0; a < p; ++a) {
+      bh[l][a] = -P.w[a] * P.d[a][l];
+      lo[l][a] = P.s * P.d[l][a];
+    }
+  bh[n][n] += 0.5;
+  bh[0][0] -= 0.5;
+  lo[n][n] -= P.s / (2 * P.w[n]);
+  lo[0][0] += P.s / (2 * P.w[0]);
+  const double hi = P.s / (2 * P.w[n]), lw = -P.s / (2 * P.w[0]);
+  auto node = [p](const int c[3]) { return c[0] + p * c[1] + p * p * c[2]; };
+  auto unit = [](int d, int sg, int o[3]) {
+    o[0] = o[1] = o[2] = 0;
+    o[d] = sg;
+  };
+  // with two elements per direction the neighbours at -1 and +1 are one
+  // element: column offsets are taken modulo 2 so that the terms of a block
+  // reached both ways are summed into one destination (in a fixed order)
+  const bool k2 = P.k_elem == 2;
+  auto add = [&](int rn, const int co[3], int cn, const int so[3], int slot, double coef) {
+    if (coef == 0.0) return;
+    int c3[3] = {co[0], co[1], co[2]};
+    if (k2)
+      for (int ax = 0; ax < 3; ++ax) c3[ax] = c3[ax] < 0 ? 1 : c3[ax];
+    t.push_back({rn, off_code(c3[0], c3[1], c3[2]), cn, off_code(so[0], so[1], so[2]), slot, coef});
+  };
+  const int Z[3] = {0, 0, 0};
+  int up[3], dn[3], o2[3];
+  for (int d = 0; d < 3; ++d) {
+    const int t0a = d == 0 ? 1 : 0, t1a = d == 2 ? 1 : 2;   // transverse axes, ascending
+    unit(d, 1, up);
+    unit(d, -1, dn);
+    for (int u0 = 0; u0 < p; ++u0)
+      for (int u1 = 0; u1 < p; ++u1) {
+        const double ct = P.jac * P.s * P.w[u0] * P.w[u1];
+        auto nd = [&](int lin) {
+          int c[3];
+          c[d] = lin;
+          c[t0a] = u0;
+          c[t1a] = u1;
+          return node(c);
+        };
+        const int face = p * p * p * kPjNode + (d * p * p + u1 * p + u0) * 2;   // PL; PR at +1 (higher axis first)
+        for (int l = 0; l < p; ++l)
+          for (int a = 0; a < p; ++a) {
+            add(nd(l), Z, nd(a), Z, nd(a) * kPjNode + d, ct * P.vw[l][a]);
+            add(nd(l), Z, nd(a), Z, nd(a) * kPjNode + 3 + d, -ct * bh[l][a]);
+            for (int b = 0; b < p; ++b) add(nd(l), Z, nd(a), Z, nd(b) * kPjNode + 6 + 4 * d, -ct * bh[l][b] * lo[b][a]);
+          }
+        // own face terms: the face Jacobians and the neighbour's lifting across the face
+        add(nd(n), Z, nd(n), Z, face, ct);
+        add(nd(n), Z, nd(n), up, nd(0) * kPjNode + 6 + 4 * d, ct * P.s / (4 * P.w[0]));
+        add(nd(0), Z, nd(0), dn, face + 1, -ct);
+        add(nd(0), Z, nd(0), dn, nd(n) * kPjNode + 6 + 4 * d, ct * P.s / (4 * P.w[n]));
+        // columns in the neighbours along d
+        for (int l = 0; l < p; ++l) {
+          add(nd(l), up, nd(0), Z, nd(n) * kPjNode + 6 + 4 * d, -bh[l][n] * ct * hi);
+          add(nd(l), dn, nd(n), Z, nd(0) * kPjNode + 6 + 4 * d, -bh[l][0] * ct * lw);
+        }
+        add(nd(n), up, nd(0), Z, face + 1, ct);
+        add(nd(n), up, nd(0), up, nd(0) * kPjNode + 3 + d, -0.5 * ct);
+        add(nd(0), dn, nd(n), dn, face, -ct);
+        add(nd(0), dn, nd(n), dn, nd(n) * kPjNode + 3 + d, 0.5 * ct);
+        for (int a = 0; a < p; ++a) {
+          add(nd(n), up, nd(a), up, nd(0) * kPjNode + 6 + 4 * d, -0.5 * ct * lo[0][a]);
+          add(nd(0), dn, nd(a), dn, nd(n) * kPjNode + 6 + 4 * d, 0.5 * ct * lo[n][a]);
+        }
+      }
+    for (int dp = 0; dp < 3; ++dp) {
+      if (dp == d) continue;
+      const int th = 3 - d - dp;
+      auto nd3 = [&](int ad, int bdp, int ct_) {
+        int c[3];
+        c[d] = ad;
+        c[dp] = bdp;
+        c[th] = ct_;
+        return node(c);
+      };
+      const int gs = 6 + 3 * d + dp;
+      for (int b = 0; b < p; ++b)
+        for (int c = 0; c < p; ++c) {
+          const double ct = P.jac * P.s * P.w[b] * P.w[c];
+          for (int l = 0; l < p; ++l)
+            for (int a = 0; a < p; ++a)
+              for (int bq = 0; bq < p; ++bq)
+                add(nd3(l, b, c), Z, nd3(a, bq, c), Z, nd3(a, b, c) * kPjNode + gs, -ct * bh[l][a] * lo[b][bq]);
+        }
+      // lifting across a dp-face of the element itself
+      for (int side = 0; side < 2; ++side) {
+        const int b = side ? n : 0, nb = side ? 0 : n, sg = side ? 1 : -1;
+        const double cf = side ? hi : lw;
+        unit(dp, sg, o2);
+        for (int c = 0; c < p; ++c) {
+          const double ct = P.jac * P.s * P.w[b] * P.w[c];
+          for (int l = 0; l < p; ++l)
+            for (int a = 0; a < p; ++a)
+              add(nd3(l, b, c), o2, nd3(a, nb, c), Z, nd3(a, b, c) * kPjNode + gs, -ct * cf * bh[l][a]);
+        }
+      }
+      // the neighbour across the d-face: its plane couplings reach the face row
+      for (int side = 0; side < 2; ++side) {
+        const int lr = side ? n : 0, lm = side ? 0 : n, sd = side ? 1 : -1;
+        const double sg = side ? 0.5 : -0.5;
+        int on[3];
+        unit(d, sd, on);
+        for (int b = 0; b < p; ++b)
+          for (int c = 0; c < p; ++c) {
+            const double ct = P.jac * P.s * P.w[b] * P.w[c];
+            for (int bq = 0; bq < p; ++bq)
+              add(nd3(lr, b, c), on, nd3(lm, bq, c), on, nd3(lm, b, c) * kPjNode + gs, -sg * ct * lo[b][bq]);
+          }
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const int b = s2 ? n : 0, nb = s2 ? 0 : n, sg2 = s2 ? 1 : -1;
+          const double cf = s2 ? hi : lw;
+          int oc[3] = {on[0], on[1], on[2]};
+          oc[dp] += sg2;
+          for (int c = 0; c < p; ++c) {
+            const double ct = P.jac * P.s * P.w[b] * P.w[c];
+            add(nd3(lr, b, c), oc, nd3(lm, nb, c), on, nd3(lm, b, c) * kPjNode + gs, -sg * ct * cf);
+          }
+        }
+      }
+    }
+  }
+  // M / dt on the diagonal (the coefficient is the mass; inv_dt enters on the device)
+  for (int k = 0; k < p; ++k)
+    for (int j = 0; j < p; ++j)
+      for (int i = 0; i < p; ++i) {
+        const int c[3] = {i, j, k};
+        add(node(c), Z, node(c), Z, -1, P.jac * P.w[i] * P.w[j] * P.w[k]);
+      }
+  std::sort(t.begin(), t.end(), [](const JacTerm &a, const JacTerm &b) {
+    if (a.rn != b.rn) return a.rn < b.rn;
+    if (a.col_off != b.col_off) return a.col_off < b.col_off;
+    if (a.cn != b.cn) return a.cn < b.cn;
+    if (a.src_off != b.src_off) return a.src_off < b.src_off;
+    return a.slot < b.slot;
+  });
+  std::vector<JacTerm> m;
+  for (const JacTerm &x : t) {
+    if (!m.empty() && m.back().rn == x.rn && m.back().col_off == x.col_off && m.back().cn == x.cn &&
+        m.back().src_off == x.src_off && m.back().slot == x.slot)
+      m.back().coef += x.coef;
+    else
+      m.push_back(x);
+  }
+  return m;
+}
+
+// what the block assembly reads and writes (uniform order, periodic K^3 mesh)
+struct JacBlocksArgs {
+  const int4 *dest;            // [n_dest] (row node, column element offset, column node, first term)
+  const int2 *term;            // [n_terms] (source element offset, source slot; -1: mass)
+  const double *coef;          // [n_terms]
+  int n_dest, n_terms;
+  const double *pj;            // pointwise Jacobians, rec blocks of 25 per element
+  int rec, k;
+  const int32_t *iidx, *rank;  // [p^3] interior index / boundary rank of each local node (-1 if none)
+  int ni, nc, ncn, nb;         // n_i, n_c (DOFs), |C_e| (nodes), boundary nodes per element
+  const int32_t *c_node;       // [n_elem * ncn] coupling sets, sorted per element
+  const int64_t *bb_rowptr;
+  const int32_t *bb_col;
+  double *aii, *aib, *abi, *bb_val;
+  double inv_dt;
+  int32_t *flag;               // set when a nonzero block has no place in the plan's structure
+};
+
+// the element at offset code oc from e on the periodic K^3 mesh
+__device__ __forceinline__ int elem_at(int e, int k, int oc) {
+  int c[3] = {e % k, (e / k) % k, e / (k * k)};
+  c[0] = (c[0] + oc % 3 - 1 + k) % k;
+  c[1] = (c[1] + (oc / 3) % 3 - 1 + k) % k;
+  c[2] = (c[2] + oc / 9 - 1 + k) % k;
+  return c[0] + k * c[1] + k * k * c[2];
+}
+
+// advective Lax-Friedrichs flux of a +e_d face (the viscous face terms enter
+// the blocks through Jv and G)
+template <class T>
+__device__ void face_flux_adv(const T ql[5], const T qr[5], int d, const DgParams &P, T fh[5]) {
+  T fl[5], fr[5];
+  flux_adv(ql, d, P.gamma, fl);
+  flux_adv(qr, d, P.gamma, fr);
+  const Prim<T> a = prim(ql, P.gamma), b = prim(qr, P.gamma);
+  const T lam_l = vabs(a.u[d]) + vsqrt(P.gamma * a.p / a.rho);
+  const T lam_r = vabs(b.u[d]) + vsqrt(P.gamma * b.p / b.rho);
+  const T lam = lam_l >= lam_r ? lam_l : lam_r;
+  for (int v = 0; v < 5; ++v) fh[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * lam * (qr[v] - ql[v]);
+}
+
+// node Jacobians: column kk of each 5x5 block from one dual evaluation seeded
+// on input kk; block layout [row v][column kk]
+__global__ __launch_bounds__(256) void pj_node_kernel(const DgParams *__restrict__ prm, const double *__restrict__ q,
+                                                      const double *__restrict__ g, double *__restrict__ pj,
+                                                      int64_t n_nodes, int rec) {
+  __shared__ DgParams P;
+  load_params(prm, &P);
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n_nodes) return;
+  const int p3 = P.p * P.p * P.p;
+  const int64_t e = i / p3;
+  const int node = (int)(i % p3);
+  double *out = pj + (e * rec + (int64_t)node * kPjNode) * 25;
+  double qv[5], gv[15];
+  for (int v = 0; v < 5; ++v) qv[v] = q[i * 5 + v];
+  for (int t = 0; t < 15; ++t) gv[t] = g[i * 15 + t];
+  for (int d = 0; d < 3; ++d) {
+    for (int kk = 0; kk < 5; ++kk) {
+      Dual qd[5], gd[15], f[5];
+      for (int v = 0; v < 5; ++v) qd[v] = Dual(qv[v], v == kk ? 1.0 : 0.0);
+      for (int t = 0; t < 15; ++t) gd[t] = Dual(gv[t], 0.0);
+      flux_adv(qd, d, P.gamma, f);
+      for (int v = 0; v < 5; ++v) out[d * 25 + v * 5 + kk] = f[v].d;
+      flux_visc(qd, gd, d, P, f);
+      for (int v = 0; v < 5; ++v) out[(3 + d) * 25 + v * 5 + kk] = f[v].d;
+    }
+    for (int dp = 0; dp < 3; ++dp)
+      for (int kk = 0; kk < 5; ++kk) {
+        Dual qd[5], gd[15], f[5];
+        for (int v = 0; v < 5; ++v) qd[v] = Dual(qv[v], 0.0);
+        for (int t = 0; t < 15; ++t) gd[t] = Dual(gv[t], t == dp * 5 + kk ? 1.0 : 0.0);
+        flux_visc(qd, gd, d, P, f);
+        for (int v = 0; v < 5; ++v) out[(6 + 3 * d + dp) * 25 + v * 5 + kk] = f[v].d;
+      }
+  }
+}
+
+// face Jacobians of every +e_d face of every element: thread (e, d, u1, u0),
+// u0 / u1 the coordinates along the lower / higher transverse axis
+__global__ __launch_bounds__(256) void pj_face_kernel(const DgParams *__restrict__ prm, const double *__restrict__ q,
+                                                      double *__restrict__ pj, int64_t n_faces, int rec) {
+  __shared__ DgParams P;
+  load_params(prm, &P);
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n_faces) return;
+  const int p = P.p, p2 = p * p, p3 = p2 * p, n = p - 1;
+  const int64_t e = i / (3 * p2);
+  const int r = (int)(i % (3 * p2));
+  const int d = r / p2, u1 = (r % p2) / p, u0 = r % p;
+  const int t0a = d == 0 ? 1 : 0, t1a = d == 2 ? 1 : 2;
+  int c[3];
+  c[t0a] = u0;
+  c[t1a] = u1;
+  c[d] = n;
+  const int nl = c[0] + p * c[1] + p2 * c[2];
+  c[d] = 0;
+  const int nr = c[0] + p * c[1] + p2 * c[2];
+  const int er = nbr_elem((int)e, P.k_elem, d, 1);
+  double ql[5], qr[5];
+  for (int v = 0; v < 5; ++v) {
+    ql[v] = q[(e * p3 + nl) * 5 + v];
+    qr[v] = q[((int64_t)er * p3 + nr) * 5 + v];
+  }
+  double *out = pj + (e * rec + (int64_t)p3 * kPjNode + r * 2) * 25;
+  for (int side = 0; side < 2; ++side)
+    for (int kk = 0; kk < 5; ++kk) {
+      Dual a[5], b[5], f[5];
+      for (int v = 0; v < 5; ++v) {
+        a[v] = Dual(ql[v], side == 0 && v == kk ? 1.0 : 0.0);
+        b[v] = Dual(qr[v], side == 1 && v == kk ? 1.0 : 0.0);
+      }
+      face_flux_adv(a, b, d, P, f);
+      for (int v = 0; v < 5; ++v) out[side * 25 + v * 5 + kk] = f[v].d;
+    }
+}
+
+// position of key in the sorted list a[0, len), or -1
+__device__ __forceinline__ int find_sorted(const int32_t *__restrict__ a, int len, int32_t key) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < len && a[lo] == key ? lo : -1;
+}
+
+// one thread per (element, destination block): the sum of its terms, written
+// to A_ii, A_ib, A_bi or A_bb by the interior / boundary roles of its row and
+// column nodes
+__global__ __launch_bounds__(256) void jac_assemble_kernel(JacBlocksArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y;
+  if (t >= a.n_dest) return;
+  const int4 ds = a.dest[t];
+  const int tb = ds.w, te = t + 1 < a.n_dest ? a.dest[t + 1].w : a.n_terms;
+  double acc[25];
+#pragma unroll
+  for (int u = 0; u < 25; ++u) acc[u] = 0.0;
+  for (int j = tb; j < te; ++j) {
+    const int2 ti = a.term[j];
+    const double cf = a.coef[j];
+    if (ti.y < 0) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[v * 6] += cf * a.inv_dt;
+      continue;
+    }
+    const double *__restrict__ src = a.pj + ((int64_t)elem_at(e, a.k, ti.x) * a.rec + ti.y) * 25;
+#pragma unroll
+    for (int u = 0; u < 25; ++u) acc[u] += cf * src[u];
+  }
+  bool nz = false;
+#pragma unroll
+  for (int u = 0; u < 25; ++u) nz = nz || acc[u] != 0.0;
+  const int rn = ds.x, cn = ds.z;
+  const int ce = elem_at(e, a.k, ds.y);
+  const int ri = a.iidx[rn], ci = a.iidx[cn];
+  double *dst = nullptr;
+  int64_t ld = 0;
+  if (ri >= 0 && ci >= 0) {
+    if (ce == e) {
+      ld = a.ni;
+      dst = a.aii + (int64_t)e * a.ni * a.ni + (int64_t)(5 * ri) * ld + 5 * ci;
+    }
+  } else if (ri >= 0) {
+    const int pos = find_sorted(a.c_node + (int64_t)e * a.ncn, a.ncn, ce * a.nb + a.rank[cn]);
+    if (pos >= 0) {
+      ld = a.nc;
+      dst = a.aib + (int64_t)e * a.ni * a.nc + (int64_t)(5 * ri) * ld + 5 * pos;
+    }
+  } else if (ci >= 0) {
+    const int pos = find_sorted(a.c_node + (int64_t)ce * a.ncn, a.ncn, e * a.nb + a.rank[rn]);
+    if (pos >= 0) {
+      ld = a.ni;
+      dst = a.abi + (int64_t)ce * a.ni * a.nc + (int64_t)(5 * pos) * ld + 5 * ci;
+    }
+  } else {
+    const int gr = e * a.nb + a.rank[rn], gc = ce * a.nb + a.rank[cn];
+    const int64_t b0 = a.bb_rowptr[gr];
+    const int pos = find_sorted(a.bb_col + b0, (int)(a.bb_rowptr[gr + 1] - b0), gc);
+    if (pos >= 0) {
+      ld = 5;
+      dst = a.bb_val + (b0 + pos) * 25;
+    }
+  }
+  if (!dst) {
+    if (nz) a.flag[0] = 1;   // a nonzero block the plan's structure has no room for
+    return;
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int w = 0; w < 5; ++w) dst[v * ld + w] = acc[v * 5 + w];
+}
+
+__global__ void fill_zero_kernel(double *__restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0;
+}
+
 struct DgContext {
   DgParams host;
   DgParams *dev = nullptr;
@@ -758,6 +1152,14 @@ struct DgContext {
   int64_t n_nodes = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
+  // device Jacobian blocks: the term template of this order and the pointwise
+  // Jacobians (allocated by the first scdg_dg_jacobian_blocks call)
+  int jt_ndest = 0, jt_nterms = 0;
+  int4 *jt_dest = nullptr;
+  int2 *jt_term = nullptr;
+  double *jt_coef = nullptr;
+  int32_t *jt_iidx = nullptr, *jt_rank = nullptr, *jt_flag = nullptr;
+  double *pj = nullptr;
 };
 
 }  // namespace scdg
@@ -896,6 +1298,115 @@ void dg_graph_state(const scdg_dg *dg, uint64_t *gen, const void **g, const void
   *params = dg->c.dev;
 }
 
+std::string dg_last_error(const scdg_dg *dg) { return dg->c.last_error; }
+
+bool dg_jacobian_shape(const scdg_dg *dg, int *k_elem, int *order, bool *cartesian_br1) {
+  *k_elem = dg->c.host.k_elem;
+  *order = dg->c.host.p - 1;
+  *cartesian_br1 = !dg->c.met && !dg->c.host.sipg;
+  return true;
+}
+
+scdg_status dg_jacobian_blocks_on(scdg_dg *dg, const JacPlanView &v, const double *q, double inv_dt, double *aii,
+                                  double *aib, double *abi, double *bb_val) {
+  auto &c = dg->c;
+  const int p = c.host.p, p3 = p * p * p, n = p - 1;
+  const int n_elem = c.host.k_elem * c.host.k_elem * c.host.k_elem;
+  const int rec = p3 * kPjNode + 3 * p * p * 2;
+  auto fail = [&](const char *what) {
+    c.last_error = std::string("scdg_dg_jacobian_blocks: ") + what;
+    return SCDG_ERR_HIP;
+  };
+  if (!c.jt_dest) {
+    const std::vector<JacTerm> t = jac_terms(c.host);
+    std::vector<int4> dest;
+    std::vector<int2> term(t.size());
+    std::vector<double> coef(t.size());
+    for (size_t j = 0; j < t.size(); ++j) {
+      if (j == 0 || t[j].rn != t[j - 1].rn || t[j].col_off != t[j - 1].col_off || t[j].cn != t[j - 1].cn)
+        dest.push_back(make_int4(t[j].rn, t[j].col_off, t[j].cn, (int)j));
+      term[j] = make_int2(t[j].src_off, t[j].slot);
+      coef[j] = t[j].coef;
+    }
+    std::vector<int32_t> iidx(p3, -1), rank(p3, -1);
+    int ni = 0, nb = 0;
+    for (int node = 0; node < p3; ++node) {
+      const int cc[3] = {node % p, (node / p) % p, node / (p * p)};
+      const bool in = cc[0] >= 1 && cc[0] <= n - 1 && cc[1] >= 1 && cc[1] <= n - 1 && cc[2] >= 1 && cc[2] <= n - 1;
+      if (in)
+        iidx[node] = ni++;
+      else
+        rank[node] = nb++;
+    }
+    c.jt_ndest = (int)dest.size();
+    c.jt_nterms = (int)t.size();
+    if (hipMalloc(&c.jt_dest, sizeof(int4) * dest.size()) != hipSuccess ||
+        hipMalloc(&c.jt_term, sizeof(int2) * term.size()) != hipSuccess ||
+        hipMalloc(&c.jt_coef, sizeof(double) * coef.size()) != hipSuccess ||
+        hipMalloc(&c.jt_iidx, sizeof(int32_t) * p3) != hipSuccess ||
+        hipMalloc(&c.jt_rank, sizeof(int32_t) * p3) != hipSuccess ||
+        hipMalloc(&c.jt_flag, sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c.pj, sizeof(double) * 25 * (size_t)rec * n_elem) != hipSuccess)
+      return SCDG_ERR_NOMEM;
+    if (hipMemcpy(c.jt_dest, dest.data(), sizeof(int4) * dest.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.jt_term, term.data(), sizeof(int2) * term.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.jt_coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.jt_iidx, iidx.data(), sizeof(int32_t) * p3, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.jt_rank, rank.data(), sizeof(int32_t) * p3, hipMemcpyHostToDevice) != hipSuccess)
+      return fail("upload of the term template");
+  }
+  const hipStream_t s = c.stream;
+  const int64_t n_ii = (int64_t)n_elem * v.ni * v.ni, n_ib = (int64_t)n_elem * v.ni * v.nc;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(2048), dim3(256), 0, s, aii, n_ii);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(2048), dim3(256), 0, s, aib, n_ib);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(2048), dim3(256), 0, s, abi, n_ib);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(2048), dim3(256), 0, s, bb_val, v.nnzb * 25);
+  if (hipMemsetAsync(c.jt_flag, 0, sizeof(int32_t), s) != hipSuccess) return fail("flag reset");
+  const int threads = ((p3 + 63) / 64) * 64;
+  hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g, nullptr);
+  const int64_t n_nodes = (int64_t)n_elem * p3, n_faces = (int64_t)n_elem * 3 * p * p;
+  hipLaunchKernelGGL(pj_node_kernel, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s, c.dev, q, c.g, c.pj,
+                     n_nodes, rec);
+  hipLaunchKernelGGL(pj_face_kernel, dim3((unsigned)((n_faces + 255) / 256)), dim3(256), 0, s, c.dev, q, c.pj,
+                     n_faces, rec);
+  JacBlocksArgs a;
+  a.dest = c.jt_dest;
+  a.term = c.jt_term;
+  a.coef = c.jt_coef;
+  a.n_dest = c.jt_ndest;
+  a.n_terms = c.jt_nterms;
+  a.pj = c.pj;
+  a.rec = rec;
+  a.k = c.host.k_elem;
+  a.iidx = c.jt_iidx;
+  a.rank = c.jt_rank;
+  a.ni = v.ni;
+  a.nc = v.nc;
+  a.ncn = v.ncn;
+  a.nb = v.nb;
+  a.c_node = v.c_node;
+  a.bb_rowptr = v.bb_rowptr;
+  a.bb_col = v.bb_col;
+  a.aii = aii;
+  a.aib = aib;
+  a.abi = abi;
+  a.bb_val = bb_val;
+  a.inv_dt = inv_dt;
+  a.flag = c.jt_flag;
+  hipLaunchKernelGGL(jac_assemble_kernel, dim3((unsigned)((c.jt_ndest + 255) / 256), (unsigned)n_elem), dim3(256), 0,
+                     s, a);
+  if (hipGetLastError() != hipSuccess) return fail("launch");
+  int32_t flag = 0;
+  if (hipMemcpyAsync(&flag, c.jt_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail("synchronisation");
+  if (flag) {
+    c.last_error = "scdg_dg_jacobian_blocks: a nonzero block has no place in the plan's coupling sets or A_bb pattern";
+    return SCDG_ERR_ARG;
+  }
+  return SCDG_OK;
+}
+
 }  // namespace scdg
 
 extern "C" {
@@ -958,6 +1469,9 @@ scdg_status scdg_dg_destroy(scdg_dg *dg) {
   if (dg->c.gb) (void)hipFree(dg->c.gb);
   if (dg->c.gbd) (void)hipFree(dg->c.gbd);
   if (dg->c.met) (void)hipFree(dg->c.met);
+  for (void *ptr : {(void *)dg->c.jt_dest, (void *)dg->c.jt_term, (void *)dg->c.jt_coef, (void *)dg->c.jt_iidx,
+                    (void *)dg->c.jt_rank, (void *)dg->c.jt_flag, (void *)dg->c.pj})
+    if (ptr) (void)hipFree(ptr);
   delete dg;
   return SCDG_OK;
 }

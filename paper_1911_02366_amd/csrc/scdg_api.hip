@@ -847,6 +847,7 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.d_fold_dst); dfree(p.d_fold_nc); dfree(p.d_fold_src);
   dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk); dfree(p.rem_val);
   dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_inv_order); dfree(p.d_info);
+  dfree(p.d_jac_cnode);
   dfree(p.d_gx); dfree(p.d_gs); dfree(p.d_tiles_x); dfree(p.d_tiles_s);
   dfree(p.d_gv_inv); dfree(p.d_gv_abi); dfree(p.d_gv_aib); dfree(p.d_gv_s);
   dfree(p.d_rt_inv); dfree(p.d_rt_abi); dfree(p.d_rt_aib); dfree(p.d_rt_s);
@@ -1501,6 +1502,46 @@ scdg_status scdg_backsolve(scdg_plan *pl, const double *b, const double *qb, dou
   Plan &p = pl->p;
   if (p.state < 3) return SCDG_ERR_STATE;
   return backsolve_impl(p, b, qb, dq);
+}
+
+scdg_status scdg_dg_jacobian_blocks(scdg_dg *dg, scdg_plan *pl, const double *q, double inv_dt, double *aii,
+                                    double *aib, double *abi, double *bb_val) {
+  if (!dg || !pl || !q || !aii || !aib || !abi || (pl->p.nnzb > 0 && !bb_val) || !(inv_dt >= 0.0) ||
+      !std::isfinite(inv_dt))
+    return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  int k = 0, order = 0;
+  bool cart = false;
+  dg_jacobian_shape(dg, &k, &order, &cart);
+  const int pp = order + 1;
+  const int nb = pp * pp * pp - (order - 1) * (order - 1) * (order - 1);
+  const int ni = 5 * (order - 1) * (order - 1) * (order - 1);
+  if (!cart) {
+    p.last_error = "scdg_dg_jacobian_blocks: Cartesian cubes and the Bassi-Rebay 1 flux only";
+    return SCDG_ERR_UNSUPPORTED;
+  }
+  bool same = p.n_elem == k * k * k;
+  const int64_t ncn = p.n_elem > 0 ? p.h_c_ptr[1] - p.h_c_ptr[0] : 0;
+  for (int e = 0; same && e < p.n_elem; ++e)
+    same = p.order[e] == order && p.ni[e] == ni && p.nc[e] == 5 * ncn && p.bnode_off[e] == (int64_t)e * nb &&
+           p.h_c_ptr[e + 1] - p.h_c_ptr[e] == ncn;
+  if (!same) {
+    p.last_error = "scdg_dg_jacobian_blocks: the plan is not the DG object's periodic mesh of uniform order";
+    return SCDG_ERR_UNSUPPORTED;
+  }
+  if (!p.d_jac_cnode) ST_TRY(upload(p, &p.d_jac_cnode, p.h_c_node));
+  JacPlanView v;
+  v.ni = ni;
+  v.nc = (int)(5 * ncn);
+  v.ncn = (int)ncn;
+  v.nb = nb;
+  v.nnzb = p.nnzb;
+  v.c_node = p.d_jac_cnode;
+  v.bb_rowptr = p.d_bb_rowptr;
+  v.bb_col = p.d_bb_col;
+  const scdg_status st = dg_jacobian_blocks_on(dg, v, q, inv_dt, aii, aib, abi, bb_val);
+  if (st != SCDG_OK) p.last_error = dg_last_error(dg);
+  return st;
 }
 
 scdg_status scdg_residual(scdg_plan *pl, const double *b, const double *dq, double *r,

@@ -53,6 +53,25 @@ class DgResidual:
             raise L.ScdgError(st, "scdg_dg_residual")
         return out
 
+    def jacobian_blocks(self, plan, q: torch.Tensor, inv_dt: float) -> dict:
+        """Element blocks of A = M inv_dt + dH/dQ(q) in the plan's format (aii,
+        aib, abi, bb_val), formed on the device (scdg_dg_jacobian_blocks)."""
+        self._check(q, "q")
+        h = plan._host
+        n_i = 5 * (h["order"].astype(np.int64) - 1) ** 3
+        n_c = 5 * np.diff(h["c_ptr"])
+        dev = q.device
+        out = dict(aii=torch.empty(int((n_i * n_i).sum()), dtype=torch.float64, device=dev),
+                   aib=torch.empty(int((n_i * n_c).sum()), dtype=torch.float64, device=dev),
+                   abi=torch.empty(int((n_i * n_c).sum()), dtype=torch.float64, device=dev),
+                   bb_val=torch.empty(max(1, 25 * len(h["bb_col"])), dtype=torch.float64, device=dev))
+        st = self.lib.scdg_dg_jacobian_blocks(self.handle, plan.handle, _ptr(q), float(inv_dt), _ptr(out["aii"]),
+                                              _ptr(out["aib"]), _ptr(out["abi"]), _ptr(out["bb_val"]))
+        if st != L.SCDG_OK:
+            raise L.ScdgError(st, "scdg_dg_jacobian_blocks", L.last_error(plan.handle))
+        out["bb_val"] = out["bb_val"][:25 * len(h["bb_col"])]
+        return out
+
     def jacobian_apply(self, q: torch.Tensor, v: torch.Tensor, inv_dt: float = 0.0,
                        out: torch.Tensor | None = None) -> torch.Tensor:
         """A v = M v inv_dt + dH/dQ(q) v, the Newton matrix at q applied to v

@@ -51,7 +51,14 @@ class ImplicitStepper:
         self.dg = DgResidual(k_elem, order, mach=mach, reynolds=reynolds, viscous=viscous)
         if xyz is not None:
             self.dg.set_geometry(xyz)            # curved hexahedra: the residual takes the metric terms
-        self.dt, self.jacobian = dt, jacobian
+        self.dt = dt
+        # jacobian: a callable q -> blocks, or "device" for the library's own
+        # blocks (scdg_dg_jacobian_blocks; Cartesian cubes, Bassi-Rebay 1)
+        if isinstance(jacobian, str):
+            if jacobian != "device":
+                raise ValueError("jacobian: a callable or 'device'")
+            jacobian = lambda q: self.dg.jacobian_blocks(self.plan, q, 1.0 / self.dt)
+        self.jacobian = jacobian
         self.lin_tol, self.newton_tol, self.max_newton = lin_tol, newton_tol, max_newton
         self.restart, self.precond, self.precision = restart, precond, precision
         self._tune = autotune
