@@ -182,7 +182,7 @@ scdg_status scdg_get_schur_mode(const scdg_plan *p, int32_t *mode);
  * form 2); 1 one workgroup per element for the whole elimination, 24- or
  * 32-column panels in LDS; 2 blocked: outer panels of 128 columns whose update
  * of the rest of the block is a batched matrix-core GEMM; 3 resident panel:
- * one workgroup per element holding an outer panel of 48 (FP64) or up to 112
+ * one workgroup per element holding an outer panel of 48 (FP64) or 64
  * (FP32) columns in LDS, so the rest of the block is streamed once per outer
  * panel (n_i <= 352, SCDG_ERR_UNSUPPORTED from scdg_factor otherwise).  All
  * forms use the same pivot rule (largest |a| among unused rows, lowest row on

@@ -336,8 +336,8 @@ __global__ __launch_bounds__(kThreads) void gj_inverse_kernel(const double *__re
 // ---------------------------------------------------------------------------
 // Resident-panel form (n_i <= kResMaxN).  One workgroup per element, as in the
 // single-kernel form, but the LDS holds an outer panel of NBO columns (48 in
-// FP64, up to 112 in FP32), so the rest of the block in global memory is read
-// and written once per NBO columns instead of once per 24 or 32.
+// FP64, 64 in FP32), so the rest of the block in global memory is read and
+// written once per NBO columns instead of once per 24 or 32.
 //   * The block is bordered to rp = n rounded up to 16 with an identity block
 //     (rows and columns n..rp-1).  Its inverse is the inverse of A bordered
 //     with the same identity, the border never mixes with A (its rows and
@@ -381,12 +381,13 @@ constexpr int res_slots(int panel_tiles, int max_tiles, int waves) {
   return worst / waves + 2;
 }
 
-template <typename T_, int NBO_, int G_, int MAXN_>
+template <typename T_, int NBO_, int G_, int MAXN_, int NT_ = kResThreads>
 struct GjRes {
   using T = T_;
-  static constexpr int NBO = NBO_, G = G_, MAXN = MAXN_;
-  static constexpr int SLOTS = res_slots(NBO_ / 16, (MAXN_ + 15) / 16, kResWaves);
-  static constexpr int PS = NBO_ + (sizeof(T_) == 8 ? 2 : 4);   // 400 B rows at 48 / 96: conflict-free A reads
+  static constexpr int NBO = NBO_, G = G_, MAXN = MAXN_, NT = NT_, W = NT_ / 64;
+  static constexpr int SLOTS = res_slots(NBO_ / 16, (MAXN_ + 15) / 16, NT_ / 64);
+  static_assert(NT_ >= 64 * kResElimWaves && MAXN_ <= 128 * kResElimWaves, "rows held two per lane by four waves");
+  static constexpr int PS = NBO_ + (sizeof(T_) == 8 ? 2 : 4);   // 100 / 68 dwords at FP64 48 / FP32 64: conflict-free A reads
   static size_t lds_bytes(int max_n) {
     const size_t rp = (size_t)((max_n + 15) & ~15);
     return sizeof(T) * (rp * PS + 2 * kResElimWaves * kResInner + 4 * kResElimWaves) +
@@ -430,7 +431,7 @@ __device__ __forceinline__ T pivot_key(T a, bool live) {
 }
 
 template <class L>
-__global__ __launch_bounds__(kResThreads) void gj_resident_kernel(const double *__restrict__ src,
+__global__ __launch_bounds__(L::NT) void gj_resident_kernel(const double *__restrict__ src,
                                                                   typename L::T *__restrict__ work,
                                                                   typename L::T *__restrict__ out,
                                                                   const int32_t *__restrict__ n_arr,
@@ -439,9 +440,9 @@ __global__ __launch_bounds__(kResThreads) void gj_resident_kernel(const double *
                                                                   int32_t *__restrict__ info) {
   using T = typename L::T;
   using M = Mfma<T>;
-  constexpr int NBO = L::NBO, PS = L::PS, G = L::G, W = kResWaves, EW = kResElimWaves, NI = kResInner;
+  constexpr int NBO = L::NBO, PS = L::PS, G = L::G, W = L::W, NT = L::NT, EW = kResElimWaves, NI = kResInner;
   constexpr int NQ = NBO / 4;                                          // K steps of the outer pass
-  constexpr int NLD = (L::MAXN * NBO + kResThreads - 1) / kResThreads;   // panel values per thread
+  constexpr int NLD = (L::MAXN * NBO + NT - 1) / NT;                   // panel values per thread
   constexpr int NLB = NLD < 40 ? NLD : 40;                             // loaded per batch
   constexpr int SL = L::SLOTS;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -481,12 +482,12 @@ __global__ __launch_bounds__(kResThreads) void gj_resident_kernel(const double *
       // kept live across the whole kernel
 #pragma unroll 1
       for (int u0 = 0; u0 < NLD; u0 += NLB) {
-        int tl = tid + u0 * kResThreads;
+        int tl = tid + u0 * NT;
         asm volatile("" : "+v"(tl));
         T tmp[NLB];
 #pragma unroll
         for (int u = 0; u < NLB; ++u) {
-          const int idx = tl + u * kResThreads;
+          const int idx = tl + u * NT;
           const int i = idx / NBO, c = idx % NBO, col = kb + c;
           T v = T(0);
           if (idx < rp * NBO) {
@@ -499,12 +500,12 @@ __global__ __launch_bounds__(kResThreads) void gj_resident_kernel(const double *
         }
 #pragma unroll
         for (int u = 0; u < NLB; ++u) {
-          const int idx = tl + u * kResThreads;
+          const int idx = tl + u * NT;
           if (idx < rp * NBO) pnl[(idx / NBO) * PS + idx % NBO] = tmp[u];
         }
       }
     }
-    for (int i = tid; i < rp; i += kResThreads) pflag[i] = 0;
+    for (int i = tid; i < rp; i += NT) pflag[i] = 0;
     __syncthreads();
 
     for (int c0 = 0; c0 < nbo; c0 += NI) {
@@ -697,7 +698,7 @@ __global__ __launch_bounds__(kResThreads) void gj_resident_kernel(const double *
         }
       }
       // the transformed outer panel goes back to global memory (columns of A only)
-      for (int idx = tid; idx < n * NBO; idx += kResThreads) {
+      for (int idx = tid; idx < n * NBO; idx += NT) {
         const int i = idx / NBO, c = idx % NBO;
         if (kb + c < n) w[i * n + kb + c] = pnl[i * PS + c];
       }
@@ -783,7 +784,7 @@ __global__ __launch_bounds__(kResThreads) void gj_resident_kernel(const double *
   }
 
   // read the inverse out through the pivot permutation: A^-1[k][m] = W[p_k][q_m]
-  for (int k = tid; k < rp; k += kResThreads) qinv[piv[k]] = k;
+  for (int k = tid; k < rp; k += NT) qinv[piv[k]] = k;
   __syncthreads();
   {
     constexpr int kCols = (kResMaxN + 63) / 64, kRows = 4;
@@ -1038,30 +1039,37 @@ hipError_t gj_res_launch(Plan &p, typename L::T *work, typename L::T *out) {
   hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(gj_resident_kernel<L>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((gj_resident_kernel<L>), dim3(p.n_elem), dim3(kResThreads), lds, p.stream, p.aii, work, out,
+  hipLaunchKernelGGL((gj_resident_kernel<L>), dim3(p.n_elem), dim3(L::NT), lds, p.stream, p.aii, work, out,
                      p.d_inv_n, p.d_inv_off, p.d_inv_order, p.d_info);
   return hipGetLastError();
 }
 
-// FP64: 48-column outer panels; FP32: the widest of 112 / 96 / 48 that fits
+// outer panels of 48 FP64 / 64 FP32 columns, one 512-thread workgroup per CU.
+// Measured at n_i = 320 (8^3 x N = 5): FP32 112 / 96 / 80 / 64 / 48 / 32
+// columns take 1.54 / 1.62 / 1.55 / 1.43 / 1.64 / 1.81 ms (wider panels: fewer
+// passes but a larger in-LDS update per inner panel); two 256-thread
+// workgroups per CU with 48 columns 1.53 ms.  FP64 48 is the widest that fits.
+// Each comes in two sizes: up to n_i = 320 (N <= 5; fewer column tiles, so
+// fewer registers for the B operands of a wave's share: FP32 1.43 against
+// 1.54 ms) and up to kResMaxN.
 using GjRes64 = GjRes<double, 48, 2, kResMaxN>;
-using GjRes32w = GjRes<float, 112, 2, 320>;
-using GjRes32m = GjRes<float, 96, 2, kResMaxN>;
-using GjRes32s = GjRes<float, 48, 2, kResMaxN>;
+using GjRes32 = GjRes<float, 64, 2, kResMaxN>;
+using GjRes64n5 = GjRes<double, 48, 2, 320>;
+using GjRes32n5 = GjRes<float, 64, 2, 320>;
 
 }  // namespace
 
 bool gj_resident_supported(int max_n, bool fp32) {
   if (max_n > kResMaxN) return false;
-  return fp32 ? GjRes32s::lds_bytes(max_n) <= kLdsLimit : GjRes64::lds_bytes(max_n) <= kLdsLimit;
+  return fp32 ? GjRes32::lds_bytes(max_n) <= kLdsLimit : GjRes64::lds_bytes(max_n) <= kLdsLimit;
 }
 
 hipError_t launch_gj_inverse_resident(Plan &p, void *work, void *out, bool fp32) {
-  if (!fp32) return gj_res_launch<GjRes64>(p, static_cast<double *>(work), static_cast<double *>(out));
   float *wf = static_cast<float *>(work), *of = static_cast<float *>(out);
-  if (p.max_ni <= GjRes32w::MAXN && GjRes32w::lds_bytes(p.max_ni) <= kLdsLimit) return gj_res_launch<GjRes32w>(p, wf, of);
-  if (GjRes32m::lds_bytes(p.max_ni) <= kLdsLimit) return gj_res_launch<GjRes32m>(p, wf, of);
-  return gj_res_launch<GjRes32s>(p, wf, of);
+  double *wd = static_cast<double *>(work), *od = static_cast<double *>(out);
+  if (p.max_ni <= GjRes32n5::MAXN)
+    return fp32 ? gj_res_launch<GjRes32n5>(p, wf, of) : gj_res_launch<GjRes64n5>(p, wd, od);
+  return fp32 ? gj_res_launch<GjRes32>(p, wf, of) : gj_res_launch<GjRes64>(p, wd, od);
 }
 
 bool gj_supported(int max_n, bool fp32) {

@@ -87,3 +87,113 @@ def load_traffic(path: str, sources) -> dict | None:
     if rec.get("source_digest") != source_digest(sources):
         return None
     return rec
+
+
+# ---------------------------------------------------------------------------
+# Command line: summaries under profiles/ from rocprofv3 csv directories
+#   python -m paper_1911_02366_amd.profiling stats DIR OUT.md --command "..." [--note "..."]
+#   python -m paper_1911_02366_amd.profiling traffic --fetch D --write D --copy-fetch D --copy-write D
+#          --workload W --precision P --command "..." (repeatable)
+# ---------------------------------------------------------------------------
+_COPY_BYTES = 2 << 30     # bench.py --calibrate-copy copies a 2 GiB FP64 buffer
+
+
+def _by_kernel(directory: str, counter: str):
+    """{(short kernel name, grid): [per-dispatch values]} of one counter."""
+    out = {}
+    for r in _rows(directory, "*counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        key = (short_name(r.get("Kernel_Name", "")), int(float(r.get("Grid_Size", -1))))
+        out.setdefault(key, []).append(float(r["Counter_Value"]))
+    return out
+
+
+def _copy_scale(directory: str, counter: str) -> float:
+    vals = [v for (k, _), vs in _by_kernel(directory, counter).items() if "copyBuffer" in k for v in vs]
+    if not vals:
+        raise RuntimeError(f"no copy kernel in {directory}")
+    return _COPY_BYTES / (1024.0 * max(vals))
+
+
+def traffic_summary(fetch: str, write: str, copy_fetch: str, copy_write: str, workload: str, precision: str,
+                    commands, root: str = "."):
+    fs, ws = _copy_scale(copy_fetch, "FETCH_SIZE"), _copy_scale(copy_write, "WRITE_SIZE")
+    fk, wk = _by_kernel(fetch, "FETCH_SIZE"), _by_kernel(write, "WRITE_SIZE")
+    mean = lambda v: sum(v) / len(v)
+    rows = []
+    for key, fv in fk.items():
+        wv = wk.get(key, [0.0])
+        rows.append(dict(kernel=key[0], grid=key[1], n=len(fv), fetch=mean(fv), write=mean(wv),
+                         bytes=1024.0 * (mean(fv) * fs + mean(wv) * ws)))
+    rows.sort(key=lambda r: -r["bytes"] * r["n"])
+    csrc = os.path.join(root, "paper_1911_02366_amd", "csrc")
+    pick = lambda part: [r for r in rows if part in r["kernel"]]
+    recs = {}
+    gemv = pick("schur_gemv_rem_kernel")
+    if gemv:
+        g = gemv[0]
+        pulls = sorted(pick("bsr_pull_kernel"), key=lambda r: (abs(r["n"] - g["n"]), -r["n"]))
+        b = g["bytes"] + (pulls[0]["bytes"] if pulls else 0.0)
+        recs["schur_apply"] = (dict(kernel="schur_apply (schur_gemv_rem_kernel: T_e GEMV tiles and A_bb remainder "
+                                           "rows; bsr_pull_kernel)", traffic_bytes_per_launch=b),
+                               ["k_vec.hip"])
+    inv = pick("gj_resident_kernel") or pick("gj_inverse_kernel")
+    if inv:
+        recs["inverse"] = (dict(kernel=inv[0]["kernel"], traffic_bytes_per_launch=inv[0]["bytes"]), ["k_inverse.hip"])
+    gemms = sorted(pick("gemm_batched_kernel"), key=lambda r: -r["grid"])
+    if len(gemms) >= 2:
+        recs["gemm_s"] = (dict(kernel=gemms[0]["kernel"] + " (A_bi X_e)",
+                               traffic_bytes_per_launch=gemms[0]["bytes"]), ["k_gemm.hip"])
+        recs["gemm_x"] = (dict(kernel=gemms[1]["kernel"] + " (A_ii^-1 A_ib)",
+                               traffic_bytes_per_launch=gemms[1]["bytes"]), ["k_gemm.hip"])
+    md = os.path.join(root, "profiles", f"hbm_counters_{workload}_{precision}.md")
+    for name, (rec, srcs) in recs.items():
+        rec.update(workload=workload, precision=precision, fetch_scale=fs, write_scale=ws,
+                   source_digest=source_digest([os.path.join(csrc, s) for s in srcs]),
+                   commands=list(commands), summary=os.path.relpath(md, root))
+        with open(os.path.join(root, "profiles", f"traffic_{name}_{workload}_{precision}.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+    with open(md, "w") as fh:
+        fh.write(f"# HBM traffic counters, {workload}, {precision.upper()}\n\n")
+        fh.write("Commands (repository root, MI355X), one counter per run; the kernel-trace run writes the tile "
+                 "choice to the autotune cache first, so the counter runs take the same tiles:\n\n```\n")
+        fh.write("\n".join(commands) + "\n```\n\n")
+        fh.write(f"Calibration: the {_COPY_BYTES >> 30} GiB device copy of `bench.py --calibrate-copy` gives "
+                 f"scale factors fetch x{fs:.3f}, write x{ws:.3f} (bytes = KiB x 1024 x factor).\n\n")
+        fh.write("| kernel | grid (threads) | dispatches | FETCH KiB/dispatch | WRITE KiB/dispatch | "
+                 "calibrated bytes/dispatch |\n|---|---|---|---|---|---|\n")
+        for r in rows[:24]:
+            fh.write(f"| `{r['kernel']}` | {r['grid']} | {r['n']} | {r['fetch']:.0f} | {r['write']:.0f} | "
+                     f"{r['bytes']:.4g} |\n")
+        fh.write("\nTraffic records (read by bench.py while the kernels' sources are unchanged): " +
+                 ", ".join(f"`traffic_{k}_{workload}_{precision}.json` {v[0]['traffic_bytes_per_launch']:.4g} B"
+                           for k, v in recs.items()) + "\n")
+    return recs
+
+
+def _main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(prog="python -m paper_1911_02366_amd.profiling")
+    sub = ap.add_subparsers(dest="what", required=True)
+    st = sub.add_parser("stats")
+    st.add_argument("directory")
+    st.add_argument("out")
+    st.add_argument("--command", required=True)
+    st.add_argument("--note", default="")
+    st.add_argument("--top", type=int, default=24)
+    tr = sub.add_parser("traffic")
+    for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--workload", "--precision"):
+        tr.add_argument(a, required=True)
+    tr.add_argument("--command", action="append", default=[])
+    a = ap.parse_args(argv)
+    if a.what == "stats":
+        write_stats_markdown(summarize_stats(a.directory, a.top), a.out, a.command, a.note)
+    else:
+        for k, (rec, _) in traffic_summary(a.fetch, a.write, a.copy_fetch, a.copy_write, a.workload, a.precision,
+                                           a.command).items():
+            print(k, f"{rec['traffic_bytes_per_launch']:.4g}")
+
+
+if __name__ == "__main__":
+    _main()

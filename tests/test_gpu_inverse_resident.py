@@ -1,5 +1,5 @@
 """The resident-panel form of the batched Gauss-Jordan inverse (one workgroup
-per element holding an outer panel of 48 FP64 / 112 FP32 columns in LDS,
+per element holding an outer panel of 48 FP64 / 64 FP32 columns in LDS,
 16-column inner panels eliminated in registers, one matrix-core pass over the
 rest of the block per outer panel) against the oracle's inverse and against
 the single-kernel form.
