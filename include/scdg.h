@@ -265,7 +265,7 @@ scdg_status scdg_phase_times(scdg_plan *p, double *ms, int32_t *count, int32_t n
  * scdg_factor; leaves the plan factored but not condensed.  ms_x / ms_s (host,
  * n entries, may be NULL) receive the time per configuration (-1 if skipped). */
 scdg_status scdg_autotune(scdg_plan *p, double *ms_x, double *ms_s, int32_t n);
-/* Select / query the tile configuration of the two GEMMs (0 .. 6). */
+/* Select / query the tile configuration of the two GEMMs (0 .. 8). */
 scdg_status scdg_set_gemm_config(scdg_plan *p, int32_t cfg_x, int32_t cfg_s);
 scdg_status scdg_get_gemm_config(const scdg_plan *p, int32_t *cfg_x, int32_t *cfg_s);
 

@@ -35,7 +35,7 @@ EXPORTED = [
     "scdg_guess_features", "scdg_guess_target", "scdg_guess_apply",
     "scdg_probe_mfma", "scdg_probe_hbm_read",
 ]
-GEMM_CONFIGS = ["64x64", "64x128", "128x128", "128x128w8", "128x64", "240x80", "80x80"]
+GEMM_CONFIGS = ["64x64", "64x128", "128x128", "128x128w8", "128x64", "240x80", "80x80", "256x128", "128x256"]
 PHASES = ["inverse", "gemm_x", "gemm_s", "rhs", "schur_apply", "condensed_solve", "backsolve",
           "residual"]
 

@@ -94,7 +94,7 @@ struct SparseOp {
 };
 
 // GEMM tile configurations (rows x columns of C per workgroup)
-enum { kGemm64x64 = 0, kGemm64x128 = 1, kGemm128x128 = 2, kGemm128x128w8 = 3, kGemmConfigs = 7 };
+enum { kGemm64x64 = 0, kGemm64x128 = 1, kGemm128x128 = 2, kGemm128x128w8 = 3, kGemmConfigs = 9 };
 
 template <typename T>
 struct DevBuf {

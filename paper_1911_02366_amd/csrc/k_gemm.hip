@@ -13,6 +13,8 @@
 // consecutive words.  The tile list orders tiles so that one problem's tiles
 // share an XCD (workgroups are dealt to the 8 XCDs round-robin), keeping an
 // element's operands in that XCD's L2.
+#include <type_traits>
+
 #include "internal.hpp"
 #include "mfma.hpp"
 
@@ -107,27 +109,38 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_batched_kernel(const GemmDe
   load(0);
   store(0);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * BK);
+  // the K loop is compiled twice: without per-block guards for a wave whose
+  // blocks all hold real rows and columns (every wave but those on the ragged
+  // edge), so the matrix-core instructions issue back to back with the LDS
+  // reads scheduled around them, and with the guards for the others
+  auto kloop = [&](auto full_c) {
+    constexpr bool FULL = decltype(full_c)::value;
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) load((kt + 1) * BK);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      T af[TM], bf[TN];
+      for (int kk = 0; kk < BK; kk += 4) {
+        T af[TM], bf[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
-        af[i] = as[buf][kk + (lane >> 4)][wm * WTM + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-        bf[j] = bs[buf][kk + (lane >> 4)][wn * WTN + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
+          af[i] = as[buf][kk + (lane >> 4)][wm * WTM + i * 16 + (lane & 15)];
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          if (i < tm_valid && j < tn_valid) acc[i][j] = M::mma(af[i], bf[j], acc[i][j]);
+          bf[j] = bs[buf][kk + (lane >> 4)][wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            if (FULL || (i < tm_valid && j < tn_valid)) acc[i][j] = M::mma(af[i], bf[j], acc[i][j]);
+      }
+      if (kt + 1 < nk) store(buf ^ 1);
+      __syncthreads();
     }
-    if (kt + 1 < nk) store(buf ^ 1);
-    __syncthreads();
-  }
+  };
+  if (tm_valid == TM && tn_valid == TN)
+    kloop(std::true_type{});
+  else
+    kloop(std::false_type{});
 
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -170,10 +183,10 @@ hipError_t launch_cfg(const GemmDesc *d_desc, const int32_t *d_tiles, int32_t n_
 // Tile configurations: C tile rows x columns and the wave grid.
 //   0: 64x64 (2x2 waves)    1: 64x128 (2x2)    2: 128x128 (2x2)
 //   3: 128x128 (2x4 waves)  4: 128x64 (2x2)    5: 240x80 (5x1; divides 1200 = n_c at N = 5)
-//   6: 80x80 (5x1 waves)
+//   6: 80x80 (5x1 waves)   7: 256x128 (4x2 waves)   8: 128x256 (2x4 waves)
 void gemm_tile_shape(int cfg, int *bm, int *bn) {
-  static const int shapes[kGemmConfigs][2] = {{64, 64}, {64, 128}, {128, 128}, {128, 128},
-                                              {128, 64}, {240, 80}, {80, 80}};
+  static const int shapes[kGemmConfigs][2] = {{64, 64}, {64, 128}, {128, 128}, {128, 128}, {128, 64},
+                                              {240, 80}, {80, 80},          {256, 128}, {128, 256}};
   if (cfg < 0 || cfg >= kGemmConfigs) cfg = 0;
   *bm = shapes[cfg][0];
   *bn = shapes[cfg][1];
@@ -190,6 +203,8 @@ hipError_t launch_gemm_batched(int cfg, const GemmDesc *d_desc, const int32_t *d
     case 4: return launch_cfg<128, 64, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
     case 5: return launch_cfg<240, 80, 5, 1>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
     case 6: return launch_cfg<80, 80, 5, 1>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
+    case 7: return launch_cfg<256, 128, 4, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
+    case 8: return launch_cfg<128, 256, 2, 4>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
     default: return launch_cfg<64, 64, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
   }
 }

@@ -111,7 +111,7 @@ def test_condensed_pipeline_by_stages(setup):
     assert rel(to_np(dq), ref) <= 1e-10, info
 
 
-@pytest.mark.parametrize("cfg", list(range(7)))
+@pytest.mark.parametrize("cfg", list(range(9)))
 def test_every_gemm_tile_config(setup, cfg):
     name, case, d, dev, plan = setup
     plan.set_gemm_config(cfg, cfg)
