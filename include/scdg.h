@@ -39,9 +39,10 @@
  *     A_bb in BSR with 5x5 row-major blocks over global boundary nodes.
  *
  * Ownership and streams: the caller owns every buffer passed in.  Blocks given
- * to scdg_assemble are BORROWED until the next scdg_assemble or
- * scdg_plan_destroy (the FP64 originals are read again by the full-system
- * residual).  The plan owns its factors, Schur blocks and workspaces.  Every
+ * to scdg_assemble are copied into plan-owned storage (SCDG_COPY) or
+ * BORROWED until the next scdg_assemble or scdg_plan_destroy (SCDG_BORROW;
+ * the FP64 originals are read again by the full-system residual).  The plan
+ * owns its factors, Schur blocks and workspaces.  Every
  * call enqueues work on the plan's HIP stream; calls that return host data
  * (scdg_solve*, scdg_residual, scdg_factor_info) synchronize that stream.
  * A plan is not thread-safe; distinct plans are independent.
@@ -118,8 +119,12 @@ typedef struct {
 
 /* Build the index maps of the partition (Section 3.2: permutation indexes from
  * the mesh connectivity), the Schur-apply maps and the work lists.  hip_stream
- * may be NULL (default stream).  The current HIP device is used. */
-scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip_stream);
+ * may be NULL (default stream) and must belong to the plan's device.  device:
+ * -1 for the current HIP device, else a device index, which is made current
+ * for the calling thread (SCDG_ERR_ARG if there is no such device).  Every
+ * later call on the plan that enqueues work must be made with that device
+ * current: SCDG_ERR_STATE otherwise. */
+scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip_stream, int32_t device);
 scdg_status scdg_plan_destroy(scdg_plan *p);
 scdg_status scdg_set_stream(scdg_plan *p, void *hip_stream);
 /* Sizes: natural DOFs, n1 = 5 n_bnodes (condensed size), n2 = sum n_i, n_bnodes. */
@@ -130,9 +135,21 @@ scdg_status scdg_plan_sizes(const scdg_plan *p, int64_t *n_dof, int64_t *n1, int
  * BSR remainder (see scdg_condense). */
 scdg_status scdg_plan_fold_counts(const scdg_plan *p, int64_t *n_folded, int64_t *n_remainder);
 
-/* Register the Jacobian blocks (device pointers, borrowed, FP64). */
+/* Register the Jacobian blocks (device pointers, FP64) of A dQ = B
+ * (eq. NewtonLinSys1) in the partition of Section 3.1.  flags:
+ *   SCDG_COPY   (0)  the plan copies the four arrays into storage it owns
+ *                    (allocated by the first copying call, freed by
+ *                    scdg_plan_destroy) on its stream; the caller may reuse
+ *                    its buffers as soon as the copy has run on that stream;
+ *   SCDG_BORROW (1)  the plan keeps the caller's pointers until the next
+ *                    scdg_assemble or scdg_plan_destroy (no copy; needed
+ *                    where the blocks are large, 27 GB in FP64 at N = 7);
+ *                    the caller must not change or free them meanwhile.
+ * SCDG_ERR_ARG for NULL pointers or other flags; SCDG_ERR_NOMEM if the copy's
+ * storage cannot be allocated. */
+enum { SCDG_COPY = 0, SCDG_BORROW = 1 };
 scdg_status scdg_assemble(scdg_plan *p, const double *aii, const double *aib,
-                          const double *abi, const double *bb_val);
+                          const double *abi, const double *bb_val, int32_t flags);
 
 /* Invert every A_ii(e) by Gauss-Jordan elimination with partial pivoting
  * (the paper inverts each interior block with LU routines, Section 3.2), in

@@ -16,6 +16,7 @@ STATUS = {0: "SCDG_OK", -1: "SCDG_ERR_ARG", -2: "SCDG_ERR_STATE", -3: "SCDG_ERR_
           -4: "SCDG_ERR_NOMEM", -5: "SCDG_ERR_SINGULAR", -6: "SCDG_ERR_NOCONV",
           -7: "SCDG_ERR_NONFINITE", -8: "SCDG_ERR_UNSUPPORTED"}
 SCDG_FP64, SCDG_FP32 = 0, 1
+SCDG_COPY, SCDG_BORROW = 0, 1          # scdg_assemble flags
 SOLVER_AUTO, SOLVER_DENSE, SOLVER_GMRES = 0, 1, 2
 EXPORT_AII_INV, EXPORT_SCHUR, EXPORT_X = 1, 2, 3
 
@@ -107,11 +108,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib = C.CDLL(path)
     vp, i32, i64, d, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
     sig = {
-        "scdg_plan_create": (i32, [C.POINTER(vp), C.POINTER(Structure), vp]),
+        "scdg_plan_create": (i32, [C.POINTER(vp), C.POINTER(Structure), vp, i32]),
         "scdg_plan_destroy": (i32, [vp]),
         "scdg_set_stream": (i32, [vp, vp]),
         "scdg_plan_sizes": (i32, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
-        "scdg_assemble": (i32, [vp, vp, vp, vp, vp]),
+        "scdg_assemble": (i32, [vp, vp, vp, vp, vp, i32]),
         "scdg_factor": (i32, [vp, i32]),
         "scdg_factor_info": (i32, [vp, C.POINTER(i64), C.POINTER(i32)]),
         "scdg_condense": (i32, [vp]),

@@ -176,8 +176,9 @@ struct Plan {
   RowTile *d_rt_inv = nullptr, *d_rt_abi = nullptr, *d_rt_aib = nullptr, *d_rt_s = nullptr;
   int32_t n_rt_inv = 0, n_rt_abi = 0, n_rt_aib = 0, n_rt_s = 0;
 
-  // borrowed FP64 blocks
+  // FP64 blocks: the caller's (SCDG_BORROW) or the plan's copies (SCDG_COPY)
   const double *aii = nullptr, *aib = nullptr, *abi = nullptr, *bb_val = nullptr;
+  double *own_aii = nullptr, *own_aib = nullptr, *own_abi = nullptr, *own_bb = nullptr;
 
   // factors and Schur blocks (precision = prec)
   void *ainv = nullptr;   // sum n_i^2

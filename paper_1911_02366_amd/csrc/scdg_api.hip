@@ -53,6 +53,16 @@ scdg_status dalloc(Plan &p, T **ptr, size_t count) {
   return SCDG_OK;
 }
 
+// work may be enqueued only with the plan's device current
+scdg_status on_device(Plan &p) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != p.device) {
+    p.last_error = "call with the plan's HIP device (" + std::to_string(p.device) + ") current";
+    return SCDG_ERR_STATE;
+  }
+  return SCDG_OK;
+}
+
 template <typename T>
 scdg_status upload(Plan &p, T **ptr, const std::vector<T> &host) {
   ST_TRY(dalloc(p, ptr, host.size()));
@@ -848,6 +858,7 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk); dfree(p.rem_val);
   dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_inv_order); dfree(p.d_info);
   dfree(p.d_jac_cnode);
+  dfree(p.own_aii); dfree(p.own_aib); dfree(p.own_abi); dfree(p.own_bb);
   dfree(p.d_gx); dfree(p.d_gs); dfree(p.d_tiles_x); dfree(p.d_tiles_s);
   dfree(p.d_gv_inv); dfree(p.d_gv_abi); dfree(p.d_gv_aib); dfree(p.d_gv_s);
   dfree(p.d_rt_inv); dfree(p.d_rt_abi); dfree(p.d_rt_aib); dfree(p.d_rt_s);
@@ -872,12 +883,26 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   return SCDG_OK;
 }
 
-scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip_stream) {
+scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip_stream, int32_t device) {
   if (!out || !s || !s->order || !s->c_ptr || !s->c_node || !s->bb_rowptr || s->n_elem <= 0) {
     g_create_error = "null pointer or empty mesh in scdg_structure";
     return SCDG_ERR_ARG;
   }
   *out = nullptr;
+  if (device >= 0) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+      g_create_error = "no HIP device " + std::to_string(device);
+      return SCDG_ERR_ARG;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+      g_create_error = "hipSetDevice failed";
+      return SCDG_ERR_HIP;
+    }
+  } else if (device != -1) {
+    g_create_error = "device must be -1 or a device index";
+    return SCDG_ERR_ARG;
+  }
   scdg_plan *pl = new (std::nothrow) scdg_plan();
   if (!pl) return SCDG_ERR_NOMEM;
   Plan &p = pl->p;
@@ -1197,9 +1222,28 @@ scdg_status scdg_plan_fold_counts(const scdg_plan *pl, int64_t *n_folded, int64_
 }
 
 scdg_status scdg_assemble(scdg_plan *pl, const double *aii, const double *aib, const double *abi,
-                          const double *bb_val) {
-  if (!pl || !aii || !aib || !abi || (pl->p.nnzb > 0 && !bb_val)) return SCDG_ERR_ARG;
+                          const double *bb_val, int32_t flags) {
+  if (!pl || !aii || !aib || !abi || (pl->p.nnzb > 0 && !bb_val) || (flags != SCDG_COPY && flags != SCDG_BORROW))
+    return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
+  if (flags == SCDG_COPY) {
+    const size_t n_ii = (size_t)p.off_ii[p.n_elem], n_ib = (size_t)p.off_ib[p.n_elem], n_bb = 25 * (size_t)p.nnzb;
+    if (!p.own_aii) {
+      ST_TRY(dalloc(p, &p.own_aii, std::max<size_t>(1, n_ii)));
+      ST_TRY(dalloc(p, &p.own_aib, std::max<size_t>(1, n_ib)));
+      ST_TRY(dalloc(p, &p.own_abi, std::max<size_t>(1, n_ib)));
+      ST_TRY(dalloc(p, &p.own_bb, std::max<size_t>(1, n_bb)));
+    }
+    HIP_TRY(hipMemcpyAsync(p.own_aii, aii, sizeof(double) * n_ii, hipMemcpyDeviceToDevice, p.stream));
+    HIP_TRY(hipMemcpyAsync(p.own_aib, aib, sizeof(double) * n_ib, hipMemcpyDeviceToDevice, p.stream));
+    HIP_TRY(hipMemcpyAsync(p.own_abi, abi, sizeof(double) * n_ib, hipMemcpyDeviceToDevice, p.stream));
+    if (n_bb) HIP_TRY(hipMemcpyAsync(p.own_bb, bb_val, sizeof(double) * n_bb, hipMemcpyDeviceToDevice, p.stream));
+    aii = p.own_aii;
+    aib = p.own_aib;
+    abi = p.own_abi;
+    bb_val = p.own_bb;
+  }
   p.aii = aii;
   p.aib = aib;
   p.abi = abi;
@@ -1283,6 +1327,7 @@ scdg_status prepare_blocked_inverse(Plan &p) {
 scdg_status scdg_factor(scdg_plan *pl, scdg_precision prec) {
   if (!pl) return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
   if (p.state < 1) {
     p.last_error = "scdg_factor before scdg_assemble";
     return SCDG_ERR_STATE;
@@ -1383,6 +1428,7 @@ scdg_status scdg_factor_info(scdg_plan *pl, int64_t *first_bad_elem, int32_t *in
 scdg_status scdg_condense(scdg_plan *pl) {
   if (!pl) return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
   if (p.state < 2) {
     p.last_error = "scdg_condense before scdg_factor";
     return SCDG_ERR_STATE;
@@ -1467,6 +1513,7 @@ scdg_status scdg_condense(scdg_plan *pl) {
 scdg_status scdg_condense_rhs(scdg_plan *pl, const double *b, double *bs) {
   if (!pl || !b || !bs) return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
   if (p.state < 3) return SCDG_ERR_STATE;
   return condense_rhs_impl(p, b, bs);
 }
@@ -1482,6 +1529,7 @@ scdg_status scdg_solve_condensed(scdg_plan *pl, const double *bs, double *qb, co
                                  const scdg_solve_opts *o, scdg_solve_info *info) {
   if (!pl || !bs || !qb) return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
   if (p.state < 3) return SCDG_ERR_STATE;
   scdg_solve_opts opts{};
   if (o) opts = *o;
@@ -1500,6 +1548,7 @@ scdg_status scdg_solve_condensed(scdg_plan *pl, const double *bs, double *qb, co
 scdg_status scdg_backsolve(scdg_plan *pl, const double *b, const double *qb, double *dq) {
   if (!pl || !b || !qb || !dq) return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
   if (p.state < 3) return SCDG_ERR_STATE;
   return backsolve_impl(p, b, qb, dq);
 }
@@ -1548,6 +1597,7 @@ scdg_status scdg_residual(scdg_plan *pl, const double *b, const double *dq, doub
                           double *rel2) {
   if (!pl || !b || !dq) return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
   if (p.state < 1) return SCDG_ERR_STATE;
   double *rr = r ? r : p.w_r;
   ST_TRY(residual_impl(p, b, dq, rr));
@@ -1564,6 +1614,7 @@ scdg_status scdg_solve(scdg_plan *pl, const double *b, double *dq, const double 
                        const scdg_solve_opts *o, scdg_solve_info *info) {
   if (!pl || !b || !dq) return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
   if (p.state < 3) return SCDG_ERR_STATE;
   scdg_solve_opts opts{};
   if (o) opts = *o;
@@ -1635,6 +1686,7 @@ scdg_status scdg_newton_step(scdg_plan *pl, scdg_dg *dg, const double *q_s, doub
                              const scdg_newton_opts *o, scdg_newton_info *info) {
   if (!pl || !dg || !q_s || !q || q == q_s) return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
   if (p.state < 3) {
     p.last_error = "scdg_newton_step before scdg_condense";
     return SCDG_ERR_STATE;

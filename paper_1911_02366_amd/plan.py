@@ -35,7 +35,7 @@ def _stream(stream) -> int:
 class Plan:
     """Owns one scdg_plan.  Call order: assemble -> factor -> condense -> solve*."""
 
-    def __init__(self, order, c_ptr, c_node, bb_rowptr, bb_col, stream=None, phys_faces=None):
+    def __init__(self, order, c_ptr, c_node, bb_rowptr, bb_col, stream=None, phys_faces=None, device: int = -1):
         self.lib = L.load()
         self._host = dict(
             order=np.ascontiguousarray(order, dtype=np.int32),
@@ -54,7 +54,7 @@ class Plan:
                         h["bb_col"].ctypes.data if len(h["bb_col"]) else None,
                         h["phys_faces"].ctypes.data if phys_faces is not None else None)
         handle = C.c_void_p()
-        st = self.lib.scdg_plan_create(C.byref(handle), C.byref(s), _stream(stream))
+        st = self.lib.scdg_plan_create(C.byref(handle), C.byref(s), _stream(stream), int(device))
         if st != L.SCDG_OK:
             raise L.ScdgError(st, "scdg_plan_create", L.last_error(None))
         self.handle = handle
@@ -67,9 +67,9 @@ class Plan:
         self.n_folded, self.n_remainder = nf.value, nr.value
 
     @classmethod
-    def from_structure(cls, st: dict, stream=None) -> "Plan":
+    def from_structure(cls, st: dict, stream=None, device: int = -1) -> "Plan":
         return cls(st["order"], st["c_ptr"], st["c_node"], st["bb_rowptr"], st["bb_col"], stream,
-                   st.get("phys_faces"))
+                   st.get("phys_faces"), device)
 
     def _check(self, st: int, where: str):
         if st != L.SCDG_OK:
@@ -89,12 +89,15 @@ class Plan:
     def set_stream(self, stream=None):
         self._check(self.lib.scdg_set_stream(self.handle, _stream(stream)), "scdg_set_stream")
 
-    def assemble(self, aii, aib, abi, bb_val):
+    def assemble(self, aii, aib, abi, bb_val, copy: bool = False):
+        """Register the blocks: borrowed (kept referenced here until the next
+        assemble) or, with copy=True, copied into plan-owned storage."""
         for t in (aii, aib, abi, bb_val):
             if t.dtype != torch.float64:
                 raise TypeError("blocks must be float64")
-        self._keep = (aii, aib, abi, bb_val)       # borrowed by the library
-        self._check(self.lib.scdg_assemble(self.handle, _ptr(aii), _ptr(aib), _ptr(abi), _ptr(bb_val)),
+        self._keep = () if copy else (aii, aib, abi, bb_val)
+        flags = L.SCDG_COPY if copy else L.SCDG_BORROW
+        self._check(self.lib.scdg_assemble(self.handle, _ptr(aii), _ptr(aib), _ptr(abi), _ptr(bb_val), flags),
                     "scdg_assemble")
 
     def factor(self, precision: str = "fp64"):

@@ -55,4 +55,4 @@ def test_create_rejects_bad_structure_without_gpu(lib_path):
     from paper_1911_02366_amd import _lib
     lib = _lib.load(lib_path)
     handle = ctypes.c_void_p()
-    assert lib.scdg_plan_create(ctypes.byref(handle), None, None) == -1
+    assert lib.scdg_plan_create(ctypes.byref(handle), None, None, -1) == -1
