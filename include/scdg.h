@@ -249,6 +249,14 @@ scdg_status scdg_residual(scdg_plan *p, const double *b, const double *dq, doubl
 
 /* y = S x with the condensed operator as stored (boundary vectors, device). */
 scdg_status scdg_schur_apply(scdg_plan *p, const double *x, double *y);
+/* y = S^T x with the condensed operator as stored (eq. SC_step1: S^T =
+ * A_bb^T - sum_e A_ib(e)^T A_ii(e)^-T A_bi(e)^T): the transposed element Schur
+ * blocks and the transposed A_bb remainder, gathered and pulled exactly as
+ * scdg_schur_apply does (for residual-weighted objectives, e.g. the gradient
+ * S^T S e of ||S e||^2).  Boundary vectors of n1 doubles on the device; x and
+ * y must differ.  Needs a condensed plan in the assembled form (schur mode
+ * 0): SCDG_ERR_STATE otherwise.  Asynchronous on the plan's stream. */
+scdg_status scdg_schur_apply_transpose(scdg_plan *p, const double *x, double *y);
 
 /* Copy internal arrays to caller device memory (for inspection and tests):
  * SCDG_EXPORT_AII_INV: sum n_i^2 values of A_ii(e)^-1; SCDG_EXPORT_SCHUR:

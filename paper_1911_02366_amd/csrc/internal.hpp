@@ -155,6 +155,12 @@ struct Plan {
   int64_t *d_rem_rowptr = nullptr;  // [n_bnodes+1]
   int32_t *d_rem_col = nullptr;     // [n_rem]
   int32_t *d_rem_src = nullptr;     // [n_rem] block index into bb_val
+  // the remainder transposed (rows = its columns), for S^T x: source index into rem_val
+  int64_t *d_remt_rowptr = nullptr; // [n_bnodes+1]
+  int32_t *d_remt_col = nullptr;    // [n_rem]
+  int32_t *d_remt_src = nullptr;    // [n_rem] remainder-order index of the block (read transposed)
+  RowTile *d_ct_s = nullptr;        // 256-column tiles of the element Schur blocks (S^T x)
+  int32_t n_ct_s = 0;
   int32_t *d_inv_n = nullptr;     // [n_elem] n_i per element
   int64_t *d_inv_off = nullptr;   // [n_elem] offset of A_ii(e)
   int32_t *d_inv_order = nullptr; // [n_elem] elements by decreasing n_i (stable)
@@ -280,6 +286,7 @@ hipError_t launch_gemv_batched(const GemvDesc *d_desc, const RowTile *d_tiles, i
 // out[j] = c0 * src0[map0 ? map0[j] : j] + c1 * (B x)[j] + c2 * sum_{s in pull(j/5)} t[5 s + j%5]
 // with B = A_bb (full = true) or the remainder of A_bb not folded into T_e.
 // Assembled Schur product, first launch: t = T_e x[C_e] per slot and rx = R x.
+hipError_t launch_schur_apply_t(const Plan &p, const double *x, double *z, double *y, bool lo);
 hipError_t launch_schur_gemv_rem(const Plan &p, const double *x, double *t, double *rx, bool lo);
 hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *src0,
                            const int32_t *map0, double c1, const double *x, double c2,

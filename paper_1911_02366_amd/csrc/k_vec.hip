@@ -5,6 +5,8 @@
 // Krylov vector operations (deterministic two-stage multi-dot for Gram-Schmidt,
 // multi-AXPY, scaling).  All vectors are FP64; element matrices may be FP64 or
 // FP32 (accumulation is always FP64).
+#include <algorithm>
+
 #include "internal.hpp"
 #include "mfma.hpp"
 
@@ -136,8 +138,8 @@ __global__ __launch_bounds__(kThreads) void gemv_batched_kernel(
 // ..., l+55 hold row l % 5): no LDS and no workgroup barrier.  The block
 // values are FP64, or an FP32 copy inside the products of the FP32 forms
 // (accumulation in FP64 either way).
-template <typename TV>
-__global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
+template <typename TV, bool TRANS>
+__global__ __launch_bounds__(kThreads) void bsr_pull_kernel_impl(
     int64_t n_bnodes, double c0, const double *__restrict__ src0, const int32_t *__restrict__ map0,
     double c1, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
     const int32_t *__restrict__ src_idx, const TV *__restrict__ val,
@@ -157,6 +159,9 @@ __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
   }
   double s = 0.0;
   const int v = lane % 5, bq = lane / 5;
+  // row v of a stored block, or of its transpose (column v)
+  constexpr int SW = TRANS ? 5 : 1;
+  const int ro = TRANS ? v : v * 5;
   if (c1 != 0.0 && lane < 60) {
     const int64_t b0 = rowptr[g], b1 = rowptr[g + 1];
     double s2 = 0.0;
@@ -164,13 +169,13 @@ __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
     for (; blk + 12 < b1; blk += 24) {
       const int64_t va = src_idx ? (int64_t)src_idx[blk] : blk;
       const int64_t vb = src_idx ? (int64_t)src_idx[blk + 12] : blk + 12;
-      const TV *ra = val + va * 25 + v * 5, *rb = val + vb * 25 + v * 5;
+      const TV *ra = val + va * 25 + ro, *rb = val + vb * 25 + ro;
       const double *xa = x + (int64_t)col[blk] * 5, *xb = x + (int64_t)col[blk + 12] * 5;
       double ma[5], mb[5], ya[5], yb[5];
 #pragma unroll
       for (int w = 0; w < 5; ++w) {
-        ma[w] = (double)ra[w];
-        mb[w] = (double)rb[w];
+        ma[w] = (double)ra[w * SW];
+        mb[w] = (double)rb[w * SW];
         ya[w] = xa[w];
         yb[w] = xb[w];
       }
@@ -182,10 +187,10 @@ __global__ __launch_bounds__(kThreads) void bsr_pull_kernel(
     }
     if (blk < b1) {
       const int64_t va = src_idx ? (int64_t)src_idx[blk] : blk;
-      const TV *ra = val + va * 25 + v * 5;
+      const TV *ra = val + va * 25 + ro;
       const double *xa = x + (int64_t)col[blk] * 5;
 #pragma unroll
-      for (int w = 0; w < 5; ++w) s += (double)ra[w] * xa[w];
+      for (int w = 0; w < 5; ++w) s += (double)ra[w * SW] * xa[w];
     }
     s += s2;
   }
@@ -749,6 +754,61 @@ hipError_t launch_gemv_batched(const GemvDesc *d_desc, const RowTile *d_tiles, i
   return hipGetLastError();
 }
 
+// z_e = T_e^T x[C_e] for every element (the transposed Schur product's
+// element part): one workgroup per (element, 256 columns of T_e); each thread
+// owns a column and walks the rows, so the workgroup reads every row segment
+// contiguously; four rows in flight per thread, FP64 accumulation.
+template <typename TM>
+__global__ __launch_bounds__(256) void gemv_t_kernel(const GemvDesc *__restrict__ desc,
+                                                     const RowTile *__restrict__ tiles, const TM *__restrict__ mat,
+                                                     const double *__restrict__ x, const int32_t *__restrict__ xmap,
+                                                     double *__restrict__ z) {
+  extern __shared__ double xs[];
+  const RowTile t = tiles[blockIdx.x];
+  const GemvDesc d = desc[t.prob];
+  for (int r = threadIdx.x; r < d.rows; r += blockDim.x) xs[r] = x[xmap[d.x_off + r]];
+  __syncthreads();
+  const int j = t.row0 + threadIdx.x;
+  if (j >= d.cols) return;
+  const TM *__restrict__ col = mat + d.m_off + j;
+  const int64_t ld = d.cols;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int r = 0;
+  for (; r + 4 <= d.rows; r += 4) {
+    a0 += (double)col[r * ld] * xs[r];
+    a1 += (double)col[(r + 1) * ld] * xs[r + 1];
+    a2 += (double)col[(r + 2) * ld] * xs[r + 2];
+    a3 += (double)col[(r + 3) * ld] * xs[r + 3];
+  }
+  for (; r < d.rows; ++r) a0 += (double)col[r * ld] * xs[r];
+  z[d.y_off + j] = (a0 + a1) + (a2 + a3);
+}
+
+// y = S^T x (assembled form): z = T_e^T x[C_e] per element, then
+// y = R^T x + pull(z), R^T from the transposed remainder pattern
+hipError_t launch_schur_apply_t(const Plan &p, const double *x, double *z, double *y, bool lo) {
+  const size_t lds = sizeof(double) * (size_t)std::max(1, p.max_nc);
+  if (lo)
+    hipLaunchKernelGGL(gemv_t_kernel<float>, dim3(p.n_ct_s), dim3(256), lds, p.stream, p.d_gv_s, p.d_ct_s,
+                       static_cast<const float *>(p.sloc), x, p.d_cmap, z);
+  else
+    hipLaunchKernelGGL(gemv_t_kernel<double>, dim3(p.n_ct_s), dim3(256), lds, p.stream, p.d_gv_s, p.d_ct_s,
+                       static_cast<const double *>(p.sloc), x, p.d_cmap, z);
+  const int64_t nb = p.n_bnodes;
+  const int grid = (int)((nb + (kThreads / 64) - 1) / (kThreads / 64));
+  if (lo) {
+    if (p.n_rem > 0 && !p.rem_lo) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((bsr_pull_kernel_impl<float, true>), dim3(grid), dim3(kThreads), 0, p.stream, nb, 0.0,
+                       nullptr, nullptr, 1.0, p.d_remt_rowptr, p.d_remt_col, p.d_remt_src, p.rem_lo, x, 1.0,
+                       p.d_pull_ptr, p.d_pull_idx, z, y, nullptr);
+  } else {
+    hipLaunchKernelGGL((bsr_pull_kernel_impl<double, true>), dim3(grid), dim3(kThreads), 0, p.stream, nb, 0.0,
+                       nullptr, nullptr, 1.0, p.d_remt_rowptr, p.d_remt_col, p.d_remt_src, p.rem_val, x, 1.0,
+                       p.d_pull_ptr, p.d_pull_idx, z, y, nullptr);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *src0,
                            const int32_t *map0, double c1, const double *x, double c2,
                            const double *t, double *out, bool lo) {
@@ -759,10 +819,10 @@ hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *sr
   if (lo) {
     const float *v = full ? p.bb_lo : p.rem_lo;
     if (c1 != 0.0 && !v && (full ? p.nnzb : p.n_rem) > 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(bsr_pull_kernel<float>, dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0, c1,
+    hipLaunchKernelGGL((bsr_pull_kernel_impl<float, false>), dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0, c1,
                        rp, cl, nullptr, v, x, c2, p.d_pull_ptr, p.d_pull_idx, t, out, p.halt);
   } else {
-    hipLaunchKernelGGL(bsr_pull_kernel<double>, dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0, c1,
+    hipLaunchKernelGGL((bsr_pull_kernel_impl<double, false>), dim3(grid), dim3(kThreads), 0, p.stream, nb, c0, src0, map0, c1,
                        rp, cl, nullptr, full ? p.bb_val : p.rem_val, x, c2, p.d_pull_ptr, p.d_pull_idx, t, out,
                        p.halt);
   }

@@ -856,6 +856,7 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   dfree(p.d_mask); dfree(p.d_e_offib); dfree(p.d_e_maskoff); dfree(p.d_e_ri); dfree(p.d_e_rc); dfree(p.w_z2);
   dfree(p.d_fold_dst); dfree(p.d_fold_nc); dfree(p.d_fold_src);
   dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk); dfree(p.rem_val);
+  dfree(p.d_remt_rowptr); dfree(p.d_remt_col); dfree(p.d_remt_src); dfree(p.d_ct_s);
   dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_inv_order); dfree(p.d_info);
   dfree(p.d_jac_cnode);
   dfree(p.own_aii); dfree(p.own_aib); dfree(p.own_abi); dfree(p.own_bb);
@@ -1129,6 +1130,28 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   chk(upload(p, &p.d_rem_rowptr, rem_rowptr));
   chk(upload(p, &p.d_rem_col, rem_col));
   chk(upload(p, &p.d_rem_src, rem_src));
+  {
+    // transposed remainder: entry k = (row g, column h) becomes (row h, column g)
+    std::vector<int64_t> rt_ptr(p.n_bnodes + 1, 0);
+    for (int32_t h : rem_col) ++rt_ptr[h + 1];
+    for (int64_t g = 0; g < p.n_bnodes; ++g) rt_ptr[g + 1] += rt_ptr[g];
+    std::vector<int32_t> rt_col(rem_col.size()), rt_src(rem_col.size());
+    std::vector<int64_t> fill(rt_ptr.begin(), rt_ptr.end() - 1);
+    for (int64_t g = 0; g < p.n_bnodes; ++g)
+      for (int64_t k = rem_rowptr[g]; k < rem_rowptr[g + 1]; ++k) {
+        const int64_t at = fill[rem_col[k]]++;
+        rt_col[at] = (int32_t)g;
+        rt_src[at] = (int32_t)k;
+      }
+    chk(upload(p, &p.d_remt_rowptr, rt_ptr));
+    chk(upload(p, &p.d_remt_col, rt_col));
+    chk(upload(p, &p.d_remt_src, rt_src));
+    std::vector<RowTile> ct;
+    for (int e = 0; e < E; ++e)
+      for (int j0 = 0; j0 < p.nc[e]; j0 += 256) ct.push_back(RowTile{e, j0});
+    p.n_ct_s = (int32_t)ct.size();
+    chk(upload(p, &p.d_ct_s, ct));
+  }
   chk(dalloc(p, &p.pc_blk, (size_t)p.n_bnodes * 25));
   chk(upload(p, &p.d_bb_col, bb_col));
   chk(upload(p, &p.d_inv_n, inv_n));
@@ -1523,6 +1546,18 @@ scdg_status scdg_schur_apply(scdg_plan *pl, const double *x, double *y) {
   Plan &p = pl->p;
   if (p.state < 3) return SCDG_ERR_STATE;
   return schur_apply_impl(p, x, y);
+}
+
+scdg_status scdg_schur_apply_transpose(scdg_plan *pl, const double *x, double *y) {
+  if (!pl || !x || !y || x == y) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  ST_TRY(on_device(p));
+  if (p.state < 3 || p.schur_mode != 0) {
+    p.last_error = "scdg_schur_apply_transpose: needs the condensed plan in the assembled form (mode 0)";
+    return SCDG_ERR_STATE;
+  }
+  HIP_TRY(launch_schur_apply_t(p, x, p.w_t, y, fp32(p)));
+  return SCDG_OK;
 }
 
 scdg_status scdg_solve_condensed(scdg_plan *pl, const double *bs, double *qb, const double *x0,

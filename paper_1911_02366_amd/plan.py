@@ -166,6 +166,14 @@ class Plan:
         self._check(self.lib.scdg_schur_apply(self.handle, _ptr(x), _ptr(y)), "scdg_schur_apply")
         return y
 
+    def schur_apply_transpose(self, x, y=None):
+        """y = S^T x (scdg_schur_apply_transpose; assembled form)."""
+        if y is None:
+            y = torch.empty_like(x)
+        self._check(self.lib.scdg_schur_apply_transpose(self.handle, _ptr(x), _ptr(y)),
+                    "scdg_schur_apply_transpose")
+        return y
+
     def newton_step(self, dg, q_s, inv_dt: float, q, check=True, **opts):
         """Newton iterations of one backward-Euler step (scdg_newton_step): each
         iteration is one replay of a captured graph.  q holds the starting state on
