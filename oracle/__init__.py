@@ -18,7 +18,8 @@ What it computes (each function cites the passage it follows):
     of the backward-Euler GL-DGSEM step, with H from the weak form of
     eq. DGSEMsystem evaluated as Gauss-Lobatto quadrature sums;
   * (module `oracle.mlp`) the learned-initial-guess network in FP64: forward,
-    chain-rule backward, Adam, mean-squared loss and the feature maps;
+    chain-rule backward, Adam, mean-squared loss, the feature maps and the
+    condensed-residual loss of a predicted increment;
   * (module `oracle.sparsity1d`) the Jacobian of the 1D scalar DGSEM on
     Gauss and Gauss-Lobatto nodes, for the sparsity claims of Section 3.1.
 """

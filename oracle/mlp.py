@@ -163,3 +163,29 @@ def apply(dq_prev, y, stats, n_elem: int):
     rms = stats[3]
     dv = np.asarray(dq_prev, dtype=np.float64).reshape(n_elem, -1, 5)
     return (dv + rms * np.asarray(y, dtype=np.float64).reshape(n_elem, -1, 5)).reshape(-1)
+
+
+# --------------------------------------------------------------------------
+# condensed-residual loss of a predicted increment
+# --------------------------------------------------------------------------
+
+def condensed_loss(s: np.ndarray, bnode_dofs: np.ndarray, y, t, rc):
+    """||S P_b (rc (y - t))||^2 and its gradient with respect to y.
+
+    A guess x0 for the condensed system S Q_b = b_S (eq. SC_step1) starts GMRES
+    at the residual b_S - S x0_b = S (Q_b - x0_b): the error of the guess's
+    boundary part weighted by S.  y and t are the network's normalised output
+    and target as natural vectors (variable fastest), rc the five scales that
+    map them back (target: (dQ - dQprev) / rc), s the dense condensed matrix in
+    the boundary-vector order and bnode_dofs[node, v] (dof_maps) the natural
+    index of each boundary slot.  The gradient is the chain rule written out:
+    2 rc P_b^T S^T S e, zero on interior DOFs."""
+    y = np.asarray(y, dtype=np.float64).reshape(-1)
+    t = np.asarray(t, dtype=np.float64).reshape(-1)
+    w = np.tile(np.asarray(rc, dtype=np.float64), y.size // 5)
+    idx = np.asarray(bnode_dofs, dtype=np.int64).reshape(-1)
+    e = (w * (y - t))[idx]
+    r = np.asarray(s, dtype=np.float64) @ e
+    g = np.zeros_like(y)
+    g[idx] = 2.0 * (np.asarray(s, dtype=np.float64).T @ r)
+    return float(r @ r), w * g

@@ -217,3 +217,80 @@ def test_bf16_planted_truncation_is_caught(monkeypatch):
     monkeypatch.setattr(om, "bf16_round", truncate)
     with pytest.raises(AssertionError):
         test_bf16_round_hand_values()
+
+
+# ---- condensed-residual loss (om.condensed_loss) ----
+
+def _loss_case(seed=5, orders=(2, 3)):
+    import oracle
+    _, bnode = oracle.dof_maps(np.array(orders))
+    n_dof = sum(5 * (p + 1) ** 3 for p in orders)
+    n1 = bnode.size
+    rng = np.random.default_rng(seed)
+    s = rng.standard_normal((n1, n1)) + 3.0 * np.eye(n1)     # not symmetric
+    y, t = rng.standard_normal(n_dof), rng.standard_normal(n_dof)
+    rc = rng.uniform(0.2, 3.0, 5)
+    return s, bnode, y, t, rc
+
+
+def test_condensed_loss_with_identity_is_the_weighted_boundary_sum():
+    s, bnode, y, t, rc = _loss_case()
+    loss, g = om.condensed_loss(np.eye(s.shape[0]), bnode, y, t, rc)
+    # plain loops over boundary slots
+    want, gw = 0.0, np.zeros_like(y)
+    for node in range(bnode.shape[0]):
+        for v in range(5):
+            i = int(bnode[node, v])
+            assert i % 5 == v
+            d = rc[v] * (y[i] - t[i])
+            want += d * d
+            gw[i] = 2.0 * rc[v] * d
+    assert loss == pytest.approx(want, rel=1e-13)
+    np.testing.assert_allclose(g, gw, rtol=1e-13, atol=0)
+
+
+def test_condensed_loss_zero_error_and_interior_blindness():
+    s, bnode, y, t, rc = _loss_case()
+    loss, g = om.condensed_loss(s, bnode, t, t, rc)
+    assert loss == 0.0 and not g.any()
+    interior = np.setdiff1d(np.arange(y.size), bnode.reshape(-1))
+    assert interior.size > 0
+    y2 = y.copy()
+    y2[interior] += 7.0
+    l1, g1 = om.condensed_loss(s, bnode, y, t, rc)
+    l2, _ = om.condensed_loss(s, bnode, y2, t, rc)
+    assert l1 == l2 and not g1[interior].any()
+
+
+def test_condensed_loss_gradient_matches_central_differences():
+    s, bnode, y, t, rc = _loss_case()
+    loss, g = om.condensed_loss(s, bnode, y, t, rc)
+    rng = np.random.default_rng(9)
+    picks = np.concatenate([bnode.reshape(-1)[rng.choice(bnode.size, 12, replace=False)], [0, 13]])
+    h = 1e-6
+    for i in picks:
+        yp, ym = y.copy(), y.copy()
+        yp[i] += h
+        ym[i] -= h
+        fd = (om.condensed_loss(s, bnode, yp, t, rc)[0] - om.condensed_loss(s, bnode, ym, t, rc)[0]) / (2 * h)
+        assert fd == pytest.approx(g[i], rel=1e-6, abs=1e-6 * loss)
+
+
+def test_condensed_loss_planted_transpose_is_caught():
+    # a gradient built with S S^T in place of S^T S misses the central differences
+    s, bnode, y, t, rc = _loss_case()
+    idx = bnode.reshape(-1)
+    w = np.tile(rc, y.size // 5)
+    e = (w * (y - t))[idx]
+    wrong = np.zeros_like(y)
+    wrong[idx] = 2.0 * (s @ (s.T @ e))
+    wrong *= w
+    _, g = om.condensed_loss(s, bnode, y, t, rc)
+    i = int(idx[3])
+    h = 1e-6
+    yp, ym = y.copy(), y.copy()
+    yp[i] += h
+    ym[i] -= h
+    fd = (om.condensed_loss(s, bnode, yp, t, rc)[0] - om.condensed_loss(s, bnode, ym, t, rc)[0]) / (2 * h)
+    assert fd == pytest.approx(g[i], rel=1e-6)
+    assert abs(wrong[i] - fd) > 1e-3 * abs(fd)
