@@ -326,9 +326,22 @@ def learned_guess_experiment(args) -> dict:
     torch.cuda.synchronize()
     t_train_r = time.perf_counter() - t0
     log(f"residual-input network: loss {history_r[0]:.3e} -> {history_r[-1]:.3e}, hold-out {hold_r:.3e}")
+    # the same network trained on the condensed residual its guess leaves (S of the
+    # last training step weighting every stored step), on the same samples
+    lgs = LearnedGuess(n_elem, dpe, capacity=args.lg_train, seed=args.lg_seed, batch=args.lg_batch)
+    lgs.copy_samples(lg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    history_s, hold_s = lgs.train_condensed(st.plan, epochs=args.lg_condensed_epochs, lr=args.lg_lr)
+    torch.cuda.synchronize()
+    t_train_s = time.perf_counter() - t0
+    last = lg.count // n_elem - 1
+    hold_s_mse = lg.condensed_loss_on(st.plan, last)
+    log(f"condensed-loss network: loss {history_s[0]:.3e} -> {history_s[-1]:.3e}, hold-out {hold_s:.3e} "
+        f"(alpha {lgs.alpha:.3f}); mean-squared network on that measure {hold_s_mse:.3e}")
     log(f"trained {args.lg_epochs} epochs in {t_train:.1f} s: loss {history[0]:.3e} -> {history[-1]:.3e}, "
         f"hold-out {hold:.3e} (previous increment: {hold_zero:.3e})")
-    variants = [("zero", "gmres"), ("previous", "gmres"), ("learned", "gmres"),
+    variants = [("zero", "gmres"), ("previous", "gmres"), ("learned", "gmres"), ("learned_s", "gmres"),
                 ("previous_newton_start", "newton"), ("learned_newton_start", "newton"),
                 ("learned_bf16_newton_start", "newton"), ("learned_r_newton_start", "newton"),
                 ("fp32_ir_zero", "gmres"), ("fp32_ir_previous_newton_start", "newton"),
@@ -338,7 +351,7 @@ def learned_guess_experiment(args) -> dict:
     names = [v for v, _ in variants]
     rec = {k: {"first": [], "total": [], "newton": [], "seconds": [], "guess_res": [], "rejected": []}
            for k in names}
-    infer_ms, infer16_ms, infer_r_ms = [], [], []
+    infer_ms, infer16_ms, infer_r_ms, infer_s_ms = [], [], [], []
     prep = {"fp64": [], "fp32": []}
     for step in range(args.lg_train + 1, args.lg_steps + 1):
         prep["fp64"].append(st.prepare(q))
@@ -356,11 +369,16 @@ def learned_guess_experiment(args) -> dict:
         pred_r = lgr.predict(q, dq_prev, rc_prev, st.dg.residual(q, q, inv_dt))
         torch.cuda.synchronize()
         infer_r_ms.append((time.perf_counter() - t1) * 1e3)
+        t1 = time.perf_counter()
+        pred_s = lgs.predict(q, dq_prev, rc_prev)
+        torch.cuda.synchronize()
+        infer_s_ms.append((time.perf_counter() - t1) * 1e3)
         out = {}
         for name, mode in variants:
             g = None if name.endswith("zero") else (dq_prev if "previous" in name else
                                                     (pred16 if "bf16" in name else
-                                                     (pred_r if "learned_r" in name else pred)))
+                                                     (pred_r if "learned_r" in name else
+                                                      (pred_s if name == "learned_s" else pred))))
             q1, info = (st32 if name.startswith("fp32") else st).solve_step(q, guess=g, mode=mode,
                                                                             graph="graph" in name)
             if not info["converged"]:
@@ -369,7 +387,9 @@ def learned_guess_experiment(args) -> dict:
             r["first"].append(info["first_gmres"])
             r["total"].append(info["gmres"])
             r["newton"].append(info["newton"])
-            infer = infer16_ms[-1] if "bf16" in name else (infer_r_ms[-1] if "learned_r" in name else infer_ms[-1])
+            infer = (infer16_ms[-1] if "bf16" in name else
+                     (infer_r_ms[-1] if "learned_r" in name else
+                      (infer_s_ms[-1] if name == "learned_s" else infer_ms[-1])))
             r["seconds"].append(info["seconds"] + (infer * 1e-3 if "learned" in name else 0.0))
             r["guess_res"].append(info["guess_res"])
             r["rejected"].append(info["guess_rejected"])
@@ -400,6 +420,14 @@ def learned_guess_experiment(args) -> dict:
                                  "loss_last_epoch": history_r[-1], "holdout_loss": hold_r, "alpha": lgr.alpha,
                                  "network": f"{3 * dpe}-256-256-{dpe} tanh, FP32, {lgr.net.n_params} parameters"},
         "inference_residual_input_ms_mean": mean(infer_r_ms),
+        "train_condensed": {"seconds": t_train_s, "epochs": args.lg_condensed_epochs,
+                            "batch": f"one step ({n_elem} elements)", "lr": args.lg_lr,
+                            "loss_first_epoch": history_s[0], "loss_last_epoch": history_s[-1],
+                            "holdout_condensed_loss": hold_s, "alpha": lgs.alpha,
+                            "holdout_condensed_loss_mse_network": hold_s_mse,
+                            "holdout_condensed_loss_previous_increment": 1.0,
+                            "weighting": "S of the last training step for every stored step"},
+        "inference_condensed_ms_mean": mean(infer_s_ms),
         "guess_rejected": {k: int(np.sum(rec[k]["rejected"])) for k in names},
         "forcing": "GMRES tol per Newton iteration = clip(0.5 newton_tol |R0| / |R|, gmres_tol, 0.1)",
     }
@@ -418,6 +446,7 @@ def learned_guess_experiment(args) -> dict:
     lg.close()
     lg16.close()
     lgr.close()
+    lgs.close()
     st.close()
     st32.close()
     return result
@@ -541,6 +570,8 @@ def main() -> int:
     ap.add_argument("--lg-steps", type=int, default=200)
     ap.add_argument("--lg-train", type=int, default=50)
     ap.add_argument("--lg-epochs", type=int, default=20)
+    ap.add_argument("--lg-condensed-epochs", type=int, default=40,
+                    help="epochs of the network trained on the condensed residual (one step per batch)")
     ap.add_argument("--lg-batch", type=int, default=1024)
     ap.add_argument("--lg-lr", type=float, default=1e-3)
     ap.add_argument("--lg-seed", type=int, default=0)

@@ -258,6 +258,23 @@ scdg_status scdg_schur_apply(scdg_plan *p, const double *x, double *y);
  * 0): SCDG_ERR_STATE otherwise.  Asynchronous on the plan's stream. */
 scdg_status scdg_schur_apply_transpose(scdg_plan *p, const double *x, double *y);
 
+/* Condensed-residual error of a predicted increment, for training the learned
+ * initial guess (Section 3.2: the guess seeds GMRES on S Q_b = b_S, whose
+ * starting residual is b_S - S x0_b = S (Q_b - x0_b)).  y and t are network
+ * outputs and targets in the normalised natural order of scdg_guess_target
+ * (n_dof floats each, device; either may be NULL for zero), stats the 25
+ * device doubles of scdg_guess_stats whose entries 15..19 (rc) scale them back:
+ *   e = P_b (rc (y - t)),  *loss = scale ||S e||_2^2 (one device double),
+ *   dy = d loss / d y = 2 scale rc P_b^T S^T S e (n_dof floats, device; zero
+ *   on interior DOFs; may be NULL to evaluate the loss only).
+ * P_b restricts a natural vector to the plan's boundary vector.  Uses the
+ * plan's boundary workspace (no other call may run on the plan meanwhile);
+ * needs a condensed plan in the assembled form (schur mode 0), SCDG_ERR_STATE
+ * otherwise; SCDG_ERR_ARG for scale < 0 or both y and t NULL.  Asynchronous
+ * on the plan's stream. */
+scdg_status scdg_guess_schur_loss(scdg_plan *p, const float *y, const float *t, const double *stats,
+                                  double scale, float *dy, double *loss);
+
 /* Copy internal arrays to caller device memory (for inspection and tests):
  * SCDG_EXPORT_AII_INV: sum n_i^2 values of A_ii(e)^-1; SCDG_EXPORT_SCHUR:
  * sum n_c^2 values of T_e; SCDG_EXPORT_X: sum n_i n_c values of X_e; all in the

@@ -31,6 +31,7 @@ EXPORTED = [
     "scdg_dg_create", "scdg_dg_destroy", "scdg_dg_residual", "scdg_dg_gradient", "scdg_dg_set_geometry",
     "scdg_dg_jacobian_apply",
     "scdg_dg_jacobian_apply_noalloc", "scdg_dg_jacobian_blocks", "scdg_schur_apply_transpose",
+    "scdg_guess_schur_loss",
     "scdg_mlp_create", "scdg_mlp_destroy", "scdg_mlp_param_count", "scdg_mlp_set_compute", "scdg_mlp_forward",
     "scdg_mlp_backward", "scdg_mlp_adam", "scdg_mlp_mse", "scdg_mlp_gather", "scdg_guess_stats",
     "scdg_guess_features", "scdg_guess_target", "scdg_guess_apply",
@@ -145,6 +146,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "scdg_dg_jacobian_apply_noalloc": (i32, [vp, vp, vp, d, vp]),
         "scdg_dg_jacobian_blocks": (i32, [vp, vp, vp, d, vp, vp, vp, vp]),
         "scdg_schur_apply_transpose": (i32, [vp, vp, vp]),
+        "scdg_guess_schur_loss": (i32, [vp, vp, vp, vp, d, vp, vp]),
         "scdg_dg_set_geometry": (i32, [vp, vp]),
         "scdg_mlp_create": (i32, [C.POINTER(vp), C.POINTER(MlpShape), vp]),
         "scdg_mlp_destroy": (i32, [vp]),

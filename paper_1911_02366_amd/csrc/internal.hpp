@@ -316,6 +316,10 @@ hipError_t launch_gather(const double *src, const int32_t *map, double *dst, int
 hipError_t launch_gather_blocks(const double *src, const int32_t *idx, double *dst, int64_t nblocks,
                                 hipStream_t s);
 hipError_t launch_scatter(const double *src, const int32_t *map, double *dst, int64_t n, hipStream_t s);
+hipError_t launch_guess_err_gather(const float *y, const float *t, const double *stats, const int32_t *map,
+                                   int64_t n, double *e, hipStream_t s);
+hipError_t launch_guess_grad_scatter(const double *g, const double *stats, const int32_t *map, int64_t n,
+                                     int64_t n_dof, double a, float *dy, hipStream_t s);
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s,
                         const int32_t *halt = nullptr);
 hipError_t launch_fill(double *y, int64_t n, double v, hipStream_t s, const int32_t *halt = nullptr);

@@ -573,6 +573,39 @@ __global__ void scatter_kernel(const double *__restrict__ src, const int32_t *__
     dst[map[i]] = src[i];
 }
 
+// Boundary part of a predicted increment's error in natural units: e[k] =
+// rc_v (y_i - t_i) for the natural DOF i = map[k] of boundary slot k, with v = i
+// mod 5 the conserved variable and rc_v = stats[15 + v] the scale the network's
+// outputs and targets were normalised by; a missing y or t counts as zero.
+__global__ void guess_err_gather_kernel(const float *__restrict__ y, const float *__restrict__ t,
+                                        const double *__restrict__ stats, const int32_t *__restrict__ map,
+                                        int64_t n, double *__restrict__ e) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = map[k];
+    const double yi = y ? (double)y[i] : 0.0, ti = t ? (double)t[i] : 0.0;
+    e[k] = stats[15 + i % 5] * (yi - ti);
+  }
+}
+
+// dy[map[k]] = a rc_v g[k] (the chain rule through e = rc (y - t)); the caller
+// zeroes dy first, so interior DOFs keep a zero gradient
+__global__ void guess_grad_scatter_kernel(const double *__restrict__ g, const double *__restrict__ stats,
+                                          const int32_t *__restrict__ map, int64_t n, double a,
+                                          float *__restrict__ dy) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = map[k];
+    dy[i] = (float)(a * stats[15 + i % 5] * g[k]);
+  }
+}
+
+__global__ void fill_zero_f32_kernel(float *__restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = 0.f;
+}
+
 __global__ void axpby_kernel(int64_t n, double a, const double *__restrict__ x, double b,
                              double *__restrict__ y, const int32_t *__restrict__ halt) {
   if (halt && *halt) return;
@@ -962,6 +995,23 @@ hipError_t launch_gather_blocks(const double *src, const int32_t *idx, double *d
   if (nblocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(gather_blocks_kernel, dim3(grid_for(nblocks * 25)), dim3(kThreads), 0, s, src, idx, dst,
                      nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_guess_err_gather(const float *y, const float *t, const double *stats, const int32_t *map,
+                                   int64_t n, double *e, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(guess_err_gather_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, y, t, stats, map, n, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_guess_grad_scatter(const double *g, const double *stats, const int32_t *map, int64_t n,
+                                     int64_t n_dof, double a, float *dy, hipStream_t s) {
+  if (n_dof > 0)
+    hipLaunchKernelGGL(fill_zero_f32_kernel, dim3(grid_for(n_dof)), dim3(kThreads), 0, s, dy, n_dof);
+  if (n > 0)
+    hipLaunchKernelGGL(guess_grad_scatter_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, g, stats, map, n, a,
+                       dy);
   return hipGetLastError();
 }
 

@@ -1544,6 +1544,7 @@ scdg_status scdg_condense_rhs(scdg_plan *pl, const double *b, double *bs) {
 scdg_status scdg_schur_apply(scdg_plan *pl, const double *x, double *y) {
   if (!pl || !x || !y) return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
   if (p.state < 3) return SCDG_ERR_STATE;
   return schur_apply_impl(p, x, y);
 }
@@ -1557,6 +1558,28 @@ scdg_status scdg_schur_apply_transpose(scdg_plan *pl, const double *x, double *y
     return SCDG_ERR_STATE;
   }
   HIP_TRY(launch_schur_apply_t(p, x, p.w_t, y, fp32(p)));
+  return SCDG_OK;
+}
+
+scdg_status scdg_guess_schur_loss(scdg_plan *pl, const float *y, const float *t, const double *stats,
+                                  double scale, float *dy, double *loss) {
+  if (!pl || (!y && !t) || !stats || !loss || !(scale >= 0.0) || !std::isfinite(scale)) return SCDG_ERR_ARG;
+  Plan &p = pl->p;
+  ST_TRY(on_device(p));
+  if (p.state < 3 || p.schur_mode != 0) {
+    p.last_error = "scdg_guess_schur_loss: needs the condensed plan in the assembled form (mode 0)";
+    return SCDG_ERR_STATE;
+  }
+  // e = P_b (rc (y - t)), s = S e, loss = scale s.s; dy = 2 scale rc P_b^T S^T s
+  double *e = p.w_bs, *sv = p.w_qb;
+  HIP_TRY(launch_guess_err_gather(y, t, stats, p.d_bmap, p.n1, e, p.stream));
+  ST_TRY(schur_apply_impl(p, e, sv));
+  HIP_TRY(launch_multidot(sv, 0, 1, sv, p.n1, p.gm_part, p.red_blocks, p.gm_h, p.stream));
+  HIP_TRY(launch_axpby(1, scale, p.gm_h, 0.0, loss, p.stream));
+  if (dy) {
+    HIP_TRY(launch_schur_apply_t(p, sv, p.w_t, e, fp32(p)));
+    HIP_TRY(launch_guess_grad_scatter(e, stats, p.d_bmap, p.n1, p.n_dof, 2.0 * scale, dy, p.stream));
+  }
   return SCDG_OK;
 }
 

@@ -221,6 +221,7 @@ class LearnedGuess:
         self.x = torch.empty(capacity * n_elem * self.nx, dtype=torch.float32, device=device)
         self.t = torch.empty(capacity * n_elem * dofs_per_elem, dtype=torch.float32, device=device)
         self.count = 0                      # stored rows
+        self.step_stats = []                # field statistics of every stored step (25 device doubles)
         self.dev = device
 
     def correction_rms(self, q_s, dq_prev, dq):
@@ -243,6 +244,7 @@ class LearnedGuess:
                           x=self.x[self.count * nx:(self.count + self.n_elem) * nx], r=r)
         self.net.target(dq, dq_prev, stats, self.n_elem,
                         t=self.t[self.count * nt:(self.count + self.n_elem) * nt])
+        self.step_stats.append(stats.clone())
         self.count += self.n_elem
 
     def copy_samples(self, other: "LearnedGuess"):
@@ -253,6 +255,7 @@ class LearnedGuess:
         nx, nt = self.nx, self.dpe
         self.x[:other.count * nx].copy_(other.x[:other.count * nx])
         self.t[:other.count * nt].copy_(other.t[:other.count * nt])
+        self.step_stats = [st.clone() for st in other.step_stats]
         self.count = other.count
 
     def train(self, epochs: int, lr: float = 1e-3, holdout_rows: int = 0, alpha_rows: int | None = None):
@@ -327,6 +330,77 @@ class LearnedGuess:
             return stt / n
         a = self.alpha
         return (stt - 2 * a * sty + a * a * syy) / n
+
+    # ---- training against the condensed residual the guess leaves ----
+
+    def _step_rows(self, k: int):
+        n, nx, nt = self.n_elem, self.nx, self.dpe
+        return self.x[k * n * nx:(k + 1) * n * nx], self.t[k * n * nt:(k + 1) * n * nt]
+
+    def _condensed_abc(self, plan, k: int):
+        """For stored step k: A = |S e(y, 0)|^2, B = <S e(y, 0), S e(0, t)> and
+        C = |S e(0, t)|^2 with e(y, t) = P_b (rc (y - t)), so that the loss of the
+        shrunk output a y is a^2 A - 2 a B + C (three library loss evaluations)."""
+        x, t = self._step_rows(k)
+        st = self.step_stats[k]
+        y = self.net.forward(self.w, x, self.n_elem)
+        a = float(plan.guess_schur_loss(y, None, st, grad=False)[0])
+        c = float(plan.guess_schur_loss(None, t, st, grad=False)[0])
+        lyt = float(plan.guess_schur_loss(y, t, st, grad=False)[0])
+        return a, 0.5 * (a + c - lyt), c
+
+    def condensed_loss_on(self, plan, k: int) -> float:
+        """||S P_b (rc (alpha y - t))||^2 / ||S P_b (rc t)||^2 for stored step k,
+        S the plan's condensed operator (the zero correction, i.e. the previous
+        increment, scores 1)."""
+        a, b, c = self._condensed_abc(plan, k)
+        al = self.alpha
+        return (al * al * a - 2.0 * al * b + c) / c
+
+    def train_condensed(self, plan, epochs: int, lr: float = 1e-3, holdout_steps: int = 1,
+                        alpha_steps: int = 1):
+        """Adam on the condensed-residual loss: GMRES started from the guess x0
+        begins at b_S - S x0_b = S (Q_b - x0_b), so each stored step's loss is
+        ||S P_b (rc (y - t))||^2 divided by that of the zero correction (an
+        untrained network scores 1).  S couples neighbouring elements, so a batch
+        is one whole step (every element), the training steps visited in a seeded
+        random order each epoch.  The plan's condensed operator (the step it was
+        last condensed at) weights every stored step: one S per step would not
+        fit in memory at the sizes this is used at.  The last stored steps split
+        as with train(): alpha_steps validation steps fit the shrinkage alpha (by
+        the same weighted least squares), then holdout_steps are scored only.
+        Returns per-epoch mean losses and the mean hold-out loss."""
+        n_steps = self.count // self.n_elem
+        n_train = n_steps - holdout_steps - alpha_steps
+        if n_train < 1 or (holdout_steps and alpha_steps < 1):
+            raise ValueError("too few stored steps for training after the validation and hold-out splits")
+        den = [float(plan.guess_schur_loss(None, self._step_rows(k)[1], self.step_stats[k], grad=False)[0])
+               for k in range(n_steps)]
+        dy = torch.empty(self.n_elem * self.dpe, dtype=torch.float32, device=self.dev)
+        loss = torch.empty(1, dtype=torch.float64, device=self.dev)
+        history = []
+        for _ in range(epochs):
+            total = 0.0
+            for k in self.rng.permutation(n_train):
+                x, t = self._step_rows(int(k))
+                y = self.net.forward(self.w, x, self.n_elem)
+                plan.guess_schur_loss(y, t, self.step_stats[k], scale=1.0 / den[k], dy=dy, loss=loss)
+                dw = self.net.backward(self.w, x, dy, self.n_elem)
+                self.adam_step += 1
+                self.net.adam(self.w, dw, self.m1, self.m2, lr=lr, step=self.adam_step)
+                total += float(loss)
+            history.append(total / n_train)
+        hold = None
+        if holdout_steps:
+            # minimise the sum over the validation steps of (a^2 A - 2 a B + C) / C
+            sa = sb = 0.0
+            for k in range(n_train, n_train + alpha_steps):
+                a, b, c = self._condensed_abc(plan, k)
+                sa, sb = sa + a / c, sb + b / c
+            self.alpha = float(min(1.0, max(0.0, sb / sa))) if sa > 0 else 0.0
+            hold = float(np.mean([self.condensed_loss_on(plan, k)
+                                  for k in range(n_steps - holdout_steps, n_steps)]))
+        return history, hold
 
     def predict(self, q_s, dq_prev, rc_prev, r=None):
         """Predicted increment of the step from q_s (natural DOF order); rc_prev is

@@ -174,6 +174,21 @@ class Plan:
                     "scdg_schur_apply_transpose")
         return y
 
+    def guess_schur_loss(self, y, t, stats, scale: float = 1.0, dy=None, loss=None, grad: bool = True):
+        """Condensed-residual loss scale ||S P_b (rc (y - t))||^2 of a normalised
+        guess y against its target t (float32 natural vectors, either None for
+        zero), and its gradient dy with respect to y when grad
+        (scdg_guess_schur_loss; assembled form).  Returns (loss, dy), loss a
+        one-element device double."""
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device=stats.device)
+        if grad and dy is None:
+            dy = torch.empty(self.n_dof, dtype=torch.float32, device=stats.device)
+        self._check(self.lib.scdg_guess_schur_loss(self.handle, _ptr(y), _ptr(t), _ptr(stats), float(scale),
+                                                   _ptr(dy) if grad else None, _ptr(loss)),
+                    "scdg_guess_schur_loss")
+        return loss, (dy if grad else None)
+
     def newton_step(self, dg, q_s, inv_dt: float, q, check=True, **opts):
         """Newton iterations of one backward-Euler step (scdg_newton_step): each
         iteration is one replay of a captured graph.  q holds the starting state on
