@@ -105,6 +105,7 @@ struct DevBuf {
 struct Plan {
   hipStream_t stream = nullptr;
   int device = 0;
+  uint64_t uid = 0;   // distinct for every plan the process creates (never reused)
   std::string last_error;
   int state = 0;  // 0 created, 1 assembled, 2 factored, 3 condensed
   // Schur products: 0 through the element blocks T_e and the A_bb remainder
@@ -357,6 +358,7 @@ int64_t dg_dof_count(const scdg_dg *dg);
 void dg_graph_state(const scdg_dg *dg, uint64_t *gen, const void **g, const void **met, const void **params);
 // device Jacobian blocks (k_dgsem.hip): the plan's structure as the assembly sees it
 struct JacPlanView {
+  uint64_t plan_uid;             // the plan's uid: its coupling sets and A_bb pattern never change
   int ni, nc, ncn, nb;           // n_i, n_c (DOFs), |C_e| (nodes), boundary nodes per element
   int64_t nnzb;
   const int32_t *c_node;         // [n_elem * ncn] device copy of the coupling sets

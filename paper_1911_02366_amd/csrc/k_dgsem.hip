@@ -1133,9 +1133,39 @@ __global__ __launch_bounds__(256) void jac_assemble_kernel(JacBlocksArgs a) {
     for (int w = 0; w < 5; ++w) dst[v * ld + w] = acc[v * 5 + w];
 }
 
+// structural check of a plan: one thread per (element, destination); flags a
+// destination whose block has no place in the plan's coupling sets or A_bb
+// pattern (the places are found as jac_assemble_kernel finds them)
+__global__ __launch_bounds__(256) void jac_cover_kernel(JacBlocksArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y;
+  if (t >= a.n_dest) return;
+  const int4 ds = a.dest[t];
+  const int rn = ds.x, cn = ds.z;
+  const int ce = elem_at(e, a.k, ds.y);
+  const int ri = a.iidx[rn], ci = a.iidx[cn];
+  bool found;
+  if (ri >= 0 && ci >= 0)
+    found = ce == e;
+  else if (ri >= 0)
+    found = find_sorted(a.c_node + (int64_t)e * a.ncn, a.ncn, ce * a.nb + a.rank[cn]) >= 0;
+  else if (ci >= 0)
+    found = find_sorted(a.c_node + (int64_t)ce * a.ncn, a.ncn, e * a.nb + a.rank[rn]) >= 0;
+  else {
+    const int gr = e * a.nb + a.rank[rn], gc = ce * a.nb + a.rank[cn];
+    const int64_t b0 = a.bb_rowptr[gr];
+    found = find_sorted(a.bb_col + b0, (int)(a.bb_rowptr[gr + 1] - b0), gc) >= 0;
+  }
+  if (!found) a.flag[0] = 1;
+}
+
+// x[0, n) = 0 in 16-byte stores (x 16-byte aligned), the odd last entry alone
 __global__ void fill_zero_kernel(double *__restrict__ x, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = 0.0;
+  double2 *x2 = reinterpret_cast<double2 *>(x);
+  const int64_t n2 = n / 2;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
+    x2[i] = make_double2(0.0, 0.0);
+  if (n % 2 && blockIdx.x == 0 && threadIdx.x == 0) x[n - 1] = 0.0;
 }
 
 struct DgContext {
@@ -1160,6 +1190,9 @@ struct DgContext {
   double *jt_coef = nullptr;
   int32_t *jt_iidx = nullptr, *jt_rank = nullptr, *jt_flag = nullptr;
   double *pj = nullptr;
+  // the last plan checked for a place for every template block (uid, result)
+  uint64_t cover_uid = 0;
+  bool cover_ok = false;
 };
 
 }  // namespace scdg
@@ -1357,10 +1390,11 @@ scdg_status dg_jacobian_blocks_on(scdg_dg *dg, const JacPlanView &v, const doubl
   }
   const hipStream_t s = c.stream;
   const int64_t n_ii = (int64_t)n_elem * v.ni * v.ni, n_ib = (int64_t)n_elem * v.ni * v.nc;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(2048), dim3(256), 0, s, aii, n_ii);
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(2048), dim3(256), 0, s, aib, n_ib);
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(2048), dim3(256), 0, s, abi, n_ib);
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(2048), dim3(256), 0, s, bb_val, v.nnzb * 25);
+  const unsigned fill_grid = 8192;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(fill_grid), dim3(256), 0, s, aii, n_ii);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(fill_grid), dim3(256), 0, s, aib, n_ib);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(fill_grid), dim3(256), 0, s, abi, n_ib);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(fill_grid), dim3(256), 0, s, bb_val, v.nnzb * 25);
   if (hipMemsetAsync(c.jt_flag, 0, sizeof(int32_t), s) != hipSuccess) return fail("flag reset");
   const int threads = ((p3 + 63) / 64) * 64;
   hipLaunchKernelGGL(lift_kernel, dim3(n_elem), dim3(threads), 0, s, c.dev, q, c.g, nullptr);
@@ -1393,9 +1427,25 @@ scdg_status dg_jacobian_blocks_on(scdg_dg *dg, const JacPlanView &v, const doubl
   a.bb_val = bb_val;
   a.inv_dt = inv_dt;
   a.flag = c.jt_flag;
-  hipLaunchKernelGGL(jac_assemble_kernel, dim3((unsigned)((c.jt_ndest + 255) / 256), (unsigned)n_elem), dim3(256), 0,
-                     s, a);
+  const dim3 dest_grid((unsigned)((c.jt_ndest + 255) / 256), (unsigned)n_elem);
+  if (c.cover_uid != v.plan_uid) {
+    // does the plan hold a place for every block of the template?  (once per
+    // plan; its coupling sets and A_bb pattern never change)
+    c.cover_uid = 0;
+    hipLaunchKernelGGL(jac_cover_kernel, dest_grid, dim3(256), 0, s, a);
+    int32_t missing = 0;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&missing, c.jt_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail("structure check");
+    c.cover_uid = v.plan_uid;
+    c.cover_ok = missing == 0;
+    if (hipMemsetAsync(c.jt_flag, 0, sizeof(int32_t), s) != hipSuccess) return fail("flag reset");
+  }
+  hipLaunchKernelGGL(jac_assemble_kernel, dest_grid, dim3(256), 0, s, a);
   if (hipGetLastError() != hipSuccess) return fail("launch");
+  // every block has a place: nothing to check, the call returns without waiting
+  if (c.cover_ok) return SCDG_OK;
   int32_t flag = 0;
   if (hipMemcpyAsync(&flag, c.jt_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)

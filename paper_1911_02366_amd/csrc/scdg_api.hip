@@ -3,6 +3,7 @@
 // for factor / condense / condensed RHS / condensed solve / back-substitution
 // / full residual and iterative refinement.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -907,6 +908,8 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   scdg_plan *pl = new (std::nothrow) scdg_plan();
   if (!pl) return SCDG_ERR_NOMEM;
   Plan &p = pl->p;
+  static std::atomic<uint64_t> next_uid{1};
+  p.uid = next_uid.fetch_add(1);
   p.stream = static_cast<hipStream_t>(hip_stream);
   (void)hipGetDevice(&p.device);
   const int E = s->n_elem;
@@ -1617,6 +1620,7 @@ scdg_status scdg_dg_jacobian_blocks(scdg_dg *dg, scdg_plan *pl, const double *q,
       !std::isfinite(inv_dt))
     return SCDG_ERR_ARG;
   Plan &p = pl->p;
+  ST_TRY(on_device(p));
   int k = 0, order = 0;
   bool cart = false;
   dg_jacobian_shape(dg, &k, &order, &cart);
@@ -1638,6 +1642,7 @@ scdg_status scdg_dg_jacobian_blocks(scdg_dg *dg, scdg_plan *pl, const double *q,
   }
   if (!p.d_jac_cnode) ST_TRY(upload(p, &p.d_jac_cnode, p.h_c_node));
   JacPlanView v;
+  v.plan_uid = p.uid;
   v.ni = ni;
   v.nc = (int)(5 * ncn);
   v.ncn = (int)ncn;

@@ -115,3 +115,68 @@ def test_unsupported_configurations_refused():
     assert err.value.status == -8
     for o in (plan, sipg, other):
         o.close()
+
+
+def _pattern_blocks(rowptr, col, val):
+    """{(row, col): 5x5 block} of an A_bb pattern."""
+    val = to_np(val).reshape(-1, 5, 5)
+    out = {}
+    for r in range(len(rowptr) - 1):
+        for j in range(rowptr[r], rowptr[r + 1]):
+            out[(r, int(col[j]))] = val[j]
+    return out
+
+
+def test_plan_pattern_without_room_and_with_extra_blocks():
+    """Whether the plan holds a place for every block the Jacobian can fill is
+    checked once per plan (the call is asynchronous afterwards when it does;
+    otherwise each call checks the values): a plan whose A_bb pattern lacks a
+    nonzero block is refused (SCDG_ERR_ARG), one whose pattern has an extra
+    block gets zeros there and the same values everywhere else; alternating
+    between plans on one DG object gives bitwise the same blocks each time."""
+    k, n, re, dt = 3, 3, 400.0, 1e-2
+    case = build_case(k, n, re, dt, seed=12, device=DEV)
+    q = case.q_state.reshape(-1).to(DEV).contiguous()
+    dg = DgResidual(k, n, mach=0.1, reynolds=re)
+    st = case.structure()
+    plan = Plan.from_structure(st)
+    ref = dg.jacobian_blocks(plan, q, 1.0 / dt)
+    rowptr, col = np.asarray(st["bb_rowptr"], dtype=np.int64), np.asarray(st["bb_col"], dtype=np.int32)
+    blocks = _pattern_blocks(rowptr, col, ref["bb_val"])
+    # drop the largest off-diagonal block of row 0
+    r0 = 0
+    js = [j for j in range(rowptr[r0], rowptr[r0 + 1]) if col[j] != r0]
+    jd = max(js, key=lambda j: np.abs(blocks[(r0, int(col[j]))]).max())
+    assert np.abs(blocks[(r0, int(col[jd]))]).max() > 0
+    col_less = np.delete(col, jd)
+    rowptr_less = rowptr.copy()
+    rowptr_less[r0 + 1:] -= 1
+    less = Plan.from_structure(dict(st, bb_rowptr=rowptr_less, bb_col=col_less))
+    with pytest.raises(ScdgError) as err:
+        dg.jacobian_blocks(less, q, 1.0 / dt)
+    assert err.value.status == -1
+    # add a block to row 1 in a column it does not couple to
+    r1 = 1
+    present = set(int(c) for c in col[rowptr[r1]:rowptr[r1 + 1]])
+    extra = next(c for c in range(int(col.max()) + 1) if c not in present)
+    row_cols = sorted(present | {extra})
+    col_more = np.concatenate([col[:rowptr[r1]], np.array(row_cols, dtype=np.int32), col[rowptr[r1 + 1]:]])
+    rowptr_more = rowptr.copy()
+    rowptr_more[r1 + 1:] += 1
+    more = Plan.from_structure(dict(st, bb_rowptr=rowptr_more, bb_col=col_more))
+    got = dg.jacobian_blocks(more, q, 1.0 / dt)
+    for name in ("aii", "aib", "abi"):
+        assert torch.equal(got[name], ref[name]), name
+    gb = _pattern_blocks(rowptr_more, col_more, got["bb_val"])
+    assert not gb.pop((r1, extra)).any()
+    assert gb.keys() == blocks.keys()
+    assert all(np.array_equal(gb[key], blocks[key]) for key in blocks)
+    # back to the first plan, then the extended one again: same blocks bitwise
+    again = dg.jacobian_blocks(plan, q, 1.0 / dt)
+    for name in ("aii", "aib", "abi", "bb_val"):
+        assert torch.equal(again[name], ref[name]), name
+    got2 = dg.jacobian_blocks(more, q, 1.0 / dt)
+    for name in ("aii", "aib", "abi", "bb_val"):
+        assert torch.equal(got2[name], got[name]), name
+    for o in (plan, less, more, dg):
+        o.close()
