@@ -195,13 +195,13 @@ scdg_status scdg_set_schur_mode(scdg_plan *p, int32_t mode);
 scdg_status scdg_get_schur_mode(const scdg_plan *p, int32_t *mode);
 
 /* Form of the batched inverse (Gauss-Jordan with partial pivoting, Section 3.2):
- * 0 automatic (form 3 up to n_i = 352, else form 1 up to n_i = 320, else
- * form 2); 1 one workgroup per element for the whole elimination, 24- or
+ * 0 automatic (form 3 up to n_i = 400, else form 2); 1 one workgroup per element for the whole elimination, 24- or
  * 32-column panels in LDS; 2 blocked: outer panels of 128 columns whose update
  * of the rest of the block is a batched matrix-core GEMM; 3 resident panel:
- * one workgroup per element holding an outer panel of 48 (FP64) or 64
- * (FP32) columns in LDS, so the rest of the block is streamed once per outer
- * panel (n_i <= 352, SCDG_ERR_UNSUPPORTED from scdg_factor otherwise).  All
+ * one workgroup per element holding an outer panel of 48 (FP64; 32 when some
+ * n_i exceeds 320) or 64 (FP32) columns in LDS, so the rest of the block is
+ * streamed once per outer panel (n_i <= 400, SCDG_ERR_UNSUPPORTED from
+ * scdg_factor otherwise).  All
  * forms use the same pivot rule (largest |a| among unused rows, lowest row on
  * ties); rounding differs with the blocking, so near-ties may pick different
  * rows.  SCDG_ERR_ARG for a mode other than 0..3.  scdg_get_inverse_mode

@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kThreads) void gj_inverse_kernel(const double *__re
 constexpr int kResThreads = 512;
 constexpr int kResWaves = kResThreads / 64;
 constexpr int kResElimWaves = 4;                     // waves holding rows during the column steps
-constexpr int kResMaxN = 352;                        // 22 column tiles; 2 rows per lane of 4 waves
+constexpr int kResMaxN = 400;                        // 25 column tiles; 2 rows per lane of 4 waves
 constexpr int kResInner = 16;
 
 // column tiles one wave's contiguous share of an outer pass can span: its
@@ -787,7 +787,9 @@ __global__ __launch_bounds__(L::NT) void gj_resident_kernel(const double *__rest
   for (int k = tid; k < rp; k += NT) qinv[piv[k]] = k;
   __syncthreads();
   {
-    constexpr int kCols = (kResMaxN + 63) / 64, kRows = 4;
+    // 6 columns of 64 at least: at n_i <= 320 five would do, but the register
+    // allocation of the FP64 kernel then spills
+    constexpr int kCols = (L::MAXN > 384 ? L::MAXN + 63 : 384) / 64, kRows = 4;
     int qc[kCols];
 #pragma unroll
     for (int t = 0; t < kCols; ++t) {
@@ -1051,8 +1053,10 @@ hipError_t gj_res_launch(Plan &p, typename L::T *work, typename L::T *out) {
 // workgroups per CU with 48 columns 1.53 ms.  FP64 48 is the widest that fits.
 // Each comes in two sizes: up to n_i = 320 (N <= 5; fewer column tiles, so
 // fewer registers for the B operands of a wave's share: FP32 1.43 against
-// 1.54 ms) and up to kResMaxN.
-using GjRes64 = GjRes<double, 48, 2, kResMaxN>;
+// 1.54 ms) and up to kResMaxN = 400 (N = 5 elements with a wall face among
+// their interior nodes), where an FP64 panel of 48 columns no longer fits in
+// LDS and the FP64 form takes 32.
+using GjRes64 = GjRes<double, 32, 2, kResMaxN>;
 using GjRes32 = GjRes<float, 64, 2, kResMaxN>;
 using GjRes64n5 = GjRes<double, 48, 2, 320>;
 using GjRes32n5 = GjRes<float, 64, 2, 320>;

@@ -160,9 +160,15 @@ class Plan:
                     "scdg_residual")
         return r, rel.value
 
+    def _boundary_vectors(self, *vs):
+        for v in vs:
+            if v.dtype != torch.float64 or v.numel() < self.n1 or not v.is_contiguous():
+                raise ValueError(f"boundary vectors are contiguous float64 tensors of at least {self.n1} entries")
+
     def schur_apply(self, x, y=None):
         if y is None:
             y = torch.empty_like(x)
+        self._boundary_vectors(x, y)
         self._check(self.lib.scdg_schur_apply(self.handle, _ptr(x), _ptr(y)), "scdg_schur_apply")
         return y
 
@@ -170,6 +176,7 @@ class Plan:
         """y = S^T x (scdg_schur_apply_transpose; assembled form)."""
         if y is None:
             y = torch.empty_like(x)
+        self._boundary_vectors(x, y)
         self._check(self.lib.scdg_schur_apply_transpose(self.handle, _ptr(x), _ptr(y)),
                     "scdg_schur_apply_transpose")
         return y
@@ -180,8 +187,15 @@ class Plan:
         zero), and its gradient dy with respect to y when grad
         (scdg_guess_schur_loss; assembled form).  Returns (loss, dy), loss a
         one-element device double."""
+        for name, v in (("y", y), ("t", t), ("dy", dy if grad else None)):
+            if v is not None and (v.dtype != torch.float32 or v.numel() < self.n_dof or not v.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float32 tensor of at least {self.n_dof} entries")
+        if stats.dtype != torch.float64 or stats.numel() < 25 or not stats.is_contiguous():
+            raise ValueError("stats must be a contiguous float64 tensor of 25 entries")
         if loss is None:
             loss = torch.empty(1, dtype=torch.float64, device=stats.device)
+        elif loss.dtype != torch.float64 or loss.numel() < 1:
+            raise ValueError("loss must be a float64 tensor")
         if grad and dy is None:
             dy = torch.empty(self.n_dof, dtype=torch.float32, device=stats.device)
         self._check(self.lib.scdg_guess_schur_loss(self.handle, _ptr(y), _ptr(t), _ptr(stats), float(scale),

@@ -8,7 +8,7 @@ Bars as for the other forms: 1e-11 relative per element in FP64, 5e-5 in FP32
 (the interior blocks are mass-dominated and well conditioned).  Cases:
 n_i = 5, 40, 135, 320 (one, one, three and seven FP64 outer panels; ragged last
 outer and inner panels at 5, 40 and 135), a mixed-order plan with orders 2..5
-in one launch, blocks whose rows are permuted so that the pivots are off the
+in one launch, wall elements with n_i = 400 beside inner ones with 320, blocks whose rows are permuted so that the pivots are off the
 diagonal, and singular and NaN blocks, which must be reported through
 scdg_factor_info like the other forms do."""
 import numpy as np
@@ -144,4 +144,45 @@ def test_resident_form_refuses_large_blocks():
     with pytest.raises(Exception) as err:
         plan.factor("fp64")
     assert getattr(err.value, "status", None) == -8
+    plan.close()
+
+
+def test_resident_inverse_wall_elements():
+    """Elements with n_i = 320 and 400 in one launch: 3^3 x N = 5 with
+    isothermal walls normal to z, whose wall-face nodes join the interior of
+    the two outer element layers (the layout up to n_i = 400: 32-column FP64
+    and 64-column FP32 outer panels, 25 column tiles).  Inverse against the
+    oracle's per element in both precisions, and a full FP64 solve whose
+    residual the oracle forms from the blocks (<= 1e-12 relative)."""
+    from workload.walls import build_wall_case
+    print("[3^3 x N = 5 wall case: generation on the device]", flush=True)
+    case = build_wall_case(k_elem=3, order=5, reynolds=1600.0, dt=5e-3, seed=2, device=DEV)
+    assert sorted(set(case.n_i.tolist())) == [320, 400]
+    eb = case.element_blocks()
+    for precision, tol in (("fp64", 1e-11), ("fp32", 5e-5)):
+        res, bad, _ = _inverse(case.structure(), case.aii, case.aib, case.abi, case.bb_val, "resident",
+                               precision, case.n_elem, case.n_i)
+        assert bad == -1
+        off, worst = 0, 0.0
+        for e in range(case.n_elem):
+            m = int(case.n_i[e])
+            worst = max(worst, rel(res[off:off + m * m].reshape(m, m), oracle.element_inverse(eb["aii"][e])))
+            off += m * m
+        print(f"  {precision}: worst element error vs oracle {worst:.2e}", flush=True)
+        assert worst <= tol
+    plan = Plan.from_structure(case.structure())
+    plan.assemble(case.aii, case.aib, case.abi, case.bb_val)
+    plan.factor("fp64")
+    assert plan.inverse_mode_used() == "resident"
+    plan.condense()
+    dq, _ = plan.solve(case.rhs, solver="gmres", precond=1, tol=1e-13, ir_tol=1e-12, max_iters=4000)
+    # the full residual formed by the oracle block by block (a sparse LU of
+    # this 29k-DOF system takes minutes on the host)
+    b = to_np(case.rhs)
+    r = oracle.full_residual_blocks(case.order, case.c_ptr, case.c_node, case.bb_rowptr, case.bb_col,
+                                    eb["bb_val"], eb["aii"], eb["aib"], eb["abi"], b, to_np(dq),
+                                    phys=case.phys_faces)
+    res = float(np.linalg.norm(r) / np.linalg.norm(b))
+    print(f"  wall solve with the resident inverse: oracle full residual {res:.2e}", flush=True)
+    assert res <= 1e-12
     plan.close()

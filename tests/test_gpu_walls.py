@@ -102,3 +102,33 @@ def test_wall_fp32_refinement(setup):
     assert info["rel_res_full"] <= 1e-8 and res <= 1e-8
     assert rel(x, ref) <= 1e-5
     plan.close()
+
+
+def test_wall_transpose_and_condensed_loss(setup):
+    """S^T x (scdg_schur_apply_transpose) and the condensed-residual loss of a
+    guess (scdg_guess_schur_loss) on wall meshes, where element sizes and the
+    boundary numbering follow the physical faces: against the oracle's dense S
+    and its definition of the loss (oracle.mlp.condensed_loss)."""
+    from oracle import mlp as om
+    name, case, h, a, b, ref = setup
+    if case.n1 > 15000:
+        pytest.skip("the oracle's dense S is formed only for small wall meshes")
+    plan = _plan(case)
+    s = oracle.condensed_matrix_dense(h["c_ptr"], h["c_node"], h["bb_rowptr"], h["bb_col"], h["bb_val"],
+                                      h["aii"], h["aib"], h["abi"])
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(s.shape[0])
+    y = to_np(plan.schur_apply_transpose(torch.tensor(x, device=DEV)))
+    err = rel(y, s.T @ x)
+    _, bnode = oracle.dof_maps(case.order, case.phys_faces)
+    yv = rng.standard_normal(plan.n_dof).astype(np.float32)
+    tv = rng.standard_normal(plan.n_dof).astype(np.float32)
+    stats = rng.uniform(-1.0, 1.0, 25)
+    stats[15:20] = rng.uniform(0.1, 4.0, 5)
+    want, gw = om.condensed_loss(s, bnode, yv, tv, stats[15:20])
+    loss, dy = plan.guess_schur_loss(torch.tensor(yv, device=DEV), torch.tensor(tv, device=DEV),
+                                     torch.tensor(stats, device=DEV))
+    lerr, gerr = abs(float(loss) - want) / want, rel(to_np(dy).astype(np.float64), gw)
+    print(f"{name}: S^T x {err:.2e}, loss {lerr:.2e}, gradient {gerr:.2e}", flush=True)
+    assert err <= 1e-12 and lerr <= 1e-12 and gerr <= 1e-6
+    plan.close()
