@@ -21,6 +21,9 @@ constexpr int kGjAutoBlocked = 320;  // automatic choice: blocked form above thi
 struct GemmDesc {
   int64_t a_off, b_off, c_off;
   int32_t m, n, k, lda, ldb, ldc;
+  // fold map of this problem's C (m/5 x n/5 node blocks: index into the folded
+  // blocks' values, -1 for none), added in the epilogue; -1: no fold
+  int64_t f_off = -1;
 };
 
 // One tile of a batched GEMV: rows [row0, row0 + rows) of problem `prob`.
@@ -150,9 +153,9 @@ struct Plan {
   int32_t *d_bb_col = nullptr;    // [nnzb]
   // A_bb blocks folded into the element Schur blocks T_e, and the remainder
   int64_t n_fold = 0, n_rem = 0;
-  int64_t *d_fold_dst = nullptr;  // [n_fold] offset of the block's (0,0) entry in T
-  int32_t *d_fold_nc = nullptr;   // [n_fold] row stride (n_c of the element)
-  int32_t *d_fold_src = nullptr;  // [n_fold] block index into bb_val
+  // [sum |C_e|^2] per element, the A_bb block folded into each node block of
+  // T_e (index into bb_val) or -1; the Schur GEMM adds them in its epilogue
+  int32_t *d_fold_map = nullptr;
   int64_t *d_rem_rowptr = nullptr;  // [n_bnodes+1]
   int32_t *d_rem_col = nullptr;     // [n_rem]
   int32_t *d_rem_src = nullptr;     // [n_rem] block index into bb_val
@@ -272,9 +275,12 @@ bool gj_resident_supported(int max_n, bool fp32);
 hipError_t launch_cast_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_copy_f64(const double *src, double *dst, size_t n, hipStream_t s);
 void gemm_tile_shape(int cfg, int *bm, int *bn);
+// C = alpha A B + beta C per problem, plus the folded A_bb blocks of
+// fold_val (FP64) where fold_map (and the problem's f_off) names them
 hipError_t launch_gemm_batched(int cfg, const GemmDesc *d_desc, const int32_t *d_tiles,
                                int32_t n_tiles, const void *a, const void *b, void *c, double alpha,
-                               double beta, bool fp32, hipStream_t s);
+                               double beta, bool fp32, hipStream_t s, const int32_t *fold_map = nullptr,
+                               const double *fold_val = nullptr);
 
 // y[omap?omap[y_off+r]:y_off+r] = alpha * sum_c M[r,c] x[xmap?xmap[x_off+c]:x_off+c]
 //                                 + beta * y0[y_off + r]
@@ -293,7 +299,6 @@ hipError_t launch_bsr_pull(const Plan &p, bool full, double c0, const double *sr
                            const int32_t *map0, double c1, const double *x, double c2,
                            const double *t, double *out, bool lo = false);
 // T[dst + v nc + w] += A_bb[src][v][w] for the folded blocks
-hipError_t launch_fold_add(const Plan &p, void *t, bool fp32);
 // 5x5 diagonal blocks of S (remainder + element blocks), inverted; point inverse too
 // Matrix-free mode: diagonal 5x5 blocks of A_bi(e) X_e per slot, and the
 // Jacobi preconditioners from diag(A_bb) minus their pulled sums.

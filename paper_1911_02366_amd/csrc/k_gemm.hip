@@ -2,8 +2,10 @@
 //   C_p = alpha A_p B_p + beta C_p    for every problem p of the batch,
 // row-major operands with per-problem sizes and leading dimensions.
 //
-// It forms X_e = A_ii(e)^-1 A_ib(e) and the element blocks -A_bi(e) X_e of the
-// condensed matrix (eq. SC_step1), and the trailing updates of the dense LU of S.
+// It forms X_e = A_ii(e)^-1 A_ib(e) and the element blocks T_e = F_e - A_bi(e) X_e
+// of the condensed matrix (eq. SC_step1; F_e the A_bb node blocks folded into
+// the element, added from a per-element map in the epilogue, so T_e is written
+// once), and the trailing updates of the dense LU of S.
 //
 // Tiling: a workgroup computes a BM x BN tile of one problem; its waves form a
 // WM x WN grid, each owning (BM/WM) x (BN/WN) as a block of 16x16x4 MFMAs.  K advances in steps of 16: the next A and B slabs are loaded
@@ -29,7 +31,9 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_batched_kernel(const GemmDe
                                                                 const int32_t *__restrict__ tiles,
                                                                 const T *__restrict__ A,
                                                                 const T *__restrict__ B,
-                                                                T *__restrict__ C, T alpha, T beta) {
+                                                                T *__restrict__ C, T alpha, T beta,
+                                                                const int32_t *__restrict__ fmap,
+                                                                const double *__restrict__ fval) {
   using M = Mfma<T>;
   constexpr int kThreads = 64 * WM * WN;
   constexpr int PA = BM + 4;             // LDS row strides (padding against bank conflicts)
@@ -142,6 +146,23 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_batched_kernel(const GemmDe
   else
     kloop(std::false_type{});
 
+  // the folded A_bb node blocks of this problem's C (Schur GEMM only): the
+  // tile's part of the fold map is staged in LDS (free after the K loop), so
+  // the epilogue looks it up there and reads values only where a block folds
+  const bool fold = fmap != nullptr && d.f_off >= 0;
+  int *fm_s = reinterpret_cast<int *>(&as[0][0][0]);
+  const int rb0 = m0 / 5, cb0 = n0 / 5;
+  const int frw = (min(m0 + BM, d.m) - 1) / 5 - rb0 + 1, fcw = (min(n0 + BN, d.n) - 1) / 5 - cb0 + 1;
+  static_assert((BM / 5 + 2) * (BN / 5 + 2) * sizeof(int) <= sizeof(as), "fold map tile fits in LDS");
+  if (fold) {
+    const int32_t *__restrict__ fm = fmap + d.f_off;
+    const int fbn = d.n / 5;
+    for (int q = threadIdx.x; q < frw * fcw; q += kThreads) {
+      const int a = q / fcw, b = q - a * fcw;
+      fm_s[q] = fm[(int64_t)(rb0 + a) * fbn + cb0 + b];
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -155,6 +176,11 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_batched_kernel(const GemmDe
           T *dst = c + (int64_t)row * d.ldc + col;
           T v = alpha * acc[i][j][r];
           if (beta != T(0)) v += beta * (*dst);
+          if (fold) {
+            const int rb = row / 5, cb = col / 5;
+            const int f = fm_s[(rb - rb0) * fcw + cb - cb0];
+            if (f >= 0) v = (T)((double)v + fval[(int64_t)f * 25 + (row - 5 * rb) * 5 + (col - 5 * cb)]);
+          }
           *dst = v;
         }
       }
@@ -164,16 +190,16 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_batched_kernel(const GemmDe
 template <int BM, int BN, int WM, int WN>
 hipError_t launch_cfg(const GemmDesc *d_desc, const int32_t *d_tiles, int32_t n_tiles,
                       const void *a, const void *b, void *c, double alpha, double beta, bool fp32,
-                      hipStream_t s) {
+                      hipStream_t s, const int32_t *fmap, const double *fval) {
   const dim3 block(64 * WM * WN);
   if (fp32) {
     hipLaunchKernelGGL((gemm_batched_kernel<float, BM, BN, WM, WN>), dim3(n_tiles), block, 0, s,
                        d_desc, d_tiles, static_cast<const float *>(a), static_cast<const float *>(b),
-                       static_cast<float *>(c), (float)alpha, (float)beta);
+                       static_cast<float *>(c), (float)alpha, (float)beta, fmap, fval);
   } else {
     hipLaunchKernelGGL((gemm_batched_kernel<double, BM, BN, WM, WN>), dim3(n_tiles), block, 0, s,
                        d_desc, d_tiles, static_cast<const double *>(a), static_cast<const double *>(b),
-                       static_cast<double *>(c), alpha, beta);
+                       static_cast<double *>(c), alpha, beta, fmap, fval);
   }
   return hipGetLastError();
 }
@@ -194,18 +220,19 @@ void gemm_tile_shape(int cfg, int *bm, int *bn) {
 
 hipError_t launch_gemm_batched(int cfg, const GemmDesc *d_desc, const int32_t *d_tiles,
                                int32_t n_tiles, const void *a, const void *b, void *c, double alpha,
-                               double beta, bool fp32, hipStream_t s) {
+                               double beta, bool fp32, hipStream_t s, const int32_t *fold_map,
+                               const double *fold_val) {
   if (n_tiles <= 0) return hipSuccess;
   switch (cfg) {
-    case 1: return launch_cfg<64, 128, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
-    case 2: return launch_cfg<128, 128, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
-    case 3: return launch_cfg<128, 128, 2, 4>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
-    case 4: return launch_cfg<128, 64, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
-    case 5: return launch_cfg<240, 80, 5, 1>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
-    case 6: return launch_cfg<80, 80, 5, 1>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
-    case 7: return launch_cfg<256, 128, 4, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
-    case 8: return launch_cfg<128, 256, 2, 4>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
-    default: return launch_cfg<64, 64, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s);
+    case 1: return launch_cfg<64, 128, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s, fold_map, fold_val);
+    case 2: return launch_cfg<128, 128, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s, fold_map, fold_val);
+    case 3: return launch_cfg<128, 128, 2, 4>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s, fold_map, fold_val);
+    case 4: return launch_cfg<128, 64, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s, fold_map, fold_val);
+    case 5: return launch_cfg<240, 80, 5, 1>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s, fold_map, fold_val);
+    case 6: return launch_cfg<80, 80, 5, 1>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s, fold_map, fold_val);
+    case 7: return launch_cfg<256, 128, 4, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s, fold_map, fold_val);
+    case 8: return launch_cfg<128, 256, 2, 4>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s, fold_map, fold_val);
+    default: return launch_cfg<64, 64, 2, 2>(d_desc, d_tiles, n_tiles, a, b, c, alpha, beta, fp32, s, fold_map, fold_val);
   }
 }
 

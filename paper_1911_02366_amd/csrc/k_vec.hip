@@ -1,9 +1,8 @@
 // Memory-bound kernels of the condensed solve: batched element GEMVs with
 // coalesced gathers of the DOFs they read, the (remainder of the) A_bb BSR
-// product fused with the "pull" reduction of element contributions, the A_bb
-// fold into the element Schur blocks, the Jacobi preconditioners, and the
-// Krylov vector operations (deterministic two-stage multi-dot for Gram-Schmidt,
-// multi-AXPY, scaling).  All vectors are FP64; element matrices may be FP64 or
+// product fused with the "pull" reduction of element contributions, the Jacobi
+// preconditioners, and the Krylov vector operations (deterministic two-stage
+// multi-dot for Gram-Schmidt, multi-AXPY, scaling).  All vectors are FP64; element matrices may be FP64 or
 // FP32 (accumulation is always FP64).
 #include <algorithm>
 
@@ -274,19 +273,6 @@ __global__ __launch_bounds__(kThreads) void schur_gemv_rem_kernel(
   const int64_t g = j * (kThreads / 64) + (threadIdx.x >> 6);
   if (g >= n_bnodes) return;
   bsr_rows_wave<TV>(g, rowptr, col, val, x, rx);
-}
-
-// T[dst + v nc + w] += A_bb[src][v][w]
-template <typename TM>
-__global__ void fold_add_kernel(int64_t n_fold, const int64_t *__restrict__ dst,
-                                const int32_t *__restrict__ nc, const int32_t *__restrict__ src,
-                                const double *__restrict__ val, TM *__restrict__ t) {
-  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (q >= n_fold * 25) return;
-  const int64_t f = q / 25;
-  const int k = (int)(q % 25), v = k / 5, w = k % 5;
-  TM *p = t + dst[f] + (int64_t)v * nc[f] + w;
-  *p = (TM)((double)*p + val[(int64_t)src[f] * 25 + k]);
 }
 
 // 5x5 inverse by Gauss-Jordan with partial pivoting, in registers
@@ -882,19 +868,6 @@ hipError_t launch_schur_gemv_rem(const Plan &p, const double *x, double *t, doub
                        p.stream, p.d_gv_s, p.d_rt_s, p.n_rt_s, static_cast<const double *>(p.sloc), x, p.d_cmap, t,
                        ratio, nb, p.d_rem_rowptr, p.d_rem_col, p.rem_val, rx, p.halt);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_fold_add(const Plan &p, void *t, bool fp32) {
-  if (p.n_fold == 0) return hipSuccess;
-  const int64_t n = p.n_fold * 25;
-  const int grid = (int)((n + kThreads - 1) / kThreads);
-  if (fp32)
-    hipLaunchKernelGGL(fold_add_kernel<float>, dim3(grid), dim3(kThreads), 0, p.stream, p.n_fold,
-                       p.d_fold_dst, p.d_fold_nc, p.d_fold_src, p.bb_val, static_cast<float *>(t));
-  else
-    hipLaunchKernelGGL(fold_add_kernel<double>, dim3(grid), dim3(kThreads), 0, p.stream, p.n_fold,
-                       p.d_fold_dst, p.d_fold_nc, p.d_fold_src, p.bb_val, static_cast<double *>(t));
   return hipGetLastError();
 }
 

@@ -855,7 +855,7 @@ scdg_status scdg_plan_destroy(scdg_plan *pl) {
   }
   dfree(p.d_mask_flag); dfree(p.bb_lo); dfree(p.rem_lo);
   dfree(p.d_mask); dfree(p.d_e_offib); dfree(p.d_e_maskoff); dfree(p.d_e_ri); dfree(p.d_e_rc); dfree(p.w_z2);
-  dfree(p.d_fold_dst); dfree(p.d_fold_nc); dfree(p.d_fold_src);
+  dfree(p.d_fold_map);
   dfree(p.d_rem_rowptr); dfree(p.d_rem_col); dfree(p.d_rem_src); dfree(p.pc_blk); dfree(p.rem_val);
   dfree(p.d_remt_rowptr); dfree(p.d_remt_col); dfree(p.d_remt_src); dfree(p.d_ct_s);
   dfree(p.d_bb_rowptr); dfree(p.d_bb_col); dfree(p.d_inv_n); dfree(p.d_inv_off); dfree(p.d_inv_order); dfree(p.d_info);
@@ -1038,9 +1038,17 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   for (int e = 0; e < E; ++e)
     for (int64_t q = s->c_ptr[e]; q < s->c_ptr[e + 1]; ++q)
       slot_elem[p.off_c[e] / kNvar + (q - s->c_ptr[e])] = e;
-  std::vector<int64_t> fold_dst;
-  std::vector<int32_t> fold_nc, fold_src, rem_col, rem_src;
+  // per element, the A_bb block folded into each node block of T_e (|C_e|^2
+  // entries, -1 for none)
+  std::vector<int64_t> fm_off(E + 1, 0);
+  for (int e = 0; e < E; ++e) {
+    const int64_t ncn = p.nc[e] / kNvar;
+    fm_off[e + 1] = fm_off[e] + ncn * ncn;
+  }
+  std::vector<int32_t> fold_map((size_t)std::max<int64_t>(fm_off[E], 1), -1);
+  std::vector<int32_t> rem_col, rem_src;
   std::vector<int64_t> rem_rowptr(p.n_bnodes + 1, 0);
+  int64_t n_fold = 0;
   {
     std::vector<std::pair<int, int>> cand;
     for (int64_t g = 0; g < p.n_bnodes; ++g) {
@@ -1063,9 +1071,8 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
           const int32_t *it = std::lower_bound(cb, ce, h);
           if (it != ce && *it == h) {
             const int64_t pos_h = it - cb;
-            fold_dst.push_back(p.off_cc[e] + (int64_t)(kNvar * cp.second) * p.nc[e] + kNvar * pos_h);
-            fold_nc.push_back(p.nc[e]);
-            fold_src.push_back((int32_t)t);
+            fold_map[fm_off[e] + (int64_t)cp.second * (p.nc[e] / kNvar) + pos_h] = (int32_t)t;
+            ++n_fold;
             done = true;
             break;
           }
@@ -1078,7 +1085,7 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
       rem_rowptr[g + 1] = (int64_t)rem_col.size();
     }
   }
-  p.n_fold = (int64_t)fold_dst.size();
+  p.n_fold = n_fold;
   p.n_rem = (int64_t)rem_col.size();
   std::vector<int64_t> bb_rowptr(s->bb_rowptr, s->bb_rowptr + p.n_bnodes + 1);
   std::vector<int32_t> bb_col(s->bb_col, s->bb_col + p.nnzb);
@@ -1091,7 +1098,7 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   for (int e = 0; e < E; ++e) {
     const int ni = p.ni[e], nc = p.nc[e];
     gx[e] = GemmDesc{p.off_ii[e], p.off_ib[e], p.off_ib[e], ni, nc, ni, ni, nc, nc};
-    gs[e] = GemmDesc{p.off_ib[e], p.off_ib[e], p.off_cc[e], nc, nc, ni, ni, nc, nc};
+    gs[e] = GemmDesc{p.off_ib[e], p.off_ib[e], p.off_cc[e], nc, nc, ni, ni, nc, nc, fm_off[e]};
     gv_inv[e] = GemvDesc{p.off_ii[e], ni, ni, (int32_t)p.off_i[e], (int32_t)p.off_i[e]};
     gv_abi[e] = GemvDesc{p.off_ib[e], nc, ni, (int32_t)p.off_i[e], (int32_t)p.off_c[e]};
     gv_aib[e] = GemvDesc{p.off_ib[e], ni, nc, (int32_t)p.off_c[e], (int32_t)p.off_i[e]};
@@ -1127,9 +1134,7 @@ scdg_status scdg_plan_create(scdg_plan **out, const scdg_structure *s, void *hip
   chk(upload(p, &p.d_slot_ib, slot_ib));
   chk(upload(p, &p.d_slot_ni, slot_ni));
   chk(upload(p, &p.d_bb_rowptr, bb_rowptr));
-  chk(upload(p, &p.d_fold_dst, fold_dst));
-  chk(upload(p, &p.d_fold_nc, fold_nc));
-  chk(upload(p, &p.d_fold_src, fold_src));
+  chk(upload(p, &p.d_fold_map, fold_map));
   chk(upload(p, &p.d_rem_rowptr, rem_rowptr));
   chk(upload(p, &p.d_rem_col, rem_col));
   chk(upload(p, &p.d_rem_src, rem_src));
@@ -1515,10 +1520,10 @@ scdg_status scdg_condense(scdg_plan *pl) {
   }
   {
     PhaseTimer tm(p, SCDG_PHASE_GEMM_S);
+    // T_e = F_e - A_bi X_e: the folded A_bb blocks F_e are added in the epilogue
     HIP_TRY(launch_gemm_batched(p.gemm_cfg_s, p.d_gs, p.d_tiles_s, p.n_tiles_s, abi, p.xmat, p.sloc,
-                                -1.0, 0.0, fp32(p), p.stream));
+                                -1.0, 0.0, fp32(p), p.stream, p.d_fold_map, p.bb_val));
   }
-  HIP_TRY(launch_fold_add(p, p.sloc, fp32(p)));
   // the A_bb remainder blocks, copied contiguously in remainder order: every
   // Schur product then streams them instead of gathering from A_bb
   if (p.n_rem > 0) {
@@ -1952,7 +1957,7 @@ scdg_status scdg_autotune(scdg_plan *pl, double *ms_x, double *ms_s, int32_t n) 
                                         1.0, 0.0, fp32(p), p.stream));
           else
             HIP_TRY(launch_gemm_batched(cfg, p.d_gs, p.d_tiles_s, p.n_tiles_s, abi, p.xmat, p.sloc,
-                                        -1.0, 0.0, fp32(p), p.stream));
+                                        -1.0, 0.0, fp32(p), p.stream, p.d_fold_map, p.bb_val));
           HIP_TRY(hipEventRecord(t1, p.stream));
           HIP_TRY(hipEventSynchronize(t1));
           HIP_TRY(hipEventElapsedTime(&t, t0, t1));
