@@ -287,6 +287,10 @@ def learned_guess_experiment(args) -> dict:
     # the same network with the step's right-hand side R(Q_s) as a third input block
     lgr = LearnedGuess(n_elem, dpe, capacity=args.lg_train, seed=args.lg_seed, batch=args.lg_batch,
                        use_residual=True)
+    # the same network trained on the step's first Newton correction (the solution
+    # of the first linear system, which the GMRES x0 seeds) instead of the step increment
+    lg1 = LearnedGuess(n_elem, dpe, capacity=args.lg_train, seed=args.lg_seed, batch=args.lg_batch)
+    rc_prev1 = None
     inv_dt = 1.0 / dt
     q = case.q_state.reshape(-1).contiguous()
     dq_prev = torch.zeros_like(q)
@@ -296,14 +300,16 @@ def learned_guess_experiment(args) -> dict:
     for step in range(1, args.lg_train + 1):
         st.prepare(q)
         r_s = st.dg.residual(q, q, inv_dt)
-        q1, info = st.solve_step(q, guess=dq_prev if step > 1 else None)
+        q1, info = st.solve_step(q, guess=dq_prev if step > 1 else None, keep_first=True)
         if not info["converged"]:
             raise RuntimeError(f"step {step} did not converge: {info}")
         dq = q1 - q
         if step > 1:
             lg.record(q, dq_prev, dq)
             lgr.record(q, dq_prev, dq, r_s)
+            lg1.record(q, dq_prev, info["first_dq"])
             rc_prev = lg.correction_rms(q, dq_prev, dq)
+            rc_prev1 = lg1.correction_rms(q, dq_prev, info["first_dq"])
         q, dq_prev = q1, dq
         log(f"train-phase step {step}: newton {info['newton']} gmres {info['gmres']}")
     t_collect = time.perf_counter() - t_collect
@@ -328,6 +334,13 @@ def learned_guess_experiment(args) -> dict:
     torch.cuda.synchronize()
     t_train_r = time.perf_counter() - t0
     log(f"residual-input network: loss {history_r[0]:.3e} -> {history_r[-1]:.3e}, hold-out {hold_r:.3e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    history_1, hold_1 = lg1.train(epochs=args.lg_epochs, lr=args.lg_lr, holdout_rows=n_elem)
+    torch.cuda.synchronize()
+    t_train_1 = time.perf_counter() - t0
+    log(f"first-correction network: loss {history_1[0]:.3e} -> {history_1[-1]:.3e}, hold-out {hold_1:.3e} "
+        f"(alpha {lg1.alpha:.3f})")
     # the same network trained on the condensed residual its guess leaves (S of the
     # last training step weighting every stored step), on the same samples
     lgs = LearnedGuess(n_elem, dpe, capacity=args.lg_train, seed=args.lg_seed, batch=args.lg_batch)
@@ -344,6 +357,7 @@ def learned_guess_experiment(args) -> dict:
     log(f"trained {args.lg_epochs} epochs in {t_train:.1f} s: loss {history[0]:.3e} -> {history[-1]:.3e}, "
         f"hold-out {hold:.3e} (previous increment: {hold_zero:.3e})")
     variants = [("zero", "gmres"), ("previous", "gmres"), ("learned", "gmres"), ("learned_s", "gmres"),
+                ("learned_first", "gmres"),
                 ("previous_newton_start", "newton"), ("learned_newton_start", "newton"),
                 ("learned_bf16_newton_start", "newton"), ("learned_r_newton_start", "newton"),
                 ("fp32_ir_zero", "gmres"), ("fp32_ir_previous_newton_start", "newton"),
@@ -353,7 +367,7 @@ def learned_guess_experiment(args) -> dict:
     names = [v for v, _ in variants]
     rec = {k: {"first": [], "total": [], "newton": [], "seconds": [], "guess_res": [], "rejected": []}
            for k in names}
-    infer_ms, infer16_ms, infer_r_ms, infer_s_ms = [], [], [], []
+    infer_ms, infer16_ms, infer_r_ms, infer_s_ms, infer_1_ms = [], [], [], [], []
     prep = {"fp64": [], "fp32": []}
     for step in range(args.lg_train + 1, args.lg_steps + 1):
         prep["fp64"].append(st.prepare(q))
@@ -375,14 +389,23 @@ def learned_guess_experiment(args) -> dict:
         pred_s = lgs.predict(q, dq_prev, rc_prev)
         torch.cuda.synchronize()
         infer_s_ms.append((time.perf_counter() - t1) * 1e3)
+        t1 = time.perf_counter()
+        pred_1 = lg1.predict(q, dq_prev, rc_prev1)
+        torch.cuda.synchronize()
+        infer_1_ms.append((time.perf_counter() - t1) * 1e3)
         out = {}
+        first_zero = None
         for name, mode in variants:
             g = None if name.endswith("zero") else (dq_prev if "previous" in name else
                                                     (pred16 if "bf16" in name else
                                                      (pred_r if "learned_r" in name else
-                                                      (pred_s if name == "learned_s" else pred))))
+                                                      (pred_s if name == "learned_s" else
+                                                       (pred_1 if name == "learned_first" else pred)))))
             q1, info = (st32 if name.startswith("fp32") else st).solve_step(q, guess=g, mode=mode,
-                                                                            graph="graph" in name)
+                                                                            graph="graph" in name,
+                                                                            keep_first=name == "zero")
+            if name == "zero":
+                first_zero = info["first_dq"]
             if not info["converged"]:
                 raise RuntimeError(f"step {step} ({name}) did not converge: {info}")
             r = rec[name]
@@ -391,7 +414,8 @@ def learned_guess_experiment(args) -> dict:
             r["newton"].append(info["newton"])
             infer = (infer16_ms[-1] if "bf16" in name else
                      (infer_r_ms[-1] if "learned_r" in name else
-                      (infer_s_ms[-1] if name == "learned_s" else infer_ms[-1])))
+                      (infer_s_ms[-1] if name == "learned_s" else
+                       (infer_1_ms[-1] if name == "learned_first" else infer_ms[-1]))))
             r["seconds"].append(info["seconds"] + (infer * 1e-3 if "learned" in name else 0.0))
             r["guess_res"].append(info["guess_res"])
             r["rejected"].append(info["guess_rejected"])
@@ -399,6 +423,7 @@ def learned_guess_experiment(args) -> dict:
         log(f"step {step}: GMRES per step " + " ".join(f"{k} {rec[k]['total'][-1]}" for k in names))
         dq = out["zero"] - q
         rc_prev = lg.correction_rms(q, dq_prev, dq)
+        rc_prev1 = lg1.correction_rms(q, dq_prev, first_zero)
         dq_prev = dq
         q = out["zero"]
     mean = lambda v: float(np.mean(v))
@@ -430,6 +455,10 @@ def learned_guess_experiment(args) -> dict:
                             "holdout_condensed_loss_previous_increment": 1.0,
                             "weighting": "S of the last training step for every stored step"},
         "inference_condensed_ms_mean": mean(infer_s_ms),
+        "train_first_correction": {"seconds": t_train_1, "loss_first_epoch": history_1[0],
+                                   "loss_last_epoch": history_1[-1], "holdout_loss": hold_1, "alpha": lg1.alpha,
+                                   "target": "first Newton correction of the step (first linear solve's solution)"},
+        "inference_first_correction_ms_mean": mean(infer_1_ms),
         "guess_rejected": {k: int(np.sum(rec[k]["rejected"])) for k in names},
         "forcing": "GMRES tol per Newton iteration = clip(0.5 newton_tol |R0| / |R|, gmres_tol, 0.1)",
     }
@@ -449,6 +478,7 @@ def learned_guess_experiment(args) -> dict:
     lg16.close()
     lgr.close()
     lgs.close()
+    lg1.close()
     st.close()
     st32.close()
     return result

@@ -97,12 +97,16 @@ class ImplicitStepper:
         return time.perf_counter() - t0
 
     def solve_step(self, q_s: torch.Tensor, guess: torch.Tensor | None = None, mode: str = "gmres",
-                   graph: bool | None = None):
+                   graph: bool | None = None, keep_first: bool = False):
         """Newton iterations of one step from a prepared Jacobian; returns (q, info).
         graph (default: the stepper's setting) runs every Newton iteration as one
         replay of the library's captured iteration (scdg_newton_step); there the
-        guess can only enter as the Newton starting state."""
+        guess can only enter as the Newton starting state.  keep_first returns
+        the first Newton correction (the solution of the step's first linear
+        system) as info["first_dq"] (host-driven iterations only)."""
         if self.graph if graph is None else graph:
+            if keep_first:
+                raise ValueError("the captured Newton iteration does not return its first correction")
             return self._solve_step_graph(q_s, guess, mode)
         inv_dt = 1.0 / self.dt
         torch.cuda.synchronize()
@@ -121,6 +125,7 @@ class ImplicitStepper:
             else:
                 rejected = 1
         gmres_iters, first_iters, newton, guess_res = 0, None, 0, 1.0
+        first_dq = None
         while rnorm > self.newton_tol * r0 and newton < self.max_newton:
             x0 = guess if (guess is not None and mode == "gmres" and newton == 0) else None
             tol = self.lin_tol
@@ -144,15 +149,20 @@ class ImplicitStepper:
             if first_iters is None:
                 first_iters = info["iters"]
                 guess_res = info["rel_res_guess"]
+                if keep_first:
+                    first_dq = dq.clone()
             q += dq
             r = self.dg.residual(q, q_s, inv_dt)
             rnorm = float(torch.linalg.vector_norm(r))
             newton += 1
         torch.cuda.synchronize()
-        return q, dict(newton=newton, gmres=gmres_iters, first_gmres=first_iters or 0,
-                       rel_res=rnorm / r0 if r0 > 0 else 0.0, guess_rejected=rejected,
-                       guess_res=guess_res,
-                       seconds=time.perf_counter() - t0, converged=rnorm <= self.newton_tol * r0)
+        out = dict(newton=newton, gmres=gmres_iters, first_gmres=first_iters or 0,
+                   rel_res=rnorm / r0 if r0 > 0 else 0.0, guess_rejected=rejected,
+                   guess_res=guess_res,
+                   seconds=time.perf_counter() - t0, converged=rnorm <= self.newton_tol * r0)
+        if keep_first:
+            out["first_dq"] = first_dq if first_dq is not None else torch.zeros_like(q_s)
+        return q, out
 
     def _solve_step_graph(self, q_s: torch.Tensor, guess: torch.Tensor | None, mode: str):
         if guess is not None and mode != "newton":

@@ -1,5 +1,6 @@
 """The resident-panel form of the batched Gauss-Jordan inverse (one workgroup
-per element holding an outer panel of 48 FP64 / 64 FP32 columns in LDS,
+per element holding an outer panel of 48 FP64 / 64 FP32 columns in LDS, 32
+FP64 columns when some n_i exceeds 320,
 16-column inner panels eliminated in registers, one matrix-core pass over the
 rest of the block per outer panel) against the oracle's inverse and against
 the single-kernel form.
