@@ -147,24 +147,51 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_batched_kernel(const GemmDe
     kloop(std::false_type{});
 
   // the folded A_bb node blocks of this problem's C (Schur GEMM only): the
-  // tile's part of the fold map is staged in LDS (free after the K loop), so
-  // the epilogue looks it up there and reads values only where a block folds
+  // tile's part of the fold map is staged in LDS (free after the K loop), and
+  // for each row group of 16 the epilogue first issues every fold-value load
+  // of its entries (entries without a fold read block 0, which exists when the
+  // tile has any fold, and discard it), then adds and stores, so the loads are
+  // in flight together
   const bool fold = fmap != nullptr && d.f_off >= 0;
   int *fm_s = reinterpret_cast<int *>(&as[0][0][0]);
   const int rb0 = m0 / 5, cb0 = n0 / 5;
   const int frw = (min(m0 + BM, d.m) - 1) / 5 - rb0 + 1, fcw = (min(n0 + BN, d.n) - 1) / 5 - cb0 + 1;
   static_assert((BM / 5 + 2) * (BN / 5 + 2) * sizeof(int) <= sizeof(as), "fold map tile fits in LDS");
+  bool tile_fold = false;
   if (fold) {
     const int32_t *__restrict__ fm = fmap + d.f_off;
     const int fbn = d.n / 5;
+    int any = 0;
     for (int q = threadIdx.x; q < frw * fcw; q += kThreads) {
       const int a = q / fcw, b = q - a * fcw;
-      fm_s[q] = fm[(int64_t)(rb0 + a) * fbn + cb0 + b];
+      const int32_t f = fm[(int64_t)(rb0 + a) * fbn + cb0 + b];
+      fm_s[q] = f;
+      any |= f >= 0;
     }
-    __syncthreads();
+    tile_fold = __syncthreads_or(any) != 0;
   }
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TM; ++i) {
+    double fv[TN][4];
+    int fok = 0;   // bit 4 j + r: entry (j, r) has a folded value
+    if (tile_fold) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * WTM + i * 16 + M::row(lane, r);
+          int f = -1, off = 0;
+          if (col < d.n && row < d.m) {
+            const int rb = row / 5, cb = col / 5;
+            f = fm_s[(rb - rb0) * fcw + cb - cb0];
+            off = (row - 5 * rb) * 5 + (col - 5 * cb);
+          }
+          fok |= (f >= 0 ? 1 : 0) << (4 * j + r);
+          fv[j][r] = fval[(int64_t)(f >= 0 ? f : 0) * 25 + (f >= 0 ? off : 0)];
+        }
+      }
+    }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int col = n0 + wn * WTN + j * 16 + (lane & 15);
@@ -176,15 +203,12 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_batched_kernel(const GemmDe
           T *dst = c + (int64_t)row * d.ldc + col;
           T v = alpha * acc[i][j][r];
           if (beta != T(0)) v += beta * (*dst);
-          if (fold) {
-            const int rb = row / 5, cb = col / 5;
-            const int f = fm_s[(rb - rb0) * fcw + cb - cb0];
-            if (f >= 0) v = (T)((double)v + fval[(int64_t)f * 25 + (row - 5 * rb) * 5 + (col - 5 * cb)]);
-          }
+          if ((fok >> (4 * j + r)) & 1) v = (T)((double)v + fv[j][r]);
           *dst = v;
         }
       }
     }
+  }
 }
 
 template <int BM, int BN, int WM, int WN>
