@@ -92,3 +92,45 @@ def test_refusals():
         plan.guess_schur_loss(yd, td, sd)
     assert err.value.status == -2
     plan.close()
+
+
+def test_mixed_orders_against_oracle():
+    """Elements of orders 2..5 in one plan: the restriction to the boundary
+    vector follows each element's own node sets."""
+    from paper_1911_02366_amd import Plan
+    from workload.mixed import mixed_order_case
+    c = mixed_order_case(2, lo=2, hi=5, seed=4)
+    blocks = c.element_blocks()
+    cd = c.to(DEV)
+    plan = Plan.from_structure(cd.structure())
+    plan.assemble(cd.aii, cd.aib, cd.abi, cd.bb_val)
+    plan.factor("fp64")
+    plan.condense()
+    s = oracle.condensed_matrix_dense(c.c_ptr, c.c_node, c.bb_rowptr, c.bb_col, blocks["bb_val"],
+                                      blocks["aii"], blocks["aib"], blocks["abi"])
+    _, bnode = oracle.dof_maps(c.order)
+    y, t, stats = _inputs(plan.n_dof, 12)
+    want, gwant = om.condensed_loss(s, bnode, y, t, stats[15:20])
+    yd, td, sd = _dev(y, t, stats)
+    loss, dy = plan.guess_schur_loss(yd, td, sd)
+    assert abs(float(loss) - want) <= 1e-12 * want
+    assert rel(to_np(dy).astype(np.float64), gwant) <= 1e-6
+    plan.close()
+
+
+def test_follows_a_new_jacobian():
+    """After new blocks are assembled and condensed, the loss uses the new S."""
+    case = build_case(2, 3, 400.0, 1e-2, seed=62)
+    dev = device_case(case)
+    plan = make_plan(case, dev)
+    y, t, stats = _inputs(plan.n_dof, 5)
+    yd, td, sd = _dev(y, t, stats)
+    l1 = float(plan.guess_schur_loss(yd, td, sd, grad=False)[0])
+    scaled = {k: (v * 2.0).contiguous() for k, v in dev.items() if k != "b"}
+    plan.assemble(scaled["aii"], scaled["aib"], scaled["abi"], scaled["bb_val"], copy=True)
+    plan.factor("fp64")
+    plan.condense()
+    l2 = float(plan.guess_schur_loss(yd, td, sd, grad=False)[0])
+    # every block doubled: S doubles, the loss grows by exactly 4 (up to rounding)
+    assert abs(l2 / l1 - 4.0) <= 1e-12
+    plan.close()
