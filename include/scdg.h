@@ -440,12 +440,13 @@ scdg_status scdg_dg_jacobian_apply_noalloc(scdg_dg *dg, const double *q, const d
  * uniform order with no physical faces; otherwise SCDG_ERR_UNSUPPORTED.
  * SCDG_ERR_ARG for NULL pointers, a negative or non-finite inv_dt, or a
  * nonzero block outside the plan's coupling sets or A_bb pattern (the
- * outputs are then incomplete).  Runs on the DG object's stream.  The first
- * call with a plan checks (one synchronisation) that its coupling sets and
- * A_bb pattern hold a place for every block the template can fill; when they
- * do, this and every later call with that plan return without waiting for
- * the stream.  Otherwise every call returns after the stream, having checked
- * that no block without a place is nonzero.  Workspaces (the term template
+ * outputs are then incomplete).  Runs on the DG object's stream.  A call
+ * with a plan other than the previous call's checks (one synchronisation)
+ * that the plan's coupling sets and A_bb pattern hold a place for every block
+ * the template can fill; when they do, this call and the following ones with
+ * the same plan return without waiting for the stream.  Otherwise every call
+ * returns after the stream, having checked that no block without a place is
+ * nonzero.  Workspaces (the term template
  * and about 3.4 KB of pointwise Jacobians per node) are allocated on the
  * first call and freed by scdg_dg_destroy. */
 scdg_status scdg_dg_jacobian_blocks(scdg_dg *dg, scdg_plan *plan, const double *q, double inv_dt, double *aii,
