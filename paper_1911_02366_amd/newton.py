@@ -380,6 +380,8 @@ class LearnedGuess:
         as with train(): alpha_steps validation steps fit the shrinkage alpha (by
         the same weighted least squares), then holdout_steps are scored only.
         Returns per-epoch mean losses and the mean hold-out loss."""
+        if not holdout_steps:
+            alpha_steps = 0
         n_steps = self.count // self.n_elem
         n_train = n_steps - holdout_steps - alpha_steps
         if n_train < 1 or (holdout_steps and alpha_steps < 1):
