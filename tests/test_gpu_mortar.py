@@ -1,0 +1,102 @@
+"""The uneven-order configuration with its physics: elements of different
+polynomial order on displaced (trilinear, non-affine) hexahedra, coupled
+through mortars on the p-nonconforming faces, Taylor-Green state with the
+seeded perturbation, Re = 1600, Ma = 0.1, dt = 5e-3 (one backward-Euler Newton
+system, eq. NewtonLinSys1 at Q = Q_s, B = -H(Q_s)).
+
+The Newton matrix is the oracle's complex-step Jacobian of its mortar residual
+(oracle/mortar.py); workload/sliced.py cuts it into the per-element blocks the
+library condenses, with coupling sets read off the matrix.  Expected values
+come from the oracle: SuperLU on the global matrix, the condensed quantities
+written as their definitions.  Bars: 1e-12 on S x and b_S, 1e-10 on dQ in
+FP64, full residual 1e-8 and 1e-5 from the oracle with FP32 factors and FP64
+refinement."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import DEV, rel, to_np
+from oracle import dgsem as od
+from oracle import mortar as om
+from paper_1911_02366_amd import Plan
+from workload.dgsem import taylor_green_state
+from workload.physics import FlowParams
+from workload.sliced import blocks_from_matrix
+
+pytestmark = pytest.mark.gpu
+
+K = 2
+CASES = {
+    # a seeded draw from {3, 4}: faces 3|3, 3|4, 4|4
+    "o34": tuple(int(n) for n in np.random.default_rng(1).integers(3, 5, K ** 3)),   # 3 4 4 4 3 3 4 4
+    # the extreme pair of the order range: one order-7 element (n_i = 1080, blocked
+    # inverse) whose six faces are 3|7 mortars
+    "o37": (3, 7, 3, 3, 3, 3, 3, 3),
+}
+MACH, RE, DT = 0.1, 1600.0, 5e-3
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    ORDERS = CASES[request.param]
+    print(f"\n[mortar case K={K} orders {ORDERS}: oracle Jacobian on the CPU]", flush=True)
+    mesh = om.MortarMesh(K, ORDERS)
+    geo = om.build_geometry(mesh)
+    xyz = np.concatenate([om.element_nodes(mesh, e).reshape(-1, 3) for e in range(mesh.n_elem)])
+    q = taylor_green_state(None, FlowParams(mach=MACH, reynolds=RE), seed=0, coords=xyz).reshape(-1)
+    flow = od.Flow(MACH, RE)
+    a = om.jacobian_matrix(q, geo, flow, DT)
+    b = -om.residual(q, geo, flow)
+    c = blocks_from_matrix(a, ORDERS, K, b)
+    eb = c.element_blocks()
+    d = dict(order=c.order, c_ptr=c.c_ptr, c_node=c.c_node, bb_rowptr=c.bb_rowptr, bb_col=c.bb_col, **eb)
+    ref = oracle.solve_sparse(a, b)
+    print(f"[n_dof {mesh.n_dof}, n_i {sorted(set(c.n_i.tolist()))}, n_c {sorted(set(c.n_c.tolist()))}]",
+          flush=True)
+    return c, c.to(DEV), d, a, b, ref
+
+
+def _plan(cd, precision="fp64"):
+    plan = Plan.from_structure(cd.structure())
+    plan.assemble(cd.aii, cd.aib, cd.abi, cd.bb_val)
+    plan.factor(precision)
+    plan.condense()
+    return plan
+
+
+def test_mortar_condensed_operators(case):
+    c, cd, d, a, b, ref = case
+    plan = _plan(cd)
+    s = oracle.condensed_matrix_dense(d["c_ptr"], d["c_node"], d["bb_rowptr"], d["bb_col"], d["bb_val"],
+                                      d["aii"], d["aib"], d["abi"])
+    x = np.random.default_rng(3).standard_normal(s.shape[0])
+    y = plan.schur_apply(torch.tensor(x, device=DEV))
+    assert rel(to_np(y), s @ x) <= 1e-12
+    bs = plan.condense_rhs(cd.rhs)
+    bs_ref = oracle.condensed_rhs(d["order"], d["c_ptr"], d["c_node"], d["aii"], d["abi"], b)
+    assert rel(to_np(bs), bs_ref) <= 1e-12
+    plan.close()
+
+
+@pytest.mark.parametrize("solver", ["dense", "gmres"])
+def test_mortar_full_solve(case, solver):
+    c, cd, d, a, b, ref = case
+    plan = _plan(cd)
+    dq, info = plan.solve(cd.rhs, solver=solver, tol=1e-13)
+    print(solver, info, flush=True)
+    assert rel(to_np(dq), ref) <= 1e-10, info
+    r = oracle.full_residual(a, to_np(dq), b)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b)
+    plan.close()
+
+
+def test_mortar_fp32_factors_with_refinement(case):
+    c, cd, d, a, b, ref = case
+    plan = _plan(cd, precision="fp32")
+    dq, info = plan.solve(cd.rhs, solver="gmres", tol=1e-6, ir_tol=1e-8)
+    print(info, flush=True)
+    r = oracle.full_residual(a, to_np(dq), b)
+    assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b), info
+    assert rel(to_np(dq), ref) <= 1e-5
+    plan.close()
