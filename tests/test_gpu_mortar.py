@@ -52,13 +52,16 @@ def case(request):
     eb = c.element_blocks()
     d = dict(order=c.order, c_ptr=c.c_ptr, c_node=c.c_node, bb_rowptr=c.bb_rowptr, bb_col=c.bb_col, **eb)
     ref = oracle.solve_sparse(a, b)
+    d["s_dense"] = oracle.condensed_matrix_dense(d["c_ptr"], d["c_node"], d["bb_rowptr"], d["bb_col"],
+                                                 d["bb_val"], d["aii"], d["aib"], d["abi"])
     print(f"[n_dof {mesh.n_dof}, n_i {sorted(set(c.n_i.tolist()))}, n_c {sorted(set(c.n_c.tolist()))}]",
           flush=True)
     return c, c.to(DEV), d, a, b, ref
 
 
-def _plan(cd, precision="fp64"):
+def _plan(cd, precision="fp64", mode="assembled"):
     plan = Plan.from_structure(cd.structure())
+    plan.set_schur_mode(mode)
     plan.assemble(cd.aii, cd.aib, cd.abi, cd.bb_val)
     plan.factor(precision)
     plan.condense()
@@ -68,11 +71,12 @@ def _plan(cd, precision="fp64"):
 def test_mortar_condensed_operators(case):
     c, cd, d, a, b, ref = case
     plan = _plan(cd)
-    s = oracle.condensed_matrix_dense(d["c_ptr"], d["c_node"], d["bb_rowptr"], d["bb_col"], d["bb_val"],
-                                      d["aii"], d["aib"], d["abi"])
+    s = d["s_dense"]
     x = np.random.default_rng(3).standard_normal(s.shape[0])
     y = plan.schur_apply(torch.tensor(x, device=DEV))
     assert rel(to_np(y), s @ x) <= 1e-12
+    yt = plan.schur_apply_transpose(torch.tensor(x, device=DEV))
+    assert rel(to_np(yt), s.T @ x) <= 1e-12
     bs = plan.condense_rhs(cd.rhs)
     bs_ref = oracle.condensed_rhs(d["order"], d["c_ptr"], d["c_node"], d["aii"], d["abi"], b)
     assert rel(to_np(bs), bs_ref) <= 1e-12
@@ -99,4 +103,20 @@ def test_mortar_fp32_factors_with_refinement(case):
     r = oracle.full_residual(a, to_np(dq), b)
     assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b), info
     assert rel(to_np(dq), ref) <= 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("mode", ["matrix_free", "matrix_free_sparse"])
+def test_mortar_matrix_free_forms(case, mode):
+    """S applied without forming T_e: through X_e, A_bi and A_bb, or through the
+    nonzero 5x5 blocks of A_ib and A_bi (the mortar couplings give these blocks
+    a pattern of their own, found from the values on the device)."""
+    c, cd, d, a, b, ref = case
+    plan = _plan(cd, mode=mode)
+    x = np.random.default_rng(5).standard_normal(c.n1)
+    y = plan.schur_apply(torch.tensor(x, device=DEV))
+    assert rel(to_np(y), d["s_dense"] @ x) <= 1e-12
+    dq, info = plan.solve(cd.rhs, solver="gmres", tol=1e-13)
+    print(mode, info, flush=True)
+    assert rel(to_np(dq), ref) <= 1e-10, info
     plan.close()
