@@ -207,3 +207,15 @@ def test_planted_mortar_mistakes_break_a_pin(monkeypatch):
         cons_ok = np.max(np.abs(total)) <= 1e-12 * np.max(np.abs(h))
         assert not (free_ok and cons_ok), wrong.__name__
     monkeypatch.setattr(om, "_to_side", right)
+
+
+def test_mass_integrates_the_volume_of_the_torus():
+    """sum_j J_j w_j over every node is the volume L^3: the displacement is periodic,
+    so the displaced elements still tile the periodic box, and J (degree <= 2 per
+    direction on a trilinear element) is integrated exactly at every order >= 2."""
+    mesh = om.MortarMesh(3, tuple(int(n) for n in np.random.default_rng(7).integers(2, 8, 27)))
+    geo = om.build_geometry(mesh)
+    m = om.mass(geo)
+    assert m.shape == (mesh.n_dof,)
+    assert math.isclose(m.sum() / 5.0, mesh.length ** 3, rel_tol=1e-13)
+    assert max(np.ptp(el.jac) for el in geo.elems) > 1e-2          # not a uniform grid

@@ -33,6 +33,10 @@ def test_mortar_matrix_blocks():
     geo = om.build_geometry(mesh)
     q = _state(geo, np.random.default_rng(0))
     a = om.jacobian_matrix(q, geo, flow, dt=1e-2)
+    # the assembled columns are the complex-step products with unit vectors
+    v = np.random.default_rng(1).standard_normal(q.shape)
+    av = om.jacobian_apply(q, v, geo, flow, 1e-2)
+    assert np.linalg.norm(a @ v - av) <= 1e-13 * np.linalg.norm(av)
     b = -om.residual(q, geo, flow)
     c = blocks_from_matrix(a, ORDERS, 2, b)
     eb = c.element_blocks()
