@@ -288,17 +288,43 @@ def jacobian_apply(q: np.ndarray, v: np.ndarray, geo: MortarGeometry, flow: Flow
     return residual(qc, geo, flow, q_s=q, dt=dt).imag / CS_STEP
 
 
+_WORKER_ARGS = None
+
+
+def _worker_init(*args):
+    global _WORKER_ARGS
+    _WORKER_ARGS = args
+
+
+def _unit_columns(c0: int, nb: int, args=None):
+    """Columns c0 .. c0 + nb - 1 of A (as rows of a sparse matrix)."""
+    q, geo, flow, dt = _WORKER_ARGS if args is None else args
+    v = np.zeros((nb, q.shape[-1]))
+    v[np.arange(nb), c0 + np.arange(nb)] = 1.0
+    return sp.csr_matrix(jacobian_apply(q, v, geo, flow, dt))
+
+
+def _unit_columns_star(c):
+    return _unit_columns(*c)
+
+
 def jacobian_matrix(q: np.ndarray, geo: MortarGeometry, flow: Flow, dt: float | None = None,
-                    batch: int = 256) -> sp.csr_matrix:
+                    batch: int = 64, workers: int = 1) -> sp.csr_matrix:
     """The Newton matrix A of eq. NewtonLinSys1, column by column (complex step on
-    batches of unit vectors); exact to rounding."""
+    batches of unit vectors); exact to rounding.  With workers > 1 the batches
+    are shared out to that many spawned processes (the same arithmetic per
+    column; the batches only decide which columns are evaluated together)."""
     n = q.shape[-1]
-    cols = []
-    for c0 in range(0, n, batch):
-        nb = min(batch, n - c0)
-        v = np.zeros((nb, n))
-        v[np.arange(nb), c0 + np.arange(nb)] = 1.0
-        cols.append(sp.csr_matrix(jacobian_apply(q, v, geo, flow, dt)))   # rows = columns of A
-    a = sp.vstack(cols).T.tocsr()
+    chunks = [(c0, min(batch, n - c0)) for c0 in range(0, n, batch)]
+    if workers > 1:
+        import multiprocessing
+        from concurrent.futures import ProcessPoolExecutor
+        ctx = multiprocessing.get_context("spawn")
+        with ProcessPoolExecutor(workers, mp_context=ctx, initializer=_worker_init,
+                                 initargs=(q, geo, flow, dt)) as ex:
+            cols = list(ex.map(_unit_columns_star, chunks, chunksize=max(1, len(chunks) // (4 * workers))))
+    else:
+        cols = [_unit_columns(c0, nb, (q, geo, flow, dt)) for c0, nb in chunks]
+    a = sp.vstack(cols).T.tocsr()                      # rows of the stack are columns of A
     a.eliminate_zeros()
     return a

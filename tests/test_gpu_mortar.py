@@ -7,10 +7,12 @@ system, eq. NewtonLinSys1 at Q = Q_s, B = -H(Q_s)).
 The Newton matrix is the oracle's complex-step Jacobian of its mortar residual
 (oracle/mortar.py); workload/sliced.py cuts it into the per-element blocks the
 library condenses, with coupling sets read off the matrix.  Expected values
-come from the oracle: SuperLU on the global matrix, the condensed quantities
+come from the oracle: LAPACK LU of the global matrix, the condensed quantities
 written as their definitions.  Bars: 1e-12 on S x and b_S, 1e-10 on dQ in
 FP64, full residual 1e-8 and 1e-5 from the oracle with FP32 factors and FP64
 refinement."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -33,6 +35,9 @@ CASES = {
     # the extreme pair of the order range: one order-7 element (n_i = 1080, blocked
     # inverse) whose six faces are 3|7 mortars
     "o37": (3, 7, 3, 3, 3, 3, 3, 3),
+    # the seeded draw from the configuration's range {3..7}: 5 5 6 7 3 3 7 7
+    # (12 195 DOFs; the oracle's Jacobian columns are spread over worker processes)
+    "o3to7": tuple(int(n) for n in np.random.default_rng(1).integers(3, 8, K ** 3)),
 }
 MACH, RE, DT = 0.1, 1600.0, 5e-3
 
@@ -46,12 +51,12 @@ def case(request):
     xyz = np.concatenate([om.element_nodes(mesh, e).reshape(-1, 3) for e in range(mesh.n_elem)])
     q = taylor_green_state(None, FlowParams(mach=MACH, reynolds=RE), seed=0, coords=xyz).reshape(-1)
     flow = od.Flow(MACH, RE)
-    a = om.jacobian_matrix(q, geo, flow, DT)
+    a = om.jacobian_matrix(q, geo, flow, DT, workers=min(8, len(os.sched_getaffinity(0))))
     b = -om.residual(q, geo, flow)
     c = blocks_from_matrix(a, ORDERS, K, b)
     eb = c.element_blocks()
     d = dict(order=c.order, c_ptr=c.c_ptr, c_node=c.c_node, bb_rowptr=c.bb_rowptr, bb_col=c.bb_col, **eb)
-    ref = oracle.solve_sparse(a, b)
+    ref = oracle.solve_dense(a, b)
     d["s_dense"] = oracle.condensed_matrix_dense(d["c_ptr"], d["c_node"], d["bb_rowptr"], d["bb_col"],
                                                  d["bb_val"], d["aii"], d["aib"], d["abi"])
     print(f"[n_dof {mesh.n_dof}, n_i {sorted(set(c.n_i.tolist()))}, n_c {sorted(set(c.n_c.tolist()))}]",
@@ -84,7 +89,7 @@ def test_mortar_condensed_operators(case):
 
 
 @pytest.mark.parametrize("solver", ["dense", "gmres"])
-def test_mortar_full_solve(case, solver):
+def test_mortar_full_solve(case, solver):   # against the brute-force LU of A
     c, cd, d, a, b, ref = case
     plan = _plan(cd)
     dq, info = plan.solve(cd.rhs, solver=solver, tol=1e-13)

@@ -33,6 +33,8 @@ def test_mortar_matrix_blocks():
     geo = om.build_geometry(mesh)
     q = _state(geo, np.random.default_rng(0))
     a = om.jacobian_matrix(q, geo, flow, dt=1e-2)
+    # worker processes evaluate the same columns
+    assert abs(om.jacobian_matrix(q, geo, flow, dt=1e-2, workers=2) - a).max() == 0.0
     # the assembled columns are the complex-step products with unit vectors
     v = np.random.default_rng(1).standard_normal(q.shape)
     av = om.jacobian_apply(q, v, geo, flow, 1e-2)
