@@ -21,7 +21,10 @@ What it computes (each function cites the passage it follows):
     chain-rule backward, Adam, mean-squared loss, the feature maps and the
     condensed-residual loss of a predicted increment;
   * (module `oracle.sparsity1d`) the Jacobian of the 1D scalar DGSEM on
-    Gauss and Gauss-Lobatto nodes, for the sparsity claims of Section 3.1.
+    Gauss and Gauss-Lobatto nodes, for the sparsity claims of Section 3.1;
+  * (module `oracle.mortar`) the residual of elements of uneven order on
+    displaced trilinear hexahedra, coupled through mortars on faces between
+    different orders, and its Newton matrix by complex step.
 """
 from .linalg import (  # noqa: F401
     NodeSets, node_sets, dof_maps, assemble_global, solve_dense, solve_sparse,
