@@ -15,6 +15,7 @@ import os
 
 import numpy as np
 import pytest
+import scipy.linalg as sla
 import torch
 
 import oracle
@@ -124,4 +125,56 @@ def test_mortar_matrix_free_forms(case, mode):
     dq, info = plan.solve(cd.rhs, solver="gmres", tol=1e-13)
     print(mode, info, flush=True)
     assert rel(to_np(dq), ref) <= 1e-10, info
+    plan.close()
+
+
+def test_mortar_implicit_steps():
+    """Ten backward-Euler steps of the uneven-order physics (orders {3, 4}, the
+    first case) with one plan: every step re-assembles it with the step's Newton
+    matrix (the oracle's Jacobian at Q_s, kept through the step's chord Newton
+    iterations) and every correction comes from the library's condensed solve.
+    The oracle runs the same steps with the LAPACK LU of A; both stop each step
+    at ||R|| <= 1e-10 ||R(Q_s)||, and the states agree to 1e-9."""
+    orders = CASES["o34"]
+    mesh = om.MortarMesh(K, orders)
+    geo = om.build_geometry(mesh)
+    xyz = np.concatenate([om.element_nodes(mesh, e).reshape(-1, 3) for e in range(mesh.n_elem)])
+    q0 = taylor_green_state(None, FlowParams(mach=MACH, reynolds=RE), seed=0, coords=xyz).reshape(-1)
+    flow = od.Flow(MACH, RE)
+    workers = min(8, len(os.sched_getaffinity(0)))
+    plan = None
+    q_gpu, q_orc = q0.copy(), q0.copy()
+    for step in range(10):
+        # library path: blocks of A(Q_s) for this step, chord Newton with GPU solves
+        a = om.jacobian_matrix(q_gpu, geo, flow, DT, workers=workers)
+        c = blocks_from_matrix(a, orders, K, np.zeros(mesh.n_dof))
+        cd = c.to(DEV)
+        if plan is None:
+            plan = Plan.from_structure(cd.structure())
+        plan.assemble(cd.aii, cd.aib, cd.abi, cd.bb_val)
+        plan.factor("fp64")
+        plan.condense()
+        q_s = q_gpu.copy()
+        r0 = np.linalg.norm(om.residual(q_s, geo, flow, q_s, DT))
+        for it in range(20):
+            r = om.residual(q_gpu, geo, flow, q_s, DT)
+            if np.linalg.norm(r) <= 1e-10 * r0:
+                break
+            dq, info = plan.solve(torch.tensor(-r, device=DEV), solver="gmres", tol=1e-13)
+            q_gpu = q_gpu + to_np(dq)
+        assert it >= 1 and np.linalg.norm(r) <= 1e-10 * r0, (step, it)
+        # oracle path: the same steps with the brute-force solve
+        a_o = om.jacobian_matrix(q_orc, geo, flow, DT, workers=workers)
+        lu = sla.lu_factor(a_o.toarray())
+        q_so = q_orc.copy()
+        r0o = np.linalg.norm(om.residual(q_so, geo, flow, q_so, DT))
+        for _ in range(20):
+            ro = om.residual(q_orc, geo, flow, q_so, DT)
+            if np.linalg.norm(ro) <= 1e-10 * r0o:
+                break
+            q_orc = q_orc + sla.lu_solve(lu, -ro)
+        print(f"step {step}: {it} chord iterations, state difference "
+              f"{np.linalg.norm(q_gpu - q_orc) / np.linalg.norm(q_orc):.2e}", flush=True)
+    assert np.linalg.norm(q_gpu - q_orc) <= 1e-9 * np.linalg.norm(q_orc)
+    assert np.linalg.norm(q_gpu - q0) > 1e-6 * np.linalg.norm(q0)      # the state moved
     plan.close()
