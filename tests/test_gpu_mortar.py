@@ -178,3 +178,16 @@ def test_mortar_implicit_steps():
     assert np.linalg.norm(q_gpu - q_orc) <= 1e-9 * np.linalg.norm(q_orc)
     assert np.linalg.norm(q_gpu - q0) > 1e-6 * np.linalg.norm(q0)      # the state moved
     plan.close()
+
+
+@pytest.mark.parametrize("krylov", ["device", "graph"])
+def test_mortar_gmres_device_cycles(case, krylov):
+    """GMRES with the restart cycle kept on the device, and replayed from a
+    captured HIP graph, on the mortar systems: the same solution as the oracle."""
+    c, cd, d, a, b, ref = case
+    plan = _plan(cd)
+    plan.set_krylov_mode(krylov)
+    for _ in range(2):                      # a replay after the first capture
+        dq, info = plan.solve(cd.rhs, solver="gmres", tol=1e-13)
+        assert rel(to_np(dq), ref) <= 1e-10, (krylov, info)
+    plan.close()
