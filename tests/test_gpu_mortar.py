@@ -191,3 +191,20 @@ def test_mortar_gmres_device_cycles(case, krylov):
         dq, info = plan.solve(cd.rhs, solver="gmres", tol=1e-13)
         assert rel(to_np(dq), ref) <= 1e-10, (krylov, info)
     plan.close()
+
+
+@pytest.mark.parametrize("inverse", ["single", "blocked"])
+def test_mortar_inverse_forms_and_autotuned_tiles(case, inverse, tmp_path):
+    """The other two forms of the batched inverse, and the GEMM tiles the
+    autotuner picks for the uneven batch, give the same solution."""
+    c, cd, d, a, b, ref = case
+    plan = Plan.from_structure(cd.structure())
+    plan.set_inverse_mode(inverse)
+    plan.assemble(cd.aii, cd.aib, cd.abi, cd.bb_val)
+    plan.factor("fp64")
+    assert plan.inverse_mode_used() == inverse
+    plan.autotune(cache=str(tmp_path / "autotune.json"))
+    plan.condense()
+    dq, info = plan.solve(cd.rhs, solver="gmres", tol=1e-13)
+    assert rel(to_np(dq), ref) <= 1e-10, (inverse, plan.gemm_config(), info)
+    plan.close()
