@@ -73,3 +73,22 @@ def test_mortar_matrix_blocks():
     xc = oracle.condensed_solve_dense(c.order, c.c_ptr, c.c_node, c.bb_rowptr, c.bb_col, eb["bb_val"],
                                       eb["aii"], eb["aib"], eb["abi"], b)
     assert np.linalg.norm(xc - x) <= 1e-11 * np.linalg.norm(x)
+
+
+def test_slicer_refuses_what_condensation_cannot_take():
+    """A matrix coupling the interior DOFs of two elements has no element-local
+    Schur complement, and sizes must match the orders: both are refused."""
+    import pytest
+    import scipy.sparse as sp
+
+    orders = (2,) * 8
+    n = 8 * 5 * 27
+    eye = sp.identity(n, format="csr")
+    blocks_from_matrix(eye, orders, 2, np.ones(n))               # block diagonal: accepted
+    # the single interior node of an order-2 element is local node 13 (i = j = k = 1)
+    i0, i1 = 5 * 13, 5 * 27 + 5 * 13
+    bad = (eye + sp.csr_matrix(([0.5], ([i0], [i1])), shape=(n, n))).tocsr()
+    with pytest.raises(ValueError, match="interior"):
+        blocks_from_matrix(bad, orders, 2, np.ones(n))
+    with pytest.raises(ValueError, match="match"):
+        blocks_from_matrix(eye, orders, 2, np.ones(n - 1))
